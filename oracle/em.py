@@ -1,0 +1,107 @@
+"""Multigrain Sinkhorn-EM driver of the oracle (paper Sec. 5, Alg. LaueOT).
+
+Test infrastructure: FP64, plain NumPy.
+
+Each EM iteration: model rays and spots of the frozen model-spot list at the
+current grains (Alg. LaueOT, first step; the list itself is fixed at the
+prototypes, Sec. 4.2), costs, the E-step Sinkhorn (oracle/sinkhorn.py), then
+the M-step (oracle/mstep.py) with the plan held fixed.  Reading of the
+annealing (Sec. 5.1): a fixed geometric temperature schedule of n_stages
+stages, iters_per_stage EM iterations each, eps_s = eps_0 (eps_end/eps_0)^(s/(S-1));
+Sinkhorn potentials are carried over between iterations (warm start).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import cost, forward, mstep, sinkhorn
+
+
+def eps_schedule(eps0, eps_end, n_stages, iters_per_stage):
+    if n_stages == 1:
+        stages = [eps0]
+    else:
+        stages = [eps0 * (eps_end / eps0) ** (s / (n_stages - 1)) for s in range(n_stages)]
+    return [e for e in stages for _ in range(iters_per_stage)]
+
+
+def obs_lab(geom, p12, block):
+    det = np.asarray(block) % geom.n_det
+    return geom.det_center[det] + p12[:, :1] * geom.det_a1[det] + p12[:, 1:2] * geom.det_a2[det]
+
+
+def build_costs(planes, geom, distance, p12, obs_off, model, q, x):
+    """Column data at (q, x) and the cost blocks."""
+    ev = forward.eval_fixed(planes, q, x, geom, model["m"], model["n"], model["t"], model["det"])
+    vloc = cost.v_local(geom, model["det"], ev["v"])
+    col_off = model["offsets"]
+    C = []
+    for b in range(geom.n_blocks):
+        i0, i1 = obs_off[b], obs_off[b + 1]
+        j0, j1 = col_off[b], col_off[b + 1]
+        C.append(cost.chord_cost(p12[i0:i1], ev["s12"][j0:j1], vloc[j0:j1], distance))
+    return C, ev, vloc
+
+
+def grain_pairs(planes, geom, p_lab, obs_off, model, Qb, n_grains):
+    """Pairs of every grain: (detected spot, model spot of that grain, Q_ij)."""
+    per = [([], [], [], []) for _ in range(n_grains)]
+    col_off = model["offsets"]
+    for b in range(geom.n_blocks):
+        i0, i1 = obs_off[b], obs_off[b + 1]
+        j0, j1 = col_off[b], col_off[b + 1]
+        if i1 == i0 or j1 == j0:
+            continue
+        for jj in range(j1 - j0):
+            j = j0 + jj
+            n = model["n"][j]
+            P, T, W, Q = per[n]
+            P.append(p_lab[i0:i1])
+            T.append(np.full(i1 - i0, model["t"][j]))
+            W.append(np.repeat(planes["w"][model["m"][j]][None], i1 - i0, axis=0))
+            Q.append(Qb[b][:, jj])
+    out = []
+    for P, T, W, Q in per:
+        if P:
+            out.append(mstep.Pairs(np.concatenate(P), np.concatenate(T), np.concatenate(W), np.concatenate(Q)))
+        else:
+            out.append(None)
+    return out
+
+
+def run(planes, geom, distance, p12, obs_off, model, q0, x0, eps_list, c_out, c_unm=0.0,
+        c_sink=None, t_b=None, k_gn=2, tol=1e-5, n_max=2000, record=False):
+    """Run the EM.  model: dict with m, n, t, det (block-sorted) and offsets.
+
+    Returns dict with q, x, f, g, f0, g0 and per-iteration stats."""
+    c_sink = c_out if c_sink is None else c_sink
+    J = len(model["m"])
+    t_b = sinkhorn.default_tb(J) if t_b is None else t_b
+    q = np.array(q0, dtype=np.float64).copy()
+    x = np.array(x0, dtype=np.float64).copy()
+    N = q.shape[0]
+    p_lab = obs_lab(geom, p12, np.repeat(np.arange(geom.n_blocks), np.diff(obs_off)))
+    f = g = None
+    f0 = g0 = 0.0
+    stats = []
+    for it, eps in enumerate(eps_list):
+        C, _, _ = build_costs(planes, geom, distance, p12, obs_off, model, q, x)
+        P = sinkhorn.Problem(C, c_out, c_unm, c_sink, t_b)
+        sol = sinkhorn.solve(P, eps, tol=tol, n_max=n_max, f=f, g=g, f0=f0, g0=g0)
+        f, g, f0, g0 = sol["f"], sol["g"], sol["f0"], sol["g0"]
+        Qb = sinkhorn.plan_blocks(P, f, g, eps)
+        pairs = grain_pairs(planes, geom, p_lab, obs_off, model, Qb, N)
+        steps = np.zeros((N, 6))
+        for k in range(k_gn):
+            for n in range(N):
+                if pairs[n] is None:
+                    continue
+                q[n], x[n], st, _, _, _ = mstep.gn_step(pairs[n], q[n], x[n], geom, distance)
+                steps[n] = st
+        rec = {"eps": eps, "n_iter": sol["n_iter"], "err": sol["err"],
+               "step_max": float(np.max(np.linalg.norm(steps, axis=1))) if N else 0.0}
+        if record:
+            rec["q"] = q.copy()
+            rec["x"] = x.copy()
+        stats.append(rec)
+    return {"q": q, "x": x, "f": f, "g": g, "f0": f0, "g0": g0, "stats": stats, "t_b": t_b}
