@@ -1,0 +1,335 @@
+/*
+ * laueot.h -- C ABI of the MI355X (gfx950) LaueOT hot-path library.
+ *
+ * The library implements the data-parallel hot path of Laue indexing with
+ * optimal transport (Kacprzak et al., "Laue Indexing with Optimal Transport"):
+ *   - the forward model (Sec. 3.2-3.3: Eqs. ray_mnt, s_mnt, wavelength,
+ *     model_spot_cut),
+ *   - the assignment cost and the entropic-OT E-step with an outlier row and
+ *     column (Sec. 4: Eqs. likelihood, update_L, elbo, estep_obj;
+ *     Alg. BalancedOT), run as a streamed log-domain Sinkhorn that never
+ *     materialises the detected x model matrix,
+ *   - the per-grain M-step (Sec. 4.4, Eq. mstep_obj) as a weighted
+ *     Gauss-Newton step over rotation and position with FP64 6x6 solves,
+ *   - the multigrain EM driver (Alg. LaueOT) and a simulator of detected spots
+ *     (Sec. 3.3.1, Eq. spot_noisy) for synthetic inputs.
+ *
+ * Conventions (apply to every entry point):
+ *   - Units: millimetres, Angstrom, radians; costs and temperatures in mm^2.
+ *     The beam is e = (1,0,0).
+ *   - "device" pointers are HIP device memory owned by the caller; "host"
+ *     pointers are ordinary host memory owned by the caller.  The library
+ *     never allocates device memory: entry points that need scratch take a
+ *     caller-allocated device workspace (ws, ws_bytes) whose minimum size the
+ *     matching *_workspace_size query returns.  Workspaces must be 256-byte
+ *     aligned and must not be shared by calls that may overlap.
+ *   - stream is a hipStream_t passed as void*.  NULL means the default
+ *     stream.  Unless stated otherwise, calls enqueue work and return; calls
+ *     documented as "synchronous" wait for their stream before returning.
+ *   - Return value: LAUE_OK (0) on success, a negative LAUE_E* code on error
+ *     (nothing was enqueued, outputs are unspecified), or a positive warning
+ *     (results valid).  laue_last_error() gives the message of the last
+ *     failure on the calling thread.
+ *   - Arrays are structure-of-arrays.  Detected and model spots are sorted by
+ *     block b = t * n_det + d (rotation t, detector d) and described by CSR
+ *     block offsets; model spots are additionally sorted by grain, then plane,
+ *     inside each block (the order laue_forward_enumerate produces).
+ *   - Precision: geometry and Sinkhorn arithmetic in FP32; the 6x6 normal
+ *     equations, per-grain reductions, marginal errors, bin potentials and
+ *     likelihood accumulations in FP64.
+ */
+#ifndef LAUEOT_H
+#define LAUEOT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LAUE_OK 0
+#define LAUE_ENOCONV 1          /* warning: Sinkhorn stopped at its iteration cap */
+#define LAUE_EINVAL (-1)        /* invalid argument (null pointer, bad size, NaN) */
+#define LAUE_EINFEASIBLE (-2)   /* T_a = T_b + |I| - |J| < 0 */
+#define LAUE_ECAPACITY (-3)     /* output capacity too small; required size reported */
+#define LAUE_EDEVICE (-4)       /* a HIP runtime call failed */
+#define LAUE_EWORKSPACE (-5)    /* workspace missing, too small or misaligned */
+
+#define LAUE_MAX_DET 4
+#define LAUE_MAX_ROT 360
+
+/* Version of this ABI (major * 10000 + minor * 100 + patch). */
+int laue_version(void);
+
+/* Message of the last error on the calling thread ("" if none).  The string
+ * stays valid until the next library call on that thread. */
+const char *laue_last_error(void);
+
+/* ---- problem description ---------------------------------------------- */
+
+/* A flat square detector (Sec. 3.3.1: centre gamma, normal nu, side l).
+ * axis1, axis2: in-plane unit axes; detector-local coordinates of a point P
+ * on the detector are (axis1.(P - center), axis2.(P - center)). */
+typedef struct laue_detector {
+    double center[3];
+    double normal[3];
+    double axis1[3];
+    double axis2[3];
+    double half_size;           /* l / 2 */
+} laue_detector;
+
+/* Scan, detectors and band.  Sample rotation t is Gamma_t = R_z(omega0 +
+ * t * domega) about (0,0,1) (Sec. 3.3); band [lambda_min, lambda_max]
+ * (Eq. model_spot_cut). */
+typedef struct laue_geometry {
+    int32_t n_rot;              /* T, 1 .. LAUE_MAX_ROT */
+    int32_t n_det;              /* 1 .. LAUE_MAX_DET */
+    double omega0, domega;
+    double lambda_min, lambda_max;
+    laue_detector det[LAUE_MAX_DET];
+} laue_geometry;
+
+/* Miller-plane set {(w_m, d_m)} (Sec. 3.3), device arrays.
+ * w: [n][3] unit normals in the crystal frame; d: [n] spacings (A);
+ * harmonic_prev: [n] index of the parallel plane of next lower order, or -1
+ * (used to merge harmonics, which produce identical spots). */
+typedef struct laue_planes {
+    int32_t n;
+    const float *w;
+    const float *d;
+    const int32_t *harmonic_prev;
+} laue_planes;
+
+/* Grains G_n = (R_n, x_n) (Sec. 3.3), device arrays, FP64.
+ * q: [n][4] unit quaternions (w,x,y,z); x: [n][3] positions (mm). */
+typedef struct laue_grains {
+    int32_t n;
+    double *q;
+    double *x;
+} laue_grains;
+
+/* Detected spots {p_i, t_i} (Sec. 3.3.1), device arrays sorted by block.
+ * p1, p2: [n] detector-local coordinates (mm).  block_off: HOST [n_blocks+1]
+ * CSR offsets (n_blocks = n_rot * n_det). */
+typedef struct laue_obs_spots {
+    int64_t n;
+    const float *p1;
+    const float *p2;
+    const int64_t *block_off;
+} laue_obs_spots;
+
+/* Model spots (Eq. model_spot_cut), device SoA arrays of length n sorted by
+ * block, then grain, then plane.  block_off: HOST [n_blocks+1].
+ * Geometry arrays (filled by laue_forward_enumerate / laue_forward_eval):
+ *   s1, s2     detector-local spot position (mm);
+ *   vn, v1, v2 ray vector s - Gamma_t x_n in the detector frame (normal,
+ *              axis1, axis2) (mm);
+ *   lam        Bragg wavelength (A) (may be NULL);
+ *   flags      bit0: within 1e-6 A of a band edge; bit1: within 1e-4 mm of a
+ *              detector edge (may be NULL). */
+typedef struct laue_model_spots {
+    int64_t n;
+    int32_t *plane;
+    int32_t *grain;
+    int32_t *block;
+    float *s1, *s2;
+    float *vn, *v1, *v2;
+    float *lam;
+    uint8_t *flags;
+    int64_t *block_off;
+} laue_model_spots;
+
+/* ---- host helper ------------------------------------------------------- */
+
+/* Cubic plane list (Sec. 3.1: d = a / sqrt(h^2+k^2+l^2)).  All signed
+ * (h,k,l) != 0 with h^2+k^2+l^2 <= n_max surviving the extinction rule of
+ * centering 'P' (none), 'I' (h+k+l even) or 'F' (all even or all odd),
+ * ordered by (N, h, k, l).  HOST arrays; pass NULL arrays to query *n_planes.
+ * hkl [n][3], w [n][3] (unit normal), d [n], harmonic_prev [n]. */
+int laue_planes_cubic(double a, char centering, int n_max, int32_t *n_planes,
+                      int32_t *hkl, float *w, float *d, int32_t *harmonic_prev);
+
+/* ---- forward model ------------------------------------------------------ */
+
+/* Workspace for laue_forward_enumerate / laue_simulate. */
+size_t laue_forward_workspace_size(const laue_geometry *geom, int32_t n_planes, int32_t n_grains);
+
+/* Visible reflections of grains (Eq. model_spot_cut), in block, grain, plane
+ * order.  merge_harmonics = 0: every plane in band and on a detector (the
+ * literal set); 1: of parallel planes giving the same spot keep only the
+ * lowest order.  out->n is the capacity on entry; on return *n_out (HOST) is
+ * the number found and out->block_off is filled.  If *n_out > capacity the
+ * call returns LAUE_ECAPACITY and writes no spot.  Synchronous. */
+int laue_forward_enumerate(const laue_geometry *geom, const laue_planes *planes,
+                           const laue_grains *grains, int merge_harmonics,
+                           laue_model_spots *out, int64_t *n_out,
+                           void *ws, size_t ws_bytes, void *stream);
+
+/* Forward model on a frozen list (Sec. 4.2: the model-spot set is fixed at
+ * the prototypes): recomputes s1, s2, vn, v1, v2 (and lam) of every spot of
+ * `spots` from its (plane, grain, block) at the given grains; no filtering. */
+int laue_forward_eval(const laue_geometry *geom, const laue_planes *planes,
+                      const laue_grains *grains, laue_model_spots *spots,
+                      void *ws, size_t ws_bytes, void *stream);
+
+/* Workspace for laue_simulate: n_true_max bounds the harmonic-merged visible
+ * spots of the truth (laue_forward_enumerate with capacity 0 returns it),
+ * n_obs_max the output capacity. */
+size_t laue_simulate_workspace_size(const laue_geometry *geom, int32_t n_planes, int32_t n_grains,
+                                    int64_t n_true_max, int64_t n_obs_max);
+
+/* Synthetic detected spots (Sec. 3.3.1, Eq. spot_noisy): the harmonic-merged
+ * model spots of `truth`, each ray perturbed by an isotropic Gaussian of
+ * angular sigma sigma_mm / distance and renormalised, re-intersected with its
+ * detector (spots leaving it are dropped); plus, per block, floor(frac *
+ * n_true + 0.5) outliers uniform on the detector; ordered per block by a
+ * 64-bit random key (ties: true spots first, then by index).  Random numbers:
+ * Philox4x32-10 keyed by (seed low word, seed high word) with counters
+ * (n, t, m + 65536 d, 1) for ray noise, (k, t, 65536 d, 2) for outlier k,
+ * (n, t, m + 65536 d, 3) / (k, t, 65536 d, 4) for order keys; uniforms
+ * (x + 0.5) / 2^32, Gaussians by Box-Muller.  The simulator runs in FP64.
+ * Outputs (device, capacity = *n_out on entry): p1, p2, grain (-1 outlier),
+ * plane (-1 outlier); block_off (HOST [n_blocks+1]).  Returns LAUE_ECAPACITY
+ * with the required *n_out if the capacity is too small (no spot written),
+ * or with *n_out = -(visible spots) if n_true_max is too small.
+ * Synchronous. */
+int laue_simulate(const laue_geometry *geom, const laue_planes *planes,
+                  const laue_grains *truth, double sigma_mm, double distance,
+                  double outlier_frac, uint64_t seed, int64_t n_true_max,
+                  float *p1, float *p2, int32_t *grain, int32_t *plane,
+                  int64_t *block_off, int64_t *n_out,
+                  void *ws, size_t ws_bytes, void *stream);
+
+/* ---- E-step: streamed log-domain Sinkhorn -------------------------------- */
+
+/* Costs and marginals (Sec. 4, Eq. update_L; Sec. 4.3).  Pair cost
+ * c_ij = D^2 ||rhat_ij - r_j||^2 (mm^2) for a detected and a model spot of
+ * the same block (rhat: unit vector from the grain centre to the detected
+ * spot; r: model ray), i.e. the likelihood L_ij = sigma^-2 rhat^T r up to a
+ * constant with sigma = sigma_mm / D.  Bins: c_out for a detected spot in the
+ * outlier column, c_unm for a model spot in the unmatched row, c_sink for
+ * Q_00.  Marginals: 1 per spot, T_b for row 0 and T_a = T_b + |I| - |J| for
+ * column 0. */
+typedef struct laue_ot_params {
+    double eps;                 /* entropic temperature (mm^2) */
+    double distance;            /* D (mm) */
+    double c_out, c_unm, c_sink;
+    double t_b;
+    double tol;                 /* stop when max relative row-marginal error <= tol */
+    int32_t n_max;              /* iteration cap (>= 1) */
+    int32_t chunk;              /* iterations between host polls (0: 16) */
+} laue_ot_params;
+
+/* Dual potentials: Q_ij = exp((f_i + g_j - c_ij) / eps).  f [n_obs], g
+ * [n_model] device FP32 (in: warm start, out: result); f0, g0 host FP64. */
+typedef struct laue_potentials {
+    float *f;
+    float *g;
+    double f0, g0;
+} laue_potentials;
+
+typedef struct laue_ot_stats {
+    int32_t n_iter;             /* completed row+column iterations */
+    int32_t converged;
+    double err;                 /* max relative row-marginal error at the end */
+} laue_ot_stats;
+
+size_t laue_sinkhorn_workspace_size(const laue_geometry *geom, int64_t n_obs, int64_t n_model,
+                                    int32_t n_grains);
+
+/* Sinkhorn iterations (Alg. BalancedOT in the log domain) from the given
+ * potentials: row half (all f_i and f_0 from g, g0), then column half (all
+ * g_j and g_0 from the new f, f0), until the max relative row-marginal error
+ * after a column half is <= tol or n_max iterations.  Uses the model spots'
+ * s1, s2, vn, v1, v2.  Synchronous.  Returns LAUE_ENOCONV at the cap. */
+int laue_sinkhorn(const laue_geometry *geom, const laue_obs_spots *obs,
+                  const laue_model_spots *model, const laue_ot_params *par,
+                  laue_potentials *pot, laue_ot_stats *stats,
+                  void *ws, size_t ws_bytes, void *stream);
+
+/* Dense plan block b: Q[i][j] = exp((f_i + g_j - c_ij)/eps) for the
+ * detected x model spots of block b, row-major FP32 [I_b][J_b] (device).
+ * For tests and small problems. */
+int laue_plan_block(const laue_geometry *geom, const laue_obs_spots *obs,
+                    const laue_model_spots *model, const laue_ot_params *par,
+                    const laue_potentials *pot, int32_t block, float *Q, void *stream);
+
+/* Dense cost block b: C[i][j] = c_ij = D^2 ||rhat_ij - r_j||^2 (mm^2,
+ * Sec. 4, the likelihood L_ij up to a constant and the factor -1/(2 sigma^2))
+ * for the detected x model spots of block b, row-major FP32 [I_b][J_b]
+ * (device), computed exactly as the streamed passes compute it.  For tests
+ * and small problems. */
+int laue_cost_block(const laue_geometry *geom, const laue_obs_spots *obs,
+                    const laue_model_spots *model, double distance, int32_t block, float *C,
+                    void *stream);
+
+/* ---- M-step: per-grain weighted Gauss-Newton ----------------------------- */
+
+typedef struct laue_gn_params {
+    int32_t k_gn;               /* Gauss-Newton steps with the plan held fixed */
+    double mu_rel;              /* Levenberg term mu = mu_rel * tr(H) / 6 */
+} laue_gn_params;
+
+/* M-step (Eq. mstep_obj): the plan Q is given by (pot, par->eps) and the
+ * model spots' current geometry (the E-step state); each of k_gn steps
+ * re-evaluates the model spots at the current grains, forms per grain the
+ * FP64 normal equations H = sum Q J^T J + mu I, g = sum Q J^T rho with
+ * rho = D (rhat - r), and applies R <- exp([omega]_x) R, x <- x + dx with
+ * (omega, dx) = -H^-1 g.  Grains without weight stay unchanged.  step_norm:
+ * optional device FP64 [n_grains], |(omega, dx)| of the last step. */
+int laue_mstep(const laue_geometry *geom, const laue_planes *planes,
+               const laue_obs_spots *obs, laue_model_spots *model,
+               const laue_ot_params *par, const laue_potentials *pot,
+               const laue_gn_params *gn, laue_grains *grains, double *step_norm,
+               void *ws, size_t ws_bytes, void *stream);
+
+/* ---- EM driver (Alg. LaueOT) ---------------------------------------------- */
+
+typedef struct laue_em_params {
+    laue_ot_params ot;          /* eps is ignored: schedule below */
+    laue_gn_params gn;
+    double eps_start, eps_end;  /* geometric schedule over n_stages stages */
+    int32_t n_stages;
+    int32_t iters_per_stage;
+} laue_em_params;
+
+typedef struct laue_em_stats {
+    int32_t n_em_iter;
+    int64_t sinkhorn_iters;     /* total over the run */
+    int64_t cost_entries;       /* same-block (i,j) pairs streamed, all passes */
+    int32_t not_converged;      /* EM iterations whose Sinkhorn hit the cap */
+    double last_err;
+    /* GPU time measured with HIP events on the call's stream (ms) and the
+     * work it covers: Sinkhorn row/column passes, M-step passes. */
+    double sinkhorn_ms;
+    int64_t sinkhorn_passes;
+    int64_t sinkhorn_entries;
+    double mstep_ms;
+    int64_t mstep_entries;
+} laue_em_stats;
+
+/* Per detected spot (device, may be NULL): j_star = argmax over its block's
+ * model spots and the outlier column of Q (lowest index on ties; -1 for the
+ * outlier column), its grain (-1 for outlier), q_star = Q_ij*, q_out = Q_i0. */
+typedef struct laue_assignments {
+    int32_t *j_star;
+    int32_t *grain;
+    float *q_star;
+    float *q_out;
+} laue_assignments;
+
+/* Full EM: for each stage s and iteration: forward eval -> Sinkhorn (warm
+ * started) -> M-step.  The model-spot list is frozen.  pot: in = warm start
+ * (zeros for Alg. BalancedOT's x = y = 1), out = final.  Synchronous. */
+int laue_em(const laue_geometry *geom, const laue_planes *planes,
+            const laue_obs_spots *obs, laue_model_spots *model,
+            const laue_em_params *par, laue_grains *grains, laue_potentials *pot,
+            laue_assignments *assign, laue_em_stats *stats,
+            void *ws, size_t ws_bytes, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LAUEOT_H */

@@ -1,0 +1,379 @@
+"""Python binding of liblaueot (MI355X LaueOT hot path).
+
+Argument marshalling only: every step runs in the HIP library behind the C
+ABI of include/laueot.h.  PyTorch provides device memory and the stream.
+Functions carry the names of the C entry points they call.  There is no CPU
+fallback: if the library is missing the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+import os
+
+import numpy as np
+
+from . import _abi
+from ._abi import (laue_assignments, laue_em_params, laue_em_stats, laue_geometry, laue_gn_params,
+                   laue_grains, laue_model_spots, laue_obs_spots, laue_ot_params, laue_ot_stats,
+                   laue_planes, laue_potentials)
+
+__all__ = ["LaueError", "require_native", "make_geometry", "geometry_from_preset", "Planes",
+           "Grains", "ModelSpots", "ObsSpots", "ot_params", "laue_planes_cubic",
+           "laue_forward_enumerate", "laue_forward_eval", "laue_simulate", "laue_sinkhorn",
+           "laue_plan_block", "laue_cost_block", "laue_mstep", "laue_em", "laue_version"]
+
+_LIB = None
+
+
+class LaueError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"liblaueot error {code}: {msg}")
+        self.code = code
+
+
+def require_native():
+    """Load liblaueot.so (built in-tree) or raise: there is no fallback path."""
+    global _LIB
+    if _LIB is None:
+        import torch  # noqa: F401  (the HIP runtime of torch must be loaded first)
+        if not os.path.exists(_abi.LIB_PATH):
+            raise ImportError(f"{_abi.LIB_PATH} is missing: run python -m paper_2404_06478_amd.build")
+        _LIB = _abi.load()
+    return _LIB
+
+
+def _check(rc):
+    if rc < 0:
+        raise LaueError(rc, require_native().laue_last_error().decode())
+    return rc
+
+
+def _ptr(t):
+    return C.c_void_p(0 if t is None else t.data_ptr())
+
+
+def _stream():
+    import torch
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dev():
+    import torch
+    return torch.device("cuda", torch.cuda.current_device())
+
+
+def _workspace(nbytes):
+    import torch
+    return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=_dev())
+
+
+def laue_version():
+    return require_native().laue_version()
+
+
+# ---------------------------------------------------------------- geometry
+
+def make_geometry(n_rot, domega, detectors, lam_min, lam_max, omega0=0.0):
+    """laue_geometry from detector records with center/normal/axis1/axis2/size."""
+    g = laue_geometry()
+    g.n_rot, g.n_det = int(n_rot), len(detectors)
+    g.omega0, g.domega = float(omega0), float(domega)
+    g.lambda_min, g.lambda_max = float(lam_min), float(lam_max)
+    for k, d in enumerate(detectors):
+        for name in ("center", "normal", "axis1", "axis2"):
+            getattr(g.det[k], name)[:] = [float(v) for v in getattr(d, name)]
+        g.det[k].half_size = float(d.size) / 2.0
+    return g
+
+
+def geometry_from_preset(p, n_rot=None):
+    return make_geometry(p.n_rot if n_rot is None else n_rot, math.radians(p.domega_deg),
+                         p.detectors, p.lam_min, p.lam_max)
+
+
+def n_blocks(geom):
+    return geom.n_rot * geom.n_det
+
+
+# ---------------------------------------------------------------- planes / grains
+
+class Planes:
+    def __init__(self, hkl, w, d, prev):
+        import torch
+        self.hkl = np.asarray(hkl)
+        self.w = torch.as_tensor(np.asarray(w, np.float32)).reshape(-1, 3).to(_dev())
+        self.d = torch.as_tensor(np.asarray(d, np.float32)).to(_dev())
+        self.prev = torch.as_tensor(np.asarray(prev, np.int32)).to(_dev())
+        self.n = int(self.d.numel())
+
+    @property
+    def struct(self):
+        return laue_planes(self.n, self.w.data_ptr(), self.d.data_ptr(), self.prev.data_ptr())
+
+
+def laue_planes_cubic(a, centering, n_max):
+    lib = require_native()
+    n = C.c_int32()
+    _check(lib.laue_planes_cubic(float(a), centering.encode(), int(n_max), C.byref(n), None, None, None, None))
+    hkl = np.zeros((n.value, 3), np.int32)
+    w = np.zeros((n.value, 3), np.float32)
+    d = np.zeros(n.value, np.float32)
+    prev = np.zeros(n.value, np.int32)
+    _check(lib.laue_planes_cubic(float(a), centering.encode(), int(n_max), C.byref(n),
+                                 hkl.ctypes.data, w.ctypes.data, d.ctypes.data, prev.ctypes.data))
+    return Planes(hkl, w, d, prev)
+
+
+class Grains:
+    """FP64 quaternions [n,4] and positions [n,3] on the device."""
+
+    def __init__(self, q, x):
+        import torch
+        self.q = torch.as_tensor(np.asarray(q, np.float64)).reshape(-1, 4).to(_dev()).contiguous()
+        self.x = torch.as_tensor(np.asarray(x, np.float64)).reshape(-1, 3).to(_dev()).contiguous()
+        self.n = int(self.q.shape[0])
+
+    @property
+    def struct(self):
+        return laue_grains(self.n, self.q.data_ptr(), self.x.data_ptr())
+
+    def numpy(self):
+        return self.q.cpu().numpy(), self.x.cpu().numpy()
+
+
+# ---------------------------------------------------------------- spots
+
+class ModelSpots:
+    """Block-sorted model spots (device SoA) with host block offsets."""
+
+    FIELDS_I = ("plane", "grain", "block")
+    FIELDS_F = ("s1", "s2", "vn", "v1", "v2", "lam")
+
+    def __init__(self, n, nb):
+        import torch
+        dev = _dev()
+        self.n = int(n)
+        m = max(self.n, 1)
+        for f in self.FIELDS_I:
+            setattr(self, f, torch.zeros(m, dtype=torch.int32, device=dev))
+        for f in self.FIELDS_F:
+            setattr(self, f, torch.zeros(m, dtype=torch.float32, device=dev))
+        self.flags = torch.zeros(m, dtype=torch.uint8, device=dev)
+        self.block_off = np.zeros(nb + 1, np.int64)
+
+    def struct(self):
+        s = laue_model_spots()
+        s.n = self.n
+        for f in self.FIELDS_I + self.FIELDS_F + ("flags",):
+            setattr(s, f, getattr(self, f).data_ptr())
+        s.block_off = self.block_off.ctypes.data
+        return s
+
+    @classmethod
+    def from_arrays(cls, nb, block_off, plane, grain, block, s1=None, s2=None, vn=None, v1=None,
+                    v2=None):
+        import torch
+        m = cls(len(plane), nb)
+        m.block_off[:] = np.asarray(block_off, np.int64)
+        if m.n:
+            for f, v in (("plane", plane), ("grain", grain), ("block", block)):
+                getattr(m, f)[:m.n] = torch.as_tensor(np.asarray(v, np.int32))
+            for f, v in (("s1", s1), ("s2", s2), ("vn", vn), ("v1", v1), ("v2", v2)):
+                if v is not None:
+                    getattr(m, f)[:m.n] = torch.as_tensor(np.asarray(v, np.float32))
+        return m
+
+    def numpy(self):
+        out = {f: getattr(self, f)[:self.n].cpu().numpy() for f in self.FIELDS_I + self.FIELDS_F + ("flags",)}
+        out["block_off"] = self.block_off.copy()
+        return out
+
+
+class ObsSpots:
+    """Block-sorted detected spots (device FP32) with host block offsets."""
+
+    def __init__(self, p1, p2, block_off, grain=None, plane=None):
+        self.p1, self.p2 = p1, p2
+        self.block_off = np.asarray(block_off, np.int64).copy()
+        self.n = int(self.block_off[-1])
+        self.grain, self.plane = grain, plane
+
+    @classmethod
+    def from_numpy(cls, p12, block_off):
+        import torch
+        p12 = np.asarray(p12, np.float32).reshape(-1, 2)
+        dev = _dev()
+        p1 = torch.as_tensor(np.ascontiguousarray(p12[:, 0])).to(dev)
+        p2 = torch.as_tensor(np.ascontiguousarray(p12[:, 1])).to(dev)
+        if p1.numel() == 0:
+            p1 = torch.zeros(1, dtype=torch.float32, device=dev)
+            p2 = torch.zeros(1, dtype=torch.float32, device=dev)
+        return cls(p1, p2, block_off)
+
+    def struct(self):
+        return laue_obs_spots(self.n, self.p1.data_ptr(), self.p2.data_ptr(), self.block_off.ctypes.data)
+
+
+def laue_forward_enumerate(geom, planes, grains, merge_harmonics=True):
+    lib = require_native()
+    ws = _workspace(lib.laue_forward_workspace_size(C.byref(geom), planes.n, grains.n))
+    nb = n_blocks(geom)
+    probe = ModelSpots(0, nb)
+    ps = probe.struct()
+    ps.n = 0
+    nout = C.c_int64()
+    ps_planes, ps_grains = planes.struct, grains.struct
+    rc = lib.laue_forward_enumerate(C.byref(geom), C.byref(ps_planes), C.byref(ps_grains),
+                                    int(bool(merge_harmonics)), C.byref(ps), C.byref(nout),
+                                    _ptr(ws), ws.numel(), _stream())
+    if rc == _abi.LAUE_ECAPACITY:
+        out = ModelSpots(nout.value, nb)
+        s = out.struct()
+        rc = lib.laue_forward_enumerate(C.byref(geom), C.byref(ps_planes), C.byref(ps_grains),
+                                        int(bool(merge_harmonics)), C.byref(s), C.byref(nout),
+                                        _ptr(ws), ws.numel(), _stream())
+        _check(rc)
+        return out
+    _check(rc)
+    probe.block_off[:] = np.zeros(nb + 1, np.int64)
+    return probe
+
+
+def laue_forward_eval(geom, planes, grains, model):
+    lib = require_native()
+    ws = _workspace(lib.laue_forward_workspace_size(C.byref(geom), planes.n, grains.n))
+    s = model.struct()
+    _check(lib.laue_forward_eval(C.byref(geom), C.byref(planes.struct), C.byref(grains.struct),
+                                 C.byref(s), _ptr(ws), ws.numel(), _stream()))
+    return model
+
+
+def laue_simulate(geom, planes, truth, sigma_mm, distance, outlier_frac, seed):
+    import torch
+    lib = require_native()
+    probe = laue_forward_enumerate(geom, planes, truth, True)
+    n_true = probe.n
+    # capacity: true spots + outliers (frac * n_true rounded per block, + 1 per block)
+    cap = int(n_true * (1.0 + outlier_frac)) + n_blocks(geom) + 1
+    ws = _workspace(lib.laue_simulate_workspace_size(C.byref(geom), planes.n, truth.n, n_true, cap))
+    dev = _dev()
+    p1 = torch.zeros(cap, dtype=torch.float32, device=dev)
+    p2 = torch.zeros(cap, dtype=torch.float32, device=dev)
+    gr = torch.zeros(cap, dtype=torch.int32, device=dev)
+    pl = torch.zeros(cap, dtype=torch.int32, device=dev)
+    boff = np.zeros(n_blocks(geom) + 1, np.int64)
+    nout = C.c_int64(cap)
+    _check(lib.laue_simulate(C.byref(geom), C.byref(planes.struct), C.byref(truth.struct),
+                             float(sigma_mm), float(distance), float(outlier_frac), int(seed),
+                             int(n_true), _ptr(p1), _ptr(p2), _ptr(gr), _ptr(pl),
+                             C.c_void_p(boff.ctypes.data), C.byref(nout), _ptr(ws), ws.numel(),
+                             _stream()))
+    n = nout.value
+    return ObsSpots(p1, p2, boff, gr[:max(n, 1)], pl[:max(n, 1)])
+
+
+# ---------------------------------------------------------------- E / M steps
+
+def ot_params(eps, distance, c_out, t_b, c_unm=0.0, c_sink=None, tol=1e-5, n_max=2000, chunk=16):
+    p = laue_ot_params()
+    p.eps, p.distance, p.c_out, p.c_unm = float(eps), float(distance), float(c_out), float(c_unm)
+    p.c_sink = float(c_out if c_sink is None else c_sink)
+    p.t_b, p.tol, p.n_max, p.chunk = float(t_b), float(tol), int(n_max), int(chunk)
+    return p
+
+
+def laue_sinkhorn(geom, obs, model, ot, f, g, f0=0.0, g0=0.0):
+    """Runs Sinkhorn in place on f, g (device FP32); returns (f0, g0, stats dict, code)."""
+    lib = require_native()
+    ws = _workspace(lib.laue_sinkhorn_workspace_size(C.byref(geom), obs.n, model.n, 0))
+    pot = laue_potentials(f.data_ptr(), g.data_ptr(), float(f0), float(g0))
+    st = laue_ot_stats()
+    o, m = obs.struct(), model.struct()
+    rc = _check(lib.laue_sinkhorn(C.byref(geom), C.byref(o), C.byref(m), C.byref(ot), C.byref(pot),
+                                  C.byref(st), _ptr(ws), ws.numel(), _stream()))
+    return pot.f0, pot.g0, {"n_iter": st.n_iter, "converged": bool(st.converged), "err": st.err}, rc
+
+
+def laue_plan_block(geom, obs, model, ot, f, g, block):
+    import torch
+    lib = require_native()
+    b = int(block)
+    nI = int(obs.block_off[b + 1] - obs.block_off[b])
+    nJ = int(model.block_off[b + 1] - model.block_off[b])
+    Q = torch.zeros(max(nI * nJ, 1), dtype=torch.float32, device=_dev())
+    pot = laue_potentials(f.data_ptr(), g.data_ptr(), 0.0, 0.0)
+    o, m = obs.struct(), model.struct()
+    _check(lib.laue_plan_block(C.byref(geom), C.byref(o), C.byref(m), C.byref(ot), C.byref(pot),
+                               b, _ptr(Q), _stream()))
+    return Q[:nI * nJ].reshape(nI, nJ)
+
+
+def laue_cost_block(geom, obs, model, distance, block):
+    import torch
+    lib = require_native()
+    b = int(block)
+    nI = int(obs.block_off[b + 1] - obs.block_off[b])
+    nJ = int(model.block_off[b + 1] - model.block_off[b])
+    Cm = torch.zeros(max(nI * nJ, 1), dtype=torch.float32, device=_dev())
+    o, m = obs.struct(), model.struct()
+    _check(lib.laue_cost_block(C.byref(geom), C.byref(o), C.byref(m), float(distance), b, _ptr(Cm),
+                               _stream()))
+    return Cm[:nI * nJ].reshape(nI, nJ)
+
+
+def laue_mstep(geom, planes, obs, model, ot, f, g, grains, k_gn=2, mu_rel=1e-9):
+    import torch
+    lib = require_native()
+    ws = _workspace(lib.laue_sinkhorn_workspace_size(C.byref(geom), obs.n, model.n, grains.n))
+    gn = laue_gn_params(int(k_gn), float(mu_rel))
+    pot = laue_potentials(f.data_ptr(), g.data_ptr(), 0.0, 0.0)
+    steps = torch.zeros(max(grains.n, 1), dtype=torch.float64, device=_dev())
+    o, m = obs.struct(), model.struct()
+    _check(lib.laue_mstep(C.byref(geom), C.byref(planes.struct), C.byref(o), C.byref(m),
+                          C.byref(ot), C.byref(pot), C.byref(gn), C.byref(grains.struct),
+                          _ptr(steps), _ptr(ws), ws.numel(), _stream()))
+    return steps[:grains.n]
+
+
+def em_params(ot, eps_start, eps_end, n_stages, iters_per_stage, k_gn=2, mu_rel=1e-9):
+    p = laue_em_params()
+    p.ot = ot
+    p.gn = laue_gn_params(int(k_gn), float(mu_rel))
+    p.eps_start, p.eps_end = float(eps_start), float(eps_end)
+    p.n_stages, p.iters_per_stage = int(n_stages), int(iters_per_stage)
+    return p
+
+
+def laue_em(geom, planes, obs, model, par, grains, f=None, g=None, f0=0.0, g0=0.0, assign=True):
+    """Full EM; grains are updated in place.  Returns a dict of results."""
+    import torch
+    lib = require_native()
+    dev = _dev()
+    f = torch.zeros(max(obs.n, 1), dtype=torch.float32, device=dev) if f is None else f
+    g = torch.zeros(max(model.n, 1), dtype=torch.float32, device=dev) if g is None else g
+    ws = _workspace(lib.laue_sinkhorn_workspace_size(C.byref(geom), obs.n, model.n, grains.n))
+    pot = laue_potentials(f.data_ptr(), g.data_ptr(), float(f0), float(g0))
+    st = laue_em_stats()
+    asg = None
+    if assign:
+        n = max(obs.n, 1)
+        asg_t = {"j_star": torch.zeros(n, dtype=torch.int32, device=dev),
+                 "grain": torch.zeros(n, dtype=torch.int32, device=dev),
+                 "q_star": torch.zeros(n, dtype=torch.float32, device=dev),
+                 "q_out": torch.zeros(n, dtype=torch.float32, device=dev)}
+        asg = laue_assignments(*(asg_t[k].data_ptr() for k in ("j_star", "grain", "q_star", "q_out")))
+    o, m = obs.struct(), model.struct()
+    rc = _check(lib.laue_em(C.byref(geom), C.byref(planes.struct), C.byref(o), C.byref(m),
+                            C.byref(par), C.byref(grains.struct), C.byref(pot),
+                            C.byref(asg) if asg is not None else None, C.byref(st), _ptr(ws),
+                            ws.numel(), _stream()))
+    out = {"f": f, "g": g, "f0": pot.f0, "g0": pot.g0, "code": rc, "n_em_iter": st.n_em_iter,
+           "sinkhorn_iters": st.sinkhorn_iters, "cost_entries": st.cost_entries,
+           "not_converged": st.not_converged, "last_err": st.last_err,
+           "sinkhorn_ms": st.sinkhorn_ms, "sinkhorn_passes": st.sinkhorn_passes,
+           "sinkhorn_entries": st.sinkhorn_entries, "mstep_ms": st.mstep_ms,
+           "mstep_entries": st.mstep_entries}
+    if assign:
+        out.update({k: v[:obs.n] for k, v in asg_t.items()})
+    return out

@@ -1,0 +1,125 @@
+"""ctypes mirror of include/laueot.h (structs, codes, prototypes)."""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liblaueot.so")
+
+LAUE_OK = 0
+LAUE_ENOCONV = 1
+LAUE_EINVAL = -1
+LAUE_EINFEASIBLE = -2
+LAUE_ECAPACITY = -3
+LAUE_EDEVICE = -4
+LAUE_EWORKSPACE = -5
+MAX_DET = 4
+MAX_ROT = 360
+
+vp = C.c_void_p
+d3 = C.c_double * 3
+
+
+class laue_detector(C.Structure):
+    _fields_ = [("center", d3), ("normal", d3), ("axis1", d3), ("axis2", d3), ("half_size", C.c_double)]
+
+
+class laue_geometry(C.Structure):
+    _fields_ = [("n_rot", C.c_int32), ("n_det", C.c_int32), ("omega0", C.c_double),
+                ("domega", C.c_double), ("lambda_min", C.c_double), ("lambda_max", C.c_double),
+                ("det", laue_detector * MAX_DET)]
+
+
+class laue_planes(C.Structure):
+    _fields_ = [("n", C.c_int32), ("w", vp), ("d", vp), ("harmonic_prev", vp)]
+
+
+class laue_grains(C.Structure):
+    _fields_ = [("n", C.c_int32), ("q", vp), ("x", vp)]
+
+
+class laue_obs_spots(C.Structure):
+    _fields_ = [("n", C.c_int64), ("p1", vp), ("p2", vp), ("block_off", vp)]
+
+
+class laue_model_spots(C.Structure):
+    _fields_ = [("n", C.c_int64), ("plane", vp), ("grain", vp), ("block", vp), ("s1", vp),
+                ("s2", vp), ("vn", vp), ("v1", vp), ("v2", vp), ("lam", vp), ("flags", vp),
+                ("block_off", vp)]
+
+
+class laue_ot_params(C.Structure):
+    _fields_ = [("eps", C.c_double), ("distance", C.c_double), ("c_out", C.c_double),
+                ("c_unm", C.c_double), ("c_sink", C.c_double), ("t_b", C.c_double),
+                ("tol", C.c_double), ("n_max", C.c_int32), ("chunk", C.c_int32)]
+
+
+class laue_potentials(C.Structure):
+    _fields_ = [("f", vp), ("g", vp), ("f0", C.c_double), ("g0", C.c_double)]
+
+
+class laue_ot_stats(C.Structure):
+    _fields_ = [("n_iter", C.c_int32), ("converged", C.c_int32), ("err", C.c_double)]
+
+
+class laue_gn_params(C.Structure):
+    _fields_ = [("k_gn", C.c_int32), ("mu_rel", C.c_double)]
+
+
+class laue_em_params(C.Structure):
+    _fields_ = [("ot", laue_ot_params), ("gn", laue_gn_params), ("eps_start", C.c_double),
+                ("eps_end", C.c_double), ("n_stages", C.c_int32), ("iters_per_stage", C.c_int32)]
+
+
+class laue_em_stats(C.Structure):
+    _fields_ = [("n_em_iter", C.c_int32), ("sinkhorn_iters", C.c_int64),
+                ("cost_entries", C.c_int64), ("not_converged", C.c_int32), ("last_err", C.c_double),
+                ("sinkhorn_ms", C.c_double), ("sinkhorn_passes", C.c_int64),
+                ("sinkhorn_entries", C.c_int64), ("mstep_ms", C.c_double),
+                ("mstep_entries", C.c_int64)]
+
+
+class laue_assignments(C.Structure):
+    _fields_ = [("j_star", vp), ("grain", vp), ("q_star", vp), ("q_out", vp)]
+
+
+P = C.POINTER
+SIGNATURES = {
+    "laue_version": (C.c_int, []),
+    "laue_last_error": (C.c_char_p, []),
+    "laue_planes_cubic": (C.c_int, [C.c_double, C.c_char, C.c_int, P(C.c_int32), vp, vp, vp, vp]),
+    "laue_forward_workspace_size": (C.c_size_t, [P(laue_geometry), C.c_int32, C.c_int32]),
+    "laue_forward_enumerate": (C.c_int, [P(laue_geometry), P(laue_planes), P(laue_grains), C.c_int,
+                                         P(laue_model_spots), P(C.c_int64), vp, C.c_size_t, vp]),
+    "laue_forward_eval": (C.c_int, [P(laue_geometry), P(laue_planes), P(laue_grains),
+                                    P(laue_model_spots), vp, C.c_size_t, vp]),
+    "laue_simulate_workspace_size": (C.c_size_t, [P(laue_geometry), C.c_int32, C.c_int32, C.c_int64,
+                                                  C.c_int64]),
+    "laue_simulate": (C.c_int, [P(laue_geometry), P(laue_planes), P(laue_grains), C.c_double,
+                                C.c_double, C.c_double, C.c_uint64, C.c_int64, vp, vp, vp, vp, vp,
+                                P(C.c_int64), vp, C.c_size_t, vp]),
+    "laue_sinkhorn_workspace_size": (C.c_size_t, [P(laue_geometry), C.c_int64, C.c_int64, C.c_int32]),
+    "laue_sinkhorn": (C.c_int, [P(laue_geometry), P(laue_obs_spots), P(laue_model_spots),
+                                P(laue_ot_params), P(laue_potentials), P(laue_ot_stats), vp,
+                                C.c_size_t, vp]),
+    "laue_plan_block": (C.c_int, [P(laue_geometry), P(laue_obs_spots), P(laue_model_spots),
+                                  P(laue_ot_params), P(laue_potentials), C.c_int32, vp, vp]),
+    "laue_cost_block": (C.c_int, [P(laue_geometry), P(laue_obs_spots), P(laue_model_spots),
+                                  C.c_double, C.c_int32, vp, vp]),
+    "laue_mstep": (C.c_int, [P(laue_geometry), P(laue_planes), P(laue_obs_spots),
+                             P(laue_model_spots), P(laue_ot_params), P(laue_potentials),
+                             P(laue_gn_params), P(laue_grains), vp, vp, C.c_size_t, vp]),
+    "laue_em": (C.c_int, [P(laue_geometry), P(laue_planes), P(laue_obs_spots), P(laue_model_spots),
+                          P(laue_em_params), P(laue_grains), P(laue_potentials),
+                          P(laue_assignments), P(laue_em_stats), vp, C.c_size_t, vp]),
+}
+
+
+def load(path: str = LIB_PATH) -> C.CDLL:
+    lib = C.CDLL(path)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib

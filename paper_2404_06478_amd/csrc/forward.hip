@@ -1,0 +1,677 @@
+// Forward model kernels (paper Sec. 3.2-3.3) and the synthetic-spot simulator
+// (Sec. 3.3.1).
+#include <algorithm>
+#include <cmath>
+
+#include "common.h"
+
+namespace laue {
+
+constexpr int kMaxPlanes = 1024;
+
+// ---------------------------------------------------------------- grains
+
+__global__ void k_grain_prep(const double *__restrict__ q, const double *__restrict__ x, int n,
+                             GrainF *__restrict__ out) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double w = q[4 * i], a = q[4 * i + 1], b = q[4 * i + 2], c = q[4 * i + 3];
+    double nrm = sqrt(w * w + a * a + b * b + c * c);
+    w /= nrm; a /= nrm; b /= nrm; c /= nrm;
+    double R[9] = {1 - 2 * (b * b + c * c), 2 * (a * b - w * c),     2 * (a * c + w * b),
+                   2 * (a * b + w * c),     1 - 2 * (a * a + c * c), 2 * (b * c - w * a),
+                   2 * (a * c - w * b),     2 * (b * c + w * a),     1 - 2 * (a * a + b * b)};
+    for (int k = 0; k < 9; ++k) out[i].R[k] = static_cast<float>(R[k]);
+    for (int k = 0; k < 3; ++k) out[i].x[k] = static_cast<float>(x[3 * i + k]);
+}
+
+int prep_grains(const laue_grains *g, GrainF *dst, hipStream_t s) {
+    if (g->n == 0) return LAUE_OK;
+    k_grain_prep<<<(g->n + 255) / 256, 256, 0, s>>>(g->q, g->x, g->n, dst);
+    LAUE_CHECK_HIP(hipGetLastError());
+    return LAUE_OK;
+}
+
+// ---------------------------------------------------------------- enumerate
+
+// One wave per (grain n, rotation t).  Phase 1 marks, per detector, every
+// plane whose spot is in band and on the detector (the literal set).  Phase 2
+// applies the harmonic merge (drop a plane if a lower-order parallel plane is
+// visible on the same detector) and either counts (pass 0) or writes (pass 1)
+// the kept spots in (t, d, n, m) order.
+__global__ __launch_bounds__(64) void k_enumerate(
+    const GeomF *__restrict__ Gp, const float *__restrict__ W, const float *__restrict__ Dsp,
+    const int *__restrict__ prev, int M, const GrainF *__restrict__ grains, int N, int merge,
+    int pass, int *__restrict__ counts, const int64_t *__restrict__ offs, int *__restrict__ o_plane,
+    int *__restrict__ o_grain, int *__restrict__ o_block, float *__restrict__ o_s1,
+    float *__restrict__ o_s2, float *__restrict__ o_vn, float *__restrict__ o_v1,
+    float *__restrict__ o_v2, float *__restrict__ o_lam, uint8_t *__restrict__ o_flags) {
+    const GeomF &G = *Gp;
+    const int item = blockIdx.x;
+    const int n = item % N;
+    const int t = item / N;
+    const int lane = threadIdx.x;
+    __shared__ uint8_t vis[LAUE_MAX_DET][kMaxPlanes];
+    const GrainF gr = grains[n];
+    const float c = G.cs[t][0], s = G.cs[t][1];
+    const int D = G.n_det;
+    for (int m = lane; m < M; m += 64) {
+        float wx = W[3 * m], wy = W[3 * m + 1], wz = W[3 * m + 2];
+        for (int d = 0; d < D; ++d) {
+            SpotGeo o = spot_geometry(G, G.det[d], gr.R, gr.x, c, s, wx, wy, wz, Dsp[m]);
+            vis[d][m] = (o.inband && o.on) ? 1 : 0;
+        }
+    }
+    __syncthreads();
+    for (int d = 0; d < D; ++d) {
+        const int slot = (t * D + d) * N + n;
+        int64_t base = pass ? offs[slot] : 0;
+        int running = 0;
+        for (int m0 = 0; m0 < M; m0 += 64) {
+            int m = m0 + lane;
+            bool keep = (m < M) && vis[d][m];
+            if (merge && keep) {
+                int a = prev[m];
+                for (int hop = 0; hop < 16 && a >= 0 && a < M; ++hop) {
+                    if (vis[d][a]) { keep = false; break; }
+                    a = prev[a];
+                }
+            }
+            unsigned long long bal = __ballot(keep);
+            if (pass && keep) {
+                unsigned long long lower = bal & ((1ull << lane) - 1ull);
+                int64_t pos = base + running + __popcll(lower);
+                SpotGeo o = spot_geometry(G, G.det[d], gr.R, gr.x, c, s, W[3 * m], W[3 * m + 1],
+                                          W[3 * m + 2], Dsp[m]);
+                o_plane[pos] = m;
+                o_grain[pos] = n;
+                o_block[pos] = t * D + d;
+                if (o_s1) {
+                    o_s1[pos] = o.s1;
+                    o_s2[pos] = o.s2;
+                    o_vn[pos] = o.vn;
+                    o_v1[pos] = o.v1;
+                    o_v2[pos] = o.v2;
+                }
+                if (o_lam) o_lam[pos] = o.lam;
+                if (o_flags) o_flags[pos] = o.flags;
+            }
+            running += __popcll(bal);
+        }
+        if (!pass && lane == 0) counts[slot] = running;
+    }
+}
+
+// Exclusive scan of L counts by one workgroup; out has L + 1 entries.  Also
+// extracts per-block offsets: blk[b] = out[b * stride] for b <= n_blocks.
+__global__ __launch_bounds__(1024) void k_scan(const int *__restrict__ in, int64_t *__restrict__ out,
+                                               int64_t L, int64_t *__restrict__ blk, int n_blocks,
+                                               int64_t stride) {
+    __shared__ int64_t part[1024];
+    const int tid = threadIdx.x;
+    const int64_t chunk = (L + 1023) / 1024;
+    const int64_t b0 = std::min<int64_t>(L, tid * chunk), b1 = std::min<int64_t>(L, b0 + chunk);
+    int64_t sum = 0;
+    for (int64_t i = b0; i < b1; ++i) sum += in[i];
+    part[tid] = sum;
+    __syncthreads();
+    if (tid == 0) {
+        int64_t run = 0;
+        for (int k = 0; k < 1024; ++k) {
+            int64_t v = part[k];
+            part[k] = run;
+            run += v;
+        }
+    }
+    __syncthreads();
+    int64_t run = part[tid];
+    for (int64_t i = b0; i < b1; ++i) {
+        out[i] = run;
+        run += in[i];
+    }
+    if (tid == 1023) out[L] = run;
+    __syncthreads();
+    if (blk)
+        for (int b = tid; b <= n_blocks; b += 1024) blk[b] = out[std::min<int64_t>(L, b * stride)];
+}
+
+// ---------------------------------------------------------------- eval
+
+__global__ void k_eval(const GeomF *__restrict__ Gp, const float *__restrict__ W,
+                       const float *__restrict__ Dsp, const GrainF *__restrict__ grains,
+                       const int *__restrict__ plane, const int *__restrict__ grain,
+                       const int *__restrict__ block, int64_t n, int n_planes, int n_grains,
+                       float *__restrict__ o_s1,
+                       float *__restrict__ o_s2, float *__restrict__ o_vn,
+                       float *__restrict__ o_v1, float *__restrict__ o_v2,
+                       float *__restrict__ o_lam, Col8 *__restrict__ cols) {
+    int64_t j = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    const GeomF &G = *Gp;
+    int m = plane[j], g = grain[j], b = block[j];
+    if (m < 0 || m >= n_planes || g < 0 || g >= n_grains || b < 0 || b >= G.n_rot * G.n_det) {
+        // invalid ids: no geometry (NaN) rather than an out-of-bounds read
+        const float nan = __builtin_nanf("");
+        if (o_s1) { o_s1[j] = nan; o_s2[j] = nan; o_vn[j] = nan; o_v1[j] = nan; o_v2[j] = nan; }
+        if (o_lam) o_lam[j] = nan;
+        if (cols) cols[j] = Col8{nan, nan, nan, nan, nan, nan, nan, 0.0f};
+        return;
+    }
+    int t = b / G.n_det, d = b - t * G.n_det;
+    const GrainF &gr = grains[g];
+    SpotGeo o = spot_geometry(G, G.det[d], gr.R, gr.x, G.cs[t][0], G.cs[t][1], W[3 * m],
+                              W[3 * m + 1], W[3 * m + 2], Dsp[m]);
+    if (o_s1) {
+        o_s1[j] = o.s1;
+        o_s2[j] = o.s2;
+        o_vn[j] = o.vn;
+        o_v1[j] = o.v1;
+        o_v2[j] = o.v2;
+    }
+    if (o_lam) o_lam[j] = o.lam;
+    if (cols) {
+        Col8 c;
+        c.s1 = o.s1;
+        c.s2 = o.s2;
+        c.v1 = o.v1;
+        c.v2 = o.v2;
+        c.vn2 = o.vn * o.vn;
+        c.vv = fmaf(o.v2, o.v2, fmaf(o.v1, o.v1, o.vn * o.vn));
+        c.vn = o.vn;
+        c.pad = 0.0f;
+        cols[j] = c;
+    }
+}
+
+__global__ void k_pack_cols(const float *__restrict__ s1, const float *__restrict__ s2,
+                            const float *__restrict__ vn, const float *__restrict__ v1,
+                            const float *__restrict__ v2, int64_t n, Col8 *__restrict__ cols) {
+    int64_t j = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    Col8 c;
+    c.s1 = s1[j];
+    c.s2 = s2[j];
+    c.v1 = v1[j];
+    c.v2 = v2[j];
+    c.vn2 = vn[j] * vn[j];
+    c.vv = fmaf(v2[j], v2[j], fmaf(v1[j], v1[j], vn[j] * vn[j]));
+    c.vn = vn[j];
+    c.pad = 0.0f;
+    cols[j] = c;
+}
+
+int launch_eval(const GeomF *dG, const laue_planes *pl, const GrainF *dgr, int n_grains,
+                const int *plane, const int *grain, const int *block, int64_t n, float *s1,
+                float *s2, float *vn, float *v1, float *v2, float *lam, Col8 *cols, hipStream_t s) {
+    if (n == 0) return LAUE_OK;
+    int64_t nb = (n + 255) / 256;
+    k_eval<<<static_cast<unsigned>(nb), 256, 0, s>>>(dG, pl->w, pl->d, dgr, plane, grain, block,
+                                                     n, pl->n, n_grains, s1, s2, vn, v1, v2, lam,
+                                                     cols);
+    LAUE_CHECK_HIP(hipGetLastError());
+    return LAUE_OK;
+}
+
+int launch_pack(const laue_model_spots *m, Col8 *cols, hipStream_t s) {
+    if (m->n == 0) return LAUE_OK;
+    int64_t nb = (m->n + 255) / 256;
+    k_pack_cols<<<static_cast<unsigned>(nb), 256, 0, s>>>(m->s1, m->s2, m->vn, m->v1, m->v2, m->n,
+                                                          cols);
+    LAUE_CHECK_HIP(hipGetLastError());
+    return LAUE_OK;
+}
+
+int validate_planes(const laue_planes *p) {
+    LAUE_REQUIRE(p != nullptr && p->w && p->d && p->harmonic_prev, LAUE_EINVAL,
+                 "planes or one of its arrays is NULL");
+    LAUE_REQUIRE(p->n >= 1 && p->n <= kMaxPlanes, LAUE_EINVAL, "n_planes must be in 1..1024");
+    return LAUE_OK;
+}
+
+int validate_grains(const laue_grains *g) {
+    LAUE_REQUIRE(g != nullptr && g->n >= 0, LAUE_EINVAL, "grains is NULL or n < 0");
+    LAUE_REQUIRE(g->n == 0 || (g->q && g->x), LAUE_EINVAL, "grain arrays are NULL");
+    return LAUE_OK;
+}
+
+struct EnumWs {
+    GeomF *geom;
+    GrainF *grains;
+    int *counts;
+    int64_t *offs;
+    int64_t *blk;
+};
+
+static size_t carve_enum(Carver &cv, EnumWs &w, const laue_geometry *g, int n_grains) {
+    int64_t L = static_cast<int64_t>(g->n_rot) * g->n_det * std::max(n_grains, 1);
+    w.geom = cv.take<GeomF>(1);
+    w.grains = cv.take<GrainF>(std::max(n_grains, 1));
+    w.counts = cv.take<int>(L);
+    w.offs = cv.take<int64_t>(L + 1);
+    w.blk = cv.take<int64_t>(g->n_rot * g->n_det + 1);
+    return cv.size();
+}
+
+// Count pass, scan and block offsets of the (merged) visible set.  Leaves
+// host_blk filled; returns the total in *total.
+static int enumerate_count(const laue_geometry *geom, const laue_planes *planes,
+                           const laue_grains *grains, int merge, EnumWs &w,
+                           std::vector<int64_t> &host_blk, int64_t *total, hipStream_t s) {
+    GeomF hg;
+    make_geomf(geom, &hg);
+    LAUE_CHECK_HIP(hipMemcpyAsync(w.geom, &hg, sizeof(GeomF), hipMemcpyHostToDevice, s));
+    int rc = prep_grains(grains, w.grains, s);
+    if (rc) return rc;
+    const int N = grains->n;
+    const int nb = geom->n_rot * geom->n_det;
+    host_blk.assign(nb + 1, 0);
+    if (N == 0) {
+        *total = 0;
+        LAUE_CHECK_HIP(hipStreamSynchronize(s));
+        return LAUE_OK;
+    }
+    const int64_t L = static_cast<int64_t>(geom->n_rot) * geom->n_det * N;
+    k_enumerate<<<geom->n_rot * N, 64, 0, s>>>(w.geom, planes->w, planes->d, planes->harmonic_prev,
+                                               planes->n, w.grains, N, merge, 0, w.counts, nullptr,
+                                               nullptr, nullptr, nullptr, nullptr, nullptr,
+                                               nullptr, nullptr, nullptr, nullptr, nullptr);
+    LAUE_CHECK_HIP(hipGetLastError());
+    k_scan<<<1, 1024, 0, s>>>(w.counts, w.offs, L, w.blk, nb, N);
+    LAUE_CHECK_HIP(hipGetLastError());
+    LAUE_CHECK_HIP(hipMemcpyAsync(host_blk.data(), w.blk, (nb + 1) * sizeof(int64_t),
+                                  hipMemcpyDeviceToHost, s));
+    LAUE_CHECK_HIP(hipStreamSynchronize(s));
+    *total = host_blk[nb];
+    return LAUE_OK;
+}
+
+// ---------------------------------------------------------------- simulate
+
+// Philox4x32-10 (Salmon et al., SC'11), from its published definition.
+__device__ __forceinline__ void philox(uint32_t c[4], uint32_t k0, uint32_t k1) {
+    for (int r = 0; r < 10; ++r) {
+        uint64_t p0 = static_cast<uint64_t>(0xD2511F53u) * c[0];
+        uint64_t p1 = static_cast<uint64_t>(0xCD9E8D57u) * c[2];
+        uint32_t hi0 = static_cast<uint32_t>(p0 >> 32), lo0 = static_cast<uint32_t>(p0);
+        uint32_t hi1 = static_cast<uint32_t>(p1 >> 32), lo1 = static_cast<uint32_t>(p1);
+        uint32_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
+        c[0] = n0;
+        c[1] = lo1;
+        c[2] = n2;
+        c[3] = lo0;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+}
+
+__device__ __forceinline__ double u01(uint32_t v) { return (static_cast<double>(v) + 0.5) * (1.0 / 4294967296.0); }
+
+// Noisy ray and detector hit of each visible spot (FP64; the simulator is
+// not on the hot path).  keep = tau > 0 and inside the detector square.
+__global__ void k_sim_noise(const laue_geometry G, const float *__restrict__ W,
+                            const double *__restrict__ q, const double *__restrict__ x,
+                            const int *__restrict__ plane, const int *__restrict__ grain,
+                            const int *__restrict__ block, int64_t n, double sig, uint32_t k0,
+                            uint32_t k1, double *__restrict__ o_p1, double *__restrict__ o_p2,
+                            uint8_t *__restrict__ keep, uint64_t *__restrict__ key) {
+    int64_t j = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    int m = plane[j], g = grain[j], b = block[j];
+    int t = b / G.n_det, d = b - t * G.n_det;
+    double qw = q[4 * g], qa = q[4 * g + 1], qb = q[4 * g + 2], qc = q[4 * g + 3];
+    double qn = sqrt(qw * qw + qa * qa + qb * qb + qc * qc);
+    qw /= qn; qa /= qn; qb /= qn; qc /= qn;
+    double R[9] = {1 - 2 * (qb * qb + qc * qc), 2 * (qa * qb - qw * qc), 2 * (qa * qc + qw * qb),
+                   2 * (qa * qb + qw * qc), 1 - 2 * (qa * qa + qc * qc), 2 * (qb * qc - qw * qa),
+                   2 * (qa * qc - qw * qb), 2 * (qb * qc + qw * qa), 1 - 2 * (qa * qa + qb * qb)};
+    double wx = W[3 * m], wy = W[3 * m + 1], wz = W[3 * m + 2];
+    double vx = R[0] * wx + R[1] * wy + R[2] * wz;
+    double vy = R[3] * wx + R[4] * wy + R[5] * wz;
+    double vz = R[6] * wx + R[7] * wy + R[8] * wz;
+    double om = G.omega0 + G.domega * t, c = cos(om), s = sin(om);
+    double ux = c * vx - s * vy, uy = s * vx + c * vy, uz = vz;
+    double r[3] = {1 - 2 * ux * ux, -2 * ux * uy, -2 * ux * uz};
+    double y[3] = {c * x[3 * g] - s * x[3 * g + 1], s * x[3 * g] + c * x[3 * g + 1], x[3 * g + 2]};
+    uint32_t ctr[4] = {static_cast<uint32_t>(g), static_cast<uint32_t>(t),
+                       static_cast<uint32_t>(m + 65536 * d), 1u};
+    philox(ctr, k0, k1);
+    double z[3];
+    {
+        double rad = sqrt(-2.0 * log(u01(ctr[0]))), ang = 2.0 * M_PI * u01(ctr[1]);
+        z[0] = rad * cos(ang);
+        z[1] = rad * sin(ang);
+        double rad2 = sqrt(-2.0 * log(u01(ctr[2]))), ang2 = 2.0 * M_PI * u01(ctr[3]);
+        z[2] = rad2 * cos(ang2);
+    }
+    double rn[3];
+    double nn = 0;
+    for (int k = 0; k < 3; ++k) {
+        rn[k] = r[k] + sig * z[k];
+        nn += rn[k] * rn[k];
+    }
+    nn = sqrt(nn);
+    for (int k = 0; k < 3; ++k) rn[k] /= nn;
+    const laue_detector &D = G.det[d];
+    double den = 0, num = 0;
+    for (int k = 0; k < 3; ++k) {
+        den += D.normal[k] * rn[k];
+        num += D.normal[k] * (D.center[k] - y[k]);
+    }
+    double tau = num / den;
+    double p1 = 0, p2 = 0;
+    for (int k = 0; k < 3; ++k) {
+        double rel = y[k] + tau * rn[k] - D.center[k];
+        p1 += D.axis1[k] * rel;
+        p2 += D.axis2[k] * rel;
+    }
+    o_p1[j] = p1;
+    o_p2[j] = p2;
+    keep[j] = (tau > 0 && fmax(fabs(p1), fabs(p2)) < D.half_size) ? 1 : 0;
+    uint32_t kc[4] = {static_cast<uint32_t>(g), static_cast<uint32_t>(t),
+                      static_cast<uint32_t>(m + 65536 * d), 3u};
+    philox(kc, k0, k1);
+    key[j] = (static_cast<uint64_t>(kc[0]) << 32) | kc[1];
+}
+
+// Kept true spots per block (one workgroup per block, fixed order).
+__global__ __launch_bounds__(256) void k_sim_count(const int64_t *__restrict__ sblk,
+                                                   const uint8_t *__restrict__ keep,
+                                                   int *__restrict__ n_true) {
+    int b = blockIdx.x;
+    __shared__ int part[256];
+    int c = 0;
+    for (int64_t j = sblk[b] + threadIdx.x; j < sblk[b + 1]; j += 256) c += keep[j];
+    part[threadIdx.x] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int s = 0;
+        for (int k = 0; k < 256; ++k) s += part[k];
+        n_true[b] = s;
+    }
+}
+
+// Per block: gather kept true spots (in visible-set order) and outliers, rank
+// them by (key, source, index) and scatter to the output at the block offset.
+__global__ __launch_bounds__(256) void k_sim_emit(
+    const laue_geometry G, const int64_t *__restrict__ sblk, const uint8_t *__restrict__ keep,
+    const double *__restrict__ np1, const double *__restrict__ np2, const uint64_t *__restrict__ key,
+    const int *__restrict__ s_plane, const int *__restrict__ s_grain, const int64_t *__restrict__ oblk,
+    const int *__restrict__ n_out, uint32_t k0, uint32_t k1, uint64_t *__restrict__ tkey,
+    int *__restrict__ tsrc, float *__restrict__ tp1, float *__restrict__ tp2,
+    int *__restrict__ tgr, int *__restrict__ tpl, float *__restrict__ p1, float *__restrict__ p2,
+    int *__restrict__ o_grain, int *__restrict__ o_plane) {
+    const int b = blockIdx.x;
+    const int t = b / G.n_det, d = b - t * G.n_det;
+    const int64_t base = oblk[b];
+    __shared__ int part[256];
+    // compaction of kept true spots: thread-contiguous chunks, then a prefix
+    const int64_t s0 = sblk[b], s1 = sblk[b + 1], ns = s1 - s0;
+    const int64_t chunk = (ns + 255) / 256;
+    const int64_t c0 = s0 + std::min<int64_t>(ns, threadIdx.x * chunk);
+    const int64_t c1 = s0 + std::min<int64_t>(ns, (threadIdx.x + 1) * chunk);
+    int cnt = 0;
+    for (int64_t j = c0; j < c1; ++j) cnt += keep[j];
+    part[threadIdx.x] = cnt;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int run = 0;
+        for (int k = 0; k < 256; ++k) {
+            int v = part[k];
+            part[k] = run;
+            run += v;
+        }
+    }
+    __syncthreads();
+    int pos = part[threadIdx.x];
+    for (int64_t j = c0; j < c1; ++j) {
+        if (!keep[j]) continue;
+        int64_t o = base + pos++;
+        tkey[o] = key[j];
+        tsrc[o] = pos - 1;  // index among kept true spots
+        tp1[o] = static_cast<float>(np1[j]);
+        tp2[o] = static_cast<float>(np2[j]);
+        tgr[o] = s_grain[j];
+        tpl[o] = s_plane[j];
+    }
+    __syncthreads();
+    __shared__ int ntrue_s;
+    if (threadIdx.x == 255) ntrue_s = part[255] + cnt;
+    __syncthreads();
+    const int nt = ntrue_s;
+    const int no = n_out[b];
+    const double side = 2.0 * G.det[d].half_size;
+    for (int k = threadIdx.x; k < no; k += 256) {
+        uint32_t c[4] = {static_cast<uint32_t>(k), static_cast<uint32_t>(t),
+                         static_cast<uint32_t>(65536 * d), 2u};
+        philox(c, k0, k1);
+        uint32_t kc[4] = {static_cast<uint32_t>(k), static_cast<uint32_t>(t),
+                          static_cast<uint32_t>(65536 * d), 4u};
+        philox(kc, k0, k1);
+        int64_t o = base + nt + k;
+        tkey[o] = (static_cast<uint64_t>(kc[0]) << 32) | kc[1];
+        tsrc[o] = (1 << 30) + k;
+        tp1[o] = static_cast<float>((u01(c[0]) - 0.5) * side);
+        tp2[o] = static_cast<float>((u01(c[1]) - 0.5) * side);
+        tgr[o] = -1;
+        tpl[o] = -1;
+    }
+    __syncthreads();
+    const int tot = nt + no;
+    for (int a = threadIdx.x; a < tot; a += 256) {
+        const uint64_t ka = tkey[base + a];
+        const int sa = tsrc[base + a];
+        int rank = 0;
+        for (int c = 0; c < tot; ++c) {
+            uint64_t kb = tkey[base + c];
+            int sb = tsrc[base + c];
+            rank += (kb < ka) || (kb == ka && sb < sa);
+        }
+        int64_t o = base + rank;
+        p1[o] = tp1[base + a];
+        p2[o] = tp2[base + a];
+        o_grain[o] = tgr[base + a];
+        o_plane[o] = tpl[base + a];
+    }
+}
+
+}  // namespace laue
+
+using namespace laue;
+
+extern "C" size_t laue_forward_workspace_size(const laue_geometry *geom, int32_t n_planes,
+                                              int32_t n_grains) {
+    (void)n_planes;
+    if (!geom || validate_geometry(geom) != LAUE_OK || n_grains < 0) return 0;
+    Carver cv(nullptr);
+    EnumWs w;
+    return carve_enum(cv, w, geom, n_grains);
+}
+
+extern "C" int laue_forward_enumerate(const laue_geometry *geom, const laue_planes *planes,
+                                      const laue_grains *grains, int merge_harmonics,
+                                      laue_model_spots *out, int64_t *n_out, void *ws,
+                                      size_t ws_bytes, void *stream) {
+    clear_error();
+    int rc;
+    if ((rc = validate_geometry(geom)) || (rc = validate_planes(planes)) ||
+        (rc = validate_grains(grains)))
+        return rc;
+    LAUE_REQUIRE(out && n_out && out->block_off, LAUE_EINVAL, "output or n_out is NULL");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    Carver cv(ws);
+    EnumWs w;
+    size_t need = carve_enum(cv, w, geom, grains->n);
+    if ((rc = check_ws(ws, ws_bytes, need))) return rc;
+    std::vector<int64_t> hb;
+    int64_t total = 0;
+    if ((rc = enumerate_count(geom, planes, grains, merge_harmonics ? 1 : 0, w, hb, &total, s)))
+        return rc;
+    *n_out = total;
+    std::memcpy(out->block_off, hb.data(), hb.size() * sizeof(int64_t));
+    if (total > out->n) {
+        set_error("model-spot capacity " + std::to_string(out->n) + " < required " +
+                  std::to_string(total));
+        return LAUE_ECAPACITY;
+    }
+    if (total > 0) {
+        LAUE_REQUIRE(out->plane && out->grain && out->block && out->s1 && out->s2 && out->vn &&
+                         out->v1 && out->v2,
+                     LAUE_EINVAL, "model-spot arrays are NULL");
+        k_enumerate<<<geom->n_rot * grains->n, 64, 0, s>>>(
+            w.geom, planes->w, planes->d, planes->harmonic_prev, planes->n, w.grains, grains->n,
+            merge_harmonics ? 1 : 0, 1, nullptr, w.offs, out->plane, out->grain, out->block,
+            out->s1, out->s2, out->vn, out->v1, out->v2, out->lam, out->flags);
+        LAUE_CHECK_HIP(hipGetLastError());
+    }
+    out->n = total;
+    LAUE_CHECK_HIP(hipStreamSynchronize(s));
+    return LAUE_OK;
+}
+
+extern "C" int laue_forward_eval(const laue_geometry *geom, const laue_planes *planes,
+                                 const laue_grains *grains, laue_model_spots *spots, void *ws,
+                                 size_t ws_bytes, void *stream) {
+    clear_error();
+    int rc;
+    if ((rc = validate_geometry(geom)) || (rc = validate_planes(planes)) ||
+        (rc = validate_grains(grains)))
+        return rc;
+    LAUE_REQUIRE(spots && spots->n >= 0, LAUE_EINVAL, "spots is NULL");
+    LAUE_REQUIRE(spots->n == 0 || (spots->plane && spots->grain && spots->block && spots->s1 &&
+                                   spots->s2 && spots->vn && spots->v1 && spots->v2),
+                 LAUE_EINVAL, "spot arrays are NULL");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    Carver cv(ws);
+    EnumWs w;
+    size_t need = carve_enum(cv, w, geom, grains->n);
+    if ((rc = check_ws(ws, ws_bytes, need))) return rc;
+    GeomF hg;
+    make_geomf(geom, &hg);
+    LAUE_CHECK_HIP(hipMemcpyAsync(w.geom, &hg, sizeof(GeomF), hipMemcpyHostToDevice, s));
+    if ((rc = prep_grains(grains, w.grains, s))) return rc;
+    rc = launch_eval(w.geom, planes, w.grains, grains->n, spots->plane, spots->grain, spots->block, spots->n,
+                     spots->s1, spots->s2, spots->vn, spots->v1, spots->v2, spots->lam, nullptr, s);
+    if (rc) return rc;
+    // the geometry copy above is from a stack object: wait before returning
+    LAUE_CHECK_HIP(hipStreamSynchronize(s));
+    return LAUE_OK;
+}
+
+struct SimWs {
+    EnumWs e;
+    int *plane, *grain, *block;
+    double *np1, *np2;
+    uint8_t *keep;
+    uint64_t *key;
+    int *n_true, *n_out;
+    int64_t *oblk;
+    uint64_t *tkey;
+    int *tsrc, *tgr, *tpl;
+    float *tp1, *tp2;
+};
+
+static size_t carve_sim(Carver &cv, SimWs &w, const laue_geometry *g, int n_grains, int64_t n_true_max,
+                        int64_t n_obs_max) {
+    carve_enum(cv, w.e, g, n_grains);
+    int64_t S = std::max<int64_t>(n_true_max, 1), O = std::max<int64_t>(n_obs_max, 1);
+    int nb = g->n_rot * g->n_det;
+    w.plane = cv.take<int>(S);
+    w.grain = cv.take<int>(S);
+    w.block = cv.take<int>(S);
+    w.np1 = cv.take<double>(S);
+    w.np2 = cv.take<double>(S);
+    w.keep = cv.take<uint8_t>(S);
+    w.key = cv.take<uint64_t>(S);
+    w.n_true = cv.take<int>(nb);
+    w.n_out = cv.take<int>(nb);
+    w.oblk = cv.take<int64_t>(nb + 1);
+    w.tkey = cv.take<uint64_t>(O);
+    w.tsrc = cv.take<int>(O);
+    w.tgr = cv.take<int>(O);
+    w.tpl = cv.take<int>(O);
+    w.tp1 = cv.take<float>(O);
+    w.tp2 = cv.take<float>(O);
+    return cv.size();
+}
+
+extern "C" size_t laue_simulate_workspace_size(const laue_geometry *geom, int32_t n_planes,
+                                               int32_t n_grains, int64_t n_true_max,
+                                               int64_t n_obs_max) {
+    (void)n_planes;
+    if (!geom || validate_geometry(geom) != LAUE_OK || n_grains < 0) return 0;
+    Carver cv(nullptr);
+    SimWs w;
+    return carve_sim(cv, w, geom, n_grains, n_true_max, n_obs_max);
+}
+
+extern "C" int laue_simulate(const laue_geometry *geom, const laue_planes *planes,
+                             const laue_grains *truth, double sigma_mm, double distance,
+                             double outlier_frac, uint64_t seed, int64_t n_true_max,
+                             float *p1, float *p2, int32_t *grain, int32_t *plane,
+                             int64_t *block_off, int64_t *n_out, void *ws, size_t ws_bytes,
+                             void *stream) {
+    clear_error();
+    int rc;
+    if ((rc = validate_geometry(geom)) || (rc = validate_planes(planes)) ||
+        (rc = validate_grains(truth)))
+        return rc;
+    LAUE_REQUIRE(n_out && block_off, LAUE_EINVAL, "n_out or block_off is NULL");
+    LAUE_REQUIRE(std::isfinite(sigma_mm) && sigma_mm >= 0 && std::isfinite(distance) && distance > 0,
+                 LAUE_EINVAL, "sigma must be >= 0 and distance > 0");
+    LAUE_REQUIRE(std::isfinite(outlier_frac) && outlier_frac >= 0 && outlier_frac <= 100,
+                 LAUE_EINVAL, "bad outlier fraction");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int64_t cap = *n_out;
+    Carver cv(ws);
+    SimWs w;
+    size_t need = carve_sim(cv, w, geom, truth->n, n_true_max, cap);
+    if ((rc = check_ws(ws, ws_bytes, need))) return rc;
+    std::vector<int64_t> sb;
+    int64_t S = 0;
+    if ((rc = enumerate_count(geom, planes, truth, 1, w.e, sb, &S, s))) return rc;
+    if (S > n_true_max) {
+        *n_out = -S;
+        set_error("n_true_max " + std::to_string(n_true_max) + " < visible spots " + std::to_string(S));
+        return LAUE_ECAPACITY;
+    }
+    const int nb = geom->n_rot * geom->n_det;
+    const uint32_t k0 = static_cast<uint32_t>(seed & 0xffffffffu), k1 = static_cast<uint32_t>(seed >> 32);
+    std::vector<int> nt(nb, 0), no(nb, 0);
+    if (S > 0) {
+        k_enumerate<<<geom->n_rot * truth->n, 64, 0, s>>>(
+            w.e.geom, planes->w, planes->d, planes->harmonic_prev, planes->n, w.e.grains, truth->n, 1,
+            1, nullptr, w.e.offs, w.plane, w.grain, w.block, nullptr, nullptr, nullptr, nullptr,
+            nullptr, nullptr, nullptr);
+        LAUE_CHECK_HIP(hipGetLastError());
+        k_sim_noise<<<static_cast<unsigned>((S + 255) / 256), 256, 0, s>>>(
+            *geom, planes->w, truth->q, truth->x, w.plane, w.grain, w.block, S, sigma_mm / distance,
+            k0, k1, w.np1, w.np2, w.keep, w.key);
+        LAUE_CHECK_HIP(hipGetLastError());
+        k_sim_count<<<nb, 256, 0, s>>>(w.e.blk, w.keep, w.n_true);
+        LAUE_CHECK_HIP(hipGetLastError());
+        LAUE_CHECK_HIP(hipMemcpyAsync(nt.data(), w.n_true, nb * sizeof(int), hipMemcpyDeviceToHost, s));
+        LAUE_CHECK_HIP(hipStreamSynchronize(s));
+    }
+    std::vector<int64_t> ob(nb + 1, 0);
+    for (int b = 0; b < nb; ++b) {
+        no[b] = static_cast<int>(std::floor(outlier_frac * nt[b] + 0.5));
+        ob[b + 1] = ob[b] + nt[b] + no[b];
+    }
+    const int64_t total = ob[nb];
+    *n_out = total;
+    std::memcpy(block_off, ob.data(), (nb + 1) * sizeof(int64_t));
+    if (total > cap) {
+        set_error("observed-spot capacity " + std::to_string(cap) + " < required " + std::to_string(total));
+        return LAUE_ECAPACITY;
+    }
+    if (total == 0) return LAUE_OK;
+    LAUE_REQUIRE(p1 && p2 && grain && plane, LAUE_EINVAL, "output arrays are NULL");
+    LAUE_CHECK_HIP(hipMemcpyAsync(w.n_out, no.data(), nb * sizeof(int), hipMemcpyHostToDevice, s));
+    LAUE_CHECK_HIP(hipMemcpyAsync(w.oblk, ob.data(), (nb + 1) * sizeof(int64_t), hipMemcpyHostToDevice, s));
+    k_sim_emit<<<nb, 256, 0, s>>>(*geom, w.e.blk, w.keep, w.np1, w.np2, w.key, w.plane, w.grain,
+                                   w.oblk, w.n_out, k0, k1, w.tkey, w.tsrc, w.tp1, w.tp2, w.tgr,
+                                   w.tpl, p1, p2, grain, plane);
+    LAUE_CHECK_HIP(hipGetLastError());
+    LAUE_CHECK_HIP(hipStreamSynchronize(s));
+    return LAUE_OK;
+}

@@ -1,0 +1,67 @@
+"""Seeded synthetic problems for the parity tests: everything here is built by
+the oracle (simulation, model-spot sets, FP32-rounded column data) and then
+handed, unchanged, to both the oracle and the HIP library."""
+from __future__ import annotations
+
+import dataclasses
+
+import numpy as np
+
+import inputgen as ig
+from oracle import cost, crystal, forward, simulate
+
+
+@dataclasses.dataclass
+class Problem:
+    preset: object
+    planes: dict
+    geom: object
+    q_true: np.ndarray
+    x_true: np.ndarray
+    obs: dict            # p12 (FP32-exact FP64), block, offsets, grain, plane
+    q0: np.ndarray
+    x0: np.ndarray
+    model: dict          # oracle model-spot set at (q0, x0) with offsets
+    s12: np.ndarray      # FP32-exact column data at (q0, x0)
+    vloc: np.ndarray
+
+
+def make(preset, n_rot=None, n_grains=None, sigma=None, frac=None, seed_shift=0, perturb=(0.5, 0.5)):
+    p = preset
+    pl = crystal.cubic_planes(p.a, p.centering, p.n_max)
+    geom = forward.Geometry(p.n_rot if n_rot is None else n_rot, np.deg2rad(p.domega_deg),
+                            p.detectors, p.lam_min, p.lam_max)
+    q, x = ig.random_grains(p, n=n_grains, seed=p.seed + seed_shift)
+    sim = simulate.simulate(pl, q, x, geom, p.sigma_mm if sigma is None else sigma,
+                            p.outlier_frac if frac is None else frac, p.seed + seed_shift, p.distance)
+    sim["p12"] = ig.to_f32_exact(sim["p12"])
+    q0, x0 = ig.perturb_grains(q, x, perturb[0], perturb[1], p.seed + 17 + seed_shift)
+    model = forward.enumerate_visible(pl, q0, x0, geom)
+    model["offsets"] = forward.block_offsets(model["block"], geom.n_blocks)
+    ev = forward.eval_fixed(pl, q0, x0, geom, model["m"], model["n"], model["t"], model["det"])
+    s12 = ig.to_f32_exact(ev["s12"])
+    vloc = ig.to_f32_exact(cost.v_local(geom, model["det"], ev["v"]))
+    return Problem(p, pl, geom, q, x, sim, q0, x0, model, s12, vloc)
+
+
+def oracle_costs(P):
+    C = []
+    off, mo = P.obs["offsets"], P.model["offsets"]
+    for b in range(P.geom.n_blocks):
+        C.append(cost.chord_cost(P.obs["p12"][off[b]:off[b + 1]], P.s12[mo[b]:mo[b + 1]],
+                                 P.vloc[mo[b]:mo[b + 1]], P.preset.distance))
+    return C
+
+
+def gpu_objects(laue, P):
+    """Geometry, planes, detected spots and model spots (with the FP32 column
+    data of the problem) for the HIP library."""
+    p = P.preset
+    geom = laue.make_geometry(P.geom.n_rot, np.deg2rad(p.domega_deg), p.detectors, p.lam_min, p.lam_max)
+    planes = laue.laue_planes_cubic(p.a, p.centering, p.n_max)
+    obs = laue.ObsSpots.from_numpy(P.obs["p12"], P.obs["offsets"])
+    m = P.model
+    model = laue.ModelSpots.from_arrays(P.geom.n_blocks, m["offsets"], m["m"], m["n"], m["block"],
+                                        P.s12[:, 0], P.s12[:, 1], P.vloc[:, 0], P.vloc[:, 1],
+                                        P.vloc[:, 2])
+    return geom, planes, obs, model

@@ -1,0 +1,71 @@
+"""CPU checks of the C-ABI library: it loads, exports every symbol the header
+declares, and its host-only helper agrees with the oracle's plane lists."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import crystal
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "laueot.h")
+LIB = os.path.join(ROOT, "paper_2404_06478_amd", "liblaueot.so")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(laue_[a-z_0-9]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        pytest.fail("liblaueot.so is not built (python -m paper_2404_06478_amd.build)")
+    from paper_2404_06478_amd import _abi
+    return _abi.load(LIB)
+
+
+def test_exports_every_declared_symbol(lib):
+    names = _declared()
+    assert len(names) >= 14
+    for n in names:
+        assert hasattr(lib, n), n
+    from paper_2404_06478_amd import _abi
+    assert set(names) == set(_abi.SIGNATURES), "binding and header disagree"
+
+
+def test_version(lib):
+    assert lib.laue_version() == 100
+
+
+@pytest.mark.parametrize("a,cen,nmax", [(2.87, "I", 14), (2.87, "I", 30), (3.52, "F", 40), (4.05, "F", 30)])
+def test_plane_list_matches_oracle(lib, a, cen, nmax):
+    n = ctypes.c_int32()
+    assert lib.laue_planes_cubic(a, cen.encode(), nmax, ctypes.byref(n), None, None, None, None) == 0
+    hkl = np.zeros((n.value, 3), np.int32)
+    w = np.zeros((n.value, 3), np.float32)
+    d = np.zeros(n.value, np.float32)
+    prev = np.zeros(n.value, np.int32)
+    assert lib.laue_planes_cubic(a, cen.encode(), nmax, ctypes.byref(n), hkl.ctypes.data,
+                                 w.ctypes.data, d.ctypes.data, prev.ctypes.data) == 0
+    ref = crystal.cubic_planes(a, cen, nmax)
+    assert np.array_equal(hkl, ref["hkl"])
+    assert np.array_equal(prev, ref["harmonic_prev"])
+    assert np.array_equal(w, ref["w"].astype(np.float32))
+    assert np.array_equal(d, ref["d"].astype(np.float32))
+
+
+def test_bad_arguments_are_rejected(lib):
+    n = ctypes.c_int32()
+    assert lib.laue_planes_cubic(2.87, b"X", 14, ctypes.byref(n), None, None, None, None) == -1
+    assert b"centering" in lib.laue_last_error()
+    assert lib.laue_planes_cubic(-1.0, b"I", 14, ctypes.byref(n), None, None, None, None) == -1
+    assert lib.laue_planes_cubic(2.87, b"I", 14, None, None, None, None, None) == -1
+    from paper_2404_06478_amd import _abi
+    g = _abi.laue_geometry()
+    g.n_rot = 0
+    assert lib.laue_forward_workspace_size(ctypes.byref(g), 10, 10) == 0
+    assert lib.laue_sinkhorn_workspace_size(ctypes.byref(g), 10, 10, 1) == 0
