@@ -138,30 +138,34 @@ __device__ __forceinline__ SpotGeo spot_geometry(const GeomF &G, const DetF &D, 
 }
 
 // Packed column of the streamed cost (one model spot), 32 bytes:
-// detector-local position, in-plane ray components, squared normal
-// component, squared length, normal component.
+// detector-local position, in-plane ray components, |v|^2, |v|^4 and the
+// normal component of the ray vector v = tau r.
 struct Col8 {
-    float s1, s2, v1, v2, vn2, vv, vn, pad;
+    float s1, s2, v1, v2, vv, vv2, vn, pad;
 };
 
-// Exponent (in log2 units) of one plan entry:
-//   base - K * c' with c = 2 D^2 c' the chord cost D^2 ||rhat - r||^2,
-// computed from the in-plane difference (p - s) without the 1 - cos
-// cancellation:  c' = |v x d|^2 / (|v|^2 |d|^2 + (v.d) |v||d|), d = v + (p - s).
+// Exponent (in log2 units) of one plan entry:  base - K * c'  with
+// c = 2 D^2 c' the chord cost D^2 ||rhat - r||^2 (Sec. 4, L_ij up to a
+// constant).  With v the model ray vector, delta = p - s the in-plane
+// difference (exact when p and s are close) and d = v + delta:
+//   c' = |v x d|^2 / (|v|^2 |d|^2 + (v.d) |v| |d|)
+// which avoids the cancellation of 1 - rhat.r.  Since delta lies in the
+// detector plane, |v x d|^2 = |v x delta|^2 = |v|^2 |delta|^2 - (v.delta)^2 and
+// |v|^2 |d|^2 = |v|^4 + |v|^2 (2 v.delta + |delta|^2); neither cancels badly
+// because the normal component of v is at least ~0.7 |v| on the detectors.
+// 17 VALU + sqrt, rcp and exp per entry in the passes (a = |v|^2, a2 = |v|^4).
 __device__ __forceinline__ float entry_exponent(float p1, float p2, float s1, float s2, float v1,
-                                                float v2, float vn2, float vv, float K,
-                                                float base) {
-    float dy = p1 - s1;
-    float dz = p2 - s2;
-    float cn = fmaf(-v2, dy, v1 * dz);
-    float d2 = fmaf(dz, dz, dy * dy);
-    float x2 = fmaf(vn2, d2, cn * cn);
-    float vd = fmaf(v2, dz, v1 * dy);
-    float vdd = vv + vd;
-    float dd = (vd + d2) + vdd;
-    float P = vv * dd;
-    float den = fmaf(vdd, __builtin_amdgcn_sqrtf(P), P);
-    float cp = x2 * __builtin_amdgcn_rcpf(den);
+                                                float v2, float a, float a2, float K, float base) {
+    const float dy = p1 - s1;
+    const float dz = p2 - s2;
+    const float e = fmaf(dz, dz, dy * dy);        // |delta|^2
+    const float b = fmaf(v2, dz, v1 * dy);        // v.delta
+    const float x2 = fmaf(a, e, -(b * b));        // |v x delta|^2
+    const float vdd = a + b;                      // v.d
+    const float w = fmaf(2.0f, b, e);             // |d|^2 - |v|^2
+    const float P = fmaf(a, w, a2);               // |v|^2 |d|^2
+    const float den = fmaf(vdd, __builtin_amdgcn_sqrtf(P), P);
+    const float cp = x2 * __builtin_amdgcn_rcpf(den);
     return fmaf(-K, cp, base);
 }
 

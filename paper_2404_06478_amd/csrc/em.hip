@@ -148,7 +148,7 @@ __global__ __launch_bounds__(64) void k_row(const Item *__restrict__ items,
         for (int j = j0; j < j1; ++j) {
             const Col8 c = cols[j];
             const float base = fmaf(G[j], kx, fk);
-            a += fast_exp2(entry_exponent(p1, p2, c.s1, c.s2, c.v1, c.v2, c.vn2, c.vv, K, base));
+            a += fast_exp2(entry_exponent(p1, p2, c.s1, c.s2, c.v1, c.v2, c.vv, c.vv2, K, base));
         }
         acc += static_cast<double>(a);
     }
@@ -161,14 +161,14 @@ __global__ __launch_bounds__(64) void k_row(const Item *__restrict__ items,
         float mx = static_cast<float>(eb);
         for (int j = it.c0; j < it.c1; ++j) {
             const Col8 c = cols[j];
-            mx = fmaxf(mx, entry_exponent(p1, p2, c.s1, c.s2, c.v1, c.v2, c.vn2, c.vv, K,
+            mx = fmaxf(mx, entry_exponent(p1, p2, c.s1, c.s2, c.v1, c.v2, c.vv, c.vv2, K,
                                           fmaf(G[j], kx, fk)));
         }
         double s2 = exp2(eb - mx);
         for (int j = it.c0; j < it.c1; ++j) {
             const Col8 c = cols[j];
-            s2 += exp2(static_cast<double>(entry_exponent(p1, p2, c.s1, c.s2, c.v1, c.v2, c.vn2,
-                                                          c.vv, K, fmaf(G[j], kx, fk)) - mx));
+            s2 += exp2(static_cast<double>(entry_exponent(p1, p2, c.s1, c.s2, c.v1, c.v2, c.vv,
+                                                          c.vv2, K, fmaf(G[j], kx, fk)) - mx));
         }
         logS = slow ? log(s2) + static_cast<double>(mx) * 0.6931471805599453 : log(acc);
     } else {
@@ -242,7 +242,7 @@ __global__ __launch_bounds__(64) void k_col(const Item *__restrict__ items,
     const Item it = items[blockIdx.x];
     const int j = it.c0 + static_cast<int>(threadIdx.x);
     const bool act = j < it.c1;
-    Col8 c = {0, 0, 0, 0, 0, 1, 0, 0};
+    Col8 c = {0, 0, 0, 0, 1, 1, 1, 0};
     float g = 0.0f;
     if (act) {
         c = cols[j];
@@ -256,7 +256,7 @@ __global__ __launch_bounds__(64) void k_col(const Item *__restrict__ items,
 #pragma unroll 4
         for (int i = i0; i < i1; ++i) {
             const float base = fmaf(F[i], kx, gk);
-            a += fast_exp2(entry_exponent(P1[i], P2[i], c.s1, c.s2, c.v1, c.v2, c.vn2, c.vv, K, base));
+            a += fast_exp2(entry_exponent(P1[i], P2[i], c.s1, c.s2, c.v1, c.v2, c.vv, c.vv2, K, base));
         }
         acc += static_cast<double>(a);
     }
@@ -267,12 +267,12 @@ __global__ __launch_bounds__(64) void k_col(const Item *__restrict__ items,
     if (__any(slow)) {
         float mx = static_cast<float>(eb);
         for (int i = it.r0; i < it.r1; ++i)
-            mx = fmaxf(mx, entry_exponent(P1[i], P2[i], c.s1, c.s2, c.v1, c.v2, c.vn2, c.vv, K,
+            mx = fmaxf(mx, entry_exponent(P1[i], P2[i], c.s1, c.s2, c.v1, c.v2, c.vv, c.vv2, K,
                                           fmaf(F[i], kx, gk)));
         double s2 = exp2(eb - mx);
         for (int i = it.r0; i < it.r1; ++i)
             s2 += exp2(static_cast<double>(entry_exponent(P1[i], P2[i], c.s1, c.s2, c.v1, c.v2,
-                                                          c.vn2, c.vv, K, fmaf(F[i], kx, gk))) -
+                                                          c.vv, c.vv2, K, fmaf(F[i], kx, gk))) -
                        mx);
         logS = slow ? log(s2) + static_cast<double>(mx) * 0.6931471805599453 : log(acc);
     } else {
@@ -322,7 +322,7 @@ __global__ __launch_bounds__(64) void k_assign(const Item *__restrict__ items,
     int arg = -1;
     for (int j = it.c0; j < it.c1; ++j) {
         const Col8 c = cols[j];
-        float e = entry_exponent(p1, p2, c.s1, c.s2, c.v1, c.v2, c.vn2, c.vv, K, fmaf(G[j], kx, fk));
+        float e = entry_exponent(p1, p2, c.s1, c.s2, c.v1, c.v2, c.vv, c.vv2, K, fmaf(G[j], kx, fk));
         if (e > best) {
             best = e;
             arg = j;
@@ -362,7 +362,7 @@ __global__ __launch_bounds__(64) void k_mstep_acc(
     const Item it = items[blockIdx.x];
     const int j = it.c0 + static_cast<int>(threadIdx.x);
     const bool act = j < it.c1;
-    Col8 cE = {0, 0, 0, 0, 0, 1, 0, 0}, cC = {0, 0, 0, 0, 0, 1, 1, 0};
+    Col8 cE = {0, 0, 0, 0, 1, 1, 1, 0}, cC = {0, 0, 0, 0, 1, 1, 1, 0};
     float g = 0.0f;
     if (act) {
         cE = colsE[j];
@@ -381,8 +381,8 @@ __global__ __launch_bounds__(64) void k_mstep_acc(
         for (int k = 0; k < kStat; ++k) a[k] = 0.0f;
         for (int i = i0; i < i1; ++i) {
             const float p1 = P1[i], p2 = P2[i];
-            const float Q = fast_exp2(entry_exponent(p1, p2, cE.s1, cE.s2, cE.v1, cE.v2, cE.vn2,
-                                                     cE.vv, K, fmaf(F[i], kx, gk)));
+            const float Q = fast_exp2(entry_exponent(p1, p2, cE.s1, cE.s2, cE.v1, cE.v2, cE.vv,
+                                                     cE.vv2, K, fmaf(F[i], kx, gk)));
             if (Q > 0.0f) {
                 const float dy = p1 - cC.s1, dz = p2 - cC.s2;
                 const float h0u = cC.vn, h1u = cC.v1 + dy, h2u = cC.v2 + dz;
@@ -925,7 +925,7 @@ __global__ void k_plan_soa(const float *__restrict__ P1, const float *__restrict
     int i = r0 + idx / nJ, j = c0 + idx % nJ;
     float vnn = vn[j];
     float vv = fmaf(v2[j], v2[j], fmaf(v1[j], v1[j], vnn * vnn));
-    Q[idx] = fast_exp2(entry_exponent(P1[i], P2[i], s1[j], s2[j], v1[j], v2[j], vnn * vnn, vv, K,
+    Q[idx] = fast_exp2(entry_exponent(P1[i], P2[i], s1[j], s2[j], v1[j], v2[j], vv, vv * vv, K,
                                       fmaf(F[i], kx, G[j] * kx)));
 }
 
@@ -940,7 +940,7 @@ __global__ void k_cost_soa(const float *__restrict__ P1, const float *__restrict
     float vnn = vn[j];
     float vv = fmaf(v2[j], v2[j], fmaf(v1[j], v1[j], vnn * vnn));
     // entry_exponent(..., K = -1, base = 0) returns c' = c / (2 D^2)
-    Cout[idx] = twoD2 * entry_exponent(P1[i], P2[i], s1[j], s2[j], v1[j], v2[j], vnn * vnn, vv,
+    Cout[idx] = twoD2 * entry_exponent(P1[i], P2[i], s1[j], s2[j], v1[j], v2[j], vv, vv * vv,
                                        -1.0f, 0.0f);
 }
 

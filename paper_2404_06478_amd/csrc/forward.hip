@@ -175,8 +175,8 @@ __global__ void k_eval(const GeomF *__restrict__ Gp, const float *__restrict__ W
         c.s2 = o.s2;
         c.v1 = o.v1;
         c.v2 = o.v2;
-        c.vn2 = o.vn * o.vn;
         c.vv = fmaf(o.v2, o.v2, fmaf(o.v1, o.v1, o.vn * o.vn));
+        c.vv2 = c.vv * c.vv;
         c.vn = o.vn;
         c.pad = 0.0f;
         cols[j] = c;
@@ -193,8 +193,8 @@ __global__ void k_pack_cols(const float *__restrict__ s1, const float *__restric
     c.s2 = s2[j];
     c.v1 = v1[j];
     c.v2 = v2[j];
-    c.vn2 = vn[j] * vn[j];
     c.vv = fmaf(v2[j], v2[j], fmaf(v1[j], v1[j], vn[j] * vn[j]));
+    c.vv2 = c.vv * c.vv;
     c.vn = vn[j];
     c.pad = 0.0f;
     cols[j] = c;
