@@ -328,6 +328,103 @@ int laue_em(const laue_geometry *geom, const laue_planes *planes,
             laue_assignments *assign, laue_em_stats *stats,
             void *ws, size_t ws_bytes, void *stream);
 
+/* ---- prototype scoring (Sec. 6, App. D-E) -------------------------------- */
+
+/* Spot-pair candidate orientations.  Each detected spot of a pair is read as
+ * a reflection of a grain at the sample centre: its ray rhat = p/|p| gives the
+ * lab normal u = (e - rhat)/|e - rhat| and sin(theta) = u.e (Eqs. ray_r, bragg),
+ * the sample-frame normal n = Gamma_t^T u.  Pair k is drawn with Philox4x32-10
+ * (counter (k, 0, 0, 5), key = seed): word 0 mod n_rot picks the rotation,
+ * words 1 and 2 mod (spots of that rotation) the two spots (a == b: none).
+ * Hypotheses: plane m_a among one representative per orbit of the 24 proper
+ * cubic rotations (the first plane of each orbit in list order) and any
+ * non-parallel plane m_b, both with
+ * 2 d sin(theta) in band, the angle between their normals within delta of the
+ * angle between n_a and n_b; the orientation solves Wahba's problem (App. A)
+ * for (n_a, w_a), (n_b, w_b), (n_a x n_b, w_a x w_b) (Davenport's q-method,
+ * FP64).  Position hypothesis x = 0.  Ordered by (pair, m_a, m_b). */
+typedef struct laue_cand_params {
+    int64_t n_pairs;
+    uint64_t seed;
+    double delta_deg;
+} laue_cand_params;
+
+/* Candidate outputs (device; capacity n on entry, count written on return;
+ * every array except q may be NULL).  feat: [n][16] FP32 features
+ * (0 cos(n_a,n_b), 1 cos(w_a,w_b), 2 |angle difference|/delta, 3-4 sin theta,
+ * 5-6 wavelength within the band, 7-8 N/N_max, 9 |p_a - p_b|/(2 l),
+ * 10-11 |(p1,p2)|/l, 12-13 detector ids, 14-15 cheap support, see
+ * laue_candidate_support). */
+typedef struct laue_candidates {
+    int64_t n;
+    double *q;
+    int32_t *pair, *ma, *mb, *spot_a, *spot_b;
+    float *feat;
+} laue_candidates;
+
+size_t laue_candidates_workspace_size(const laue_geometry *geom, int32_t n_planes, int64_t n_pairs);
+
+/* Generates the hypotheses of pairs 0 .. n_pairs-1.  *n_found (HOST) is the
+ * total; out->n becomes min(total, capacity) and the first ones are written.
+ * Synchronous. */
+int laue_candidates_generate(const laue_geometry *geom, const laue_planes *planes,
+                             const laue_obs_spots *obs, const laue_cand_params *par,
+                             laue_candidates *out, int64_t *n_found, void *ws, size_t ws_bytes,
+                             void *stream);
+
+/* Single-grain refinement and scoring of candidate grains (App. D-E).
+ * Refinement: k_refine iterations on the temperature schedule eps_start ->
+ * eps_end (geometric), each a row-softmax E-step over the candidate's frozen
+ * model spots plus the outlier column (Eq. elbo_single), then k_gn
+ * Gauss-Newton steps with Q fixed.  Scoring at the refined grain: a model
+ * spot is unmatched when no detected spot of its block is within c_out; a
+ * candidate is kept when unmatched < f_out * model spots; kept candidates
+ * get SPOT entries Lbar_in = ln sum_j exp(-c_ij / (2 sigma^2)) for every
+ * detected spot i of a block where the sum exceeds exp(-c_out / (2 sigma^2))
+ * (the outlier floor).  Candidates run in batches of `chunk`; a batch holds
+ * at most chunk * max_spots_per_cand model spots. */
+typedef struct laue_score_params {
+    double sigma_mm, distance, c_out, f_out;
+    double eps_start, eps_end;
+    int32_t k_refine, k_gn;
+    double mu_rel;
+    int32_t chunk, max_spots_per_cand;
+} laue_score_params;
+
+/* Scoring outputs (device).  n_model, n_unmatched, keep: [n_cand] (may be
+ * NULL).  SPOT matrix as CSR by candidate: lbar_off [n_cand + 1], lbar_row,
+ * lbar_val [lbar_cap]; lbar_n (out) entries. */
+typedef struct laue_score_out {
+    int32_t *n_model;
+    int32_t *n_unmatched;
+    uint8_t *keep;
+    int64_t *lbar_off;
+    int32_t *lbar_row;
+    float *lbar_val;
+    int64_t lbar_cap;
+    int64_t lbar_n;
+} laue_score_out;
+
+size_t laue_score_workspace_size(const laue_geometry *geom, const laue_score_params *par);
+
+/* Refines the candidates in place (q, x) and scores them.  Returns
+ * LAUE_ECAPACITY if a batch or the SPOT output overflows.  Synchronous. */
+int laue_score_candidates(const laue_geometry *geom, const laue_planes *planes,
+                          const laue_obs_spots *obs, laue_grains *cand,
+                          const laue_score_params *par, laue_score_out *out, void *ws,
+                          size_t ws_bytes, void *stream);
+
+size_t laue_spot_greedy_workspace_size(int32_t n_cand, int64_t n_rows);
+
+/* Greedy SPOT prototype selection (Alg. LaueSpotGreedy) on a sparse Lbar with
+ * floor phi: f(S) = sum_i max(phi, max_{n in S} Lbar_in) - |I| phi; each step
+ * adds the candidate of largest increment (lowest index on ties) until k_max
+ * or no increment is left.  picks [k_max], gains [k_max] (device, FP64
+ * increments Delta_k); *n_picked (HOST).  Synchronous. */
+int laue_spot_greedy(const int64_t *lbar_off, const int32_t *lbar_row, const float *lbar_val,
+                     int32_t n_cand, int64_t n_rows, double phi, int32_t k_max, int32_t *picks,
+                     double *gains, int32_t *n_picked, void *ws, size_t ws_bytes, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

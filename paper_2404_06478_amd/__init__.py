@@ -377,3 +377,95 @@ def laue_em(geom, planes, obs, model, par, grains, f=None, g=None, f0=0.0, g0=0.
     if assign:
         out.update({k: v[:obs.n] for k, v in asg_t.items()})
     return out
+
+
+# ---------------------------------------------------------------- prototype scoring
+
+def laue_candidates_generate(geom, planes, obs, n_pairs, seed, delta_deg=1.5, capacity=None,
+                             with_ids=True, with_feat=True):
+    """Spot-pair candidates.  Returns a dict of device tensors (q [n,4] FP64, ...)."""
+    import torch
+    lib = require_native()
+    dev = _dev()
+    ws = _workspace(lib.laue_candidates_workspace_size(C.byref(geom), planes.n, int(n_pairs)))
+    par = _abi.laue_cand_params(int(n_pairs), int(seed), float(delta_deg))
+    nfound = C.c_int64()
+    o = obs.struct()
+    probe = _abi.laue_candidates()
+    q0 = torch.zeros(4, dtype=torch.float64, device=dev)
+    probe.n, probe.q = 0, q0.data_ptr()
+    _check(lib.laue_candidates_generate(C.byref(geom), C.byref(planes.struct), C.byref(o), C.byref(par),
+                                        C.byref(probe), C.byref(nfound), _ptr(ws), ws.numel(), _stream()))
+    n = nfound.value if capacity is None else min(int(capacity), nfound.value)
+    m = max(n, 1)
+    out = {"q": torch.zeros((m, 4), dtype=torch.float64, device=dev)}
+    if with_ids:
+        for k in ("pair", "ma", "mb", "spot_a", "spot_b"):
+            out[k] = torch.zeros(m, dtype=torch.int32, device=dev)
+    if with_feat:
+        out["feat"] = torch.zeros((m, 16), dtype=torch.float32, device=dev)
+    c = _abi.laue_candidates()
+    c.n = n
+    c.q = out["q"].data_ptr()
+    for k in ("pair", "ma", "mb", "spot_a", "spot_b"):
+        setattr(c, k, out[k].data_ptr() if k in out else None)
+    c.feat = out["feat"].data_ptr() if "feat" in out else None
+    if n > 0:
+        _check(lib.laue_candidates_generate(C.byref(geom), C.byref(planes.struct), C.byref(o), C.byref(par),
+                                            C.byref(c), C.byref(nfound), _ptr(ws), ws.numel(), _stream()))
+    res = {k: v[:n] for k, v in out.items()}
+    res["n_found"] = nfound.value
+    return res
+
+
+def score_params(sigma_mm, distance, c_out, f_out=0.1, k_refine=8, k_gn=2, mu_rel=1e-9, chunk=4096,
+                 max_spots_per_cand=4096, eps_start=None, eps_end=None):
+    p = _abi.laue_score_params()
+    p.sigma_mm, p.distance, p.c_out, p.f_out = float(sigma_mm), float(distance), float(c_out), float(f_out)
+    p.eps_start = float(111.0 * sigma_mm ** 2 if eps_start is None else eps_start)
+    p.eps_end = float(1.11 * sigma_mm ** 2 if eps_end is None else eps_end)
+    p.k_refine, p.k_gn, p.mu_rel = int(k_refine), int(k_gn), float(mu_rel)
+    p.chunk, p.max_spots_per_cand = int(chunk), int(max_spots_per_cand)
+    return p
+
+
+def laue_score_candidates(geom, planes, obs, cand, par, lbar_cap=None):
+    """Refines cand (Grains) in place and scores it.  Returns a dict of tensors."""
+    import torch
+    lib = require_native()
+    dev = _dev()
+    n = cand.n
+    cap = int(lbar_cap if lbar_cap is not None else max(1024, 64 * obs.n))
+    ws = _workspace(lib.laue_score_workspace_size(C.byref(geom), C.byref(par)))
+    out_t = {"n_model": torch.zeros(max(n, 1), dtype=torch.int32, device=dev),
+             "n_unmatched": torch.zeros(max(n, 1), dtype=torch.int32, device=dev),
+             "keep": torch.zeros(max(n, 1), dtype=torch.uint8, device=dev),
+             "lbar_off": torch.zeros(n + 1, dtype=torch.int64, device=dev),
+             "lbar_row": torch.zeros(cap, dtype=torch.int32, device=dev),
+             "lbar_val": torch.zeros(cap, dtype=torch.float32, device=dev)}
+    so = _abi.laue_score_out()
+    for k in ("n_model", "n_unmatched", "keep", "lbar_off", "lbar_row", "lbar_val"):
+        setattr(so, k, out_t[k].data_ptr())
+    so.lbar_cap = cap
+    o = obs.struct()
+    _check(lib.laue_score_candidates(C.byref(geom), C.byref(planes.struct), C.byref(o), C.byref(cand.struct),
+                                     C.byref(par), C.byref(so), _ptr(ws), ws.numel(), _stream()))
+    res = {k: (v[:n] if k in ("n_model", "n_unmatched", "keep") else v) for k, v in out_t.items()}
+    res["lbar_row"] = out_t["lbar_row"][:so.lbar_n]
+    res["lbar_val"] = out_t["lbar_val"][:so.lbar_n]
+    res["lbar_n"] = so.lbar_n
+    return res
+
+
+def laue_spot_greedy(lbar_off, lbar_row, lbar_val, n_cand, n_rows, phi, k_max):
+    import torch
+    lib = require_native()
+    dev = _dev()
+    ws = _workspace(lib.laue_spot_greedy_workspace_size(int(n_cand), int(n_rows)))
+    picks = torch.zeros(max(int(k_max), 1), dtype=torch.int32, device=dev)
+    gains = torch.zeros(max(int(k_max), 1), dtype=torch.float64, device=dev)
+    npk = C.c_int32()
+    _check(lib.laue_spot_greedy(_ptr(lbar_off), _ptr(lbar_row), _ptr(lbar_val), int(n_cand), int(n_rows),
+                                float(phi), int(k_max), _ptr(picks), _ptr(gains), C.byref(npk), _ptr(ws),
+                                ws.numel(), _stream()))
+    return picks[:npk.value], gains[:npk.value]

@@ -84,6 +84,27 @@ class laue_assignments(C.Structure):
     _fields_ = [("j_star", vp), ("grain", vp), ("q_star", vp), ("q_out", vp)]
 
 
+class laue_cand_params(C.Structure):
+    _fields_ = [("n_pairs", C.c_int64), ("seed", C.c_uint64), ("delta_deg", C.c_double)]
+
+
+class laue_candidates(C.Structure):
+    _fields_ = [("n", C.c_int64), ("q", vp), ("pair", vp), ("ma", vp), ("mb", vp), ("spot_a", vp),
+                ("spot_b", vp), ("feat", vp)]
+
+
+class laue_score_params(C.Structure):
+    _fields_ = [("sigma_mm", C.c_double), ("distance", C.c_double), ("c_out", C.c_double),
+                ("f_out", C.c_double), ("eps_start", C.c_double), ("eps_end", C.c_double),
+                ("k_refine", C.c_int32), ("k_gn", C.c_int32), ("mu_rel", C.c_double),
+                ("chunk", C.c_int32), ("max_spots_per_cand", C.c_int32)]
+
+
+class laue_score_out(C.Structure):
+    _fields_ = [("n_model", vp), ("n_unmatched", vp), ("keep", vp), ("lbar_off", vp),
+                ("lbar_row", vp), ("lbar_val", vp), ("lbar_cap", C.c_int64), ("lbar_n", C.c_int64)]
+
+
 P = C.POINTER
 SIGNATURES = {
     "laue_version": (C.c_int, []),
@@ -113,6 +134,17 @@ SIGNATURES = {
     "laue_em": (C.c_int, [P(laue_geometry), P(laue_planes), P(laue_obs_spots), P(laue_model_spots),
                           P(laue_em_params), P(laue_grains), P(laue_potentials),
                           P(laue_assignments), P(laue_em_stats), vp, C.c_size_t, vp]),
+    "laue_candidates_workspace_size": (C.c_size_t, [P(laue_geometry), C.c_int32, C.c_int64]),
+    "laue_candidates_generate": (C.c_int, [P(laue_geometry), P(laue_planes), P(laue_obs_spots),
+                                           P(laue_cand_params), P(laue_candidates), P(C.c_int64), vp,
+                                           C.c_size_t, vp]),
+    "laue_score_workspace_size": (C.c_size_t, [P(laue_geometry), P(laue_score_params)]),
+    "laue_score_candidates": (C.c_int, [P(laue_geometry), P(laue_planes), P(laue_obs_spots),
+                                        P(laue_grains), P(laue_score_params), P(laue_score_out), vp,
+                                        C.c_size_t, vp]),
+    "laue_spot_greedy_workspace_size": (C.c_size_t, [C.c_int32, C.c_int64]),
+    "laue_spot_greedy": (C.c_int, [vp, vp, vp, C.c_int32, C.c_int64, C.c_double, C.c_int32, vp, vp,
+                                   P(C.c_int32), vp, C.c_size_t, vp]),
 }
 
 

@@ -171,6 +171,270 @@ __device__ __forceinline__ float entry_exponent(float p1, float p2, float s1, fl
 
 __device__ __forceinline__ float fast_exp2(float x) { return __builtin_amdgcn_exp2f(x); }
 
+constexpr int kStat = 16;   // per-column sufficient statistics of the M-step
+constexpr int kHg = 27;     // per-column normal-equation contribution (21 + 6)
+
+// M-step sufficient statistics of one (detected spot p, model spot) pair with
+// plan weight Q, at the current column geometry cC (detector frame).  With
+// delta = p - s, d = v + delta, tau = |d|, rhat = d / tau, P = I - rhat rhat^T:
+//   a[0] += Q, a[1..3] += Q (rhat - r), a[4..9] += Q P / tau^2, a[10..15] += Q P / tau
+// where rhat - r = (delta - r dl) / tau, dl = |d| - |v| = (2 v.delta + |delta|^2) / (|d| + |v|),
+// is formed without cancellation.  vlen = |v|, (rn, r1, r2) = v / |v|.
+__device__ __forceinline__ void accumulate_stats(float *a, float Q, float p1, float p2,
+                                                 const Col8 &cC, float vlen, float rn, float r1,
+                                                 float r2) {
+    const float dy = p1 - cC.s1, dz = p2 - cC.s2;
+    const float h0u = cC.vn, h1u = cC.v1 + dy, h2u = cC.v2 + dz;
+    const float dd = fmaf(h2u, h2u, fmaf(h1u, h1u, h0u * h0u));
+    const float itau = 1.0f / sqrtf(dd);
+    const float tau = dd * itau;
+    const float dl = fmaf(2.0f, fmaf(cC.v2, dz, cC.v1 * dy), fmaf(dz, dz, dy * dy)) / (tau + vlen);
+    const float e0 = (-rn * dl) * itau;
+    const float e1 = fmaf(-r1, dl, dy) * itau;
+    const float e2 = fmaf(-r2, dl, dz) * itau;
+    const float h0 = h0u * itau, h1 = h1u * itau, h2 = h2u * itau;
+    const float wa = Q * itau * itau, wb = Q * itau;
+    const float P00 = fmaf(-h0, h0, 1.0f), P01 = -h0 * h1, P02 = -h0 * h2;
+    const float P11 = fmaf(-h1, h1, 1.0f), P12 = -h1 * h2, P22 = fmaf(-h2, h2, 1.0f);
+    a[0] += Q;
+    a[1] = fmaf(Q, e0, a[1]);
+    a[2] = fmaf(Q, e1, a[2]);
+    a[3] = fmaf(Q, e2, a[3]);
+    a[4] = fmaf(wa, P00, a[4]);
+    a[5] = fmaf(wa, P01, a[5]);
+    a[6] = fmaf(wa, P02, a[6]);
+    a[7] = fmaf(wa, P11, a[7]);
+    a[8] = fmaf(wa, P12, a[8]);
+    a[9] = fmaf(wa, P22, a[9]);
+    a[10] = fmaf(wb, P00, a[10]);
+    a[11] = fmaf(wb, P01, a[11]);
+    a[12] = fmaf(wb, P02, a[12]);
+    a[13] = fmaf(wb, P11, a[13]);
+    a[14] = fmaf(wb, P12, a[14]);
+    a[15] = fmaf(wb, P22, a[15]);
+}
+
+// FP64 contribution of one model spot (plane m, grain n, block b) to its
+// grain's Gauss-Newton normal equations, from the column statistics s64
+// (detector frame, see accumulate_stats).  Residual rho = D (rhat - r);
+// Jacobians (from Eqs. ray_mnt and s_mnt, left perturbation
+// R <- exp([omega]_x) R): d rho/d x = -(D/tau) P Gt, d rho/d omega = -D K with
+// K = 2 (u e^T + (u.e) I) Gt [R w]_x, u = Gt R w.  Hence
+//   H_ww = D^2 S0 K^T K, H_xx = D^2 Gt^T A Gt, H_xw = D^2 Gt^T B K,
+//   g_w = -D^2 K^T e,    g_x = D^2 Gt^T B r,
+// written as the 21 upper-triangle entries of H (theta = (omega, x)) and g.
+// Invalid ids contribute zeros.
+__device__ inline void column_normal_equations(const GeomF &Gm, const float *W, int n_planes,
+                                               const GrainF *grains, int n_grains, int m, int n,
+                                               int b, const double *s64, float rn, float r1,
+                                               float r2, double D2, double *o) {
+    if (m < 0 || m >= n_planes || n < 0 || n >= n_grains || b < 0 || b >= Gm.n_rot * Gm.n_det) {
+        for (int k = 0; k < kHg; ++k) o[k] = 0.0;
+        return;
+    }
+    const int t = b / Gm.n_det, d = b - t * Gm.n_det;
+    const DetF &Dt = Gm.det[d];
+    double Mf[3][3];  // columns: normal, axis1, axis2 (lab = Mf * local)
+    for (int a_ = 0; a_ < 3; ++a_) {
+        Mf[a_][0] = Dt.n[a_];
+        Mf[a_][1] = Dt.a1[a_];
+        Mf[a_][2] = Dt.a2[a_];
+    }
+    const double cs = Gm.cs[t][0], sn = Gm.cs[t][1];
+    const double Gt[3][3] = {{cs, -sn, 0.0}, {sn, cs, 0.0}, {0.0, 0.0, 1.0}};
+    const float *R = grains[n].R;
+    double vs[3];
+    for (int a_ = 0; a_ < 3; ++a_)
+        vs[a_] = static_cast<double>(R[3 * a_]) * W[3 * m] +
+                 static_cast<double>(R[3 * a_ + 1]) * W[3 * m + 1] +
+                 static_cast<double>(R[3 * a_ + 2]) * W[3 * m + 2];
+    double u[3];
+    for (int a_ = 0; a_ < 3; ++a_) u[a_] = Gt[a_][0] * vs[0] + Gt[a_][1] * vs[1] + Gt[a_][2] * vs[2];
+    const double Vx[3][3] = {{0.0, -vs[2], vs[1]}, {vs[2], 0.0, -vs[0]}, {-vs[1], vs[0], 0.0}};
+    double GV[3][3], Kj[3][3];
+    for (int a_ = 0; a_ < 3; ++a_)
+        for (int b_ = 0; b_ < 3; ++b_)
+            GV[a_][b_] = Gt[a_][0] * Vx[0][b_] + Gt[a_][1] * Vx[1][b_] + Gt[a_][2] * Vx[2][b_];
+    for (int a_ = 0; a_ < 3; ++a_)
+        for (int b_ = 0; b_ < 3; ++b_) Kj[a_][b_] = 2.0 * (u[a_] * GV[0][b_] + u[0] * GV[a_][b_]);
+    const double S0 = s64[0];
+    const double eloc[3] = {s64[1], s64[2], s64[3]};
+    const double Aloc[3][3] = {{s64[4], s64[5], s64[6]}, {s64[5], s64[7], s64[8]}, {s64[6], s64[8], s64[9]}};
+    const double Bloc[3][3] = {{s64[10], s64[11], s64[12]}, {s64[11], s64[13], s64[14]}, {s64[12], s64[14], s64[15]}};
+    const double rloc[3] = {rn, r1, r2};
+    double el[3], rl[3], Al[3][3], Bl[3][3], T1[3][3], T2[3][3];
+    for (int a_ = 0; a_ < 3; ++a_) {
+        el[a_] = Mf[a_][0] * eloc[0] + Mf[a_][1] * eloc[1] + Mf[a_][2] * eloc[2];
+        rl[a_] = Mf[a_][0] * rloc[0] + Mf[a_][1] * rloc[1] + Mf[a_][2] * rloc[2];
+    }
+    for (int a_ = 0; a_ < 3; ++a_)
+        for (int b_ = 0; b_ < 3; ++b_) {
+            T1[a_][b_] = Mf[a_][0] * Aloc[0][b_] + Mf[a_][1] * Aloc[1][b_] + Mf[a_][2] * Aloc[2][b_];
+            T2[a_][b_] = Mf[a_][0] * Bloc[0][b_] + Mf[a_][1] * Bloc[1][b_] + Mf[a_][2] * Bloc[2][b_];
+        }
+    for (int a_ = 0; a_ < 3; ++a_)
+        for (int b_ = 0; b_ < 3; ++b_) {
+            Al[a_][b_] = T1[a_][0] * Mf[b_][0] + T1[a_][1] * Mf[b_][1] + T1[a_][2] * Mf[b_][2];
+            Bl[a_][b_] = T2[a_][0] * Mf[b_][0] + T2[a_][1] * Mf[b_][1] + T2[a_][2] * Mf[b_][2];
+        }
+    double GA[3][3], GB[3][3];
+    for (int a_ = 0; a_ < 3; ++a_)
+        for (int b_ = 0; b_ < 3; ++b_) {
+            GA[a_][b_] = Gt[0][a_] * Al[0][b_] + Gt[1][a_] * Al[1][b_] + Gt[2][a_] * Al[2][b_];
+            GB[a_][b_] = Gt[0][a_] * Bl[0][b_] + Gt[1][a_] * Bl[1][b_] + Gt[2][a_] * Bl[2][b_];
+        }
+    double H[6][6], gv[6];
+    for (int a_ = 0; a_ < 3; ++a_)
+        for (int b_ = 0; b_ < 3; ++b_) {
+            double ww = 0.0, xx = 0.0, xw = 0.0;
+            for (int c_ = 0; c_ < 3; ++c_) {
+                ww += Kj[c_][a_] * Kj[c_][b_];
+                xx += GA[a_][c_] * Gt[c_][b_];
+                xw += GB[a_][c_] * Kj[c_][b_];
+            }
+            H[a_][b_] = D2 * S0 * ww;
+            H[3 + a_][3 + b_] = D2 * xx;
+            H[3 + a_][b_] = D2 * xw;
+            H[b_][3 + a_] = D2 * xw;
+        }
+    for (int a_ = 0; a_ < 3; ++a_) {
+        double gw = 0.0, gx = 0.0;
+        for (int c_ = 0; c_ < 3; ++c_) {
+            gw += Kj[c_][a_] * el[c_];
+            gx += GB[a_][c_] * rl[c_];
+        }
+        gv[a_] = -D2 * gw;
+        gv[3 + a_] = D2 * gx;
+    }
+    int q = 0;
+    for (int a_ = 0; a_ < 6; ++a_)
+        for (int b_ = a_; b_ < 6; ++b_) o[q++] = H[a_][b_];
+    for (int a_ = 0; a_ < 6; ++a_) o[q++] = gv[a_];
+}
+
+// Gauss-Newton step of one grain from its summed normal equations acc
+// (21 upper-triangle entries of H, then g): (H + mu I) step = -g with
+// mu = mu_rel tr(H) / 6, solved by FP64 Cholesky; R <- exp([omega]_x) R as the
+// quaternion product dq * q, x <- x + dx.  A grain without weight (tr H ~ 0)
+// or with a non-positive pivot keeps its parameters (step 0).
+__device__ inline void gn_solve_apply(const double *acc, double mu_rel, double *q, double *x,
+                                      GrainF *gf, double *step_norm) {
+    double H[6][6], gv[6];
+    int c = 0;
+    for (int a = 0; a < 6; ++a)
+        for (int b = a; b < 6; ++b) {
+            H[a][b] = acc[c];
+            H[b][a] = acc[c];
+            ++c;
+        }
+    for (int a = 0; a < 6; ++a) gv[a] = acc[21 + a];
+    double tr = 0.0;
+    for (int a = 0; a < 6; ++a) tr += H[a][a];
+    double step[6] = {0, 0, 0, 0, 0, 0};
+    bool ok = tr > 1e-300 && isfinite(tr);
+    if (ok) {
+        const double mu = mu_rel * tr / 6.0;
+        for (int a = 0; a < 6; ++a) H[a][a] += mu;
+        double L[6][6] = {};
+        for (int a = 0; a < 6 && ok; ++a) {
+            for (int b = 0; b <= a; ++b) {
+                double s = H[a][b];
+                for (int k = 0; k < b; ++k) s -= L[a][k] * L[b][k];
+                if (a == b) {
+                    if (!(s > 0.0)) { ok = false; break; }
+                    L[a][a] = sqrt(s);
+                } else {
+                    L[a][b] = s / L[b][b];
+                }
+            }
+        }
+        if (ok) {
+            double y[6];
+            for (int a = 0; a < 6; ++a) {
+                double s = -gv[a];
+                for (int k = 0; k < a; ++k) s -= L[a][k] * y[k];
+                y[a] = s / L[a][a];
+            }
+            for (int a = 5; a >= 0; --a) {
+                double s = y[a];
+                for (int k = a + 1; k < 6; ++k) s -= L[k][a] * step[k];
+                step[a] = s / L[a][a];
+            }
+        }
+    }
+    if (!ok) {
+        for (int a = 0; a < 6; ++a) step[a] = 0.0;
+    }
+    // R <- exp([w]_x) R as the quaternion product dq * q
+    double qw = q[0], qa = q[1], qb = q[2], qc = q[3];
+    const double th = sqrt(step[0] * step[0] + step[1] * step[1] + step[2] * step[2]);
+    if (th > 0.0) {
+        const double h = 0.5 * th, sh = sin(h) / th;
+        const double dw = cos(h), da = step[0] * sh, db = step[1] * sh, dc = step[2] * sh;
+        const double nw = dw * qw - da * qa - db * qb - dc * qc;
+        const double na = dw * qa + da * qw + db * qc - dc * qb;
+        const double nb = dw * qb - da * qc + db * qw + dc * qa;
+        const double nc = dw * qc + da * qb - db * qa + dc * qw;
+        qw = nw; qa = na; qb = nb; qc = nc;
+    }
+    double nrm = sqrt(qw * qw + qa * qa + qb * qb + qc * qc);
+    qw /= nrm; qa /= nrm; qb /= nrm; qc /= nrm;
+    if (qw < 0) { qw = -qw; qa = -qa; qb = -qb; qc = -qc; }
+    q[0] = qw; q[1] = qa; q[2] = qb; q[3] = qc;
+    for (int a = 0; a < 3; ++a) x[a] += step[3 + a];
+    const double Rm[9] = {1 - 2 * (qb * qb + qc * qc), 2 * (qa * qb - qw * qc), 2 * (qa * qc + qw * qb),
+                          2 * (qa * qb + qw * qc), 1 - 2 * (qa * qa + qc * qc), 2 * (qb * qc - qw * qa),
+                          2 * (qa * qc - qw * qb), 2 * (qb * qc + qw * qa), 1 - 2 * (qa * qa + qb * qb)};
+    for (int k = 0; k < 9; ++k) gf->R[k] = static_cast<float>(Rm[k]);
+    for (int k = 0; k < 3; ++k) gf->x[k] = static_cast<float>(x[k]);
+    if (step_norm) {
+        double s = 0.0;
+        for (int a = 0; a < 6; ++a) s += step[a] * step[a];
+        *step_norm = sqrt(s);
+    }
+}
+
+// Workspace of the enumerate count/scan (forward.hip).
+struct EnumWs {
+    GeomF *geom;
+    GrainF *grains;
+    int *counts;
+    int64_t *offs;      // exclusive scan of counts in (t, d, n) order, L + 1 entries
+    int64_t *blk;       // per-block offsets (n_blocks + 1)
+};
+size_t carve_enum(Carver &cv, EnumWs &w, const laue_geometry *g, int n_grains);
+int enumerate_count(const laue_geometry *geom, const laue_planes *planes, const laue_grains *grains,
+                    int merge, EnumWs &w, std::vector<int64_t> &host_blk, int64_t *total,
+                    hipStream_t s);
+int prep_grains(const laue_grains *g, GrainF *dst, hipStream_t s);
+int launch_eval(const GeomF *dG, const laue_planes *pl, const GrainF *dgr, int n_grains,
+                const int *plane, const int *grain, const int *block, int64_t n, float *s1,
+                float *s2, float *vn, float *v1, float *v2, float *lam, Col8 *cols, hipStream_t s);
+int launch_enumerate_ids(const laue_geometry *geom, const laue_planes *planes, EnumWs &w, int N,
+                         int merge, int *plane, int *grain, int *block, hipStream_t s);
+int validate_planes(const laue_planes *p);
+int validate_grains(const laue_grains *g);
+// exclusive scan of L ints into L + 1 int64 (one workgroup)
+int launch_scan(const int *in, int64_t *out, int64_t L, hipStream_t s);
+
+// Philox4x32-10 (Salmon et al., SC'11), from its published definition.
+__device__ __forceinline__ void philox(uint32_t c[4], uint32_t k0, uint32_t k1) {
+    for (int r = 0; r < 10; ++r) {
+        uint64_t p0 = static_cast<uint64_t>(0xD2511F53u) * c[0];
+        uint64_t p1 = static_cast<uint64_t>(0xCD9E8D57u) * c[2];
+        uint32_t hi0 = static_cast<uint32_t>(p0 >> 32), lo0 = static_cast<uint32_t>(p0);
+        uint32_t hi1 = static_cast<uint32_t>(p1 >> 32), lo1 = static_cast<uint32_t>(p1);
+        uint32_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
+        c[0] = n0;
+        c[1] = lo1;
+        c[2] = n2;
+        c[3] = lo0;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+}
+
+
 // Wave-wide (64-lane) reductions in a fixed butterfly order (deterministic).
 __device__ __forceinline__ double wave_sum(double v) {
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);

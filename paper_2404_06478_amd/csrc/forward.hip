@@ -135,6 +135,12 @@ __global__ __launch_bounds__(1024) void k_scan(const int *__restrict__ in, int64
         for (int b = tid; b <= n_blocks; b += 1024) blk[b] = out[std::min<int64_t>(L, b * stride)];
 }
 
+int launch_scan(const int *in, int64_t *out, int64_t L, hipStream_t s) {
+    k_scan<<<1, 1024, 0, s>>>(in, out, L, nullptr, 0, 1);
+    LAUE_CHECK_HIP(hipGetLastError());
+    return LAUE_OK;
+}
+
 // ---------------------------------------------------------------- eval
 
 __global__ void k_eval(const GeomF *__restrict__ Gp, const float *__restrict__ W,
@@ -234,15 +240,7 @@ int validate_grains(const laue_grains *g) {
     return LAUE_OK;
 }
 
-struct EnumWs {
-    GeomF *geom;
-    GrainF *grains;
-    int *counts;
-    int64_t *offs;
-    int64_t *blk;
-};
-
-static size_t carve_enum(Carver &cv, EnumWs &w, const laue_geometry *g, int n_grains) {
+size_t carve_enum(Carver &cv, EnumWs &w, const laue_geometry *g, int n_grains) {
     int64_t L = static_cast<int64_t>(g->n_rot) * g->n_det * std::max(n_grains, 1);
     w.geom = cv.take<GeomF>(1);
     w.grains = cv.take<GrainF>(std::max(n_grains, 1));
@@ -254,7 +252,7 @@ static size_t carve_enum(Carver &cv, EnumWs &w, const laue_geometry *g, int n_gr
 
 // Count pass, scan and block offsets of the (merged) visible set.  Leaves
 // host_blk filled; returns the total in *total.
-static int enumerate_count(const laue_geometry *geom, const laue_planes *planes,
+int enumerate_count(const laue_geometry *geom, const laue_planes *planes,
                            const laue_grains *grains, int merge, EnumWs &w,
                            std::vector<int64_t> &host_blk, int64_t *total, hipStream_t s) {
     GeomF hg;
@@ -285,24 +283,19 @@ static int enumerate_count(const laue_geometry *geom, const laue_planes *planes,
     return LAUE_OK;
 }
 
-// ---------------------------------------------------------------- simulate
-
-// Philox4x32-10 (Salmon et al., SC'11), from its published definition.
-__device__ __forceinline__ void philox(uint32_t c[4], uint32_t k0, uint32_t k1) {
-    for (int r = 0; r < 10; ++r) {
-        uint64_t p0 = static_cast<uint64_t>(0xD2511F53u) * c[0];
-        uint64_t p1 = static_cast<uint64_t>(0xCD9E8D57u) * c[2];
-        uint32_t hi0 = static_cast<uint32_t>(p0 >> 32), lo0 = static_cast<uint32_t>(p0);
-        uint32_t hi1 = static_cast<uint32_t>(p1 >> 32), lo1 = static_cast<uint32_t>(p1);
-        uint32_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
-        c[0] = n0;
-        c[1] = lo1;
-        c[2] = n2;
-        c[3] = lo0;
-        k0 += 0x9E3779B9u;
-        k1 += 0xBB67AE85u;
-    }
+// Write pass of the enumerate (ids only) after enumerate_count on the same workspace.
+int launch_enumerate_ids(const laue_geometry *geom, const laue_planes *planes, EnumWs &w, int N,
+                         int merge, int *plane, int *grain, int *block, hipStream_t s) {
+    if (N == 0) return LAUE_OK;
+    k_enumerate<<<geom->n_rot * N, 64, 0, s>>>(w.geom, planes->w, planes->d, planes->harmonic_prev,
+                                               planes->n, w.grains, N, merge, 1, nullptr, w.offs,
+                                               plane, grain, block, nullptr, nullptr, nullptr,
+                                               nullptr, nullptr, nullptr, nullptr);
+    LAUE_CHECK_HIP(hipGetLastError());
+    return LAUE_OK;
 }
+
+// ---------------------------------------------------------------- simulate
 
 __device__ __forceinline__ double u01(uint32_t v) { return (static_cast<double>(v) + 0.5) * (1.0 / 4294967296.0); }
 

@@ -1,0 +1,938 @@
+// Prototype scoring (paper Sec. 6, App. D-E; Algs. SingleLaueOT and
+// LaueSpotGreedy): spot-pair candidate orientations, single-grain refinement
+// with a row-softmax E-step, the unmatched (3 sigma) filter, the sparse SPOT
+// grain-to-spot matrix and greedy prototype selection.
+//
+// Candidate work is laid out in "slots": a wave serves one (rotation,
+// detector) block and 64/S candidates, S lanes per candidate (S = smallest
+// power of two >= the largest number of model spots a candidate has in one
+// block).  Each lane owns one model spot; the block's detected spots stream
+// through scalar loads.  The softmax normaliser of a detected spot over the
+// candidate's spots is a butterfly sum within the S lanes, so the M-step
+// statistics stay in the lane that owns the spot.
+#include <algorithm>
+#include <cmath>
+
+#include "common.h"
+
+namespace laue {
+
+constexpr int kMaxReps = 128;
+
+// ---------------------------------------------------------------- candidates
+
+// Sample-frame plane normal n and sin(theta) of a detected spot read as a
+// reflection of a grain at the sample centre: rhat = p/|p|, u = (e - rhat)/|e - rhat|,
+// sin(theta) = |e - rhat|/2 (Eqs. ray_r, bragg), n = Gamma_t^T u.  FP64.
+__device__ inline void spot_normal(const laue_geometry &G, int b, float p1, float p2, double *n,
+                                   double &sth, double *plab) {
+    const int t = b / G.n_det, d = b - t * G.n_det;
+    const laue_detector &D = G.det[d];
+    double nrm = 0.0;
+    for (int k = 0; k < 3; ++k) {
+        plab[k] = D.center[k] + static_cast<double>(p1) * D.axis1[k] + static_cast<double>(p2) * D.axis2[k];
+        nrm += plab[k] * plab[k];
+    }
+    nrm = sqrt(nrm);
+    double dv[3] = {1.0 - plab[0] / nrm, -plab[1] / nrm, -plab[2] / nrm};
+    const double nd = sqrt(dv[0] * dv[0] + dv[1] * dv[1] + dv[2] * dv[2]);
+    const double inv = nd > 0.0 ? 1.0 / nd : 0.0;
+    const double u[3] = {dv[0] * inv, dv[1] * inv, dv[2] * inv};
+    const double om = G.omega0 + G.domega * t, c = cos(om), s = sin(om);
+    n[0] = c * u[0] + s * u[1];
+    n[1] = -s * u[0] + c * u[1];
+    n[2] = u[2];
+    sth = 0.5 * nd;
+}
+
+// Largest-eigenvalue eigenvector of a symmetric 4x4 matrix (cyclic Jacobi, FP64).
+__device__ inline void sym4_top_eigvec(double A[4][4], double v[4]) {
+    double V[4][4] = {{1, 0, 0, 0}, {0, 1, 0, 0}, {0, 0, 1, 0}, {0, 0, 0, 1}};
+    for (int sweep = 0; sweep < 12; ++sweep) {
+        double off = 0.0, dia = 0.0;
+        for (int p = 0; p < 4; ++p) {
+            dia += A[p][p] * A[p][p];
+            for (int q = p + 1; q < 4; ++q) off += A[p][q] * A[p][q];
+        }
+        if (off <= 1e-30 * dia) break;
+        for (int p = 0; p < 3; ++p)
+            for (int q = p + 1; q < 4; ++q) {
+                if (fabs(A[p][q]) < 1e-300) continue;
+                const double th = (A[q][q] - A[p][p]) / (2.0 * A[p][q]);
+                const double t = (th >= 0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
+                const double c = 1.0 / sqrt(t * t + 1.0), s = t * c;
+                for (int k = 0; k < 4; ++k) {
+                    const double kp = A[k][p], kq = A[k][q];
+                    A[k][p] = c * kp - s * kq;
+                    A[k][q] = s * kp + c * kq;
+                }
+                for (int k = 0; k < 4; ++k) {
+                    const double pk = A[p][k], qk = A[q][k];
+                    A[p][k] = c * pk - s * qk;
+                    A[q][k] = s * pk + c * qk;
+                }
+                for (int k = 0; k < 4; ++k) {
+                    const double kp = V[k][p], kq = V[k][q];
+                    V[k][p] = c * kp - s * kq;
+                    V[k][q] = s * kp + c * kq;
+                }
+            }
+    }
+    int best = 0;
+    for (int i = 1; i < 4; ++i)
+        if (A[i][i] > A[best][best]) best = i;
+    for (int k = 0; k < 4; ++k) v[k] = V[k][best];
+}
+
+// Wahba's problem (App. A): the rotation R minimising sum_k ||a_k - R b_k||^2,
+// solved through Davenport's q-method (the same minimiser as the SVD form of
+// Alg. Wahba): the optimal unit quaternion is the top eigenvector of
+// K = [[tr B, z^T], [z, B + B^T - tr(B) I]], B = sum a_k b_k^T,
+// z = (B32 - B23, B13 - B31, B21 - B12).
+__device__ inline void wahba_quat(const double a[3][3], const double b[3][3], double *q) {
+    double B[3][3] = {};
+    for (int k = 0; k < 3; ++k)
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) B[i][j] += a[k][i] * b[k][j];
+    const double tr = B[0][0] + B[1][1] + B[2][2];
+    const double z[3] = {B[2][1] - B[1][2], B[0][2] - B[2][0], B[1][0] - B[0][1]};
+    double K[4][4];
+    K[0][0] = tr;
+    for (int i = 0; i < 3; ++i) {
+        K[0][1 + i] = z[i];
+        K[1 + i][0] = z[i];
+        for (int j = 0; j < 3; ++j) K[1 + i][1 + j] = B[i][j] + B[j][i] - (i == j ? tr : 0.0);
+    }
+    sym4_top_eigvec(K, q);
+    double nrm = sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+    const double sg = q[0] < 0 ? -1.0 : 1.0;
+    for (int k = 0; k < 4; ++k) q[k] = sg * q[k] / nrm;
+}
+
+__device__ __forceinline__ void cross3(const double *a, const double *b, double *c) {
+    c[0] = a[1] * b[2] - a[2] * b[1];
+    c[1] = a[2] * b[0] - a[0] * b[2];
+    c[2] = a[0] * b[1] - a[1] * b[0];
+}
+
+struct PairTab {
+    int n_rep;
+    int M;
+    int rep[kMaxReps];
+};
+
+// One thread per pair k.  pass 0 counts hypotheses, pass 1 writes them at
+// offs[k] (only below capacity).
+__global__ void k_pairs(int pass, const laue_geometry G, const float *__restrict__ P1,
+                        const float *__restrict__ P2, const int64_t *__restrict__ ooff,
+                        const float *__restrict__ W, const float *__restrict__ Dsp,
+                        const PairTab *__restrict__ tab, const double *__restrict__ angw,
+                        const float *__restrict__ nrat, int64_t n_pairs, uint32_t k0, uint32_t k1,
+                        double delta, double l_side, int *__restrict__ counts,
+                        const int64_t *__restrict__ offs, int64_t cap, double *__restrict__ oq,
+                        int *__restrict__ opair, int *__restrict__ oma, int *__restrict__ omb,
+                        int *__restrict__ oa, int *__restrict__ ob, float *__restrict__ ofeat) {
+    const int64_t k = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (k >= n_pairs) return;
+    uint32_t c[4] = {static_cast<uint32_t>(k), 0u, 0u, 5u};
+    philox(c, k0, k1);
+    const int t = static_cast<int>(c[0] % static_cast<uint32_t>(G.n_rot));
+    const int64_t lo = ooff[t * G.n_det], hi = ooff[(t + 1) * G.n_det];
+    const uint32_t cnt = static_cast<uint32_t>(hi - lo);
+    int found = 0;
+    int64_t base = pass ? offs[k] : 0;
+    if (cnt > 0) {
+        const int64_t a = lo + c[1] % cnt, b = lo + c[2] % cnt;
+        if (a != b) {
+            int ba = t * G.n_det, bb = t * G.n_det;
+            while (ba + 1 < (t + 1) * G.n_det && ooff[ba + 1] <= a) ++ba;
+            while (bb + 1 < (t + 1) * G.n_det && ooff[bb + 1] <= b) ++bb;
+            double na[3], nb[3], pa[3], pb[3], sa, sb;
+            spot_normal(G, ba, P1[a], P2[a], na, sa, pa);
+            spot_normal(G, bb, P1[b], P2[b], nb, sb, pb);
+            double cab = na[0] * nb[0] + na[1] * nb[1] + na[2] * nb[2];
+            cab = fmin(1.0, fmax(-1.0, cab));
+            const double ang_n = acos(cab);
+            const int M = tab->M;
+            const double lmin = G.lambda_min, lmax = G.lambda_max;
+            for (int r = 0; r < tab->n_rep; ++r) {
+                const int ma = tab->rep[r];
+                const double la = 2.0 * static_cast<double>(Dsp[ma]) * sa;
+                if (!(la >= lmin && la <= lmax)) continue;
+                for (int mb = 0; mb < M; ++mb) {
+                    const double aw = angw[static_cast<int64_t>(r) * M + mb];
+                    if (!(aw >= 0.0)) continue;          // parallel planes are marked NaN
+                    if (!(fabs(aw - ang_n) <= delta)) continue;
+                    const double lb = 2.0 * static_cast<double>(Dsp[mb]) * sb;
+                    if (!(lb >= lmin && lb <= lmax)) continue;
+                    if (pass) {
+                        const int64_t pos = base + found;
+                        if (pos < cap) {
+                            double wa[3] = {W[3 * ma], W[3 * ma + 1], W[3 * ma + 2]};
+                            double wb[3] = {W[3 * mb], W[3 * mb + 1], W[3 * mb + 2]};
+                            double cn[3], cw[3];
+                            cross3(na, nb, cn);
+                            cross3(wa, wb, cw);
+                            const double ln = sqrt(cn[0] * cn[0] + cn[1] * cn[1] + cn[2] * cn[2]);
+                            const double lw = sqrt(cw[0] * cw[0] + cw[1] * cw[1] + cw[2] * cw[2]);
+                            double A[3][3], Bm[3][3];
+                            for (int i = 0; i < 3; ++i) {
+                                A[0][i] = na[i];
+                                A[1][i] = nb[i];
+                                A[2][i] = ln > 0 ? cn[i] / ln : 0.0;
+                                Bm[0][i] = wa[i];
+                                Bm[1][i] = wb[i];
+                                Bm[2][i] = lw > 0 ? cw[i] / lw : 0.0;
+                            }
+                            double q[4];
+                            wahba_quat(A, Bm, q);
+                            for (int i = 0; i < 4; ++i) oq[4 * pos + i] = q[i];
+                            if (opair) opair[pos] = static_cast<int>(k);
+                            if (oma) oma[pos] = ma;
+                            if (omb) omb[pos] = mb;
+                            if (oa) oa[pos] = static_cast<int>(a);
+                            if (ob) ob[pos] = static_cast<int>(b);
+                            if (ofeat) {
+                                float *f = ofeat + 16 * pos;
+                                const double dw = wa[0] * wb[0] + wa[1] * wb[1] + wa[2] * wb[2];
+                                double dp = 0.0;
+                                for (int i = 0; i < 3; ++i) dp += (pa[i] - pb[i]) * (pa[i] - pb[i]);
+                                f[0] = static_cast<float>(cab);
+                                f[1] = static_cast<float>(dw);
+                                f[2] = static_cast<float>(fabs(aw - ang_n) / delta);
+                                f[3] = static_cast<float>(sa);
+                                f[4] = static_cast<float>(sb);
+                                f[5] = static_cast<float>((la - lmin) / (lmax - lmin));
+                                f[6] = static_cast<float>((lb - lmin) / (lmax - lmin));
+                                f[7] = nrat[ma];
+                                f[8] = nrat[mb];
+                                f[9] = static_cast<float>(sqrt(dp) / (2.0 * l_side));
+                                f[10] = static_cast<float>(sqrt(static_cast<double>(P1[a]) * P1[a] +
+                                                                static_cast<double>(P2[a]) * P2[a]) / l_side);
+                                f[11] = static_cast<float>(sqrt(static_cast<double>(P1[b]) * P1[b] +
+                                                                static_cast<double>(P2[b]) * P2[b]) / l_side);
+                                f[12] = static_cast<float>(ba - t * G.n_det);
+                                f[13] = static_cast<float>(bb - t * G.n_det);
+                                f[14] = 0.0f;
+                                f[15] = 0.0f;
+                            }
+                        }
+                    }
+                    ++found;
+                }
+            }
+        }
+    }
+    if (!pass) counts[k] = found;
+}
+
+// ---------------------------------------------------------------- slots
+
+template <int S>
+__device__ __forceinline__ float seg_sum(float v) {
+#pragma unroll
+    for (int o = S / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+template <int S>
+__device__ __forceinline__ double seg_sum_d(double v) {
+#pragma unroll
+    for (int o = S / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+struct SlotArgs {
+    int C;                  // candidates in the batch
+    int nb;                 // blocks
+    int G;                  // groups per block
+    const int64_t *offs;    // [nb * C + 1] model-spot offsets per (block, candidate)
+    const float *P1, *P2;
+    const int64_t *ooff;    // detected-spot block offsets (device)
+    const Col8 *colsE, *colsC;
+    const GeomF *geom;
+    const float *W;
+    int n_planes;
+    const GrainF *grains;
+    const int *mplane, *mgrain, *mblock;
+};
+
+// Single-grain E-step (row softmax with the outlier column, App. D) fused
+// with the M-step statistics; writes per (candidate, block) the summed
+// 27-value normal-equation contribution.
+template <int S>
+__global__ __launch_bounds__(64) void k_single_acc(SlotArgs A, float K, float bin_e, double D2,
+                                                   double *__restrict__ hg_out) {
+    const int item = blockIdx.x;
+    const int b = item / A.G, g = item - b * A.G;
+    const int lane = threadIdx.x;
+    const int c = g * (64 / S) + lane / S, k = lane % S;
+    const bool cv = c < A.C;
+    const int64_t o0 = cv ? A.offs[static_cast<int64_t>(b) * A.C + c] : 0;
+    const int64_t o1 = cv ? A.offs[static_cast<int64_t>(b) * A.C + c + 1] : 0;
+    const bool act = cv && (k < o1 - o0);
+    const int64_t col = o0 + k;
+    Col8 cE = {0, 0, 0, 0, 1, 1, 1, 0}, cC = {0, 0, 0, 0, 1, 1, 1, 0};
+    if (act) {
+        cE = A.colsE[col];
+        cC = A.colsC[col];
+    }
+    const float vlen = sqrtf(cC.vv), ivl = 1.0f / vlen;
+    const float rn = cC.vn * ivl, r1 = cC.v1 * ivl, r2 = cC.v2 * ivl;
+    const int64_t r0 = A.ooff[b], rend = A.ooff[b + 1];
+    double s64[kStat];
+    for (int q = 0; q < kStat; ++q) s64[q] = 0.0;
+    for (int64_t i0 = r0; i0 < rend; i0 += 64) {
+        const int64_t i1 = min(i0 + 64, rend);
+        float a[kStat];
+        for (int q = 0; q < kStat; ++q) a[q] = 0.0f;
+        for (int64_t i = i0; i < i1; ++i) {
+            const float p1 = A.P1[i], p2 = A.P2[i];
+            const float e = act ? fast_exp2(entry_exponent(p1, p2, cE.s1, cE.s2, cE.v1, cE.v2, cE.vv,
+                                                           cE.vv2, K, 0.0f))
+                                : 0.0f;
+            const float z = seg_sum<S>(e) + bin_e;
+            const float Q = e * __builtin_amdgcn_rcpf(z);
+            if (Q > 0.0f) accumulate_stats(a, Q, p1, p2, cC, vlen, rn, r1, r2);
+        }
+        for (int q = 0; q < kStat; ++q) s64[q] += static_cast<double>(a[q]);
+    }
+    double hg[kHg];
+    if (act)
+        column_normal_equations(*A.geom, A.W, A.n_planes, A.grains, A.C, A.mplane[col],
+                                A.mgrain[col], A.mblock[col], s64, rn, r1, r2, D2, hg);
+    else
+        for (int q = 0; q < kHg; ++q) hg[q] = 0.0;
+    for (int q = 0; q < kHg; ++q) {
+        const double v = seg_sum_d<S>(hg[q]);
+        if (k == 0 && cv) hg_out[(static_cast<int64_t>(c) * A.nb + b) * kHg + q] = v;
+    }
+}
+
+// One wave per candidate: sum its per-block contributions (fixed order),
+// then the FP64 Gauss-Newton step.
+__global__ __launch_bounds__(64) void k_single_solve(const double *__restrict__ hg, int nb, int C,
+                                                     double mu_rel, double *q, double *x,
+                                                     GrainF *__restrict__ gf) {
+    const int c = blockIdx.x;
+    if (c >= C) return;
+    double acc[kHg];
+    for (int k = 0; k < kHg; ++k) acc[k] = 0.0;
+    for (int b = threadIdx.x; b < nb; b += 64)
+        for (int k = 0; k < kHg; ++k) acc[k] += hg[(static_cast<int64_t>(c) * nb + b) * kHg + k];
+    for (int k = 0; k < kHg; ++k) acc[k] = wave_sum(acc[k]);
+    if (threadIdx.x != 0) return;
+    gn_solve_apply(acc, mu_rel, q + 4 * c, x + 3 * c, gf + c, nullptr);
+}
+
+// Scoring at the final grains.  Per model spot: unmatched when no detected
+// spot of its block is within c_out.  Per detected spot and candidate: the
+// SPOT entry Lbar = ln sum_j exp(-c_ij / (2 sigma^2)) when above the floor
+// exp(-c_out / (2 sigma^2)).  pass 0 counts per (candidate, block); pass 1
+// writes the entries at loff (CSR by candidate, then block, then row).
+template <int S>
+__global__ __launch_bounds__(64) void k_single_score(SlotArgs A, int pass, float twoD2, float K2,
+                                                     float floor_e, float c_out,
+                                                     int *__restrict__ unm, int *__restrict__ lcnt,
+                                                     const int64_t *__restrict__ loff,
+                                                     const uint8_t *__restrict__ keep,
+                                                     int *__restrict__ lrow,
+                                                     float *__restrict__ lval) {
+    const int item = blockIdx.x;
+    const int b = item / A.G, g = item - b * A.G;
+    const int lane = threadIdx.x;
+    const int c = g * (64 / S) + lane / S, k = lane % S;
+    const bool cv = c < A.C;
+    const int64_t o0 = cv ? A.offs[static_cast<int64_t>(b) * A.C + c] : 0;
+    const int64_t o1 = cv ? A.offs[static_cast<int64_t>(b) * A.C + c + 1] : 0;
+    // pass 1 writes entries of kept candidates only (dropped ones have no range)
+    const bool has = cv && o1 > o0 && (!pass || keep[c]);
+    const bool act = cv && (k < o1 - o0);
+    Col8 cC = {0, 0, 0, 0, 1, 1, 1, 0};
+    if (act) cC = A.colsC[o0 + k];
+    const int64_t r0 = A.ooff[b], rend = A.ooff[b + 1];
+    float cmin = INFINITY;
+    int cnt = 0;
+    int64_t pos = (pass && cv) ? loff[static_cast<int64_t>(c) * A.nb + b] : 0;
+    for (int64_t i = r0; i < rend; ++i) {
+        const float cp = act ? entry_exponent(A.P1[i], A.P2[i], cC.s1, cC.s2, cC.v1, cC.v2, cC.vv,
+                                              cC.vv2, -1.0f, 0.0f)
+                             : INFINITY;
+        cmin = fminf(cmin, twoD2 * cp);
+        const float e = act ? fast_exp2(-K2 * cp) : 0.0f;
+        const float z = seg_sum<S>(e);
+        if (has && z > floor_e) {
+            if (pass && k == 0) {
+                lrow[pos] = static_cast<int>(i);
+                lval[pos] = __logf(z);
+            }
+            ++pos;
+            ++cnt;
+        }
+    }
+    if (!pass) {
+        const float um = seg_sum<S>((act && cmin > c_out) ? 1.0f : 0.0f);
+        if (k == 0 && cv) {
+            unm[static_cast<int64_t>(c) * A.nb + b] = static_cast<int>(um);
+            lcnt[static_cast<int64_t>(c) * A.nb + b] = cnt;
+        }
+    }
+}
+
+// Keep decision per candidate: unmatched fraction < f_out (Sec. 6.2, Sec. 7).
+// Dropped candidates get no SPOT entries.
+__global__ void k_single_keep(int C, int nb, const int64_t *__restrict__ offs,
+                              const int *__restrict__ unm, int *__restrict__ lcnt, double f_out,
+                              uint8_t *__restrict__ keep_ws, int *__restrict__ o_nmodel,
+                              int *__restrict__ o_unm, uint8_t *__restrict__ o_keep) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= C) return;
+    int64_t nm = 0, nu = 0;
+    for (int b = 0; b < nb; ++b) {
+        nm += offs[static_cast<int64_t>(b) * C + c + 1] - offs[static_cast<int64_t>(b) * C + c];
+        nu += unm[static_cast<int64_t>(c) * nb + b];
+    }
+    const bool keep = nm > 0 && static_cast<double>(nu) < f_out * static_cast<double>(nm);
+    if (!keep)
+        for (int b = 0; b < nb; ++b) lcnt[static_cast<int64_t>(c) * nb + b] = 0;
+    keep_ws[c] = keep ? 1 : 0;
+    if (o_nmodel) o_nmodel[c] = static_cast<int>(nm);
+    if (o_unm) o_unm[c] = static_cast<int>(nu);
+    if (o_keep) o_keep[c] = keep ? 1 : 0;
+}
+
+__global__ void k_max_int(const int *__restrict__ v, int64_t n, int *__restrict__ out) {
+    __shared__ int part[256];
+    int m = 0;
+    for (int64_t i = threadIdx.x; i < n; i += 256) m = max(m, v[i]);
+    part[threadIdx.x] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int r = 0;
+        for (int k = 0; k < 256; ++k) r = max(r, part[k]);
+        *out = r;
+    }
+}
+
+// cand_off[c0 + c] = base + loff[c * nb] for the batch's candidates.
+__global__ void k_cand_off(const int64_t *__restrict__ loff, int C, int nb, int64_t base,
+                           int64_t *__restrict__ cand_off, int c0, int last) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c < C) cand_off[c0 + c] = base + loff[static_cast<int64_t>(c) * nb];
+    if (last && c == C) cand_off[c0 + C] = base + loff[static_cast<int64_t>(C) * nb];
+}
+
+// ---------------------------------------------------------------- SPOT greedy
+
+__global__ __launch_bounds__(64) void k_gain(const int64_t *__restrict__ off,
+                                             const int *__restrict__ row,
+                                             const float *__restrict__ val,
+                                             const float *__restrict__ cur,
+                                             const uint8_t *__restrict__ picked,
+                                             double *__restrict__ gain, const int *__restrict__ done,
+                                             int n) {
+    const int c = blockIdx.x;
+    if (c >= n || *done) return;
+    if (picked[c]) {
+        if (threadIdx.x == 0) gain[c] = -1.0;
+        return;
+    }
+    double s = 0.0;
+    for (int64_t e = off[c] + threadIdx.x; e < off[c + 1]; e += 64)
+        s += fmax(0.0, static_cast<double>(val[e]) - static_cast<double>(cur[row[e]]));
+    s = wave_sum(s);
+    if (threadIdx.x == 0) gain[c] = s;
+}
+
+// Pick the largest gain (lowest index on ties), record it and raise the
+// covered rows' current values.
+__global__ __launch_bounds__(1024) void k_pick(const double *__restrict__ gain, int n,
+                                               const int64_t *__restrict__ off,
+                                               const int *__restrict__ row,
+                                               const float *__restrict__ val, float *cur,
+                                               uint8_t *picked, int *picks, double *pgain,
+                                               int step, int *done) {
+    if (*done) return;
+    __shared__ double bv[1024];
+    __shared__ int bi[1024];
+    double best = 0.0;
+    int arg = -1;
+    for (int c = threadIdx.x; c < n; c += 1024) {
+        const double g = gain[c];
+        if (g > best) {
+            best = g;
+            arg = c;
+        }
+    }
+    bv[threadIdx.x] = best;
+    bi[threadIdx.x] = arg;
+    __syncthreads();
+    for (int s = 512; s > 0; s >>= 1) {
+        if (threadIdx.x < s) {
+            const double o = bv[threadIdx.x + s];
+            const int oi = bi[threadIdx.x + s];
+            if (o > bv[threadIdx.x] || (o == bv[threadIdx.x] && oi >= 0 &&
+                                        (bi[threadIdx.x] < 0 || oi < bi[threadIdx.x]))) {
+                bv[threadIdx.x] = o;
+                bi[threadIdx.x] = oi;
+            }
+        }
+        __syncthreads();
+    }
+    const int c = bi[0];
+    const double g = bv[0];
+    __syncthreads();
+    if (c < 0 || !(g > 0.0)) {
+        if (threadIdx.x == 0) *done = 1;
+        return;
+    }
+    for (int64_t e = off[c] + threadIdx.x; e < off[c + 1]; e += 1024)
+        cur[row[e]] = fmaxf(cur[row[e]], val[e]);
+    if (threadIdx.x == 0) {
+        picked[c] = 1;
+        picks[step] = c;
+        pgain[step] = g;
+    }
+}
+
+__global__ void k_set_i64(int64_t *p, int64_t v) { *p = v; }
+__global__ void k_fill_f(float *p, int64_t n, float v) {
+    int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+__global__ void k_fill_u8(uint8_t *p, int64_t n, uint8_t v) {
+    int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+__global__ void k_fill_i(int *p, int64_t n, int v) {
+    int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+}  // namespace laue
+
+using namespace laue;
+
+// ---------------------------------------------------------------- host: candidates
+
+namespace {
+
+struct CandWs {
+    PairTab *tab;
+    double *angw;
+    float *nrat;
+    int64_t *ooff;
+    int *counts;
+    int64_t *offs;
+};
+
+size_t carve_cand(Carver &cv, CandWs &w, int M, int nb, int64_t n_pairs) {
+    w.tab = cv.take<PairTab>(1);
+    w.angw = cv.take<double>(static_cast<size_t>(kMaxReps) * std::max(M, 1));
+    w.nrat = cv.take<float>(std::max(M, 1));
+    w.ooff = cv.take<int64_t>(nb + 1);
+    w.counts = cv.take<int>(std::max<int64_t>(n_pairs, 1));
+    w.offs = cv.take<int64_t>(std::max<int64_t>(n_pairs, 1) + 1);
+    return cv.size();
+}
+
+int validate_obs_host(const laue_obs_spots *o, int nb) {
+    LAUE_REQUIRE(o && o->block_off && o->n >= 0, LAUE_EINVAL, "detected spots or block_off is NULL");
+    LAUE_REQUIRE(o->n == 0 || (o->p1 && o->p2), LAUE_EINVAL, "detected-spot arrays are NULL");
+    LAUE_REQUIRE(o->block_off[0] == 0 && o->block_off[nb] == o->n, LAUE_EINVAL,
+                 "detected-spot block offsets must run from 0 to n");
+    for (int b = 0; b < nb; ++b)
+        LAUE_REQUIRE(o->block_off[b + 1] >= o->block_off[b], LAUE_EINVAL,
+                     "detected-spot block offsets must be non-decreasing");
+    LAUE_REQUIRE(o->n < (int64_t(1) << 31), LAUE_EINVAL, "too many detected spots");
+    return LAUE_OK;
+}
+
+}  // namespace
+
+extern "C" size_t laue_candidates_workspace_size(const laue_geometry *geom, int32_t n_planes,
+                                                 int64_t n_pairs) {
+    if (!geom || validate_geometry(geom) != LAUE_OK || n_planes < 0 || n_pairs < 0) return 0;
+    Carver cv(nullptr);
+    CandWs w;
+    return carve_cand(cv, w, n_planes, geom->n_rot * geom->n_det, n_pairs);
+}
+
+extern "C" int laue_candidates_generate(const laue_geometry *geom, const laue_planes *planes,
+                                        const laue_obs_spots *obs, const laue_cand_params *par,
+                                        laue_candidates *out, int64_t *n_found, void *ws,
+                                        size_t ws_bytes, void *stream) {
+    clear_error();
+    int rc;
+    if ((rc = validate_geometry(geom)) || (rc = validate_planes(planes))) return rc;
+    const int nb = geom->n_rot * geom->n_det;
+    if ((rc = validate_obs_host(obs, nb))) return rc;
+    LAUE_REQUIRE(par && out && n_found && out->q, LAUE_EINVAL, "NULL argument");
+    LAUE_REQUIRE(par->n_pairs >= 0 && par->n_pairs < (int64_t(1) << 31), LAUE_EINVAL, "bad n_pairs");
+    LAUE_REQUIRE(std::isfinite(par->delta_deg) && par->delta_deg > 0 && par->delta_deg < 90,
+                 LAUE_EINVAL, "bad angle tolerance");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    Carver cv(ws);
+    CandWs w;
+    size_t need = carve_cand(cv, w, planes->n, nb, par->n_pairs);
+    if ((rc = check_ws(ws, ws_bytes, need))) return rc;
+    // plane tables on the host: family representatives (w_x >= w_y >= w_z >= 0),
+    // pairwise angles in FP64 (NaN for parallel planes), N / N_max from d
+    const int M = planes->n;
+    std::vector<float> hw(3 * M), hd(M);
+    LAUE_CHECK_HIP(hipMemcpyAsync(hw.data(), planes->w, 3 * M * sizeof(float), hipMemcpyDeviceToHost, s));
+    LAUE_CHECK_HIP(hipMemcpyAsync(hd.data(), planes->d, M * sizeof(float), hipMemcpyDeviceToHost, s));
+    LAUE_CHECK_HIP(hipStreamSynchronize(s));
+    // one representative per orbit of the 24 proper cubic rotations (signed
+    // permutation matrices of determinant +1; exact on FP32 normals), the first
+    // plane of each orbit in list order
+    PairTab tab{};
+    tab.M = M;
+    {
+        std::vector<char> covered(M, 0);
+        const int perms[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
+        const int psign[6] = {1, -1, -1, 1, 1, -1};
+        for (int m = 0; m < M; ++m) {
+            if (covered[m]) continue;
+            LAUE_REQUIRE(tab.n_rep < kMaxReps, LAUE_EINVAL, "too many plane families");
+            tab.rep[tab.n_rep++] = m;
+            for (int pi = 0; pi < 6; ++pi)
+                for (int sg = 0; sg < 8; ++sg) {
+                    const int s0 = (sg & 1) ? -1 : 1, s1 = (sg & 2) ? -1 : 1, s2 = (sg & 4) ? -1 : 1;
+                    if (psign[pi] * s0 * s1 * s2 != 1) continue;
+                    const float v[3] = {s0 * hw[3 * m + perms[pi][0]], s1 * hw[3 * m + perms[pi][1]],
+                                        s2 * hw[3 * m + perms[pi][2]]};
+                    // same normal and same spacing (harmonics share the normal)
+                    for (int j = 0; j < M; ++j)
+                        if (hd[j] == hd[m] && hw[3 * j] == v[0] && hw[3 * j + 1] == v[1] &&
+                            hw[3 * j + 2] == v[2]) {
+                            covered[j] = 1;
+                            break;
+                        }
+                }
+        }
+    }
+    std::vector<double> angw(static_cast<size_t>(tab.n_rep) * M);
+    for (int r = 0; r < tab.n_rep; ++r) {
+        const int a = tab.rep[r];
+        for (int m = 0; m < M; ++m) {
+            double c = 0.0;
+            for (int k = 0; k < 3; ++k) c += static_cast<double>(hw[3 * a + k]) * hw[3 * m + k];
+            const bool par_ = std::fabs(std::fabs(c) - 1.0) < 1e-6;
+            angw[static_cast<size_t>(r) * M + m] = par_ ? std::nan("") : std::acos(std::max(-1.0, std::min(1.0, c)));
+        }
+    }
+    float dmin = *std::min_element(hd.begin(), hd.end());
+    std::vector<float> nrat(M);
+    for (int m = 0; m < M; ++m) nrat[m] = static_cast<float>((static_cast<double>(dmin) * dmin) / (static_cast<double>(hd[m]) * hd[m]));
+    LAUE_CHECK_HIP(hipMemcpyAsync(w.tab, &tab, sizeof(PairTab), hipMemcpyHostToDevice, s));
+    LAUE_CHECK_HIP(hipMemcpyAsync(w.angw, angw.data(), angw.size() * sizeof(double), hipMemcpyHostToDevice, s));
+    LAUE_CHECK_HIP(hipMemcpyAsync(w.nrat, nrat.data(), M * sizeof(float), hipMemcpyHostToDevice, s));
+    LAUE_CHECK_HIP(hipMemcpyAsync(w.ooff, obs->block_off, (nb + 1) * sizeof(int64_t), hipMemcpyHostToDevice, s));
+    const uint32_t k0 = static_cast<uint32_t>(par->seed & 0xffffffffu), k1 = static_cast<uint32_t>(par->seed >> 32);
+    const double delta = par->delta_deg * M_PI / 180.0;
+    const double l_side = 2.0 * geom->det[0].half_size;
+    const int64_t P = par->n_pairs;
+    int64_t total = 0;
+    if (P > 0) {
+        const unsigned nbk = static_cast<unsigned>((P + 127) / 128);
+        k_pairs<<<nbk, 128, 0, s>>>(0, *geom, obs->p1, obs->p2, w.ooff, planes->w, planes->d, w.tab,
+                                     w.angw, w.nrat, P, k0, k1, delta, l_side, w.counts, nullptr, 0,
+                                     nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr);
+        LAUE_CHECK_HIP(hipGetLastError());
+        if ((rc = launch_scan(w.counts, w.offs, P, s))) return rc;
+        LAUE_CHECK_HIP(hipMemcpyAsync(&total, w.offs + P, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+        LAUE_CHECK_HIP(hipStreamSynchronize(s));
+    }
+    *n_found = total;
+    const int64_t cap = out->n;
+    if (total > 0 && cap > 0) {
+        k_pairs<<<static_cast<unsigned>((P + 127) / 128), 128, 0, s>>>(
+            1, *geom, obs->p1, obs->p2, w.ooff, planes->w, planes->d, w.tab, w.angw, w.nrat, P, k0, k1,
+            delta, l_side, nullptr, w.offs, cap, out->q, out->pair, out->ma, out->mb, out->spot_a,
+            out->spot_b, out->feat);
+        LAUE_CHECK_HIP(hipGetLastError());
+    }
+    out->n = std::min(total, cap);
+    LAUE_CHECK_HIP(hipStreamSynchronize(s));
+    return LAUE_OK;
+}
+
+// ---------------------------------------------------------------- host: scoring
+
+namespace {
+
+struct ScoreWs {
+    EnumWs e;
+    int *plane, *grain, *block;
+    Col8 *colsE, *colsC;
+    double *hg;
+    int *unm, *lcnt;
+    uint8_t *keep;
+    int64_t *loff;
+    int64_t *ooff;
+    int *maxc;
+};
+
+size_t carve_score(Carver &cv, ScoreWs &w, const laue_geometry *g, int chunk, int64_t spot_cap) {
+    const int nb = g->n_rot * g->n_det;
+    carve_enum(cv, w.e, g, chunk);
+    const int64_t S = std::max<int64_t>(spot_cap, 1);
+    w.plane = cv.take<int>(S);
+    w.grain = cv.take<int>(S);
+    w.block = cv.take<int>(S);
+    w.colsE = cv.take<Col8>(S);
+    w.colsC = cv.take<Col8>(S);
+    w.hg = cv.take<double>(static_cast<size_t>(chunk) * nb * kHg);
+    w.unm = cv.take<int>(static_cast<size_t>(chunk) * nb);
+    w.lcnt = cv.take<int>(static_cast<size_t>(chunk) * nb + 1);
+    w.loff = cv.take<int64_t>(static_cast<size_t>(chunk) * nb + 1);
+    w.keep = cv.take<uint8_t>(chunk);
+    w.ooff = cv.take<int64_t>(nb + 1);
+    w.maxc = cv.take<int>(1);
+    return cv.size();
+}
+
+int dispatch_acc(int S, const SlotArgs &A, float K, float bin_e, double D2, double *hg, hipStream_t s) {
+    const unsigned grid = static_cast<unsigned>(A.nb) * A.G;
+    switch (S) {
+        case 1: k_single_acc<1><<<grid, 64, 0, s>>>(A, K, bin_e, D2, hg); break;
+        case 2: k_single_acc<2><<<grid, 64, 0, s>>>(A, K, bin_e, D2, hg); break;
+        case 4: k_single_acc<4><<<grid, 64, 0, s>>>(A, K, bin_e, D2, hg); break;
+        case 8: k_single_acc<8><<<grid, 64, 0, s>>>(A, K, bin_e, D2, hg); break;
+        case 16: k_single_acc<16><<<grid, 64, 0, s>>>(A, K, bin_e, D2, hg); break;
+        case 32: k_single_acc<32><<<grid, 64, 0, s>>>(A, K, bin_e, D2, hg); break;
+        default: k_single_acc<64><<<grid, 64, 0, s>>>(A, K, bin_e, D2, hg); break;
+    }
+    LAUE_CHECK_HIP(hipGetLastError());
+    return LAUE_OK;
+}
+
+int dispatch_score(int S, const SlotArgs &A, int pass, float twoD2, float K2, float floor_e,
+                   float c_out, int *unm, int *lcnt, const int64_t *loff, const uint8_t *keep,
+                   int *lrow, float *lval, hipStream_t s) {
+    const unsigned grid = static_cast<unsigned>(A.nb) * A.G;
+#define LAUE_SCORE(SS) k_single_score<SS><<<grid, 64, 0, s>>>(A, pass, twoD2, K2, floor_e, c_out, unm, lcnt, loff, keep, lrow, lval)
+    switch (S) {
+        case 1: LAUE_SCORE(1); break;
+        case 2: LAUE_SCORE(2); break;
+        case 4: LAUE_SCORE(4); break;
+        case 8: LAUE_SCORE(8); break;
+        case 16: LAUE_SCORE(16); break;
+        case 32: LAUE_SCORE(32); break;
+        default: LAUE_SCORE(64); break;
+    }
+#undef LAUE_SCORE
+    LAUE_CHECK_HIP(hipGetLastError());
+    return LAUE_OK;
+}
+
+}  // namespace
+
+extern "C" size_t laue_score_workspace_size(const laue_geometry *geom, const laue_score_params *par) {
+    if (!geom || !par || validate_geometry(geom) != LAUE_OK || par->chunk < 1 || par->max_spots_per_cand < 1)
+        return 0;
+    Carver cv(nullptr);
+    ScoreWs w;
+    return carve_score(cv, w, geom, par->chunk, static_cast<int64_t>(par->chunk) * par->max_spots_per_cand);
+}
+
+extern "C" int laue_score_candidates(const laue_geometry *geom, const laue_planes *planes,
+                                     const laue_obs_spots *obs, laue_grains *cand,
+                                     const laue_score_params *par, laue_score_out *out, void *ws,
+                                     size_t ws_bytes, void *stream) {
+    clear_error();
+    int rc;
+    if ((rc = validate_geometry(geom)) || (rc = validate_planes(planes)) || (rc = validate_grains(cand)))
+        return rc;
+    const int nb = geom->n_rot * geom->n_det;
+    if ((rc = validate_obs_host(obs, nb))) return rc;
+    LAUE_REQUIRE(par && out, LAUE_EINVAL, "NULL argument");
+    LAUE_REQUIRE(par->chunk >= 1 && par->max_spots_per_cand >= 1 && par->k_refine >= 0 && par->k_gn >= 0,
+                 LAUE_EINVAL, "bad scoring parameters");
+    LAUE_REQUIRE(std::isfinite(par->sigma_mm) && par->sigma_mm > 0 && std::isfinite(par->distance) &&
+                     par->distance > 0 && std::isfinite(par->c_out) && par->c_out > 0 &&
+                     std::isfinite(par->f_out) && std::isfinite(par->mu_rel) && par->mu_rel >= 0 &&
+                     std::isfinite(par->eps_start) && std::isfinite(par->eps_end) &&
+                     par->eps_start > 0 && par->eps_end > 0,
+                 LAUE_EINVAL, "bad scoring parameters");
+    LAUE_REQUIRE(out->lbar_off && (out->lbar_cap == 0 || (out->lbar_row && out->lbar_val)), LAUE_EINVAL,
+                 "SPOT output arrays are NULL");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int chunk = par->chunk;
+    const int64_t spot_cap = static_cast<int64_t>(chunk) * par->max_spots_per_cand;
+    Carver cv(ws);
+    ScoreWs w;
+    size_t need = carve_score(cv, w, geom, chunk, spot_cap);
+    if ((rc = check_ws(ws, ws_bytes, need))) return rc;
+    LAUE_CHECK_HIP(hipMemcpyAsync(w.ooff, obs->block_off, (nb + 1) * sizeof(int64_t), hipMemcpyHostToDevice, s));
+    const double l2e = 1.4426950408889634;
+    const double D2 = par->distance * par->distance;
+    const float twoD2 = static_cast<float>(2.0 * D2);
+    const float K2 = static_cast<float>(2.0 * D2 * l2e / (2.0 * par->sigma_mm * par->sigma_mm));
+    const float floor_e = static_cast<float>(std::exp(-par->c_out / (2.0 * par->sigma_mm * par->sigma_mm)));
+    int64_t lbar_total = 0;
+    const int N = cand->n;
+    if (N == 0) {
+        k_set_i64<<<1, 1, 0, s>>>(out->lbar_off, 0);
+        LAUE_CHECK_HIP(hipGetLastError());
+    }
+    for (int c0 = 0; c0 < N; c0 += chunk) {
+        const int C = std::min(chunk, N - c0);
+        laue_grains sub{C, cand->q + 4 * static_cast<int64_t>(c0), cand->x + 3 * static_cast<int64_t>(c0)};
+        std::vector<int64_t> hb;
+        int64_t total = 0;
+        if ((rc = enumerate_count(geom, planes, &sub, 1, w.e, hb, &total, s))) return rc;
+        if (total > spot_cap) {
+            set_error("candidate model spots " + std::to_string(total) + " exceed the batch capacity " +
+                      std::to_string(spot_cap) + " (raise max_spots_per_cand or lower chunk)");
+            return LAUE_ECAPACITY;
+        }
+        const int64_t L = static_cast<int64_t>(nb) * C;
+        k_max_int<<<1, 256, 0, s>>>(w.e.counts, L, w.maxc);
+        int maxc = 0;
+        LAUE_CHECK_HIP(hipMemcpyAsync(&maxc, w.maxc, sizeof(int), hipMemcpyDeviceToHost, s));
+        LAUE_CHECK_HIP(hipStreamSynchronize(s));
+        LAUE_REQUIRE(maxc <= 64, LAUE_ECAPACITY, "a candidate has more than 64 model spots in one block");
+        int S = 1;
+        while (S < maxc) S <<= 1;
+        if ((rc = launch_enumerate_ids(geom, planes, w.e, C, 1, w.plane, w.grain, w.block, s))) return rc;
+        SlotArgs A;
+        A.C = C;
+        A.nb = nb;
+        A.G = (C * S + 63) / 64;
+        A.offs = w.e.offs;
+        A.P1 = obs->p1;
+        A.P2 = obs->p2;
+        A.ooff = w.ooff;
+        A.colsE = w.colsE;
+        A.colsC = w.colsC;
+        A.geom = w.e.geom;
+        A.W = planes->w;
+        A.n_planes = planes->n;
+        A.grains = w.e.grains;
+        A.mplane = w.plane;
+        A.mgrain = w.grain;
+        A.mblock = w.block;
+        for (int it = 0; it < par->k_refine; ++it) {
+            const double eps = par->k_refine == 1 ? par->eps_start
+                               : par->eps_start * std::pow(par->eps_end / par->eps_start,
+                                                           static_cast<double>(it) / (par->k_refine - 1));
+            const float K = static_cast<float>(2.0 * D2 * l2e / eps);
+            const float bin_e = static_cast<float>(std::exp(-par->c_out / eps));
+            if ((rc = launch_eval(w.e.geom, planes, w.e.grains, C, w.plane, w.grain, w.block, total,
+                                  nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, w.colsE, s)))
+                return rc;
+            for (int k = 0; k < par->k_gn; ++k) {
+                A.colsC = w.colsE;
+                if (k > 0) {
+                    if ((rc = launch_eval(w.e.geom, planes, w.e.grains, C, w.plane, w.grain, w.block,
+                                          total, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
+                                          w.colsC, s)))
+                        return rc;
+                    A.colsC = w.colsC;
+                }
+                if ((rc = dispatch_acc(S, A, K, bin_e, D2, w.hg, s))) return rc;
+                k_single_solve<<<C, 64, 0, s>>>(w.hg, nb, C, par->mu_rel, sub.q, sub.x, w.e.grains);
+                LAUE_CHECK_HIP(hipGetLastError());
+            }
+        }
+        // scoring at the refined grains
+        if ((rc = launch_eval(w.e.geom, planes, w.e.grains, C, w.plane, w.grain, w.block, total,
+                              nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, w.colsC, s)))
+            return rc;
+        A.colsC = w.colsC;
+        if ((rc = dispatch_score(S, A, 0, twoD2, K2, floor_e, static_cast<float>(par->c_out), w.unm,
+                                 w.lcnt, nullptr, nullptr, nullptr, nullptr, s)))
+            return rc;
+        k_single_keep<<<(C + 127) / 128, 128, 0, s>>>(C, nb, w.e.offs, w.unm, w.lcnt, par->f_out,
+                                                      w.keep,
+                                                      out->n_model ? out->n_model + c0 : nullptr,
+                                                      out->n_unmatched ? out->n_unmatched + c0 : nullptr,
+                                                      out->keep ? out->keep + c0 : nullptr);
+        LAUE_CHECK_HIP(hipGetLastError());
+        if ((rc = launch_scan(w.lcnt, w.loff, L, s))) return rc;
+        int64_t ctot = 0;
+        LAUE_CHECK_HIP(hipMemcpyAsync(&ctot, w.loff + L, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+        LAUE_CHECK_HIP(hipStreamSynchronize(s));
+        if (lbar_total + ctot > out->lbar_cap) {
+            out->lbar_n = lbar_total + ctot;
+            set_error("SPOT entry capacity " + std::to_string(out->lbar_cap) + " exceeded");
+            return LAUE_ECAPACITY;
+        }
+        k_cand_off<<<(C + 1 + 127) / 128, 128, 0, s>>>(w.loff, C, nb, lbar_total, out->lbar_off, c0, 1);
+        LAUE_CHECK_HIP(hipGetLastError());
+        if (ctot > 0 &&
+            (rc = dispatch_score(S, A, 1, twoD2, K2, floor_e, static_cast<float>(par->c_out), nullptr,
+                                 nullptr, w.loff, w.keep, out->lbar_row + lbar_total,
+                                 out->lbar_val + lbar_total, s)))
+            return rc;
+        lbar_total += ctot;
+    }
+    out->lbar_n = lbar_total;
+    LAUE_CHECK_HIP(hipStreamSynchronize(s));
+    return LAUE_OK;
+}
+
+// ---------------------------------------------------------------- host: greedy
+
+namespace {
+struct GreedyWs {
+    float *cur;
+    uint8_t *picked;
+    double *gain;
+    int *done;
+};
+size_t carve_greedy(Carver &cv, GreedyWs &w, int n_cand, int64_t n_rows) {
+    w.cur = cv.take<float>(std::max<int64_t>(n_rows, 1));
+    w.picked = cv.take<uint8_t>(std::max(n_cand, 1));
+    w.gain = cv.take<double>(std::max(n_cand, 1));
+    w.done = cv.take<int>(1);
+    return cv.size();
+}
+}  // namespace
+
+extern "C" size_t laue_spot_greedy_workspace_size(int32_t n_cand, int64_t n_rows) {
+    if (n_cand < 0 || n_rows < 0) return 0;
+    Carver cv(nullptr);
+    GreedyWs w;
+    return carve_greedy(cv, w, n_cand, n_rows);
+}
+
+extern "C" int laue_spot_greedy(const int64_t *lbar_off, const int32_t *lbar_row,
+                                const float *lbar_val, int32_t n_cand, int64_t n_rows, double phi,
+                                int32_t k_max, int32_t *picks, double *gains, int32_t *n_picked,
+                                void *ws, size_t ws_bytes, void *stream) {
+    clear_error();
+    int rc;
+    LAUE_REQUIRE(n_cand >= 0 && n_rows >= 0 && k_max >= 0 && n_picked, LAUE_EINVAL, "bad sizes");
+    LAUE_REQUIRE(n_cand == 0 || (lbar_off && lbar_row && lbar_val), LAUE_EINVAL, "SPOT arrays are NULL");
+    LAUE_REQUIRE(k_max == 0 || (picks && gains), LAUE_EINVAL, "outputs are NULL");
+    LAUE_REQUIRE(std::isfinite(phi), LAUE_EINVAL, "phi must be finite");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    Carver cv(ws);
+    GreedyWs w;
+    size_t need = carve_greedy(cv, w, n_cand, n_rows);
+    if ((rc = check_ws(ws, ws_bytes, need))) return rc;
+    *n_picked = 0;
+    if (n_cand == 0 || k_max == 0) return LAUE_OK;
+    k_fill_f<<<static_cast<unsigned>((std::max<int64_t>(n_rows, 1) + 255) / 256), 256, 0, s>>>(w.cur, n_rows, static_cast<float>(phi));
+    k_fill_u8<<<(n_cand + 255) / 256, 256, 0, s>>>(w.picked, n_cand, 0);
+    k_fill_i<<<1, 64, 0, s>>>(w.done, 1, 0);
+    k_fill_i<<<(k_max + 255) / 256, 256, 0, s>>>(picks, k_max, -1);
+    LAUE_CHECK_HIP(hipGetLastError());
+    const int K = std::min(k_max, n_cand);
+    for (int k = 0; k < K; ++k) {
+        k_gain<<<n_cand, 64, 0, s>>>(lbar_off, lbar_row, lbar_val, w.cur, w.picked, w.gain, w.done, n_cand);
+        k_pick<<<1, 1024, 0, s>>>(w.gain, n_cand, lbar_off, lbar_row, lbar_val, w.cur, w.picked, picks,
+                                  gains, k, w.done);
+    }
+    LAUE_CHECK_HIP(hipGetLastError());
+    std::vector<int> hp(K);
+    LAUE_CHECK_HIP(hipMemcpyAsync(hp.data(), picks, K * sizeof(int), hipMemcpyDeviceToHost, s));
+    LAUE_CHECK_HIP(hipStreamSynchronize(s));
+    int n = 0;
+    while (n < K && hp[n] >= 0) ++n;
+    *n_picked = n;
+    return LAUE_OK;
+}

@@ -1,0 +1,111 @@
+"""GPU parity of prototype scoring: pair candidates, single-grain refinement,
+the unmatched filter, SPOT entries and greedy selection, against the oracle."""
+import numpy as np
+import pytest
+import torch
+
+import inputgen as ig
+from oracle import candidates, cost, crystal, forward, metrics, simulate, single
+
+pytestmark = pytest.mark.gpu
+
+
+def _setup(laue, n_rot=8, n_grains=12, sigma=1.0, frac=0.3, seed=11):
+    p = ig.MEDIUM
+    pl = crystal.cubic_planes(p.a, p.centering, p.n_max)
+    g = forward.Geometry(n_rot, np.deg2rad(180.0 / n_rot), p.detectors, p.lam_min, p.lam_max)
+    q, x = ig.random_grains(p, n=n_grains, seed=seed)
+    sim = simulate.simulate(pl, q, x, g, sigma, frac, seed, p.distance)
+    p12 = ig.to_f32_exact(sim["p12"])
+    geom = laue.make_geometry(n_rot, np.deg2rad(180.0 / n_rot), p.detectors, p.lam_min, p.lam_max)
+    planes = laue.laue_planes_cubic(p.a, p.centering, p.n_max)
+    obs = laue.ObsSpots.from_numpy(p12, sim["offsets"])
+    return p, pl, g, q, x, sim, p12, geom, planes, obs
+
+
+def test_candidates_match_oracle(gpu_lib):
+    laue = gpu_lib
+    p, pl, g, q, x, sim, p12, geom, planes, obs = _setup(laue)
+    ref = candidates.generate(pl, g, p12, sim["offsets"], 400, 77)
+    gc = laue.laue_candidates_generate(geom, planes, obs, 400, 77)
+    assert gc["n_found"] > 1000
+    ko = set(zip(ref["pair"].tolist(), ref["ma"].tolist(), ref["mb"].tolist()))
+    kg = set(zip(gc["pair"].cpu().tolist(), gc["ma"].cpu().tolist(), gc["mb"].cpu().tolist()))
+    # hypotheses agree except at the angle-threshold edge (FP32 plane normals)
+    diff = ko ^ kg
+    assert len(diff) <= 2e-3 * len(ko), len(diff)
+    idx = {k: i for i, k in enumerate(zip(ref["pair"].tolist(), ref["ma"].tolist(), ref["mb"].tolist()))}
+    gi, oi = [], []
+    for j, k in enumerate(zip(gc["pair"].cpu().tolist(), gc["ma"].cpu().tolist(), gc["mb"].cpu().tolist())):
+        if k in idx:
+            gi.append(j)
+            oi.append(idx[k])
+    qg = gc["q"].cpu().numpy()[gi]
+    mis = np.degrees(metrics.misorientation(qg, ref["q"][oi]))
+    assert np.max(mis) < 1e-4
+    fg = gc["feat"].cpu().numpy()[gi][:, :14]
+    assert np.allclose(fg, ref["feat"][oi], atol=2e-5)
+    assert np.array_equal(gc["spot_a"].cpu().numpy()[gi], ref["a"][oi])
+
+
+def test_refine_score_match_oracle(gpu_lib):
+    laue = gpu_lib
+    p, pl, g, q, x, sim, p12, geom, planes, obs = _setup(laue)
+    ref = candidates.generate(pl, g, p12, sim["offsets"], 200, 5)
+    mis = np.degrees(metrics.misorientation(ref["q"][:, None, :], q[None, :, :])).min(axis=1)
+    # a few candidates near true grains, a few random ones
+    sel = np.concatenate([np.argsort(mis)[:6], np.arange(0, len(mis), max(1, len(mis) // 6))[:6]])
+    cq = ref["q"][sel]
+    cx = np.zeros((len(sel), 3))
+    c_out = cost.c_out(p.sigma_mm, p.distance)
+    outs = []
+    for k in range(len(sel)):
+        qq, xx, mod = single.refine(pl, g, p.distance, p12, sim["offsets"], cq[k], cx[k], p.sigma_mm, c_out,
+                                    k_refine=6, k_gn=2)
+        outs.append((qq, xx) + single.score(pl, g, p.distance, p12, sim["offsets"], mod, qq, xx, p.sigma_mm, c_out))
+    grains = laue.Grains(cq, cx)
+    par = laue.score_params(p.sigma_mm, p.distance, c_out, k_refine=6, k_gn=2, chunk=5)
+    res = laue.laue_score_candidates(geom, planes, obs, grains, par)
+    qg, xg = grains.numpy()
+    for k, (qq, xx, un, nm, rows, vals) in enumerate(outs):
+        assert np.degrees(metrics.misorientation(qg[k], qq)) < 1e-3
+        assert np.linalg.norm(xg[k] - xx) < 2e-3
+        assert res["n_model"][k].item() == nm
+        assert abs(res["n_unmatched"][k].item() - un) <= 1
+        keep = nm > 0 and un < 0.1 * nm
+        assert bool(res["keep"][k].item()) == keep
+        lo, hi = res["lbar_off"][k].item(), res["lbar_off"][k + 1].item()
+        if not keep:
+            assert hi == lo
+            continue
+        gr = res["lbar_row"][lo:hi].cpu().numpy()
+        gv = res["lbar_val"][lo:hi].cpu().numpy()
+        phi = -c_out / (2 * p.sigma_mm ** 2)
+        safe = np.abs(vals - phi) > 1e-3
+        ro = set(rows[safe].tolist())
+        assert ro <= set(gr.tolist())
+        m = {r: v for r, v in zip(gr.tolist(), gv.tolist())}
+        assert np.max(np.abs(np.array([m[r] for r in rows[safe]]) - vals[safe])) < 1e-4
+    # at least some true-grain candidates survive the filter
+    assert res["keep"].sum().item() >= 3
+
+
+def test_greedy_matches_oracle(gpu_lib):
+    laue = gpu_lib
+    rng = np.random.default_rng(3)
+    n_rows, n_cand, phi = 400, 30, -4.5
+    cols = []
+    for n in range(n_cand):
+        r = np.sort(rng.choice(n_rows, size=rng.integers(5, 60), replace=False))
+        v = phi + rng.uniform(0.01, 4.0, len(r))
+        cols.append((r, v.astype(np.float32).astype(np.float64)))
+    picks, gains = single.greedy(cols, n_rows, phi)
+    off = np.concatenate([[0], np.cumsum([len(c[0]) for c in cols])])
+    rows = np.concatenate([c[0] for c in cols]).astype(np.int32)
+    vals = np.concatenate([c[1] for c in cols]).astype(np.float32)
+    dev = torch.device("cuda")
+    gp, gg = laue.laue_spot_greedy(torch.tensor(off, device=dev), torch.tensor(rows, device=dev),
+                                   torch.tensor(vals, device=dev), n_cand, n_rows, phi, n_cand)
+    assert gp.cpu().tolist() == picks
+    assert np.allclose(gg.cpu().numpy(), gains, rtol=1e-9, atol=1e-9)
+    assert single.n_prototypes(gg.cpu().numpy()) == single.n_prototypes(gains)
