@@ -425,6 +425,54 @@ int laue_spot_greedy(const int64_t *lbar_off, const int32_t *lbar_row, const flo
                      int32_t n_cand, int64_t n_rows, double phi, int32_t k_max, int32_t *picks,
                      double *gains, int32_t *n_picked, void *ws, size_t ws_bytes, void *stream);
 
+/* ---- learned proposal: a small network that ranks candidates ------------ */
+
+/* 16-256-256-1 perceptron (ReLU, sigmoid output) on the 16 candidate
+ * features.  params: FP32 masters, layout W1 [256][16], b1 [256],
+ * W2 [256][256], b2 [256], w3 [256], b3 [1] (laue_mlp_n_params entries);
+ * wbf16: bfloat16 copies of W1, W2, W2^T and w3 (laue_mlp_n_bf16 entries),
+ * refreshed by laue_mlp_init / laue_mlp_adam / laue_mlp_sync_bf16.  Weights and
+ * the activations entering each product are rounded to bfloat16 (nearest
+ * even); products run on the matrix cores with FP32 accumulation.  adam_m,
+ * adam_v: FP32 moments (training only); step: Adam step count.  All device. */
+typedef struct laue_mlp {
+    int32_t n_in;
+    int32_t n_hidden;
+    float *params;
+    uint16_t *wbf16;
+    float *adam_m, *adam_v;
+    int32_t step;
+} laue_mlp;
+
+typedef struct laue_adam_params {
+    double lr, beta1, beta2, eps;
+} laue_adam_params;
+
+int64_t laue_mlp_n_params(int32_t n_in, int32_t n_hidden);
+int64_t laue_mlp_n_bf16(int32_t n_in, int32_t n_hidden);
+
+/* He-uniform weights from Philox4x32-10 (counter (i, 0, 0, 6)), zero biases,
+ * output layer scaled by 0.1; step = 0.  Adam moments are not touched. */
+int laue_mlp_init(laue_mlp *m, uint64_t seed, void *stream);
+int laue_mlp_sync_bf16(laue_mlp *m, void *stream);
+
+size_t laue_mlp_forward_workspace_size(int64_t n);
+/* prob[i] = sigmoid(network(feat[i])) for feat [n][16] FP32 (device). */
+int laue_mlp_forward(const laue_mlp *m, const float *feat, int64_t n, float *prob, void *ws,
+                     size_t ws_bytes, void *stream);
+
+size_t laue_mlp_train_workspace_size(int64_t batch);
+/* Gradient of the mean binary cross-entropy over a batch (batch % 16 == 0)
+ * into grad [n_params] (device, may be NULL) and the loss (HOST).  Synchronous. */
+int laue_mlp_backward(const laue_mlp *m, const float *feat, const float *label, int64_t batch,
+                      float *grad, double *loss, void *ws, size_t ws_bytes, void *stream);
+/* One Adam step (bias-corrected) on the masters, then the bf16 copies. */
+int laue_mlp_adam(laue_mlp *m, const float *grad, const laue_adam_params *ap, void *stream);
+/* backward + Adam. */
+int laue_mlp_train_step(laue_mlp *m, const float *feat, const float *label, int64_t batch,
+                        const laue_adam_params *ap, double *loss, void *ws, size_t ws_bytes,
+                        void *stream);
+
 #ifdef __cplusplus
 }
 #endif

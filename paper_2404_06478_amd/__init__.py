@@ -469,3 +469,94 @@ def laue_spot_greedy(lbar_off, lbar_row, lbar_val, n_cand, n_rows, phi, k_max):
                                 float(phi), int(k_max), _ptr(picks), _ptr(gains), C.byref(npk), _ptr(ws),
                                 ws.numel(), _stream()))
     return picks[:npk.value], gains[:npk.value]
+
+
+# ---------------------------------------------------------------- learned proposal
+
+class Mlp:
+    """Device storage of the 16-256-256-1 network (FP32 masters, bf16 copies, Adam moments)."""
+
+    N_IN, N_HID = 16, 256
+
+    def __init__(self, seed=0, params=None):
+        import torch
+        lib = require_native()
+        dev = _dev()
+        n = lib.laue_mlp_n_params(self.N_IN, self.N_HID)
+        nb = lib.laue_mlp_n_bf16(self.N_IN, self.N_HID)
+        self.params = torch.zeros(n, dtype=torch.float32, device=dev)
+        self.wbf16 = torch.zeros(nb, dtype=torch.int16, device=dev)
+        self.m = torch.zeros(n, dtype=torch.float32, device=dev)
+        self.v = torch.zeros(n, dtype=torch.float32, device=dev)
+        self.s = _abi.laue_mlp(self.N_IN, self.N_HID, self.params.data_ptr(), self.wbf16.data_ptr(),
+                               self.m.data_ptr(), self.v.data_ptr(), 0)
+        if params is None:
+            _check(lib.laue_mlp_init(C.byref(self.s), int(seed), _stream()))
+        else:
+            self.params.copy_(torch.as_tensor(np.asarray(params, np.float32)))
+            _check(lib.laue_mlp_sync_bf16(C.byref(self.s), _stream()))
+
+    @staticmethod
+    def pack(p):
+        """FP32 parameter vector from a dict W1, b1, W2, b2, w3, b3."""
+        return np.concatenate([np.ravel(p[k]) for k in ("W1", "b1", "W2", "b2", "w3", "b3")]).astype(np.float32)
+
+    @staticmethod
+    def unpack(v, n_in=16, n_hid=256):
+        v = np.asarray(v, dtype=np.float64)
+        o = 0
+        out = {}
+        for k, shape in (("W1", (n_hid, n_in)), ("b1", (n_hid,)), ("W2", (n_hid, n_hid)),
+                         ("b2", (n_hid,)), ("w3", (n_hid,)), ("b3", (1,))):
+            size = int(np.prod(shape))
+            out[k] = v[o:o + size].reshape(shape)
+            o += size
+        return out
+
+
+def laue_mlp_forward(mlp, feat):
+    import torch
+    lib = require_native()
+    n = int(feat.shape[0])
+    prob = torch.zeros(max(n, 1), dtype=torch.float32, device=_dev())
+    ws = _workspace(lib.laue_mlp_forward_workspace_size(n))
+    _check(lib.laue_mlp_forward(C.byref(mlp.s), _ptr(feat.contiguous()), n, _ptr(prob), _ptr(ws), ws.numel(),
+                                _stream()))
+    return prob[:n]
+
+
+def laue_mlp_backward(mlp, feat, label):
+    import torch
+    lib = require_native()
+    B = int(feat.shape[0])
+    grad = torch.zeros_like(mlp.params)
+    ws = _workspace(lib.laue_mlp_train_workspace_size(B))
+    loss = C.c_double()
+    _check(lib.laue_mlp_backward(C.byref(mlp.s), _ptr(feat.contiguous()), _ptr(label.contiguous()), B,
+                                 _ptr(grad), C.byref(loss), _ptr(ws), ws.numel(), _stream()))
+    return grad, loss.value
+
+
+def adam_params(lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+    return _abi.laue_adam_params(float(lr), float(beta1), float(beta2), float(eps))
+
+
+def laue_mlp_adam(mlp, grad, ap):
+    _check(require_native().laue_mlp_adam(C.byref(mlp.s), _ptr(grad), C.byref(ap), _stream()))
+
+
+class MlpTrainer:
+    """Holds the training workspace for a fixed batch size."""
+
+    def __init__(self, mlp, batch, ap=None):
+        lib = require_native()
+        self.mlp, self.batch = mlp, int(batch)
+        self.ap = adam_params() if ap is None else ap
+        self.ws = _workspace(lib.laue_mlp_train_workspace_size(self.batch))
+
+    def laue_mlp_train_step(self, feat, label):
+        loss = C.c_double()
+        _check(require_native().laue_mlp_train_step(C.byref(self.mlp.s), _ptr(feat), _ptr(label), self.batch,
+                                                     C.byref(self.ap), C.byref(loss), _ptr(self.ws),
+                                                     self.ws.numel(), _stream()))
+        return loss.value

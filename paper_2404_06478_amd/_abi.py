@@ -105,6 +105,15 @@ class laue_score_out(C.Structure):
                 ("lbar_row", vp), ("lbar_val", vp), ("lbar_cap", C.c_int64), ("lbar_n", C.c_int64)]
 
 
+class laue_mlp(C.Structure):
+    _fields_ = [("n_in", C.c_int32), ("n_hidden", C.c_int32), ("params", vp), ("wbf16", vp),
+                ("adam_m", vp), ("adam_v", vp), ("step", C.c_int32)]
+
+
+class laue_adam_params(C.Structure):
+    _fields_ = [("lr", C.c_double), ("beta1", C.c_double), ("beta2", C.c_double), ("eps", C.c_double)]
+
+
 P = C.POINTER
 SIGNATURES = {
     "laue_version": (C.c_int, []),
@@ -145,6 +154,17 @@ SIGNATURES = {
     "laue_spot_greedy_workspace_size": (C.c_size_t, [C.c_int32, C.c_int64]),
     "laue_spot_greedy": (C.c_int, [vp, vp, vp, C.c_int32, C.c_int64, C.c_double, C.c_int32, vp, vp,
                                    P(C.c_int32), vp, C.c_size_t, vp]),
+    "laue_mlp_n_params": (C.c_int64, [C.c_int32, C.c_int32]),
+    "laue_mlp_n_bf16": (C.c_int64, [C.c_int32, C.c_int32]),
+    "laue_mlp_init": (C.c_int, [P(laue_mlp), C.c_uint64, vp]),
+    "laue_mlp_sync_bf16": (C.c_int, [P(laue_mlp), vp]),
+    "laue_mlp_forward_workspace_size": (C.c_size_t, [C.c_int64]),
+    "laue_mlp_forward": (C.c_int, [P(laue_mlp), vp, C.c_int64, vp, vp, C.c_size_t, vp]),
+    "laue_mlp_train_workspace_size": (C.c_size_t, [C.c_int64]),
+    "laue_mlp_backward": (C.c_int, [P(laue_mlp), vp, vp, C.c_int64, vp, P(C.c_double), vp, C.c_size_t, vp]),
+    "laue_mlp_adam": (C.c_int, [P(laue_mlp), vp, P(laue_adam_params), vp]),
+    "laue_mlp_train_step": (C.c_int, [P(laue_mlp), vp, vp, C.c_int64, P(laue_adam_params), P(C.c_double), vp,
+                                      C.c_size_t, vp]),
 }
 
 
