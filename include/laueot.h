@@ -347,6 +347,10 @@ typedef struct laue_cand_params {
     int64_t n_pairs;
     uint64_t seed;
     double delta_deg;
+    /* optional explicit pairs (device [n_pairs] detected-spot indices, both
+     * NULL for the random draw); a pair whose spots are out of range or not of
+     * one rotation yields no hypothesis */
+    const int32_t *pair_a, *pair_b;
 } laue_cand_params;
 
 /* Candidate outputs (device; capacity n on entry, count written on return;
@@ -427,6 +431,56 @@ int laue_spot_greedy(const int64_t *lbar_off, const int32_t *lbar_row, const flo
 
 /* ---- learned proposal: a small network that ranks candidates ------------ */
 
+/* Cheap support of candidates (features 14 and 15).  The candidate grain,
+ * placed at the sample centre (the position hypothesis of the spot-pair
+ * candidates), predicts the reflections of the first n_support_planes planes
+ * of the list that have no lower-order parallel plane (forward model of
+ * Sec. 3.3: wavelength in band, tau > 0, strictly inside the detector) at the
+ * probe rotations t_k = (t + floor(k T / 3)) mod T, k = 1, 2, where t is the
+ * rotation of the candidate's spot_a.  A prediction is hit when a detected
+ * spot of the same (rotation, detector) block lies within radius_mm (<=).
+ * feat[16 c + 13 + k] = hits / max(predictions, 1).  FP64 geometry. */
+typedef struct laue_support_params {
+    double radius_mm;
+    int32_t n_support_planes;
+} laue_support_params;
+
+size_t laue_candidate_support_workspace_size(const laue_geometry *geom, int32_t n_planes,
+                                             int64_t n_obs, const laue_support_params *par);
+/* cand: q, spot_a and feat are read / written (device); asynchronous. */
+int laue_candidate_support(const laue_geometry *geom, const laue_planes *planes,
+                           const laue_obs_spots *obs, const laue_candidates *cand,
+                           const laue_support_params *par, void *ws, size_t ws_bytes,
+                           void *stream);
+
+/* Training labels of candidates drawn on simulated spots: label[c] = 1 when
+ * both spots of the pair come from one true grain g (spot_grain [n_obs],
+ * -1 for outliers, device) and the candidate orientation is within max_deg
+ * of truth->q[g] up to the 24 proper cubic rotations; else 0.  mis_deg
+ * (may be NULL) receives that misorientation (degrees; +inf when the spots
+ * are not from one grain).  Device outputs [cand->n]; asynchronous. */
+int laue_candidate_labels(const laue_candidates *cand, const int32_t *spot_grain, int64_t n_obs,
+                          const laue_grains *truth, double max_deg, float *label, float *mis_deg,
+                          void *stream);
+
+/* Same-grain spot pairs for training the proposal on simulated spots.  Pair k
+ * draws Philox4x32-10 counter (k, 0, 0, 7) under the key (seed low, seed
+ * high): a = x0 mod n_obs; if spot a is an outlier (spot_grain -1) or no
+ * other spot of its grain lies in its rotation (either detector), the pair is
+ * (-1, -1); else b is the (x1 mod count)-th of those spots in index order.
+ * out_a, out_b [n_pairs] (device).  Asynchronous. */
+int laue_pairs_same_grain(const laue_geometry *geom, const laue_obs_spots *obs,
+                          const int32_t *spot_grain, int64_t n_pairs, uint64_t seed,
+                          int32_t *out_a, int32_t *out_b, void *ws, size_t ws_bytes, void *stream);
+size_t laue_pairs_same_grain_workspace_size(const laue_geometry *geom);
+
+size_t laue_select_top_workspace_size(int64_t n);
+/* Indices of the k largest of score [n] (device, n < 2^31), equal scores in
+ * increasing index order (-0 equals +0), NaN below everything; written ascending to
+ * out [k] (device).  Asynchronous. */
+int laue_select_top(const float *score, int64_t n, int64_t k, int32_t *out, void *ws,
+                    size_t ws_bytes, void *stream);
+
 /* 16-256-256-1 perceptron (ReLU, sigmoid output) on the 16 candidate
  * features.  params: FP32 masters, layout W1 [256][16], b1 [256],
  * W2 [256][256], b2 [256], w3 [256], b3 [1] (laue_mlp_n_params entries);
@@ -472,6 +526,67 @@ int laue_mlp_adam(laue_mlp *m, const float *grad, const laue_adam_params *ap, vo
 int laue_mlp_train_step(laue_mlp *m, const float *feat, const float *label, int64_t batch,
                         const laue_adam_params *ap, double *loss, void *ws, size_t ws_bytes,
                         void *stream);
+
+/* ---- end-to-end indexing ------------------------------------------------- */
+
+#define LAUE_INDEX_PLAIN 0      /* every candidate is refined and scored */
+#define LAUE_INDEX_LEARNED 1    /* the network keeps the best-scored fraction */
+
+/* The multigrain solve (Sec. 6, Alg. MultiGrainLaueOT) from detected spots:
+ *   1. spot-pair candidates (laue_candidates_generate; at most max_candidates
+ *      of them, the first ones, are kept);
+ *   2. learned mode: support features (laue_candidate_support), the network
+ *      (laue_mlp_forward), the ceil(top_frac * n) best (laue_select_top);
+ *   3. single-grain refinement and scoring (laue_score_candidates, x = 0 start);
+ *   4. greedy SPOT (laue_spot_greedy, floor -c_out / (2 sigma^2), at most k_max
+ *      picks) and k* = argmax_k (Delta_k - Delta_{k+1}) (Delta beyond the picks
+ *      is 0): the first k* picks are the prototypes;
+ *   5. the harmonic-merged model spots of the prototypes, frozen (Sec. 4.2),
+ *      and the EM of laue_em from zero potentials with
+ *      T_b = max(ceil(t_b_frac |J|), |J| - |I|).
+ * Capacities bound the workspace: max_candidates, lbar_cap SPOT entries,
+ * k_max prototypes, max_model_spots; an overflow returns LAUE_ECAPACITY. */
+typedef struct laue_index_params {
+    int32_t mode;
+    laue_cand_params cand;          /* pair_a / pair_b must be NULL */
+    int64_t max_candidates;
+    const laue_mlp *mlp;            /* learned mode */
+    laue_support_params support;    /* learned mode */
+    double top_frac;                /* learned mode */
+    laue_score_params score;
+    int64_t lbar_cap;
+    int32_t k_max;
+    int64_t max_model_spots;
+    double t_b_frac;
+    laue_em_params em;              /* em.ot.t_b is set from t_b_frac */
+} laue_index_params;
+
+/* Per-stage wall-clock times (ms, host clock around each synchronous stage)
+ * and sizes. */
+typedef struct laue_index_stats {
+    int64_t n_candidates_found, n_candidates, n_scored, lbar_entries;
+    int32_t n_picked, n_prototypes;
+    int64_t n_model_spots;
+    double ms_candidates, ms_proposal, ms_score, ms_greedy, ms_em, ms_total;
+    laue_em_stats em;
+} laue_index_stats;
+
+/* Output grains (device, capacity >= k_max; n_grains = k* on return) and the
+ * per-detected-spot assignments of the final EM (all four arrays or none). */
+typedef struct laue_index_out {
+    int32_t capacity;
+    int32_t n_grains;
+    double *q, *x;
+    laue_assignments assign;
+} laue_index_out;
+
+size_t laue_index_workspace_size(const laue_geometry *geom, int32_t n_planes, int64_t n_obs,
+                                 const laue_index_params *par);
+/* Synchronous.  Returns LAUE_ENOCONV (a warning) when an EM Sinkhorn stopped
+ * at its cap. */
+int laue_index(const laue_geometry *geom, const laue_planes *planes, const laue_obs_spots *obs,
+               const laue_index_params *par, laue_index_out *out, laue_index_stats *stats,
+               void *ws, size_t ws_bytes, void *stream);
 
 #ifdef __cplusplus
 }

@@ -94,13 +94,24 @@ def draw_pairs(geom, obs_off, n_pairs, seed):
     return np.where(bad, -1, a), np.where(bad, -1, b), t
 
 
-def generate(planes, geom, p12, obs_off, n_pairs, seed, delta_deg=1.5, l_side=200.0):
-    """All hypotheses of the first n_pairs pairs.  Returns dict of arrays."""
+def generate(planes, geom, p12, obs_off, n_pairs, seed, delta_deg=1.5, l_side=200.0, pairs=None):
+    """All hypotheses of the first n_pairs pairs (or of the explicit pairs
+    (a, b); a pair whose spots are out of range or of two rotations yields
+    nothing).  Returns dict of arrays."""
     block = np.repeat(np.arange(geom.n_blocks), np.diff(obs_off))
     n, sth, plab = spot_normals(geom, p12, block)
     w, d, nsq = planes["w"], planes["d"], planes["nsq"]
     reps = family_representatives(planes)
-    a_idx, b_idx, _ = draw_pairs(geom, obs_off, n_pairs, seed)
+    if pairs is None:
+        a_idx, b_idx, _ = draw_pairs(geom, obs_off, n_pairs, seed)
+    else:
+        a_idx, b_idx = (np.asarray(v, dtype=np.int64).copy() for v in pairs)
+        n_pairs = len(a_idx)
+        n_obs = len(block)
+        valid = (a_idx >= 0) & (b_idx >= 0) & (a_idx < n_obs) & (b_idx < n_obs)
+        ta = np.where(valid, block[np.clip(a_idx, 0, max(n_obs - 1, 0))] // geom.n_det, -1)
+        tb = np.where(valid, block[np.clip(b_idx, 0, max(n_obs - 1, 0))] // geom.n_det, -2)
+        a_idx[ta != tb] = -1
     delta = np.radians(delta_deg)
     ang_w = np.arccos(np.clip(w @ w.T, -1.0, 1.0))
     out = {k: [] for k in ("pair", "ma", "mb", "q", "feat", "a", "b")}

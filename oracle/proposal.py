@@ -27,6 +27,11 @@ cubic rotations; else 0.
 
 Top-fraction selection: the k = ceil(frac * n) highest scores, equal scores
 taken in increasing index order; the chosen indices are returned ascending.
+
+Same-grain training pairs: pair k draws Philox4x32-10 counter (k, 0, 0, 7);
+a = x0 mod n_obs; when spot a is an outlier or alone in its rotation among
+its grain's spots the pair is (-1, -1), else b is the (x1 mod count)-th other
+spot of that grain and rotation in index order.
 """
 from __future__ import annotations
 
@@ -34,7 +39,9 @@ import math
 
 import numpy as np
 
-from . import crystal, metrics
+from . import crystal, metrics, philox
+
+STREAM_SAME_PAIR = 7
 
 E = np.array([1.0, 0.0, 0.0])
 
@@ -121,3 +128,28 @@ def select_top(score, frac):
     k = min(n, int(math.ceil(frac * n)))
     order = sorted(range(n), key=lambda i: (-score[i], i))
     return np.sort(np.array(order[:k], dtype=np.int64))
+
+
+def same_grain_pairs(offsets, spot_grain, n_det, n_pairs, seed):
+    offsets = np.asarray(offsets)
+    grain = np.asarray(spot_grain)
+    n_obs = int(offsets[-1])
+    k = np.arange(n_pairs)
+    x0, x1, _, _ = philox.philox4x32_10(k, 0, 0, STREAM_SAME_PAIR, *philox.seed_key(seed))
+    a_out = -np.ones(n_pairs, dtype=np.int64)
+    b_out = -np.ones(n_pairs, dtype=np.int64)
+    if n_obs == 0:
+        return a_out, b_out
+    for j in range(n_pairs):
+        a = int(x0[j] % np.uint64(n_obs))
+        if grain[a] < 0:
+            continue
+        blk = int(np.searchsorted(offsets, a, side="right") - 1)
+        t = blk // n_det
+        lo, hi = offsets[t * n_det], offsets[(t + 1) * n_det]
+        mates = [i for i in range(lo, hi) if i != a and grain[i] == grain[a]]
+        if not mates:
+            continue
+        a_out[j] = a
+        b_out[j] = mates[int(x1[j] % np.uint64(len(mates)))]
+    return a_out, b_out

@@ -382,13 +382,18 @@ def laue_em(geom, planes, obs, model, par, grains, f=None, g=None, f0=0.0, g0=0.
 # ---------------------------------------------------------------- prototype scoring
 
 def laue_candidates_generate(geom, planes, obs, n_pairs, seed, delta_deg=1.5, capacity=None,
-                             with_ids=True, with_feat=True):
-    """Spot-pair candidates.  Returns a dict of device tensors (q [n,4] FP64, ...)."""
+                             with_ids=True, with_feat=True, pairs=None):
+    """Spot-pair candidates.  Returns a dict of device tensors (q [n,4] FP64, ...).
+    pairs: optional (a, b) int32 device tensors of explicit pairs (n_pairs = len)."""
     import torch
     lib = require_native()
     dev = _dev()
+    if pairs is not None:
+        n_pairs = int(pairs[0].numel())
     ws = _workspace(lib.laue_candidates_workspace_size(C.byref(geom), planes.n, int(n_pairs)))
-    par = _abi.laue_cand_params(int(n_pairs), int(seed), float(delta_deg))
+    par = _abi.laue_cand_params(int(n_pairs), int(seed), float(delta_deg),
+                                None if pairs is None else pairs[0].data_ptr(),
+                                None if pairs is None else pairs[1].data_ptr())
     nfound = C.c_int64()
     o = obs.struct()
     probe = _abi.laue_candidates()
@@ -560,3 +565,134 @@ class MlpTrainer:
                                                      C.byref(self.ap), C.byref(loss), _ptr(self.ws),
                                                      self.ws.numel(), _stream()))
         return loss.value
+
+
+def _cand_struct(cand):
+    c = _abi.laue_candidates()
+    c.n = int(cand["q"].shape[0])
+    c.q = cand["q"].data_ptr()
+    for k in ("pair", "ma", "mb", "spot_a", "spot_b"):
+        setattr(c, k, cand[k].data_ptr() if k in cand else None)
+    c.feat = cand["feat"].data_ptr() if "feat" in cand else None
+    return c
+
+
+def support_params(radius_mm, n_support_planes):
+    return _abi.laue_support_params(float(radius_mm), int(n_support_planes))
+
+
+def laue_candidate_support(geom, planes, obs, cand, radius_mm, n_support_planes):
+    """Fills cand['feat'][:, 14:16] (device) with the cheap-support fractions."""
+    lib = require_native()
+    par = support_params(radius_mm, n_support_planes)
+    ws = _workspace(lib.laue_candidate_support_workspace_size(C.byref(geom), planes.n, obs.n, C.byref(par)))
+    o, c = obs.struct(), _cand_struct(cand)
+    _check(lib.laue_candidate_support(C.byref(geom), C.byref(planes.struct), C.byref(o), C.byref(c), C.byref(par),
+                                      _ptr(ws), ws.numel(), _stream()))
+
+
+def laue_candidate_labels(cand, spot_grain, truth, max_deg=2.0):
+    """(label, misorientation deg) device FP32 tensors of the candidates."""
+    import torch
+    n = int(cand["q"].shape[0])
+    lab = torch.zeros(max(n, 1), dtype=torch.float32, device=_dev())
+    mis = torch.zeros(max(n, 1), dtype=torch.float32, device=_dev())
+    c = _cand_struct(cand)
+    _check(require_native().laue_candidate_labels(C.byref(c), _ptr(spot_grain), int(spot_grain.numel()),
+                                                  C.byref(truth.struct), float(max_deg), _ptr(lab), _ptr(mis),
+                                                  _stream()))
+    return lab[:n], mis[:n]
+
+
+def laue_select_top(score, k):
+    """Ascending indices (int32 device) of the k largest scores, ties by index."""
+    import torch
+    lib = require_native()
+    n = int(score.numel())
+    out = torch.zeros(max(int(k), 1), dtype=torch.int32, device=_dev())
+    ws = _workspace(lib.laue_select_top_workspace_size(n))
+    _check(lib.laue_select_top(_ptr(score.contiguous()), n, int(k), _ptr(out), _ptr(ws), ws.numel(), _stream()))
+    return out[:int(k)]
+
+
+def laue_pairs_same_grain(geom, obs, spot_grain, n_pairs, seed):
+    """(a, b) int32 device tensors of same-grain pairs (-1 where none)."""
+    import torch
+    lib = require_native()
+    a = torch.zeros(max(int(n_pairs), 1), dtype=torch.int32, device=_dev())
+    b = torch.zeros_like(a)
+    ws = _workspace(lib.laue_pairs_same_grain_workspace_size(C.byref(geom)))
+    o = obs.struct()
+    _check(lib.laue_pairs_same_grain(C.byref(geom), C.byref(o), _ptr(spot_grain), int(n_pairs), int(seed),
+                                     _ptr(a), _ptr(b), _ptr(ws), ws.numel(), _stream()))
+    return a[:int(n_pairs)], b[:int(n_pairs)]
+
+
+# ---------------------------------------------------------------- end-to-end indexing
+
+def index_params(preset_like, mode="plain", n_pairs=None, seed=0, delta_deg=1.5, max_candidates=None, mlp=None,
+                 support_radius=1.0, n_support_planes=None, top_frac=0.05, score=None, lbar_cap=None, k_max=None,
+                 max_model_spots=None, t_b_frac=0.4, em=None, n_obs=0, n_planes=0):
+    """laue_index_params from a workload description (sigma_mm, distance, grains,
+    rotations, schedule) with capacities sized for it."""
+    p = _abi.laue_index_params()
+    pl = preset_like
+    p.mode = _abi.LAUE_INDEX_LEARNED if mode == "learned" else _abi.LAUE_INDEX_PLAIN
+    n_pairs = int(n_pairs if n_pairs is not None else 8192)
+    p.cand = _abi.laue_cand_params(n_pairs, int(seed), float(delta_deg), None, None)
+    p.max_candidates = int(max_candidates if max_candidates is not None else 64 * n_pairs)
+    if mlp is not None:
+        p.mlp = C.pointer(mlp.s)
+        p._mlp_ref = mlp
+    p.support = support_params(support_radius, n_planes if n_support_planes is None else n_support_planes)
+    p.top_frac = float(top_frac)
+    c_out = 2.0 * pl.distance ** 2 * (1.0 - math.cos(3.0 * pl.sigma_mm / pl.distance))
+    p.score = score if score is not None else score_params(pl.sigma_mm, pl.distance, c_out)
+    p.lbar_cap = int(lbar_cap if lbar_cap is not None else max(1 << 16, 64 * n_obs))
+    p.k_max = int(k_max if k_max is not None else max(8, 2 * pl.n_grains))
+    p.max_model_spots = int(max_model_spots if max_model_spots is not None
+                            else 64 * pl.n_rot * p.k_max)
+    p.t_b_frac = float(t_b_frac)
+    if em is None:
+        ot = ot_params(1.0, pl.distance, c_out, 0.0)
+        em = em_params(ot, pl.eps_start, pl.eps_end, pl.n_stages, pl.iters_per_stage)
+    p.em = em
+    return p
+
+
+def laue_index(geom, planes, obs, par, assign=True):
+    """End-to-end indexing.  Returns (Grains of the k* prototypes after EM, stats dict, assignments)."""
+    import torch
+    lib = require_native()
+    dev = _dev()
+    if par.support.n_support_planes <= 0:
+        par.support.n_support_planes = planes.n
+    need = lib.laue_index_workspace_size(C.byref(geom), planes.n, obs.n, C.byref(par))
+    if need == 0:
+        raise LaueError(_abi.LAUE_EINVAL, "invalid index parameters")
+    ws = _workspace(need)
+    K = int(par.k_max)
+    q = torch.zeros((K, 4), dtype=torch.float64, device=dev)
+    x = torch.zeros((K, 3), dtype=torch.float64, device=dev)
+    out = _abi.laue_index_out()
+    out.capacity, out.q, out.x = K, q.data_ptr(), x.data_ptr()
+    asg_t = None
+    if assign:
+        n = max(obs.n, 1)
+        asg_t = {"j_star": torch.zeros(n, dtype=torch.int32, device=dev),
+                 "grain": torch.zeros(n, dtype=torch.int32, device=dev),
+                 "q_star": torch.zeros(n, dtype=torch.float32, device=dev),
+                 "q_out": torch.zeros(n, dtype=torch.float32, device=dev)}
+        out.assign = laue_assignments(*(asg_t[k].data_ptr() for k in ("j_star", "grain", "q_star", "q_out")))
+    st = _abi.laue_index_stats()
+    o = obs.struct()
+    rc = _check(lib.laue_index(C.byref(geom), C.byref(planes.struct), C.byref(o), C.byref(par), C.byref(out),
+                               C.byref(st), _ptr(ws), ws.numel(), _stream()))
+    k = out.n_grains
+    stats = {name: getattr(st, name) for name, _ in _abi.laue_index_stats._fields_ if name != "em"}
+    stats["em"] = {name: getattr(st.em, name) for name, _ in _abi.laue_em_stats._fields_}
+    stats["code"] = rc
+    g = Grains.__new__(Grains)
+    g.q, g.x, g.n = q[:max(k, 1)], x[:max(k, 1)], k
+    asg = None if asg_t is None else {kk: v[:obs.n] for kk, v in asg_t.items()}
+    return g, stats, asg

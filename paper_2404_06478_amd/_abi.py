@@ -85,7 +85,8 @@ class laue_assignments(C.Structure):
 
 
 class laue_cand_params(C.Structure):
-    _fields_ = [("n_pairs", C.c_int64), ("seed", C.c_uint64), ("delta_deg", C.c_double)]
+    _fields_ = [("n_pairs", C.c_int64), ("seed", C.c_uint64), ("delta_deg", C.c_double), ("pair_a", vp),
+                ("pair_b", vp)]
 
 
 class laue_candidates(C.Structure):
@@ -110,8 +111,36 @@ class laue_mlp(C.Structure):
                 ("adam_m", vp), ("adam_v", vp), ("step", C.c_int32)]
 
 
+class laue_support_params(C.Structure):
+    _fields_ = [("radius_mm", C.c_double), ("n_support_planes", C.c_int32)]
+
+
 class laue_adam_params(C.Structure):
     _fields_ = [("lr", C.c_double), ("beta1", C.c_double), ("beta2", C.c_double), ("eps", C.c_double)]
+
+
+LAUE_INDEX_PLAIN = 0
+LAUE_INDEX_LEARNED = 1
+
+
+class laue_index_params(C.Structure):
+    _fields_ = [("mode", C.c_int32), ("cand", laue_cand_params), ("max_candidates", C.c_int64),
+                ("mlp", C.POINTER(laue_mlp)), ("support", laue_support_params), ("top_frac", C.c_double),
+                ("score", laue_score_params), ("lbar_cap", C.c_int64), ("k_max", C.c_int32),
+                ("max_model_spots", C.c_int64), ("t_b_frac", C.c_double), ("em", laue_em_params)]
+
+
+class laue_index_stats(C.Structure):
+    _fields_ = [("n_candidates_found", C.c_int64), ("n_candidates", C.c_int64), ("n_scored", C.c_int64),
+                ("lbar_entries", C.c_int64), ("n_picked", C.c_int32), ("n_prototypes", C.c_int32),
+                ("n_model_spots", C.c_int64), ("ms_candidates", C.c_double), ("ms_proposal", C.c_double),
+                ("ms_score", C.c_double), ("ms_greedy", C.c_double), ("ms_em", C.c_double),
+                ("ms_total", C.c_double), ("em", laue_em_stats)]
+
+
+class laue_index_out(C.Structure):
+    _fields_ = [("capacity", C.c_int32), ("n_grains", C.c_int32), ("q", vp), ("x", vp),
+                ("assign", laue_assignments)]
 
 
 P = C.POINTER
@@ -165,6 +194,20 @@ SIGNATURES = {
     "laue_mlp_adam": (C.c_int, [P(laue_mlp), vp, P(laue_adam_params), vp]),
     "laue_mlp_train_step": (C.c_int, [P(laue_mlp), vp, vp, C.c_int64, P(laue_adam_params), P(C.c_double), vp,
                                       C.c_size_t, vp]),
+    "laue_candidate_support_workspace_size": (C.c_size_t, [P(laue_geometry), C.c_int32, C.c_int64,
+                                                           P(laue_support_params)]),
+    "laue_candidate_support": (C.c_int, [P(laue_geometry), P(laue_planes), P(laue_obs_spots), P(laue_candidates),
+                                         P(laue_support_params), vp, C.c_size_t, vp]),
+    "laue_candidate_labels": (C.c_int, [P(laue_candidates), vp, C.c_int64, P(laue_grains), C.c_double, vp, vp,
+                                        vp]),
+    "laue_pairs_same_grain": (C.c_int, [P(laue_geometry), P(laue_obs_spots), vp, C.c_int64, C.c_uint64, vp, vp,
+                                        vp, C.c_size_t, vp]),
+    "laue_pairs_same_grain_workspace_size": (C.c_size_t, [P(laue_geometry)]),
+    "laue_index_workspace_size": (C.c_size_t, [P(laue_geometry), C.c_int32, C.c_int64, P(laue_index_params)]),
+    "laue_index": (C.c_int, [P(laue_geometry), P(laue_planes), P(laue_obs_spots), P(laue_index_params),
+                             P(laue_index_out), P(laue_index_stats), vp, C.c_size_t, vp]),
+    "laue_select_top_workspace_size": (C.c_size_t, [C.c_int64]),
+    "laue_select_top": (C.c_int, [vp, C.c_int64, C.c_int64, vp, vp, C.c_size_t, vp]),
 }
 
 

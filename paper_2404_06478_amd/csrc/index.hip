@@ -131,18 +131,42 @@ __global__ void k_pairs(int pass, const laue_geometry G, const float *__restrict
                         double delta, double l_side, int *__restrict__ counts,
                         const int64_t *__restrict__ offs, int64_t cap, double *__restrict__ oq,
                         int *__restrict__ opair, int *__restrict__ oma, int *__restrict__ omb,
-                        int *__restrict__ oa, int *__restrict__ ob, float *__restrict__ ofeat) {
+                        int *__restrict__ oa, int *__restrict__ ob, float *__restrict__ ofeat,
+                        const int *__restrict__ pair_a, const int *__restrict__ pair_b) {
     const int64_t k = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (k >= n_pairs) return;
-    uint32_t c[4] = {static_cast<uint32_t>(k), 0u, 0u, 5u};
-    philox(c, k0, k1);
-    const int t = static_cast<int>(c[0] % static_cast<uint32_t>(G.n_rot));
-    const int64_t lo = ooff[t * G.n_det], hi = ooff[(t + 1) * G.n_det];
-    const uint32_t cnt = static_cast<uint32_t>(hi - lo);
+    const int nbk = G.n_rot * G.n_det;
+    int t = 0;
+    int64_t a = -1, b = -1;
+    if (pair_a) {
+        // explicit pair: both spots must lie in one rotation
+        const int64_t pa = pair_a[k], pb = pair_b[k];
+        if (pa >= 0 && pb >= 0 && pa < ooff[nbk] && pb < ooff[nbk]) {
+            int lo = 0, hi = nbk;
+            while (hi - lo > 1) {
+                const int mid = (lo + hi) / 2;
+                if (ooff[mid] <= pa) lo = mid; else hi = mid;
+            }
+            t = lo / G.n_det;
+            if (pb >= ooff[t * G.n_det] && pb < ooff[(t + 1) * G.n_det]) {
+                a = pa;
+                b = pb;
+            }
+        }
+    } else {
+        uint32_t c[4] = {static_cast<uint32_t>(k), 0u, 0u, 5u};
+        philox(c, k0, k1);
+        t = static_cast<int>(c[0] % static_cast<uint32_t>(G.n_rot));
+        const int64_t lo = ooff[t * G.n_det], hi = ooff[(t + 1) * G.n_det];
+        const uint32_t cnt = static_cast<uint32_t>(hi - lo);
+        if (cnt > 0) {
+            a = lo + c[1] % cnt;
+            b = lo + c[2] % cnt;
+        }
+    }
     int found = 0;
     int64_t base = pass ? offs[k] : 0;
-    if (cnt > 0) {
-        const int64_t a = lo + c[1] % cnt, b = lo + c[2] % cnt;
+    if (a >= 0) {
         if (a != b) {
             int ba = t * G.n_det, bb = t * G.n_det;
             while (ba + 1 < (t + 1) * G.n_det && ooff[ba + 1] <= a) ++ba;
@@ -569,6 +593,8 @@ extern "C" int laue_candidates_generate(const laue_geometry *geom, const laue_pl
     if ((rc = validate_obs_host(obs, nb))) return rc;
     LAUE_REQUIRE(par && out && n_found && out->q, LAUE_EINVAL, "NULL argument");
     LAUE_REQUIRE(par->n_pairs >= 0 && par->n_pairs < (int64_t(1) << 31), LAUE_EINVAL, "bad n_pairs");
+    LAUE_REQUIRE((par->pair_a == nullptr) == (par->pair_b == nullptr), LAUE_EINVAL,
+                 "pair_a and pair_b must both be given or both be NULL");
     LAUE_REQUIRE(std::isfinite(par->delta_deg) && par->delta_deg > 0 && par->delta_deg < 90,
                  LAUE_EINVAL, "bad angle tolerance");
     hipStream_t s = static_cast<hipStream_t>(stream);
@@ -638,7 +664,8 @@ extern "C" int laue_candidates_generate(const laue_geometry *geom, const laue_pl
         const unsigned nbk = static_cast<unsigned>((P + 127) / 128);
         k_pairs<<<nbk, 128, 0, s>>>(0, *geom, obs->p1, obs->p2, w.ooff, planes->w, planes->d, w.tab,
                                      w.angw, w.nrat, P, k0, k1, delta, l_side, w.counts, nullptr, 0,
-                                     nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr);
+                                     nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, par->pair_a,
+                                     par->pair_b);
         LAUE_CHECK_HIP(hipGetLastError());
         if ((rc = launch_scan(w.counts, w.offs, P, s))) return rc;
         LAUE_CHECK_HIP(hipMemcpyAsync(&total, w.offs + P, sizeof(int64_t), hipMemcpyDeviceToHost, s));
@@ -650,7 +677,7 @@ extern "C" int laue_candidates_generate(const laue_geometry *geom, const laue_pl
         k_pairs<<<static_cast<unsigned>((P + 127) / 128), 128, 0, s>>>(
             1, *geom, obs->p1, obs->p2, w.ooff, planes->w, planes->d, w.tab, w.angw, w.nrat, P, k0, k1,
             delta, l_side, nullptr, w.offs, cap, out->q, out->pair, out->ma, out->mb, out->spot_a,
-            out->spot_b, out->feat);
+            out->spot_b, out->feat, par->pair_a, par->pair_b);
         LAUE_CHECK_HIP(hipGetLastError());
     }
     out->n = std::min(total, cap);

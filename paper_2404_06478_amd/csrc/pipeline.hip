@@ -1,0 +1,323 @@
+// End-to-end indexing (the multigrain solve of Sec. 6 and Alg. MultiGrainLaueOT
+// with spot-pair candidates in place of the orientation grid):
+//   candidates -> [learned: support features, network, top fraction] ->
+//   single-grain refinement and scoring -> greedy SPOT -> k* prototypes ->
+//   model spots of the prototypes (frozen) -> EM with annealed entropic OT.
+// Every stage is one of the library's entry points; this file only carves the
+// caller's workspace and moves indices between them.  The stages are
+// synchronous, and their wall-clock times (host clock around each stage,
+// stream synchronised) are reported.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <vector>
+
+#include "common.h"
+
+namespace laue {
+namespace {
+
+struct IndexWs {
+    // candidates
+    double *cq;
+    int *pair, *ma, *mb, *sa, *sb;
+    float *feat, *prob;
+    int *sel;
+    // scored subset (refined in place)
+    double *gq, *gx;
+    int *n_model, *n_unm;
+    uint8_t *keep;
+    int64_t *loff;
+    int *lrow;
+    float *lval;
+    int *picks;
+    double *gains;
+    // model spots and potentials of the EM
+    int *mplane, *mgrain, *mblock;
+    float *s1, *s2, *vn, *v1, *v2, *lam;
+    uint8_t *flags;
+    float *f, *g;
+    void *scratch;
+    size_t scratch_bytes;
+};
+
+int64_t n_scored_max(const laue_index_params *p) {
+    if (p->mode == LAUE_INDEX_LEARNED)
+        return std::min<int64_t>(p->max_candidates,
+                                 static_cast<int64_t>(std::ceil(p->top_frac * static_cast<double>(p->max_candidates))));
+    return p->max_candidates;
+}
+
+size_t scratch_size(const laue_geometry *g, int n_planes, int64_t n_obs, const laue_index_params *p) {
+    size_t s = laue_candidates_workspace_size(g, n_planes, p->cand.n_pairs);
+    if (p->mode == LAUE_INDEX_LEARNED) {
+        s = std::max(s, laue_candidate_support_workspace_size(g, n_planes, n_obs, &p->support));
+        s = std::max(s, laue_mlp_forward_workspace_size(p->max_candidates));
+        s = std::max(s, laue_select_top_workspace_size(p->max_candidates));
+    }
+    s = std::max(s, laue_score_workspace_size(g, &p->score));
+    s = std::max(s, laue_spot_greedy_workspace_size(static_cast<int32_t>(n_scored_max(p)), n_obs));
+    s = std::max(s, laue_forward_workspace_size(g, n_planes, p->k_max));
+    s = std::max(s, laue_sinkhorn_workspace_size(g, n_obs, p->max_model_spots, p->k_max));
+    return s;
+}
+
+size_t carve_index(Carver &cv, IndexWs &w, const laue_geometry *g, int n_planes, int64_t n_obs,
+                   const laue_index_params *p) {
+    const int64_t C = std::max<int64_t>(p->max_candidates, 1), S = std::max<int64_t>(n_scored_max(p), 1);
+    const int64_t J = std::max<int64_t>(p->max_model_spots, 1), K = std::max(p->k_max, 1);
+    const bool learned = p->mode == LAUE_INDEX_LEARNED;
+    w.cq = cv.take<double>(4 * C);
+    w.pair = cv.take<int>(C);
+    w.ma = cv.take<int>(C);
+    w.mb = cv.take<int>(C);
+    w.sa = cv.take<int>(C);
+    w.sb = cv.take<int>(C);
+    w.feat = learned ? cv.take<float>(16 * C) : nullptr;
+    w.prob = learned ? cv.take<float>(C) : nullptr;
+    w.sel = learned ? cv.take<int>(S) : nullptr;
+    w.gq = cv.take<double>(4 * S);
+    w.gx = cv.take<double>(3 * S);
+    w.n_model = cv.take<int>(S);
+    w.n_unm = cv.take<int>(S);
+    w.keep = cv.take<uint8_t>(S);
+    w.loff = cv.take<int64_t>(S + 1);
+    w.lrow = cv.take<int>(std::max<int64_t>(p->lbar_cap, 1));
+    w.lval = cv.take<float>(std::max<int64_t>(p->lbar_cap, 1));
+    w.picks = cv.take<int>(K);
+    w.gains = cv.take<double>(K);
+    w.mplane = cv.take<int>(J);
+    w.mgrain = cv.take<int>(J);
+    w.mblock = cv.take<int>(J);
+    w.s1 = cv.take<float>(J);
+    w.s2 = cv.take<float>(J);
+    w.vn = cv.take<float>(J);
+    w.v1 = cv.take<float>(J);
+    w.v2 = cv.take<float>(J);
+    w.lam = cv.take<float>(J);
+    w.flags = cv.take<uint8_t>(J);
+    w.f = cv.take<float>(std::max<int64_t>(n_obs, 1));
+    w.g = cv.take<float>(J);
+    w.scratch_bytes = scratch_size(g, n_planes, n_obs, p);
+    w.scratch = cv.take<char>(w.scratch_bytes);
+    return cv.size();
+}
+
+// scored grains: q from the candidates (all, or the selected ones), x = 0
+__global__ void k_seed_grains(const double *__restrict__ cq, const int *__restrict__ sel, int64_t n,
+                              double *__restrict__ gq, double *__restrict__ gx) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int64_t c = sel ? sel[i] : i;
+    for (int k = 0; k < 4; ++k) gq[4 * i + k] = cq[4 * c + k];
+    for (int k = 0; k < 3; ++k) gx[3 * i + k] = 0.0;
+}
+
+__global__ void k_gather_protos(const double *__restrict__ gq, const double *__restrict__ gx,
+                                const int *__restrict__ picks, int k, double *__restrict__ oq,
+                                double *__restrict__ ox) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= k) return;
+    const int c = picks[i];
+    for (int j = 0; j < 4; ++j) oq[4 * i + j] = gq[4 * c + j];
+    for (int j = 0; j < 3; ++j) ox[3 * i + j] = gx[3 * c + j];
+}
+
+__global__ void k_zero_f(float *p, int64_t n) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0.0f;
+}
+
+int validate_index_params(const laue_index_params *p) {
+    LAUE_REQUIRE(p, LAUE_EINVAL, "NULL index parameters");
+    LAUE_REQUIRE(p->mode == LAUE_INDEX_PLAIN || p->mode == LAUE_INDEX_LEARNED, LAUE_EINVAL, "bad index mode");
+    LAUE_REQUIRE(p->cand.pair_a == nullptr && p->cand.pair_b == nullptr, LAUE_EINVAL,
+                 "indexing draws its own pairs");
+    LAUE_REQUIRE(p->max_candidates >= 1 && p->max_candidates < (int64_t(1) << 31), LAUE_EINVAL,
+                 "bad candidate capacity");
+    LAUE_REQUIRE(p->k_max >= 1 && p->max_model_spots >= 1 && p->lbar_cap >= 1, LAUE_EINVAL, "bad capacities");
+    LAUE_REQUIRE(std::isfinite(p->t_b_frac) && p->t_b_frac >= 0 && p->t_b_frac <= 1, LAUE_EINVAL, "bad t_b_frac");
+    if (p->mode == LAUE_INDEX_LEARNED) {
+        LAUE_REQUIRE(p->mlp != nullptr, LAUE_EINVAL, "learned mode needs a network");
+        LAUE_REQUIRE(std::isfinite(p->top_frac) && p->top_frac > 0 && p->top_frac <= 1, LAUE_EINVAL,
+                     "bad top fraction");
+    }
+    return LAUE_OK;
+}
+
+double ms_since(std::chrono::steady_clock::time_point t0) {
+    return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+}
+
+}  // namespace
+}  // namespace laue
+
+using namespace laue;
+
+extern "C" size_t laue_index_workspace_size(const laue_geometry *geom, int32_t n_planes, int64_t n_obs,
+                                            const laue_index_params *par) {
+    if (!geom || validate_geometry(geom) != LAUE_OK || n_planes < 0 || n_obs < 0 || validate_index_params(par))
+        return 0;
+    Carver cv(nullptr);
+    IndexWs w;
+    return carve_index(cv, w, geom, n_planes, n_obs, par);
+}
+
+extern "C" int laue_index(const laue_geometry *geom, const laue_planes *planes, const laue_obs_spots *obs,
+                          const laue_index_params *par, laue_index_out *out, laue_index_stats *stats, void *ws,
+                          size_t ws_bytes, void *stream) {
+    clear_error();
+    int rc;
+    if ((rc = validate_geometry(geom)) || (rc = validate_planes(planes)) || (rc = validate_index_params(par)))
+        return rc;
+    LAUE_REQUIRE(obs && obs->block_off && obs->n >= 0, LAUE_EINVAL, "detected spots are NULL");
+    LAUE_REQUIRE(out && out->q && out->x && out->capacity >= par->k_max, LAUE_EINVAL,
+                 "output grains need capacity >= k_max");
+    const laue_assignments &as = out->assign;
+    const bool with_assign = as.j_star && as.grain && as.q_star && as.q_out;
+    LAUE_REQUIRE(with_assign || (!as.j_star && !as.grain && !as.q_star && !as.q_out), LAUE_EINVAL,
+                 "assignment arrays must be all given or all NULL");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    Carver cv(ws);
+    IndexWs w;
+    const size_t need = carve_index(cv, w, geom, planes->n, obs->n, par);
+    if ((rc = check_ws(ws, ws_bytes, need))) return rc;
+    laue_index_stats st{};
+    const auto t_all = std::chrono::steady_clock::now();
+    const int nb = geom->n_rot * geom->n_det;
+    out->n_grains = 0;
+
+    // 1. spot-pair candidates
+    auto t0 = std::chrono::steady_clock::now();
+    laue_candidates cand{};
+    cand.n = par->max_candidates;
+    cand.q = w.cq;
+    cand.pair = w.pair;
+    cand.ma = w.ma;
+    cand.mb = w.mb;
+    cand.spot_a = w.sa;
+    cand.spot_b = w.sb;
+    cand.feat = w.feat;
+    int64_t n_found = 0;
+    if ((rc = laue_candidates_generate(geom, planes, obs, &par->cand, &cand, &n_found, w.scratch, w.scratch_bytes,
+                                       stream)))
+        return rc;
+    st.n_candidates = cand.n;
+    st.n_candidates_found = n_found;
+    st.ms_candidates = ms_since(t0);
+
+    // 2. learned proposal: support features, network, top fraction
+    int64_t n_sc = cand.n;
+    const int *sel = nullptr;
+    t0 = std::chrono::steady_clock::now();
+    if (par->mode == LAUE_INDEX_LEARNED && cand.n > 0) {
+        if ((rc = laue_candidate_support(geom, planes, obs, &cand, &par->support, w.scratch, w.scratch_bytes, stream)))
+            return rc;
+        if ((rc = laue_mlp_forward(par->mlp, w.feat, cand.n, w.prob, w.scratch, w.scratch_bytes, stream))) return rc;
+        n_sc = std::min<int64_t>(cand.n, static_cast<int64_t>(std::ceil(par->top_frac * static_cast<double>(cand.n))));
+        if ((rc = laue_select_top(w.prob, cand.n, n_sc, w.sel, w.scratch, w.scratch_bytes, stream))) return rc;
+        sel = w.sel;
+        LAUE_CHECK_HIP(hipStreamSynchronize(s));
+    }
+    st.ms_proposal = ms_since(t0);
+    st.n_scored = n_sc;
+
+    // 3. single-grain refinement and scoring of the chosen candidates
+    t0 = std::chrono::steady_clock::now();
+    if (n_sc > 0) {
+        k_seed_grains<<<static_cast<unsigned>((n_sc + 255) / 256), 256, 0, s>>>(w.cq, sel, n_sc, w.gq, w.gx);
+        LAUE_CHECK_HIP(hipGetLastError());
+    }
+    laue_grains scored{static_cast<int32_t>(n_sc), w.gq, w.gx};
+    laue_score_out so{};
+    so.n_model = w.n_model;
+    so.n_unmatched = w.n_unm;
+    so.keep = w.keep;
+    so.lbar_off = w.loff;
+    so.lbar_row = w.lrow;
+    so.lbar_val = w.lval;
+    so.lbar_cap = par->lbar_cap;
+    if (n_sc > 0) {
+        if ((rc = laue_score_candidates(geom, planes, obs, &scored, &par->score, &so, w.scratch, w.scratch_bytes,
+                                        stream)))
+            return rc;
+    }
+    st.lbar_entries = so.lbar_n;
+    st.ms_score = ms_since(t0);
+
+    // 4. greedy SPOT and the number of prototypes k* = argmax_k (D_k - D_{k+1})
+    t0 = std::chrono::steady_clock::now();
+    int32_t n_picked = 0;
+    if (n_sc > 0) {
+        const double phi = -par->score.c_out / (2.0 * par->score.sigma_mm * par->score.sigma_mm);
+        if ((rc = laue_spot_greedy(w.loff, w.lrow, w.lval, static_cast<int32_t>(n_sc), obs->n, phi, par->k_max,
+                                   w.picks, w.gains, &n_picked, w.scratch, w.scratch_bytes, stream)))
+            return rc;
+    }
+    int k_star = 0;
+    if (n_picked > 0) {
+        std::vector<double> gains(n_picked);
+        LAUE_CHECK_HIP(hipMemcpyAsync(gains.data(), w.gains, n_picked * sizeof(double), hipMemcpyDeviceToHost, s));
+        LAUE_CHECK_HIP(hipStreamSynchronize(s));
+        double best = -INFINITY;
+        for (int k = 0; k < n_picked; ++k) {
+            const double drop = gains[k] - (k + 1 < n_picked ? gains[k + 1] : 0.0);
+            if (drop > best) {
+                best = drop;
+                k_star = k + 1;
+            }
+        }
+        k_gather_protos<<<(k_star + 63) / 64, 64, 0, s>>>(w.gq, w.gx, w.picks, k_star, out->q, out->x);
+        LAUE_CHECK_HIP(hipGetLastError());
+    }
+    st.n_picked = n_picked;
+    st.n_prototypes = k_star;
+    st.ms_greedy = ms_since(t0);
+    out->n_grains = k_star;
+    if (k_star == 0) {
+        st.ms_total = ms_since(t_all);
+        if (stats) *stats = st;
+        LAUE_CHECK_HIP(hipStreamSynchronize(s));
+        return LAUE_OK;
+    }
+
+    // 5. frozen model spots of the prototypes, then EM
+    t0 = std::chrono::steady_clock::now();
+    laue_grains protos{k_star, out->q, out->x};
+    std::vector<int64_t> moff(nb + 1, 0);
+    laue_model_spots model{};
+    model.n = par->max_model_spots;
+    model.plane = w.mplane;
+    model.grain = w.mgrain;
+    model.block = w.mblock;
+    model.s1 = w.s1;
+    model.s2 = w.s2;
+    model.vn = w.vn;
+    model.v1 = w.v1;
+    model.v2 = w.v2;
+    model.lam = w.lam;
+    model.flags = w.flags;
+    model.block_off = moff.data();
+    int64_t n_model = 0;
+    if ((rc = laue_forward_enumerate(geom, planes, &protos, 1, &model, &n_model, w.scratch, w.scratch_bytes, stream)))
+        return rc;
+    model.n = n_model;
+    st.n_model_spots = n_model;
+    laue_em_params em = par->em;
+    const double tb = std::ceil(par->t_b_frac * static_cast<double>(n_model));
+    em.ot.t_b = std::max(tb, static_cast<double>(n_model - obs->n));
+    const int64_t nf = std::max<int64_t>(obs->n, 1), ng = std::max<int64_t>(n_model, 1);
+    k_zero_f<<<static_cast<unsigned>((nf + 255) / 256), 256, 0, s>>>(w.f, nf);
+    k_zero_f<<<static_cast<unsigned>((ng + 255) / 256), 256, 0, s>>>(w.g, ng);
+    LAUE_CHECK_HIP(hipGetLastError());
+    laue_potentials pot{w.f, w.g, 0.0, 0.0};
+    laue_em_stats es{};
+    rc = laue_em(geom, planes, obs, &model, &em, &protos, &pot, with_assign ? &out->assign : nullptr, &es,
+                 w.scratch, w.scratch_bytes, stream);
+    if (rc < 0) return rc;
+    st.em = es;
+    st.ms_em = ms_since(t0);
+    st.ms_total = ms_since(t_all);
+    if (stats) *stats = st;
+    return rc;
+}

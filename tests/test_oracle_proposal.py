@@ -110,3 +110,35 @@ def test_select_top():
     v = rng.standard_normal(1000)
     got = proposal.select_top(v, 0.05)
     assert got.tolist() == sorted(np.argsort(-v)[:50].tolist())
+
+
+def test_same_grain_pairs():
+    rng = np.random.default_rng(4)
+    n_rot, n_det = 5, 2
+    counts = rng.integers(0, 12, n_rot * n_det)
+    counts[3] = 0
+    offsets = np.concatenate([[0], np.cumsum(counts)])
+    grain = rng.integers(-1, 4, offsets[-1])
+    a, b = proposal.same_grain_pairs(offsets, grain, n_det, 4000, 123)
+    ok = a >= 0
+    assert ok.mean() > 0.3
+    rot = lambda i: (np.searchsorted(offsets, i, side="right") - 1) // n_det
+    assert np.all(b[ok] != a[ok])
+    assert np.all(grain[a[ok]] == grain[b[ok]]) and np.all(grain[a[ok]] >= 0)
+    assert np.all(rot(a[ok]) == rot(b[ok]))
+    # a pair is missing only when a has no mate: outlier, or alone in its rotation
+    x0 = __import__("oracle.philox", fromlist=["x"]).philox4x32_10(
+        np.arange(4000), 0, 0, proposal.STREAM_SAME_PAIR, 123, 0)[0]
+    a_all = (x0 % np.uint64(offsets[-1])).astype(np.int64)
+    assert np.array_equal(a[ok], a_all[ok])
+    for j in np.nonzero(~ok)[0][:200]:
+        i = a_all[j]
+        mates = [m for m in range(offsets[-1]) if m != i and rot(m) == rot(i) and grain[m] == grain[i]]
+        assert grain[i] < 0 or not mates
+    # b is uniform over the mates: for a spot with 3+ mates every mate is drawn
+    seen = {}
+    for x, y in zip(a[ok], b[ok]):
+        seen.setdefault(int(x), set()).add(int(y))
+    full = [x for x, ys in seen.items()
+            if len(ys) == sum(1 for m in range(offsets[-1]) if m != x and rot(m) == rot(x) and grain[m] == grain[x])]
+    assert len(full) > 10
