@@ -216,7 +216,10 @@ typedef struct laue_ot_params {
     double distance;            /* D (mm) */
     double c_out, c_unm, c_sink;
     double t_b;
-    double tol;                 /* stop when max relative row-marginal error <= tol */
+    double tol;                 /* stop when max relative row-marginal error <= tol, or
+                                 * when it is <= 4 tol and has not fallen by 1% over
+                                 * 64 iterations (the rounding floor of FP32
+                                 * potentials); both count as converged */
     int32_t n_max;              /* iteration cap (>= 1) */
     int32_t chunk;              /* iterations between host polls (0: 16) */
 } laue_ot_params;

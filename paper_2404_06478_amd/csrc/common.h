@@ -186,9 +186,10 @@ __device__ __forceinline__ void accumulate_stats(float *a, float Q, float p1, fl
     const float dy = p1 - cC.s1, dz = p2 - cC.s2;
     const float h0u = cC.vn, h1u = cC.v1 + dy, h2u = cC.v2 + dz;
     const float dd = fmaf(h2u, h2u, fmaf(h1u, h1u, h0u * h0u));
-    const float itau = 1.0f / sqrtf(dd);
+    const float itau = __builtin_amdgcn_rsqf(dd);
     const float tau = dd * itau;
-    const float dl = fmaf(2.0f, fmaf(cC.v2, dz, cC.v1 * dy), fmaf(dz, dz, dy * dy)) / (tau + vlen);
+    const float dl = fmaf(2.0f, fmaf(cC.v2, dz, cC.v1 * dy), fmaf(dz, dz, dy * dy)) *
+                     __builtin_amdgcn_rcpf(tau + vlen);
     const float e0 = (-rn * dl) * itau;
     const float e1 = fmaf(-r1, dl, dy) * itau;
     const float e2 = fmaf(-r2, dl, dz) * itau;
@@ -212,6 +213,42 @@ __device__ __forceinline__ void accumulate_stats(float *a, float Q, float p1, fl
     a[13] = fmaf(wb, P11, a[13]);
     a[14] = fmaf(wb, P12, a[14]);
     a[15] = fmaf(wb, P22, a[15]);
+}
+
+// The statistics of one pair alone (a[] is overwritten).
+__device__ __forceinline__ void stats_of(float *a, float Q, float p1, float p2,
+                                                 const Col8 &cC, float vlen, float rn, float r1,
+                                                 float r2) {
+    const float dy = p1 - cC.s1, dz = p2 - cC.s2;
+    const float h0u = cC.vn, h1u = cC.v1 + dy, h2u = cC.v2 + dz;
+    const float dd = fmaf(h2u, h2u, fmaf(h1u, h1u, h0u * h0u));
+    const float itau = __builtin_amdgcn_rsqf(dd);
+    const float tau = dd * itau;
+    const float dl = fmaf(2.0f, fmaf(cC.v2, dz, cC.v1 * dy), fmaf(dz, dz, dy * dy)) *
+                     __builtin_amdgcn_rcpf(tau + vlen);
+    const float e0 = (-rn * dl) * itau;
+    const float e1 = fmaf(-r1, dl, dy) * itau;
+    const float e2 = fmaf(-r2, dl, dz) * itau;
+    const float h0 = h0u * itau, h1 = h1u * itau, h2 = h2u * itau;
+    const float wa = Q * itau * itau, wb = Q * itau;
+    const float P00 = fmaf(-h0, h0, 1.0f), P01 = -h0 * h1, P02 = -h0 * h2;
+    const float P11 = fmaf(-h1, h1, 1.0f), P12 = -h1 * h2, P22 = fmaf(-h2, h2, 1.0f);
+    a[0] = Q;
+    a[1] = Q * e0;
+    a[2] = Q * e1;
+    a[3] = Q * e2;
+    a[4] = wa * P00;
+    a[5] = wa * P01;
+    a[6] = wa * P02;
+    a[7] = wa * P11;
+    a[8] = wa * P12;
+    a[9] = wa * P22;
+    a[10] = wb * P00;
+    a[11] = wb * P01;
+    a[12] = wb * P02;
+    a[13] = wb * P11;
+    a[14] = wb * P12;
+    a[15] = wb * P22;
 }
 
 // FP64 contribution of one model spot (plane m, grain n, block b) to its

@@ -3,13 +3,11 @@
 // with a row-softmax E-step, the unmatched (3 sigma) filter, the sparse SPOT
 // grain-to-spot matrix and greedy prototype selection.
 //
-// Candidate work is laid out in "slots": a wave serves one (rotation,
-// detector) block and 64/S candidates, S lanes per candidate (S = smallest
-// power of two >= the largest number of model spots a candidate has in one
-// block).  Each lane owns one model spot; the block's detected spots stream
-// through scalar loads.  The softmax normaliser of a detected spot over the
-// candidate's spots is a butterfly sum within the S lanes, so the M-step
-// statistics stay in the lane that owns the spot.
+// Candidate work is laid out by (block, candidate): one wave per pair, its
+// lanes over the block's detected spots (64 at a time) and the candidate's few
+// model spots of that block streamed as wave-uniform (scalar) loads.  The
+// softmax normaliser of a detected spot is then a plain per-lane sum, and the
+// M-step statistics of model spot j are wave-reduced and kept by lane j.
 #include <algorithm>
 #include <cmath>
 
@@ -250,26 +248,44 @@ __global__ void k_pairs(int pass, const laue_geometry G, const float *__restrict
     if (!pass) counts[k] = found;
 }
 
-// ---------------------------------------------------------------- slots
+// ---------------------------------------------------------------- per (block, candidate) waves
 
-template <int S>
-__device__ __forceinline__ float seg_sum(float v) {
+// Reduce-scatter of 16 per-lane values over the wave: on return lane l holds
+// the wave total of value l >> 2 (17 exchanges instead of 16 x 6).
+__device__ __forceinline__ float wave_reduce_scatter16(const float *a, int lane) {
+    float b8[8], b4[4], b2[2];
+    const bool h5 = lane & 32, h4 = lane & 16, h3 = lane & 8, h2 = lane & 4;
 #pragma unroll
-    for (int o = S / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    for (int k = 0; k < 8; ++k) {
+        const float keep = h5 ? a[k + 8] : a[k], send = h5 ? a[k] : a[k + 8];
+        b8[k] = keep + __shfl_xor(send, 32, 64);
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const float keep = h4 ? b8[k + 4] : b8[k], send = h4 ? b8[k] : b8[k + 4];
+        b4[k] = keep + __shfl_xor(send, 16, 64);
+    }
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        const float keep = h3 ? b4[k + 2] : b4[k], send = h3 ? b4[k] : b4[k + 2];
+        b2[k] = keep + __shfl_xor(send, 8, 64);
+    }
+    const float keep = h2 ? b2[1] : b2[0], send = h2 ? b2[0] : b2[1];
+    float v = keep + __shfl_xor(send, 4, 64);
+    v += __shfl_xor(v, 2, 64);
+    v += __shfl_xor(v, 1, 64);
     return v;
 }
 
-template <int S>
-__device__ __forceinline__ double seg_sum_d(double v) {
+__device__ __forceinline__ float wave_min_f(float v) {
 #pragma unroll
-    for (int o = S / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    for (int o = 32; o > 0; o >>= 1) v = fminf(v, __shfl_xor(v, o, 64));
     return v;
 }
 
 struct SlotArgs {
     int C;                  // candidates in the batch
     int nb;                 // blocks
-    int G;                  // groups per block
     const int64_t *offs;    // [nb * C + 1] model-spot offsets per (block, candidate)
     const float *P1, *P2;
     const int64_t *ooff;    // detected-spot block offsets (device)
@@ -281,55 +297,95 @@ struct SlotArgs {
     const int *mplane, *mgrain, *mblock;
 };
 
+// Column data of model spot j held by lane j, read by the whole wave with
+// readlane (j wave-uniform).
+struct LaneCol {
+    float s1, s2, v1, v2, vv, vv2, vn;
+};
+
+__device__ __forceinline__ LaneCol lane_col(const Col8 *cols, int64_t o0, int nc, int lane) {
+    LaneCol c{0.0f, 0.0f, 0.0f, 0.0f, 1.0f, 1.0f, 1.0f};
+    if (lane < nc) {
+        const Col8 v = cols[o0 + lane];
+        c = LaneCol{v.s1, v.s2, v.v1, v.v2, v.vv, v.vv2, v.vn};
+    }
+    return c;
+}
+
+__device__ __forceinline__ float bcast(float v, int j) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), j));
+}
+
+__device__ __forceinline__ Col8 col_of(const LaneCol &c, int j) {
+    return Col8{bcast(c.s1, j), bcast(c.s2, j), bcast(c.v1, j), bcast(c.v2, j),
+                bcast(c.vv, j), bcast(c.vv2, j), bcast(c.vn, j), 0.0f};
+}
+
 // Single-grain E-step (row softmax with the outlier column, App. D) fused
-// with the M-step statistics; writes per (candidate, block) the summed
-// 27-value normal-equation contribution.
-template <int S>
+// with the M-step statistics: Q from the columns colsE (held fixed over the
+// Gauss-Newton steps of one refinement iteration), statistics at the current
+// columns colsC.  Writes per (candidate, block) the summed 27-value
+// normal-equation contribution.  One wave per (block b, candidate c), item =
+// b * C + c so that neighbouring waves stream the same detected spots.
 __global__ __launch_bounds__(64) void k_single_acc(SlotArgs A, float K, float bin_e, double D2,
                                                    double *__restrict__ hg_out) {
     const int item = blockIdx.x;
-    const int b = item / A.G, g = item - b * A.G;
+    const int b = item / A.C, c = item - b * A.C;
     const int lane = threadIdx.x;
-    const int c = g * (64 / S) + lane / S, k = lane % S;
-    const bool cv = c < A.C;
-    const int64_t o0 = cv ? A.offs[static_cast<int64_t>(b) * A.C + c] : 0;
-    const int64_t o1 = cv ? A.offs[static_cast<int64_t>(b) * A.C + c + 1] : 0;
-    const bool act = cv && (k < o1 - o0);
-    const int64_t col = o0 + k;
-    Col8 cE = {0, 0, 0, 0, 1, 1, 1, 0}, cC = {0, 0, 0, 0, 1, 1, 1, 0};
-    if (act) {
-        cE = A.colsE[col];
-        cC = A.colsC[col];
-    }
-    const float vlen = sqrtf(cC.vv), ivl = 1.0f / vlen;
-    const float rn = cC.vn * ivl, r1 = cC.v1 * ivl, r2 = cC.v2 * ivl;
+    const int64_t o0 = A.offs[static_cast<int64_t>(b) * A.C + c];
+    const int nc = static_cast<int>(A.offs[static_cast<int64_t>(b) * A.C + c + 1] - o0);
+    double *out = hg_out + (static_cast<int64_t>(c) * A.nb + b) * kHg;
     const int64_t r0 = A.ooff[b], rend = A.ooff[b + 1];
-    double s64[kStat];
-    for (int q = 0; q < kStat; ++q) s64[q] = 0.0;
-    for (int64_t i0 = r0; i0 < rend; i0 += 64) {
-        const int64_t i1 = min(i0 + 64, rend);
-        float a[kStat];
-        for (int q = 0; q < kStat; ++q) a[q] = 0.0f;
-        for (int64_t i = i0; i < i1; ++i) {
-            const float p1 = A.P1[i], p2 = A.P2[i];
-            const float e = act ? fast_exp2(entry_exponent(p1, p2, cE.s1, cE.s2, cE.v1, cE.v2, cE.vv,
-                                                           cE.vv2, K, 0.0f))
-                                : 0.0f;
-            const float z = seg_sum<S>(e) + bin_e;
-            const float Q = e * __builtin_amdgcn_rcpf(z);
-            if (Q > 0.0f) accumulate_stats(a, Q, p1, p2, cC, vlen, rn, r1, r2);
-        }
-        for (int q = 0; q < kStat; ++q) s64[q] += static_cast<double>(a[q]);
+    if (nc == 0) {
+        if (lane < kHg) out[lane] = 0.0;
+        return;
     }
+    const LaneCol lE = lane_col(A.colsE, o0, nc, lane), lC = lane_col(A.colsC, o0, nc, lane);
+    // per-column constants at the current geometry: |v|, v / |v|
+    const float ivl_l = __builtin_amdgcn_rsqf(lC.vv), vlen_l = lC.vv * ivl_l;
+    const float rn_l = lC.vn * ivl_l, r1_l = lC.v1 * ivl_l, r2_l = lC.v2 * ivl_l;
+    // FP64 running statistics of model spot j at acc[16 j + q] (this wave only)
+    __shared__ double acc[64 * kStat];
+    for (int k = lane; k < nc * kStat; k += 64) acc[k] = 0.0;
+    __syncthreads();
+    for (int64_t i0 = r0; i0 < rend; i0 += 64) {
+        const int64_t i = i0 + lane;
+        const bool rv = i < rend;
+        const float p1 = rv ? A.P1[i] : 0.0f, p2 = rv ? A.P2[i] : 0.0f;
+        float z = bin_e;
+        for (int j = 0; j < nc; ++j) {
+            const Col8 cE = col_of(lE, j);
+            z += fast_exp2(entry_exponent(p1, p2, cE.s1, cE.s2, cE.v1, cE.v2, cE.vv, cE.vv2, K, 0.0f));
+        }
+        const float iz = rv ? __builtin_amdgcn_rcpf(z) : 0.0f;
+        for (int j = 0; j < nc; ++j) {
+            const Col8 cE = col_of(lE, j);
+            const float Q =
+                fast_exp2(entry_exponent(p1, p2, cE.s1, cE.s2, cE.v1, cE.v2, cE.vv, cE.vv2, K, 0.0f)) * iz;
+            if (!__any(Q > 0.0f)) continue;                 // no weight in this chunk
+            const Col8 cC = col_of(lC, j);
+            float a[kStat];                               // zero for Q = 0 (finite geometry)
+            stats_of(a, Q, p1, p2, cC, bcast(vlen_l, j), bcast(rn_l, j), bcast(r1_l, j), bcast(r2_l, j));
+            const float t = wave_reduce_scatter16(a, lane);
+            if ((lane & 3) == 0) acc[kStat * j + (lane >> 2)] += static_cast<double>(t);
+        }
+    }
+    __syncthreads();
     double hg[kHg];
-    if (act)
-        column_normal_equations(*A.geom, A.W, A.n_planes, A.grains, A.C, A.mplane[col],
-                                A.mgrain[col], A.mblock[col], s64, rn, r1, r2, D2, hg);
-    else
+    if (lane < nc) {
+        double s64[kStat];
+#pragma unroll
+        for (int q = 0; q < kStat; ++q) s64[q] = acc[kStat * lane + q];
+        const int64_t col = o0 + lane;
+        column_normal_equations(*A.geom, A.W, A.n_planes, A.grains, A.C, A.mplane[col], A.mgrain[col],
+                                A.mblock[col], s64, rn_l, r1_l, r2_l, D2, hg);
+    } else {
+#pragma unroll
         for (int q = 0; q < kHg; ++q) hg[q] = 0.0;
+    }
     for (int q = 0; q < kHg; ++q) {
-        const double v = seg_sum_d<S>(hg[q]);
-        if (k == 0 && cv) hg_out[(static_cast<int64_t>(c) * A.nb + b) * kHg + q] = v;
+        const double v = wave_sum(hg[q]);
+        if (lane == 0) out[q] = v;
     }
 }
 
@@ -354,7 +410,7 @@ __global__ __launch_bounds__(64) void k_single_solve(const double *__restrict__ 
 // SPOT entry Lbar = ln sum_j exp(-c_ij / (2 sigma^2)) when above the floor
 // exp(-c_out / (2 sigma^2)).  pass 0 counts per (candidate, block); pass 1
 // writes the entries at loff (CSR by candidate, then block, then row).
-template <int S>
+// One wave per (block, candidate) as in k_single_acc.
 __global__ __launch_bounds__(64) void k_single_score(SlotArgs A, int pass, float twoD2, float K2,
                                                      float floor_e, float c_out,
                                                      int *__restrict__ unm, int *__restrict__ lcnt,
@@ -363,42 +419,53 @@ __global__ __launch_bounds__(64) void k_single_score(SlotArgs A, int pass, float
                                                      int *__restrict__ lrow,
                                                      float *__restrict__ lval) {
     const int item = blockIdx.x;
-    const int b = item / A.G, g = item - b * A.G;
+    const int b = item / A.C, c = item - b * A.C;
     const int lane = threadIdx.x;
-    const int c = g * (64 / S) + lane / S, k = lane % S;
-    const bool cv = c < A.C;
-    const int64_t o0 = cv ? A.offs[static_cast<int64_t>(b) * A.C + c] : 0;
-    const int64_t o1 = cv ? A.offs[static_cast<int64_t>(b) * A.C + c + 1] : 0;
-    // pass 1 writes entries of kept candidates only (dropped ones have no range)
-    const bool has = cv && o1 > o0 && (!pass || keep[c]);
-    const bool act = cv && (k < o1 - o0);
-    Col8 cC = {0, 0, 0, 0, 1, 1, 1, 0};
-    if (act) cC = A.colsC[o0 + k];
-    const int64_t r0 = A.ooff[b], rend = A.ooff[b + 1];
-    float cmin = INFINITY;
-    int cnt = 0;
-    int64_t pos = (pass && cv) ? loff[static_cast<int64_t>(c) * A.nb + b] : 0;
-    for (int64_t i = r0; i < rend; ++i) {
-        const float cp = act ? entry_exponent(A.P1[i], A.P2[i], cC.s1, cC.s2, cC.v1, cC.v2, cC.vv,
-                                              cC.vv2, -1.0f, 0.0f)
-                             : INFINITY;
-        cmin = fminf(cmin, twoD2 * cp);
-        const float e = act ? fast_exp2(-K2 * cp) : 0.0f;
-        const float z = seg_sum<S>(e);
-        if (has && z > floor_e) {
-            if (pass && k == 0) {
-                lrow[pos] = static_cast<int>(i);
-                lval[pos] = __logf(z);
-            }
-            ++pos;
-            ++cnt;
+    const int64_t o0 = A.offs[static_cast<int64_t>(b) * A.C + c];
+    const int nc = static_cast<int>(A.offs[static_cast<int64_t>(b) * A.C + c + 1] - o0);
+    const int64_t slot = static_cast<int64_t>(c) * A.nb + b;
+    if (nc == 0 || (pass && !keep[c])) {
+        if (!pass && lane == 0) {
+            unm[slot] = 0;
+            lcnt[slot] = 0;
         }
+        return;
+    }
+    const int64_t r0 = A.ooff[b], rend = A.ooff[b + 1];
+    const LaneCol lC = lane_col(A.colsC, o0, nc, lane);
+    float cmin = INFINITY;                       // lane j: nearest detected spot of model spot j
+    int64_t pos = pass ? loff[slot] : 0;
+    int cnt = 0;
+    for (int64_t i0 = r0; i0 < rend; i0 += 64) {
+        const int64_t i = i0 + lane;
+        const bool rv = i < rend;
+        const float p1 = rv ? A.P1[i] : 0.0f, p2 = rv ? A.P2[i] : 0.0f;
+        float zz = 0.0f;
+        for (int j = 0; j < nc; ++j) {
+            const Col8 cC = col_of(lC, j);
+            const float cp = entry_exponent(p1, p2, cC.s1, cC.s2, cC.v1, cC.v2, cC.vv, cC.vv2, -1.0f, 0.0f);
+            zz += rv ? fast_exp2(-K2 * cp) : 0.0f;
+            if (!pass) {
+                const float m = wave_min_f(rv ? twoD2 * cp : INFINITY);
+                if (lane == j) cmin = fminf(cmin, m);
+            }
+        }
+        const bool hit = rv && zz > floor_e;
+        const uint64_t mask = __ballot(hit);
+        if (pass && hit) {
+            const int my = __popcll(mask & ((uint64_t(1) << lane) - 1));
+            lrow[pos + my] = static_cast<int>(i);
+            lval[pos + my] = __logf(zz);
+        }
+        const int nh = __popcll(mask);
+        pos += nh;
+        cnt += nh;
     }
     if (!pass) {
-        const float um = seg_sum<S>((act && cmin > c_out) ? 1.0f : 0.0f);
-        if (k == 0 && cv) {
-            unm[static_cast<int64_t>(c) * A.nb + b] = static_cast<int>(um);
-            lcnt[static_cast<int64_t>(c) * A.nb + b] = cnt;
+        const int um = __popcll(__ballot(lane < nc && cmin > c_out));
+        if (lane == 0) {
+            unm[slot] = um;
+            lcnt[slot] = cnt;
         }
     }
 }
@@ -720,36 +787,16 @@ size_t carve_score(Carver &cv, ScoreWs &w, const laue_geometry *g, int chunk, in
     return cv.size();
 }
 
-int dispatch_acc(int S, const SlotArgs &A, float K, float bin_e, double D2, double *hg, hipStream_t s) {
-    const unsigned grid = static_cast<unsigned>(A.nb) * A.G;
-    switch (S) {
-        case 1: k_single_acc<1><<<grid, 64, 0, s>>>(A, K, bin_e, D2, hg); break;
-        case 2: k_single_acc<2><<<grid, 64, 0, s>>>(A, K, bin_e, D2, hg); break;
-        case 4: k_single_acc<4><<<grid, 64, 0, s>>>(A, K, bin_e, D2, hg); break;
-        case 8: k_single_acc<8><<<grid, 64, 0, s>>>(A, K, bin_e, D2, hg); break;
-        case 16: k_single_acc<16><<<grid, 64, 0, s>>>(A, K, bin_e, D2, hg); break;
-        case 32: k_single_acc<32><<<grid, 64, 0, s>>>(A, K, bin_e, D2, hg); break;
-        default: k_single_acc<64><<<grid, 64, 0, s>>>(A, K, bin_e, D2, hg); break;
-    }
+int launch_acc(const SlotArgs &A, float K, float bin_e, double D2, double *hg, hipStream_t s) {
+    k_single_acc<<<static_cast<unsigned>(A.nb) * A.C, 64, 0, s>>>(A, K, bin_e, D2, hg);
     LAUE_CHECK_HIP(hipGetLastError());
     return LAUE_OK;
 }
 
-int dispatch_score(int S, const SlotArgs &A, int pass, float twoD2, float K2, float floor_e,
-                   float c_out, int *unm, int *lcnt, const int64_t *loff, const uint8_t *keep,
-                   int *lrow, float *lval, hipStream_t s) {
-    const unsigned grid = static_cast<unsigned>(A.nb) * A.G;
-#define LAUE_SCORE(SS) k_single_score<SS><<<grid, 64, 0, s>>>(A, pass, twoD2, K2, floor_e, c_out, unm, lcnt, loff, keep, lrow, lval)
-    switch (S) {
-        case 1: LAUE_SCORE(1); break;
-        case 2: LAUE_SCORE(2); break;
-        case 4: LAUE_SCORE(4); break;
-        case 8: LAUE_SCORE(8); break;
-        case 16: LAUE_SCORE(16); break;
-        case 32: LAUE_SCORE(32); break;
-        default: LAUE_SCORE(64); break;
-    }
-#undef LAUE_SCORE
+int launch_score(const SlotArgs &A, int pass, float twoD2, float K2, float floor_e, float c_out, int *unm,
+                 int *lcnt, const int64_t *loff, const uint8_t *keep, int *lrow, float *lval, hipStream_t s) {
+    k_single_score<<<static_cast<unsigned>(A.nb) * A.C, 64, 0, s>>>(A, pass, twoD2, K2, floor_e, c_out, unm,
+                                                                       lcnt, loff, keep, lrow, lval);
     LAUE_CHECK_HIP(hipGetLastError());
     return LAUE_OK;
 }
@@ -821,13 +868,10 @@ extern "C" int laue_score_candidates(const laue_geometry *geom, const laue_plane
         LAUE_CHECK_HIP(hipMemcpyAsync(&maxc, w.maxc, sizeof(int), hipMemcpyDeviceToHost, s));
         LAUE_CHECK_HIP(hipStreamSynchronize(s));
         LAUE_REQUIRE(maxc <= 64, LAUE_ECAPACITY, "a candidate has more than 64 model spots in one block");
-        int S = 1;
-        while (S < maxc) S <<= 1;
         if ((rc = launch_enumerate_ids(geom, planes, w.e, C, 1, w.plane, w.grain, w.block, s))) return rc;
         SlotArgs A;
         A.C = C;
         A.nb = nb;
-        A.G = (C * S + 63) / 64;
         A.offs = w.e.offs;
         A.P1 = obs->p1;
         A.P2 = obs->p2;
@@ -859,7 +903,7 @@ extern "C" int laue_score_candidates(const laue_geometry *geom, const laue_plane
                         return rc;
                     A.colsC = w.colsC;
                 }
-                if ((rc = dispatch_acc(S, A, K, bin_e, D2, w.hg, s))) return rc;
+                if ((rc = launch_acc(A, K, bin_e, D2, w.hg, s))) return rc;
                 k_single_solve<<<C, 64, 0, s>>>(w.hg, nb, C, par->mu_rel, sub.q, sub.x, w.e.grains);
                 LAUE_CHECK_HIP(hipGetLastError());
             }
@@ -869,7 +913,7 @@ extern "C" int laue_score_candidates(const laue_geometry *geom, const laue_plane
                               nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, w.colsC, s)))
             return rc;
         A.colsC = w.colsC;
-        if ((rc = dispatch_score(S, A, 0, twoD2, K2, floor_e, static_cast<float>(par->c_out), w.unm,
+        if ((rc = launch_score(A, 0, twoD2, K2, floor_e, static_cast<float>(par->c_out), w.unm,
                                  w.lcnt, nullptr, nullptr, nullptr, nullptr, s)))
             return rc;
         k_single_keep<<<(C + 127) / 128, 128, 0, s>>>(C, nb, w.e.offs, w.unm, w.lcnt, par->f_out,
@@ -890,7 +934,7 @@ extern "C" int laue_score_candidates(const laue_geometry *geom, const laue_plane
         k_cand_off<<<(C + 1 + 127) / 128, 128, 0, s>>>(w.loff, C, nb, lbar_total, out->lbar_off, c0, 1);
         LAUE_CHECK_HIP(hipGetLastError());
         if (ctot > 0 &&
-            (rc = dispatch_score(S, A, 1, twoD2, K2, floor_e, static_cast<float>(par->c_out), nullptr,
+            (rc = launch_score(A, 1, twoD2, K2, floor_e, static_cast<float>(par->c_out), nullptr,
                                  nullptr, w.loff, w.keep, out->lbar_row + lbar_total,
                                  out->lbar_val + lbar_total, s)))
             return rc;

@@ -97,7 +97,7 @@ def test_index_recovers_medium_grains(gpu_lib):
     obs = laue.laue_simulate(geom, planes, truth, p.sigma_mm, p.distance, p.outlier_frac, p.seed)
     par = laue.index_params(p, "plain", n_pairs=4096, seed=1, n_obs=obs.n, n_planes=planes.n)
     grains, st, asg = laue.laue_index(geom, planes, obs, par)
-    print({k: v for k, v in st.items() if k != "em"})
+    print(st)
     qg, xg = grains.numpy()
     rec, _ = metrics.match_grains(qg[:grains.n], xg[:grains.n], q, x)
     print("recovered", rec, "of", len(q), "prototypes", grains.n)
