@@ -331,6 +331,22 @@ int laue_em(const laue_geometry *geom, const laue_planes *planes,
             laue_assignments *assign, laue_em_stats *stats,
             void *ws, size_t ws_bytes, void *stream);
 
+/* Batched EM of n independent samples (arrays of n structs, one per sample;
+ * each sample's device arrays are its own).  Every pass of the E- and M-steps
+ * is one launch over the work of all samples; each sample keeps its own bins,
+ * temperature schedule, convergence and statistics, and gets the result that
+ * laue_em would give it alone.  Samples share n_stages, iters_per_stage and
+ * gn.k_gn; ot.chunk of sample 0 sets the host polling interval.  assigns may
+ * be NULL or hold NULL arrays for some samples.  The millisecond fields of
+ * every stats entry are the batch's totals.  Synchronous; LAUE_ENOCONV when
+ * some Sinkhorn of some sample stopped at its cap. */
+size_t laue_em_batched_workspace_size(int32_t n, const laue_geometry *geoms, const int64_t *n_obs,
+                                      const int64_t *n_model, const int32_t *n_grains);
+int laue_em_batched(int32_t n, const laue_geometry *geoms, const laue_planes *planes,
+                    const laue_obs_spots *obs, laue_model_spots *models, const laue_em_params *pars,
+                    laue_grains *grains, laue_potentials *pots, laue_assignments *assigns,
+                    laue_em_stats *stats, void *ws, size_t ws_bytes, void *stream);
+
 /* ---- prototype scoring (Sec. 6, App. D-E) -------------------------------- */
 
 /* Spot-pair candidate orientations.  Each detected spot of a pair is read as

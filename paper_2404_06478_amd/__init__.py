@@ -696,3 +696,49 @@ def laue_index(geom, planes, obs, par, assign=True):
     g.q, g.x, g.n = q[:max(k, 1)], x[:max(k, 1)], k
     asg = None if asg_t is None else {kk: v[:obs.n] for kk, v in asg_t.items()}
     return g, stats, asg
+
+
+def laue_em_batched(geoms, planes, obs, models, pars, grains, assign=True):
+    """Batched EM of independent samples (lists of equal length); grains are
+    updated in place.  Returns (code, list of per-sample result dicts)."""
+    import torch
+    lib = require_native()
+    dev = _dev()
+    n = len(geoms)
+    G = (laue_geometry * n)(*geoms)
+    PL = (_abi.laue_planes * n)(*[p.struct for p in planes])
+    O = (laue_obs_spots * n)(*[o.struct() for o in obs])
+    M = (laue_model_spots * n)(*[m.struct() for m in models])
+    PA = (laue_em_params * n)(*pars)
+    GR = (laue_grains * n)(*[g.struct for g in grains])
+    f = [torch.zeros(max(o.n, 1), dtype=torch.float32, device=dev) for o in obs]
+    g = [torch.zeros(max(m.n, 1), dtype=torch.float32, device=dev) for m in models]
+    POT = (laue_potentials * n)(*[laue_potentials(f[k].data_ptr(), g[k].data_ptr(), 0.0, 0.0) for k in range(n)])
+    asg_t = []
+    AS = None
+    if assign:
+        for o in obs:
+            m = max(o.n, 1)
+            asg_t.append({"j_star": torch.zeros(m, dtype=torch.int32, device=dev),
+                          "grain": torch.zeros(m, dtype=torch.int32, device=dev),
+                          "q_star": torch.zeros(m, dtype=torch.float32, device=dev),
+                          "q_out": torch.zeros(m, dtype=torch.float32, device=dev)})
+        AS = (laue_assignments * n)(*[laue_assignments(*(a[k].data_ptr() for k in ("j_star", "grain", "q_star",
+                                                                                    "q_out"))) for a in asg_t])
+    no = np.array([o.n for o in obs], np.int64)
+    nm = np.array([m.n for m in models], np.int64)
+    ng = np.array([gg.n for gg in grains], np.int32)
+    need = lib.laue_em_batched_workspace_size(n, G, C.c_void_p(no.ctypes.data), C.c_void_p(nm.ctypes.data),
+                                              C.c_void_p(ng.ctypes.data))
+    ws = _workspace(need)
+    ST = (laue_em_stats * n)()
+    rc = _check(lib.laue_em_batched(n, G, PL, O, M, PA, GR, POT, AS, ST, _ptr(ws), ws.numel(), _stream()))
+    out = []
+    for k in range(n):
+        st = ST[k]
+        r = {"f": f[k][:obs[k].n], "g": g[k][:models[k].n], "f0": POT[k].f0, "g0": POT[k].g0}
+        r.update({name: getattr(st, name) for name, _ in laue_em_stats._fields_})
+        if assign:
+            r.update({kk: v[:obs[k].n] for kk, v in asg_t[k].items()})
+        out.append(r)
+    return rc, out

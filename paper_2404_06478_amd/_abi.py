@@ -206,6 +206,10 @@ SIGNATURES = {
     "laue_index_workspace_size": (C.c_size_t, [P(laue_geometry), C.c_int32, C.c_int64, P(laue_index_params)]),
     "laue_index": (C.c_int, [P(laue_geometry), P(laue_planes), P(laue_obs_spots), P(laue_index_params),
                              P(laue_index_out), P(laue_index_stats), vp, C.c_size_t, vp]),
+    "laue_em_batched_workspace_size": (C.c_size_t, [C.c_int32, P(laue_geometry), vp, vp, vp]),
+    "laue_em_batched": (C.c_int, [C.c_int32, P(laue_geometry), P(laue_planes), P(laue_obs_spots),
+                                  P(laue_model_spots), P(laue_em_params), P(laue_grains), P(laue_potentials),
+                                  P(laue_assignments), P(laue_em_stats), vp, C.c_size_t, vp]),
     "laue_select_top_workspace_size": (C.c_size_t, [C.c_int64]),
     "laue_select_top": (C.c_int, [vp, C.c_int64, C.c_int64, vp, vp, C.c_size_t, vp]),
 }

@@ -60,6 +60,20 @@ struct GrainF {
     float x[3];
 };
 
+// FP32 grain from an FP64 quaternion (normalised) and position.
+__device__ inline GrainF grain_f32(const double *q, const double *x) {
+    double w = q[0], a = q[1], b = q[2], c = q[3];
+    const double nrm = sqrt(w * w + a * a + b * b + c * c);
+    w /= nrm; a /= nrm; b /= nrm; c /= nrm;
+    const double R[9] = {1 - 2 * (b * b + c * c), 2 * (a * b - w * c),     2 * (a * c + w * b),
+                         2 * (a * b + w * c),     1 - 2 * (a * a + c * c), 2 * (b * c - w * a),
+                         2 * (a * c - w * b),     2 * (b * c + w * a),     1 - 2 * (a * a + b * b)};
+    GrainF g;
+    for (int k = 0; k < 9; ++k) g.R[k] = static_cast<float>(R[k]);
+    for (int k = 0; k < 3; ++k) g.x[k] = static_cast<float>(x[k]);
+    return g;
+}
+
 // ---------------------------------------------------------------- workspace
 
 // Bump allocator over a caller workspace; with base == nullptr it only sizes.

@@ -1,5 +1,6 @@
 // E-step (streamed log-domain Sinkhorn with outlier row/column), M-step
-// (per-grain weighted Gauss-Newton) and the EM driver.
+// (per-grain weighted Gauss-Newton) and the EM driver, for one sample or a
+// batch of independent samples.
 //
 // Paper: Sec. 4.2-4.4 (Eqs. update_L, elbo, estep_obj, mstep_obj),
 // Alg. BalancedOT and Alg. LaueOT.
@@ -13,9 +14,17 @@
 // 64 columns (column pass) of one (rotation, detector) block and streams the
 // other side of that block through scalar loads, so the |I_b| x |J_b| cost
 // block is recomputed on the fly and never stored.
+//
+// Batching: every sample has a descriptor (its arrays, bins, temperature and
+// control block); a work item names its sample and its index within that
+// sample.  One launch per pass covers all samples; each sample finalises its
+// own bins in the last of its workgroups (a per-sample ticket) and stops on
+// its own; workgroups of finished samples exit at once.  A sample's
+// arithmetic does not depend on the other samples in the batch.
 #include <algorithm>
 #include <cmath>
 #include <numeric>
+#include <vector>
 
 #include "common.h"
 
@@ -23,9 +32,11 @@ namespace laue {
 
 int launch_pack(const laue_model_spots *m, Col8 *cols, hipStream_t s);
 
-
 struct Item {
     int r0, r1, c0, c1;
+    int s;        // sample
+    int local;    // index among the sample's items of this pass
+    int pad[2];
 };
 
 struct SinkCtl {
@@ -49,30 +60,73 @@ struct SinkParams {
     int n_max;
 };
 
+// Everything a kernel needs about one sample.
+struct SampleDesc {
+    const float *p1, *p2;          // detected spots
+    float *f, *f1, *g;             // potentials (f1: odd states, ws)
+    Col8 *colsE, *colsC;           // packed columns: plan geometry / current geometry
+    SinkCtl *ctl;
+    double2 *part;                 // per-item partials of a pass
+    int n_row_items, n_col_items;
+    SinkParams sp;
+    const int *mplane, *mgrain, *mblock;
+    float *s1, *s2, *vn, *v1, *v2, *lam;   // forward-model outputs (may be NULL)
+    const int64_t *mboff;          // model-spot block offsets (device)
+    int64_t n_obs, n_model;
+    int nb, n_grains, n_planes, pad0;
+    const GeomF *geom;
+    GrainF *grains;
+    double *q, *x;
+    double *colHg;
+    double *step_norm;             // may be NULL
+    const float *W, *Dsp;
+    double D2, mu_rel;
+    int *jstar, *gstar;            // assignments (may be NULL)
+    float *qstar, *qout;
+};
+
 // ---------------------------------------------------------------- helpers
 
-__device__ __forceinline__ bool last_block(SinkCtl *ctl) {
+__device__ __forceinline__ bool last_block(SinkCtl *ctl, int n_items) {
     __shared__ int is_last;
     __threadfence();
     __syncthreads();
     if (threadIdx.x == 0) {
         unsigned t = atomicAdd(&ctl->ticket, 1u);
-        is_last = (t == gridDim.x - 1) ? 1 : 0;
+        is_last = (t == static_cast<unsigned>(n_items) - 1u) ? 1 : 0;
     }
     __syncthreads();
     if (is_last) __threadfence();
     return is_last != 0;
 }
 
-__global__ void k_ctl_init(SinkCtl *ctl, double f0, double g0, double eps) {
-    ctl->f0[0] = f0;
-    ctl->g0[0] = g0;
-    ctl->f0[1] = f0;
-    ctl->g0[1] = g0;
+// sample s with base[s] <= i < base[s + 1] (base non-decreasing, n + 1 entries)
+__device__ __forceinline__ int sample_of(const int64_t *base, int n, int64_t i) {
+    int lo = 0, hi = n;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) / 2;
+        if (base[mid] <= i) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+struct CtlInit {
+    double f0, g0, eps;
+};
+
+__global__ void k_ctl_init(const SampleDesc *__restrict__ descs, int n, const CtlInit *__restrict__ init) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    SinkCtl *ctl = descs[s].ctl;
+    const CtlInit v = init[s];
+    ctl->f0[0] = v.f0;
+    ctl->g0[0] = v.g0;
+    ctl->f0[1] = v.f0;
+    ctl->g0[1] = v.g0;
     ctl->cs_sum = 0.0;
     ctl->err = INFINITY;
-    ctl->eps = eps;
-    ctl->kexp = 1.4426950408889634 / eps;
+    ctl->eps = v.eps;
+    ctl->kexp = 1.4426950408889634 / v.eps;
     ctl->iter = 0;
     ctl->done = 0;
     ctl->best_iter = 0;
@@ -82,25 +136,22 @@ __global__ void k_ctl_init(SinkCtl *ctl, double f0, double g0, double eps) {
     ctl->ticket = 0u;
 }
 
-// cs_sum of the initial state: sum_j exp((f0 + g_j - c_unm)/eps).
-__global__ __launch_bounds__(64) void k_cs_init(const float *__restrict__ G, int64_t nJ,
-                                                SinkCtl *ctl, double *__restrict__ part,
-                                                SinkParams p) {
+// cs_sum of the initial state: sum_j exp((f0 + g_j - c_unm)/eps); one
+// workgroup per sample, fixed summation order.
+__global__ __launch_bounds__(256) void k_cs_init(const SampleDesc *__restrict__ descs) {
+    const SampleDesc &D = descs[blockIdx.x];
+    SinkCtl *ctl = D.ctl;
     const double eps = ctl->eps, f0 = ctl->f0[0];
     double s = 0.0;
-    for (int64_t j = static_cast<int64_t>(blockIdx.x) * 64 + threadIdx.x; j < nJ;
-         j += static_cast<int64_t>(gridDim.x) * 64)
-        s += exp((f0 + static_cast<double>(G[j]) - p.c_unm) / eps);
-    s = wave_sum(s);
-    if (threadIdx.x == 0) part[blockIdx.x] = s;
-    if (last_block(ctl)) {
+    for (int64_t j = threadIdx.x; j < D.n_model; j += 256)
+        s += exp((f0 + static_cast<double>(D.g[j]) - D.sp.c_unm) / eps);
+    __shared__ double part[256];
+    part[threadIdx.x] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
         double t = 0.0;
-        for (int w = threadIdx.x; w < static_cast<int>(gridDim.x); w += 64) t += part[w];
-        t = wave_sum(t);
-        if (threadIdx.x == 0) {
-            ctl->cs_sum = t;
-            ctl->ticket = 0u;
-        }
+        for (int k = 0; k < 256; ++k) t += part[k];
+        ctl->cs_sum = t;
     }
 }
 
@@ -111,25 +162,27 @@ __global__ __launch_bounds__(64) void k_cs_init(const float *__restrict__ G, int
 // shift every term is an entry of the current plan (<= 1 after a column
 // half), so no running maximum is needed.  The sum S_i is the row marginal of
 // state k-1 (its error is the convergence test) and f_i^k = f_i^{k-1} -
-// eps ln S_i.  The last workgroup updates the bin potentials and decides
-// convergence.
+// eps ln S_i.  The sample's last workgroup updates its bin potentials and
+// decides its convergence.
 __global__ __launch_bounds__(64) void k_row(const Item *__restrict__ items,
-                                            const float *__restrict__ P1,
-                                            const float *__restrict__ P2,
-                                            const Col8 *__restrict__ cols,
-                                            const float *__restrict__ G, float *F0, float *F1,
-                                            SinkCtl *ctl, double2 *__restrict__ part,
-                                            SinkParams p) {
+                                            const SampleDesc *__restrict__ descs) {
+    const Item it = items[blockIdx.x];
+    const SampleDesc &D = descs[it.s];
+    SinkCtl *ctl = D.ctl;
     if (ctl->done) return;
+    const SinkParams p = D.sp;
+    const float *__restrict__ P1 = D.p1;
+    const float *__restrict__ P2 = D.p2;
+    const Col8 *__restrict__ cols = D.colsE;
+    const float *__restrict__ G = D.g;
     const int k = ctl->iter + 1;
-    const float *Fin = ((k - 1) & 1) ? F1 : F0;
-    float *Fout = (k & 1) ? F1 : F0;
+    const float *Fin = ((k - 1) & 1) ? D.f1 : D.f;
+    float *Fout = (k & 1) ? D.f1 : D.f;
     const double eps = ctl->eps;
     const double kexp = ctl->kexp;
     const float kx = static_cast<float>(kexp);
     const float K = p.twoD2 * kx;
     const double g0 = ctl->g0[(k - 1) & 1];
-    const Item it = items[blockIdx.x];
     const int i = it.r0 + static_cast<int>(threadIdx.x);
     const bool act = i < it.r1;
     const float p1 = act ? P1[i] : 0.0f;
@@ -180,12 +233,12 @@ __global__ __launch_bounds__(64) void k_row(const Item *__restrict__ items,
     }
     rs = wave_sum(rs);
     err = wave_max(err);
-    if (threadIdx.x == 0) part[blockIdx.x] = make_double2(rs, err);
-    if (!last_block(ctl)) return;
+    if (threadIdx.x == 0) D.part[it.local] = make_double2(rs, err);
+    if (!last_block(ctl, D.n_row_items)) return;
     double rsum = 0.0, emax = 0.0;
-    for (int w = threadIdx.x; w < static_cast<int>(gridDim.x); w += 64) {
-        rsum += part[w].x;
-        emax = fmax(emax, part[w].y);
+    for (int w = threadIdx.x; w < D.n_row_items; w += 64) {
+        rsum += D.part[w].x;
+        emax = fmax(emax, D.part[w].y);
     }
     rsum = wave_sum(rsum);
     emax = wave_max(emax);
@@ -227,29 +280,31 @@ __global__ __launch_bounds__(64) void k_row(const Item *__restrict__ items,
 // Column half of iteration k = iter for 64 model spots of one block: each
 // lane streams the block's detected spots with g_j^{k-1} as shift (terms are
 // entries of the plan after the row half, <= 1) and sets
-// g_j^k = g_j^{k-1} - eps ln(column marginal).  The last workgroup stores
-// sum_j exp((f0 + g_j - c_unm)/eps) for the next row half.
+// g_j^k = g_j^{k-1} - eps ln(column marginal).  The sample's last workgroup
+// stores sum_j exp((f0 + g_j - c_unm)/eps) for the next row half.
 __global__ __launch_bounds__(64) void k_col(const Item *__restrict__ items,
-                                            const float *__restrict__ P1,
-                                            const float *__restrict__ P2,
-                                            const Col8 *__restrict__ cols, float *G,
-                                            const float *F0, const float *F1, SinkCtl *ctl,
-                                            double2 *__restrict__ part, SinkParams p) {
+                                            const SampleDesc *__restrict__ descs) {
+    const Item it = items[blockIdx.x];
+    const SampleDesc &D = descs[it.s];
+    SinkCtl *ctl = D.ctl;
     if (ctl->done) return;
+    const SinkParams p = D.sp;
+    const float *__restrict__ P1 = D.p1;
+    const float *__restrict__ P2 = D.p2;
+    float *G = D.g;
     const int k = ctl->iter;
-    const float *__restrict__ F = (k & 1) ? F1 : F0;
+    const float *__restrict__ F = (k & 1) ? D.f1 : D.f;
     const double eps = ctl->eps;
     const double kexp = ctl->kexp;
     const float kx = static_cast<float>(kexp);
     const float K = p.twoD2 * kx;
     const double f0 = ctl->f0[k & 1];
-    const Item it = items[blockIdx.x];
     const int j = it.c0 + static_cast<int>(threadIdx.x);
     const bool act = j < it.c1;
     Col8 c = {0, 0, 0, 0, 1, 1, 1, 0};
     float g = 0.0f;
     if (act) {
-        c = cols[j];
+        c = D.colsE[j];
         g = G[j];
     }
     const float gk = g * kx;
@@ -289,10 +344,10 @@ __global__ __launch_bounds__(64) void k_col(const Item *__restrict__ items,
         cs = exp((f0 + static_cast<double>(gn) - p.c_unm) / eps);
     }
     cs = wave_sum(cs);
-    if (threadIdx.x == 0) part[blockIdx.x] = make_double2(cs, 0.0);
-    if (!last_block(ctl)) return;
+    if (threadIdx.x == 0) D.part[it.local] = make_double2(cs, 0.0);
+    if (!last_block(ctl, D.n_col_items)) return;
     double t = 0.0;
-    for (int w = threadIdx.x; w < static_cast<int>(gridDim.x); w += 64) t += part[w].x;
+    for (int w = threadIdx.x; w < D.n_col_items; w += 64) t += D.part[w].x;
     t = wave_sum(t);
     if (threadIdx.x == 0) {
         ctl->cs_sum = t;
@@ -300,33 +355,31 @@ __global__ __launch_bounds__(64) void k_col(const Item *__restrict__ items,
     }
 }
 
-// ---------------------------------------------------------------- plan / assign
+// ---------------------------------------------------------------- assign
 
 // Hard assignment per detected spot: argmax_j Q_ij over its block and the
-// outlier column (lowest index on ties, -1 = outlier).
+// outlier column (lowest index on ties, -1 = outlier), with the sample's final
+// potentials and temperature.
 __global__ __launch_bounds__(64) void k_assign(const Item *__restrict__ items,
-                                               const float *__restrict__ P1,
-                                               const float *__restrict__ P2,
-                                               const Col8 *__restrict__ cols,
-                                               const float *__restrict__ G,
-                                               const float *__restrict__ F,
-                                               const int *__restrict__ mgrain, double g0, double eps,
-                                               SinkParams p, int *__restrict__ jstar,
-                                               int *__restrict__ gstar, float *__restrict__ qstar,
-                                               float *__restrict__ qout) {
+                                               const SampleDesc *__restrict__ descs) {
     const Item it = items[blockIdx.x];
+    const SampleDesc &D = descs[it.s];
+    if (!D.jstar) return;
+    const SinkCtl *ctl = D.ctl;
+    const SinkParams p = D.sp;
+    const double eps = ctl->eps, g0 = ctl->g0[ctl->final_state & 1];
     const int i = it.r0 + static_cast<int>(threadIdx.x);
     const bool act = i < it.r1;
     const double kexp = 1.4426950408889634 / eps;
     const float kx = static_cast<float>(kexp);
     const float K = p.twoD2 * kx;
-    const float p1 = act ? P1[i] : 0.0f, p2 = act ? P2[i] : 0.0f, f = act ? F[i] : 0.0f;
+    const float p1 = act ? D.p1[i] : 0.0f, p2 = act ? D.p2[i] : 0.0f, f = act ? D.f[i] : 0.0f;
     const float fk = f * kx;
     float best = -INFINITY;
     int arg = -1;
     for (int j = it.c0; j < it.c1; ++j) {
-        const Col8 c = cols[j];
-        float e = entry_exponent(p1, p2, c.s1, c.s2, c.v1, c.v2, c.vv, c.vv2, K, fmaf(G[j], kx, fk));
+        const Col8 c = D.colsE[j];
+        float e = entry_exponent(p1, p2, c.s1, c.s2, c.v1, c.v2, c.vv, c.vv2, K, fmaf(D.g[j], kx, fk));
         if (e > best) {
             best = e;
             arg = j;
@@ -336,18 +389,20 @@ __global__ __launch_bounds__(64) void k_assign(const Item *__restrict__ items,
     const double eb = (g0 - p.c_out) * kexp + static_cast<double>(fk);
     const float qo = static_cast<float>(exp2(eb));
     const float qb = arg >= 0 ? fast_exp2(best) : 0.0f;
-    if (jstar) jstar[i] = (arg >= 0 && qb >= qo) ? arg : -1;
-    if (gstar) gstar[i] = (arg >= 0 && qb >= qo) ? mgrain[arg] : -1;
-    if (qstar) qstar[i] = (arg >= 0 && qb >= qo) ? qb : qo;
-    if (qout) qout[i] = qo;
+    const bool m = arg >= 0 && qb >= qo;
+    D.jstar[i] = m ? arg : -1;
+    D.gstar[i] = m ? D.mgrain[arg] : -1;
+    D.qstar[i] = m ? qb : qo;
+    D.qout[i] = qo;
 }
 
 // ---------------------------------------------------------------- M-step
 
 // Per model spot (lane), stream the block's detected spots: the E-step plan
-// weight Q_ij (from colsE) and the residual geometry at the current grains
-// (colsC).  In the detector frame, with d = v + (p - s), tau = |d|,
-// rhat = d / tau and P = I - rhat rhat^T, accumulate
+// weight Q_ij (from colsE, at the sample's current temperature) and the
+// residual geometry at the current grains (colsC when cur_c, else colsE).
+// In the detector frame, with d = v + (p - s), tau = |d|, rhat = d / tau and
+// P = I - rhat rhat^T, accumulate
 //   S0 = sum Q, e = sum Q (rhat - r), A = sum Q P / tau^2, B = sum Q P / tau
 // (rhat - r is formed as ((p - s) - r delta) / tau with
 // delta = |d| - |v| = (2 v.(p-s) + |p-s|^2) / (|d| + |v|), free of
@@ -356,26 +411,27 @@ __global__ __launch_bounds__(64) void k_assign(const Item *__restrict__ items,
 //   H_ww = D^2 S0 K^T K, H_xx = D^2 Gt^T A Gt, H_xw = D^2 Gt^T B K,
 //   g_w = -D^2 K^T e,    g_x = D^2 Gt^T B r,
 // with K = 2 (u e^T + (u.e) I) Gt [R w]_x the rotation Jacobian of the ray.
-__global__ __launch_bounds__(64) void k_mstep_acc(
-    const Item *__restrict__ items, const float *__restrict__ P1, const float *__restrict__ P2,
-    const float *__restrict__ F, const float *__restrict__ G, const Col8 *__restrict__ colsE,
-    const Col8 *__restrict__ colsC, const GeomF *__restrict__ Gp, const float *__restrict__ W,
-    int n_planes, const GrainF *__restrict__ grains, int n_grains, const int *__restrict__ mplane,
-    const int *__restrict__ mgrain, const int *__restrict__ mblock, float kx, float K, double D2,
-    double *__restrict__ colHg) {
+__global__ __launch_bounds__(64) void k_mstep_acc(const Item *__restrict__ items,
+                                                  const SampleDesc *__restrict__ descs, int cur_c) {
     const Item it = items[blockIdx.x];
+    const SampleDesc &D = descs[it.s];
+    const float *__restrict__ P1 = D.p1;
+    const float *__restrict__ P2 = D.p2;
+    const float *__restrict__ F = D.f;
+    const float kx = static_cast<float>(D.ctl->kexp);
+    const float K = D.sp.twoD2 * kx;
     const int j = it.c0 + static_cast<int>(threadIdx.x);
     const bool act = j < it.c1;
     Col8 cE = {0, 0, 0, 0, 1, 1, 1, 0}, cC = {0, 0, 0, 0, 1, 1, 1, 0};
     float g = 0.0f;
     if (act) {
-        cE = colsE[j];
-        cC = colsC[j];
-        g = G[j];
+        cE = D.colsE[j];
+        cC = cur_c ? D.colsC[j] : cE;
+        g = D.g[j];
     }
     const float gk = g * kx;
-    const float vlen = sqrtf(cC.vv);
-    const float ivl = 1.0f / vlen;
+    const float ivl = __builtin_amdgcn_rsqf(cC.vv);
+    const float vlen = cC.vv * ivl;
     const float rn = cC.vn * ivl, r1 = cC.v1 * ivl, r2 = cC.v2 * ivl;
     double s64[kStat];
     for (int k = 0; k < kStat; ++k) s64[k] = 0.0;
@@ -392,22 +448,24 @@ __global__ __launch_bounds__(64) void k_mstep_acc(
         for (int k = 0; k < kStat; ++k) s64[k] += static_cast<double>(a[k]);
     }
     if (!act) return;
-    column_normal_equations(*Gp, W, n_planes, grains, n_grains, mplane[j], mgrain[j], mblock[j],
-                            s64, rn, r1, r2, D2, colHg + static_cast<int64_t>(j) * kHg);
+    column_normal_equations(*D.geom, D.W, D.n_planes, D.grains, D.n_grains, D.mplane[j], D.mgrain[j],
+                            D.mblock[j], s64, rn, r1, r2, D.D2, D.colHg + static_cast<int64_t>(j) * kHg);
 }
 
-// One wave per grain: sum its columns' contributions (per block, the grain's
-// columns are one contiguous run found by binary search), then lane 0 solves
+// One wave per grain of any sample (gbase: grain offsets of the samples):
+// sum its columns' contributions (per block, the grain's columns are one
+// contiguous run found by binary search), then lane 0 solves
 // (H + mu I) step = -g by Cholesky in FP64 and applies the step.
-__global__ __launch_bounds__(64) void k_mstep_solve(
-    const double *__restrict__ colHg, const int *__restrict__ mgrain,
-    const int64_t *__restrict__ mboff, int n_blocks, double mu_rel, double *q, double *x,
-    GrainF *__restrict__ gf, double *__restrict__ step_norm) {
-    const int n = blockIdx.x;
+__global__ __launch_bounds__(64) void k_mstep_solve(const SampleDesc *__restrict__ descs, int n_samples,
+                                                    const int64_t *__restrict__ gbase) {
+    const int s = sample_of(gbase, n_samples, blockIdx.x);
+    const SampleDesc &D = descs[s];
+    const int n = static_cast<int>(blockIdx.x - gbase[s]);
+    const int *__restrict__ mgrain = D.mgrain;
     double acc[kHg];
     for (int k = 0; k < kHg; ++k) acc[k] = 0.0;
-    for (int b = threadIdx.x; b < n_blocks; b += 64) {
-        int64_t lo = mboff[b], hi = mboff[b + 1];
+    for (int b = threadIdx.x; b < D.nb; b += 64) {
+        int64_t lo = D.mboff[b], hi = D.mboff[b + 1];
         int64_t a = lo, e = hi;
         while (a < e) {
             int64_t mid = (a + e) >> 1;
@@ -420,37 +478,99 @@ __global__ __launch_bounds__(64) void k_mstep_solve(
             if (mgrain[mid] <= n) z = mid + 1; else e = mid;
         }
         for (int64_t j = a; j < z; ++j)
-            for (int k = 0; k < kHg; ++k) acc[k] += colHg[j * kHg + k];
+            for (int k = 0; k < kHg; ++k) acc[k] += D.colHg[j * kHg + k];
     }
     for (int k = 0; k < kHg; ++k) acc[k] = wave_sum(acc[k]);
     if (threadIdx.x != 0) return;
-    gn_solve_apply(acc, mu_rel, q + 4 * n, x + 3 * n, gf + n, step_norm ? step_norm + n : nullptr);
+    gn_solve_apply(acc, D.mu_rel, D.q + 4 * n, D.x + 3 * n, D.grains + n,
+                   D.step_norm ? D.step_norm + n : nullptr);
+}
+
+// ---------------------------------------------------------------- forward model
+
+// FP32 grains of all samples from their FP64 quaternions and positions.
+__global__ void k_grain_prep_b(const SampleDesc *__restrict__ descs, int n_samples,
+                               const int64_t *__restrict__ gbase) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= gbase[n_samples]) return;
+    const int s = sample_of(gbase, n_samples, i);
+    const SampleDesc &D = descs[s];
+    const int64_t n = i - gbase[s];
+    D.grains[n] = grain_f32(D.q + 4 * n, D.x + 3 * n);
+}
+
+// Forward model on the frozen model-spot lists of all samples (mbase: model
+// offsets of the samples): the model arrays (when present) and the packed
+// columns colsE (to_c = 0) or colsC (to_c = 1).
+__global__ void k_eval_b(const SampleDesc *__restrict__ descs, int n_samples, const int64_t *__restrict__ mbase,
+                         int to_c, int with_outputs) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= mbase[n_samples]) return;
+    const int s = sample_of(mbase, n_samples, i);
+    const SampleDesc &D = descs[s];
+    const int64_t j = i - mbase[s];
+    const GeomF &G = *D.geom;
+    Col8 *cols = to_c ? D.colsC : D.colsE;
+    const int m = D.mplane[j], g = D.mgrain[j], b = D.mblock[j];
+    if (m < 0 || m >= D.n_planes || g < 0 || g >= D.n_grains || b < 0 || b >= G.n_rot * G.n_det) {
+        // invalid ids: no geometry (NaN) rather than an out-of-bounds read
+        const float nan = __builtin_nanf("");
+        if (with_outputs && D.s1) { D.s1[j] = nan; D.s2[j] = nan; D.vn[j] = nan; D.v1[j] = nan; D.v2[j] = nan; }
+        if (with_outputs && D.lam) D.lam[j] = nan;
+        cols[j] = Col8{nan, nan, nan, nan, nan, nan, nan, 0.0f};
+        return;
+    }
+    const int t = b / G.n_det, d = b - t * G.n_det;
+    const GrainF &gr = D.grains[g];
+    const SpotGeo o = spot_geometry(G, G.det[d], gr.R, gr.x, G.cs[t][0], G.cs[t][1], D.W[3 * m],
+                                    D.W[3 * m + 1], D.W[3 * m + 2], D.Dsp[m]);
+    if (with_outputs && D.s1) {
+        D.s1[j] = o.s1;
+        D.s2[j] = o.s2;
+        D.vn[j] = o.vn;
+        D.v1[j] = o.v1;
+        D.v2[j] = o.v2;
+    }
+    if (with_outputs && D.lam) D.lam[j] = o.lam;
+    Col8 c;
+    c.s1 = o.s1;
+    c.s2 = o.s2;
+    c.v1 = o.v1;
+    c.v2 = o.v2;
+    c.vv = fmaf(o.v2, o.v2, fmaf(o.v1, o.v1, o.vn * o.vn));
+    c.vv2 = c.vv * c.vv;
+    c.vn = o.vn;
+    c.pad = 0.0f;
+    cols[j] = c;
 }
 
 // ---------------------------------------------------------------- host side
 
-struct Plan {
+struct SamplePlan {
     std::vector<Item> rows, cols;
     int64_t entries = 0;   // sum_b I_b J_b
 };
 
-static Plan make_plan(const int64_t *ob, const int64_t *mb, int nb) {
-    Plan p;
+static SamplePlan make_plan(const int64_t *ob, const int64_t *mb, int nb, int s) {
+    SamplePlan p;
     for (int b = 0; b < nb; ++b) {
         int r0 = static_cast<int>(ob[b]), r1 = static_cast<int>(ob[b + 1]);
         int c0 = static_cast<int>(mb[b]), c1 = static_cast<int>(mb[b + 1]);
         p.entries += static_cast<int64_t>(r1 - r0) * (c1 - c0);
-        for (int r = r0; r < r1; r += 64) p.rows.push_back({r, std::min(r + 64, r1), c0, c1});
-        for (int c = c0; c < c1; c += 64) p.cols.push_back({r0, r1, c, std::min(c + 64, c1)});
+        for (int r = r0; r < r1; r += 64) p.rows.push_back({r, std::min(r + 64, r1), c0, c1, s, 0, {0, 0}});
+        for (int c = c0; c < c1; c += 64) p.cols.push_back({r0, r1, c, std::min(c + 64, c1), s, 0, {0, 0}});
     }
-    // the passes always launch at least one (possibly empty) workgroup
-    if (p.rows.empty()) p.rows.push_back({0, 0, 0, 0});
-    if (p.cols.empty()) p.cols.push_back({0, 0, 0, 0});
+    // a pass always has at least one (possibly empty) workgroup per sample:
+    // the last one finalises the sample's bins
+    if (p.rows.empty()) p.rows.push_back({0, 0, 0, 0, s, 0, {0, 0}});
+    if (p.cols.empty()) p.cols.push_back({0, 0, 0, 0, s, 0, {0, 0}});
     // heaviest items first so the tail of the grid is short
     std::stable_sort(p.rows.begin(), p.rows.end(),
                      [](const Item &a, const Item &b) { return (a.c1 - a.c0) > (b.c1 - b.c0); });
     std::stable_sort(p.cols.begin(), p.cols.end(),
                      [](const Item &a, const Item &b) { return (a.r1 - a.r0) > (b.r1 - b.r0); });
+    for (size_t k = 0; k < p.rows.size(); ++k) p.rows[k].local = static_cast<int>(k);
+    for (size_t k = 0; k < p.cols.size(); ++k) p.cols[k].local = static_cast<int>(k);
     return p;
 }
 
@@ -458,10 +578,14 @@ static size_t n_items_max(int64_t n_obs, int64_t n_model, int nb) {
     return static_cast<size_t>((n_obs + 63) / 64 + (n_model + 63) / 64 + 2 * nb + 1);
 }
 
-struct EmWs {
-    SinkCtl *ctl;
+struct SampleDims {
+    const laue_geometry *geom;
+    int64_t n_obs, n_model;
+    int n_grains;
+};
+
+struct SampleWs {
     double2 *part;
-    Item *rows, *cols;
     float *F1;
     Col8 *colsE, *colsC;
     double *colHg;
@@ -470,21 +594,39 @@ struct EmWs {
     int64_t *mboff;
 };
 
-static size_t carve_em(Carver &cv, EmWs &w, const laue_geometry *g, int64_t n_obs, int64_t n_model,
-                       int n_grains) {
-    const int nb = g->n_rot * g->n_det;
-    const size_t ni = n_items_max(n_obs, n_model, nb);
-    w.ctl = cv.take<SinkCtl>(1);
-    w.part = cv.take<double2>(ni);
-    w.rows = cv.take<Item>(ni);
-    w.cols = cv.take<Item>(ni);
-    w.F1 = cv.take<float>(std::max<int64_t>(n_obs, 1));
-    w.colsE = cv.take<Col8>(std::max<int64_t>(n_model, 1));
-    w.colsC = cv.take<Col8>(std::max<int64_t>(n_model, 1));
-    w.colHg = cv.take<double>(std::max<int64_t>(n_model, 1) * kHg);
-    w.geom = cv.take<GeomF>(1);
-    w.grains = cv.take<GrainF>(std::max(n_grains, 1));
-    w.mboff = cv.take<int64_t>(nb + 1);
+struct BatchWs {
+    SampleDesc *desc;
+    SinkCtl *ctl;
+    Item *rows, *cols;
+    int64_t *mbase, *gbase;
+    CtlInit *init;
+};
+
+static size_t carve_all(Carver &cv, BatchWs &bw, std::vector<SampleWs> &sw, const std::vector<SampleDims> &dims) {
+    const int n = static_cast<int>(dims.size());
+    size_t items = 0;
+    for (const SampleDims &d : dims) items += n_items_max(d.n_obs, d.n_model, d.geom->n_rot * d.geom->n_det);
+    bw.desc = cv.take<SampleDesc>(std::max(n, 1));
+    bw.ctl = cv.take<SinkCtl>(std::max(n, 1));
+    bw.rows = cv.take<Item>(std::max<size_t>(items, 1));
+    bw.cols = cv.take<Item>(std::max<size_t>(items, 1));
+    bw.mbase = cv.take<int64_t>(n + 1);
+    bw.gbase = cv.take<int64_t>(n + 1);
+    bw.init = cv.take<CtlInit>(std::max(n, 1));
+    sw.resize(n);
+    for (int s = 0; s < n; ++s) {
+        const SampleDims &d = dims[s];
+        const int nb = d.geom->n_rot * d.geom->n_det;
+        SampleWs &w = sw[s];
+        w.part = cv.take<double2>(n_items_max(d.n_obs, d.n_model, nb));
+        w.F1 = cv.take<float>(std::max<int64_t>(d.n_obs, 1));
+        w.colsE = cv.take<Col8>(std::max<int64_t>(d.n_model, 1));
+        w.colsC = cv.take<Col8>(std::max<int64_t>(d.n_model, 1));
+        w.colHg = cv.take<double>(std::max<int64_t>(d.n_model, 1) * kHg);
+        w.geom = cv.take<GeomF>(1);
+        w.grains = cv.take<GrainF>(std::max(d.n_grains, 1));
+        w.mboff = cv.take<int64_t>(nb + 1);
+    }
     return cv.size();
 }
 
@@ -527,22 +669,50 @@ static int validate_ot(const laue_ot_params *p, bool need_eps) {
     return LAUE_OK;
 }
 
-// A prepared E/M-step problem on one stream.
-struct Engine {
-    hipStream_t s;
-    EmWs w;
-    Plan plan;
-    SinkParams sp;
+static int validate_em_params(const laue_em_params *par) {
+    int rc;
+    LAUE_REQUIRE(par != nullptr, LAUE_EINVAL, "EM parameters are NULL");
+    if ((rc = validate_ot(&par->ot, false))) return rc;
+    LAUE_REQUIRE(par->n_stages >= 1 && par->iters_per_stage >= 1 && std::isfinite(par->eps_start) &&
+                     std::isfinite(par->eps_end) && par->eps_start > 0 && par->eps_end > 0,
+                 LAUE_EINVAL, "bad temperature schedule");
+    LAUE_REQUIRE(par->gn.k_gn >= 0 && std::isfinite(par->gn.mu_rel) && par->gn.mu_rel >= 0,
+                 LAUE_EINVAL, "bad Gauss-Newton parameters");
+    return LAUE_OK;
+}
+
+// One sample's inputs to the engine.
+struct SampleIn {
+    const laue_geometry *geom;
+    const laue_planes *planes;     // may be NULL (Sinkhorn only)
     const laue_obs_spots *obs;
     laue_model_spots *model;
-    int nb;
-    int64_t sink_entries = 0;
-    // GPU time of the Sinkhorn passes and M-step passes (HIP events)
+    const laue_ot_params *ot;
+    laue_grains *grains;           // may be NULL (Sinkhorn only)
+    laue_potentials *pot;
+    double mu_rel;
+    laue_assignments *assign;      // may be NULL
+    double *step_norm;             // may be NULL
+};
+
+// E- and M-steps of one or more samples on one stream: one launch per pass.
+struct BatchEngine {
+    hipStream_t s = nullptr;
+    int n = 0;
+    BatchWs bw{};
+    std::vector<SampleWs> sw;
+    std::vector<SampleIn> in;
+    std::vector<SampleDesc> hd;
+    std::vector<SamplePlan> plans;
+    std::vector<int64_t> mbase, gbase;
+    int n_rows = 0, n_cols = 0;
+    // per sample: streamed entries, Sinkhorn passes and their entries, M-step entries
+    std::vector<int64_t> entries, passes, pass_entries, m_entries;
+    std::vector<SinkCtl> hctl;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     double sink_ms = 0.0, mstep_ms = 0.0;
-    int64_t sink_passes = 0, sink_pass_entries = 0, mstep_entries = 0;
 
-    ~Engine() {
+    ~BatchEngine() {
         if (ev0) (void)hipEventDestroy(ev0);
         if (ev1) (void)hipEventDestroy(ev1);
     }
@@ -565,149 +735,303 @@ struct Engine {
         return LAUE_OK;
     }
 
-    int upload(const laue_geometry *geom, const laue_ot_params *par) {
-        plan = make_plan(obs->block_off, model->block_off, nb);
-        std::vector<Item> rows = plan.rows, cols = plan.cols;
-        if (!rows.empty())
-            LAUE_CHECK_HIP(hipMemcpyAsync(w.rows, rows.data(), rows.size() * sizeof(Item),
+    int setup(const std::vector<SampleIn> &samples, void *ws, size_t ws_bytes, void *stream, bool need_geo) {
+        int rc;
+        in = samples;
+        n = static_cast<int>(in.size());
+        std::vector<SampleDims> dims(n);
+        for (int k = 0; k < n; ++k) {
+            const SampleIn &a = in[k];
+            if ((rc = validate_geometry(a.geom))) return rc;
+            const int nb = a.geom->n_rot * a.geom->n_det;
+            if ((rc = validate_obs(a.obs, nb)) || (rc = validate_model(a.model, nb, need_geo))) return rc;
+            const double t_a = a.ot->t_b + static_cast<double>(a.obs->n) - static_cast<double>(a.model->n);
+            LAUE_REQUIRE(t_a >= 0, LAUE_EINFEASIBLE,
+                         "infeasible masses: T_a = T_b + |I| - |J| = " + std::to_string(t_a) + " < 0");
+            LAUE_REQUIRE(a.pot != nullptr, LAUE_EINVAL, "potentials are NULL");
+            LAUE_REQUIRE(a.obs->n == 0 || a.pot->f, LAUE_EINVAL, "f is NULL");
+            LAUE_REQUIRE(a.model->n == 0 || a.pot->g, LAUE_EINVAL, "g is NULL");
+            dims[k] = SampleDims{a.geom, a.obs->n, a.model->n, a.grains ? a.grains->n : 0};
+        }
+        Carver cv(ws);
+        const size_t need = carve_all(cv, bw, sw, dims);
+        if ((rc = check_ws(ws, ws_bytes, need))) return rc;
+        s = static_cast<hipStream_t>(stream);
+        std::vector<Item> rows, cols;
+        hd.assign(n, SampleDesc{});
+        plans.resize(n);
+        mbase.assign(n + 1, 0);
+        gbase.assign(n + 1, 0);
+        entries.assign(n, 0);
+        passes.assign(n, 0);
+        pass_entries.assign(n, 0);
+        m_entries.assign(n, 0);
+        for (int k = 0; k < n; ++k) {
+            const SampleIn &a = in[k];
+            const int nb = a.geom->n_rot * a.geom->n_det;
+            plans[k] = make_plan(a.obs->block_off, a.model->block_off, nb, k);
+            rows.insert(rows.end(), plans[k].rows.begin(), plans[k].rows.end());
+            cols.insert(cols.end(), plans[k].cols.begin(), plans[k].cols.end());
+            SampleDesc &D = hd[k];
+            D.p1 = a.obs->p1;
+            D.p2 = a.obs->p2;
+            D.f = a.pot->f;
+            D.f1 = sw[k].F1;
+            D.g = a.pot->g;
+            D.colsE = sw[k].colsE;
+            D.colsC = sw[k].colsC;
+            D.ctl = bw.ctl + k;
+            D.part = sw[k].part;
+            D.n_row_items = static_cast<int>(plans[k].rows.size());
+            D.n_col_items = static_cast<int>(plans[k].cols.size());
+            SinkParams &sp = D.sp;
+            sp.c_out = a.ot->c_out;
+            sp.c_unm = a.ot->c_unm;
+            sp.c_sink = a.ot->c_sink;
+            sp.t_b = a.ot->t_b;
+            sp.t_a = a.ot->t_b + static_cast<double>(a.obs->n) - static_cast<double>(a.model->n);
+            sp.tol = a.ot->tol;
+            sp.twoD2 = static_cast<float>(2.0 * a.ot->distance * a.ot->distance);
+            sp.n_max = a.ot->n_max;
+            D.mplane = a.model->plane;
+            D.mgrain = a.model->grain;
+            D.mblock = a.model->block;
+            D.s1 = a.model->s1;
+            D.s2 = a.model->s2;
+            D.vn = a.model->vn;
+            D.v1 = a.model->v1;
+            D.v2 = a.model->v2;
+            D.lam = a.model->lam;
+            D.mboff = sw[k].mboff;
+            D.n_obs = a.obs->n;
+            D.n_model = a.model->n;
+            D.nb = nb;
+            D.n_grains = a.grains ? a.grains->n : 0;
+            D.n_planes = a.planes ? a.planes->n : 0;
+            D.geom = sw[k].geom;
+            D.grains = sw[k].grains;
+            D.q = a.grains ? a.grains->q : nullptr;
+            D.x = a.grains ? a.grains->x : nullptr;
+            D.colHg = sw[k].colHg;
+            D.step_norm = a.step_norm;
+            D.W = a.planes ? a.planes->w : nullptr;
+            D.Dsp = a.planes ? a.planes->d : nullptr;
+            D.D2 = a.ot->distance * a.ot->distance;
+            D.mu_rel = a.mu_rel;
+            if (a.assign && a.assign->j_star && a.assign->grain && a.assign->q_star && a.assign->q_out) {
+                D.jstar = a.assign->j_star;
+                D.gstar = a.assign->grain;
+                D.qstar = a.assign->q_star;
+                D.qout = a.assign->q_out;
+            }
+            mbase[k + 1] = mbase[k] + a.model->n;
+            gbase[k + 1] = gbase[k] + D.n_grains;
+            GeomF hg;
+            make_geomf(a.geom, &hg);
+            LAUE_CHECK_HIP(hipMemcpyAsync(sw[k].geom, &hg, sizeof(GeomF), hipMemcpyHostToDevice, s));
+            LAUE_CHECK_HIP(hipMemcpyAsync(sw[k].mboff, a.model->block_off, (nb + 1) * sizeof(int64_t),
                                           hipMemcpyHostToDevice, s));
-        if (!cols.empty())
-            LAUE_CHECK_HIP(hipMemcpyAsync(w.cols, cols.data(), cols.size() * sizeof(Item),
-                                          hipMemcpyHostToDevice, s));
-        LAUE_CHECK_HIP(hipMemcpyAsync(w.mboff, model->block_off, (nb + 1) * sizeof(int64_t),
-                                      hipMemcpyHostToDevice, s));
-        GeomF hg;
-        make_geomf(geom, &hg);
-        LAUE_CHECK_HIP(hipMemcpyAsync(w.geom, &hg, sizeof(GeomF), hipMemcpyHostToDevice, s));
+        }
+        // heaviest items first across the batch
+        std::stable_sort(rows.begin(), rows.end(),
+                         [](const Item &a, const Item &b) { return (a.c1 - a.c0) > (b.c1 - b.c0); });
+        std::stable_sort(cols.begin(), cols.end(),
+                         [](const Item &a, const Item &b) { return (a.r1 - a.r0) > (b.r1 - b.r0); });
+        n_rows = static_cast<int>(rows.size());
+        n_cols = static_cast<int>(cols.size());
+        LAUE_CHECK_HIP(hipMemcpyAsync(bw.rows, rows.data(), rows.size() * sizeof(Item), hipMemcpyHostToDevice, s));
+        LAUE_CHECK_HIP(hipMemcpyAsync(bw.cols, cols.data(), cols.size() * sizeof(Item), hipMemcpyHostToDevice, s));
+        LAUE_CHECK_HIP(hipMemcpyAsync(bw.desc, hd.data(), n * sizeof(SampleDesc), hipMemcpyHostToDevice, s));
+        LAUE_CHECK_HIP(hipMemcpyAsync(bw.mbase, mbase.data(), (n + 1) * sizeof(int64_t), hipMemcpyHostToDevice, s));
+        LAUE_CHECK_HIP(hipMemcpyAsync(bw.gbase, gbase.data(), (n + 1) * sizeof(int64_t), hipMemcpyHostToDevice, s));
         LAUE_CHECK_HIP(hipStreamSynchronize(s));
-        sp.c_out = par->c_out;
-        sp.c_unm = par->c_unm;
-        sp.c_sink = par->c_sink;
-        sp.t_b = par->t_b;
-        sp.t_a = par->t_b + static_cast<double>(obs->n) - static_cast<double>(model->n);
-        sp.tol = par->tol;
-        sp.twoD2 = static_cast<float>(2.0 * par->distance * par->distance);
-        sp.n_max = par->n_max;
+        hctl.assign(n, SinkCtl{});
         return LAUE_OK;
     }
 
-    // Sinkhorn from (f, g, f0, g0) at temperature eps on the packed columns.
-    int sinkhorn(double eps, int chunk, laue_potentials *pot, laue_ot_stats *st) {
-        const int nrow = static_cast<int>(plan.rows.size());
-        const int ncol = static_cast<int>(plan.cols.size());
-        double g0_in = sp.t_a > 0 ? pot->g0 : -INFINITY;
-        double f0_in = sp.t_b > 0 ? pot->f0 : -INFINITY;
-        k_ctl_init<<<1, 1, 0, s>>>(w.ctl, f0_in, g0_in, eps);
+    int grain_prep() {
+        if (gbase[n] == 0) return LAUE_OK;
+        k_grain_prep_b<<<static_cast<unsigned>((gbase[n] + 255) / 256), 256, 0, s>>>(bw.desc, n, bw.gbase);
         LAUE_CHECK_HIP(hipGetLastError());
-        if (model->n > 0) {
-            int nwg = static_cast<int>(std::min<int64_t>((model->n + 63) / 64, 1024));
-            k_cs_init<<<nwg, 64, 0, s>>>(pot->g, model->n, w.ctl, reinterpret_cast<double *>(w.part), sp);
-            LAUE_CHECK_HIP(hipGetLastError());
+        return LAUE_OK;
+    }
+
+    int eval(int to_c, int with_outputs) {
+        if (mbase[n] == 0) return LAUE_OK;
+        k_eval_b<<<static_cast<unsigned>((mbase[n] + 255) / 256), 256, 0, s>>>(bw.desc, n, bw.mbase, to_c,
+                                                                               with_outputs);
+        LAUE_CHECK_HIP(hipGetLastError());
+        return LAUE_OK;
+    }
+
+    // control blocks at temperature eps[k] from the potentials' bins
+    int init_ctl(const std::vector<double> &eps) {
+        std::vector<CtlInit> v(n);
+        for (int k = 0; k < n; ++k) {
+            const SinkParams &sp = hd[k].sp;
+            v[k] = CtlInit{sp.t_b > 0 ? in[k].pot->f0 : -INFINITY, sp.t_a > 0 ? in[k].pot->g0 : -INFINITY, eps[k]};
         }
+        LAUE_CHECK_HIP(hipMemcpyAsync(bw.init, v.data(), n * sizeof(CtlInit), hipMemcpyHostToDevice, s));
+        k_ctl_init<<<(n + 63) / 64, 64, 0, s>>>(bw.desc, n, bw.init);
+        LAUE_CHECK_HIP(hipGetLastError());
+        // the host copy must outlive the asynchronous copy
+        LAUE_CHECK_HIP(hipStreamSynchronize(s));
+        return LAUE_OK;
+    }
+
+    // Sinkhorn of every sample from its potentials at temperature eps[k].
+    int sinkhorn(const std::vector<double> &eps, int chunk, std::vector<laue_ot_stats> &st) {
+        int rc;
+        if ((rc = init_ctl(eps))) return rc;
+        k_cs_init<<<n, 256, 0, s>>>(bw.desc);
+        LAUE_CHECK_HIP(hipGetLastError());
         if (chunk <= 0) chunk = 16;
-        SinkCtl h{};
+        int cap = 0;
+        for (int k = 0; k < n; ++k) cap = std::max(cap, hd[k].sp.n_max);
         int launched = 0;
         for (;;) {
-            int rc = timer_start();
-            if (rc) return rc;
-            for (int c = 0; c < chunk && launched < sp.n_max + 1; ++c, ++launched) {
-                k_row<<<nrow, 64, 0, s>>>(w.rows, obs->p1, obs->p2, w.colsE, pot->g, pot->f,
-                                          w.F1, w.ctl, w.part, sp);
-                k_col<<<ncol, 64, 0, s>>>(w.cols, obs->p1, obs->p2, w.colsE, pot->g, pot->f,
-                                          w.F1, w.ctl, w.part, sp);
+            if ((rc = timer_start())) return rc;
+            for (int c = 0; c < chunk && launched < cap + 1; ++c, ++launched) {
+                k_row<<<n_rows, 64, 0, s>>>(bw.rows, bw.desc);
+                k_col<<<n_cols, 64, 0, s>>>(bw.cols, bw.desc);
             }
             LAUE_CHECK_HIP(hipGetLastError());
             if ((rc = timer_stop(&sink_ms))) return rc;
-            LAUE_CHECK_HIP(hipMemcpyAsync(&h, w.ctl, sizeof(SinkCtl), hipMemcpyDeviceToHost, s));
+            LAUE_CHECK_HIP(hipMemcpyAsync(hctl.data(), bw.ctl, n * sizeof(SinkCtl), hipMemcpyDeviceToHost, s));
             LAUE_CHECK_HIP(hipStreamSynchronize(s));
-            if (h.done) break;
-            if (launched >= sp.n_max + 1) {
+            bool all = true;
+            for (int k = 0; k < n; ++k) all = all && hctl[k].done;
+            if (all) break;
+            if (launched >= cap + 1) {
                 set_error("internal: Sinkhorn did not stop at its cap");
                 return LAUE_EDEVICE;
             }
         }
-        const int fin = h.final_state;
-        if (fin & 1)
-            LAUE_CHECK_HIP(hipMemcpyAsync(pot->f, w.F1, obs->n * sizeof(float),
-                                          hipMemcpyDeviceToDevice, s));
-        pot->f0 = h.f0[fin & 1];
-        pot->g0 = h.g0[fin & 1];
-        st->n_iter = fin;
-        st->converged = h.converged;
-        st->err = h.err;
-        sink_entries += plan.entries * (2 * static_cast<int64_t>(fin) + 1);
-        sink_passes += 2 * static_cast<int64_t>(fin) + 1;
-        sink_pass_entries += plan.entries * (2 * static_cast<int64_t>(fin) + 1);
+        st.assign(n, laue_ot_stats{});
+        for (int k = 0; k < n; ++k) {
+            const SinkCtl &h = hctl[k];
+            const int fin = h.final_state;
+            laue_potentials *pot = in[k].pot;
+            if ((fin & 1) && in[k].obs->n > 0)
+                LAUE_CHECK_HIP(hipMemcpyAsync(pot->f, sw[k].F1, in[k].obs->n * sizeof(float),
+                                              hipMemcpyDeviceToDevice, s));
+            pot->f0 = h.f0[fin & 1];
+            pot->g0 = h.g0[fin & 1];
+            st[k].n_iter = fin;
+            st[k].converged = h.converged;
+            st[k].err = h.err;
+            const int64_t np = 2 * static_cast<int64_t>(fin) + 1;
+            entries[k] += plans[k].entries * np;
+            passes[k] += np;
+            pass_entries[k] += plans[k].entries * np;
+        }
         return LAUE_OK;
     }
 
-    // k_gn Gauss-Newton steps with the plan of (pot, eps, colsE) fixed.
-    int mstep(const laue_planes *planes, laue_grains *grains, const laue_potentials *pot, double eps,
-              double distance, const laue_gn_params *gn, double *step_norm) {
-        const int ncol = static_cast<int>(plan.cols.size());
-        const float kx = static_cast<float>(1.4426950408889634 / eps);
-        const float K = sp.twoD2 * kx;
-        int trc = timer_start();
-        if (trc) return trc;
-        for (int k = 0; k < gn->k_gn; ++k) {
-            Col8 *cur = w.colsE;
-            if (k > 0) {
-                int rc = launch_eval(w.geom, planes, w.grains, grains->n, model->plane, model->grain,
-                                     model->block, model->n, nullptr, nullptr, nullptr, nullptr,
-                                     nullptr, nullptr, w.colsC, s);
-                if (rc) return rc;
-                cur = w.colsC;
-            }
-            if (model->n > 0) {
-                k_mstep_acc<<<ncol, 64, 0, s>>>(w.cols, obs->p1, obs->p2, pot->f, pot->g, w.colsE,
-                                                cur, w.geom, planes->w, planes->n, w.grains,
-                                                grains->n, model->plane, model->grain,
-                                                model->block, kx, K, distance * distance, w.colHg);
+    // k_gn Gauss-Newton steps with the plan of (potentials, eps, colsE) fixed.
+    int mstep(int k_gn) {
+        int rc;
+        if ((rc = timer_start())) return rc;
+        for (int k = 0; k < k_gn; ++k) {
+            if (k > 0 && (rc = eval(1, 0))) return rc;
+            if (mbase[n] > 0) {
+                k_mstep_acc<<<n_cols, 64, 0, s>>>(bw.cols, bw.desc, k > 0 ? 1 : 0);
                 LAUE_CHECK_HIP(hipGetLastError());
             }
-            if (grains->n > 0) {
-                k_mstep_solve<<<grains->n, 64, 0, s>>>(w.colHg, model->grain, w.mboff, nb,
-                                                       gn->mu_rel, grains->q, grains->x, w.grains,
-                                                       step_norm);
+            if (gbase[n] > 0) {
+                k_mstep_solve<<<static_cast<unsigned>(gbase[n]), 64, 0, s>>>(bw.desc, n, bw.gbase);
                 LAUE_CHECK_HIP(hipGetLastError());
             }
-            sink_entries += plan.entries;
-            mstep_entries += plan.entries;
+            for (int j = 0; j < n; ++j) {
+                entries[j] += plans[j].entries;
+                m_entries[j] += plans[j].entries;
+            }
         }
         return timer_stop(&mstep_ms);
     }
+
+    int assign() {
+        bool any = false;
+        for (int k = 0; k < n; ++k) any = any || (hd[k].jstar && in[k].obs->n > 0);
+        if (!any) return LAUE_OK;
+        k_assign<<<n_rows, 64, 0, s>>>(bw.rows, bw.desc);
+        LAUE_CHECK_HIP(hipGetLastError());
+        for (int k = 0; k < n; ++k)
+            if (hd[k].jstar) entries[k] += plans[k].entries;
+        return LAUE_OK;
+    }
 };
 
-static int setup_engine(Engine &e, const laue_geometry *geom, const laue_obs_spots *obs,
-                        laue_model_spots *model, const laue_ot_params *par, int n_grains, void *ws,
-                        size_t ws_bytes, void *stream, bool need_geo) {
+static int run_em(BatchEngine &e, const std::vector<const laue_em_params *> &par, std::vector<laue_em_stats> &stats) {
     int rc;
-    if ((rc = validate_geometry(geom))) return rc;
-    e.nb = geom->n_rot * geom->n_det;
-    if ((rc = validate_obs(obs, e.nb)) || (rc = validate_model(model, e.nb, need_geo))) return rc;
-    double t_a = par->t_b + static_cast<double>(obs->n) - static_cast<double>(model->n);
-    LAUE_REQUIRE(t_a >= 0, LAUE_EINFEASIBLE,
-                 "infeasible masses: T_a = T_b + |I| - |J| = " + std::to_string(t_a) + " < 0");
-    Carver cv(ws);
-    size_t need = carve_em(cv, e.w, geom, obs->n, model->n, n_grains);
-    if ((rc = check_ws(ws, ws_bytes, need))) return rc;
-    e.s = static_cast<hipStream_t>(stream);
-    e.obs = obs;
-    e.model = model;
-    return e.upload(geom, par);
+    const int n = e.n;
+    if ((rc = e.grain_prep())) return rc;
+    stats.assign(n, laue_em_stats{});
+    const int S = par[0]->n_stages;
+    std::vector<double> eps(n);
+    std::vector<laue_ot_stats> os;
+    for (int st = 0; st < S; ++st) {
+        for (int k = 0; k < n; ++k)
+            eps[k] = S == 1 ? par[k]->eps_start
+                            : par[k]->eps_start * std::pow(par[k]->eps_end / par[k]->eps_start,
+                                                           static_cast<double>(st) / (S - 1));
+        for (int it = 0; it < par[0]->iters_per_stage; ++it) {
+            if ((rc = e.eval(0, 1))) return rc;
+            if ((rc = e.sinkhorn(eps, par[0]->ot.chunk, os))) return rc;
+            for (int k = 0; k < n; ++k) {
+                stats[k].sinkhorn_iters += os[k].n_iter;
+                stats[k].not_converged += os[k].converged ? 0 : 1;
+                stats[k].last_err = os[k].err;
+                stats[k].n_em_iter += 1;
+            }
+            // all samples share k_gn (checked by the caller)
+            if ((rc = e.mstep(par[0]->gn.k_gn))) return rc;
+        }
+    }
+    // assignments at the final grains with the final potentials
+    if ((rc = e.eval(0, 1)) || (rc = e.assign())) return rc;
+    for (int k = 0; k < n; ++k) {
+        stats[k].cost_entries = e.entries[k];
+        stats[k].sinkhorn_ms = e.sink_ms;
+        stats[k].sinkhorn_passes = e.passes[k];
+        stats[k].sinkhorn_entries = e.pass_entries[k];
+        stats[k].mstep_ms = e.mstep_ms;
+        stats[k].mstep_entries = e.m_entries[k];
+    }
+    LAUE_CHECK_HIP(hipStreamSynchronize(e.s));
+    return LAUE_OK;
 }
 
 }  // namespace laue
 
 using namespace laue;
 
+static std::vector<SampleDims> dims_of(int n, const laue_geometry *geoms, const int64_t *n_obs, const int64_t *n_model,
+                                       const int32_t *n_grains) {
+    std::vector<SampleDims> d(n);
+    for (int k = 0; k < n; ++k) d[k] = SampleDims{geoms + k, n_obs[k], n_model[k], n_grains ? n_grains[k] : 0};
+    return d;
+}
+
 extern "C" size_t laue_sinkhorn_workspace_size(const laue_geometry *geom, int64_t n_obs,
                                                int64_t n_model, int32_t n_grains) {
     if (!geom || validate_geometry(geom) != LAUE_OK || n_obs < 0 || n_model < 0 || n_grains < 0)
         return 0;
     Carver cv(nullptr);
-    EmWs w;
-    return carve_em(cv, w, geom, n_obs, n_model, n_grains);
+    BatchWs bw;
+    std::vector<SampleWs> sw;
+    return carve_all(cv, bw, sw, dims_of(1, geom, &n_obs, &n_model, &n_grains));
+}
+
+extern "C" size_t laue_em_batched_workspace_size(int32_t n, const laue_geometry *geoms, const int64_t *n_obs,
+                                                 const int64_t *n_model, const int32_t *n_grains) {
+    if (n < 1 || !geoms || !n_obs || !n_model || !n_grains) return 0;
+    for (int k = 0; k < n; ++k)
+        if (validate_geometry(geoms + k) != LAUE_OK || n_obs[k] < 0 || n_model[k] < 0 || n_grains[k] < 0) return 0;
+    Carver cv(nullptr);
+    BatchWs bw;
+    std::vector<SampleWs> sw;
+    return carve_all(cv, bw, sw, dims_of(n, geoms, n_obs, n_model, n_grains));
 }
 
 extern "C" int laue_sinkhorn(const laue_geometry *geom, const laue_obs_spots *obs,
@@ -720,13 +1044,15 @@ extern "C" int laue_sinkhorn(const laue_geometry *geom, const laue_obs_spots *ob
     LAUE_REQUIRE(pot && stats, LAUE_EINVAL, "potentials or stats is NULL");
     LAUE_REQUIRE(std::isfinite(pot->f0) && std::isfinite(pot->g0), LAUE_EINVAL,
                  "bin potentials must be finite");
-    Engine e;
+    BatchEngine e;
     laue_model_spots *m = const_cast<laue_model_spots *>(model);
-    if ((rc = setup_engine(e, geom, obs, m, par, 0, ws, ws_bytes, stream, true))) return rc;
-    LAUE_REQUIRE(obs->n == 0 || pot->f, LAUE_EINVAL, "f is NULL");
-    LAUE_REQUIRE(model->n == 0 || pot->g, LAUE_EINVAL, "g is NULL");
-    if ((rc = launch_pack(model, e.w.colsE, e.s))) return rc;
-    if ((rc = e.sinkhorn(par->eps, par->chunk, pot, stats))) return rc;
+    if ((rc = e.setup({SampleIn{geom, nullptr, obs, m, par, nullptr, pot, 0.0, nullptr, nullptr}}, ws, ws_bytes,
+                      stream, true)))
+        return rc;
+    if ((rc = launch_pack(model, e.sw[0].colsE, e.s))) return rc;
+    std::vector<laue_ot_stats> os;
+    if ((rc = e.sinkhorn({par->eps}, par->chunk, os))) return rc;
+    *stats = os[0];
     LAUE_CHECK_HIP(hipStreamSynchronize(e.s));
     return stats->converged ? LAUE_OK : LAUE_ENOCONV;
 }
@@ -813,6 +1139,7 @@ extern "C" int laue_plan_block(const laue_geometry *geom, const laue_obs_spots *
     return LAUE_OK;
 }
 
+
 extern "C" int laue_mstep(const laue_geometry *geom, const laue_planes *planes,
                           const laue_obs_spots *obs, laue_model_spots *model,
                           const laue_ot_params *par, const laue_potentials *pot,
@@ -824,13 +1151,16 @@ extern "C" int laue_mstep(const laue_geometry *geom, const laue_planes *planes,
         return rc;
     LAUE_REQUIRE(gn && gn->k_gn >= 0 && std::isfinite(gn->mu_rel) && gn->mu_rel >= 0, LAUE_EINVAL,
                  "bad Gauss-Newton parameters");
-    LAUE_REQUIRE(pot && (obs == nullptr || obs->n == 0 || pot->f) && (model->n == 0 || pot->g),
+    LAUE_REQUIRE(pot && obs && (obs->n == 0 || pot->f) && (model == nullptr || model->n == 0 || pot->g),
                  LAUE_EINVAL, "potentials are NULL");
-    Engine e;
-    if ((rc = setup_engine(e, geom, obs, model, par, grains->n, ws, ws_bytes, stream, true))) return rc;
-    if ((rc = launch_pack(model, e.w.colsE, e.s))) return rc;
-    if ((rc = prep_grains(grains, e.w.grains, e.s))) return rc;
-    if ((rc = e.mstep(planes, grains, pot, par->eps, par->distance, gn, step_norm))) return rc;
+    LAUE_REQUIRE(std::isfinite(pot->f0) && std::isfinite(pot->g0), LAUE_EINVAL, "bin potentials must be finite");
+    BatchEngine e;
+    laue_potentials p = *pot;           // read only
+    if ((rc = e.setup({SampleIn{geom, planes, obs, model, par, grains, &p, gn->mu_rel, nullptr, step_norm}}, ws,
+                      ws_bytes, stream, true)))
+        return rc;
+    if ((rc = launch_pack(model, e.sw[0].colsE, e.s))) return rc;
+    if ((rc = e.grain_prep()) || (rc = e.init_ctl({par->eps})) || (rc = e.mstep(gn->k_gn))) return rc;
     LAUE_CHECK_HIP(hipStreamSynchronize(e.s));
     return LAUE_OK;
 }
@@ -843,62 +1173,51 @@ extern "C" int laue_em(const laue_geometry *geom, const laue_planes *planes,
     clear_error();
     int rc;
     LAUE_REQUIRE(par && stats && pot, LAUE_EINVAL, "NULL argument");
-    if ((rc = validate_ot(&par->ot, false)) || (rc = validate_planes(planes)) ||
-        (rc = validate_grains(grains)))
+    if ((rc = validate_em_params(par)) || (rc = validate_planes(planes)) || (rc = validate_grains(grains)))
         return rc;
-    LAUE_REQUIRE(par->n_stages >= 1 && par->iters_per_stage >= 1 && std::isfinite(par->eps_start) &&
-                     std::isfinite(par->eps_end) && par->eps_start > 0 && par->eps_end > 0,
-                 LAUE_EINVAL, "bad temperature schedule");
-    LAUE_REQUIRE(par->gn.k_gn >= 0 && std::isfinite(par->gn.mu_rel) && par->gn.mu_rel >= 0,
-                 LAUE_EINVAL, "bad Gauss-Newton parameters");
     LAUE_REQUIRE(std::isfinite(pot->f0) && std::isfinite(pot->g0), LAUE_EINVAL,
                  "bin potentials must be finite");
-    Engine e;
-    if ((rc = setup_engine(e, geom, obs, model, &par->ot, grains->n, ws, ws_bytes, stream, false)))
+    BatchEngine e;
+    if ((rc = e.setup({SampleIn{geom, planes, obs, model, &par->ot, grains, pot, par->gn.mu_rel, assign, nullptr}},
+                      ws, ws_bytes, stream, false)))
         return rc;
-    LAUE_REQUIRE(obs->n == 0 || pot->f, LAUE_EINVAL, "f is NULL");
-    LAUE_REQUIRE(model->n == 0 || pot->g, LAUE_EINVAL, "g is NULL");
-    if ((rc = prep_grains(grains, e.w.grains, e.s))) return rc;
-    *stats = laue_em_stats{};
-    const int S = par->n_stages;
-    for (int st = 0; st < S; ++st) {
-        const double eps = S == 1 ? par->eps_start
-                                  : par->eps_start * std::pow(par->eps_end / par->eps_start,
-                                                              static_cast<double>(st) / (S - 1));
-        for (int it = 0; it < par->iters_per_stage; ++it) {
-            rc = launch_eval(e.w.geom, planes, e.w.grains, grains->n, model->plane, model->grain, model->block,
-                             model->n, model->s1, model->s2, model->vn, model->v1, model->v2,
-                             model->lam, e.w.colsE, e.s);
-            if (rc) return rc;
-            laue_ot_stats os{};
-            if ((rc = e.sinkhorn(eps, par->ot.chunk, pot, &os))) return rc;
-            stats->sinkhorn_iters += os.n_iter;
-            stats->not_converged += os.converged ? 0 : 1;
-            stats->last_err = os.err;
-            if ((rc = e.mstep(planes, grains, pot, eps, par->ot.distance, &par->gn, nullptr))) return rc;
-            stats->n_em_iter += 1;
-        }
-    }
-    if (assign && obs->n > 0) {
-        // assignments at the final grains with the final potentials
-        const double eps_fin = par->eps_end;
-        int rc2 = launch_eval(e.w.geom, planes, e.w.grains, grains->n, model->plane, model->grain, model->block,
-                              model->n, model->s1, model->s2, model->vn, model->v1, model->v2,
-                              model->lam, e.w.colsE, e.s);
-        if (rc2) return rc2;
-        k_assign<<<static_cast<int>(e.plan.rows.size()), 64, 0, e.s>>>(
-            e.w.rows, obs->p1, obs->p2, e.w.colsE, pot->g, pot->f, model->grain, pot->g0,
-            S == 1 ? par->eps_start : eps_fin, e.sp, assign->j_star, assign->grain,
-            assign->q_star, assign->q_out);
-        LAUE_CHECK_HIP(hipGetLastError());
-        e.sink_entries += e.plan.entries;
-    }
-    stats->cost_entries = e.sink_entries;
-    stats->sinkhorn_ms = e.sink_ms;
-    stats->sinkhorn_passes = e.sink_passes;
-    stats->sinkhorn_entries = e.sink_pass_entries;
-    stats->mstep_ms = e.mstep_ms;
-    stats->mstep_entries = e.mstep_entries;
-    LAUE_CHECK_HIP(hipStreamSynchronize(e.s));
+    std::vector<laue_em_stats> st;
+    if ((rc = run_em(e, {par}, st))) return rc;
+    *stats = st[0];
     return stats->not_converged ? LAUE_ENOCONV : LAUE_OK;
+}
+
+extern "C" int laue_em_batched(int32_t n, const laue_geometry *geoms, const laue_planes *planes,
+                               const laue_obs_spots *obs, laue_model_spots *models, const laue_em_params *pars,
+                               laue_grains *grains, laue_potentials *pots, laue_assignments *assigns,
+                               laue_em_stats *stats, void *ws, size_t ws_bytes, void *stream) {
+    clear_error();
+    int rc;
+    LAUE_REQUIRE(n >= 1 && geoms && planes && obs && models && pars && grains && pots && stats, LAUE_EINVAL,
+                 "NULL argument");
+    std::vector<SampleIn> in(n);
+    std::vector<const laue_em_params *> par(n);
+    for (int k = 0; k < n; ++k) {
+        if ((rc = validate_em_params(pars + k)) || (rc = validate_planes(planes + k)) ||
+            (rc = validate_grains(grains + k)))
+            return rc;
+        LAUE_REQUIRE(pars[k].n_stages == pars[0].n_stages && pars[k].iters_per_stage == pars[0].iters_per_stage &&
+                         pars[k].gn.k_gn == pars[0].gn.k_gn,
+                     LAUE_EINVAL, "samples of a batch share n_stages, iters_per_stage and k_gn");
+        LAUE_REQUIRE(std::isfinite(pots[k].f0) && std::isfinite(pots[k].g0), LAUE_EINVAL,
+                     "bin potentials must be finite");
+        in[k] = SampleIn{geoms + k, planes + k, obs + k, models + k, &pars[k].ot, grains + k, pots + k,
+                         pars[k].gn.mu_rel, assigns ? assigns + k : nullptr, nullptr};
+        par[k] = pars + k;
+    }
+    BatchEngine e;
+    if ((rc = e.setup(in, ws, ws_bytes, stream, false))) return rc;
+    std::vector<laue_em_stats> st;
+    if ((rc = run_em(e, par, st))) return rc;
+    int nc = 0;
+    for (int k = 0; k < n; ++k) {
+        stats[k] = st[k];
+        nc += st[k].not_converged;
+    }
+    return nc ? LAUE_ENOCONV : LAUE_OK;
 }

@@ -15,14 +15,7 @@ __global__ void k_grain_prep(const double *__restrict__ q, const double *__restr
                              GrainF *__restrict__ out) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    double w = q[4 * i], a = q[4 * i + 1], b = q[4 * i + 2], c = q[4 * i + 3];
-    double nrm = sqrt(w * w + a * a + b * b + c * c);
-    w /= nrm; a /= nrm; b /= nrm; c /= nrm;
-    double R[9] = {1 - 2 * (b * b + c * c), 2 * (a * b - w * c),     2 * (a * c + w * b),
-                   2 * (a * b + w * c),     1 - 2 * (a * a + c * c), 2 * (b * c - w * a),
-                   2 * (a * c - w * b),     2 * (b * c + w * a),     1 - 2 * (a * a + b * b)};
-    for (int k = 0; k < 9; ++k) out[i].R[k] = static_cast<float>(R[k]);
-    for (int k = 0; k < 3; ++k) out[i].x[k] = static_cast<float>(x[3 * i + k]);
+    out[i] = grain_f32(q + 4 * i, x + 3 * i);
 }
 
 int prep_grains(const laue_grains *g, GrainF *dst, hipStream_t s) {

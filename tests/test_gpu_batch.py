@@ -1,0 +1,78 @@
+"""Batched EM: one launch per pass over several independent samples gives
+each sample exactly what laue_em gives it alone, and matches the oracle."""
+import dataclasses
+
+import numpy as np
+import pytest
+import torch
+
+import inputgen as ig
+from oracle import cost, em as oem, metrics, sinkhorn
+from tests import _problems
+
+pytestmark = pytest.mark.gpu
+
+
+def _sample(laue, preset, n_grains, seed_shift=0):
+    p = dataclasses.replace(preset, n_grains=n_grains)
+    geom = laue.geometry_from_preset(p)
+    planes = laue.laue_planes_cubic(p.a, p.centering, p.n_max)
+    q, x = ig.random_grains(p, seed=p.seed + seed_shift)
+    obs = laue.laue_simulate(geom, planes, laue.Grains(q, x), p.sigma_mm, p.distance, p.outlier_frac,
+                             p.seed + seed_shift)
+    q0, x0 = ig.perturb_grains(q, x, 0.5, 0.5, p.seed + 17 + seed_shift)
+    model = laue.laue_forward_enumerate(geom, planes, laue.Grains(q0, x0), True)
+    c_out = cost.c_out(p.sigma_mm, p.distance)
+    ot = laue.ot_params(p.eps_start, p.distance, c_out, sinkhorn.default_tb(model.n), tol=1e-5, n_max=2000)
+    par = laue.em_params(ot, p.eps_start, p.eps_end, 3, 2)
+    return p, geom, planes, obs, model, par, (q0, x0), (q, x)
+
+
+def test_batched_equals_sequential(gpu_lib):
+    laue = gpu_lib
+    presets = ig.batching_samples(5)
+    samples = [_sample(laue, pr, int(g), k) for k, (pr, g) in enumerate(zip(presets, (12, 30, 7, 20, 16)))]
+    # sequential, each alone
+    seq = []
+    for p, geom, planes, obs, model, par, (q0, x0), _ in samples:
+        gr = laue.Grains(q0, x0)
+        out = laue.laue_em(geom, planes, obs, model, par, gr)
+        seq.append((gr.numpy(), out))
+    # one batch
+    grains = [laue.Grains(*s[6]) for s in samples]
+    rc, outs = laue.laue_em_batched([s[1] for s in samples], [s[2] for s in samples], [s[3] for s in samples],
+                                    [s[4] for s in samples], [s[5] for s in samples], grains)
+    for k in range(len(samples)):
+        (qs, xs), o1 = seq[k]
+        qb, xb = grains[k].numpy()
+        o2 = outs[k]
+        assert np.array_equal(qs, qb) and np.array_equal(xs, xb), k
+        for key in ("f", "g", "j_star", "grain", "q_star", "q_out"):
+            assert torch.equal(o1[key][:o2[key].numel()], o2[key]), (k, key)
+        assert o1["f0"] == o2["f0"] and o1["g0"] == o2["g0"]
+        for key in ("n_em_iter", "sinkhorn_iters", "not_converged", "cost_entries", "sinkhorn_passes",
+                    "mstep_entries"):
+            assert o1[key] == o2[key], (k, key)
+
+
+def test_batched_matches_oracle(gpu_lib):
+    laue = gpu_lib
+    probs = [_problems.make(ig.TINY), _problems.make(ig.TINY, seed_shift=5, frac=0.2)]
+    args, refs = [], []
+    for P in probs:
+        p = P.preset
+        c_out = cost.c_out(p.sigma_mm, p.distance)
+        t_b = sinkhorn.default_tb(len(P.model["m"]))
+        eps_list = oem.eps_schedule(p.eps_start, p.eps_end, p.n_stages, p.iters_per_stage)
+        refs.append(oem.run(P.planes, P.geom, p.distance, P.obs["p12"], P.obs["offsets"], P.model, P.q0, P.x0,
+                            eps_list, c_out, t_b=t_b, k_gn=2, tol=1e-5, n_max=2000))
+        geom, planes, obs, model = _problems.gpu_objects(laue, P)
+        ot = laue.ot_params(p.eps_start, p.distance, c_out, t_b, tol=1e-5, n_max=2000)
+        par = laue.em_params(ot, p.eps_start, p.eps_end, p.n_stages, p.iters_per_stage, k_gn=2)
+        args.append((geom, planes, obs, model, par, laue.Grains(P.q0, P.x0)))
+    rc, outs = laue.laue_em_batched(*[list(t) for t in zip(*args)])
+    for (geom, planes, obs, model, par, gr), ref, o in zip(args, refs, outs):
+        qg, xg = gr.numpy()
+        assert np.max(np.degrees(metrics.misorientation(qg, ref["q"]))) < 0.01
+        assert np.max(np.linalg.norm(xg - ref["x"], axis=1)) < 0.01
+        assert o["n_em_iter"] == 20 and o["not_converged"] == 0
