@@ -221,7 +221,8 @@ typedef struct laue_ot_params {
                                  * 64 iterations (the rounding floor of FP32
                                  * potentials); both count as converged */
     int32_t n_max;              /* iteration cap (>= 1) */
-    int32_t chunk;              /* iterations between host polls (0: 16) */
+    int32_t chunk;              /* iterations between host polls (0: 16; in an EM, sized
+                                 * per temperature stage) */
 } laue_ot_params;
 
 /* Dual potentials: Q_ij = exp((f_i + g_j - c_ij) / eps).  f [n_obs], g
@@ -295,6 +296,12 @@ typedef struct laue_em_params {
     double eps_start, eps_end;  /* geometric schedule over n_stages stages */
     int32_t n_stages;
     int32_t iters_per_stage;
+    /* how the Sinkhorn passes are issued between host polls: 1 direct kernel
+     * launches, 2 replay of a captured hipGraph of one polling chunk, 0 tune:
+     * time both on chunks in which every pass does work and keep the faster;
+     * with ot.chunk == 0 the chunk of each temperature stage is sized from the
+     * iterations that stage needed in the previous EM iteration */
+    int32_t launch;
 } laue_em_params;
 
 typedef struct laue_em_stats {
@@ -310,6 +317,8 @@ typedef struct laue_em_stats {
     int64_t sinkhorn_entries;
     double mstep_ms;
     int64_t mstep_entries;
+    int32_t launch_used;        /* 1 direct launches, 2 graph replay */
+    int32_t polls;              /* host polls of the Sinkhorn control blocks */
 } laue_em_stats;
 
 /* Per detected spot (device, may be NULL): j_star = argmax over its block's
@@ -336,7 +345,7 @@ int laue_em(const laue_geometry *geom, const laue_planes *planes,
  * is one launch over the work of all samples; each sample keeps its own bins,
  * temperature schedule, convergence and statistics, and gets the result that
  * laue_em would give it alone.  Samples share n_stages, iters_per_stage and
- * gn.k_gn; ot.chunk of sample 0 sets the host polling interval.  assigns may
+ * gn.k_gn, launch and ot.chunk.  assigns may
  * be NULL or hold NULL arrays for some samples.  The millisecond fields of
  * every stats entry are the batch's totals.  Synchronous; LAUE_ENOCONV when
  * some Sinkhorn of some sample stopped at its cap. */

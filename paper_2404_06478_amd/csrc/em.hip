@@ -678,6 +678,7 @@ static int validate_em_params(const laue_em_params *par) {
                  LAUE_EINVAL, "bad temperature schedule");
     LAUE_REQUIRE(par->gn.k_gn >= 0 && std::isfinite(par->gn.mu_rel) && par->gn.mu_rel >= 0,
                  LAUE_EINVAL, "bad Gauss-Newton parameters");
+    LAUE_REQUIRE(par->launch >= 0 && par->launch <= 2, LAUE_EINVAL, "launch must be 0, 1 or 2");
     return LAUE_OK;
 }
 
@@ -711,10 +712,48 @@ struct BatchEngine {
     std::vector<SinkCtl> hctl;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     double sink_ms = 0.0, mstep_ms = 0.0;
+    // issuing of the Sinkhorn passes: 1 direct launches, 2 graph replay, 0 tune
+    int launch_mode = 1, chosen = 0, polls = 0;
+    double t_direct = -1.0, t_graph = -1.0;     // ms per iteration on chunks where every pass worked
+    std::vector<std::pair<int, hipGraphExec_t>> graphs;   // one captured chunk per chunk length
+    hipStream_t cap_stream = nullptr;
+    std::vector<int> stage_iters;               // iterations of the latest Sinkhorn of each stage
 
     ~BatchEngine() {
+        if (!graphs.empty()) (void)hipStreamSynchronize(s);
+        for (auto &g : graphs) (void)hipGraphExecDestroy(g.second);
+        if (cap_stream) (void)hipStreamDestroy(cap_stream);
         if (ev0) (void)hipEventDestroy(ev0);
         if (ev1) (void)hipEventDestroy(ev1);
+    }
+
+    // A captured graph of `chunk` Sinkhorn iterations (row and column pass of
+    // every sample); the passes read their state from the control blocks, so
+    // one graph serves every chunk, temperature and EM iteration of the call.
+    int graph_for(int chunk, hipGraphExec_t *out) {
+        for (auto &g : graphs)
+            if (g.first == chunk) {
+                *out = g.second;
+                return LAUE_OK;
+            }
+        if (!cap_stream) LAUE_CHECK_HIP(hipStreamCreateWithFlags(&cap_stream, hipStreamNonBlocking));
+        LAUE_CHECK_HIP(hipStreamBeginCapture(cap_stream, hipStreamCaptureModeThreadLocal));
+        for (int c = 0; c < chunk; ++c) {
+            k_row<<<n_rows, 64, 0, cap_stream>>>(bw.rows, bw.desc);
+            k_col<<<n_cols, 64, 0, cap_stream>>>(bw.cols, bw.desc);
+        }
+        const hipError_t le = hipGetLastError();
+        hipGraph_t g = nullptr;
+        const hipError_t ce = hipStreamEndCapture(cap_stream, &g);
+        LAUE_CHECK_HIP(le);
+        LAUE_CHECK_HIP(ce);
+        hipGraphExec_t x = nullptr;
+        const hipError_t ie = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        LAUE_CHECK_HIP(ie);
+        graphs.emplace_back(chunk, x);
+        *out = x;
+        return LAUE_OK;
     }
 
     int timer_start() {
@@ -726,12 +765,13 @@ struct BatchEngine {
         return LAUE_OK;
     }
 
-    int timer_stop(double *acc) {
+    int timer_stop(double *acc, double *dt = nullptr) {
         LAUE_CHECK_HIP(hipEventRecord(ev1, s));
         LAUE_CHECK_HIP(hipEventSynchronize(ev1));
         float ms = 0.0f;
         LAUE_CHECK_HIP(hipEventElapsedTime(&ms, ev0, ev1));
         *acc += ms;
+        if (dt) *dt = ms;
         return LAUE_OK;
     }
 
@@ -879,33 +919,70 @@ struct BatchEngine {
         return LAUE_OK;
     }
 
+    int current_mode() const {
+        if (launch_mode != 0) return launch_mode;
+        if (chosen) return chosen;
+        return t_direct < 0.0 ? 1 : 2;
+    }
+
     // Sinkhorn of every sample from its potentials at temperature eps[k].
-    int sinkhorn(const std::vector<double> &eps, int chunk, std::vector<laue_ot_stats> &st) {
+    // chunk: iterations between host polls (0: from the stage's history).
+    int sinkhorn(const std::vector<double> &eps, int chunk, std::vector<laue_ot_stats> &st, int stage = -1) {
         int rc;
         if ((rc = init_ctl(eps))) return rc;
         k_cs_init<<<n, 256, 0, s>>>(bw.desc);
         LAUE_CHECK_HIP(hipGetLastError());
-        if (chunk <= 0) chunk = 16;
+        if (chunk <= 0) {
+            chunk = 16;
+            if (stage >= 0 && stage < static_cast<int>(stage_iters.size()) && stage_iters[stage] >= 0) {
+                chunk = 4;
+                while (chunk < stage_iters[stage] + 2 && chunk < 64) chunk <<= 1;
+            }
+        }
         int cap = 0;
         for (int k = 0; k < n; ++k) cap = std::max(cap, hd[k].sp.n_max);
         int launched = 0;
         for (;;) {
+            const int mode = current_mode();
+            hipGraphExec_t gx = nullptr;
+            if (mode == 2 && (rc = graph_for(chunk, &gx))) return rc;
             if ((rc = timer_start())) return rc;
-            for (int c = 0; c < chunk && launched < cap + 1; ++c, ++launched) {
-                k_row<<<n_rows, 64, 0, s>>>(bw.rows, bw.desc);
-                k_col<<<n_cols, 64, 0, s>>>(bw.cols, bw.desc);
+            if (mode == 2) {
+                LAUE_CHECK_HIP(hipGraphLaunch(gx, s));
+            } else {
+                for (int c = 0; c < chunk; ++c) {
+                    k_row<<<n_rows, 64, 0, s>>>(bw.rows, bw.desc);
+                    k_col<<<n_cols, 64, 0, s>>>(bw.cols, bw.desc);
+                }
+                LAUE_CHECK_HIP(hipGetLastError());
             }
-            LAUE_CHECK_HIP(hipGetLastError());
-            if ((rc = timer_stop(&sink_ms))) return rc;
+            launched += chunk;
+            double dt = 0.0;
+            if ((rc = timer_stop(&sink_ms, &dt))) return rc;
             LAUE_CHECK_HIP(hipMemcpyAsync(hctl.data(), bw.ctl, n * sizeof(SinkCtl), hipMemcpyDeviceToHost, s));
             LAUE_CHECK_HIP(hipStreamSynchronize(s));
-            bool all = true;
-            for (int k = 0; k < n; ++k) all = all && hctl[k].done;
+            ++polls;
+            bool all = true, any = false;
+            for (int k = 0; k < n; ++k) {
+                all = all && hctl[k].done;
+                any = any || hctl[k].done;
+            }
+            // tuning: a chunk in which no sample finished timed every pass at work
+            if (launch_mode == 0 && !chosen && !any) {
+                (mode == 2 ? t_graph : t_direct) = dt / chunk;
+                if (t_direct >= 0.0 && t_graph >= 0.0) chosen = t_graph < t_direct ? 2 : 1;
+            }
             if (all) break;
-            if (launched >= cap + 1) {
+            if (launched > cap + 1) {
                 set_error("internal: Sinkhorn did not stop at its cap");
                 return LAUE_EDEVICE;
             }
+        }
+        if (stage >= 0) {
+            if (stage >= static_cast<int>(stage_iters.size())) stage_iters.resize(stage + 1, -1);
+            int mx = 0;
+            for (int k = 0; k < n; ++k) mx = std::max(mx, hctl[k].final_state);
+            stage_iters[stage] = mx;
         }
         st.assign(n, laue_ot_stats{});
         for (int k = 0; k < n; ++k) {
@@ -967,6 +1044,7 @@ static int run_em(BatchEngine &e, const std::vector<const laue_em_params *> &par
     const int n = e.n;
     if ((rc = e.grain_prep())) return rc;
     stats.assign(n, laue_em_stats{});
+    e.launch_mode = par[0]->launch;
     const int S = par[0]->n_stages;
     std::vector<double> eps(n);
     std::vector<laue_ot_stats> os;
@@ -977,7 +1055,7 @@ static int run_em(BatchEngine &e, const std::vector<const laue_em_params *> &par
                                                            static_cast<double>(st) / (S - 1));
         for (int it = 0; it < par[0]->iters_per_stage; ++it) {
             if ((rc = e.eval(0, 1))) return rc;
-            if ((rc = e.sinkhorn(eps, par[0]->ot.chunk, os))) return rc;
+            if ((rc = e.sinkhorn(eps, par[0]->ot.chunk, os, st))) return rc;
             for (int k = 0; k < n; ++k) {
                 stats[k].sinkhorn_iters += os[k].n_iter;
                 stats[k].not_converged += os[k].converged ? 0 : 1;
@@ -997,6 +1075,8 @@ static int run_em(BatchEngine &e, const std::vector<const laue_em_params *> &par
         stats[k].sinkhorn_entries = e.pass_entries[k];
         stats[k].mstep_ms = e.mstep_ms;
         stats[k].mstep_entries = e.m_entries[k];
+        stats[k].launch_used = e.current_mode();
+        stats[k].polls = e.polls;
     }
     LAUE_CHECK_HIP(hipStreamSynchronize(e.s));
     return LAUE_OK;
@@ -1204,6 +1284,8 @@ extern "C" int laue_em_batched(int32_t n, const laue_geometry *geoms, const laue
         LAUE_REQUIRE(pars[k].n_stages == pars[0].n_stages && pars[k].iters_per_stage == pars[0].iters_per_stage &&
                          pars[k].gn.k_gn == pars[0].gn.k_gn,
                      LAUE_EINVAL, "samples of a batch share n_stages, iters_per_stage and k_gn");
+        LAUE_REQUIRE(pars[k].launch == pars[0].launch && pars[k].ot.chunk == pars[0].ot.chunk, LAUE_EINVAL,
+                     "samples of a batch share launch and ot.chunk");
         LAUE_REQUIRE(std::isfinite(pots[k].f0) && std::isfinite(pots[k].g0), LAUE_EINVAL,
                      "bin potentials must be finite");
         in[k] = SampleIn{geoms + k, planes + k, obs + k, models + k, &pars[k].ot, grains + k, pots + k,

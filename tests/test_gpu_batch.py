@@ -76,3 +76,31 @@ def test_batched_matches_oracle(gpu_lib):
         assert np.max(np.degrees(metrics.misorientation(qg, ref["q"]))) < 0.01
         assert np.max(np.linalg.norm(xg - ref["x"], axis=1)) < 0.01
         assert o["n_em_iter"] == 20 and o["not_converged"] == 0
+
+
+@pytest.mark.parametrize("n_grains", [5, 60])
+def test_graph_replay_and_tuning_match_direct_launches(gpu_lib, n_grains):
+    """The captured chunk is replayed many times per call, with the EM's own
+    eager work (evaluation, M-step, polls) between replays; every mode must give
+    the direct-launch result bit for bit."""
+    laue = gpu_lib
+    pr = dataclasses.replace(ig.batching_samples(1)[0], n_rot=30, domega_deg=6.0)
+    p, geom, planes, obs, model, par, (q0, x0), _ = _sample(laue, pr, n_grains, 3)
+    res = {}
+    for launch in (1, 2, 0):
+        par.launch = launch
+        gr = laue.Grains(q0, x0)
+        out = laue.laue_em(geom, planes, obs, model, par, gr)
+        res[launch] = (gr.numpy(), out)
+    (q1, x1), o1 = res[1]
+    assert o1["launch_used"] == 1
+    for launch in (2, 0):
+        (q, x), o = res[launch]
+        assert np.array_equal(q, q1) and np.array_equal(x, x1), launch
+        for key in ("f", "g", "j_star", "q_star"):
+            assert torch.equal(o[key], o1[key]), (launch, key)
+        assert o["sinkhorn_iters"] == o1["sinkhorn_iters"]
+    assert res[2][1]["launch_used"] == 2
+    assert res[0][1]["launch_used"] in (1, 2)
+    # per-stage chunks: fewer polls than iterations
+    assert o1["polls"] < o1["sinkhorn_iters"] / 2
