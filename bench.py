@@ -95,6 +95,141 @@ def cpu_baseline(preset, n_rows=10000, chunk=1000):
             "numpy": np.__version__}
 
 
+def misorientation_deg(qa, qb):
+    """Smallest rotation angle between cubic orientations, all pairs [na, nb]:
+    2 acos of the largest |<dq, s>| over the 24 proper cubic rotations s
+    (as quaternions: axis units, (+-e_a +- e_b)/sqrt 2, (+-1,+-1,+-1,+-1)/2)."""
+    qa = np.asarray(qa, np.float64)[:, None, :]
+    qb = np.asarray(qb, np.float64)[None, :, :]
+    w1, x1, y1, z1 = (qa[..., k] for k in range(4))
+    w2, x2, y2, z2 = (qb[..., k] for k in range(4))
+    # dq = conj(qa) * qb
+    d = np.stack([w1 * w2 + x1 * x2 + y1 * y2 + z1 * z2, w1 * x2 - x1 * w2 - y1 * z2 + z1 * y2,
+                  w1 * y2 + x1 * z2 - y1 * w2 - z1 * x2, w1 * z2 - x1 * y2 + y1 * x2 - z1 * w2], axis=-1)
+    a = -np.sort(-np.abs(d), axis=-1)
+    c = np.maximum(a[..., 0], np.maximum((a[..., 0] + a[..., 1]) / math.sqrt(2.0), 0.5 * a.sum(axis=-1)))
+    return np.degrees(2.0 * np.arccos(np.clip(c, -1.0, 1.0)))
+
+
+def recall(q_est, x_est, q_true, x_true, ang_deg=0.25, pos_mm=0.5):
+    """True grains matched one-to-one (greedily, by misorientation) by an
+    estimate within ang_deg and pos_mm."""
+    if len(q_est) == 0:
+        return 0
+    mis = misorientation_deg(q_true, q_est)
+    dist = np.linalg.norm(np.asarray(x_true)[:, None, :] - np.asarray(x_est)[None, :, :], axis=-1)
+    ok = (mis <= ang_deg) & (dist <= pos_mm)
+    used, n = set(), 0
+    for i in np.argsort(np.where(ok, mis, np.inf).min(axis=1)):
+        for j in np.argsort(mis[i]):
+            if ok[i, j] and j not in used:
+                used.add(int(j))
+                n += 1
+                break
+    return n
+
+
+def bench_batching(laue, n_samples, n_stages, log):
+    """64 uneven samples: one batched EM (one launch per pass for all samples)
+    against the same samples run one after another."""
+    import torch
+    import inputgen as ig
+    samples = ig.batching_samples(n_samples)
+    planes_of, items = {}, []
+    for p in samples:
+        geom = laue.geometry_from_preset(p)
+        key = (p.a, p.centering, p.n_max)
+        if key not in planes_of:
+            planes_of[key] = laue.laue_planes_cubic(p.a, p.centering, p.n_max)
+        planes = planes_of[key]
+        q, x = ig.random_grains(p)
+        obs = laue.laue_simulate(geom, planes, laue.Grains(q, x), p.sigma_mm, p.distance, p.outlier_frac, p.seed)
+        q0, x0 = ig.perturb_grains(q, x, 0.5, 0.5, p.seed + 17)
+        model = laue.laue_forward_enumerate(geom, planes, laue.Grains(q0, x0), True)
+        c_out = 2.0 * p.distance ** 2 * (1.0 - math.cos(3.0 * p.sigma_mm / p.distance))
+        ot = laue.ot_params(p.eps_start, p.distance, c_out, float(math.ceil(0.4 * model.n)))
+        par = laue.em_params(ot, p.eps_start, p.eps_end, n_stages, 1)
+        items.append((geom, planes, obs, model, par, (q0, x0), p))
+    log(f"batching: {n_samples} samples, {sum(it[2].n for it in items)} detected and "
+        f"{sum(it[3].n for it in items)} model spots in all")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    seq, seq_entries = [], 0
+    for geom, planes, obs, model, par, (q0, x0), _ in items:
+        gr = laue.Grains(q0, x0)
+        o = laue.laue_em(geom, planes, obs, model, par, gr, assign=False)
+        seq.append(gr)
+        seq_entries += o["cost_entries"]
+    torch.cuda.synchronize()
+    t_seq = time.perf_counter() - t0
+    log(f"batching: sequential {t_seq:.2f} s")
+    grains = [laue.Grains(*it[5]) for it in items]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rc, outs = laue.laue_em_batched([it[0] for it in items], [it[1] for it in items], [it[2] for it in items],
+                                    [it[3] for it in items], [it[4] for it in items], grains, assign=False)
+    torch.cuda.synchronize()
+    t_b = time.perf_counter() - t0
+    log(f"batching: batched {t_b:.2f} s")
+    b_entries = sum(o["cost_entries"] for o in outs)
+    same = all(torch.equal(a.q, b.q) and torch.equal(a.x, b.x) for a, b in zip(seq, grains))
+    return {"samples": n_samples, "em_iterations": n_stages,
+            "grains": [int(it[6].n_grains) for it in items][:8] + ["..."],
+            "sequential_s": t_seq, "batched_s": t_b, "speedup": t_seq / t_b,
+            "sequential_entries_per_s": seq_entries / t_seq, "batched_entries_per_s": b_entries / t_b,
+            "batched_em_iters_per_s": n_samples * n_stages / t_b,
+            "launch_used": outs[0]["launch_used"], "identical_to_sequential": bool(same)}
+
+
+def bench_index(laue, workload, n_pairs, learned_pairs, log):
+    """Time to index from device-resident spots (laue_index): plain exhaustive
+    scoring of the candidates of n_pairs spot pairs, against the learned
+    proposal scoring the top 5% of the candidates of learned_pairs pairs, with
+    a network trained here on 10^6 simulated examples."""
+    import torch
+    import inputgen as ig
+    from paper_2404_06478_amd import learned
+    p = ig.PRESETS[workload]
+    geom = laue.geometry_from_preset(p)
+    planes = laue.laue_planes_cubic(p.a, p.centering, p.n_max)
+    radius = 4.0 * p.sigma_mm
+    truths = [ig.random_grains(p, seed=p.seed + 1000 + k) for k in range(10)]
+    seeds = [p.seed + 1000 + k for k in range(10)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    feat, lab = learned.training_set(geom, planes, truths, p.sigma_mm, p.distance, p.outlier_frac, seeds,
+                                     1_000_000, support_radius=radius)
+    torch.cuda.synchronize()
+    t_data = time.perf_counter() - t0
+    net = laue.Mlp(seed=3)
+    t0 = time.perf_counter()
+    losses = learned.train(net, feat, lab, epochs=10, lr=2e-3)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    log(f"index: training set {feat.shape[0]} examples in {t_data:.1f} s, 10 epochs in {t_train:.1f} s")
+    q, x = ig.random_grains(p)
+    obs = laue.laue_simulate(geom, planes, laue.Grains(q, x), p.sigma_mm, p.distance, p.outlier_frac, p.seed)
+    out = {"workload": workload, "grains": p.n_grains, "detected_spots": obs.n,
+           "training": {"examples": int(feat.shape[0]), "positives": int(lab.sum().item()),
+                        "data_s": t_data, "train_s": t_train, "epochs": 10, "final_loss": losses[-1]}}
+    for mode, pairs in (("plain", n_pairs), ("learned", learned_pairs)):
+        par = laue.index_params(p, mode, n_pairs=pairs, seed=1, mlp=net if mode == "learned" else None,
+                                support_radius=radius, n_obs=obs.n, n_planes=planes.n)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        g, st, _ = laue.laue_index(geom, planes, obs, par, assign=False)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        qg, xg = g.numpy()
+        r = recall(qg[:g.n], xg[:g.n], q, x)
+        out[mode] = {"pairs": pairs, "candidates": st["n_candidates"], "scored": st["n_scored"],
+                     "prototypes": st["n_prototypes"], "recall": r / len(q), "time_s": wall,
+                     "stage_ms": {k: st[k] for k in ("ms_candidates", "ms_proposal", "ms_score", "ms_greedy",
+                                                     "ms_em")}}
+        log(f"index: {mode}: {pairs} pairs, {st['n_scored']} scored, recall {r}/{len(q)}, {wall:.2f} s")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -102,6 +237,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="learned", choices=["learned", "medium"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batching", action="store_true")
+    ap.add_argument("--no-index", action="store_true")
+    ap.add_argument("--batch-samples", type=int, default=64)
+    ap.add_argument("--index-workload", default="medium", choices=["medium", "learned"])
+    ap.add_argument("--index-pairs", type=int, default=4096)
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}), flush=True)
@@ -180,6 +320,11 @@ def main():
         "mstep": {"ms": sum(s["mstep_ms"] for s in stats),
                   "entries": int(sum(s["mstep_entries"] for s in stats))},
     }
+    log = lambda m: print("bench: " + m, file=sys.stderr, flush=True)
+    if not args.no_batching:
+        line["batching"] = bench_batching(laue, args.batch_samples, 3, log)
+    if not args.no_index:
+        line["time_to_index"] = bench_index(laue, args.index_workload, args.index_pairs, 8 * args.index_pairs, log)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(preset)
     print(json.dumps(line), flush=True)

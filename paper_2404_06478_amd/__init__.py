@@ -632,7 +632,7 @@ def laue_pairs_same_grain(geom, obs, spot_grain, n_pairs, seed):
 # ---------------------------------------------------------------- end-to-end indexing
 
 def index_params(preset_like, mode="plain", n_pairs=None, seed=0, delta_deg=1.5, max_candidates=None, mlp=None,
-                 support_radius=1.0, n_support_planes=None, top_frac=0.05, score=None, lbar_cap=None, k_max=None,
+                 support_radius=None, n_support_planes=None, top_frac=0.05, score=None, lbar_cap=None, k_max=None,
                  max_model_spots=None, t_b_frac=0.4, em=None, n_obs=0, n_planes=0):
     """laue_index_params from a workload description (sigma_mm, distance, grains,
     rotations, schedule) with capacities sized for it."""
@@ -645,7 +645,8 @@ def index_params(preset_like, mode="plain", n_pairs=None, seed=0, delta_deg=1.5,
     if mlp is not None:
         p.mlp = C.pointer(mlp.s)
         p._mlp_ref = mlp
-    p.support = support_params(support_radius, n_planes if n_support_planes is None else n_support_planes)
+    radius = 4.0 * pl.sigma_mm if support_radius is None else support_radius
+    p.support = support_params(radius, n_planes if n_support_planes is None else n_support_planes)
     p.top_frac = float(top_frac)
     c_out = 2.0 * pl.distance ** 2 * (1.0 - math.cos(3.0 * pl.sigma_mm / pl.distance))
     p.score = score if score is not None else score_params(pl.sigma_mm, pl.distance, c_out)

@@ -100,6 +100,19 @@ __device__ __forceinline__ bool last_block(SinkCtl *ctl, int n_items) {
     return is_last != 0;
 }
 
+// Pointers read from a descriptor are generic; the pass bodies take the hot
+// arrays as global-address-space, restrict-qualified parameters so that the
+// wave-uniform streams (columns, potentials) compile to scalar loads.
+#define LAUE_GLOBAL __attribute__((address_space(1)))
+template <class T>
+__device__ __forceinline__ LAUE_GLOBAL T *gptr(T *p) {
+    return (LAUE_GLOBAL T *)p;
+}
+
+__device__ __forceinline__ Col8 ld_col(const LAUE_GLOBAL Col8 *p) {
+    return Col8{p->s1, p->s2, p->v1, p->v2, p->vv, p->vv2, p->vn, p->pad};
+}
+
 // sample s with base[s] <= i < base[s + 1] (base non-decreasing, n + 1 entries)
 __device__ __forceinline__ int sample_of(const int64_t *base, int n, int64_t i) {
     int lo = 0, hi = n;
@@ -164,20 +177,19 @@ __global__ __launch_bounds__(256) void k_cs_init(const SampleDesc *__restrict__ 
 // state k-1 (its error is the convergence test) and f_i^k = f_i^{k-1} -
 // eps ln S_i.  The sample's last workgroup updates its bin potentials and
 // decides its convergence.
-__global__ __launch_bounds__(64) void k_row(const Item *__restrict__ items,
-                                            const SampleDesc *__restrict__ descs) {
-    const Item it = items[blockIdx.x];
-    const SampleDesc &D = descs[it.s];
-    SinkCtl *ctl = D.ctl;
+// The pass bodies take the sample's arrays as restrict-qualified parameters:
+// inlined into the kernels they keep their no-alias scopes, so the
+// wave-uniform streams (columns, potentials) stay scalar loads.
+__device__ __forceinline__ void row_pass(const Item &it, const LAUE_GLOBAL float *__restrict__ P1,
+                                         const LAUE_GLOBAL float *__restrict__ P2,
+                                         const LAUE_GLOBAL Col8 *__restrict__ cols,
+                                         const LAUE_GLOBAL float *__restrict__ G, LAUE_GLOBAL float *__restrict__ F0,
+                                         LAUE_GLOBAL float *__restrict__ F1, SinkCtl *__restrict__ ctl,
+                                         double2 *__restrict__ part, const SinkParams &p, int n_items) {
     if (ctl->done) return;
-    const SinkParams p = D.sp;
-    const float *__restrict__ P1 = D.p1;
-    const float *__restrict__ P2 = D.p2;
-    const Col8 *__restrict__ cols = D.colsE;
-    const float *__restrict__ G = D.g;
     const int k = ctl->iter + 1;
-    const float *Fin = ((k - 1) & 1) ? D.f1 : D.f;
-    float *Fout = (k & 1) ? D.f1 : D.f;
+    const LAUE_GLOBAL float *Fin = ((k - 1) & 1) ? F1 : F0;
+    LAUE_GLOBAL float *Fout = (k & 1) ? F1 : F0;
     const double eps = ctl->eps;
     const double kexp = ctl->kexp;
     const float kx = static_cast<float>(kexp);
@@ -195,7 +207,7 @@ __global__ __launch_bounds__(64) void k_row(const Item *__restrict__ items,
         float a = 0.0f;
 #pragma unroll 4
         for (int j = j0; j < j1; ++j) {
-            const Col8 c = cols[j];
+            const Col8 c = ld_col(cols + j);
             const float base = fmaf(G[j], kx, fk);
             a += fast_exp2(entry_exponent(p1, p2, c.s1, c.s2, c.v1, c.v2, c.vv, c.vv2, K, base));
         }
@@ -209,13 +221,13 @@ __global__ __launch_bounds__(64) void k_row(const Item *__restrict__ items,
         // every term underflowed: recompute with the row maximum as shift
         float mx = static_cast<float>(eb);
         for (int j = it.c0; j < it.c1; ++j) {
-            const Col8 c = cols[j];
+            const Col8 c = ld_col(cols + j);
             mx = fmaxf(mx, entry_exponent(p1, p2, c.s1, c.s2, c.v1, c.v2, c.vv, c.vv2, K,
                                           fmaf(G[j], kx, fk)));
         }
         double s2 = exp2(eb - mx);
         for (int j = it.c0; j < it.c1; ++j) {
-            const Col8 c = cols[j];
+            const Col8 c = ld_col(cols + j);
             s2 += exp2(static_cast<double>(entry_exponent(p1, p2, c.s1, c.s2, c.v1, c.v2, c.vv,
                                                           c.vv2, K, fmaf(G[j], kx, fk)) - mx));
         }
@@ -233,12 +245,12 @@ __global__ __launch_bounds__(64) void k_row(const Item *__restrict__ items,
     }
     rs = wave_sum(rs);
     err = wave_max(err);
-    if (threadIdx.x == 0) D.part[it.local] = make_double2(rs, err);
-    if (!last_block(ctl, D.n_row_items)) return;
+    if (threadIdx.x == 0) part[it.local] = make_double2(rs, err);
+    if (!last_block(ctl, n_items)) return;
     double rsum = 0.0, emax = 0.0;
-    for (int w = threadIdx.x; w < D.n_row_items; w += 64) {
-        rsum += D.part[w].x;
-        emax = fmax(emax, D.part[w].y);
+    for (int w = threadIdx.x; w < n_items; w += 64) {
+        rsum += part[w].x;
+        emax = fmax(emax, part[w].y);
     }
     rsum = wave_sum(rsum);
     emax = wave_max(emax);
@@ -275,6 +287,14 @@ __global__ __launch_bounds__(64) void k_row(const Item *__restrict__ items,
     }
 }
 
+__global__ __launch_bounds__(64) void k_row(const Item *__restrict__ items,
+                                            const SampleDesc *__restrict__ descs) {
+    const Item it = items[blockIdx.x];
+    const SampleDesc &D = descs[it.s];
+    row_pass(it, gptr(D.p1), gptr(D.p2), gptr(D.colsE), gptr(D.g), gptr(D.f), gptr(D.f1), D.ctl, D.part, D.sp,
+             D.n_row_items);
+}
+
 // ---------------------------------------------------------------- column pass
 
 // Column half of iteration k = iter for 64 model spots of one block: each
@@ -282,18 +302,15 @@ __global__ __launch_bounds__(64) void k_row(const Item *__restrict__ items,
 // entries of the plan after the row half, <= 1) and sets
 // g_j^k = g_j^{k-1} - eps ln(column marginal).  The sample's last workgroup
 // stores sum_j exp((f0 + g_j - c_unm)/eps) for the next row half.
-__global__ __launch_bounds__(64) void k_col(const Item *__restrict__ items,
-                                            const SampleDesc *__restrict__ descs) {
-    const Item it = items[blockIdx.x];
-    const SampleDesc &D = descs[it.s];
-    SinkCtl *ctl = D.ctl;
+__device__ __forceinline__ void col_pass(const Item &it, const LAUE_GLOBAL float *__restrict__ P1,
+                                         const LAUE_GLOBAL float *__restrict__ P2,
+                                         const LAUE_GLOBAL Col8 *__restrict__ cols, LAUE_GLOBAL float *__restrict__ G,
+                                         const LAUE_GLOBAL float *__restrict__ F0,
+                                         const LAUE_GLOBAL float *__restrict__ F1, SinkCtl *__restrict__ ctl,
+                                         double2 *__restrict__ part, const SinkParams &p, int n_items) {
     if (ctl->done) return;
-    const SinkParams p = D.sp;
-    const float *__restrict__ P1 = D.p1;
-    const float *__restrict__ P2 = D.p2;
-    float *G = D.g;
     const int k = ctl->iter;
-    const float *__restrict__ F = (k & 1) ? D.f1 : D.f;
+    const LAUE_GLOBAL float *__restrict__ F = (k & 1) ? F1 : F0;
     const double eps = ctl->eps;
     const double kexp = ctl->kexp;
     const float kx = static_cast<float>(kexp);
@@ -304,7 +321,7 @@ __global__ __launch_bounds__(64) void k_col(const Item *__restrict__ items,
     Col8 c = {0, 0, 0, 0, 1, 1, 1, 0};
     float g = 0.0f;
     if (act) {
-        c = D.colsE[j];
+        c = ld_col(cols + j);
         g = G[j];
     }
     const float gk = g * kx;
@@ -344,10 +361,10 @@ __global__ __launch_bounds__(64) void k_col(const Item *__restrict__ items,
         cs = exp((f0 + static_cast<double>(gn) - p.c_unm) / eps);
     }
     cs = wave_sum(cs);
-    if (threadIdx.x == 0) D.part[it.local] = make_double2(cs, 0.0);
-    if (!last_block(ctl, D.n_col_items)) return;
+    if (threadIdx.x == 0) part[it.local] = make_double2(cs, 0.0);
+    if (!last_block(ctl, n_items)) return;
     double t = 0.0;
-    for (int w = threadIdx.x; w < D.n_col_items; w += 64) t += D.part[w].x;
+    for (int w = threadIdx.x; w < n_items; w += 64) t += part[w].x;
     t = wave_sum(t);
     if (threadIdx.x == 0) {
         ctl->cs_sum = t;
@@ -355,16 +372,22 @@ __global__ __launch_bounds__(64) void k_col(const Item *__restrict__ items,
     }
 }
 
+__global__ __launch_bounds__(64) void k_col(const Item *__restrict__ items,
+                                            const SampleDesc *__restrict__ descs) {
+    const Item it = items[blockIdx.x];
+    const SampleDesc &D = descs[it.s];
+    col_pass(it, gptr(D.p1), gptr(D.p2), gptr(D.colsE), gptr(D.g), gptr(D.f), gptr(D.f1), D.ctl, D.part, D.sp,
+             D.n_col_items);
+}
+
 // ---------------------------------------------------------------- assign
 
 // Hard assignment per detected spot: argmax_j Q_ij over its block and the
 // outlier column (lowest index on ties, -1 = outlier), with the sample's final
 // potentials and temperature.
-__global__ __launch_bounds__(64) void k_assign(const Item *__restrict__ items,
-                                               const SampleDesc *__restrict__ descs) {
-    const Item it = items[blockIdx.x];
-    const SampleDesc &D = descs[it.s];
-    if (!D.jstar) return;
+__device__ __forceinline__ void assign_pass(const Item &it, const SampleDesc &D,
+                                            const LAUE_GLOBAL Col8 *__restrict__ cols,
+                                            const LAUE_GLOBAL float *__restrict__ G) {
     const SinkCtl *ctl = D.ctl;
     const SinkParams p = D.sp;
     const double eps = ctl->eps, g0 = ctl->g0[ctl->final_state & 1];
@@ -378,8 +401,8 @@ __global__ __launch_bounds__(64) void k_assign(const Item *__restrict__ items,
     float best = -INFINITY;
     int arg = -1;
     for (int j = it.c0; j < it.c1; ++j) {
-        const Col8 c = D.colsE[j];
-        float e = entry_exponent(p1, p2, c.s1, c.s2, c.v1, c.v2, c.vv, c.vv2, K, fmaf(D.g[j], kx, fk));
+        const Col8 c = ld_col(cols + j);
+        float e = entry_exponent(p1, p2, c.s1, c.s2, c.v1, c.v2, c.vv, c.vv2, K, fmaf(G[j], kx, fk));
         if (e > best) {
             best = e;
             arg = j;
@@ -394,6 +417,14 @@ __global__ __launch_bounds__(64) void k_assign(const Item *__restrict__ items,
     D.gstar[i] = m ? D.mgrain[arg] : -1;
     D.qstar[i] = m ? qb : qo;
     D.qout[i] = qo;
+}
+
+__global__ __launch_bounds__(64) void k_assign(const Item *__restrict__ items,
+                                               const SampleDesc *__restrict__ descs) {
+    const Item it = items[blockIdx.x];
+    const SampleDesc &D = descs[it.s];
+    if (!D.jstar) return;
+    assign_pass(it, D, gptr(D.colsE), gptr(D.g));
 }
 
 // ---------------------------------------------------------------- M-step
@@ -411,13 +442,13 @@ __global__ __launch_bounds__(64) void k_assign(const Item *__restrict__ items,
 //   H_ww = D^2 S0 K^T K, H_xx = D^2 Gt^T A Gt, H_xw = D^2 Gt^T B K,
 //   g_w = -D^2 K^T e,    g_x = D^2 Gt^T B r,
 // with K = 2 (u e^T + (u.e) I) Gt [R w]_x the rotation Jacobian of the ray.
-__global__ __launch_bounds__(64) void k_mstep_acc(const Item *__restrict__ items,
-                                                  const SampleDesc *__restrict__ descs, int cur_c) {
-    const Item it = items[blockIdx.x];
-    const SampleDesc &D = descs[it.s];
-    const float *__restrict__ P1 = D.p1;
-    const float *__restrict__ P2 = D.p2;
-    const float *__restrict__ F = D.f;
+__device__ __forceinline__ void mstep_pass(const Item &it, const SampleDesc &D,
+                                           const LAUE_GLOBAL float *__restrict__ P1,
+                                           const LAUE_GLOBAL float *__restrict__ P2,
+                                           const LAUE_GLOBAL float *__restrict__ F,
+                                           const LAUE_GLOBAL float *__restrict__ G,
+                                           const LAUE_GLOBAL Col8 *__restrict__ colsE,
+                                           const LAUE_GLOBAL Col8 *__restrict__ colsC, int cur_c) {
     const float kx = static_cast<float>(D.ctl->kexp);
     const float K = D.sp.twoD2 * kx;
     const int j = it.c0 + static_cast<int>(threadIdx.x);
@@ -425,9 +456,9 @@ __global__ __launch_bounds__(64) void k_mstep_acc(const Item *__restrict__ items
     Col8 cE = {0, 0, 0, 0, 1, 1, 1, 0}, cC = {0, 0, 0, 0, 1, 1, 1, 0};
     float g = 0.0f;
     if (act) {
-        cE = D.colsE[j];
-        cC = cur_c ? D.colsC[j] : cE;
-        g = D.g[j];
+        cE = ld_col(colsE + j);
+        if (cur_c) cC = ld_col(colsC + j); else cC = cE;
+        g = G[j];
     }
     const float gk = g * kx;
     const float ivl = __builtin_amdgcn_rsqf(cC.vv);
@@ -450,6 +481,13 @@ __global__ __launch_bounds__(64) void k_mstep_acc(const Item *__restrict__ items
     if (!act) return;
     column_normal_equations(*D.geom, D.W, D.n_planes, D.grains, D.n_grains, D.mplane[j], D.mgrain[j],
                             D.mblock[j], s64, rn, r1, r2, D.D2, D.colHg + static_cast<int64_t>(j) * kHg);
+}
+
+__global__ __launch_bounds__(64) void k_mstep_acc(const Item *__restrict__ items,
+                                                  const SampleDesc *__restrict__ descs, int cur_c) {
+    const Item it = items[blockIdx.x];
+    const SampleDesc &D = descs[it.s];
+    mstep_pass(it, D, gptr(D.p1), gptr(D.p2), gptr(D.f), gptr(D.g), gptr(D.colsE), gptr(D.colsC), cur_c);
 }
 
 // One wave per grain of any sample (gbase: grain offsets of the samples):

@@ -21,7 +21,7 @@ from . import (Grains, MlpTrainer, adam_params, laue_candidate_labels, laue_cand
 
 
 def sample_examples(geom, planes, truth, sigma_mm, distance, outlier_frac, seed, n_pairs_random,
-                    n_pairs_same, support_radius=1.0, max_deg=2.0):
+                    n_pairs_same, support_radius, max_deg=2.0):
     """Features [n, 16] and labels [n] (device FP32) of one simulated sample."""
     import torch
     obs = laue_simulate(geom, planes, truth, sigma_mm, distance, outlier_frac, seed)
@@ -41,7 +41,7 @@ def sample_examples(geom, planes, truth, sigma_mm, distance, outlier_frac, seed,
 
 
 def training_set(geom, planes, truths, sigma_mm, distance, outlier_frac, seeds, n_examples,
-                 support_radius=1.0):
+                 support_radius):
     """At least n_examples examples from the given true grain sets (one sample
     each, in turn, until enough)."""
     import torch
