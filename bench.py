@@ -45,6 +45,12 @@ TRANS_PER_ENTRY = 3
 VALU_LANE_OPS_PER_S = 256 * 4 * 32 * 2.4e9
 PEAK_ENTRIES_PER_S = VALU_LANE_OPS_PER_S / (VALU_PER_ENTRY + 4 * TRANS_PER_ENTRY)
 
+# HBM bytes of one working row pass (k_row) on this workload, from rocprofv3
+# FETCH_SIZE and WRITE_SIZE (KiB per dispatch) scaled by what the same
+# counters read for a plain 1 GiB device copy (x2.000 and x1.000):
+# 148,400 KiB x 2 + 4,456 KiB.  The column pass moves 1.57e8 B.
+ROW_PASS_HBM_BYTES = (148_400 * 2.0 + 4_456 * 1.0) * 1024
+
 
 def build_problem(laue, preset):
     import inputgen as ig
@@ -242,7 +248,18 @@ def main():
     ap.add_argument("--batch-samples", type=int, default=64)
     ap.add_argument("--index-workload", default="medium", choices=["medium", "learned"])
     ap.add_argument("--index-pairs", type=int, default=4096)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only copy 1 GiB device to device three times (reference for HBM byte counters)")
     args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+        a = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_each_way": a.numel() * 4, "copies": 3}), flush=True)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}), flush=True)
         sys.exit(2)
@@ -314,7 +331,9 @@ def main():
         "sinkhorn_capped": int(sum(s["not_converged"] for s in stats)),
         "roofline": {"kernel": "Sinkhorn row/column pass (k_row, k_col)", "bound": "alu",
                      "achieved": achieved / 1e9, "peak": PEAK_ENTRIES_PER_S / 1e9,
-                     "unit": "Gentries/s", "frac": achieved / PEAK_ENTRIES_PER_S, "traffic": None,
+                     "unit": "Gentries/s", "frac": achieved / PEAK_ENTRIES_PER_S,
+                     "traffic": ROW_PASS_HBM_BYTES if args.workload == "learned" else None,
+                     "traffic_unit": "HBM bytes per row-pass launch",
                      "per_entry": {"valu": VALU_PER_ENTRY, "trans": TRANS_PER_ENTRY},
                      "passes": sk_pass, "avg_pass_ms": sk_ms / max(sk_pass, 1)},
         "mstep": {"ms": sum(s["mstep_ms"] for s in stats),

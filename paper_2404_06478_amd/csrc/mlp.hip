@@ -171,32 +171,52 @@ __global__ __launch_bounds__(256) void k_mlp_dz(const float *__restrict__ prob,
     lrow[r] = -(y[r] * log(pc) + (1.0 - y[r]) * log(1.0 - pc));
 }
 
-// per column c of h2: dw3[c] = sum_r dz_r h2b[r][c]; dh2 = dz w3b[c] [h2b > 0]
-// stored as bf16 row-major and transposed; db2[c] = sum_r dh2 (FP32)
+// per column c of h2: dh2 = dz w3b[c] [h2b > 0] stored as bf16 row-major and
+// transposed; per block of kDh2Rows rows, the partial sums of
+// dw3[c] = sum_r dz_r h2b[r][c] and db2[c] = sum_r dh2 (FP32), and of db3.
+constexpr int kDh2Rows = 256;
+
 __global__ __launch_bounds__(256) void k_mlp_dh2(const float *__restrict__ dz,
                                                  const uint16_t *__restrict__ h2,
                                                  const uint16_t *__restrict__ wb, int64_t n,
-                                                 float *__restrict__ g, uint16_t *__restrict__ dh2,
+                                                 float *__restrict__ part, uint16_t *__restrict__ dh2,
                                                  uint16_t *__restrict__ dh2T) {
     const int c = threadIdx.x;
+    const int64_t r0 = static_cast<int64_t>(blockIdx.x) * kDh2Rows;
+    const int64_t r1 = min(r0 + kDh2Rows, n);
     const float w3 = bf2f(wb[kBfW3 + c]);
-    float sw = 0.0f, sb = 0.0f;
-    for (int64_t r = 0; r < n; ++r) {
+    float sw = 0.0f, sb = 0.0f, sz = 0.0f;
+    for (int64_t r = r0; r < r1; ++r) {
+        const float z = dz[r];
         const float hv = bf2f(h2[r * kHid + c]);
-        sw = fmaf(dz[r], hv, sw);
-        const float d = hv > 0.0f ? dz[r] * w3 : 0.0f;
+        sw = fmaf(z, hv, sw);
+        const float d = hv > 0.0f ? z * w3 : 0.0f;
         sb += d;
+        sz += z;
         const uint16_t db = f2bf(d);
         dh2[r * kHid + c] = db;
         dh2T[static_cast<int64_t>(c) * n + r] = db;
     }
+    float *p = part + static_cast<int64_t>(blockIdx.x) * (2 * kHid + 1);
+    p[c] = sw;
+    p[kHid + c] = sb;
+    if (c == 0) p[2 * kHid] = sz;
+}
+
+// Sum of the partials over the row blocks, in block order.
+__global__ __launch_bounds__(256) void k_mlp_dh2_sum(const float *__restrict__ part, int nblk,
+                                                     float *__restrict__ g) {
+    const int c = threadIdx.x;
+    float sw = 0.0f, sb = 0.0f, sz = 0.0f;
+    for (int k = 0; k < nblk; ++k) {
+        const float *p = part + static_cast<int64_t>(k) * (2 * kHid + 1);
+        sw += p[c];
+        sb += p[kHid + c];
+        if (c == 0) sz += p[2 * kHid];
+    }
     g[kOffW3 + c] = sw;
     g[kOffB2 + c] = sb;
-    if (c == 0) {
-        float s = 0.0f;
-        for (int64_t r = 0; r < n; ++r) s += dz[r];
-        g[kOffB3] = s;
-    }
+    if (c == 0) g[kOffB3] = sz;
 }
 
 // dh1^T [256][n] (FP32, from the GEMM) -> mask with h1b > 0 -> bf16 dh1b^T, db1
@@ -293,7 +313,7 @@ size_t carve_fwd(Carver &cv, MlpFwdWs &w, int64_t n, bool train) {
 
 struct MlpTrainWs {
     MlpFwdWs f;
-    float *prob, *dz, *grad, *dh1T;
+    float *prob, *dz, *grad, *dh1T, *part;
     double *lrow, *lsum;
     uint16_t *dh2, *dh2T, *dh1bT;
 };
@@ -304,6 +324,7 @@ size_t carve_train(Carver &cv, MlpTrainWs &w, int64_t B) {
     w.dz = cv.take<float>(B);
     w.grad = cv.take<float>(kNParams);
     w.dh1T = cv.take<float>(B * kHid);
+    w.part = cv.take<float>(((B + kDh2Rows - 1) / kDh2Rows) * (2 * kHid + 1));
     w.lrow = cv.take<double>(B);
     w.lsum = cv.take<double>(1);
     w.dh2 = cv.take<uint16_t>(B * kHid);
@@ -405,7 +426,9 @@ extern "C" int laue_mlp_backward(const laue_mlp *m, const float *feat, const flo
     const int64_t B = batch;
     if ((rc = mlp_forward_chunk(m->params, m->wbf16, feat, B, w.prob, w.f, true, B, s))) return rc;
     k_mlp_dz<<<static_cast<unsigned>((B + 255) / 256), 256, 0, s>>>(w.prob, label, B, w.dz, w.lrow);
-    k_mlp_dh2<<<1, 256, 0, s>>>(w.dz, w.f.h2, m->wbf16, B, w.grad, w.dh2, w.dh2T);
+    const int nblk = static_cast<int>((B + kDh2Rows - 1) / kDh2Rows);
+    k_mlp_dh2<<<nblk, 256, 0, s>>>(w.dz, w.f.h2, m->wbf16, B, w.part, w.dh2, w.dh2T);
+    k_mlp_dh2_sum<<<1, 256, 0, s>>>(w.part, nblk, w.grad);
     LAUE_CHECK_HIP(hipGetLastError());
     // dW2 = dh2b^T h1b: A = dh2b^T [256][B], B = h1b^T [256][B]
     if ((rc = gemm_nt(w.dh2T, w.f.h1T, w.grad + kOffW2, kHid, kHid, static_cast<int>(B), kHid, s))) return rc;
