@@ -236,15 +236,53 @@ def bench_index(laue, workload, n_pairs, learned_pairs, log):
     return out
 
 
+def bench_forward(laue, n_grains, log):
+    """Forward model at candidate scale: enumerate the visible reflections of
+    n_grains random grains (learned-scale scan and lattice), then time the
+    frozen-list evaluation (ids in: 12 B; s1, s2, vn, v1, v2, lambda out:
+    24 B per model spot) against the 8 TB/s HBM peak."""
+    import torch
+    import inputgen as ig
+    p = ig.LEARNED
+    geom = laue.geometry_from_preset(p)
+    planes = laue.laue_planes_cubic(p.a, p.centering, p.n_max)
+    q, x = ig.random_grains(p, n=n_grains, seed=p.seed + 7)
+    grains = laue.Grains(q, x)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    model = laue.laue_forward_enumerate(geom, planes, grains, True)
+    torch.cuda.synchronize()
+    t_enum = time.perf_counter() - t0
+    laue.laue_forward_eval(geom, planes, grains, model)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    reps = 10
+    ev[0].record()
+    for _ in range(reps):
+        laue.laue_forward_eval(geom, planes, grains, model)
+    ev[1].record()
+    torch.cuda.synchronize()
+    t_eval = ev[0].elapsed_time(ev[1]) * 1e-3 / reps
+    nbytes = 36.0 * model.n
+    log(f"forward: {n_grains} grains, {model.n} model spots, enumerate {t_enum * 1e3:.1f} ms, "
+        f"eval {t_eval * 1e3:.3f} ms")
+    triples = n_grains * p.n_rot * planes.n
+    return {"grains": n_grains, "model_spots": model.n, "triples": triples,
+            "enumerate_s": t_enum, "enumerate_triples_per_s": triples / t_enum,
+            "eval_ms": t_eval * 1e3, "eval_bytes": nbytes, "eval_GBps": nbytes / t_eval / 1e9,
+            "eval_hbm_frac": nbytes / t_eval / 8e12}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=8)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="learned", choices=["learned", "medium"])
+    ap.add_argument("--workload", default="learned", choices=["learned", "medium", "stress"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batching", action="store_true")
     ap.add_argument("--no-index", action="store_true")
+    ap.add_argument("--no-forward", action="store_true")
+    ap.add_argument("--forward-grains", type=int, default=65536)
     ap.add_argument("--batch-samples", type=int, default=64)
     ap.add_argument("--index-workload", default="medium", choices=["medium", "learned"])
     ap.add_argument("--index-pairs", type=int, default=4096)
@@ -319,7 +357,8 @@ def main():
         "ms_per_step": dt * 1e3 / args.steps,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32", "data": "synthetic",
-        "config": {"workload": f"{args.workload}: Sinkhorn-EM iterations on {preset.n_grains} BCC grains, "
+        "config": {"workload": f"{args.workload}: Sinkhorn-EM iterations on {preset.n_grains} "
+                               f"{'BCC' if preset.centering == 'I' else 'FCC'} grains (a = {preset.a} A), "
                                f"{preset.n_rot} rotations x {preset.domega_deg} deg, sigma {preset.sigma_mm} mm, "
                                f"{int(100 * preset.outlier_frac)}% outliers",
                    "detected_spots": obs.n, "model_spots": model.n,
@@ -340,6 +379,8 @@ def main():
                   "entries": int(sum(s["mstep_entries"] for s in stats))},
     }
     log = lambda m: print("bench: " + m, file=sys.stderr, flush=True)
+    if not args.no_forward:
+        line["forward_model"] = bench_forward(laue, args.forward_grains, log)
     if not args.no_batching:
         line["batching"] = bench_batching(laue, args.batch_samples, 3, log)
     if not args.no_index:

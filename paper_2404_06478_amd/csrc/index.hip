@@ -283,6 +283,8 @@ __device__ __forceinline__ float wave_min_f(float v) {
     return v;
 }
 
+constexpr int kSup = 16;    // 64-row chunks of detected spots held per lane
+
 struct SlotArgs {
     int C;                  // candidates in the batch
     int nb;                 // blocks
@@ -348,24 +350,49 @@ __global__ __launch_bounds__(64) void k_single_acc(SlotArgs A, float K, float bi
     __shared__ double acc[64 * kStat];
     for (int k = lane; k < nc * kStat; k += 64) acc[k] = 0.0;
     __syncthreads();
-    for (int64_t i0 = r0; i0 < rend; i0 += 64) {
-        const int64_t i = i0 + lane;
-        const bool rv = i < rend;
-        const float p1 = rv ? A.P1[i] : 0.0f, p2 = rv ? A.P2[i] : 0.0f;
-        float z = bin_e;
-        for (int j = 0; j < nc; ++j) {
-            const Col8 cE = col_of(lE, j);
-            z += fast_exp2(entry_exponent(p1, p2, cE.s1, cE.s2, cE.v1, cE.v2, cE.vv, cE.vv2, K, 0.0f));
+    // Detected spots in super-chunks of kSup x 64 rows: each lane keeps its
+    // kSup rows (coordinates and softmax normalisers) in registers, so the
+    // statistics of a model spot accumulate per lane over the whole
+    // super-chunk and are wave-reduced once per super-chunk.
+    for (int64_t s0 = r0; s0 < rend; s0 += 64 * kSup) {
+        const int nrow = static_cast<int>(min<int64_t>(64 * kSup, rend - s0));
+        float p1[kSup], p2[kSup], iz[kSup];
+#pragma unroll
+        for (int u = 0; u < kSup; ++u) {
+            const bool rv = 64 * u + lane < nrow;
+            p1[u] = rv ? A.P1[s0 + 64 * u + lane] : 0.0f;
+            p2[u] = rv ? A.P2[s0 + 64 * u + lane] : 0.0f;
+            iz[u] = bin_e;
         }
-        const float iz = rv ? __builtin_amdgcn_rcpf(z) : 0.0f;
         for (int j = 0; j < nc; ++j) {
             const Col8 cE = col_of(lE, j);
-            const float Q =
-                fast_exp2(entry_exponent(p1, p2, cE.s1, cE.s2, cE.v1, cE.v2, cE.vv, cE.vv2, K, 0.0f)) * iz;
-            if (!__any(Q > 0.0f)) continue;                 // no weight in this chunk
+#pragma unroll
+            for (int u = 0; u < kSup; ++u) {
+                if (64 * u >= nrow) break;
+                iz[u] += fast_exp2(entry_exponent(p1[u], p2[u], cE.s1, cE.s2, cE.v1, cE.v2, cE.vv, cE.vv2, K, 0.0f));
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kSup; ++u) iz[u] = 64 * u + lane < nrow ? __builtin_amdgcn_rcpf(iz[u]) : 0.0f;
+        for (int j = 0; j < nc; ++j) {
+            const Col8 cE = col_of(lE, j);
             const Col8 cC = col_of(lC, j);
-            float a[kStat];                               // zero for Q = 0 (finite geometry)
-            stats_of(a, Q, p1, p2, cC, bcast(vlen_l, j), bcast(rn_l, j), bcast(r1_l, j), bcast(r2_l, j));
+            const float vl = bcast(vlen_l, j), rn = bcast(rn_l, j), r1 = bcast(r1_l, j), r2 = bcast(r2_l, j);
+            float a[kStat];
+#pragma unroll
+            for (int q = 0; q < kStat; ++q) a[q] = 0.0f;
+            bool any = false;
+#pragma unroll
+            for (int u = 0; u < kSup; ++u) {
+                if (64 * u >= nrow) break;
+                const float Q =
+                    fast_exp2(entry_exponent(p1[u], p2[u], cE.s1, cE.s2, cE.v1, cE.v2, cE.vv, cE.vv2, K, 0.0f)) *
+                    iz[u];
+                if (!__any(Q > 0.0f)) continue;             // no weight in this chunk
+                any = true;
+                accumulate_stats(a, Q, p1[u], p2[u], cC, vl, rn, r1, r2);   // Q = 0 adds zeros
+            }
+            if (!any) continue;
             const float t = wave_reduce_scatter16(a, lane);
             if ((lane & 3) == 0) acc[kStat * j + (lane >> 2)] += static_cast<double>(t);
         }
