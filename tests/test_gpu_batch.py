@@ -104,3 +104,34 @@ def test_graph_replay_and_tuning_match_direct_launches(gpu_lib, n_grains):
     assert res[0][1]["launch_used"] in (1, 2)
     # per-stage chunks: fewer polls than iterations
     assert o1["polls"] < o1["sinkhorn_iters"] / 2
+
+
+def test_batch_with_degenerate_samples(gpu_lib):
+    """A sample without model spots (no grains) and one without detected spots
+    ride along; every sample still equals its solo run."""
+    laue = gpu_lib
+    pr = ig.batching_samples(3)
+    s0 = _sample(laue, pr[0], 10, 0)
+    p, geom, planes, obs, model, par, _, _ = _sample(laue, pr[1], 6, 1)
+    empty_g = laue.Grains(np.zeros((0, 4)), np.zeros((0, 3)))
+    model_e = laue.laue_forward_enumerate(geom, planes, empty_g, True)
+    assert model_e.n == 0
+    nb = len(obs.block_off) - 1
+    obs_e = laue.ObsSpots.from_numpy(np.zeros((0, 2), np.float32), np.zeros(nb + 1, np.int64))
+    samples = [(s0[1], s0[2], s0[3], s0[4], s0[5], laue.Grains(*s0[6])),
+               (geom, planes, obs, model_e, par, empty_g),
+               (geom, planes, obs_e, model, laue.em_params(laue.ot_params(par.ot.eps, par.ot.distance, par.ot.c_out,
+                                                                          float(model.n)),
+                                                           par.eps_start, par.eps_end, 3, 2),
+                laue.Grains(*_sample(laue, pr[1], 6, 1)[6]))]
+    solo = []
+    for gm, pl, ob, mo, pa, gr in samples:
+        g2 = laue.Grains(*gr.numpy())
+        out = laue.laue_em(gm, pl, ob, mo, pa, g2)
+        solo.append((g2.numpy(), out))
+    rc, outs = laue.laue_em_batched([s[0] for s in samples], [s[1] for s in samples], [s[2] for s in samples],
+                                    [s[3] for s in samples], [s[4] for s in samples], [s[5] for s in samples])
+    for k, (s, (qx, o1)) in enumerate(zip(samples, solo)):
+        qb, xb = s[5].numpy()
+        assert np.array_equal(qx[0], qb) and np.array_equal(qx[1], xb), k
+        assert o1["sinkhorn_iters"] == outs[k]["sinkhorn_iters"], k

@@ -102,3 +102,21 @@ def test_index_recovers_medium_grains(gpu_lib):
     rec, _ = metrics.match_grains(qg[:grains.n], xg[:grains.n], q, x)
     print("recovered", rec, "of", len(q), "prototypes", grains.n)
     assert rec >= 0.9 * len(q)
+
+
+def test_index_without_candidates(gpu_lib):
+    """Spots that pair into no hypothesis (one spot per rotation) index to no
+    grain, without error."""
+    laue = gpu_lib
+    p = ig.TINY
+    geom = laue.geometry_from_preset(p)
+    planes = laue.laue_planes_cubic(p.a, p.centering, p.n_max)
+    nb = p.n_rot * 2
+    p12 = np.array([[10.0 + t, -20.0] for t in range(p.n_rot)], np.float32)
+    off = np.zeros(nb + 1, np.int64)
+    for t in range(p.n_rot):
+        off[2 * t + 1:] += 1          # one spot on the transmission detector of every rotation
+    obs = laue.ObsSpots.from_numpy(p12, off)
+    par = laue.index_params(p, "plain", n_pairs=64, seed=1, n_obs=obs.n, n_planes=planes.n)
+    grains, st, asg = laue.laue_index(geom, planes, obs, par)
+    assert st["n_candidates"] == 0 and grains.n == 0 and st["n_prototypes"] == 0
