@@ -754,12 +754,16 @@ struct BatchEngine {
     int launch_mode = 1, chosen = 0, polls = 0;
     double t_direct = -1.0, t_graph = -1.0;     // ms per iteration on chunks where every pass worked
     std::vector<std::pair<int, hipGraphExec_t>> graphs;   // one captured chunk per chunk length
+    hipGraphExec_t mgraph = nullptr;            // captured M-step + forward evaluation
+    int mgraph_kgn = -1;
     hipStream_t cap_stream = nullptr;
     std::vector<int> stage_iters;               // iterations of the latest Sinkhorn of each stage
 
     ~BatchEngine() {
         if (!graphs.empty()) (void)hipStreamSynchronize(s);
+        if (mgraph) (void)hipStreamSynchronize(s);
         for (auto &g : graphs) (void)hipGraphExecDestroy(g.second);
+        if (mgraph) (void)hipGraphExecDestroy(mgraph);
         if (cap_stream) (void)hipStreamDestroy(cap_stream);
         if (ev0) (void)hipEventDestroy(ev0);
         if (ev1) (void)hipEventDestroy(ev1);
@@ -791,6 +795,32 @@ struct BatchEngine {
         LAUE_CHECK_HIP(ie);
         graphs.emplace_back(chunk, x);
         *out = x;
+        return LAUE_OK;
+    }
+
+    int mstep_graph(int k_gn, hipGraphExec_t *out) {
+        if (mgraph && mgraph_kgn == k_gn) {
+            *out = mgraph;
+            return LAUE_OK;
+        }
+        if (mgraph) {
+            LAUE_CHECK_HIP(hipStreamSynchronize(s));
+            (void)hipGraphExecDestroy(mgraph);
+            mgraph = nullptr;
+        }
+        if (!cap_stream) LAUE_CHECK_HIP(hipStreamCreateWithFlags(&cap_stream, hipStreamNonBlocking));
+        LAUE_CHECK_HIP(hipStreamBeginCapture(cap_stream, hipStreamCaptureModeThreadLocal));
+        mstep_launches(cap_stream, k_gn);
+        const hipError_t le = hipGetLastError();
+        hipGraph_t g = nullptr;
+        const hipError_t ce = hipStreamEndCapture(cap_stream, &g);
+        LAUE_CHECK_HIP(le);
+        LAUE_CHECK_HIP(ce);
+        const hipError_t ie = hipGraphInstantiate(&mgraph, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        LAUE_CHECK_HIP(ie);
+        mgraph_kgn = k_gn;
+        *out = mgraph;
         return LAUE_OK;
     }
 
@@ -935,11 +965,27 @@ struct BatchEngine {
     }
 
     int eval(int to_c, int with_outputs) {
-        if (mbase[n] == 0) return LAUE_OK;
-        k_eval_b<<<static_cast<unsigned>((mbase[n] + 255) / 256), 256, 0, s>>>(bw.desc, n, bw.mbase, to_c,
-                                                                               with_outputs);
+        eval_on(s, to_c, with_outputs);
         LAUE_CHECK_HIP(hipGetLastError());
         return LAUE_OK;
+    }
+
+    void eval_on(hipStream_t st, int to_c, int with_outputs) {
+        if (mbase[n] == 0) return;
+        k_eval_b<<<static_cast<unsigned>((mbase[n] + 255) / 256), 256, 0, st>>>(bw.desc, n, bw.mbase, to_c,
+                                                                                with_outputs);
+    }
+
+    // k_gn Gauss-Newton steps with the plan of (potentials, eps, colsE) fixed,
+    // then the forward model at the new grains for the next E-step.
+    void mstep_launches(hipStream_t st, int k_gn) {
+        for (int k = 0; k < k_gn; ++k) {
+            if (k > 0) eval_on(st, 1, 0);
+            if (mbase[n] > 0) k_mstep_acc<<<n_cols, 64, 0, st>>>(bw.cols, bw.desc, k > 0 ? 1 : 0);
+            if (gbase[n] > 0)
+                k_mstep_solve<<<static_cast<unsigned>(gbase[n]), 64, 0, st>>>(bw.desc, n, bw.gbase);
+        }
+        eval_on(st, 0, 1);
     }
 
     // control blocks at temperature eps[k] from the potentials' bins
@@ -1043,24 +1089,29 @@ struct BatchEngine {
         return LAUE_OK;
     }
 
-    // k_gn Gauss-Newton steps with the plan of (potentials, eps, colsE) fixed.
-    int mstep(int k_gn) {
+    // k_gn Gauss-Newton steps with the plan of (potentials, eps, colsE) fixed
+    // (launch mode 2: one captured graph), then the forward evaluation for
+    // the next E-step (eval_next) or none (a lone M-step call).
+    int mstep(int k_gn, bool eval_next) {
         int rc;
         if ((rc = timer_start())) return rc;
-        for (int k = 0; k < k_gn; ++k) {
-            if (k > 0 && (rc = eval(1, 0))) return rc;
-            if (mbase[n] > 0) {
-                k_mstep_acc<<<n_cols, 64, 0, s>>>(bw.cols, bw.desc, k > 0 ? 1 : 0);
-                LAUE_CHECK_HIP(hipGetLastError());
+        if (eval_next && current_mode() == 2) {
+            hipGraphExec_t gx = nullptr;
+            if ((rc = mstep_graph(k_gn, &gx))) return rc;
+            LAUE_CHECK_HIP(hipGraphLaunch(gx, s));
+        } else {
+            for (int k = 0; k < k_gn; ++k) {
+                if (k > 0) eval_on(s, 1, 0);
+                if (mbase[n] > 0) k_mstep_acc<<<n_cols, 64, 0, s>>>(bw.cols, bw.desc, k > 0 ? 1 : 0);
+                if (gbase[n] > 0)
+                    k_mstep_solve<<<static_cast<unsigned>(gbase[n]), 64, 0, s>>>(bw.desc, n, bw.gbase);
             }
-            if (gbase[n] > 0) {
-                k_mstep_solve<<<static_cast<unsigned>(gbase[n]), 64, 0, s>>>(bw.desc, n, bw.gbase);
-                LAUE_CHECK_HIP(hipGetLastError());
-            }
-            for (int j = 0; j < n; ++j) {
-                entries[j] += plans[j].entries;
-                m_entries[j] += plans[j].entries;
-            }
+            if (eval_next) eval_on(s, 0, 1);
+            LAUE_CHECK_HIP(hipGetLastError());
+        }
+        for (int j = 0; j < n; ++j) {
+            entries[j] += plans[j].entries * k_gn;
+            m_entries[j] += plans[j].entries * k_gn;
         }
         return timer_stop(&mstep_ms);
     }
@@ -1092,7 +1143,7 @@ static int run_em(BatchEngine &e, const std::vector<const laue_em_params *> &par
                             : par[k]->eps_start * std::pow(par[k]->eps_end / par[k]->eps_start,
                                                            static_cast<double>(st) / (S - 1));
         for (int it = 0; it < par[0]->iters_per_stage; ++it) {
-            if ((rc = e.eval(0, 1))) return rc;
+            if (st == 0 && it == 0 && (rc = e.eval(0, 1))) return rc;    // later: after each M-step
             if ((rc = e.sinkhorn(eps, par[0]->ot.chunk, os, st))) return rc;
             for (int k = 0; k < n; ++k) {
                 stats[k].sinkhorn_iters += os[k].n_iter;
@@ -1100,12 +1151,13 @@ static int run_em(BatchEngine &e, const std::vector<const laue_em_params *> &par
                 stats[k].last_err = os[k].err;
                 stats[k].n_em_iter += 1;
             }
-            // all samples share k_gn (checked by the caller)
-            if ((rc = e.mstep(par[0]->gn.k_gn))) return rc;
+            // all samples share k_gn (checked by the caller); the M-step ends
+            // with the forward evaluation at the new grains
+            if ((rc = e.mstep(par[0]->gn.k_gn, true))) return rc;
         }
     }
     // assignments at the final grains with the final potentials
-    if ((rc = e.eval(0, 1)) || (rc = e.assign())) return rc;
+    if ((rc = e.assign())) return rc;
     for (int k = 0; k < n; ++k) {
         stats[k].cost_entries = e.entries[k];
         stats[k].sinkhorn_ms = e.sink_ms;
@@ -1278,7 +1330,7 @@ extern "C" int laue_mstep(const laue_geometry *geom, const laue_planes *planes,
                       ws_bytes, stream, true)))
         return rc;
     if ((rc = launch_pack(model, e.sw[0].colsE, e.s))) return rc;
-    if ((rc = e.grain_prep()) || (rc = e.init_ctl({par->eps})) || (rc = e.mstep(gn->k_gn))) return rc;
+    if ((rc = e.grain_prep()) || (rc = e.init_ctl({par->eps})) || (rc = e.mstep(gn->k_gn, false))) return rc;
     LAUE_CHECK_HIP(hipStreamSynchronize(e.s));
     return LAUE_OK;
 }
