@@ -286,6 +286,8 @@ def main():
     ap.add_argument("--batch-samples", type=int, default=64)
     ap.add_argument("--index-workload", default="medium", choices=["medium", "learned"])
     ap.add_argument("--index-pairs", type=int, default=4096)
+    ap.add_argument("--tile", type=int, default=0, choices=[0, 1, 2],
+                    help="Sinkhorn tile shape: 1 or 2 spots per lane, 0 tuned per call")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy 1 GiB device to device three times (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -322,7 +324,7 @@ def main():
     def step(k):
         eps = eps_list[k % n_sched]
         ot = laue.ot_params(eps, preset.distance, c_out, t_b, tol=1e-5, n_max=2000)
-        par = laue.em_params(ot, eps, eps, 1, 1, k_gn=2)
+        par = laue.em_params(ot, eps, eps, 1, 1, k_gn=2, tile=args.tile)
         out = laue.laue_em(geom, planes, obs, model, par, grains, f, g, pot["f0"], pot["g0"], assign=False)
         pot["f0"], pot["g0"] = out["f0"], out["g0"]
         return out
@@ -368,6 +370,8 @@ def main():
         "em_iters_per_s": args.steps / dt,
         "sinkhorn_iters": int(sum(s["sinkhorn_iters"] for s in stats)),
         "sinkhorn_capped": int(sum(s["not_converged"] for s in stats)),
+        "tile": {"requested": args.tile, "two_per_lane_solves": int(sum(s["tile2_solves"] for s in stats)),
+                 "solves": len(stats)},
         "roofline": {"kernel": "Sinkhorn row/column pass (k_row, k_col)", "bound": "alu",
                      "achieved": achieved / 1e9, "peak": PEAK_ENTRIES_PER_S / 1e9,
                      "unit": "Gentries/s", "frac": achieved / PEAK_ENTRIES_PER_S,

@@ -302,6 +302,11 @@ typedef struct laue_em_params {
      * with ot.chunk == 0 the chunk of each temperature stage is sized from the
      * iterations that stage needed in the previous EM iteration */
     int32_t launch;
+    /* tile shape of the Sinkhorn passes: 1 one detected (model) spot per lane,
+     * 2 two per lane sharing each streamed load, 0 tune per temperature stage
+     * (the first row + column pass of a stage's Sinkhorns is timed in each
+     * shape and the faster kept); every shape gives the same result */
+    int32_t tile;
 } laue_em_params;
 
 typedef struct laue_em_stats {
@@ -319,6 +324,7 @@ typedef struct laue_em_stats {
     int64_t mstep_entries;
     int32_t launch_used;        /* 1 direct launches, 2 graph replay */
     int32_t polls;              /* host polls of the Sinkhorn control blocks */
+    int32_t tile2_solves;       /* Sinkhorn solves run in the two-per-lane shape */
 } laue_em_stats;
 
 /* Per detected spot (device, may be NULL): j_star = argmax over its block's

@@ -336,13 +336,14 @@ def laue_mstep(geom, planes, obs, model, ot, f, g, grains, k_gn=2, mu_rel=1e-9):
     return steps[:grains.n]
 
 
-def em_params(ot, eps_start, eps_end, n_stages, iters_per_stage, k_gn=2, mu_rel=1e-9, launch=0):
+def em_params(ot, eps_start, eps_end, n_stages, iters_per_stage, k_gn=2, mu_rel=1e-9, launch=0, tile=0):
     p = laue_em_params()
     p.ot = ot
     p.gn = laue_gn_params(int(k_gn), float(mu_rel))
     p.eps_start, p.eps_end = float(eps_start), float(eps_end)
     p.n_stages, p.iters_per_stage = int(n_stages), int(iters_per_stage)
     p.launch = int(launch)
+    p.tile = int(tile)
     return p
 
 
@@ -374,7 +375,8 @@ def laue_em(geom, planes, obs, model, par, grains, f=None, g=None, f0=0.0, g0=0.
            "not_converged": st.not_converged, "last_err": st.last_err,
            "sinkhorn_ms": st.sinkhorn_ms, "sinkhorn_passes": st.sinkhorn_passes,
            "sinkhorn_entries": st.sinkhorn_entries, "mstep_ms": st.mstep_ms,
-           "mstep_entries": st.mstep_entries, "launch_used": st.launch_used, "polls": st.polls}
+           "mstep_entries": st.mstep_entries, "launch_used": st.launch_used, "polls": st.polls,
+           "tile2_solves": st.tile2_solves}
     if assign:
         out.update({k: v[:obs.n] for k, v in asg_t.items()})
     return out

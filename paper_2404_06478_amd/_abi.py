@@ -70,7 +70,7 @@ class laue_gn_params(C.Structure):
 class laue_em_params(C.Structure):
     _fields_ = [("ot", laue_ot_params), ("gn", laue_gn_params), ("eps_start", C.c_double),
                 ("eps_end", C.c_double), ("n_stages", C.c_int32), ("iters_per_stage", C.c_int32),
-                ("launch", C.c_int32)]
+                ("launch", C.c_int32), ("tile", C.c_int32)]
 
 
 class laue_em_stats(C.Structure):
@@ -78,7 +78,8 @@ class laue_em_stats(C.Structure):
                 ("cost_entries", C.c_int64), ("not_converged", C.c_int32), ("last_err", C.c_double),
                 ("sinkhorn_ms", C.c_double), ("sinkhorn_passes", C.c_int64),
                 ("sinkhorn_entries", C.c_int64), ("mstep_ms", C.c_double),
-                ("mstep_entries", C.c_int64), ("launch_used", C.c_int32), ("polls", C.c_int32)]
+                ("mstep_entries", C.c_int64), ("launch_used", C.c_int32), ("polls", C.c_int32),
+                ("tile2_solves", C.c_int32)]
 
 
 class laue_assignments(C.Structure):

@@ -67,7 +67,8 @@ struct SampleDesc {
     Col8 *colsE, *colsC;           // packed columns: plan geometry / current geometry
     SinkCtl *ctl;
     double2 *part;                 // per-item partials of a pass
-    int n_row_items, n_col_items;
+    int n_row_items, n_col_items;  // 64-row / 64-column items
+    int n_row_wg2, n_col_wg2;      // workgroups of the two-per-lane tile shape
     SinkParams sp;
     const int *mplane, *mgrain, *mblock;
     float *s1, *s2, *vn, *v1, *v2, *lam;   // forward-model outputs (may be NULL)
@@ -180,12 +181,19 @@ __global__ __launch_bounds__(256) void k_cs_init(const SampleDesc *__restrict__ 
 // The pass bodies take the sample's arrays as restrict-qualified parameters:
 // inlined into the kernels they keep their no-alias scopes, so the
 // wave-uniform streams (columns, potentials) stay scalar loads.
-__device__ __forceinline__ void row_pass(const Item &it, const LAUE_GLOBAL float *__restrict__ P1,
+// Tile shapes: R = 1 (one detected spot per lane, 64-row workgroups) or
+// R = 2 (two adjacent 64-row items of one block per workgroup, two rows per
+// lane sharing every column load).  Each 64-row item keeps its own partial and
+// per-row arithmetic, so both shapes give identical results; the sample's
+// ticket counts the workgroups of the launched shape (n_wg), its finalisation
+// sums the partials of all 64-row items (n_items).
+template <int R>
+__device__ __forceinline__ void row_pass(const Item *its, const LAUE_GLOBAL float *__restrict__ P1,
                                          const LAUE_GLOBAL float *__restrict__ P2,
                                          const LAUE_GLOBAL Col8 *__restrict__ cols,
                                          const LAUE_GLOBAL float *__restrict__ G, LAUE_GLOBAL float *__restrict__ F0,
                                          LAUE_GLOBAL float *__restrict__ F1, SinkCtl *__restrict__ ctl,
-                                         double2 *__restrict__ part, const SinkParams &p, int n_items) {
+                                         double2 *__restrict__ part, const SinkParams &p, int n_wg, int n_items) {
     if (ctl->done) return;
     const int k = ctl->iter + 1;
     const LAUE_GLOBAL float *Fin = ((k - 1) & 1) ? F1 : F0;
@@ -195,58 +203,82 @@ __device__ __forceinline__ void row_pass(const Item &it, const LAUE_GLOBAL float
     const float kx = static_cast<float>(kexp);
     const float K = p.twoD2 * kx;
     const double g0 = ctl->g0[(k - 1) & 1];
-    const int i = it.r0 + static_cast<int>(threadIdx.x);
-    const bool act = i < it.r1;
-    const float p1 = act ? P1[i] : 0.0f;
-    const float p2 = act ? P2[i] : 0.0f;
-    const float f = act ? Fin[i] : 0.0f;
-    const float fk = f * kx;
-    double acc = 0.0;
-    for (int j0 = it.c0; j0 < it.c1; j0 += 64) {
-        const int j1 = min(j0 + 64, it.c1);
-        float a = 0.0f;
+    const int c0 = its[0].c0, c1 = its[0].c1;
+    int i[R];
+    bool act[R];
+    float p1[R], p2[R], f[R], fk[R];
+    double acc[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        i[r] = its[r].r0 + static_cast<int>(threadIdx.x);
+        act[r] = i[r] < its[r].r1;
+        p1[r] = act[r] ? P1[i[r]] : 0.0f;
+        p2[r] = act[r] ? P2[i[r]] : 0.0f;
+        f[r] = act[r] ? Fin[i[r]] : 0.0f;
+        fk[r] = f[r] * kx;
+        acc[r] = 0.0;
+    }
+    for (int j0 = c0; j0 < c1; j0 += 64) {
+        const int j1 = min(j0 + 64, c1);
+        float a[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) a[r] = 0.0f;
 #pragma unroll 4
         for (int j = j0; j < j1; ++j) {
             const Col8 c = ld_col(cols + j);
-            const float base = fmaf(G[j], kx, fk);
-            a += fast_exp2(entry_exponent(p1, p2, c.s1, c.s2, c.v1, c.v2, c.vv, c.vv2, K, base));
+            const float gj = G[j];
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+                a[r] += fast_exp2(entry_exponent(p1[r], p2[r], c.s1, c.s2, c.v1, c.v2, c.vv, c.vv2, K,
+                                                 fmaf(gj, kx, fk[r])));
         }
-        acc += static_cast<double>(a);
+#pragma unroll
+        for (int r = 0; r < R; ++r) acc[r] += static_cast<double>(a[r]);
     }
-    const double eb = (g0 - p.c_out) * kexp + static_cast<double>(fk);
-    acc += exp2(eb);
-    double logS;
-    const bool slow = act && !(acc > 1e-30);
-    if (__any(slow)) {
+    double eb[R], logS[R];
+    bool slow[R], any_slow = false;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        eb[r] = (g0 - p.c_out) * kexp + static_cast<double>(fk[r]);
+        acc[r] += exp2(eb[r]);
+        slow[r] = act[r] && !(acc[r] > 1e-30);
+        any_slow = any_slow || slow[r];
+        logS[r] = log(acc[r]);
+    }
+    if (__any(any_slow)) {
         // every term underflowed: recompute with the row maximum as shift
-        float mx = static_cast<float>(eb);
-        for (int j = it.c0; j < it.c1; ++j) {
-            const Col8 c = ld_col(cols + j);
-            mx = fmaxf(mx, entry_exponent(p1, p2, c.s1, c.s2, c.v1, c.v2, c.vv, c.vv2, K,
-                                          fmaf(G[j], kx, fk)));
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            float mx = static_cast<float>(eb[r]);
+            for (int j = c0; j < c1; ++j) {
+                const Col8 c = ld_col(cols + j);
+                mx = fmaxf(mx, entry_exponent(p1[r], p2[r], c.s1, c.s2, c.v1, c.v2, c.vv, c.vv2, K,
+                                              fmaf(G[j], kx, fk[r])));
+            }
+            double s2 = exp2(eb[r] - mx);
+            for (int j = c0; j < c1; ++j) {
+                const Col8 c = ld_col(cols + j);
+                s2 += exp2(static_cast<double>(entry_exponent(p1[r], p2[r], c.s1, c.s2, c.v1, c.v2, c.vv,
+                                                              c.vv2, K, fmaf(G[j], kx, fk[r])) - mx));
+            }
+            if (slow[r]) logS[r] = log(s2) + static_cast<double>(mx) * 0.6931471805599453;
         }
-        double s2 = exp2(eb - mx);
-        for (int j = it.c0; j < it.c1; ++j) {
-            const Col8 c = ld_col(cols + j);
-            s2 += exp2(static_cast<double>(entry_exponent(p1, p2, c.s1, c.s2, c.v1, c.v2, c.vv,
-                                                          c.vv2, K, fmaf(G[j], kx, fk)) - mx));
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        double err = act[r] ? fabs(acc[r] - 1.0) : 0.0;
+        const double fn = static_cast<double>(f[r]) - eps * logS[r];
+        double rs = 0.0;
+        if (act[r]) {
+            const float fnf = static_cast<float>(fn);
+            Fout[i[r]] = fnf;
+            rs = exp((static_cast<double>(fnf) + g0 - p.c_out) / eps);
         }
-        logS = slow ? log(s2) + static_cast<double>(mx) * 0.6931471805599453 : log(acc);
-    } else {
-        logS = log(acc);
+        rs = wave_sum(rs);
+        err = wave_max(err);
+        if (threadIdx.x == 0 && its[r].local >= 0) part[its[r].local] = make_double2(rs, err);
     }
-    double err = act ? fabs(acc - 1.0) : 0.0;
-    const double fn = static_cast<double>(f) - eps * logS;
-    double rs = 0.0;
-    if (act) {
-        const float fnf = static_cast<float>(fn);
-        Fout[i] = fnf;
-        rs = exp((static_cast<double>(fnf) + g0 - p.c_out) / eps);
-    }
-    rs = wave_sum(rs);
-    err = wave_max(err);
-    if (threadIdx.x == 0) part[it.local] = make_double2(rs, err);
-    if (!last_block(ctl, n_items)) return;
+    if (!last_block(ctl, n_wg)) return;
     double rsum = 0.0, emax = 0.0;
     for (int w = threadIdx.x; w < n_items; w += 64) {
         rsum += part[w].x;
@@ -287,27 +319,44 @@ __device__ __forceinline__ void row_pass(const Item &it, const LAUE_GLOBAL float
     }
 }
 
-__global__ __launch_bounds__(64) void k_row(const Item *__restrict__ items,
+// the items of one workgroup of shape R: groups[w] = (first item, second item or -1)
+template <int R>
+__device__ __forceinline__ void group_items(const Item *__restrict__ items, const int2 *__restrict__ groups,
+                                            Item *its) {
+    if constexpr (R == 1) {
+        its[0] = items[blockIdx.x];
+    } else {
+        const int2 gp = groups[blockIdx.x];
+        its[0] = items[gp.x];
+        its[R - 1] = gp.y >= 0 ? items[gp.y] : Item{0, 0, 0, 0, its[0].s, -1, {0, 0}};
+    }
+}
+
+template <int R>
+__global__ __launch_bounds__(64) void k_row(const Item *__restrict__ items, const int2 *__restrict__ groups,
                                             const SampleDesc *__restrict__ descs) {
-    const Item it = items[blockIdx.x];
-    const SampleDesc &D = descs[it.s];
-    row_pass(it, gptr(D.p1), gptr(D.p2), gptr(D.colsE), gptr(D.g), gptr(D.f), gptr(D.f1), D.ctl, D.part, D.sp,
-             D.n_row_items);
+    Item its[R];
+    group_items<R>(items, groups, its);
+    const SampleDesc &D = descs[its[0].s];
+    row_pass<R>(its, gptr(D.p1), gptr(D.p2), gptr(D.colsE), gptr(D.g), gptr(D.f), gptr(D.f1), D.ctl, D.part,
+                D.sp, R == 1 ? D.n_row_items : D.n_row_wg2, D.n_row_items);
 }
 
 // ---------------------------------------------------------------- column pass
 
-// Column half of iteration k = iter for 64 model spots of one block: each
-// lane streams the block's detected spots with g_j^{k-1} as shift (terms are
-// entries of the plan after the row half, <= 1) and sets
-// g_j^k = g_j^{k-1} - eps ln(column marginal).  The sample's last workgroup
-// stores sum_j exp((f0 + g_j - c_unm)/eps) for the next row half.
-__device__ __forceinline__ void col_pass(const Item &it, const LAUE_GLOBAL float *__restrict__ P1,
+// Column half of iteration k = iter for 64 model spots of one block (R = 2:
+// two adjacent 64-column items per workgroup, two columns per lane sharing
+// every row load): each lane streams the block's detected spots with
+// g_j^{k-1} as shift (terms are entries of the plan after the row half, <= 1)
+// and sets g_j^k = g_j^{k-1} - eps ln(column marginal).  The sample's last
+// workgroup stores sum_j exp((f0 + g_j - c_unm)/eps) for the next row half.
+template <int R>
+__device__ __forceinline__ void col_pass(const Item *its, const LAUE_GLOBAL float *__restrict__ P1,
                                          const LAUE_GLOBAL float *__restrict__ P2,
                                          const LAUE_GLOBAL Col8 *__restrict__ cols, LAUE_GLOBAL float *__restrict__ G,
                                          const LAUE_GLOBAL float *__restrict__ F0,
                                          const LAUE_GLOBAL float *__restrict__ F1, SinkCtl *__restrict__ ctl,
-                                         double2 *__restrict__ part, const SinkParams &p, int n_items) {
+                                         double2 *__restrict__ part, const SinkParams &p, int n_wg, int n_items) {
     if (ctl->done) return;
     const int k = ctl->iter;
     const LAUE_GLOBAL float *__restrict__ F = (k & 1) ? F1 : F0;
@@ -316,53 +365,78 @@ __device__ __forceinline__ void col_pass(const Item &it, const LAUE_GLOBAL float
     const float kx = static_cast<float>(kexp);
     const float K = p.twoD2 * kx;
     const double f0 = ctl->f0[k & 1];
-    const int j = it.c0 + static_cast<int>(threadIdx.x);
-    const bool act = j < it.c1;
-    Col8 c = {0, 0, 0, 0, 1, 1, 1, 0};
-    float g = 0.0f;
-    if (act) {
-        c = ld_col(cols + j);
-        g = G[j];
+    const int r0 = its[0].r0, r1 = its[0].r1;
+    int j[R];
+    bool act[R];
+    Col8 c[R];
+    float g[R], gk[R];
+    double acc[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        j[r] = its[r].c0 + static_cast<int>(threadIdx.x);
+        act[r] = j[r] < its[r].c1;
+        c[r] = Col8{0, 0, 0, 0, 1, 1, 1, 0};
+        g[r] = 0.0f;
+        if (act[r]) {
+            c[r] = ld_col(cols + j[r]);
+            g[r] = G[j[r]];
+        }
+        gk[r] = g[r] * kx;
+        acc[r] = 0.0;
     }
-    const float gk = g * kx;
-    double acc = 0.0;
-    for (int i0 = it.r0; i0 < it.r1; i0 += 64) {
-        const int i1 = min(i0 + 64, it.r1);
-        float a = 0.0f;
+    for (int i0 = r0; i0 < r1; i0 += 64) {
+        const int i1 = min(i0 + 64, r1);
+        float a[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) a[r] = 0.0f;
 #pragma unroll 4
         for (int i = i0; i < i1; ++i) {
-            const float base = fmaf(F[i], kx, gk);
-            a += fast_exp2(entry_exponent(P1[i], P2[i], c.s1, c.s2, c.v1, c.v2, c.vv, c.vv2, K, base));
+            const float pi1 = P1[i], pi2 = P2[i], fi = F[i];
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+                a[r] += fast_exp2(entry_exponent(pi1, pi2, c[r].s1, c[r].s2, c[r].v1, c[r].v2, c[r].vv, c[r].vv2, K,
+                                                 fmaf(fi, kx, gk[r])));
         }
-        acc += static_cast<double>(a);
+#pragma unroll
+        for (int r = 0; r < R; ++r) acc[r] += static_cast<double>(a[r]);
     }
-    const double eb = (f0 - p.c_unm) * kexp + static_cast<double>(gk);
-    acc += exp2(eb);
-    double logS;
-    const bool slow = act && !(acc > 1e-30);
-    if (__any(slow)) {
-        float mx = static_cast<float>(eb);
-        for (int i = it.r0; i < it.r1; ++i)
-            mx = fmaxf(mx, entry_exponent(P1[i], P2[i], c.s1, c.s2, c.v1, c.v2, c.vv, c.vv2, K,
-                                          fmaf(F[i], kx, gk)));
-        double s2 = exp2(eb - mx);
-        for (int i = it.r0; i < it.r1; ++i)
-            s2 += exp2(static_cast<double>(entry_exponent(P1[i], P2[i], c.s1, c.s2, c.v1, c.v2,
-                                                          c.vv, c.vv2, K, fmaf(F[i], kx, gk))) -
-                       mx);
-        logS = slow ? log(s2) + static_cast<double>(mx) * 0.6931471805599453 : log(acc);
-    } else {
-        logS = log(acc);
+    double eb[R], logS[R];
+    bool slow[R], any_slow = false;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        eb[r] = (f0 - p.c_unm) * kexp + static_cast<double>(gk[r]);
+        acc[r] += exp2(eb[r]);
+        slow[r] = act[r] && !(acc[r] > 1e-30);
+        any_slow = any_slow || slow[r];
+        logS[r] = log(acc[r]);
     }
-    double cs = 0.0;
-    if (act) {
-        const float gn = static_cast<float>(static_cast<double>(g) - eps * logS);
-        G[j] = gn;
-        cs = exp((f0 + static_cast<double>(gn) - p.c_unm) / eps);
+    if (__any(any_slow)) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            float mx = static_cast<float>(eb[r]);
+            for (int i = r0; i < r1; ++i)
+                mx = fmaxf(mx, entry_exponent(P1[i], P2[i], c[r].s1, c[r].s2, c[r].v1, c[r].v2, c[r].vv, c[r].vv2, K,
+                                              fmaf(F[i], kx, gk[r])));
+            double s2 = exp2(eb[r] - mx);
+            for (int i = r0; i < r1; ++i)
+                s2 += exp2(static_cast<double>(entry_exponent(P1[i], P2[i], c[r].s1, c[r].s2, c[r].v1, c[r].v2,
+                                                              c[r].vv, c[r].vv2, K, fmaf(F[i], kx, gk[r]))) -
+                           mx);
+            if (slow[r]) logS[r] = log(s2) + static_cast<double>(mx) * 0.6931471805599453;
+        }
     }
-    cs = wave_sum(cs);
-    if (threadIdx.x == 0) part[it.local] = make_double2(cs, 0.0);
-    if (!last_block(ctl, n_items)) return;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        double cs = 0.0;
+        if (act[r]) {
+            const float gn = static_cast<float>(static_cast<double>(g[r]) - eps * logS[r]);
+            G[j[r]] = gn;
+            cs = exp((f0 + static_cast<double>(gn) - p.c_unm) / eps);
+        }
+        cs = wave_sum(cs);
+        if (threadIdx.x == 0 && its[r].local >= 0) part[its[r].local] = make_double2(cs, 0.0);
+    }
+    if (!last_block(ctl, n_wg)) return;
     double t = 0.0;
     for (int w = threadIdx.x; w < n_items; w += 64) t += part[w].x;
     t = wave_sum(t);
@@ -372,12 +446,14 @@ __device__ __forceinline__ void col_pass(const Item &it, const LAUE_GLOBAL float
     }
 }
 
-__global__ __launch_bounds__(64) void k_col(const Item *__restrict__ items,
+template <int R>
+__global__ __launch_bounds__(64) void k_col(const Item *__restrict__ items, const int2 *__restrict__ groups,
                                             const SampleDesc *__restrict__ descs) {
-    const Item it = items[blockIdx.x];
-    const SampleDesc &D = descs[it.s];
-    col_pass(it, gptr(D.p1), gptr(D.p2), gptr(D.colsE), gptr(D.g), gptr(D.f), gptr(D.f1), D.ctl, D.part, D.sp,
-             D.n_col_items);
+    Item its[R];
+    group_items<R>(items, groups, its);
+    const SampleDesc &D = descs[its[0].s];
+    col_pass<R>(its, gptr(D.p1), gptr(D.p2), gptr(D.colsE), gptr(D.g), gptr(D.f), gptr(D.f1), D.ctl, D.part,
+                D.sp, R == 1 ? D.n_col_items : D.n_col_wg2, D.n_col_items);
 }
 
 // ---------------------------------------------------------------- assign
@@ -636,6 +712,7 @@ struct BatchWs {
     SampleDesc *desc;
     SinkCtl *ctl;
     Item *rows, *cols;
+    int2 *rows2, *cols2;      // workgroups of the two-per-lane tile shape
     int64_t *mbase, *gbase;
     CtlInit *init;
 };
@@ -648,6 +725,8 @@ static size_t carve_all(Carver &cv, BatchWs &bw, std::vector<SampleWs> &sw, cons
     bw.ctl = cv.take<SinkCtl>(std::max(n, 1));
     bw.rows = cv.take<Item>(std::max<size_t>(items, 1));
     bw.cols = cv.take<Item>(std::max<size_t>(items, 1));
+    bw.rows2 = cv.take<int2>(std::max<size_t>(items, 1));
+    bw.cols2 = cv.take<int2>(std::max<size_t>(items, 1));
     bw.mbase = cv.take<int64_t>(n + 1);
     bw.gbase = cv.take<int64_t>(n + 1);
     bw.init = cv.take<CtlInit>(std::max(n, 1));
@@ -717,6 +796,7 @@ static int validate_em_params(const laue_em_params *par) {
     LAUE_REQUIRE(par->gn.k_gn >= 0 && std::isfinite(par->gn.mu_rel) && par->gn.mu_rel >= 0,
                  LAUE_EINVAL, "bad Gauss-Newton parameters");
     LAUE_REQUIRE(par->launch >= 0 && par->launch <= 2, LAUE_EINVAL, "launch must be 0, 1 or 2");
+    LAUE_REQUIRE(par->tile >= 0 && par->tile <= 2, LAUE_EINVAL, "tile must be 0, 1 or 2");
     return LAUE_OK;
 }
 
@@ -744,7 +824,7 @@ struct BatchEngine {
     std::vector<SampleDesc> hd;
     std::vector<SamplePlan> plans;
     std::vector<int64_t> mbase, gbase;
-    int n_rows = 0, n_cols = 0;
+    int n_rows = 0, n_cols = 0, n_rows2 = 0, n_cols2 = 0;
     // per sample: streamed entries, Sinkhorn passes and their entries, M-step entries
     std::vector<int64_t> entries, passes, pass_entries, m_entries;
     std::vector<SinkCtl> hctl;
@@ -758,6 +838,12 @@ struct BatchEngine {
     int mgraph_kgn = -1;
     hipStream_t cap_stream = nullptr;
     std::vector<int> stage_iters;               // iterations of the latest Sinkhorn of each stage
+    // tile shape (1 or 2 rows / columns per lane): fixed, or tuned per stage
+    // on the first row + column pass of a Sinkhorn (which always works)
+    int tile_mode = 1;
+    std::vector<int> stage_tile;
+    std::vector<int> tiles_used;
+    hipEvent_t tev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
 
     ~BatchEngine() {
         if (!graphs.empty()) (void)hipStreamSynchronize(s);
@@ -767,23 +853,37 @@ struct BatchEngine {
         if (cap_stream) (void)hipStreamDestroy(cap_stream);
         if (ev0) (void)hipEventDestroy(ev0);
         if (ev1) (void)hipEventDestroy(ev1);
+        for (auto e : tev)
+            if (e) (void)hipEventDestroy(e);
     }
 
     // A captured graph of `chunk` Sinkhorn iterations (row and column pass of
     // every sample); the passes read their state from the control blocks, so
     // one graph serves every chunk, temperature and EM iteration of the call.
-    int graph_for(int chunk, hipGraphExec_t *out) {
+    // one row pass and one column pass in tile shape R (empty grids skipped)
+    void row_launch(hipStream_t st, int R) {
+        if (R == 2 && n_rows2) k_row<2><<<n_rows2, 64, 0, st>>>(bw.rows, bw.rows2, bw.desc);
+        if (R == 1 && n_rows) k_row<1><<<n_rows, 64, 0, st>>>(bw.rows, bw.rows2, bw.desc);
+    }
+    void col_launch(hipStream_t st, int R) {
+        if (R == 2 && n_cols2) k_col<2><<<n_cols2, 64, 0, st>>>(bw.cols, bw.cols2, bw.desc);
+        if (R == 1 && n_cols) k_col<1><<<n_cols, 64, 0, st>>>(bw.cols, bw.cols2, bw.desc);
+    }
+    void pass_pair(hipStream_t st, int R) {
+        row_launch(st, R);
+        col_launch(st, R);
+    }
+
+    int graph_for(int chunk, int R, hipGraphExec_t *out) {
+        const int key = 4 * chunk + R;
         for (auto &g : graphs)
-            if (g.first == chunk) {
+            if (g.first == key) {
                 *out = g.second;
                 return LAUE_OK;
             }
         if (!cap_stream) LAUE_CHECK_HIP(hipStreamCreateWithFlags(&cap_stream, hipStreamNonBlocking));
         LAUE_CHECK_HIP(hipStreamBeginCapture(cap_stream, hipStreamCaptureModeThreadLocal));
-        for (int c = 0; c < chunk; ++c) {
-            k_row<<<n_rows, 64, 0, cap_stream>>>(bw.rows, bw.desc);
-            k_col<<<n_cols, 64, 0, cap_stream>>>(bw.cols, bw.desc);
-        }
+        for (int c = 0; c < chunk; ++c) pass_pair(cap_stream, R);
         const hipError_t le = hipGetLastError();
         hipGraph_t g = nullptr;
         const hipError_t ce = hipStreamEndCapture(cap_stream, &g);
@@ -793,7 +893,7 @@ struct BatchEngine {
         const hipError_t ie = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
         (void)hipGraphDestroy(g);
         LAUE_CHECK_HIP(ie);
-        graphs.emplace_back(chunk, x);
+        graphs.emplace_back(key, x);
         *out = x;
         return LAUE_OK;
     }
@@ -947,8 +1047,31 @@ struct BatchEngine {
                          [](const Item &a, const Item &b) { return (a.r1 - a.r0) > (b.r1 - b.r0); });
         n_rows = static_cast<int>(rows.size());
         n_cols = static_cast<int>(cols.size());
+        // two-per-lane workgroups: adjacent items of one block and sample
+        // (after the stable sort the items of a block stay contiguous)
+        std::vector<int2> rows2, cols2;
+        auto pair_up = [&](const std::vector<Item> &v, bool by_rows, std::vector<int2> &out, bool row_side) {
+            for (size_t k = 0; k < v.size();) {
+                const Item &a = v[k];
+                bool pair = false;
+                if (k + 1 < v.size()) {
+                    const Item &b = v[k + 1];
+                    pair = b.s == a.s && (by_rows ? (b.c0 == a.c0 && b.c1 == a.c1 && b.r0 == a.r1 && a.r1 > a.r0)
+                                                  : (b.r0 == a.r0 && b.r1 == a.r1 && b.c0 == a.c1 && a.c1 > a.c0));
+                }
+                out.push_back(make_int2(static_cast<int>(k), pair ? static_cast<int>(k + 1) : -1));
+                if (row_side) hd[a.s].n_row_wg2 += 1; else hd[a.s].n_col_wg2 += 1;
+                k += pair ? 2 : 1;
+            }
+        };
+        pair_up(rows, true, rows2, true);
+        pair_up(cols, false, cols2, false);
+        n_rows2 = static_cast<int>(rows2.size());
+        n_cols2 = static_cast<int>(cols2.size());
         LAUE_CHECK_HIP(hipMemcpyAsync(bw.rows, rows.data(), rows.size() * sizeof(Item), hipMemcpyHostToDevice, s));
         LAUE_CHECK_HIP(hipMemcpyAsync(bw.cols, cols.data(), cols.size() * sizeof(Item), hipMemcpyHostToDevice, s));
+        LAUE_CHECK_HIP(hipMemcpyAsync(bw.rows2, rows2.data(), rows2.size() * sizeof(int2), hipMemcpyHostToDevice, s));
+        LAUE_CHECK_HIP(hipMemcpyAsync(bw.cols2, cols2.data(), cols2.size() * sizeof(int2), hipMemcpyHostToDevice, s));
         LAUE_CHECK_HIP(hipMemcpyAsync(bw.desc, hd.data(), n * sizeof(SampleDesc), hipMemcpyHostToDevice, s));
         LAUE_CHECK_HIP(hipMemcpyAsync(bw.mbase, mbase.data(), (n + 1) * sizeof(int64_t), hipMemcpyHostToDevice, s));
         LAUE_CHECK_HIP(hipMemcpyAsync(bw.gbase, gbase.data(), (n + 1) * sizeof(int64_t), hipMemcpyHostToDevice, s));
@@ -1025,19 +1148,47 @@ struct BatchEngine {
         }
         int cap = 0;
         for (int k = 0; k < n; ++k) cap = std::max(cap, hd[k].sp.n_max);
+        // tile shape of this Sinkhorn.  Tuning (the first Sinkhorn of a stage)
+        // times row pass 1 in the one-per-lane shape and row pass 2 in the
+        // two-per-lane shape: both always run in full (convergence is decided
+        // at the end of a row pass from iteration 2 on), and the stage keeps
+        // the faster shape.
+        const int si = std::max(stage, 0);
+        if (si >= static_cast<int>(stage_tile.size())) stage_tile.resize(si + 1, 0);
         int launched = 0;
+        if (tile_mode == 0 && stage_tile[si] == 0) {
+            if (!tev[0])
+                for (auto &e : tev) LAUE_CHECK_HIP(hipEventCreate(&e));
+            LAUE_CHECK_HIP(hipEventRecord(tev[0], s));
+            row_launch(s, 1);
+            LAUE_CHECK_HIP(hipEventRecord(tev[1], s));
+            col_launch(s, 1);
+            LAUE_CHECK_HIP(hipEventRecord(tev[2], s));
+            row_launch(s, 2);
+            LAUE_CHECK_HIP(hipEventRecord(tev[3], s));
+            col_launch(s, 2);
+            LAUE_CHECK_HIP(hipEventRecord(tev[4], s));
+            LAUE_CHECK_HIP(hipGetLastError());
+            LAUE_CHECK_HIP(hipEventSynchronize(tev[4]));
+            float t1 = 0.0f, t2 = 0.0f, tall = 0.0f;
+            LAUE_CHECK_HIP(hipEventElapsedTime(&t1, tev[0], tev[1]));
+            LAUE_CHECK_HIP(hipEventElapsedTime(&t2, tev[2], tev[3]));
+            LAUE_CHECK_HIP(hipEventElapsedTime(&tall, tev[0], tev[4]));
+            sink_ms += tall;
+            stage_tile[si] = t2 < t1 ? 2 : 1;
+            launched = 2;
+        }
+        const int R = tile_mode ? tile_mode : stage_tile[si];
+        tiles_used.push_back(R);
         for (;;) {
             const int mode = current_mode();
             hipGraphExec_t gx = nullptr;
-            if (mode == 2 && (rc = graph_for(chunk, &gx))) return rc;
+            if (mode == 2 && (rc = graph_for(chunk, R, &gx))) return rc;
             if ((rc = timer_start())) return rc;
             if (mode == 2) {
                 LAUE_CHECK_HIP(hipGraphLaunch(gx, s));
             } else {
-                for (int c = 0; c < chunk; ++c) {
-                    k_row<<<n_rows, 64, 0, s>>>(bw.rows, bw.desc);
-                    k_col<<<n_cols, 64, 0, s>>>(bw.cols, bw.desc);
-                }
+                for (int c = 0; c < chunk; ++c) pass_pair(s, R);
                 LAUE_CHECK_HIP(hipGetLastError());
             }
             launched += chunk;
@@ -1134,6 +1285,7 @@ static int run_em(BatchEngine &e, const std::vector<const laue_em_params *> &par
     if ((rc = e.grain_prep())) return rc;
     stats.assign(n, laue_em_stats{});
     e.launch_mode = par[0]->launch;
+    e.tile_mode = par[0]->tile;
     const int S = par[0]->n_stages;
     std::vector<double> eps(n);
     std::vector<laue_ot_stats> os;
@@ -1167,6 +1319,9 @@ static int run_em(BatchEngine &e, const std::vector<const laue_em_params *> &par
         stats[k].mstep_entries = e.m_entries[k];
         stats[k].launch_used = e.current_mode();
         stats[k].polls = e.polls;
+        int t2 = 0;
+        for (int t : e.tiles_used) t2 += t == 2;
+        stats[k].tile2_solves = t2;
     }
     LAUE_CHECK_HIP(hipStreamSynchronize(e.s));
     return LAUE_OK;
@@ -1374,8 +1529,9 @@ extern "C" int laue_em_batched(int32_t n, const laue_geometry *geoms, const laue
         LAUE_REQUIRE(pars[k].n_stages == pars[0].n_stages && pars[k].iters_per_stage == pars[0].iters_per_stage &&
                          pars[k].gn.k_gn == pars[0].gn.k_gn,
                      LAUE_EINVAL, "samples of a batch share n_stages, iters_per_stage and k_gn");
-        LAUE_REQUIRE(pars[k].launch == pars[0].launch && pars[k].ot.chunk == pars[0].ot.chunk, LAUE_EINVAL,
-                     "samples of a batch share launch and ot.chunk");
+        LAUE_REQUIRE(pars[k].launch == pars[0].launch && pars[k].ot.chunk == pars[0].ot.chunk &&
+                         pars[k].tile == pars[0].tile,
+                     LAUE_EINVAL, "samples of a batch share launch, tile and ot.chunk");
         LAUE_REQUIRE(std::isfinite(pots[k].f0) && std::isfinite(pots[k].g0), LAUE_EINVAL,
                      "bin potentials must be finite");
         in[k] = SampleIn{geoms + k, planes + k, obs + k, models + k, &pars[k].ot, grains + k, pots + k,

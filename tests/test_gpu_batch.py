@@ -135,3 +135,55 @@ def test_batch_with_degenerate_samples(gpu_lib):
         qb, xb = s[5].numpy()
         assert np.array_equal(qx[0], qb) and np.array_equal(qx[1], xb), k
         assert o1["sinkhorn_iters"] == outs[k]["sinkhorn_iters"], k
+
+
+@pytest.mark.parametrize("n_grains", [5, 60])
+def test_tile_shapes_match(gpu_lib, n_grains):
+    """Two detected (model) spots per lane share each streamed load but keep
+    their own arithmetic: every tile shape, fixed or tuned per temperature
+    stage, with direct launches or graph replay, gives the one-per-lane result
+    bit for bit."""
+    laue = gpu_lib
+    pr = dataclasses.replace(ig.batching_samples(1)[0], n_rot=30, domega_deg=6.0)
+    p, geom, planes, obs, model, par, (q0, x0), _ = _sample(laue, pr, n_grains, 4)
+    res = {}
+    for tile, launch in ((1, 1), (2, 1), (2, 2), (0, 0)):
+        par.tile = tile
+        par.launch = launch
+        gr = laue.Grains(q0, x0)
+        out = laue.laue_em(geom, planes, obs, model, par, gr)
+        res[(tile, launch)] = (gr.numpy(), out)
+    (q1, x1), o1 = res[(1, 1)]
+    assert o1["tile2_solves"] == 0
+    assert res[(2, 1)][1]["tile2_solves"] == o1["n_em_iter"]
+    for key_run, ((q, x), o) in res.items():
+        assert np.array_equal(q, q1) and np.array_equal(x, x1), key_run
+        for key in ("f", "g", "j_star", "q_star"):
+            assert torch.equal(o[key], o1[key]), (key_run, key)
+        assert o["sinkhorn_iters"] == o1["sinkhorn_iters"], key_run
+
+
+def test_batched_tile_two_equals_solo_tile_one(gpu_lib):
+    """Samples batched in the two-per-lane shape equal their solo one-per-lane
+    runs (pairs never straddle samples or blocks)."""
+    laue = gpu_lib
+    presets = ig.batching_samples(4)
+    samples = [_sample(laue, pr, int(g), k) for k, (pr, g) in enumerate(zip(presets, (9, 25, 14, 3)))]
+    seq = []
+    for p, geom, planes, obs, model, par, (q0, x0), _ in samples:
+        par.tile = 1
+        gr = laue.Grains(q0, x0)
+        out = laue.laue_em(geom, planes, obs, model, par, gr)
+        seq.append((gr.numpy(), out))
+    for s in samples:
+        s[5].tile = 2
+    grains = [laue.Grains(*s[6]) for s in samples]
+    rc, outs = laue.laue_em_batched([s[1] for s in samples], [s[2] for s in samples], [s[3] for s in samples],
+                                    [s[4] for s in samples], [s[5] for s in samples], grains)
+    for k in range(len(samples)):
+        (qs, xs), o1 = seq[k]
+        qb, xb = grains[k].numpy()
+        assert np.array_equal(qs, qb) and np.array_equal(xs, xb), k
+        for key in ("f", "g", "j_star", "q_star"):
+            assert torch.equal(o1[key][:outs[k][key].numel()], outs[k][key]), (k, key)
+        assert outs[k]["tile2_solves"] == outs[k]["n_em_iter"]
