@@ -346,10 +346,36 @@ __global__ __launch_bounds__(64) void k_row(const Item *__restrict__ items, cons
 
 // Column half of iteration k = iter for 64 model spots of one block (R = 2:
 // two adjacent 64-column items per workgroup, two columns per lane sharing
-// every row load): each lane streams the block's detected spots with
+// every row load): each lane streams the block's detected spots (wave-uniform
+// scalar loads) with
 // g_j^{k-1} as shift (terms are entries of the plan after the row half, <= 1)
 // and sets g_j^k = g_j^{k-1} - eps ln(column marginal).  The sample's last
 // workgroup stores sum_j exp((f0 + g_j - c_unm)/eps) for the next row half.
+// Column sums of R adjacent 64-column items over the block's rows, with the
+// row potentials F as a restrict-qualified stream (scalar loads).
+template <int R>
+__device__ __forceinline__ void col_sums(const LAUE_GLOBAL float *__restrict__ P1,
+                                         const LAUE_GLOBAL float *__restrict__ P2,
+                                         const LAUE_GLOBAL float *__restrict__ F, int r0, int r1, const Col8 *c,
+                                         const float *gk, float K, float kx, double *acc) {
+    for (int i0 = r0; i0 < r1; i0 += 64) {
+        const int i1 = min(i0 + 64, r1);
+        float a[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) a[r] = 0.0f;
+#pragma unroll 4
+        for (int i = i0; i < i1; ++i) {
+            const float pi1 = P1[i], pi2 = P2[i], fi = F[i];
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+                a[r] += fast_exp2(entry_exponent(pi1, pi2, c[r].s1, c[r].s2, c[r].v1, c[r].v2, c[r].vv, c[r].vv2, K,
+                                                 fmaf(fi, kx, gk[r])));
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) acc[r] += static_cast<double>(a[r]);
+    }
+}
+
 template <int R>
 __device__ __forceinline__ void col_pass(const Item *its, const LAUE_GLOBAL float *__restrict__ P1,
                                          const LAUE_GLOBAL float *__restrict__ P2,
@@ -384,22 +410,11 @@ __device__ __forceinline__ void col_pass(const Item *its, const LAUE_GLOBAL floa
         gk[r] = g[r] * kx;
         acc[r] = 0.0;
     }
-    for (int i0 = r0; i0 < r1; i0 += 64) {
-        const int i1 = min(i0 + 64, r1);
-        float a[R];
-#pragma unroll
-        for (int r = 0; r < R; ++r) a[r] = 0.0f;
-#pragma unroll 4
-        for (int i = i0; i < i1; ++i) {
-            const float pi1 = P1[i], pi2 = P2[i], fi = F[i];
-#pragma unroll
-            for (int r = 0; r < R; ++r)
-                a[r] += fast_exp2(entry_exponent(pi1, pi2, c[r].s1, c[r].s2, c[r].v1, c[r].v2, c[r].vv, c[r].vv2, K,
-                                                 fmaf(fi, kx, gk[r])));
-        }
-#pragma unroll
-        for (int r = 0; r < R; ++r) acc[r] += static_cast<double>(a[r]);
-    }
+    // the potentials of state k by parity, each a restrict stream of its own
+    if (k & 1)
+        col_sums<R>(P1, P2, F1, r0, r1, c, gk, K, kx, acc);
+    else
+        col_sums<R>(P1, P2, F0, r0, r1, c, gk, K, kx, acc);
     double eb[R], logS[R];
     bool slow[R], any_slow = false;
 #pragma unroll
