@@ -65,12 +65,32 @@ def build_problem(laue, preset):
     return geom, planes, obs, model, grains
 
 
-def cpu_baseline(preset, n_rows=10000, chunk=1000):
+_POOL = {}
+
+
+def _oracle_rows(args):
+    """Worker of the pooled CPU baseline: the oracle's row half-pass over a
+    slice of rows of the shared block (chord cost + log-sum-exp, FP64)."""
+    from oracle import cost, sinkhorn
+    r0, r1, chunk = args
+    d = _POOL
+    n_ent = 0
+    for r in range(r0, r1, chunk):
+        C = cost.chord_cost(d["rows"][r:min(r + chunk, r1)], d["s12"], d["vl"], d["distance"])
+        P = sinkhorn.Problem([C], d["c_out"], 0.0, d["c_out"], float(C.shape[1]))
+        sinkhorn.row_half(P, d["g"], 0.0, d["eps"])
+        n_ent += C.size
+    return n_ent
+
+
+def cpu_baseline(preset, n_rows=10000, chunk=1000, workers=None):
     """The FP64 oracle on a bounded sample: the row half of one Sinkhorn
-    iteration (chord cost + log-sum-exp) for n_rows detected spots of the
-    largest block of one projection, in row chunks."""
+    iteration (chord cost + log-sum-exp) for detected spots of the largest
+    block of one projection, in row chunks; once in this process and once
+    split over a pool of worker processes (one per host core, at most 16)."""
+    import multiprocessing as mp
     import inputgen as ig
-    from oracle import cost, crystal, forward, simulate, sinkhorn
+    from oracle import cost, crystal, forward, simulate
     pl = crystal.cubic_planes(preset.a, preset.centering, preset.n_max)
     g = forward.Geometry(1, math.radians(preset.domega_deg), preset.detectors, preset.lam_min,
                          preset.lam_max)
@@ -82,21 +102,36 @@ def cpu_baseline(preset, n_rows=10000, chunk=1000):
     ev = forward.eval_fixed(pl, q0, x0, g, mod["m"], mod["n"], mod["t"], mod["det"])
     sel = mod["block"] == b
     s12, vl = ev["s12"][sel], cost.v_local(g, mod["det"][sel], ev["v"][sel])
-    rows = ig.to_f32_exact(sim["p12"][sim["offsets"][b]:sim["offsets"][b + 1]])[:n_rows]
+    rows = ig.to_f32_exact(sim["p12"][sim["offsets"][b]:sim["offsets"][b + 1]])
     c_out = cost.c_out(preset.sigma_mm, preset.distance)
-    gpot = np.zeros(len(s12))
+    _POOL.update(rows=rows, s12=s12, vl=vl, distance=preset.distance, c_out=c_out, g=np.zeros(len(s12)),
+                 eps=preset.eps_start)
+    n1 = min(n_rows, len(rows))
     t0 = time.perf_counter()
-    n_ent = 0
-    for r in range(0, len(rows), chunk):
-        C = cost.chord_cost(rows[r:r + chunk], s12, vl, preset.distance)
-        P = sinkhorn.Problem([C], c_out, 0.0, c_out, float(C.shape[1]))
-        sinkhorn.row_half(P, gpot, 0.0, preset.eps_start)
-        n_ent += C.size
+    n_ent = _oracle_rows((0, n1, chunk))
     dt = time.perf_counter() - t0
-    return {"value": n_ent / dt, "unit": "cost-entries/s", "cores": 1, "kind": "oracle",
-            "sample": f"row half-pass (chord cost + log-sum-exp, FP64 NumPy, one process) over "
-                      f"{len(rows)} detected x {len(s12)} model spots of one backscatter block "
-                      f"({n_ent:.3g} entries, {dt:.1f} s)",
+    single = n_ent / dt
+    if workers is None:
+        workers = max(1, min(16, os.cpu_count() or 1))
+    # each worker takes a slice of the block's rows (the rows repeat if the block is short)
+    per = max(chunk, n1 // 2)
+    tasks = []
+    for w in range(workers):
+        r0 = (w * per) % max(len(rows) - per, 1)
+        tasks.append((r0, min(r0 + per, len(rows)), chunk))
+    ctx = mp.get_context("fork")
+    with ctx.Pool(workers) as pool:
+        pool.map(_oracle_rows, [(0, chunk, chunk)] * workers)      # start-up outside the timing
+        t0 = time.perf_counter()
+        ents = pool.map(_oracle_rows, tasks)
+        dtp = time.perf_counter() - t0
+    pooled = sum(ents) / dtp
+    return {"value": pooled, "unit": "cost-entries/s", "cores": workers, "kind": "oracle",
+            "sample": f"row half-pass (chord cost + log-sum-exp, FP64 NumPy) over detected x "
+                      f"{len(s12)} model spots of one backscatter block: {workers} processes x {per} rows "
+                      f"({sum(ents):.3g} entries, {dtp:.1f} s); one process: {n1} rows ({n_ent:.3g} entries, "
+                      f"{dt:.1f} s)",
+            "single_process": {"value": single, "cores": 1},
             "host": platform.processor() or platform.machine(), "os_cpu_count": os.cpu_count(),
             "numpy": np.__version__}
 
@@ -284,8 +319,9 @@ def main():
     ap.add_argument("--no-forward", action="store_true")
     ap.add_argument("--forward-grains", type=int, default=65536)
     ap.add_argument("--batch-samples", type=int, default=64)
-    ap.add_argument("--index-workload", default="medium", choices=["medium", "learned"])
-    ap.add_argument("--index-pairs", type=int, default=4096)
+    ap.add_argument("--index-workloads", default="medium:4096,learned:1024",
+                    help="comma-separated workload:pairs; plain scoring takes the candidates of that many "
+                         "spot pairs, the learned proposal of 8x as many (top 5%% scored)")
     ap.add_argument("--tile", type=int, default=0, choices=[0, 1, 2],
                     help="Sinkhorn tile shape: 1 or 2 spots per lane, 0 tuned per call")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -388,7 +424,10 @@ def main():
     if not args.no_batching:
         line["batching"] = bench_batching(laue, args.batch_samples, 3, log)
     if not args.no_index:
-        line["time_to_index"] = bench_index(laue, args.index_workload, args.index_pairs, 8 * args.index_pairs, log)
+        line["time_to_index"] = {}
+        for item in args.index_workloads.split(","):
+            wl, pairs = item.split(":")
+            line["time_to_index"][wl] = bench_index(laue, wl, int(pairs), 8 * int(pairs), log)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(preset)
     print(json.dumps(line), flush=True)

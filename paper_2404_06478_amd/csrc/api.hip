@@ -1,5 +1,9 @@
 // Host-side helpers of liblaueot: errors, geometry validation, plane lists.
 #include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
 #include <map>
 #include <numeric>
 #include <tuple>
@@ -12,6 +16,25 @@ static thread_local std::string g_err;
 
 void set_error(const std::string &msg) { g_err = msg; }
 void clear_error() { g_err.clear(); }
+
+bool log_enabled() {
+    static const bool on = [] {
+        const char *v = std::getenv("LAUE_LOG");
+        return v != nullptr && v[0] != '\0' && std::strcmp(v, "0") != 0;
+    }();
+    return on;
+}
+
+void log_line(const char *fmt, ...) {
+    if (!log_enabled()) return;
+    std::va_list ap;
+    va_start(ap, fmt);
+    std::fputs("liblaueot: ", stderr);
+    std::vfprintf(stderr, fmt, ap);
+    std::fputc('\n', stderr);
+    std::fflush(stderr);
+    va_end(ap);
+}
 
 int check_ws(void *ws, size_t ws_bytes, size_t need) {
     if (need == 0) return LAUE_OK;

@@ -16,6 +16,9 @@ namespace laue {
 
 void set_error(const std::string &msg);
 void clear_error();
+// progress lines on stderr when the environment sets LAUE_LOG (not "0")
+bool log_enabled();
+void log_line(const char *fmt, ...) __attribute__((format(printf, 1, 2)));
 
 #define LAUE_CHECK_HIP(expr)                                                        \
     do {                                                                            \

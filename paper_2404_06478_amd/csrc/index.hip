@@ -562,54 +562,98 @@ __global__ __launch_bounds__(64) void k_gain(const int64_t *__restrict__ off,
     if (threadIdx.x == 0) gain[c] = s;
 }
 
-// Pick the largest gain (lowest index on ties), record it and raise the
-// covered rows' current values.
-__global__ __launch_bounds__(1024) void k_pick(const double *__restrict__ gain, int n,
-                                               const int64_t *__restrict__ off,
-                                               const int *__restrict__ row,
-                                               const float *__restrict__ val, float *cur,
-                                               uint8_t *picked, int *picks, double *pgain,
-                                               int step, int *done) {
-    if (*done) return;
-    __shared__ double bv[1024];
-    __shared__ int bi[1024];
-    double best = 0.0;
-    int arg = -1;
-    for (int c = threadIdx.x; c < n; c += 1024) {
-        const double g = gain[c];
-        if (g > best) {
-            best = g;
-            arg = c;
-        }
-    }
-    bv[threadIdx.x] = best;
-    bi[threadIdx.x] = arg;
-    __syncthreads();
-    for (int s = 512; s > 0; s >>= 1) {
-        if (threadIdx.x < s) {
-            const double o = bv[threadIdx.x + s];
-            const int oi = bi[threadIdx.x + s];
-            if (o > bv[threadIdx.x] || (o == bv[threadIdx.x] && oi >= 0 &&
-                                        (bi[threadIdx.x] < 0 || oi < bi[threadIdx.x]))) {
-                bv[threadIdx.x] = o;
-                bi[threadIdx.x] = oi;
+// Lazy greedy: the same picks and gains as recomputing every gain at every
+// step.  A candidate's gain can only fall as rows are covered (cur only
+// rises), so a gain computed at an earlier step bounds it from above.  The 16
+// waves of the one workgroup each lead a residue class of candidates (c mod
+// 16) by (bound desc, index asc); the overall leader is the best class
+// leader.  If its bound was computed at this step it is the exact argmax and
+// is picked; otherwise every stale class leader is recomputed at once (each by
+// its wave, with k_gain's summation order, so the value is the same bit for
+// bit) and the leaders are sought again.  The loop ends after k picks or when
+// no bound is positive.
+constexpr int kGreedyWaves = 16;
+
+__global__ __launch_bounds__(64 * kGreedyWaves) void k_lazy_greedy(const int64_t *__restrict__ off,
+                                                                   const int *__restrict__ row,
+                                                                   const float *__restrict__ val, float *cur,
+                                                                   uint8_t *picked, double *ub, int *stamp,
+                                                                   int n, int k, int *picks, double *pgain,
+                                                                   int *done) {
+    __shared__ double lv[kGreedyWaves];
+    __shared__ int li[kGreedyWaves];
+    __shared__ int top;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int step = 0; step < k; ++step) {
+        for (;;) {
+            // class leader of this wave
+            double best = 0.0;
+            int arg = -1;
+            for (int c = wave + kGreedyWaves * lane; c < n; c += 64 * kGreedyWaves) {
+                if (picked[c]) continue;
+                const double g = ub[c];
+                if (g > best || (g == best && arg >= 0 && g > 0.0 && c < arg)) {
+                    best = g;
+                    arg = c;
+                }
             }
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) {
+                const double ob = __shfl_xor(best, o, 64);
+                const int oa = __shfl_xor(arg, o, 64);
+                if (ob > best || (ob == best && oa >= 0 && (arg < 0 || oa < arg))) {
+                    best = ob;
+                    arg = oa;
+                }
+            }
+            if (lane == 0) {
+                lv[wave] = best;
+                li[wave] = arg;
+            }
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                double b = 0.0;
+                int a = -1;
+                for (int w = 0; w < kGreedyWaves; ++w)
+                    if (li[w] >= 0 && (lv[w] > b || (lv[w] == b && (a < 0 || li[w] < a)))) {
+                        b = lv[w];
+                        a = li[w];
+                    }
+                top = (a >= 0 && b > 0.0) ? a : -1;
+            }
+            __syncthreads();
+            const int c = top;
+            if (c < 0) {
+                if (threadIdx.x == 0) *done = 1;
+                return;
+            }
+            if (stamp[c] == step) {
+                for (int64_t e = off[c] + threadIdx.x; e < off[c + 1]; e += 64 * kGreedyWaves)
+                    cur[row[e]] = fmaxf(cur[row[e]], val[e]);
+                if (threadIdx.x == 0) {
+                    picked[c] = 1;
+                    picks[step] = c;
+                    pgain[step] = ub[c];
+                }
+                __threadfence_block();
+                __syncthreads();
+                break;
+            }
+            // refresh every stale class leader with a positive bound
+            const int mine = li[wave];
+            if (mine >= 0 && lv[wave] > 0.0 && stamp[mine] != step) {
+                double sum = 0.0;
+                for (int64_t e = off[mine] + lane; e < off[mine + 1]; e += 64)
+                    sum += fmax(0.0, static_cast<double>(val[e]) - static_cast<double>(cur[row[e]]));
+                sum = wave_sum(sum);
+                if (lane == 0) {
+                    ub[mine] = sum;
+                    stamp[mine] = step;
+                }
+            }
+            __threadfence_block();
+            __syncthreads();
         }
-        __syncthreads();
-    }
-    const int c = bi[0];
-    const double g = bv[0];
-    __syncthreads();
-    if (c < 0 || !(g > 0.0)) {
-        if (threadIdx.x == 0) *done = 1;
-        return;
-    }
-    for (int64_t e = off[c] + threadIdx.x; e < off[c + 1]; e += 1024)
-        cur[row[e]] = fmaxf(cur[row[e]], val[e]);
-    if (threadIdx.x == 0) {
-        picked[c] = 1;
-        picks[step] = c;
-        pgain[step] = g;
     }
 }
 
@@ -878,8 +922,14 @@ extern "C" int laue_score_candidates(const laue_geometry *geom, const laue_plane
         k_set_i64<<<1, 1, 0, s>>>(out->lbar_off, 0);
         LAUE_CHECK_HIP(hipGetLastError());
     }
+    int logged = 0;
     for (int c0 = 0; c0 < N; c0 += chunk) {
         const int C = std::min(chunk, N - c0);
+        if (log_enabled() && c0 >= static_cast<int64_t>(N) * logged / 10) {
+            LAUE_CHECK_HIP(hipStreamSynchronize(s));
+            log_line("score: %d of %d candidates, %lld SPOT entries", c0, N, static_cast<long long>(lbar_total));
+            ++logged;
+        }
         laue_grains sub{C, cand->q + 4 * static_cast<int64_t>(c0), cand->x + 3 * static_cast<int64_t>(c0)};
         std::vector<int64_t> hb;
         int64_t total = 0;
@@ -978,13 +1028,15 @@ namespace {
 struct GreedyWs {
     float *cur;
     uint8_t *picked;
-    double *gain;
+    double *gain;   // upper bounds of the gains (exact at their stamp)
+    int *stamp;
     int *done;
 };
 size_t carve_greedy(Carver &cv, GreedyWs &w, int n_cand, int64_t n_rows) {
     w.cur = cv.take<float>(std::max<int64_t>(n_rows, 1));
     w.picked = cv.take<uint8_t>(std::max(n_cand, 1));
     w.gain = cv.take<double>(std::max(n_cand, 1));
+    w.stamp = cv.take<int>(std::max(n_cand, 1));
     w.done = cv.take<int>(1);
     return cv.size();
 }
@@ -1020,11 +1072,11 @@ extern "C" int laue_spot_greedy(const int64_t *lbar_off, const int32_t *lbar_row
     k_fill_i<<<(k_max + 255) / 256, 256, 0, s>>>(picks, k_max, -1);
     LAUE_CHECK_HIP(hipGetLastError());
     const int K = std::min(k_max, n_cand);
-    for (int k = 0; k < K; ++k) {
-        k_gain<<<n_cand, 64, 0, s>>>(lbar_off, lbar_row, lbar_val, w.cur, w.picked, w.gain, w.done, n_cand);
-        k_pick<<<1, 1024, 0, s>>>(w.gain, n_cand, lbar_off, lbar_row, lbar_val, w.cur, w.picked, picks,
-                                  gains, k, w.done);
-    }
+    // every gain once (exact for step 0), then the lazy steps
+    k_gain<<<n_cand, 64, 0, s>>>(lbar_off, lbar_row, lbar_val, w.cur, w.picked, w.gain, w.done, n_cand);
+    k_fill_i<<<(n_cand + 255) / 256, 256, 0, s>>>(w.stamp, n_cand, 0);
+    k_lazy_greedy<<<1, 64 * kGreedyWaves, 0, s>>>(lbar_off, lbar_row, lbar_val, w.cur, w.picked, w.gain, w.stamp,
+                                                  n_cand, K, picks, gains, w.done);
     LAUE_CHECK_HIP(hipGetLastError());
     std::vector<int> hp(K);
     LAUE_CHECK_HIP(hipMemcpyAsync(hp.data(), picks, K * sizeof(int), hipMemcpyDeviceToHost, s));

@@ -205,6 +205,8 @@ extern "C" int laue_index(const laue_geometry *geom, const laue_planes *planes, 
     st.n_candidates = cand.n;
     st.n_candidates_found = n_found;
     st.ms_candidates = ms_since(t0);
+    log_line("index: %d candidates (%lld found) in %.1f ms", cand.n, static_cast<long long>(n_found),
+             st.ms_candidates);
 
     // 2. learned proposal: support features, network, top fraction
     int64_t n_sc = cand.n;
@@ -221,6 +223,8 @@ extern "C" int laue_index(const laue_geometry *geom, const laue_planes *planes, 
     }
     st.ms_proposal = ms_since(t0);
     st.n_scored = n_sc;
+    if (par->mode == LAUE_INDEX_LEARNED)
+        log_line("index: proposal kept %lld candidates in %.1f ms", static_cast<long long>(n_sc), st.ms_proposal);
 
     // 3. single-grain refinement and scoring of the chosen candidates
     t0 = std::chrono::steady_clock::now();
@@ -243,7 +247,10 @@ extern "C" int laue_index(const laue_geometry *geom, const laue_planes *planes, 
             return rc;
     }
     st.lbar_entries = so.lbar_n;
+    if (log_enabled()) LAUE_CHECK_HIP(hipStreamSynchronize(s));
     st.ms_score = ms_since(t0);
+    log_line("index: scored %lld candidates, %lld SPOT entries, in %.1f ms", static_cast<long long>(n_sc),
+             static_cast<long long>(so.lbar_n), st.ms_score);
 
     // 4. greedy SPOT and the number of prototypes k* = argmax_k (D_k - D_{k+1})
     t0 = std::chrono::steady_clock::now();
@@ -273,6 +280,7 @@ extern "C" int laue_index(const laue_geometry *geom, const laue_planes *planes, 
     st.n_picked = n_picked;
     st.n_prototypes = k_star;
     st.ms_greedy = ms_since(t0);
+    log_line("index: greedy picked %d, k* = %d, in %.1f ms", n_picked, k_star, st.ms_greedy);
     out->n_grains = k_star;
     if (k_star == 0) {
         st.ms_total = ms_since(t_all);
@@ -317,6 +325,8 @@ extern "C" int laue_index(const laue_geometry *geom, const laue_planes *planes, 
     if (rc < 0) return rc;
     st.em = es;
     st.ms_em = ms_since(t0);
+    log_line("index: EM on %lld model spots, %d iterations, in %.1f ms", static_cast<long long>(n_model),
+             es.n_em_iter, st.ms_em);
     st.ms_total = ms_since(t_all);
     if (stats) *stats = st;
     return rc;

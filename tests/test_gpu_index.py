@@ -109,3 +109,30 @@ def test_greedy_matches_oracle(gpu_lib):
     assert gp.cpu().tolist() == picks
     assert np.allclose(gg.cpu().numpy(), gains, rtol=1e-9, atol=1e-9)
     assert single.n_prototypes(gg.cpu().numpy()) == single.n_prototypes(gains)
+
+
+def test_lazy_greedy_matches_oracle_many_candidates(gpu_lib):
+    """Hundreds of overlapping candidates, exact duplicates among them (ties
+    go to the lowest index): the lazy greedy (stale gains as upper bounds)
+    picks exactly what the plain greedy picks, with the same gains."""
+    laue = gpu_lib
+    rng = np.random.default_rng(11)
+    n_rows, phi = 3000, -4.5
+    cols = []
+    for n in range(300):
+        centre = rng.integers(0, n_rows)
+        r = np.unique(np.clip(centre + rng.integers(-150, 150, size=rng.integers(10, 120)), 0, n_rows - 1))
+        v = phi + rng.uniform(0.01, 4.0, len(r))
+        cols.append((r, v.astype(np.float32).astype(np.float64)))
+    for n in rng.choice(300, size=30, replace=False):
+        cols.append((cols[n][0].copy(), cols[n][1].copy()))
+    k_max = 150
+    picks, gains = single.greedy(cols, n_rows, phi, k_max)
+    off = np.concatenate([[0], np.cumsum([len(c[0]) for c in cols])])
+    rows = np.concatenate([c[0] for c in cols]).astype(np.int32)
+    vals = np.concatenate([c[1] for c in cols]).astype(np.float32)
+    dev = torch.device("cuda")
+    gp, gg = laue.laue_spot_greedy(torch.tensor(off, device=dev), torch.tensor(rows, device=dev),
+                                   torch.tensor(vals, device=dev), len(cols), n_rows, phi, k_max)
+    assert gp.cpu().tolist() == picks
+    assert np.allclose(gg.cpu().numpy(), gains, rtol=1e-9, atol=1e-9)
