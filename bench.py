@@ -271,6 +271,58 @@ def bench_index(laue, workload, n_pairs, learned_pairs, log):
     return out
 
 
+def bench_sparse(laue, preset, rho, n_iter, log):
+    """The same EM iterations from the same start, dense and with the sparse
+    assignment (each detected spot keeps its rho nearest model spots, sets
+    rebuilt before every Sinkhorn): time per iteration, the sparse passes'
+    pairs/s, and how far the sparse grains end from the dense ones."""
+    import torch
+    import inputgen as ig
+    q, x = ig.random_grains(preset)
+    c_out = 2.0 * preset.distance ** 2 * (1.0 - math.cos(3.0 * preset.sigma_mm / preset.distance))
+    eps_list = [preset.eps_start * (preset.eps_end / preset.eps_start) ** (s / (preset.n_stages - 1))
+                for s in range(preset.n_stages) for _ in range(preset.iters_per_stage)]
+    out = {"rho": rho, "em_iterations": n_iter}
+    res = {}
+    for r in (0, rho):
+        geom, planes, obs, model, grains = build_problem(laue, preset)
+        t_b = float(math.ceil(0.4 * model.n))
+        dev = torch.device("cuda", 0)
+        f = torch.zeros(obs.n, dtype=torch.float32, device=dev)
+        g = torch.zeros(model.n, dtype=torch.float32, device=dev)
+        f0 = g0 = 0.0
+        stats = []
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(n_iter):
+            eps = eps_list[k % len(eps_list)]
+            ot = laue.ot_params(eps, preset.distance, c_out, t_b, tol=1e-5, n_max=2000, rho=r)
+            par = laue.em_params(ot, eps, eps, 1, 1, k_gn=2)
+            o = laue.laue_em(geom, planes, obs, model, par, grains, f, g, f0, g0, assign=False)
+            f0, g0 = o["f0"], o["g0"]
+            stats.append(o)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        qg, xg = grains.numpy()
+        res[r] = (qg, xg)
+        key = "dense" if r == 0 else "sparse"
+        sk_ms = sum(s["sinkhorn_ms"] for s in stats)
+        out[key] = {"ms_per_em_iteration": dt * 1e3 / n_iter,
+                    "sinkhorn_iters": int(sum(s["sinkhorn_iters"] for s in stats)),
+                    "pass_pairs": int(sum(s["sinkhorn_entries"] for s in stats)),
+                    "pass_pairs_per_s": sum(s["sinkhorn_entries"] for s in stats) / max(sk_ms * 1e-3, 1e-12),
+                    "sinkhorn_ms": sk_ms, "mstep_ms": sum(s["mstep_ms"] for s in stats),
+                    "recall_0.25deg_0.5mm": recall(qg, xg, q, x) / len(q)}
+        log(f"sparse: rho={r}: {dt * 1e3 / n_iter:.1f} ms per EM iteration")
+    mis = np.diag(misorientation_deg(res[rho][0], res[0][0]))
+    dx = np.linalg.norm(res[rho][1] - res[0][1], axis=1)
+    out["speedup"] = out["dense"]["ms_per_em_iteration"] / out["sparse"]["ms_per_em_iteration"]
+    out["sparse_vs_dense"] = {"max_misorientation_deg": float(mis.max()), "median_misorientation_deg":
+                              float(np.median(mis)), "max_position_mm": float(dx.max()),
+                              "median_position_mm": float(np.median(dx))}
+    return out
+
+
 def bench_forward(laue, n_grains, log):
     """Forward model at candidate scale: enumerate the visible reflections of
     n_grains random grains (learned-scale scan and lattice), then time the
@@ -318,6 +370,9 @@ def main():
     ap.add_argument("--no-index", action="store_true")
     ap.add_argument("--no-forward", action="store_true")
     ap.add_argument("--forward-grains", type=int, default=65536)
+    ap.add_argument("--no-sparse", action="store_true")
+    ap.add_argument("--sparse-rho", type=int, default=32)
+    ap.add_argument("--sparse-iters", type=int, default=8)
     ap.add_argument("--batch-samples", type=int, default=64)
     ap.add_argument("--index-workloads", default="medium:4096,learned:1024",
                     help="comma-separated workload:pairs; plain scoring takes the candidates of that many "
@@ -423,6 +478,8 @@ def main():
         line["forward_model"] = bench_forward(laue, args.forward_grains, log)
     if not args.no_batching:
         line["batching"] = bench_batching(laue, args.batch_samples, 3, log)
+    if not args.no_sparse:
+        line["sparse_assignment"] = bench_sparse(laue, preset, args.sparse_rho, args.sparse_iters, log)
     if not args.no_index:
         line["time_to_index"] = {}
         for item in args.index_workloads.split(","):

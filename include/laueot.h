@@ -223,6 +223,13 @@ typedef struct laue_ot_params {
     int32_t n_max;              /* iteration cap (>= 1) */
     int32_t chunk;              /* iterations between host polls (0: 16; in an EM, sized
                                  * per temperature stage) */
+    /* sparse assignment (Sec. 4.5): 0 dense; 8, 16 or 32 = every detected
+     * spot keeps only its rho nearest model spots of its block by the chord
+     * cost (ties to the lower index), the plan being null elsewhere (the bins
+     * stay).  The sets are chosen afresh before every Sinkhorn (and before a
+     * lone M-step) from that call's model-spot columns.  The workspace then
+     * comes from laue_sparse_workspace_size. */
+    int32_t rho;
 } laue_ot_params;
 
 /* Dual potentials: Q_ij = exp((f_i + g_j - c_ij) / eps).  f [n_obs], g
@@ -345,6 +352,25 @@ int laue_em(const laue_geometry *geom, const laue_planes *planes,
             const laue_em_params *par, laue_grains *grains, laue_potentials *pot,
             laue_assignments *assign, laue_em_stats *stats,
             void *ws, size_t ws_bytes, void *stream);
+
+/* The neighbour sets of the sparse assignment (Sec. 4.5), as the sparse
+ * Sinkhorn builds them: for every detected spot the par->rho nearest model
+ * spots of its block by the chord cost, ordered by (cost, index), ties to the
+ * lower index.  nbr [n_obs x rho] (device int32, model-spot index or -1 when
+ * the block has fewer model spots), cost [n_obs x rho] (device FP32, c_ij in
+ * mm^2; +inf past the last neighbour), n_pairs (host, may be NULL) the kept
+ * pairs.  Only par->distance and par->rho are read.  Workspace:
+ * laue_sparse_workspace_size with n = 1. */
+int laue_sparse_neighbors(const laue_geometry *geom, const laue_obs_spots *obs, const laue_model_spots *model,
+                          const laue_ot_params *par, int32_t *nbr, float *cost, int64_t *n_pairs, void *ws,
+                          size_t ws_bytes, void *stream);
+
+/* Workspace of laue_sinkhorn, laue_mstep and laue_em (n = 1) or
+ * laue_em_batched (n samples) when ot.rho > 0: the dense workspace plus the
+ * neighbour sets (rho int + float per detected spot), the filter's candidate
+ * lists (8 rho per detected spot) and the column lists.  0 on bad input. */
+size_t laue_sparse_workspace_size(int32_t n, const laue_geometry *geoms, const int64_t *n_obs,
+                                  const int64_t *n_model, const int32_t *n_grains, int32_t rho);
 
 /* Batched EM of n independent samples (arrays of n structs, one per sample;
  * each sample's device arrays are its own).  Every pass of the E- and M-steps

@@ -275,18 +275,49 @@ def laue_simulate(geom, planes, truth, sigma_mm, distance, outlier_frac, seed):
 
 # ---------------------------------------------------------------- E / M steps
 
-def ot_params(eps, distance, c_out, t_b, c_unm=0.0, c_sink=None, tol=1e-5, n_max=2000, chunk=0):
+def ot_params(eps, distance, c_out, t_b, c_unm=0.0, c_sink=None, tol=1e-5, n_max=2000, chunk=0, rho=0):
+    """rho: 0 dense; 8, 16 or 32 keeps each detected spot's rho nearest model spots."""
     p = laue_ot_params()
     p.eps, p.distance, p.c_out, p.c_unm = float(eps), float(distance), float(c_out), float(c_unm)
     p.c_sink = float(c_out if c_sink is None else c_sink)
     p.t_b, p.tol, p.n_max, p.chunk = float(t_b), float(tol), int(n_max), int(chunk)
+    p.rho = int(rho)
     return p
+
+
+def _ws_size(geom, n_obs, n_model, n_grains, rho):
+    """Workspace bytes of the Sinkhorn / M-step / EM calls of one sample."""
+    lib = require_native()
+    if not rho:
+        return lib.laue_sinkhorn_workspace_size(C.byref(geom), int(n_obs), int(n_model), int(n_grains))
+    no = np.array([n_obs], np.int64)
+    nm = np.array([n_model], np.int64)
+    ng = np.array([n_grains], np.int32)
+    return lib.laue_sparse_workspace_size(1, C.byref(geom), C.c_void_p(no.ctypes.data), C.c_void_p(nm.ctypes.data),
+                                          C.c_void_p(ng.ctypes.data), int(rho))
+
+
+def laue_sparse_neighbors(geom, obs, model, ot):
+    """Neighbour sets of the sparse assignment: (nbr [n_obs, rho] int32, cost
+    [n_obs, rho] FP32 mm^2, kept pairs)."""
+    import torch
+    lib = require_native()
+    dev = _dev()
+    rho = int(ot.rho)
+    ws = _workspace(_ws_size(geom, obs.n, model.n, 0, rho))
+    nbr = torch.empty((max(obs.n, 1), rho), dtype=torch.int32, device=dev)
+    cost = torch.empty((max(obs.n, 1), rho), dtype=torch.float32, device=dev)
+    npairs = C.c_int64()
+    o, m = obs.struct(), model.struct()
+    _check(lib.laue_sparse_neighbors(C.byref(geom), C.byref(o), C.byref(m), C.byref(ot), _ptr(nbr), _ptr(cost),
+                                     C.byref(npairs), _ptr(ws), ws.numel(), _stream()))
+    return nbr[:obs.n], cost[:obs.n], npairs.value
 
 
 def laue_sinkhorn(geom, obs, model, ot, f, g, f0=0.0, g0=0.0):
     """Runs Sinkhorn in place on f, g (device FP32); returns (f0, g0, stats dict, code)."""
     lib = require_native()
-    ws = _workspace(lib.laue_sinkhorn_workspace_size(C.byref(geom), obs.n, model.n, 0))
+    ws = _workspace(_ws_size(geom, obs.n, model.n, 0, ot.rho))
     pot = laue_potentials(f.data_ptr(), g.data_ptr(), float(f0), float(g0))
     st = laue_ot_stats()
     o, m = obs.struct(), model.struct()
@@ -325,7 +356,7 @@ def laue_cost_block(geom, obs, model, distance, block):
 def laue_mstep(geom, planes, obs, model, ot, f, g, grains, k_gn=2, mu_rel=1e-9):
     import torch
     lib = require_native()
-    ws = _workspace(lib.laue_sinkhorn_workspace_size(C.byref(geom), obs.n, model.n, grains.n))
+    ws = _workspace(_ws_size(geom, obs.n, model.n, grains.n, ot.rho))
     gn = laue_gn_params(int(k_gn), float(mu_rel))
     pot = laue_potentials(f.data_ptr(), g.data_ptr(), 0.0, 0.0)
     steps = torch.zeros(max(grains.n, 1), dtype=torch.float64, device=_dev())
@@ -354,7 +385,7 @@ def laue_em(geom, planes, obs, model, par, grains, f=None, g=None, f0=0.0, g0=0.
     dev = _dev()
     f = torch.zeros(max(obs.n, 1), dtype=torch.float32, device=dev) if f is None else f
     g = torch.zeros(max(model.n, 1), dtype=torch.float32, device=dev) if g is None else g
-    ws = _workspace(lib.laue_sinkhorn_workspace_size(C.byref(geom), obs.n, model.n, grains.n))
+    ws = _workspace(_ws_size(geom, obs.n, model.n, grains.n, par.ot.rho))
     pot = laue_potentials(f.data_ptr(), g.data_ptr(), float(f0), float(g0))
     st = laue_em_stats()
     asg = None
@@ -732,8 +763,13 @@ def laue_em_batched(geoms, planes, obs, models, pars, grains, assign=True):
     no = np.array([o.n for o in obs], np.int64)
     nm = np.array([m.n for m in models], np.int64)
     ng = np.array([gg.n for gg in grains], np.int32)
-    need = lib.laue_em_batched_workspace_size(n, G, C.c_void_p(no.ctypes.data), C.c_void_p(nm.ctypes.data),
-                                              C.c_void_p(ng.ctypes.data))
+    rho = int(pars[0].ot.rho)
+    if rho:
+        need = lib.laue_sparse_workspace_size(n, G, C.c_void_p(no.ctypes.data), C.c_void_p(nm.ctypes.data),
+                                              C.c_void_p(ng.ctypes.data), rho)
+    else:
+        need = lib.laue_em_batched_workspace_size(n, G, C.c_void_p(no.ctypes.data), C.c_void_p(nm.ctypes.data),
+                                                  C.c_void_p(ng.ctypes.data))
     ws = _workspace(need)
     ST = (laue_em_stats * n)()
     rc = _check(lib.laue_em_batched(n, G, PL, O, M, PA, GR, POT, AS, ST, _ptr(ws), ws.numel(), _stream()))

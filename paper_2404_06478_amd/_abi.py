@@ -52,7 +52,7 @@ class laue_model_spots(C.Structure):
 class laue_ot_params(C.Structure):
     _fields_ = [("eps", C.c_double), ("distance", C.c_double), ("c_out", C.c_double),
                 ("c_unm", C.c_double), ("c_sink", C.c_double), ("t_b", C.c_double),
-                ("tol", C.c_double), ("n_max", C.c_int32), ("chunk", C.c_int32)]
+                ("tol", C.c_double), ("n_max", C.c_int32), ("chunk", C.c_int32), ("rho", C.c_int32)]
 
 
 class laue_potentials(C.Structure):
@@ -209,6 +209,9 @@ SIGNATURES = {
     "laue_index": (C.c_int, [P(laue_geometry), P(laue_planes), P(laue_obs_spots), P(laue_index_params),
                              P(laue_index_out), P(laue_index_stats), vp, C.c_size_t, vp]),
     "laue_em_batched_workspace_size": (C.c_size_t, [C.c_int32, P(laue_geometry), vp, vp, vp]),
+    "laue_sparse_workspace_size": (C.c_size_t, [C.c_int32, P(laue_geometry), vp, vp, vp, C.c_int32]),
+    "laue_sparse_neighbors": (C.c_int, [P(laue_geometry), P(laue_obs_spots), P(laue_model_spots), P(laue_ot_params),
+                                        vp, vp, P(C.c_int64), vp, C.c_size_t, vp]),
     "laue_em_batched": (C.c_int, [C.c_int32, P(laue_geometry), P(laue_planes), P(laue_obs_spots),
                                   P(laue_model_spots), P(laue_em_params), P(laue_grains), P(laue_potentials),
                                   P(laue_assignments), P(laue_em_stats), vp, C.c_size_t, vp]),

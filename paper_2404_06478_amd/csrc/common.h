@@ -171,8 +171,9 @@ struct Col8 {
 // |v|^2 |d|^2 = |v|^4 + |v|^2 (2 v.delta + |delta|^2); neither cancels badly
 // because the normal component of v is at least ~0.7 |v| on the detectors.
 // 17 VALU + sqrt, rcp and exp per entry in the passes (a = |v|^2, a2 = |v|^4).
-__device__ __forceinline__ float entry_exponent(float p1, float p2, float s1, float s2, float v1,
-                                                float v2, float a, float a2, float K, float base) {
+// c' = c / (2 D^2) of one (detected spot, model spot) pair.
+__device__ __forceinline__ float chord_cp(float p1, float p2, float s1, float s2, float v1, float v2, float a,
+                                          float a2) {
     const float dy = p1 - s1;
     const float dz = p2 - s2;
     const float e = fmaf(dz, dz, dy * dy);        // |delta|^2
@@ -182,8 +183,12 @@ __device__ __forceinline__ float entry_exponent(float p1, float p2, float s1, fl
     const float w = fmaf(2.0f, b, e);             // |d|^2 - |v|^2
     const float P = fmaf(a, w, a2);               // |v|^2 |d|^2
     const float den = fmaf(vdd, __builtin_amdgcn_sqrtf(P), P);
-    const float cp = x2 * __builtin_amdgcn_rcpf(den);
-    return fmaf(-K, cp, base);
+    return x2 * __builtin_amdgcn_rcpf(den);
+}
+
+__device__ __forceinline__ float entry_exponent(float p1, float p2, float s1, float s2, float v1,
+                                                float v2, float a, float a2, float K, float base) {
+    return fmaf(-K, chord_cp(p1, p2, s1, s2, v1, v2, a, a2), base);
 }
 
 __device__ __forceinline__ float fast_exp2(float x) { return __builtin_amdgcn_exp2f(x); }

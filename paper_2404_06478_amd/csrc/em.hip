@@ -84,6 +84,19 @@ struct SampleDesc {
     double D2, mu_rel;
     int *jstar, *gstar;            // assignments (may be NULL)
     float *qstar, *qout;
+    // sparse assignment (rho > 0): neighbour sets and their column lists
+    int rho, cand_cap;             // neighbours per detected spot; filter capacity per row
+    float knn_k;                   // filter threshold = knn_k / (model spots of the block)
+    int *nbr;                      // [n_obs x rho]
+    float *ncp;                    // [n_obs x rho] c / (2 D^2)
+    int *cand_j, *cand_n;          // [n_obs x cand_cap], [n_obs]
+    float *cand_c;                 // [n_obs x cand_cap]
+    int *knn_list, *knn_nlist;     // rows for the exact pass
+    int *col_cnt, *col_fill;       // [n_model]
+    int64_t *col_off;              // [n_model + 1]
+    int *col_row;                  // [n_obs x rho]
+    float *col_cp;                 // [n_obs x rho]
+    const int64_t *oboff;          // detected-spot block offsets (device)
 };
 
 // ---------------------------------------------------------------- helpers
@@ -170,6 +183,65 @@ __global__ __launch_bounds__(256) void k_cs_init(const SampleDesc *__restrict__ 
 }
 
 // ---------------------------------------------------------------- row pass
+
+// The sample's last workgroup of a row half: sums the item partials in item
+// order, updates the bin potentials f0, g0 and decides convergence.
+__device__ __forceinline__ void row_finalize(SinkCtl *__restrict__ ctl, const double2 *__restrict__ part,
+                                             const SinkParams &p, int n_items, int k, double eps) {
+    double rsum = 0.0, emax = 0.0;
+    for (int w = threadIdx.x; w < n_items; w += 64) {
+        rsum += part[w].x;
+        emax = fmax(emax, part[w].y);
+    }
+    rsum = wave_sum(rsum);
+    emax = wave_max(emax);
+    if (threadIdx.x == 0) {
+        const int slot = (k - 1) & 1;
+        const double f0p = ctl->f0[slot], g0p = ctl->g0[slot];
+        const double row0 = ctl->cs_sum + exp((f0p + g0p - p.c_sink) / eps);
+        const double err0 = p.t_b > 0 ? fabs(row0 - p.t_b) / p.t_b : 0.0;
+        const double e = fmax(emax, err0);
+        if (e < 0.99 * ctl->best_err) {
+            ctl->best_err = e;
+            ctl->best_iter = k;
+        }
+        // FP32 potentials put a rounding floor under the marginal error (about
+        // 1e-5 at the smallest temperatures): an error within 4 tol that has
+        // not fallen by 1% over 64 iterations counts as converged
+        const bool floor = e <= 4.0 * p.tol && k - ctl->best_iter >= 64;
+        if (k >= 2 && (e <= p.tol || floor || k - 1 >= p.n_max)) {
+            ctl->done = 1;
+            ctl->final_state = k - 1;
+            ctl->converged = (e <= p.tol || floor) ? 1 : 0;
+            ctl->err = e;
+        } else {
+            const double f0n = p.t_b > 0 ? f0p + eps * log(p.t_b) - eps * log(row0) : -INFINITY;
+            const double g0n =
+                p.t_a > 0 ? g0p + eps * log(p.t_a) - eps * log(rsum + exp((f0n + g0p - p.c_sink) / eps))
+                          : -INFINITY;
+            ctl->f0[k & 1] = f0n;
+            ctl->g0[k & 1] = g0n;
+            ctl->iter = k;
+            ctl->err = e;
+        }
+        ctl->ticket = 0u;
+    }
+}
+
+// The sample's last workgroup of a column half: stores
+// sum_j exp((f0 + g_j - c_unm)/eps) for the next row half.
+__device__ __forceinline__ void col_finalize(SinkCtl *__restrict__ ctl, const double2 *__restrict__ part,
+                                             int n_items) {
+    double t = 0.0;
+    for (int w = threadIdx.x; w < n_items; w += 64) t += part[w].x;
+    t = wave_sum(t);
+    if (threadIdx.x == 0) {
+        ctl->cs_sum = t;
+        ctl->ticket = 0u;
+    }
+}
+
+
 
 // Row half of Sinkhorn iteration k = iter + 1 for 64 detected spots of one
 // block.  Each lane streams the block's model spots; with the previous f_i as
@@ -279,44 +351,7 @@ __device__ __forceinline__ void row_pass(const Item *its, const LAUE_GLOBAL floa
         if (threadIdx.x == 0 && its[r].local >= 0) part[its[r].local] = make_double2(rs, err);
     }
     if (!last_block(ctl, n_wg)) return;
-    double rsum = 0.0, emax = 0.0;
-    for (int w = threadIdx.x; w < n_items; w += 64) {
-        rsum += part[w].x;
-        emax = fmax(emax, part[w].y);
-    }
-    rsum = wave_sum(rsum);
-    emax = wave_max(emax);
-    if (threadIdx.x == 0) {
-        const int slot = (k - 1) & 1;
-        const double f0p = ctl->f0[slot], g0p = ctl->g0[slot];
-        const double row0 = ctl->cs_sum + exp((f0p + g0p - p.c_sink) / eps);
-        const double err0 = p.t_b > 0 ? fabs(row0 - p.t_b) / p.t_b : 0.0;
-        const double e = fmax(emax, err0);
-        if (e < 0.99 * ctl->best_err) {
-            ctl->best_err = e;
-            ctl->best_iter = k;
-        }
-        // FP32 potentials put a rounding floor under the marginal error (about
-        // 1e-5 at the smallest temperatures): an error within 4 tol that has
-        // not fallen by 1% over 64 iterations counts as converged
-        const bool floor = e <= 4.0 * p.tol && k - ctl->best_iter >= 64;
-        if (k >= 2 && (e <= p.tol || floor || k - 1 >= p.n_max)) {
-            ctl->done = 1;
-            ctl->final_state = k - 1;
-            ctl->converged = (e <= p.tol || floor) ? 1 : 0;
-            ctl->err = e;
-        } else {
-            const double f0n = p.t_b > 0 ? f0p + eps * log(p.t_b) - eps * log(row0) : -INFINITY;
-            const double g0n =
-                p.t_a > 0 ? g0p + eps * log(p.t_a) - eps * log(rsum + exp((f0n + g0p - p.c_sink) / eps))
-                          : -INFINITY;
-            ctl->f0[k & 1] = f0n;
-            ctl->g0[k & 1] = g0n;
-            ctl->iter = k;
-            ctl->err = e;
-        }
-        ctl->ticket = 0u;
-    }
+    row_finalize(ctl, part, p, n_items, k, eps);
 }
 
 // the items of one workgroup of shape R: groups[w] = (first item, second item or -1)
@@ -452,13 +487,7 @@ __device__ __forceinline__ void col_pass(const Item *its, const LAUE_GLOBAL floa
         if (threadIdx.x == 0 && its[r].local >= 0) part[its[r].local] = make_double2(cs, 0.0);
     }
     if (!last_block(ctl, n_wg)) return;
-    double t = 0.0;
-    for (int w = threadIdx.x; w < n_items; w += 64) t += part[w].x;
-    t = wave_sum(t);
-    if (threadIdx.x == 0) {
-        ctl->cs_sum = t;
-        ctl->ticket = 0u;
-    }
+    col_finalize(ctl, part, n_items);
 }
 
 template <int R>
@@ -615,6 +644,368 @@ __global__ __launch_bounds__(64) void k_mstep_solve(const SampleDesc *__restrict
                    D.step_norm ? D.step_norm + n : nullptr);
 }
 
+// ---------------------------------------------------------------- sparse assignment
+
+// Each detected spot keeps its rho nearest model spots of its block by the
+// chord cost (ties to the lower model-spot index); the plan is null outside
+// these sets (Sec. 4.5).  The sets are chosen afresh before every Sinkhorn
+// from the packed columns of that E-step (colsE).  Row side: nbr / ncp
+// [n_obs x rho] (model-spot index or -1, c' = c / (2 D^2)), ordered by
+// (c', index).  Column side: CSR by model spot (col_off, col_row, col_cp),
+// rows ascending.
+
+// insert (x, xj) into the sorted register list (d, id) of length R; the last
+// entry falls off.  Candidates arrive in ascending index, so strict < keeps
+// the lower index on equal costs.
+template <int R>
+__device__ __forceinline__ void knn_insert(float *d, int *id, float x, int xj) {
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+        const bool sw = x < d[k];
+        const float td = sw ? d[k] : x;
+        const int tj = sw ? id[k] : xj;
+        d[k] = sw ? x : d[k];
+        id[k] = sw ? xj : id[k];
+        x = td;
+        xj = tj;
+    }
+}
+
+// Filter pass (lane = detected spot of a 64-row item): every column of the
+// block with c' below the block's threshold is appended to the row's
+// candidate list (at most M kept; the count is exact).
+__device__ __forceinline__ void knn_filter_body(const Item &it, const LAUE_GLOBAL float *__restrict__ P1,
+                                                const LAUE_GLOBAL float *__restrict__ P2,
+                                                const LAUE_GLOBAL Col8 *__restrict__ cols, int *__restrict__ cj,
+                                                float *__restrict__ cc, int *__restrict__ cnt_out, int M,
+                                                float thr) {
+    const int i = it.r0 + static_cast<int>(threadIdx.x);
+    const bool act = i < it.r1;
+    const float p1 = act ? P1[i] : 0.0f, p2 = act ? P2[i] : 0.0f;
+    int cnt = 0;
+    const int64_t base = static_cast<int64_t>(act ? i : 0) * M;
+    for (int j = it.c0; j < it.c1; ++j) {
+        const Col8 c = ld_col(cols + j);
+        const float cp = chord_cp(p1, p2, c.s1, c.s2, c.v1, c.v2, c.vv, c.vv2);
+        if (act && cp < thr) {
+            if (cnt < M) {
+                cj[base + cnt] = j;
+                cc[base + cnt] = cp;
+            }
+            ++cnt;
+        }
+    }
+    if (act) cnt_out[i] = cnt;
+}
+
+__global__ __launch_bounds__(64) void k_knn_filter(const Item *__restrict__ items,
+                                                   const SampleDesc *__restrict__ descs) {
+    const Item it = items[blockIdx.x];
+    const SampleDesc &D = descs[it.s];
+    const int Jb = it.c1 - it.c0;
+    if (Jb <= D.rho) return;      // every column is a neighbour: the exact pass takes the row
+    knn_filter_body(it, gptr(D.p1), gptr(D.p2), gptr(D.colsE), D.cand_j, D.cand_c, D.cand_n, D.cand_cap,
+                    D.knn_k / static_cast<float>(Jb));
+}
+
+// Selection (lane = detected spot): the rho smallest of the row's candidates
+// when the filter kept at least rho and at most M of them (then they hold the
+// true rho nearest: every column not kept has c' >= the threshold > the
+// rho-th kept); otherwise the row goes to the exact pass.
+template <int R>
+__global__ __launch_bounds__(64) void k_knn_select(const Item *__restrict__ items,
+                                                   const SampleDesc *__restrict__ descs) {
+    const Item it = items[blockIdx.x];
+    const SampleDesc &D = descs[it.s];
+    const int i = it.r0 + static_cast<int>(threadIdx.x);
+    if (i >= it.r1) return;
+    const int Jb = it.c1 - it.c0;
+    const int n = Jb <= R ? -1 : D.cand_n[i];
+    if (n < R || n > D.cand_cap) {
+        D.knn_list[atomicAdd(D.knn_nlist, 1)] = i;
+        return;
+    }
+    float d[R];
+    int id[R];
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+        d[k] = INFINITY;
+        id[k] = -1;
+    }
+    const int64_t base = static_cast<int64_t>(i) * D.cand_cap;
+    for (int t = 0; t < n; ++t) knn_insert<R>(d, id, D.cand_c[base + t], D.cand_j[base + t]);
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+        D.nbr[static_cast<int64_t>(i) * R + k] = id[k];
+        D.ncp[static_cast<int64_t>(i) * R + k] = d[k];
+    }
+}
+
+// Exact pass over the listed rows (lane = one listed row; the rows of a wave
+// may lie in different blocks): all columns of the row's block.
+template <int R>
+__global__ __launch_bounds__(64) void k_knn_exact(const SampleDesc *__restrict__ descs, int s, int n_list) {
+    const SampleDesc &D = descs[s];
+    const int t = blockIdx.x * 64 + static_cast<int>(threadIdx.x);
+    if (t >= n_list) return;
+    const int i = D.knn_list[t];
+    // block of row i: the last b with oboff[b] <= i
+    int lo = 0, hi = D.nb;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) / 2;
+        if (D.oboff[mid] <= i) lo = mid; else hi = mid;
+    }
+    const int c0 = static_cast<int>(D.mboff[lo]), c1 = static_cast<int>(D.mboff[lo + 1]);
+    const float p1 = D.p1[i], p2 = D.p2[i];
+    float d[R];
+    int id[R];
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+        d[k] = INFINITY;
+        id[k] = -1;
+    }
+    for (int j = c0; j < c1; ++j) {
+        const Col8 c = D.colsE[j];
+        knn_insert<R>(d, id, chord_cp(p1, p2, c.s1, c.s2, c.v1, c.v2, c.vv, c.vv2), j);
+    }
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+        D.nbr[static_cast<int64_t>(i) * R + k] = id[k];
+        D.ncp[static_cast<int64_t>(i) * R + k] = d[k];
+    }
+}
+
+// Column lists: counts, then (after a scan) filling at atomic positions, then
+// each column's list sorted by row so that sums run in a fixed order.
+__global__ void k_knn_count(const SampleDesc *__restrict__ descs, int s) {
+    const SampleDesc &D = descs[s];
+    const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (e >= D.n_obs * D.rho) return;
+    const int j = D.nbr[e];
+    if (j >= 0) atomicAdd(D.col_cnt + j, 1);
+}
+
+__global__ void k_knn_fill(const SampleDesc *__restrict__ descs, int s) {
+    const SampleDesc &D = descs[s];
+    const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (e >= D.n_obs * D.rho) return;
+    const int j = D.nbr[e];
+    if (j < 0) return;
+    const int64_t pos = D.col_off[j] + atomicAdd(D.col_fill + j, 1);
+    D.col_row[pos] = static_cast<int>(e / D.rho);
+    D.col_cp[pos] = D.ncp[e];
+}
+
+__global__ void k_knn_sort(const SampleDesc *__restrict__ descs, int s) {
+    const SampleDesc &D = descs[s];
+    const int64_t j = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (j >= D.n_model) return;
+    const int64_t a = D.col_off[j], b = D.col_off[j + 1];
+    for (int64_t u = a + 1; u < b; ++u) {
+        const int r = D.col_row[u];
+        const float c = D.col_cp[u];
+        int64_t v = u - 1;
+        while (v >= a && D.col_row[v] > r) {
+            D.col_row[v + 1] = D.col_row[v];
+            D.col_cp[v + 1] = D.col_cp[v];
+            --v;
+        }
+        D.col_row[v + 1] = r;
+        D.col_cp[v + 1] = c;
+    }
+}
+
+__global__ void k_scale_f(const float *__restrict__ a, float *__restrict__ out, int64_t n, float k) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = a[i] * k;
+}
+
+__global__ void k_zero_i(int *__restrict__ p, int64_t n) {
+    const int64_t k = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (k < n) p[k] = 0;
+}
+
+// Sparse row half (lane = detected spot): S_i over the row's neighbours, then
+// the dense pass's epilogue and finalisation.
+__global__ __launch_bounds__(64) void k_row_sparse(const Item *__restrict__ items,
+                                                   const SampleDesc *__restrict__ descs) {
+    const Item it = items[blockIdx.x];
+    const SampleDesc &D = descs[it.s];
+    SinkCtl *ctl = D.ctl;
+    if (ctl->done) return;
+    const SinkParams &p = D.sp;
+    const int k = ctl->iter + 1;
+    const float *Fin = ((k - 1) & 1) ? D.f1 : D.f;
+    float *Fout = (k & 1) ? D.f1 : D.f;
+    const double eps = ctl->eps;
+    const double kexp = ctl->kexp;
+    const float kx = static_cast<float>(kexp);
+    const float K = p.twoD2 * kx;
+    const double g0 = ctl->g0[(k - 1) & 1];
+    const int R = D.rho;
+    const int i = it.r0 + static_cast<int>(threadIdx.x);
+    const bool act = i < it.r1;
+    const float f = act ? Fin[i] : 0.0f;
+    const float fk = f * kx;
+    const int64_t base = static_cast<int64_t>(act ? i : 0) * R;
+    float a = 0.0f;
+    for (int q = 0; q < R; ++q) {
+        const int j = act ? D.nbr[base + q] : -1;
+        if (j >= 0) a += fast_exp2(fmaf(-K, D.ncp[base + q], fmaf(D.g[j], kx, fk)));
+    }
+    double acc = static_cast<double>(a);
+    const double eb = (g0 - p.c_out) * kexp + static_cast<double>(fk);
+    acc += exp2(eb);
+    const bool slow = act && !(acc > 1e-30);
+    double logS = log(acc);
+    if (__any(slow) && slow) {
+        float mx = static_cast<float>(eb);
+        for (int q = 0; q < R; ++q) {
+            const int j = D.nbr[base + q];
+            if (j >= 0) mx = fmaxf(mx, fmaf(-K, D.ncp[base + q], fmaf(D.g[j], kx, fk)));
+        }
+        double s2 = exp2(eb - mx);
+        for (int q = 0; q < R; ++q) {
+            const int j = D.nbr[base + q];
+            if (j >= 0) s2 += exp2(static_cast<double>(fmaf(-K, D.ncp[base + q], fmaf(D.g[j], kx, fk))) - mx);
+        }
+        logS = log(s2) + static_cast<double>(mx) * 0.6931471805599453;
+    }
+    double err = act ? fabs(acc - 1.0) : 0.0;
+    double rs = 0.0;
+    if (act) {
+        const float fnf = static_cast<float>(static_cast<double>(f) - eps * logS);
+        Fout[i] = fnf;
+        rs = exp((static_cast<double>(fnf) + g0 - p.c_out) / eps);
+    }
+    rs = wave_sum(rs);
+    err = wave_max(err);
+    if (threadIdx.x == 0) D.part[it.local] = make_double2(rs, err);
+    if (!last_block(ctl, D.n_row_items)) return;
+    row_finalize(ctl, D.part, p, D.n_row_items, k, eps);
+}
+
+// Sparse column half (lane = model spot): over the rows that keep it.
+__global__ __launch_bounds__(64) void k_col_sparse(const Item *__restrict__ items,
+                                                   const SampleDesc *__restrict__ descs) {
+    const Item it = items[blockIdx.x];
+    const SampleDesc &D = descs[it.s];
+    SinkCtl *ctl = D.ctl;
+    if (ctl->done) return;
+    const SinkParams &p = D.sp;
+    const int k = ctl->iter;
+    const float *F = (k & 1) ? D.f1 : D.f;
+    const double eps = ctl->eps;
+    const double kexp = ctl->kexp;
+    const float kx = static_cast<float>(kexp);
+    const float K = p.twoD2 * kx;
+    const double f0 = ctl->f0[k & 1];
+    const int j = it.c0 + static_cast<int>(threadIdx.x);
+    const bool act = j < it.c1;
+    const float g = act ? D.g[j] : 0.0f;
+    const float gk = g * kx;
+    const int64_t a0 = act ? D.col_off[j] : 0, a1 = act ? D.col_off[j + 1] : 0;
+    float a = 0.0f;
+    for (int64_t e = a0; e < a1; ++e) a += fast_exp2(fmaf(-K, D.col_cp[e], fmaf(F[D.col_row[e]], kx, gk)));
+    double acc = static_cast<double>(a);
+    const double eb = (f0 - p.c_unm) * kexp + static_cast<double>(gk);
+    acc += exp2(eb);
+    const bool slow = act && !(acc > 1e-30);
+    double logS = log(acc);
+    if (__any(slow) && slow) {
+        float mx = static_cast<float>(eb);
+        for (int64_t e = a0; e < a1; ++e) mx = fmaxf(mx, fmaf(-K, D.col_cp[e], fmaf(F[D.col_row[e]], kx, gk)));
+        double s2 = exp2(eb - mx);
+        for (int64_t e = a0; e < a1; ++e)
+            s2 += exp2(static_cast<double>(fmaf(-K, D.col_cp[e], fmaf(F[D.col_row[e]], kx, gk))) - mx);
+        logS = log(s2) + static_cast<double>(mx) * 0.6931471805599453;
+    }
+    double cs = 0.0;
+    if (act) {
+        const float gn = static_cast<float>(static_cast<double>(g) - eps * logS);
+        D.g[j] = gn;
+        cs = exp((f0 + static_cast<double>(gn) - p.c_unm) / eps);
+    }
+    cs = wave_sum(cs);
+    if (threadIdx.x == 0) D.part[it.local] = make_double2(cs, 0.0);
+    if (!last_block(ctl, D.n_col_items)) return;
+    col_finalize(ctl, D.part, D.n_col_items);
+}
+
+// Sparse M-step statistics (lane = model spot): over the rows that keep it,
+// Q from the stored E-step cost and the potentials, the residual geometry at
+// the current grains; same epilogue as the dense pass.
+__global__ __launch_bounds__(64) void k_mstep_acc_sparse(const Item *__restrict__ items,
+                                                         const SampleDesc *__restrict__ descs, int cur_c) {
+    const Item it = items[blockIdx.x];
+    const SampleDesc &D = descs[it.s];
+    const float kx = static_cast<float>(D.ctl->kexp);
+    const float K = D.sp.twoD2 * kx;
+    const int j = it.c0 + static_cast<int>(threadIdx.x);
+    const bool act = j < it.c1;
+    Col8 cC = {0, 0, 0, 0, 1, 1, 1, 0};
+    float g = 0.0f;
+    if (act) {
+        cC = cur_c ? D.colsC[j] : D.colsE[j];
+        g = D.g[j];
+    }
+    const float gk = g * kx;
+    const float ivl = __builtin_amdgcn_rsqf(cC.vv);
+    const float vlen = cC.vv * ivl;
+    const float rn = cC.vn * ivl, r1 = cC.v1 * ivl, r2 = cC.v2 * ivl;
+    const int64_t a0 = act ? D.col_off[j] : 0, a1 = act ? D.col_off[j + 1] : 0;
+    float a[kStat];
+    for (int q = 0; q < kStat; ++q) a[q] = 0.0f;
+    for (int64_t e = a0; e < a1; ++e) {
+        const int i = D.col_row[e];
+        const float Q = fast_exp2(fmaf(-K, D.col_cp[e], fmaf(D.f[i], kx, gk)));
+        if (Q > 0.0f) accumulate_stats(a, Q, D.p1[i], D.p2[i], cC, vlen, rn, r1, r2);
+    }
+    if (!act) return;
+    double s64[kStat];
+    for (int q = 0; q < kStat; ++q) s64[q] = static_cast<double>(a[q]);
+    column_normal_equations(*D.geom, D.W, D.n_planes, D.grains, D.n_grains, D.mplane[j], D.mgrain[j], D.mblock[j],
+                            s64, rn, r1, r2, D.D2, D.colHg + static_cast<int64_t>(j) * kHg);
+}
+
+// Sparse hard assignment: argmax over the row's neighbours (lowest index on
+// ties) and the outlier column.
+__global__ __launch_bounds__(64) void k_assign_sparse(const Item *__restrict__ items,
+                                                      const SampleDesc *__restrict__ descs) {
+    const Item it = items[blockIdx.x];
+    const SampleDesc &D = descs[it.s];
+    if (!D.jstar) return;
+    const SinkCtl *ctl = D.ctl;
+    const SinkParams p = D.sp;
+    const double eps = ctl->eps, g0 = ctl->g0[ctl->final_state & 1];
+    const int i = it.r0 + static_cast<int>(threadIdx.x);
+    if (i >= it.r1) return;
+    const double kexp = 1.4426950408889634 / eps;
+    const float kx = static_cast<float>(kexp);
+    const float K = p.twoD2 * kx;
+    const float fk = D.f[i] * kx;
+    const int64_t base = static_cast<int64_t>(i) * D.rho;
+    float best = -INFINITY;
+    int arg = -1;
+    for (int q = 0; q < D.rho; ++q) {
+        const int j = D.nbr[base + q];
+        if (j < 0) continue;
+        const float e = fmaf(-K, D.ncp[base + q], fmaf(D.g[j], kx, fk));
+        if (e > best || (e == best && j < arg)) {
+            best = e;
+            arg = j;
+        }
+    }
+    const double eb = (g0 - p.c_out) * kexp + static_cast<double>(fk);
+    const float qo = static_cast<float>(exp2(eb));
+    const float qb = arg >= 0 ? fast_exp2(best) : 0.0f;
+    const bool m = arg >= 0 && qb >= qo;
+    D.jstar[i] = m ? arg : -1;
+    D.gstar[i] = m ? D.mgrain[arg] : -1;
+    D.qstar[i] = m ? qb : qo;
+    D.qout[i] = qo;
+}
+
 // ---------------------------------------------------------------- forward model
 
 // FP32 grains of all samples from their FP64 quaternions and positions.
@@ -711,7 +1102,11 @@ struct SampleDims {
     const laue_geometry *geom;
     int64_t n_obs, n_model;
     int n_grains;
+    int rho;                       // sparse assignment (0: dense)
 };
+
+// filter capacity per detected spot, in neighbours
+constexpr int kCandPerNbr = 8;
 
 struct SampleWs {
     double2 *part;
@@ -721,6 +1116,11 @@ struct SampleWs {
     GeomF *geom;
     GrainF *grains;
     int64_t *mboff;
+    // sparse assignment (rho > 0)
+    int *nbr = nullptr, *cand_j = nullptr, *cand_n = nullptr, *knn_list = nullptr, *knn_nlist = nullptr;
+    float *ncp = nullptr, *cand_c = nullptr, *col_cp = nullptr;
+    int *col_cnt = nullptr, *col_fill = nullptr, *col_row = nullptr;
+    int64_t *col_off = nullptr, *oboff = nullptr;
 };
 
 struct BatchWs {
@@ -758,6 +1158,23 @@ static size_t carve_all(Carver &cv, BatchWs &bw, std::vector<SampleWs> &sw, cons
         w.geom = cv.take<GeomF>(1);
         w.grains = cv.take<GrainF>(std::max(d.n_grains, 1));
         w.mboff = cv.take<int64_t>(nb + 1);
+        if (d.rho > 0) {
+            const int64_t no = std::max<int64_t>(d.n_obs, 1), nm = std::max<int64_t>(d.n_model, 1);
+            const int64_t cap = static_cast<int64_t>(kCandPerNbr) * d.rho;
+            w.nbr = cv.take<int>(no * d.rho);
+            w.ncp = cv.take<float>(no * d.rho);
+            w.cand_j = cv.take<int>(no * cap);
+            w.cand_c = cv.take<float>(no * cap);
+            w.cand_n = cv.take<int>(no);
+            w.knn_list = cv.take<int>(no);
+            w.knn_nlist = cv.take<int>(1);
+            w.col_cnt = cv.take<int>(nm);
+            w.col_fill = cv.take<int>(nm);
+            w.col_off = cv.take<int64_t>(nm + 1);
+            w.col_row = cv.take<int>(no * d.rho);
+            w.col_cp = cv.take<float>(no * d.rho);
+            w.oboff = cv.take<int64_t>(nb + 1);
+        }
     }
     return cv.size();
 }
@@ -798,6 +1215,8 @@ static int validate_ot(const laue_ot_params *p, bool need_eps) {
     LAUE_REQUIRE(std::isfinite(p->t_b) && p->t_b >= 0, LAUE_EINVAL, "T_b must be >= 0");
     LAUE_REQUIRE(std::isfinite(p->tol) && p->tol >= 0, LAUE_EINVAL, "tol must be >= 0");
     LAUE_REQUIRE(p->n_max >= 1, LAUE_EINVAL, "n_max must be >= 1");
+    LAUE_REQUIRE(p->rho == 0 || p->rho == 8 || p->rho == 16 || p->rho == 32, LAUE_EINVAL,
+                 "rho must be 0 (dense), 8, 16 or 32");
     return LAUE_OK;
 }
 
@@ -840,6 +1259,8 @@ struct BatchEngine {
     std::vector<SamplePlan> plans;
     std::vector<int64_t> mbase, gbase;
     int n_rows = 0, n_cols = 0, n_rows2 = 0, n_cols2 = 0;
+    int rho = 0;                                 // sparse assignment (0: dense)
+    std::vector<int64_t> sparse_entries;         // per sample: kept pairs of the current sets
     // per sample: streamed entries, Sinkhorn passes and their entries, M-step entries
     std::vector<int64_t> entries, passes, pass_entries, m_entries;
     std::vector<SinkCtl> hctl;
@@ -877,13 +1298,81 @@ struct BatchEngine {
     // one graph serves every chunk, temperature and EM iteration of the call.
     // one row pass and one column pass in tile shape R (empty grids skipped)
     void row_launch(hipStream_t st, int R) {
+        if (rho > 0) {
+            if (n_rows) k_row_sparse<<<n_rows, 64, 0, st>>>(bw.rows, bw.desc);
+            return;
+        }
         if (R == 2 && n_rows2) k_row<2><<<n_rows2, 64, 0, st>>>(bw.rows, bw.rows2, bw.desc);
         if (R == 1 && n_rows) k_row<1><<<n_rows, 64, 0, st>>>(bw.rows, bw.rows2, bw.desc);
     }
     void col_launch(hipStream_t st, int R) {
+        if (rho > 0) {
+            if (n_cols) k_col_sparse<<<n_cols, 64, 0, st>>>(bw.cols, bw.desc);
+            return;
+        }
         if (R == 2 && n_cols2) k_col<2><<<n_cols2, 64, 0, st>>>(bw.cols, bw.cols2, bw.desc);
         if (R == 1 && n_cols) k_col<1><<<n_cols, 64, 0, st>>>(bw.cols, bw.cols2, bw.desc);
     }
+
+    // The neighbour sets of every sample from its packed E-step columns
+    // (colsE), and their column lists.
+    int build_neighbors() {
+        if (rho <= 0) return LAUE_OK;
+        for (int k = 0; k < n; ++k) {
+            k_zero_i<<<1, 64, 0, s>>>(sw[k].knn_nlist, 1);
+            const int64_t nm = std::max<int64_t>(in[k].model->n, 1);
+            k_zero_i<<<static_cast<unsigned>((nm + 255) / 256), 256, 0, s>>>(sw[k].col_cnt, nm);
+            k_zero_i<<<static_cast<unsigned>((nm + 255) / 256), 256, 0, s>>>(sw[k].col_fill, nm);
+        }
+        if (n_rows) {
+            k_knn_filter<<<n_rows, 64, 0, s>>>(bw.rows, bw.desc);
+            if (rho == 8) k_knn_select<8><<<n_rows, 64, 0, s>>>(bw.rows, bw.desc);
+            if (rho == 16) k_knn_select<16><<<n_rows, 64, 0, s>>>(bw.rows, bw.desc);
+            if (rho == 32) k_knn_select<32><<<n_rows, 64, 0, s>>>(bw.rows, bw.desc);
+        }
+        LAUE_CHECK_HIP(hipGetLastError());
+        std::vector<int> nl(n, 0);
+        for (int k = 0; k < n; ++k)
+            LAUE_CHECK_HIP(hipMemcpyAsync(&nl[k], sw[k].knn_nlist, sizeof(int), hipMemcpyDeviceToHost, s));
+        LAUE_CHECK_HIP(hipStreamSynchronize(s));
+        sparse_entries.assign(n, 0);
+        for (int k = 0; k < n; ++k) {
+            const int64_t no = in[k].obs->n, nm = in[k].model->n;
+            if (nl[k] > 0) {
+                const unsigned g = static_cast<unsigned>((nl[k] + 63) / 64);
+                if (rho == 8) k_knn_exact<8><<<g, 64, 0, s>>>(bw.desc, k, nl[k]);
+                if (rho == 16) k_knn_exact<16><<<g, 64, 0, s>>>(bw.desc, k, nl[k]);
+                if (rho == 32) k_knn_exact<32><<<g, 64, 0, s>>>(bw.desc, k, nl[k]);
+            }
+            if (no == 0 || nm == 0) {
+                // no pairs: every column list is empty
+                if (nm > 0) {
+                    const int64_t w = 2 * (nm + 1);   // int64 offsets as int words
+                    k_zero_i<<<static_cast<unsigned>((w + 255) / 256), 256, 0, s>>>(
+                        reinterpret_cast<int *>(sw[k].col_off), w);
+                }
+                continue;
+            }
+            const int64_t ne = no * rho;
+            k_knn_count<<<static_cast<unsigned>((ne + 255) / 256), 256, 0, s>>>(bw.desc, k);
+            int rc;
+            if ((rc = launch_scan(sw[k].col_cnt, sw[k].col_off, nm, s))) return rc;
+            k_knn_fill<<<static_cast<unsigned>((ne + 255) / 256), 256, 0, s>>>(bw.desc, k);
+            k_knn_sort<<<static_cast<unsigned>((nm + 255) / 256), 256, 0, s>>>(bw.desc, k);
+        }
+        LAUE_CHECK_HIP(hipGetLastError());
+        std::vector<int64_t> tot(n, 0);
+        for (int k = 0; k < n; ++k)
+            if (in[k].model->n > 0 && in[k].obs->n > 0)
+                LAUE_CHECK_HIP(hipMemcpyAsync(&tot[k], sw[k].col_off + in[k].model->n, sizeof(int64_t),
+                                              hipMemcpyDeviceToHost, s));
+        LAUE_CHECK_HIP(hipStreamSynchronize(s));
+        sparse_entries = tot;
+        return LAUE_OK;
+    }
+
+    // entries one pass streams for sample k
+    int64_t pass_work(int k) const { return rho > 0 ? sparse_entries[k] : plans[k].entries; }
     void pass_pair(hipStream_t st, int R) {
         row_launch(st, R);
         col_launch(st, R);
@@ -974,8 +1463,12 @@ struct BatchEngine {
             LAUE_REQUIRE(a.pot != nullptr, LAUE_EINVAL, "potentials are NULL");
             LAUE_REQUIRE(a.obs->n == 0 || a.pot->f, LAUE_EINVAL, "f is NULL");
             LAUE_REQUIRE(a.model->n == 0 || a.pot->g, LAUE_EINVAL, "g is NULL");
-            dims[k] = SampleDims{a.geom, a.obs->n, a.model->n, a.grains ? a.grains->n : 0};
+            LAUE_REQUIRE(a.ot->rho == in[0].ot->rho, LAUE_EINVAL, "samples of a batch share rho");
+            LAUE_REQUIRE(static_cast<double>(a.obs->n) * std::max(a.ot->rho, 1) < 2147483647.0, LAUE_EINVAL,
+                         "too many detected spots for sparse lists");
+            dims[k] = SampleDims{a.geom, a.obs->n, a.model->n, a.grains ? a.grains->n : 0, a.ot->rho};
         }
+        rho = n > 0 ? in[0].ot->rho : 0;
         Carver cv(ws);
         const size_t need = carve_all(cv, bw, sw, dims);
         if ((rc = check_ws(ws, ws_bytes, need))) return rc;
@@ -1046,6 +1539,32 @@ struct BatchEngine {
                 D.gstar = a.assign->grain;
                 D.qstar = a.assign->q_star;
                 D.qout = a.assign->q_out;
+            }
+            if (rho > 0) {
+                D.rho = rho;
+                D.cand_cap = kCandPerNbr * rho;
+                // filter threshold: 3 rho model spots expected within it for a
+                // uniform block (in-plane radius r with pi r^2 n_b / l^2 = 3 rho,
+                // c' ~ r^2 / (2 D^2) near normal incidence)
+                double area = 0.0;
+                for (int d = 0; d < a.geom->n_det; ++d)
+                    area = std::max(area, 4.0 * a.geom->det[d].half_size * a.geom->det[d].half_size);
+                D.knn_k = static_cast<float>(3.0 * rho * area / (M_PI * 2.0 * a.ot->distance * a.ot->distance));
+                D.nbr = sw[k].nbr;
+                D.ncp = sw[k].ncp;
+                D.cand_j = sw[k].cand_j;
+                D.cand_c = sw[k].cand_c;
+                D.cand_n = sw[k].cand_n;
+                D.knn_list = sw[k].knn_list;
+                D.knn_nlist = sw[k].knn_nlist;
+                D.col_cnt = sw[k].col_cnt;
+                D.col_fill = sw[k].col_fill;
+                D.col_off = sw[k].col_off;
+                D.col_row = sw[k].col_row;
+                D.col_cp = sw[k].col_cp;
+                D.oboff = sw[k].oboff;
+                LAUE_CHECK_HIP(hipMemcpyAsync(sw[k].oboff, a.obs->block_off, (nb + 1) * sizeof(int64_t),
+                                              hipMemcpyHostToDevice, s));
             }
             mbase[k + 1] = mbase[k] + a.model->n;
             gbase[k + 1] = gbase[k] + D.n_grains;
@@ -1119,7 +1638,12 @@ struct BatchEngine {
     void mstep_launches(hipStream_t st, int k_gn) {
         for (int k = 0; k < k_gn; ++k) {
             if (k > 0) eval_on(st, 1, 0);
-            if (mbase[n] > 0) k_mstep_acc<<<n_cols, 64, 0, st>>>(bw.cols, bw.desc, k > 0 ? 1 : 0);
+            if (mbase[n] > 0) {
+                if (rho > 0)
+                    k_mstep_acc_sparse<<<n_cols, 64, 0, st>>>(bw.cols, bw.desc, k > 0 ? 1 : 0);
+                else
+                    k_mstep_acc<<<n_cols, 64, 0, st>>>(bw.cols, bw.desc, k > 0 ? 1 : 0);
+            }
             if (gbase[n] > 0)
                 k_mstep_solve<<<static_cast<unsigned>(gbase[n]), 64, 0, st>>>(bw.desc, n, bw.gbase);
         }
@@ -1151,6 +1675,8 @@ struct BatchEngine {
     // chunk: iterations between host polls (0: from the stage's history).
     int sinkhorn(const std::vector<double> &eps, int chunk, std::vector<laue_ot_stats> &st, int stage = -1) {
         int rc;
+        // sparse: the neighbour sets of this E-step's columns
+        if ((rc = build_neighbors())) return rc;
         if ((rc = init_ctl(eps))) return rc;
         k_cs_init<<<n, 256, 0, s>>>(bw.desc);
         LAUE_CHECK_HIP(hipGetLastError());
@@ -1171,7 +1697,7 @@ struct BatchEngine {
         const int si = std::max(stage, 0);
         if (si >= static_cast<int>(stage_tile.size())) stage_tile.resize(si + 1, 0);
         int launched = 0;
-        if (tile_mode == 0 && stage_tile[si] == 0) {
+        if (tile_mode == 0 && stage_tile[si] == 0 && rho == 0) {
             if (!tev[0])
                 for (auto &e : tev) LAUE_CHECK_HIP(hipEventCreate(&e));
             LAUE_CHECK_HIP(hipEventRecord(tev[0], s));
@@ -1193,7 +1719,7 @@ struct BatchEngine {
             stage_tile[si] = t2 < t1 ? 2 : 1;
             launched = 2;
         }
-        const int R = tile_mode ? tile_mode : stage_tile[si];
+        const int R = rho > 0 ? 1 : (tile_mode ? tile_mode : std::max(stage_tile[si], 1));
         tiles_used.push_back(R);
         for (;;) {
             const int mode = current_mode();
@@ -1248,9 +1774,9 @@ struct BatchEngine {
             st[k].converged = h.converged;
             st[k].err = h.err;
             const int64_t np = 2 * static_cast<int64_t>(fin) + 1;
-            entries[k] += plans[k].entries * np;
+            entries[k] += pass_work(k) * np;
             passes[k] += np;
-            pass_entries[k] += plans[k].entries * np;
+            pass_entries[k] += pass_work(k) * np;
         }
         return LAUE_OK;
     }
@@ -1276,8 +1802,8 @@ struct BatchEngine {
             LAUE_CHECK_HIP(hipGetLastError());
         }
         for (int j = 0; j < n; ++j) {
-            entries[j] += plans[j].entries * k_gn;
-            m_entries[j] += plans[j].entries * k_gn;
+            entries[j] += pass_work(j) * k_gn;
+            m_entries[j] += pass_work(j) * k_gn;
         }
         return timer_stop(&mstep_ms);
     }
@@ -1286,10 +1812,13 @@ struct BatchEngine {
         bool any = false;
         for (int k = 0; k < n; ++k) any = any || (hd[k].jstar && in[k].obs->n > 0);
         if (!any) return LAUE_OK;
-        k_assign<<<n_rows, 64, 0, s>>>(bw.rows, bw.desc);
+        if (rho > 0)
+            k_assign_sparse<<<n_rows, 64, 0, s>>>(bw.rows, bw.desc);
+        else
+            k_assign<<<n_rows, 64, 0, s>>>(bw.rows, bw.desc);
         LAUE_CHECK_HIP(hipGetLastError());
         for (int k = 0; k < n; ++k)
-            if (hd[k].jstar) entries[k] += plans[k].entries;
+            if (hd[k].jstar) entries[k] += pass_work(k);
         return LAUE_OK;
     }
 };
@@ -1349,7 +1878,7 @@ using namespace laue;
 static std::vector<SampleDims> dims_of(int n, const laue_geometry *geoms, const int64_t *n_obs, const int64_t *n_model,
                                        const int32_t *n_grains) {
     std::vector<SampleDims> d(n);
-    for (int k = 0; k < n; ++k) d[k] = SampleDims{geoms + k, n_obs[k], n_model[k], n_grains ? n_grains[k] : 0};
+    for (int k = 0; k < n; ++k) d[k] = SampleDims{geoms + k, n_obs[k], n_model[k], n_grains ? n_grains[k] : 0, 0};
     return d;
 }
 
@@ -1361,6 +1890,21 @@ extern "C" size_t laue_sinkhorn_workspace_size(const laue_geometry *geom, int64_
     BatchWs bw;
     std::vector<SampleWs> sw;
     return carve_all(cv, bw, sw, dims_of(1, geom, &n_obs, &n_model, &n_grains));
+}
+
+extern "C" size_t laue_sparse_workspace_size(int32_t n, const laue_geometry *geoms, const int64_t *n_obs,
+                                             const int64_t *n_model, const int32_t *n_grains, int32_t rho) {
+    if (n < 1 || !geoms || !n_obs || !n_model || (rho != 0 && rho != 8 && rho != 16 && rho != 32)) return 0;
+    for (int k = 0; k < n; ++k)
+        if (validate_geometry(geoms + k) != LAUE_OK || n_obs[k] < 0 || n_model[k] < 0 ||
+            (n_grains && n_grains[k] < 0))
+            return 0;
+    std::vector<SampleDims> d = dims_of(n, geoms, n_obs, n_model, n_grains);
+    for (auto &x : d) x.rho = rho;
+    Carver cv(nullptr);
+    BatchWs bw;
+    std::vector<SampleWs> sw;
+    return carve_all(cv, bw, sw, d);
 }
 
 extern "C" size_t laue_em_batched_workspace_size(int32_t n, const laue_geometry *geoms, const int64_t *n_obs,
@@ -1480,6 +2024,39 @@ extern "C" int laue_plan_block(const laue_geometry *geom, const laue_obs_spots *
 }
 
 
+extern "C" int laue_sparse_neighbors(const laue_geometry *geom, const laue_obs_spots *obs,
+                                     const laue_model_spots *model, const laue_ot_params *par, int32_t *nbr,
+                                     float *cost, int64_t *n_pairs, void *ws, size_t ws_bytes, void *stream) {
+    clear_error();
+    int rc;
+    if ((rc = validate_ot(par, false))) return rc;
+    LAUE_REQUIRE(par->rho > 0, LAUE_EINVAL, "rho must be 8, 16 or 32");
+    LAUE_REQUIRE(obs && (obs->n == 0 || (nbr && cost)), LAUE_EINVAL, "output arrays are NULL");
+    BatchEngine e;
+    laue_model_spots *m = const_cast<laue_model_spots *>(model);
+    laue_potentials pot{nullptr, nullptr, 0.0, 0.0};
+    // the potentials are not read; give the setup checks something to hold
+    float dummy = 0.0f;
+    pot.f = &dummy;
+    pot.g = &dummy;
+    if ((rc = e.setup({SampleIn{geom, nullptr, obs, m, par, nullptr, &pot, 0.0, nullptr, nullptr}}, ws, ws_bytes,
+                      stream, true)))
+        return rc;
+    if ((rc = launch_pack(model, e.sw[0].colsE, e.s))) return rc;
+    if ((rc = e.build_neighbors())) return rc;
+    const int64_t ne = obs->n * static_cast<int64_t>(par->rho);
+    if (ne > 0) {
+        LAUE_CHECK_HIP(hipMemcpyAsync(nbr, e.sw[0].nbr, ne * sizeof(int32_t), hipMemcpyDeviceToDevice, e.s));
+        k_scale_f<<<static_cast<unsigned>((ne + 255) / 256), 256, 0, e.s>>>(e.sw[0].ncp, cost, ne,
+                                                                          static_cast<float>(2.0 * par->distance *
+                                                                                             par->distance));
+        LAUE_CHECK_HIP(hipGetLastError());
+    }
+    if (n_pairs) *n_pairs = e.sparse_entries[0];
+    LAUE_CHECK_HIP(hipStreamSynchronize(e.s));
+    return LAUE_OK;
+}
+
 extern "C" int laue_mstep(const laue_geometry *geom, const laue_planes *planes,
                           const laue_obs_spots *obs, laue_model_spots *model,
                           const laue_ot_params *par, const laue_potentials *pot,
@@ -1500,6 +2077,8 @@ extern "C" int laue_mstep(const laue_geometry *geom, const laue_planes *planes,
                       ws_bytes, stream, true)))
         return rc;
     if ((rc = launch_pack(model, e.sw[0].colsE, e.s))) return rc;
+    // sparse: the same neighbour sets as the E-step on these columns
+    if ((rc = e.build_neighbors())) return rc;
     if ((rc = e.grain_prep()) || (rc = e.init_ctl({par->eps})) || (rc = e.mstep(gn->k_gn, false))) return rc;
     LAUE_CHECK_HIP(hipStreamSynchronize(e.s));
     return LAUE_OK;

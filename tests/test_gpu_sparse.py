@@ -1,0 +1,207 @@
+"""Sparse assignment on the GPU (each detected spot keeps its rho nearest model
+spots): neighbour sets, the sparse Sinkhorn and the sparse EM against the
+oracle (oracle/sparse.py) on identical FP32 inputs, the dense limit, batching
+and degenerate inputs."""
+import dataclasses
+
+import numpy as np
+import pytest
+import torch
+
+import inputgen as ig
+from oracle import cost, metrics, sinkhorn, sparse
+from oracle import em as oem
+from tests import _problems
+
+pytestmark = pytest.mark.gpu
+
+CASES = [("tiny", None, None, 0), ("medium", 4, 60, 0), ("medium", 3, 100, 1)]
+
+
+@pytest.fixture(scope="module", params=CASES, ids=lambda c: f"{c[0]}-T{c[1]}-N{c[2]}")
+def prob(request):
+    name, n_rot, n_grains, shift = request.param
+    return _problems.make(ig.PRESETS[name], n_rot=n_rot, n_grains=n_grains, seed_shift=shift)
+
+
+def _oracle_sets(prob, rho):
+    """Per detected spot: the oracle's neighbours as model-spot indices and costs."""
+    C = _problems.oracle_costs(prob)
+    mo = prob.model["offsets"]
+    rows_j, rows_c = [], []
+    for b, Cb in enumerate(C):
+        nb = sparse.neighbours(Cb, rho)
+        for i in range(Cb.shape[0]):
+            rows_j.append([mo[b] + j for j in nb[i]])
+            rows_c.append([Cb[i, j] for j in nb[i]])
+    return C, rows_j, rows_c
+
+
+@pytest.mark.parametrize("rho", [8, 16, 32])
+def test_neighbour_sets_match_oracle(gpu_lib, prob, rho):
+    laue = gpu_lib
+    p = prob.preset
+    geom, planes, obs, model = _problems.gpu_objects(laue, prob)
+    ot = laue.ot_params(1.0, p.distance, cost.c_out(p.sigma_mm, p.distance), 1.0, rho=rho)
+    nbr, cst, npairs = laue.laue_sparse_neighbors(geom, obs, model, ot)
+    nbr = nbr.cpu().numpy()
+    cst = cst.cpu().numpy().astype(np.float64)
+    C, rj, rc = _oracle_sets(prob, rho)
+    mo = prob.model["offsets"]
+    off = prob.obs["offsets"]
+    assert npairs == sum(len(r) for r in rj)
+    mismatched = 0
+    for b, Cb in enumerate(C):
+        for li in range(Cb.shape[0]):
+            i = off[b] + li
+            k = len(rj[i])
+            got = nbr[i, :k].tolist()
+            assert np.all(nbr[i, k:] == -1) and np.all(np.isinf(cst[i, k:]))
+            # costs of the kept pairs within the accuracy contract
+            want_c = np.array(rc[i])
+            if got != rj[i]:
+                # only near-ties at the set boundary or inside it may be ordered differently
+                mismatched += 1
+                assert set(got) == set(rj[i]) or (k < Cb.shape[1] and
+                                                  abs(Cb[li, np.array(got[-1]) - mo[b]] - Cb[li, rj[i][-1] - mo[b]])
+                                                  <= 2e-6 * Cb[li, rj[i][-1] - mo[b]] + 1e-6)
+                continue
+            assert np.all(np.abs(cst[i, :k] - want_c) <= 2e-6 * want_c + 1e-6)
+    assert mismatched <= max(2, obs.n // 1000)
+
+
+@pytest.mark.parametrize("rho", [8, 16])
+def test_sparse_sinkhorn_matches_oracle(gpu_lib, prob, rho):
+    laue = gpu_lib
+    p = prob.preset
+    eps = 11.1 * p.sigma_mm ** 2
+    geom, planes, obs, model = _problems.gpu_objects(laue, prob)
+    t_b = sinkhorn.default_tb(model.n)
+    c_out = cost.c_out(p.sigma_mm, p.distance)
+    C = _problems.oracle_costs(prob)
+    P = sparse.masked_problem(sinkhorn.Problem(C, c_out, 0.0, c_out, t_b), rho)
+    ref = sinkhorn.solve(P, eps, tol=1e-5, n_max=3000)
+    ot = laue.ot_params(eps, p.distance, c_out, t_b, tol=1e-5, n_max=3000, rho=rho)
+    # the comparison needs the same sets on both sides
+    nbr, _, _ = laue.laue_sparse_neighbors(geom, obs, model, ot)
+    _, rj, _ = _oracle_sets(prob, rho)
+    nbr = nbr.cpu().numpy()
+    same = all(sorted(nbr[i, :len(rj[i])].tolist()) == sorted(rj[i]) for i in range(obs.n))
+    if not same:
+        pytest.skip("a near-tie puts a different model spot in one set; the set test covers it")
+    f = torch.zeros(max(obs.n, 1), dtype=torch.float32, device="cuda")
+    g = torch.zeros(max(model.n, 1), dtype=torch.float32, device="cuda")
+    f0, g0, st, rc = laue.laue_sinkhorn(geom, obs, model, ot, f, g)
+    assert st["converged"] and st["err"] <= 1e-5, st
+    assert abs(st["n_iter"] - ref["n_iter"]) <= 2, (st, ref["n_iter"])
+    assert f0 == pytest.approx(ref["f0"], abs=1e-3 * eps)
+    assert g0 == pytest.approx(ref["g0"], abs=1e-3 * eps)
+    fg = f[:obs.n].cpu().numpy().astype(np.float64)
+    gg = g[:model.n].cpu().numpy().astype(np.float64)
+    rows, row0, cols, col0 = sinkhorn.marginals(P, fg, gg, f0, g0, eps)
+    assert np.max(np.abs(rows - 1.0)) < 2e-4 and np.max(np.abs(cols - 1.0)) < 2e-4
+    Qg = sinkhorn.plan_blocks(P, fg, gg, eps)
+    Qr = sinkhorn.plan_blocks(P, ref["f"], ref["g"], eps)
+    worst = max((float(np.max(np.abs(a - b))) for a, b in zip(Qg, Qr) if a.size), default=0.0)
+    assert worst <= 1e-4, worst
+
+
+def test_all_neighbours_is_dense(gpu_lib):
+    """With rho at least every block's model-spot count the sparse Sinkhorn
+    solves the dense problem (summed in another order)."""
+    laue = gpu_lib
+    prob = _problems.make(ig.TINY)
+    p = prob.preset
+    assert int(np.max(np.diff(prob.model["offsets"]))) <= 32
+    eps = 11.1 * p.sigma_mm ** 2
+    geom, planes, obs, model = _problems.gpu_objects(laue, prob)
+    t_b = sinkhorn.default_tb(model.n)
+    c_out = cost.c_out(p.sigma_mm, p.distance)
+    out = {}
+    for rho in (0, 32):
+        ot = laue.ot_params(eps, p.distance, c_out, t_b, tol=1e-6, n_max=3000, rho=rho)
+        f = torch.zeros(max(obs.n, 1), dtype=torch.float32, device="cuda")
+        g = torch.zeros(max(model.n, 1), dtype=torch.float32, device="cuda")
+        f0, g0, st, rc = laue.laue_sinkhorn(geom, obs, model, ot, f, g)
+        out[rho] = (f[:obs.n].cpu().numpy(), g[:model.n].cpu().numpy(), f0, g0, st["n_iter"])
+    fd, gd, f0d, g0d, nd = out[0]
+    fs, gs, f0s, g0s, ns = out[32]
+    assert abs(nd - ns) <= 1
+    assert np.max(np.abs(fd - fs)) <= 1e-4 * eps and np.max(np.abs(gd - gs)) <= 1e-4 * eps
+    assert f0s == pytest.approx(f0d, abs=1e-4 * eps) and g0s == pytest.approx(g0d, abs=1e-4 * eps)
+
+
+@pytest.mark.parametrize("rho", [8, 32])
+def test_sparse_em_matches_oracle(gpu_lib, rho):
+    laue = gpu_lib
+    P = _problems.make(ig.TINY)
+    p = P.preset
+    c_out = cost.c_out(p.sigma_mm, p.distance)
+    t_b = sinkhorn.default_tb(len(P.model["m"]))
+    eps_list = oem.eps_schedule(p.eps_start, p.eps_end, p.n_stages, p.iters_per_stage)
+    ref = oem.run(P.planes, P.geom, p.distance, P.obs["p12"], P.obs["offsets"], P.model, P.q0, P.x0, eps_list,
+                  c_out, t_b=t_b, k_gn=2, tol=1e-5, n_max=2000, rho=rho)
+    geom, planes, obs, model = _problems.gpu_objects(laue, P)
+    ot = laue.ot_params(p.eps_start, p.distance, c_out, t_b, tol=1e-5, n_max=2000, rho=rho)
+    par = laue.em_params(ot, p.eps_start, p.eps_end, p.n_stages, p.iters_per_stage, k_gn=2)
+    gr = laue.Grains(P.q0, P.x0)
+    out = laue.laue_em(geom, planes, obs, model, par, gr)
+    qg, xg = gr.numpy()
+    assert out["n_em_iter"] == 20 and out["not_converged"] == 0
+    assert np.max(np.degrees(metrics.misorientation(qg, ref["q"]))) < 0.01
+    assert np.max(np.linalg.norm(xg - ref["x"], axis=1)) < 0.01
+    # the sparse passes stream rho pairs per detected spot, not whole blocks
+    assert out["sinkhorn_entries"] <= out["sinkhorn_passes"] * rho * obs.n
+
+
+def test_sparse_batched_equals_solo(gpu_lib):
+    laue = gpu_lib
+    from tests.test_gpu_batch import _sample
+    presets = ig.batching_samples(3)
+    samples = [_sample(laue, pr, int(g), k) for k, (pr, g) in enumerate(zip(presets, (11, 24, 5)))]
+    for s in samples:
+        s[5].ot.rho = 16
+    seq = []
+    for p, geom, planes, obs, model, par, (q0, x0), _ in samples:
+        gr = laue.Grains(q0, x0)
+        out = laue.laue_em(geom, planes, obs, model, par, gr)
+        seq.append((gr.numpy(), out))
+    grains = [laue.Grains(*s[6]) for s in samples]
+    rc, outs = laue.laue_em_batched([s[1] for s in samples], [s[2] for s in samples], [s[3] for s in samples],
+                                    [s[4] for s in samples], [s[5] for s in samples], grains)
+    for k in range(len(samples)):
+        (qs, xs), o1 = seq[k]
+        qb, xb = grains[k].numpy()
+        assert np.array_equal(qs, qb) and np.array_equal(xs, xb), k
+        for key in ("f", "g", "j_star", "q_star"):
+            assert torch.equal(o1[key][:outs[k][key].numel()], outs[k][key]), (k, key)
+        assert o1["sinkhorn_iters"] == outs[k]["sinkhorn_iters"]
+
+
+def test_sparse_degenerate_and_errors(gpu_lib):
+    laue = gpu_lib
+    P = _problems.make(ig.TINY)
+    p = P.preset
+    geom, planes, obs, model = _problems.gpu_objects(laue, P)
+    c_out = cost.c_out(p.sigma_mm, p.distance)
+    with pytest.raises(laue.LaueError):
+        laue.laue_sparse_neighbors(geom, obs, model, laue.ot_params(1.0, p.distance, c_out, 1.0, rho=5))
+    # no detected spots: empty sets, and the Sinkhorn still runs
+    nb = len(P.obs["offsets"]) - 1
+    obs_e = laue.ObsSpots.from_numpy(np.zeros((0, 2), np.float32), np.zeros(nb + 1, np.int64))
+    ot = laue.ot_params(10.0, p.distance, c_out, float(model.n), rho=8)
+    nbr, cst, npairs = laue.laue_sparse_neighbors(geom, obs_e, model, ot)
+    assert npairs == 0 and nbr.shape[0] == 0
+    f = torch.zeros(1, dtype=torch.float32, device="cuda")
+    g = torch.zeros(max(model.n, 1), dtype=torch.float32, device="cuda")
+    laue.laue_sinkhorn(geom, obs_e, model, ot, f, g)
+    # blocks with fewer model spots than rho keep all of them, the rest is -1
+    ot = laue.ot_params(10.0, p.distance, c_out, 1.0, rho=32)
+    nbr, cst, npairs = laue.laue_sparse_neighbors(geom, obs, model, ot)
+    nbr = nbr.cpu().numpy()
+    mo, oo = P.model["offsets"], P.obs["offsets"]
+    for b in range(nb):
+        jb = mo[b + 1] - mo[b]
+        for i in range(oo[b], oo[b + 1]):
+            assert sorted(nbr[i, :jb].tolist()) == list(range(mo[b], mo[b + 1]))
+            assert np.all(nbr[i, jb:] == -1)
