@@ -26,6 +26,8 @@
 #include <numeric>
 #include <vector>
 
+#include <hipcub/hipcub.hpp>
+
 #include "common.h"
 
 namespace laue {
@@ -92,11 +94,14 @@ struct SampleDesc {
     int *cand_j, *cand_n;          // [n_obs x cand_cap], [n_obs]
     float *cand_c;                 // [n_obs x cand_cap]
     int *knn_list, *knn_nlist;     // rows for the exact pass
-    int *col_cnt, *col_fill;       // [n_model]
+    int *col_cnt;                  // [n_model]
     int64_t *col_off;              // [n_model + 1]
     int *col_row;                  // [n_obs x rho]
     float *col_cp;                 // [n_obs x rho]
     const int64_t *oboff;          // detected-spot block offsets (device)
+    int *knn_hist;                 // [nb x kGrid^2] model spots per detector cell
+    int *sort_key, *sort_val;      // [n_obs x rho] radix-sort input (column, entry)
+    const int *sorted_val;         // [n_obs x rho] entries ordered by column
 };
 
 // ---------------------------------------------------------------- helpers
@@ -650,8 +655,8 @@ __global__ __launch_bounds__(64) void k_mstep_solve(const SampleDesc *__restrict
 // chord cost (ties to the lower model-spot index); the plan is null outside
 // these sets (Sec. 4.5).  The sets are chosen afresh before every Sinkhorn
 // from the packed columns of that E-step (colsE).  Row side: nbr / ncp
-// [n_obs x rho] (model-spot index or -1, c' = c / (2 D^2)), ordered by
-// (c', index).  Column side: CSR by model spot (col_off, col_row, col_cp),
+// [rho x n_obs], neighbour-major so that a wave's rows read adjacent words
+// (model-spot index or -1, c' = c / (2 D^2)), ordered by (c', index).  Column side: CSR by model spot (col_off, col_row, col_cp),
 // rows ascending.
 
 // insert (x, xj) into the sorted register list (d, id) of length R; the last
@@ -698,14 +703,63 @@ __device__ __forceinline__ void knn_filter_body(const Item &it, const LAUE_GLOBA
     if (act) cnt_out[i] = cnt;
 }
 
+// Density grid of the model spots: kGrid x kGrid cells per block over the
+// detector square (detector-local coordinates).
+constexpr int kGrid = 16;
+
+__device__ __forceinline__ int grid_cell(float u, float half) {
+    const float t = (u + half) * (static_cast<float>(kGrid) / (2.0f * half));
+    return min(max(static_cast<int>(floorf(t)), 0), kGrid - 1);
+}
+
+__global__ void k_knn_hist(const SampleDesc *__restrict__ descs, int s) {
+    const SampleDesc &D = descs[s];
+    const int64_t j = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (j >= D.n_model) return;
+    const int b = D.mblock[j];
+    if (b < 0 || b >= D.nb) return;
+    const float half = D.geom->det[b % D.geom->n_det].half;
+    const Col8 c = D.colsE[j];
+    if (!(c.s1 == c.s1) || !(c.s2 == c.s2)) return;
+    atomicAdd(D.knn_hist + b * kGrid * kGrid + grid_cell(c.s2, half) * kGrid + grid_cell(c.s1, half), 1);
+}
+
+// Per-row filter threshold: 3 rho model spots expected within it at the
+// local density of the 3x3 cells around the row (pi r^2 lambda = 3 rho,
+// c' ~ r^2 / (2 D^2) near normal incidence); the block's mean density where
+// those cells are empty.
+__device__ __forceinline__ float knn_threshold(const SampleDesc &D, int b, float p1, float p2, int Jb) {
+    const float half = D.geom->det[b % D.geom->n_det].half;
+    const int cx = grid_cell(p1, half), cy = grid_cell(p2, half);
+    int c9 = 0, n9 = 0;
+    for (int dy = -1; dy <= 1; ++dy)
+        for (int dx = -1; dx <= 1; ++dx) {
+            const int x = cx + dx, y = cy + dy;
+            if (x < 0 || x >= kGrid || y < 0 || y >= kGrid) continue;
+            c9 += D.knn_hist[b * kGrid * kGrid + y * kGrid + x];
+            ++n9;
+        }
+    const float h = 2.0f * half / static_cast<float>(kGrid);
+    const float lambda = c9 > 0 ? static_cast<float>(c9) / (static_cast<float>(n9) * h * h)
+                                : static_cast<float>(Jb) / (4.0f * half * half);
+    return static_cast<float>(3.0 * D.rho / (M_PI * lambda * 2.0 * D.D2));
+}
+
 __global__ __launch_bounds__(64) void k_knn_filter(const Item *__restrict__ items,
                                                    const SampleDesc *__restrict__ descs) {
     const Item it = items[blockIdx.x];
     const SampleDesc &D = descs[it.s];
     const int Jb = it.c1 - it.c0;
     if (Jb <= D.rho) return;      // every column is a neighbour: the exact pass takes the row
-    knn_filter_body(it, gptr(D.p1), gptr(D.p2), gptr(D.colsE), D.cand_j, D.cand_c, D.cand_n, D.cand_cap,
-                    D.knn_k / static_cast<float>(Jb));
+    // the item's block: the last b with oboff[b] <= r0
+    int lo = 0, hi = D.nb;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) / 2;
+        if (D.oboff[mid] <= it.r0) lo = mid; else hi = mid;
+    }
+    const int i = it.r0 + static_cast<int>(threadIdx.x);
+    const float thr = i < it.r1 ? knn_threshold(D, lo, D.p1[i], D.p2[i], Jb) : 0.0f;
+    knn_filter_body(it, gptr(D.p1), gptr(D.p2), gptr(D.colsE), D.cand_j, D.cand_c, D.cand_n, D.cand_cap, thr);
 }
 
 // Selection (lane = detected spot): the rho smallest of the row's candidates
@@ -736,8 +790,8 @@ __global__ __launch_bounds__(64) void k_knn_select(const Item *__restrict__ item
     for (int t = 0; t < n; ++t) knn_insert<R>(d, id, D.cand_c[base + t], D.cand_j[base + t]);
 #pragma unroll
     for (int k = 0; k < R; ++k) {
-        D.nbr[static_cast<int64_t>(i) * R + k] = id[k];
-        D.ncp[static_cast<int64_t>(i) * R + k] = d[k];
+        D.nbr[k * D.n_obs + i] = id[k];
+        D.ncp[k * D.n_obs + i] = d[k];
     }
 }
 
@@ -770,13 +824,14 @@ __global__ __launch_bounds__(64) void k_knn_exact(const SampleDesc *__restrict__
     }
 #pragma unroll
     for (int k = 0; k < R; ++k) {
-        D.nbr[static_cast<int64_t>(i) * R + k] = id[k];
-        D.ncp[static_cast<int64_t>(i) * R + k] = d[k];
+        D.nbr[k * D.n_obs + i] = id[k];
+        D.ncp[k * D.n_obs + i] = d[k];
     }
 }
 
-// Column lists: counts, then (after a scan) filling at atomic positions, then
-// each column's list sorted by row so that sums run in a fixed order.
+// Column lists: counts and their scan give the offsets; the entries are then
+// ordered by model spot with a stable radix sort, so every list has a fixed
+// order and the sums over it are reproducible.
 __global__ void k_knn_count(const SampleDesc *__restrict__ descs, int s) {
     const SampleDesc &D = descs[s];
     const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -785,39 +840,35 @@ __global__ void k_knn_count(const SampleDesc *__restrict__ descs, int s) {
     if (j >= 0) atomicAdd(D.col_cnt + j, 1);
 }
 
-__global__ void k_knn_fill(const SampleDesc *__restrict__ descs, int s) {
+// radix-sort input: key = model spot (n_model for an empty slot), value = entry
+__global__ void k_knn_keys(const SampleDesc *__restrict__ descs, int s) {
     const SampleDesc &D = descs[s];
     const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (e >= D.n_obs * D.rho) return;
     const int j = D.nbr[e];
-    if (j < 0) return;
-    const int64_t pos = D.col_off[j] + atomicAdd(D.col_fill + j, 1);
-    D.col_row[pos] = static_cast<int>(e / D.rho);
-    D.col_cp[pos] = D.ncp[e];
+    D.sort_key[e] = j >= 0 ? j : static_cast<int>(D.n_model);
+    D.sort_val[e] = static_cast<int>(e);
 }
 
-__global__ void k_knn_sort(const SampleDesc *__restrict__ descs, int s) {
+// column lists from the entries sorted by model spot (stable: within a
+// column, entries keep their neighbour-major order)
+__global__ void k_knn_gather(const SampleDesc *__restrict__ descs, int s) {
     const SampleDesc &D = descs[s];
-    const int64_t j = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (j >= D.n_model) return;
-    const int64_t a = D.col_off[j], b = D.col_off[j + 1];
-    for (int64_t u = a + 1; u < b; ++u) {
-        const int r = D.col_row[u];
-        const float c = D.col_cp[u];
-        int64_t v = u - 1;
-        while (v >= a && D.col_row[v] > r) {
-            D.col_row[v + 1] = D.col_row[v];
-            D.col_cp[v + 1] = D.col_cp[v];
-            --v;
-        }
-        D.col_row[v + 1] = r;
-        D.col_cp[v + 1] = c;
-    }
+    const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (t >= D.col_off[D.n_model]) return;
+    const int e = D.sorted_val[t];
+    D.col_row[t] = static_cast<int>(e % D.n_obs);
+    D.col_cp[t] = D.ncp[e];
 }
 
-__global__ void k_scale_f(const float *__restrict__ a, float *__restrict__ out, int64_t n, float k) {
-    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i < n) out[i] = a[i] * k;
+// neighbour-major sets to row-major output ([n_obs x rho]), costs in mm^2
+__global__ void k_knn_out(const int *__restrict__ nbr, const float *__restrict__ ncp, int64_t n_obs, int rho,
+                          float twoD2, int *__restrict__ onbr, float *__restrict__ ocost) {
+    const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (e >= n_obs * rho) return;
+    const int64_t i = e / rho, q = e % rho;
+    onbr[e] = nbr[q * n_obs + i];
+    ocost[e] = ncp[q * n_obs + i] * twoD2;
 }
 
 __global__ void k_zero_i(int *__restrict__ p, int64_t n) {
@@ -847,11 +898,11 @@ __global__ __launch_bounds__(64) void k_row_sparse(const Item *__restrict__ item
     const bool act = i < it.r1;
     const float f = act ? Fin[i] : 0.0f;
     const float fk = f * kx;
-    const int64_t base = static_cast<int64_t>(act ? i : 0) * R;
+    const int64_t base = act ? i : 0, st = D.n_obs;   // neighbour-major: entry q of row i at q n_obs + i
     float a = 0.0f;
     for (int q = 0; q < R; ++q) {
-        const int j = act ? D.nbr[base + q] : -1;
-        if (j >= 0) a += fast_exp2(fmaf(-K, D.ncp[base + q], fmaf(D.g[j], kx, fk)));
+        const int j = act ? D.nbr[q * st + base] : -1;
+        if (j >= 0) a += fast_exp2(fmaf(-K, D.ncp[q * st + base], fmaf(D.g[j], kx, fk)));
     }
     double acc = static_cast<double>(a);
     const double eb = (g0 - p.c_out) * kexp + static_cast<double>(fk);
@@ -861,13 +912,14 @@ __global__ __launch_bounds__(64) void k_row_sparse(const Item *__restrict__ item
     if (__any(slow) && slow) {
         float mx = static_cast<float>(eb);
         for (int q = 0; q < R; ++q) {
-            const int j = D.nbr[base + q];
-            if (j >= 0) mx = fmaxf(mx, fmaf(-K, D.ncp[base + q], fmaf(D.g[j], kx, fk)));
+            const int j = D.nbr[q * st + base];
+            if (j >= 0) mx = fmaxf(mx, fmaf(-K, D.ncp[q * st + base], fmaf(D.g[j], kx, fk)));
         }
         double s2 = exp2(eb - mx);
         for (int q = 0; q < R; ++q) {
-            const int j = D.nbr[base + q];
-            if (j >= 0) s2 += exp2(static_cast<double>(fmaf(-K, D.ncp[base + q], fmaf(D.g[j], kx, fk))) - mx);
+            const int j = D.nbr[q * st + base];
+            if (j >= 0)
+                s2 += exp2(static_cast<double>(fmaf(-K, D.ncp[q * st + base], fmaf(D.g[j], kx, fk))) - mx);
         }
         logS = log(s2) + static_cast<double>(mx) * 0.6931471805599453;
     }
@@ -984,13 +1036,12 @@ __global__ __launch_bounds__(64) void k_assign_sparse(const Item *__restrict__ i
     const float kx = static_cast<float>(kexp);
     const float K = p.twoD2 * kx;
     const float fk = D.f[i] * kx;
-    const int64_t base = static_cast<int64_t>(i) * D.rho;
     float best = -INFINITY;
     int arg = -1;
     for (int q = 0; q < D.rho; ++q) {
-        const int j = D.nbr[base + q];
+        const int j = D.nbr[q * D.n_obs + i];
         if (j < 0) continue;
-        const float e = fmaf(-K, D.ncp[base + q], fmaf(D.g[j], kx, fk));
+        const float e = fmaf(-K, D.ncp[q * D.n_obs + i], fmaf(D.g[j], kx, fk));
         if (e > best || (e == best && j < arg)) {
             best = e;
             arg = j;
@@ -1119,7 +1170,10 @@ struct SampleWs {
     // sparse assignment (rho > 0)
     int *nbr = nullptr, *cand_j = nullptr, *cand_n = nullptr, *knn_list = nullptr, *knn_nlist = nullptr;
     float *ncp = nullptr, *cand_c = nullptr, *col_cp = nullptr;
-    int *col_cnt = nullptr, *col_fill = nullptr, *col_row = nullptr;
+    int *col_cnt = nullptr, *col_row = nullptr, *knn_hist = nullptr;
+    int *sk_in = nullptr, *sk_out = nullptr, *sv_in = nullptr, *sv_out = nullptr;
+    void *sort_tmp = nullptr;
+    size_t sort_tmp_bytes = 0;
     int64_t *col_off = nullptr, *oboff = nullptr;
 };
 
@@ -1169,7 +1223,15 @@ static size_t carve_all(Carver &cv, BatchWs &bw, std::vector<SampleWs> &sw, cons
             w.knn_list = cv.take<int>(no);
             w.knn_nlist = cv.take<int>(1);
             w.col_cnt = cv.take<int>(nm);
-            w.col_fill = cv.take<int>(nm);
+            w.knn_hist = cv.take<int>(static_cast<int64_t>(nb) * kGrid * kGrid);
+            w.sk_in = cv.take<int>(no * d.rho);
+            w.sk_out = cv.take<int>(no * d.rho);
+            w.sv_in = cv.take<int>(no * d.rho);
+            w.sv_out = cv.take<int>(no * d.rho);
+            // radix-sort scratch: a bound on what the sort asks for (its own
+            // double buffers and digit histograms); checked at run time
+            w.sort_tmp_bytes = static_cast<size_t>(no * d.rho) * 24 + (size_t(32) << 20);
+            w.sort_tmp = cv.take<uint8_t>(static_cast<int64_t>(w.sort_tmp_bytes));
             w.col_off = cv.take<int64_t>(nm + 1);
             w.col_row = cv.take<int>(no * d.rho);
             w.col_cp = cv.take<float>(no * d.rho);
@@ -1322,7 +1384,10 @@ struct BatchEngine {
             k_zero_i<<<1, 64, 0, s>>>(sw[k].knn_nlist, 1);
             const int64_t nm = std::max<int64_t>(in[k].model->n, 1);
             k_zero_i<<<static_cast<unsigned>((nm + 255) / 256), 256, 0, s>>>(sw[k].col_cnt, nm);
-            k_zero_i<<<static_cast<unsigned>((nm + 255) / 256), 256, 0, s>>>(sw[k].col_fill, nm);
+            const int64_t nh = static_cast<int64_t>(in[k].geom->n_rot) * in[k].geom->n_det * kGrid * kGrid;
+            k_zero_i<<<static_cast<unsigned>((nh + 255) / 256), 256, 0, s>>>(sw[k].knn_hist, nh);
+            if (in[k].model->n > 0)
+                k_knn_hist<<<static_cast<unsigned>((in[k].model->n + 255) / 256), 256, 0, s>>>(bw.desc, k);
         }
         if (n_rows) {
             k_knn_filter<<<n_rows, 64, 0, s>>>(bw.rows, bw.desc);
@@ -1357,8 +1422,19 @@ struct BatchEngine {
             k_knn_count<<<static_cast<unsigned>((ne + 255) / 256), 256, 0, s>>>(bw.desc, k);
             int rc;
             if ((rc = launch_scan(sw[k].col_cnt, sw[k].col_off, nm, s))) return rc;
-            k_knn_fill<<<static_cast<unsigned>((ne + 255) / 256), 256, 0, s>>>(bw.desc, k);
-            k_knn_sort<<<static_cast<unsigned>((nm + 255) / 256), 256, 0, s>>>(bw.desc, k);
+            k_knn_keys<<<static_cast<unsigned>((ne + 255) / 256), 256, 0, s>>>(bw.desc, k);
+            int bits = 1;
+            while ((int64_t(1) << bits) <= nm) ++bits;
+            size_t tmp = 0;
+            LAUE_CHECK_HIP(hipcub::DeviceRadixSort::SortPairs(nullptr, tmp, sw[k].sk_in, sw[k].sk_out, sw[k].sv_in,
+                                                             sw[k].sv_out, static_cast<int>(ne), 0, bits, s));
+            LAUE_REQUIRE(tmp <= sw[k].sort_tmp_bytes, LAUE_EWORKSPACE,
+                         "internal: radix sort needs " + std::to_string(tmp) + " bytes, the workspace holds " +
+                             std::to_string(sw[k].sort_tmp_bytes));
+            LAUE_CHECK_HIP(hipcub::DeviceRadixSort::SortPairs(sw[k].sort_tmp, tmp, sw[k].sk_in, sw[k].sk_out,
+                                                             sw[k].sv_in, sw[k].sv_out, static_cast<int>(ne), 0,
+                                                             bits, s));
+            k_knn_gather<<<static_cast<unsigned>((ne + 255) / 256), 256, 0, s>>>(bw.desc, k);
         }
         LAUE_CHECK_HIP(hipGetLastError());
         std::vector<int64_t> tot(n, 0);
@@ -1558,7 +1634,10 @@ struct BatchEngine {
                 D.knn_list = sw[k].knn_list;
                 D.knn_nlist = sw[k].knn_nlist;
                 D.col_cnt = sw[k].col_cnt;
-                D.col_fill = sw[k].col_fill;
+                D.knn_hist = sw[k].knn_hist;
+                D.sort_key = sw[k].sk_in;
+                D.sort_val = sw[k].sv_in;
+                D.sorted_val = sw[k].sv_out;
                 D.col_off = sw[k].col_off;
                 D.col_row = sw[k].col_row;
                 D.col_cp = sw[k].col_cp;
@@ -1635,7 +1714,8 @@ struct BatchEngine {
 
     // k_gn Gauss-Newton steps with the plan of (potentials, eps, colsE) fixed,
     // then the forward model at the new grains for the next E-step.
-    void mstep_launches(hipStream_t st, int k_gn) {
+    // k_gn Gauss-Newton steps: statistics (dense or sparse) and the per-grain solve
+    void gn_steps(hipStream_t st, int k_gn) {
         for (int k = 0; k < k_gn; ++k) {
             if (k > 0) eval_on(st, 1, 0);
             if (mbase[n] > 0) {
@@ -1647,6 +1727,10 @@ struct BatchEngine {
             if (gbase[n] > 0)
                 k_mstep_solve<<<static_cast<unsigned>(gbase[n]), 64, 0, st>>>(bw.desc, n, bw.gbase);
         }
+    }
+
+    void mstep_launches(hipStream_t st, int k_gn) {
+        gn_steps(st, k_gn);
         eval_on(st, 0, 1);
     }
 
@@ -1792,12 +1876,7 @@ struct BatchEngine {
             if ((rc = mstep_graph(k_gn, &gx))) return rc;
             LAUE_CHECK_HIP(hipGraphLaunch(gx, s));
         } else {
-            for (int k = 0; k < k_gn; ++k) {
-                if (k > 0) eval_on(s, 1, 0);
-                if (mbase[n] > 0) k_mstep_acc<<<n_cols, 64, 0, s>>>(bw.cols, bw.desc, k > 0 ? 1 : 0);
-                if (gbase[n] > 0)
-                    k_mstep_solve<<<static_cast<unsigned>(gbase[n]), 64, 0, s>>>(bw.desc, n, bw.gbase);
-            }
+            gn_steps(s, k_gn);
             if (eval_next) eval_on(s, 0, 1);
             LAUE_CHECK_HIP(hipGetLastError());
         }
@@ -2046,10 +2125,9 @@ extern "C" int laue_sparse_neighbors(const laue_geometry *geom, const laue_obs_s
     if ((rc = e.build_neighbors())) return rc;
     const int64_t ne = obs->n * static_cast<int64_t>(par->rho);
     if (ne > 0) {
-        LAUE_CHECK_HIP(hipMemcpyAsync(nbr, e.sw[0].nbr, ne * sizeof(int32_t), hipMemcpyDeviceToDevice, e.s));
-        k_scale_f<<<static_cast<unsigned>((ne + 255) / 256), 256, 0, e.s>>>(e.sw[0].ncp, cost, ne,
-                                                                          static_cast<float>(2.0 * par->distance *
-                                                                                             par->distance));
+        k_knn_out<<<static_cast<unsigned>((ne + 255) / 256), 256, 0, e.s>>>(
+            e.sw[0].nbr, e.sw[0].ncp, obs->n, par->rho, static_cast<float>(2.0 * par->distance * par->distance), nbr,
+            cost);
         LAUE_CHECK_HIP(hipGetLastError());
     }
     if (n_pairs) *n_pairs = e.sparse_entries[0];

@@ -205,3 +205,53 @@ def test_sparse_degenerate_and_errors(gpu_lib):
         for i in range(oo[b], oo[b + 1]):
             assert sorted(nbr[i, :jb].tolist()) == list(range(mo[b], mo[b + 1]))
             assert np.all(nbr[i, jb:] == -1)
+
+
+def test_sparse_mstep_matches_oracle(gpu_lib, prob):
+    """One sparse M-step (k_GN = 2) from the oracle's sparse potentials at a
+    hot temperature, where the dropped pairs would still weigh a lot: the
+    library's grains match the oracle's, and a dense M-step on the same
+    potentials lands visibly elsewhere (so the test tells the two apart)."""
+    from oracle import mstep
+    laue = gpu_lib
+    p = prob.preset
+    rho = 8
+    eps = 111.0 * p.sigma_mm ** 2
+    geom, planes, obs, model = _problems.gpu_objects(laue, prob)
+    t_b = sinkhorn.default_tb(model.n)
+    c_out = cost.c_out(p.sigma_mm, p.distance)
+    ot = laue.ot_params(eps, p.distance, c_out, t_b, rho=rho)
+    nbr, _, _ = laue.laue_sparse_neighbors(geom, obs, model, ot)
+    _, rj, _ = _oracle_sets(prob, rho)
+    nbr = nbr.cpu().numpy()
+    if not all(sorted(nbr[i, :len(rj[i])].tolist()) == sorted(rj[i]) for i in range(obs.n)):
+        pytest.skip("a near-tie puts a different model spot in one set; the set test covers it")
+    C = _problems.oracle_costs(prob)
+    P = sparse.masked_problem(sinkhorn.Problem(C, c_out, 0.0, c_out, t_b), rho)
+    ref = sinkhorn.solve(P, eps, tol=1e-6, n_max=5000)
+    f32 = ig.to_f32_exact(ref["f"])
+    g32 = ig.to_f32_exact(ref["g"])
+    Qb = sinkhorn.plan_blocks(P, f32, g32, eps)
+    p_lab = oem.obs_lab(prob.geom, prob.obs["p12"], prob.obs["block"])
+    pairs = oem.grain_pairs(prob.planes, prob.geom, p_lab, prob.obs["offsets"], prob.model, Qb, len(prob.q0))
+    q_or, x_or = prob.q0.copy(), prob.x0.copy()
+    for _ in range(2):
+        for n, pr in enumerate(pairs):
+            if pr is not None:
+                q_or[n], x_or[n], *_ = mstep.gn_step(pr, q_or[n], x_or[n], prob.geom, p.distance)
+    res = {}
+    for r in (rho, 0):
+        grains = laue.Grains(prob.q0, prob.x0)
+        f = torch.tensor(f32, dtype=torch.float32, device="cuda")
+        g = torch.tensor(g32, dtype=torch.float32, device="cuda")
+        laue.laue_mstep(geom, planes, obs, model, laue.ot_params(eps, p.distance, c_out, t_b, rho=r), f, g, grains,
+                        k_gn=2)
+        res[r] = grains.numpy()
+    qg, xg = res[rho]
+    assert np.max(np.degrees(metrics.misorientation(qg, q_or))) < 1e-3
+    assert np.max(np.linalg.norm(xg - x_or, axis=1)) < 2e-3
+    if int(np.max(np.diff(prob.model["offsets"]))) > 4 * rho:
+        # blocks far wider than rho: the dropped pairs matter at this temperature
+        qd, xd = res[0]
+        assert (np.max(np.degrees(metrics.misorientation(qd, q_or))) > 1e-2 or
+                np.max(np.linalg.norm(xd - x_or, axis=1)) > 2e-2)
