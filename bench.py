@@ -271,18 +271,23 @@ def bench_index(laue, workload, n_pairs, learned_pairs, log):
     return out
 
 
-def bench_sparse(laue, preset, rho, n_iter, log):
+def bench_sparse(laue, preset, rho, n_iter, log, first_iter=8):
     """The same EM iterations from the same start, dense and with the sparse
     assignment (each detected spot keeps its rho nearest model spots, sets
     rebuilt before every Sinkhorn): time per iteration, the sparse passes'
-    pairs/s, and how far the sparse grains end from the dense ones."""
+    pairs/s, and how far the sparse grains end from the dense ones.  The
+    iterations start at first_iter of the schedule (stage 2, eps = 11.1
+    sigma^2): the paper starts a sparse EM at a temperature tied to the
+    farthest kept neighbour, reported here as median c_(rho) / ln 100."""
     import torch
     import inputgen as ig
     q, x = ig.random_grains(preset)
     c_out = 2.0 * preset.distance ** 2 * (1.0 - math.cos(3.0 * preset.sigma_mm / preset.distance))
     eps_list = [preset.eps_start * (preset.eps_end / preset.eps_start) ** (s / (preset.n_stages - 1))
                 for s in range(preset.n_stages) for _ in range(preset.iters_per_stage)]
-    out = {"rho": rho, "em_iterations": n_iter}
+    out = {"rho": rho, "em_iterations": [first_iter, first_iter + n_iter],
+           "eps_mm2": sorted({round(eps_list[k % len(eps_list)], 4) for k in range(first_iter, first_iter + n_iter)},
+                             reverse=True)}
     res = {}
     for r in (0, rho):
         geom, planes, obs, model, grains = build_problem(laue, preset)
@@ -294,7 +299,15 @@ def bench_sparse(laue, preset, rho, n_iter, log):
         stats = []
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        for k in range(n_iter):
+        if r:
+            nbr, cst, _ = laue.laue_sparse_neighbors(
+                geom, obs, model, laue.ot_params(1.0, preset.distance, c_out, 1.0, rho=r))
+            far = cst[:, -1].double().cpu().numpy()
+            far = far[np.isfinite(far)]
+            out["eps_init_mm2"] = float(np.median(far) / math.log(100.0)) if len(far) else None
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+        for k in range(first_iter, first_iter + n_iter):
             eps = eps_list[k % len(eps_list)]
             ot = laue.ot_params(eps, preset.distance, c_out, t_b, tol=1e-5, n_max=2000, rho=r)
             par = laue.em_params(ot, eps, eps, 1, 1, k_gn=2)

@@ -94,7 +94,6 @@ struct SampleDesc {
     int *cand_j, *cand_n;          // [n_obs x cand_cap], [n_obs]
     float *cand_c;                 // [n_obs x cand_cap]
     int *knn_list, *knn_nlist;     // rows for the exact pass
-    int *col_cnt;                  // [n_model]
     int64_t *col_off;              // [n_model + 1]
     int *col_row;                  // [n_obs x rho]
     float *col_cp;                 // [n_obs x rho]
@@ -683,19 +682,19 @@ __device__ __forceinline__ void knn_filter_body(const Item &it, const LAUE_GLOBA
                                                 const LAUE_GLOBAL float *__restrict__ P2,
                                                 const LAUE_GLOBAL Col8 *__restrict__ cols, int *__restrict__ cj,
                                                 float *__restrict__ cc, int *__restrict__ cnt_out, int M,
-                                                float thr) {
+                                                float thr, int64_t n_obs) {
     const int i = it.r0 + static_cast<int>(threadIdx.x);
     const bool act = i < it.r1;
     const float p1 = act ? P1[i] : 0.0f, p2 = act ? P2[i] : 0.0f;
     int cnt = 0;
-    const int64_t base = static_cast<int64_t>(act ? i : 0) * M;
+    const int64_t base = act ? i : 0;   // candidate-major: candidate t of row i at t n_obs + i
     for (int j = it.c0; j < it.c1; ++j) {
         const Col8 c = ld_col(cols + j);
         const float cp = chord_cp(p1, p2, c.s1, c.s2, c.v1, c.v2, c.vv, c.vv2);
         if (act && cp < thr) {
             if (cnt < M) {
-                cj[base + cnt] = j;
-                cc[base + cnt] = cp;
+                cj[cnt * n_obs + base] = j;
+                cc[cnt * n_obs + base] = cp;
             }
             ++cnt;
         }
@@ -759,7 +758,8 @@ __global__ __launch_bounds__(64) void k_knn_filter(const Item *__restrict__ item
     }
     const int i = it.r0 + static_cast<int>(threadIdx.x);
     const float thr = i < it.r1 ? knn_threshold(D, lo, D.p1[i], D.p2[i], Jb) : 0.0f;
-    knn_filter_body(it, gptr(D.p1), gptr(D.p2), gptr(D.colsE), D.cand_j, D.cand_c, D.cand_n, D.cand_cap, thr);
+    knn_filter_body(it, gptr(D.p1), gptr(D.p2), gptr(D.colsE), D.cand_j, D.cand_c, D.cand_n, D.cand_cap, thr,
+                    D.n_obs);
 }
 
 // Selection (lane = detected spot): the rho smallest of the row's candidates
@@ -786,8 +786,7 @@ __global__ __launch_bounds__(64) void k_knn_select(const Item *__restrict__ item
         d[k] = INFINITY;
         id[k] = -1;
     }
-    const int64_t base = static_cast<int64_t>(i) * D.cand_cap;
-    for (int t = 0; t < n; ++t) knn_insert<R>(d, id, D.cand_c[base + t], D.cand_j[base + t]);
+    for (int t = 0; t < n; ++t) knn_insert<R>(d, id, D.cand_c[t * D.n_obs + i], D.cand_j[t * D.n_obs + i]);
 #pragma unroll
     for (int k = 0; k < R; ++k) {
         D.nbr[k * D.n_obs + i] = id[k];
@@ -829,17 +828,9 @@ __global__ __launch_bounds__(64) void k_knn_exact(const SampleDesc *__restrict__
     }
 }
 
-// Column lists: counts and their scan give the offsets; the entries are then
-// ordered by model spot with a stable radix sort, so every list has a fixed
-// order and the sums over it are reproducible.
-__global__ void k_knn_count(const SampleDesc *__restrict__ descs, int s) {
-    const SampleDesc &D = descs[s];
-    const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (e >= D.n_obs * D.rho) return;
-    const int j = D.nbr[e];
-    if (j >= 0) atomicAdd(D.col_cnt + j, 1);
-}
-
+// Column lists: the entries are ordered by model spot with a stable radix
+// sort (every list then has a fixed order and the sums over it are
+// reproducible); the offsets are found by binary search in the sorted keys.
 // radix-sort input: key = model spot (n_model for an empty slot), value = entry
 __global__ void k_knn_keys(const SampleDesc *__restrict__ descs, int s) {
     const SampleDesc &D = descs[s];
@@ -848,6 +839,20 @@ __global__ void k_knn_keys(const SampleDesc *__restrict__ descs, int s) {
     const int j = D.nbr[e];
     D.sort_key[e] = j >= 0 ? j : static_cast<int>(D.n_model);
     D.sort_val[e] = static_cast<int>(e);
+}
+
+// column offsets from the sorted keys: col_off[j] = first sorted entry with
+// key >= j (keys of empty slots are n_model and sort last)
+__global__ void k_knn_offsets(const SampleDesc *__restrict__ descs, int s, const int *__restrict__ skey) {
+    const SampleDesc &D = descs[s];
+    const int64_t j = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (j > D.n_model) return;
+    int64_t lo = 0, hi = D.n_obs * D.rho;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (skey[mid] < j) lo = mid + 1; else hi = mid;
+    }
+    D.col_off[j] = lo;
 }
 
 // column lists from the entries sorted by model spot (stable: within a
@@ -1170,7 +1175,7 @@ struct SampleWs {
     // sparse assignment (rho > 0)
     int *nbr = nullptr, *cand_j = nullptr, *cand_n = nullptr, *knn_list = nullptr, *knn_nlist = nullptr;
     float *ncp = nullptr, *cand_c = nullptr, *col_cp = nullptr;
-    int *col_cnt = nullptr, *col_row = nullptr, *knn_hist = nullptr;
+    int *col_row = nullptr, *knn_hist = nullptr;
     int *sk_in = nullptr, *sk_out = nullptr, *sv_in = nullptr, *sv_out = nullptr;
     void *sort_tmp = nullptr;
     size_t sort_tmp_bytes = 0;
@@ -1222,7 +1227,6 @@ static size_t carve_all(Carver &cv, BatchWs &bw, std::vector<SampleWs> &sw, cons
             w.cand_n = cv.take<int>(no);
             w.knn_list = cv.take<int>(no);
             w.knn_nlist = cv.take<int>(1);
-            w.col_cnt = cv.take<int>(nm);
             w.knn_hist = cv.take<int>(static_cast<int64_t>(nb) * kGrid * kGrid);
             w.sk_in = cv.take<int>(no * d.rho);
             w.sk_out = cv.take<int>(no * d.rho);
@@ -1383,7 +1387,6 @@ struct BatchEngine {
         for (int k = 0; k < n; ++k) {
             k_zero_i<<<1, 64, 0, s>>>(sw[k].knn_nlist, 1);
             const int64_t nm = std::max<int64_t>(in[k].model->n, 1);
-            k_zero_i<<<static_cast<unsigned>((nm + 255) / 256), 256, 0, s>>>(sw[k].col_cnt, nm);
             const int64_t nh = static_cast<int64_t>(in[k].geom->n_rot) * in[k].geom->n_det * kGrid * kGrid;
             k_zero_i<<<static_cast<unsigned>((nh + 255) / 256), 256, 0, s>>>(sw[k].knn_hist, nh);
             if (in[k].model->n > 0)
@@ -1419,9 +1422,6 @@ struct BatchEngine {
                 continue;
             }
             const int64_t ne = no * rho;
-            k_knn_count<<<static_cast<unsigned>((ne + 255) / 256), 256, 0, s>>>(bw.desc, k);
-            int rc;
-            if ((rc = launch_scan(sw[k].col_cnt, sw[k].col_off, nm, s))) return rc;
             k_knn_keys<<<static_cast<unsigned>((ne + 255) / 256), 256, 0, s>>>(bw.desc, k);
             int bits = 1;
             while ((int64_t(1) << bits) <= nm) ++bits;
@@ -1434,6 +1434,7 @@ struct BatchEngine {
             LAUE_CHECK_HIP(hipcub::DeviceRadixSort::SortPairs(sw[k].sort_tmp, tmp, sw[k].sk_in, sw[k].sk_out,
                                                              sw[k].sv_in, sw[k].sv_out, static_cast<int>(ne), 0,
                                                              bits, s));
+            k_knn_offsets<<<static_cast<unsigned>((nm + 1 + 255) / 256), 256, 0, s>>>(bw.desc, k, sw[k].sk_out);
             k_knn_gather<<<static_cast<unsigned>((ne + 255) / 256), 256, 0, s>>>(bw.desc, k);
         }
         LAUE_CHECK_HIP(hipGetLastError());
@@ -1633,7 +1634,6 @@ struct BatchEngine {
                 D.cand_n = sw[k].cand_n;
                 D.knn_list = sw[k].knn_list;
                 D.knn_nlist = sw[k].knn_nlist;
-                D.col_cnt = sw[k].col_cnt;
                 D.knn_hist = sw[k].knn_hist;
                 D.sort_key = sw[k].sk_in;
                 D.sort_val = sw[k].sv_in;
