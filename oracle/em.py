@@ -14,7 +14,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from . import cost, forward, mstep, sinkhorn, sparse
+from . import cost, forward, mstep, sinkhorn, sparse, unbalanced
 
 
 def eps_schedule(eps0, eps_end, n_stages, iters_per_stage):
@@ -70,10 +70,14 @@ def grain_pairs(planes, geom, p_lab, obs_off, model, Qb, n_grains):
 
 
 def run(planes, geom, distance, p12, obs_off, model, q0, x0, eps_list, c_out, c_unm=0.0,
-        c_sink=None, t_b=None, k_gn=2, tol=1e-5, n_max=2000, record=False, rho=None):
+        c_sink=None, t_b=None, k_gn=2, tol=1e-5, n_max=2000, record=False, rho=None,
+        unbalanced_kl=None):
     """Run the EM.  model: dict with m, n, t, det (block-sorted) and offsets.
     rho: keep only each detected spot's rho nearest model spots, re-chosen at
     every EM iteration from that iteration's costs (oracle/sparse.py).
+    unbalanced_kl: (kappa, lambda) replaces the E-step by unbalanced OT
+    (oracle/unbalanced.py; no bins, so c_out, c_unm, c_sink and t_b are
+    unused and f0, g0 come back as -inf).
 
     Returns dict with q, x, f, g, f0, g0 and per-iteration stats."""
     c_sink = c_out if c_sink is None else c_sink
@@ -88,12 +92,18 @@ def run(planes, geom, distance, p12, obs_off, model, q0, x0, eps_list, c_out, c_
     stats = []
     for it, eps in enumerate(eps_list):
         C, _, _ = build_costs(planes, geom, distance, p12, obs_off, model, q, x)
-        P = sinkhorn.Problem(C, c_out, c_unm, c_sink, t_b)
-        if rho:
-            P = sparse.masked_problem(P, rho)
-        sol = sinkhorn.solve(P, eps, tol=tol, n_max=n_max, f=f, g=g, f0=f0, g0=g0)
-        f, g, f0, g0 = sol["f"], sol["g"], sol["f0"], sol["g0"]
-        Qb = sinkhorn.plan_blocks(P, f, g, eps)
+        if unbalanced_kl is not None:
+            Cm = sparse.masked_blocks(C, rho) if rho else C
+            sol = unbalanced.solve(Cm, eps, unbalanced_kl[0], unbalanced_kl[1], tol=tol, n_max=n_max, f=f, g=g)
+            f, g, f0, g0 = sol["f"], sol["g"], -np.inf, -np.inf
+            Qb = unbalanced.plan_blocks(Cm, f, g, eps)
+        else:
+            P = sinkhorn.Problem(C, c_out, c_unm, c_sink, t_b)
+            if rho:
+                P = sparse.masked_problem(P, rho)
+            sol = sinkhorn.solve(P, eps, tol=tol, n_max=n_max, f=f, g=g, f0=f0, g0=g0)
+            f, g, f0, g0 = sol["f"], sol["g"], sol["f0"], sol["g0"]
+            Qb = sinkhorn.plan_blocks(P, f, g, eps)
         pairs = grain_pairs(planes, geom, p_lab, obs_off, model, Qb, N)
         steps = np.zeros((N, 6))
         for k in range(k_gn):
