@@ -18,9 +18,15 @@ Readings:
     lambda on the column marginal, the printed algorithm the other way round;
     the text is followed: tau_r = kappa / (kappa + eps), tau_c = lambda /
     (lambda + eps);
-  * stopping: the algorithm's max(||x' - x||, ||y' - y||) has no norm; read as
-    the largest relative change of a scaling, max(|f' - f|, |g' - g|) / eps,
-    after a column half, <= tol, or n_max iterations;
+  * stopping: the algorithm's max(||x' - x||, ||y' - y||) names neither norm
+    nor scale; read as the largest change an update makes to a row (column)
+    marginal of the plan, S |exp(du / eps) - 1| with S that row's (column's)
+    plan mass before the update and du its potential change, after a column
+    half, <= tol, or n_max iterations.  It is the balanced rule's |row - 1|
+    (the row-marginal error) carried over: an update scales its row by
+    exp(du / eps).  A relative change of the scaling alone, |du| / eps, would
+    also count spots far from every model spot, whose potentials are large,
+    carry no mass and cannot settle below their rounding in FP32;
   * a row (column) with no finite cost (a block without model (detected)
     spots, or no kept entry under a sparse mask) carries no plan mass; its
     potential is set to 0;
@@ -79,6 +85,16 @@ def col_update(C_blocks, row_off, col_off, f, eps, tau):
     return g
 
 
+def mass_change(S, du, eps):
+    """max |S exp(du / eps) - S| over rows (columns) with plan mass S before
+    an update that changes their potential by du (0 for no rows)."""
+    if len(S) == 0:
+        return 0.0
+    with np.errstate(divide="ignore"):
+        logS = np.log(S)
+    return float(np.max(np.abs(np.exp(logS + du / eps) - S)))
+
+
 def solve(C_blocks, eps, kappa, lam, tol=1e-5, n_max=2000, f=None, g=None):
     """Iterations from (f, g) (zeros = the algorithm's x = y = 1).  Returns
     dict with f, g, n_iter, err, row_off, col_off."""
@@ -91,10 +107,11 @@ def solve(C_blocks, eps, kappa, lam, tol=1e-5, n_max=2000, f=None, g=None):
     err = math.inf
     k = 0
     for k in range(1, n_max + 1):
+        s_row = marginals(C_blocks, f, g, eps)[0]
         fn = row_update(C_blocks, row_off, col_off, g, eps, tau_r)
+        s_col = marginals(C_blocks, fn, g, eps)[1]
         gn = col_update(C_blocks, row_off, col_off, fn, eps, tau_c)
-        err = max(float(np.max(np.abs(fn - f))) if len(f) else 0.0,
-                  float(np.max(np.abs(gn - g))) if len(g) else 0.0) / eps
+        err = max(mass_change(s_row, fn - f, eps), mass_change(s_col, gn - g, eps))
         f, g = fn, gn
         if err <= tol:
             break

@@ -65,13 +65,34 @@ def test_contraction_rate():
     eps, kappa, lam = 1.0, 2.0, 0.5
     tau = kappa / (kappa + eps) * lam / (lam + eps)
     errs = []
-    f = g = None
+    f, g = np.zeros(sum(c.shape[0] for c in C)), np.zeros(sum(c.shape[1] for c in C))
     for _ in range(12):
         s = ub.solve(C, eps, kappa, lam, tol=0.0, n_max=1, f=f, g=g)
+        errs.append(max(np.max(np.abs(s["f"] - f)), np.max(np.abs(s["g"] - g))))
         f, g = s["f"], s["g"]
-        errs.append(s["err"])
     for a, b in zip(errs[1:], errs[2:]):
         assert b <= tau * a * (1 + 1e-9) + 1e-15
+
+
+def test_stopping_value_is_the_marginal_change():
+    """The stopping value is the largest change an update makes to a plan
+    marginal: a row half from (f, g) moves row i from S_i to
+    S_i exp((f'_i - f_i)/eps), checked against plan sums taken directly."""
+    rng = np.random.default_rng(10)
+    C = _blocks(rng, [(5, 7), (6, 4)])
+    eps, kappa, lam = 0.9, 0.7, 1.3
+    f, g = rng.normal(0, 0.5, 11), rng.normal(0, 0.5, 11)
+    s = ub.solve(C, eps, kappa, lam, tol=0.0, n_max=1, f=f, g=g)
+    r0 = ub.marginals(C, f, g, eps)[0]
+    r1 = ub.marginals(C, s["f"], g, eps)[0]
+    c0 = ub.marginals(C, s["f"], g, eps)[1]
+    c1 = ub.marginals(C, s["f"], s["g"], eps)[1]
+    want = max(np.max(np.abs(r1 - r0)), np.max(np.abs(c1 - c0)))
+    assert s["err"] == pytest.approx(want, rel=1e-12)
+    # a row far from everything moves its potential a lot but its (zero) mass not at all
+    Cf = [np.vstack([C[0], np.full((1, 7), 1e4)]), C[1]]
+    s = ub.solve(Cf, eps, kappa, lam, tol=1e-9, n_max=10000)
+    assert s["err"] <= 1e-9 and s["f"][5] > 1e3
 
 
 def test_balanced_limit_is_an_optimal_assignment():
