@@ -230,6 +230,22 @@ typedef struct laue_ot_params {
      * lone M-step) from that call's model-spot columns.  The workspace then
      * comes from laue_sparse_workspace_size. */
     int32_t rho;
+    /* outlier treatment: 0 = the outlier row and column of Sec. 4.3 (bins
+     * c_out, c_unm, c_sink and mass T_b); 1 = unbalanced OT (App. B,
+     * Problem B): no bins (c_out, c_unm, c_sink and t_b are ignored; the bin
+     * potentials come back as -inf), the row and column marginals relaxed by
+     * KL penalties of strengths kappa (detected spots) and lam (model spots),
+     * in mm^2 like eps (a strength k in log-likelihood units is
+     * k * 2 sigma_mm^2).  Rows update as f <- tau_r (f - eps ln S_row),
+     * columns as g <- tau_c (g - eps ln S_col), with tau_r = kappa / (kappa +
+     * eps), tau_c = lam / (lam + eps) and S the previous state's plan sums; a
+     * row or column with no entry gets potential 0.  Stop when the largest
+     * change an update of the iteration makes to a row or column marginal of
+     * the plan, S |exp(du / eps) - 1| (S its mass before the update, du its
+     * potential change), is <= tol (or, as above, within 4 tol and stalled
+     * for 64 iterations). */
+    int32_t outlier_model;
+    double kappa, lam;
 } laue_ot_params;
 
 /* Dual potentials: Q_ij = exp((f_i + g_j - c_ij) / eps).  f [n_obs], g
@@ -243,7 +259,9 @@ typedef struct laue_potentials {
 typedef struct laue_ot_stats {
     int32_t n_iter;             /* completed row+column iterations */
     int32_t converged;
-    double err;                 /* max relative row-marginal error at the end */
+    double err;                 /* the stopping test's value at the end: max relative
+                                 * row-marginal error (outlier_model 0), largest
+                                 * marginal change of an update (outlier_model 1) */
 } laue_ot_stats;
 
 size_t laue_sinkhorn_workspace_size(const laue_geometry *geom, int64_t n_obs, int64_t n_model,
@@ -252,8 +270,11 @@ size_t laue_sinkhorn_workspace_size(const laue_geometry *geom, int64_t n_obs, in
 /* Sinkhorn iterations (Alg. BalancedOT in the log domain) from the given
  * potentials: row half (all f_i and f_0 from g, g0), then column half (all
  * g_j and g_0 from the new f, f0), until the max relative row-marginal error
- * after a column half is <= tol or n_max iterations.  Uses the model spots'
- * s1, s2, vn, v1, v2.  Synchronous.  Returns LAUE_ENOCONV at the cap. */
+ * after a column half is <= tol or n_max iterations.  With
+ * par->outlier_model = 1 the iterations are those of Alg. UnbalancedOT
+ * instead (see laue_ot_params; f0, g0 are then not read and come back as
+ * -inf).  Uses the model spots' s1, s2, vn, v1, v2.  Synchronous.  Returns
+ * LAUE_ENOCONV at the cap. */
 int laue_sinkhorn(const laue_geometry *geom, const laue_obs_spots *obs,
                   const laue_model_spots *model, const laue_ot_params *par,
                   laue_potentials *pot, laue_ot_stats *stats,
@@ -336,7 +357,10 @@ typedef struct laue_em_stats {
 
 /* Per detected spot (device, may be NULL): j_star = argmax over its block's
  * model spots and the outlier column of Q (lowest index on ties; -1 for the
- * outlier column), its grain (-1 for outlier), q_star = Q_ij*, q_out = Q_i0. */
+ * outlier column), its grain (-1 for outlier), q_star = Q_ij*, q_out = Q_i0.
+ * Under unbalanced OT (no outlier column) q_out is the mass the plan leaves
+ * untransported, max(0, 1 - sum_j Q_ij), and takes the outlier column's
+ * place in the comparison. */
 typedef struct laue_assignments {
     int32_t *j_star;
     int32_t *grain;

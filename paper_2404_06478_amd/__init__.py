@@ -275,13 +275,18 @@ def laue_simulate(geom, planes, truth, sigma_mm, distance, outlier_frac, seed):
 
 # ---------------------------------------------------------------- E / M steps
 
-def ot_params(eps, distance, c_out, t_b, c_unm=0.0, c_sink=None, tol=1e-5, n_max=2000, chunk=0, rho=0):
-    """rho: 0 dense; 8, 16 or 32 keeps each detected spot's rho nearest model spots."""
+def ot_params(eps, distance, c_out, t_b, c_unm=0.0, c_sink=None, tol=1e-5, n_max=2000, chunk=0, rho=0,
+              unbalanced_kl=None):
+    """rho: 0 dense; 8, 16 or 32 keeps each detected spot's rho nearest model spots.
+    unbalanced_kl: (kappa, lam) in mm^2 selects unbalanced OT (no bins)."""
     p = laue_ot_params()
     p.eps, p.distance, p.c_out, p.c_unm = float(eps), float(distance), float(c_out), float(c_unm)
     p.c_sink = float(c_out if c_sink is None else c_sink)
     p.t_b, p.tol, p.n_max, p.chunk = float(t_b), float(tol), int(n_max), int(chunk)
     p.rho = int(rho)
+    if unbalanced_kl is not None:
+        p.outlier_model = 1
+        p.kappa, p.lam = float(unbalanced_kl[0]), float(unbalanced_kl[1])
     return p
 
 

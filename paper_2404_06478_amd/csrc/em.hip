@@ -54,13 +54,37 @@ struct SinkCtl {
     int best_iter;         // iteration of the last 1% improvement of the error
     int pad[2];
     double best_err;
+    double errf, errg;     // unbalanced OT: largest marginal change of the latest row / column half
 };
 
 struct SinkParams {
     double c_out, c_unm, c_sink, t_a, t_b, tol;
+    double kappa, lam;     // unbalanced OT: marginal penalties (unb = 1)
     float twoD2;
     int n_max;
+    int unb;               // 0: outlier row and column; 1: unbalanced OT (no bins)
+    int pad;
 };
+
+// New potential of a row (column) from ln S, S the sum of the previous
+// state's plan entries of that row (column) including its bin entry.  The
+// paper's model: u - eps ln S (Alg. BalancedOT).  Unbalanced OT (Alg.
+// UnbalancedOT): tau (u - eps ln S), tau = kappa / (kappa + eps) for rows and
+// lam / (lam + eps) for columns, and 0 for a row (column) without entries.
+__device__ __forceinline__ float potential_update(float u, double logS, double eps, bool unb, double tau,
+                                                  bool empty) {
+    if (!unb) return static_cast<float>(static_cast<double>(u) - eps * logS);
+    return empty ? 0.0f : static_cast<float>(tau * (static_cast<double>(u) - eps * logS));
+}
+
+// Unbalanced OT's stopping value for one row (column): the change its update
+// makes to its plan marginal, S |exp((u_new - u)/eps) - 1| with S = exp(logS)
+// the mass before the update (0 for a row without entries).
+__device__ __forceinline__ double mass_change(double logS, float u_new, float u, double eps, bool empty) {
+    if (empty) return 0.0;
+    const double d = (static_cast<double>(u_new) - static_cast<double>(u)) / eps;
+    return fabs(exp(logS + d) - exp(logS));
+}
 
 // Everything a kernel needs about one sample.
 struct SampleDesc {
@@ -162,6 +186,8 @@ __global__ void k_ctl_init(const SampleDesc *__restrict__ descs, int n, const Ct
     ctl->done = 0;
     ctl->best_iter = 0;
     ctl->best_err = INFINITY;
+    ctl->errf = INFINITY;
+    ctl->errg = INFINITY;
     ctl->final_state = 0;
     ctl->converged = 0;
     ctl->ticket = 0u;
@@ -204,7 +230,13 @@ __device__ __forceinline__ void row_finalize(SinkCtl *__restrict__ ctl, const do
         const double f0p = ctl->f0[slot], g0p = ctl->g0[slot];
         const double row0 = ctl->cs_sum + exp((f0p + g0p - p.c_sink) / eps);
         const double err0 = p.t_b > 0 ? fabs(row0 - p.t_b) / p.t_b : 0.0;
-        const double e = fmax(emax, err0);
+        double e = fmax(emax, err0);
+        if (p.unb) {
+            // unbalanced OT: the marginal changes of iteration k-1 decide
+            // whether state k-1 is final; this half's changes wait for the next
+            e = fmax(ctl->errf, ctl->errg);
+            ctl->errf = emax;
+        }
         if (e < 0.99 * ctl->best_err) {
             ctl->best_err = e;
             ctl->best_iter = k;
@@ -233,14 +265,20 @@ __device__ __forceinline__ void row_finalize(SinkCtl *__restrict__ ctl, const do
 }
 
 // The sample's last workgroup of a column half: stores
-// sum_j exp((f0 + g_j - c_unm)/eps) for the next row half.
+// sum_j exp((f0 + g_j - c_unm)/eps) for the next row half and the largest
+// marginal change of the half (unbalanced OT's stopping test).
 __device__ __forceinline__ void col_finalize(SinkCtl *__restrict__ ctl, const double2 *__restrict__ part,
                                              int n_items) {
-    double t = 0.0;
-    for (int w = threadIdx.x; w < n_items; w += 64) t += part[w].x;
+    double t = 0.0, m = 0.0;
+    for (int w = threadIdx.x; w < n_items; w += 64) {
+        t += part[w].x;
+        m = fmax(m, part[w].y);
+    }
     t = wave_sum(t);
+    m = wave_max(m);
     if (threadIdx.x == 0) {
         ctl->cs_sum = t;
+        ctl->errg = m;
         ctl->ticket = 0u;
     }
 }
@@ -340,13 +378,16 @@ __device__ __forceinline__ void row_pass(const Item *its, const LAUE_GLOBAL floa
             if (slow[r]) logS[r] = log(s2) + static_cast<double>(mx) * 0.6931471805599453;
         }
     }
+    const bool unb = p.unb != 0;
+    const double tau = unb ? p.kappa / (p.kappa + eps) : 1.0;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-        double err = act[r] ? fabs(acc[r] - 1.0) : 0.0;
-        const double fn = static_cast<double>(f[r]) - eps * logS[r];
+        const float fnf = potential_update(f[r], logS[r], eps, unb, tau, c1 <= c0);
+        double err = !act[r] ? 0.0
+                     : unb   ? mass_change(logS[r], fnf, f[r], eps, c1 <= c0)
+                             : fabs(acc[r] - 1.0);
         double rs = 0.0;
         if (act[r]) {
-            const float fnf = static_cast<float>(fn);
             Fout[i[r]] = fnf;
             rs = exp((static_cast<double>(fnf) + g0 - p.c_out) / eps);
         }
@@ -479,16 +520,20 @@ __device__ __forceinline__ void col_pass(const Item *its, const LAUE_GLOBAL floa
             if (slow[r]) logS[r] = log(s2) + static_cast<double>(mx) * 0.6931471805599453;
         }
     }
+    const bool unb = p.unb != 0;
+    const double tau = unb ? p.lam / (p.lam + eps) : 1.0;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-        double cs = 0.0;
+        double cs = 0.0, err = 0.0;
         if (act[r]) {
-            const float gn = static_cast<float>(static_cast<double>(g[r]) - eps * logS[r]);
+            const float gn = potential_update(g[r], logS[r], eps, unb, tau, r1 <= r0);
             G[j[r]] = gn;
             cs = exp((f0 + static_cast<double>(gn) - p.c_unm) / eps);
+            if (unb) err = mass_change(logS[r], gn, g[r], eps, r1 <= r0);
         }
         cs = wave_sum(cs);
-        if (threadIdx.x == 0 && its[r].local >= 0) part[its[r].local] = make_double2(cs, 0.0);
+        err = wave_max(err);
+        if (threadIdx.x == 0 && its[r].local >= 0) part[its[r].local] = make_double2(cs, err);
     }
     if (!last_block(ctl, n_wg)) return;
     col_finalize(ctl, part, n_items);
@@ -508,7 +553,8 @@ __global__ __launch_bounds__(64) void k_col(const Item *__restrict__ items, cons
 
 // Hard assignment per detected spot: argmax_j Q_ij over its block and the
 // outlier column (lowest index on ties, -1 = outlier), with the sample's final
-// potentials and temperature.
+// potentials and temperature.  Unbalanced OT has no outlier column: the mass
+// the plan leaves untransported, max(0, 1 - sum_j Q_ij), takes its place.
 __device__ __forceinline__ void assign_pass(const Item &it, const SampleDesc &D,
                                             const LAUE_GLOBAL Col8 *__restrict__ cols,
                                             const LAUE_GLOBAL float *__restrict__ G) {
@@ -522,11 +568,13 @@ __device__ __forceinline__ void assign_pass(const Item &it, const SampleDesc &D,
     const float K = p.twoD2 * kx;
     const float p1 = act ? D.p1[i] : 0.0f, p2 = act ? D.p2[i] : 0.0f, f = act ? D.f[i] : 0.0f;
     const float fk = f * kx;
-    float best = -INFINITY;
+    const bool unb = p.unb != 0;
+    float best = -INFINITY, sum = 0.0f;
     int arg = -1;
     for (int j = it.c0; j < it.c1; ++j) {
         const Col8 c = ld_col(cols + j);
         float e = entry_exponent(p1, p2, c.s1, c.s2, c.v1, c.v2, c.vv, c.vv2, K, fmaf(G[j], kx, fk));
+        if (unb) sum += fast_exp2(e);
         if (e > best) {
             best = e;
             arg = j;
@@ -534,7 +582,7 @@ __device__ __forceinline__ void assign_pass(const Item &it, const SampleDesc &D,
     }
     if (!act) return;
     const double eb = (g0 - p.c_out) * kexp + static_cast<double>(fk);
-    const float qo = static_cast<float>(exp2(eb));
+    const float qo = unb ? fmaxf(0.0f, 1.0f - sum) : static_cast<float>(exp2(eb));
     const float qb = arg >= 0 ? fast_exp2(best) : 0.0f;
     const bool m = arg >= 0 && qb >= qo;
     D.jstar[i] = m ? arg : -1;
@@ -928,10 +976,12 @@ __global__ __launch_bounds__(64) void k_row_sparse(const Item *__restrict__ item
         }
         logS = log(s2) + static_cast<double>(mx) * 0.6931471805599453;
     }
-    double err = act ? fabs(acc - 1.0) : 0.0;
+    const bool unb = p.unb != 0;
+    const bool empty = !act || D.nbr[base] < 0;
+    const float fnf = potential_update(f, logS, eps, unb, unb ? p.kappa / (p.kappa + eps) : 1.0, empty);
+    double err = !act ? 0.0 : unb ? mass_change(logS, fnf, f, eps, empty) : fabs(acc - 1.0);
     double rs = 0.0;
     if (act) {
-        const float fnf = static_cast<float>(static_cast<double>(f) - eps * logS);
         Fout[i] = fnf;
         rs = exp((static_cast<double>(fnf) + g0 - p.c_out) / eps);
     }
@@ -977,14 +1027,17 @@ __global__ __launch_bounds__(64) void k_col_sparse(const Item *__restrict__ item
             s2 += exp2(static_cast<double>(fmaf(-K, D.col_cp[e], fmaf(F[D.col_row[e]], kx, gk))) - mx);
         logS = log(s2) + static_cast<double>(mx) * 0.6931471805599453;
     }
-    double cs = 0.0;
+    const bool unb = p.unb != 0;
+    double cs = 0.0, err = 0.0;
     if (act) {
-        const float gn = static_cast<float>(static_cast<double>(g) - eps * logS);
+        const float gn = potential_update(g, logS, eps, unb, unb ? p.lam / (p.lam + eps) : 1.0, a1 <= a0);
         D.g[j] = gn;
         cs = exp((f0 + static_cast<double>(gn) - p.c_unm) / eps);
+        if (unb) err = mass_change(logS, gn, g, eps, a1 <= a0);
     }
     cs = wave_sum(cs);
-    if (threadIdx.x == 0) D.part[it.local] = make_double2(cs, 0.0);
+    err = wave_max(err);
+    if (threadIdx.x == 0) D.part[it.local] = make_double2(cs, err);
     if (!last_block(ctl, D.n_col_items)) return;
     col_finalize(ctl, D.part, D.n_col_items);
 }
@@ -1026,7 +1079,7 @@ __global__ __launch_bounds__(64) void k_mstep_acc_sparse(const Item *__restrict_
 }
 
 // Sparse hard assignment: argmax over the row's neighbours (lowest index on
-// ties) and the outlier column.
+// ties) and the outlier column (unbalanced OT: the untransported mass).
 __global__ __launch_bounds__(64) void k_assign_sparse(const Item *__restrict__ items,
                                                       const SampleDesc *__restrict__ descs) {
     const Item it = items[blockIdx.x];
@@ -1041,19 +1094,21 @@ __global__ __launch_bounds__(64) void k_assign_sparse(const Item *__restrict__ i
     const float kx = static_cast<float>(kexp);
     const float K = p.twoD2 * kx;
     const float fk = D.f[i] * kx;
-    float best = -INFINITY;
+    const bool unb = p.unb != 0;
+    float best = -INFINITY, sum = 0.0f;
     int arg = -1;
     for (int q = 0; q < D.rho; ++q) {
         const int j = D.nbr[q * D.n_obs + i];
         if (j < 0) continue;
         const float e = fmaf(-K, D.ncp[q * D.n_obs + i], fmaf(D.g[j], kx, fk));
+        if (unb) sum += fast_exp2(e);
         if (e > best || (e == best && j < arg)) {
             best = e;
             arg = j;
         }
     }
     const double eb = (g0 - p.c_out) * kexp + static_cast<double>(fk);
-    const float qo = static_cast<float>(exp2(eb));
+    const float qo = unb ? fmaxf(0.0f, 1.0f - sum) : static_cast<float>(exp2(eb));
     const float qb = arg >= 0 ? fast_exp2(best) : 0.0f;
     const bool m = arg >= 0 && qb >= qo;
     D.jstar[i] = m ? arg : -1;
@@ -1283,7 +1338,18 @@ static int validate_ot(const laue_ot_params *p, bool need_eps) {
     LAUE_REQUIRE(p->n_max >= 1, LAUE_EINVAL, "n_max must be >= 1");
     LAUE_REQUIRE(p->rho == 0 || p->rho == 8 || p->rho == 16 || p->rho == 32, LAUE_EINVAL,
                  "rho must be 0 (dense), 8, 16 or 32");
+    LAUE_REQUIRE(p->outlier_model == 0 || p->outlier_model == 1, LAUE_EINVAL,
+                 "outlier_model must be 0 (outlier row and column) or 1 (unbalanced OT)");
+    LAUE_REQUIRE(p->outlier_model == 0 || (std::isfinite(p->kappa) && p->kappa > 0 && std::isfinite(p->lam) &&
+                                           p->lam > 0),
+                 LAUE_EINVAL, "unbalanced OT needs finite kappa > 0 and lam > 0");
     return LAUE_OK;
+}
+
+// bin potentials a call reads: finite under the outlier row and column, unread
+// under unbalanced OT
+static bool bins_ok(const laue_ot_params *p, const laue_potentials *pot) {
+    return p->outlier_model != 0 || (std::isfinite(pot->f0) && std::isfinite(pot->g0));
 }
 
 static int validate_em_params(const laue_em_params *par) {
@@ -1535,7 +1601,7 @@ struct BatchEngine {
             const int nb = a.geom->n_rot * a.geom->n_det;
             if ((rc = validate_obs(a.obs, nb)) || (rc = validate_model(a.model, nb, need_geo))) return rc;
             const double t_a = a.ot->t_b + static_cast<double>(a.obs->n) - static_cast<double>(a.model->n);
-            LAUE_REQUIRE(t_a >= 0, LAUE_EINFEASIBLE,
+            LAUE_REQUIRE(a.ot->outlier_model != 0 || t_a >= 0, LAUE_EINFEASIBLE,
                          "infeasible masses: T_a = T_b + |I| - |J| = " + std::to_string(t_a) + " < 0");
             LAUE_REQUIRE(a.pot != nullptr, LAUE_EINVAL, "potentials are NULL");
             LAUE_REQUIRE(a.obs->n == 0 || a.pot->f, LAUE_EINVAL, "f is NULL");
@@ -1581,8 +1647,13 @@ struct BatchEngine {
             sp.c_out = a.ot->c_out;
             sp.c_unm = a.ot->c_unm;
             sp.c_sink = a.ot->c_sink;
-            sp.t_b = a.ot->t_b;
-            sp.t_a = a.ot->t_b + static_cast<double>(a.obs->n) - static_cast<double>(a.model->n);
+            sp.unb = a.ot->outlier_model == 1 ? 1 : 0;
+            // no bins under unbalanced OT: zero masses make their potentials -inf
+            sp.t_b = sp.unb ? 0.0 : a.ot->t_b;
+            sp.t_a = sp.unb ? 0.0 : a.ot->t_b + static_cast<double>(a.obs->n) - static_cast<double>(a.model->n);
+            sp.kappa = sp.unb ? a.ot->kappa : 0.0;
+            sp.lam = sp.unb ? a.ot->lam : 0.0;
+            sp.pad = 0;
             sp.tol = a.ot->tol;
             sp.twoD2 = static_cast<float>(2.0 * a.ot->distance * a.ot->distance);
             sp.n_max = a.ot->n_max;
@@ -2005,8 +2076,7 @@ extern "C" int laue_sinkhorn(const laue_geometry *geom, const laue_obs_spots *ob
     int rc;
     if ((rc = validate_ot(par, true))) return rc;
     LAUE_REQUIRE(pot && stats, LAUE_EINVAL, "potentials or stats is NULL");
-    LAUE_REQUIRE(std::isfinite(pot->f0) && std::isfinite(pot->g0), LAUE_EINVAL,
-                 "bin potentials must be finite");
+    LAUE_REQUIRE(bins_ok(par, pot), LAUE_EINVAL, "bin potentials must be finite");
     BatchEngine e;
     laue_model_spots *m = const_cast<laue_model_spots *>(model);
     if ((rc = e.setup({SampleIn{geom, nullptr, obs, m, par, nullptr, pot, 0.0, nullptr, nullptr}}, ws, ws_bytes,
@@ -2148,7 +2218,7 @@ extern "C" int laue_mstep(const laue_geometry *geom, const laue_planes *planes,
                  "bad Gauss-Newton parameters");
     LAUE_REQUIRE(pot && obs && (obs->n == 0 || pot->f) && (model == nullptr || model->n == 0 || pot->g),
                  LAUE_EINVAL, "potentials are NULL");
-    LAUE_REQUIRE(std::isfinite(pot->f0) && std::isfinite(pot->g0), LAUE_EINVAL, "bin potentials must be finite");
+    LAUE_REQUIRE(bins_ok(par, pot), LAUE_EINVAL, "bin potentials must be finite");
     BatchEngine e;
     laue_potentials p = *pot;           // read only
     if ((rc = e.setup({SampleIn{geom, planes, obs, model, par, grains, &p, gn->mu_rel, nullptr, step_norm}}, ws,
@@ -2172,8 +2242,7 @@ extern "C" int laue_em(const laue_geometry *geom, const laue_planes *planes,
     LAUE_REQUIRE(par && stats && pot, LAUE_EINVAL, "NULL argument");
     if ((rc = validate_em_params(par)) || (rc = validate_planes(planes)) || (rc = validate_grains(grains)))
         return rc;
-    LAUE_REQUIRE(std::isfinite(pot->f0) && std::isfinite(pot->g0), LAUE_EINVAL,
-                 "bin potentials must be finite");
+    LAUE_REQUIRE(bins_ok(&par->ot, pot), LAUE_EINVAL, "bin potentials must be finite");
     BatchEngine e;
     if ((rc = e.setup({SampleIn{geom, planes, obs, model, &par->ot, grains, pot, par->gn.mu_rel, assign, nullptr}},
                       ws, ws_bytes, stream, false)))
@@ -2204,8 +2273,7 @@ extern "C" int laue_em_batched(int32_t n, const laue_geometry *geoms, const laue
         LAUE_REQUIRE(pars[k].launch == pars[0].launch && pars[k].ot.chunk == pars[0].ot.chunk &&
                          pars[k].tile == pars[0].tile,
                      LAUE_EINVAL, "samples of a batch share launch, tile and ot.chunk");
-        LAUE_REQUIRE(std::isfinite(pots[k].f0) && std::isfinite(pots[k].g0), LAUE_EINVAL,
-                     "bin potentials must be finite");
+        LAUE_REQUIRE(bins_ok(&pars[k].ot, pots + k), LAUE_EINVAL, "bin potentials must be finite");
         in[k] = SampleIn{geoms + k, planes + k, obs + k, models + k, &pars[k].ot, grains + k, pots + k,
                          pars[k].gn.mu_rel, assigns ? assigns + k : nullptr, nullptr};
         par[k] = pars + k;

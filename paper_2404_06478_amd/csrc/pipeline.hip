@@ -205,7 +205,8 @@ extern "C" int laue_index(const laue_geometry *geom, const laue_planes *planes, 
     st.n_candidates = cand.n;
     st.n_candidates_found = n_found;
     st.ms_candidates = ms_since(t0);
-    log_line("index: %d candidates (%lld found) in %.1f ms", cand.n, static_cast<long long>(n_found),
+    log_line("index: %lld candidates (%lld found) in %.1f ms", static_cast<long long>(cand.n),
+             static_cast<long long>(n_found),
              st.ms_candidates);
 
     // 2. learned proposal: support features, network, top fraction
