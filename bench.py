@@ -271,6 +271,66 @@ def bench_index(laue, workload, n_pairs, learned_pairs, log):
     return out
 
 
+def _em_schedule(preset):
+    return [preset.eps_start * (preset.eps_end / preset.eps_start) ** (s / (preset.n_stages - 1))
+            for s in range(preset.n_stages) for _ in range(preset.iters_per_stage)]
+
+
+def _c_out(preset):
+    return 2.0 * preset.distance ** 2 * (1.0 - math.cos(3.0 * preset.sigma_mm / preset.distance))
+
+
+def _em_iterations(laue, preset, ks, log, label, **ot_kw):
+    """EM iterations ks of the schedule from the same start (fresh problem,
+    zero potentials), each one laue_em call of one iteration; returns the
+    per-iteration stats summary and the final grains."""
+    import torch
+    eps_list = _em_schedule(preset)
+    geom, planes, obs, model, grains = build_problem(laue, preset)
+    t_b = float(math.ceil(0.4 * model.n))
+    dev = torch.device("cuda", 0)
+    f = torch.zeros(obs.n, dtype=torch.float32, device=dev)
+    g = torch.zeros(model.n, dtype=torch.float32, device=dev)
+    f0 = g0 = 0.0
+    stats = []
+    extra = {}
+    if ot_kw.get("rho"):
+        nbr, cst, _ = laue.laue_sparse_neighbors(
+            geom, obs, model, laue.ot_params(1.0, preset.distance, _c_out(preset), 1.0, rho=ot_kw["rho"]))
+        far = cst[:, -1].double().cpu().numpy()
+        far = far[np.isfinite(far)]
+        extra["eps_init_mm2"] = float(np.median(far) / math.log(100.0)) if len(far) else None
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in ks:
+        eps = eps_list[k % len(eps_list)]
+        ot = laue.ot_params(eps, preset.distance, _c_out(preset), t_b, tol=1e-5, n_max=2000, **ot_kw)
+        par = laue.em_params(ot, eps, eps, 1, 1, k_gn=2)
+        o = laue.laue_em(geom, planes, obs, model, par, grains, f, g, f0, g0, assign=False)
+        if not ot_kw.get("unbalanced_kl"):
+            f0, g0 = o["f0"], o["g0"]
+        stats.append(o)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    qg, xg = grains.numpy()
+    sk_ms = sum(s["sinkhorn_ms"] for s in stats)
+    summ = {"ms_per_em_iteration": dt * 1e3 / len(ks),
+            "sinkhorn_iters": int(sum(s["sinkhorn_iters"] for s in stats)),
+            "not_converged": int(sum(s["not_converged"] for s in stats)),
+            "pass_pairs": int(sum(s["sinkhorn_entries"] for s in stats)),
+            "pass_pairs_per_s": sum(s["sinkhorn_entries"] for s in stats) / max(sk_ms * 1e-3, 1e-12),
+            "sinkhorn_ms": sk_ms, "mstep_ms": sum(s["mstep_ms"] for s in stats)}
+    log(f"{label}: {dt * 1e3 / len(ks):.1f} ms per EM iteration")
+    return summ, qg, xg, extra
+
+
+def _deviation(a, b):
+    mis = np.diag(misorientation_deg(a[0], b[0]))
+    dx = np.linalg.norm(a[1] - b[1], axis=1)
+    return {"max_misorientation_deg": float(mis.max()), "median_misorientation_deg": float(np.median(mis)),
+            "max_position_mm": float(dx.max()), "median_position_mm": float(np.median(dx))}
+
+
 def bench_sparse(laue, preset, rho, n_iter, log, first_iter=8):
     """The same EM iterations from the same start, dense and with the sparse
     assignment (each detected spot keeps its rho nearest model spots, sets
@@ -279,60 +339,53 @@ def bench_sparse(laue, preset, rho, n_iter, log, first_iter=8):
     iterations start at first_iter of the schedule (stage 2, eps = 11.1
     sigma^2): the paper starts a sparse EM at a temperature tied to the
     farthest kept neighbour, reported here as median c_(rho) / ln 100."""
-    import torch
     import inputgen as ig
     q, x = ig.random_grains(preset)
-    c_out = 2.0 * preset.distance ** 2 * (1.0 - math.cos(3.0 * preset.sigma_mm / preset.distance))
-    eps_list = [preset.eps_start * (preset.eps_end / preset.eps_start) ** (s / (preset.n_stages - 1))
-                for s in range(preset.n_stages) for _ in range(preset.iters_per_stage)]
+    eps_list = _em_schedule(preset)
+    ks = list(range(first_iter, first_iter + n_iter))
     out = {"rho": rho, "em_iterations": [first_iter, first_iter + n_iter],
-           "eps_mm2": sorted({round(eps_list[k % len(eps_list)], 4) for k in range(first_iter, first_iter + n_iter)},
-                             reverse=True)}
+           "eps_mm2": sorted({round(eps_list[k % len(eps_list)], 4) for k in ks}, reverse=True)}
     res = {}
     for r in (0, rho):
-        geom, planes, obs, model, grains = build_problem(laue, preset)
-        t_b = float(math.ceil(0.4 * model.n))
-        dev = torch.device("cuda", 0)
-        f = torch.zeros(obs.n, dtype=torch.float32, device=dev)
-        g = torch.zeros(model.n, dtype=torch.float32, device=dev)
-        f0 = g0 = 0.0
-        stats = []
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        if r:
-            nbr, cst, _ = laue.laue_sparse_neighbors(
-                geom, obs, model, laue.ot_params(1.0, preset.distance, c_out, 1.0, rho=r))
-            far = cst[:, -1].double().cpu().numpy()
-            far = far[np.isfinite(far)]
-            out["eps_init_mm2"] = float(np.median(far) / math.log(100.0)) if len(far) else None
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-        for k in range(first_iter, first_iter + n_iter):
-            eps = eps_list[k % len(eps_list)]
-            ot = laue.ot_params(eps, preset.distance, c_out, t_b, tol=1e-5, n_max=2000, rho=r)
-            par = laue.em_params(ot, eps, eps, 1, 1, k_gn=2)
-            o = laue.laue_em(geom, planes, obs, model, par, grains, f, g, f0, g0, assign=False)
-            f0, g0 = o["f0"], o["g0"]
-            stats.append(o)
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - t0
-        qg, xg = grains.numpy()
-        res[r] = (qg, xg)
         key = "dense" if r == 0 else "sparse"
-        sk_ms = sum(s["sinkhorn_ms"] for s in stats)
-        out[key] = {"ms_per_em_iteration": dt * 1e3 / n_iter,
-                    "sinkhorn_iters": int(sum(s["sinkhorn_iters"] for s in stats)),
-                    "pass_pairs": int(sum(s["sinkhorn_entries"] for s in stats)),
-                    "pass_pairs_per_s": sum(s["sinkhorn_entries"] for s in stats) / max(sk_ms * 1e-3, 1e-12),
-                    "sinkhorn_ms": sk_ms, "mstep_ms": sum(s["mstep_ms"] for s in stats),
-                    "recall_0.25deg_0.5mm": recall(qg, xg, q, x) / len(q)}
-        log(f"sparse: rho={r}: {dt * 1e3 / n_iter:.1f} ms per EM iteration")
-    mis = np.diag(misorientation_deg(res[rho][0], res[0][0]))
-    dx = np.linalg.norm(res[rho][1] - res[0][1], axis=1)
+        summ, qg, xg, extra = _em_iterations(laue, preset, ks, log, f"sparse: rho={r}", rho=r)
+        summ["recall_0.25deg_0.5mm"] = recall(qg, xg, q, x) / len(q)
+        out[key] = summ
+        out.update(extra)
+        res[r] = (qg, xg)
     out["speedup"] = out["dense"]["ms_per_em_iteration"] / out["sparse"]["ms_per_em_iteration"]
-    out["sparse_vs_dense"] = {"max_misorientation_deg": float(mis.max()), "median_misorientation_deg":
-                              float(np.median(mis)), "max_position_mm": float(dx.max()),
-                              "median_position_mm": float(np.median(dx))}
+    out["sparse_vs_dense"] = _deviation(res[rho], res[0])
+    return out
+
+
+def bench_unbalanced(laue, preset, kls, n_iter, log, first_iter=0):
+    """The same EM iterations from the same start with the paper's outlier
+    row and column and with unbalanced OT at each (kappa, lambda) of kls
+    (units of 2 sigma^2, the paper's log-likelihood units): time per
+    iteration, the passes' entries/s (same streamed kernels, other epilogue),
+    Sinkhorn iterations, recall, and how far the grains end from those of the
+    paper's model.  Run on a workload where the paper's model recovers the
+    grains (100 grains, 30% outliers), so that recall compares the two
+    outlier treatments."""
+    import inputgen as ig
+    q, x = ig.random_grains(preset)
+    eps_list = _em_schedule(preset)
+    ks = list(range(first_iter, first_iter + n_iter))
+    s2 = 2.0 * preset.sigma_mm ** 2
+    out = {"em_iterations": [first_iter, first_iter + n_iter],
+           "eps_mm2": sorted({round(eps_list[k % len(eps_list)], 4) for k in ks}, reverse=True)}
+    summ, qb, xb, _ = _em_iterations(laue, preset, ks, log, "unbalanced: outlier bins")
+    summ["recall_0.25deg_0.5mm"] = recall(qb, xb, q, x) / len(q)
+    out["outlier_bins"] = summ
+    out["unbalanced"] = []
+    for kl in kls:
+        summ, qg, xg, _ = _em_iterations(laue, preset, ks, log, f"unbalanced: kappa, lambda = {kl}",
+                                         unbalanced_kl=(kl[0] * s2, kl[1] * s2))
+        summ["kappa_lambda_2sigma2"] = list(kl)
+        summ["kappa_lambda_mm2"] = [kl[0] * s2, kl[1] * s2]
+        summ["recall_0.25deg_0.5mm"] = recall(qg, xg, q, x) / len(q)
+        summ["vs_outlier_bins"] = _deviation((qg, xg), (qb, xb))
+        out["unbalanced"].append(summ)
     return out
 
 
@@ -386,6 +439,12 @@ def main():
     ap.add_argument("--no-sparse", action="store_true")
     ap.add_argument("--sparse-rho", type=int, default=32)
     ap.add_argument("--sparse-iters", type=int, default=8)
+    ap.add_argument("--no-unbalanced", action="store_true")
+    ap.add_argument("--unbalanced-kl", default="0.01,0.01;0.1,0.1;1,1",
+                    help="kappa,lambda pairs (';'-separated) of unbalanced OT in units of 2 sigma^2 "
+                         "(the paper's log-likelihood units)")
+    ap.add_argument("--unbalanced-iters", type=int, default=20)
+    ap.add_argument("--unbalanced-workload", default="medium", choices=["medium", "learned", "stress"])
     ap.add_argument("--batch-samples", type=int, default=64)
     ap.add_argument("--index-workloads", default="medium:4096,learned:1024",
                     help="comma-separated workload:pairs; plain scoring takes the candidates of that many "
@@ -493,6 +552,12 @@ def main():
         line["batching"] = bench_batching(laue, args.batch_samples, 3, log)
     if not args.no_sparse:
         line["sparse_assignment"] = bench_sparse(laue, preset, args.sparse_rho, args.sparse_iters, log)
+    if not args.no_unbalanced:
+        kl = [tuple(float(v) for v in item.split(",")) for item in args.unbalanced_kl.split(";")]
+        import inputgen as ig
+        line["unbalanced_ot"] = bench_unbalanced(laue, ig.PRESETS[args.unbalanced_workload], kl,
+                                                 args.unbalanced_iters, log)
+        line["unbalanced_ot"]["workload"] = args.unbalanced_workload
     if not args.no_index:
         line["time_to_index"] = {}
         for item in args.index_workloads.split(","):
