@@ -44,8 +44,9 @@ def build_costs(planes, geom, distance, p12, obs_off, model, q, x):
 
 
 def grain_pairs(planes, geom, p_lab, obs_off, model, Qb, n_grains):
-    """Pairs of every grain: (detected spot, model spot of that grain, Q_ij)."""
-    per = [([], [], [], []) for _ in range(n_grains)]
+    """Pairs of every grain: (detected spot, model spot of that grain, Q_ij),
+    with the model spot's plane index."""
+    per = [([], [], [], [], []) for _ in range(n_grains)]
     col_off = model["offsets"]
     for b in range(geom.n_blocks):
         i0, i1 = obs_off[b], obs_off[b + 1]
@@ -55,15 +56,17 @@ def grain_pairs(planes, geom, p_lab, obs_off, model, Qb, n_grains):
         for jj in range(j1 - j0):
             j = j0 + jj
             n = model["n"][j]
-            P, T, W, Q = per[n]
+            P, T, W, Q, Mi = per[n]
             P.append(p_lab[i0:i1])
             T.append(np.full(i1 - i0, model["t"][j]))
             W.append(np.repeat(planes["w"][model["m"][j]][None], i1 - i0, axis=0))
             Q.append(Qb[b][:, jj])
+            Mi.append(np.full(i1 - i0, model["m"][j]))
     out = []
-    for P, T, W, Q in per:
+    for P, T, W, Q, Mi in per:
         if P:
-            out.append(mstep.Pairs(np.concatenate(P), np.concatenate(T), np.concatenate(W), np.concatenate(Q)))
+            out.append(mstep.Pairs(np.concatenate(P), np.concatenate(T), np.concatenate(W), np.concatenate(Q),
+                                   np.concatenate(Mi)))
         else:
             out.append(None)
     return out
@@ -71,13 +74,16 @@ def grain_pairs(planes, geom, p_lab, obs_off, model, Qb, n_grains):
 
 def run(planes, geom, distance, p12, obs_off, model, q0, x0, eps_list, c_out, c_unm=0.0,
         c_sink=None, t_b=None, k_gn=2, tol=1e-5, n_max=2000, record=False, rho=None,
-        unbalanced_kl=None):
+        unbalanced_kl=None, mstep_method="gn", paper_kw=None):
     """Run the EM.  model: dict with m, n, t, det (block-sorted) and offsets.
     rho: keep only each detected spot's rho nearest model spots, re-chosen at
     every EM iteration from that iteration's costs (oracle/sparse.py).
     unbalanced_kl: (kappa, lambda) replaces the E-step by unbalanced OT
     (oracle/unbalanced.py; no bins, so c_out, c_unm, c_sink and t_b are
     unused and f0, g0 come back as -inf).
+    mstep_method: "gn" (k_gn joint Gauss-Newton steps) or "paper" (k_gn
+    coordinate-descent sweeps of LauePosNewton then LaueRotMM,
+    mstep.paper_step with the keyword arguments paper_kw).
 
     Returns dict with q, x, f, g, f0, g0 and per-iteration stats."""
     c_sink = c_out if c_sink is None else c_sink
@@ -110,8 +116,13 @@ def run(planes, geom, distance, p12, obs_off, model, q0, x0, eps_list, c_out, c_
             for n in range(N):
                 if pairs[n] is None:
                     continue
-                q[n], x[n], st, _, _, _ = mstep.gn_step(pairs[n], q[n], x[n], geom, distance)
-                steps[n] = st
+                if mstep_method == "paper":
+                    qn, xn = mstep.paper_step(pairs[n], q[n], x[n], geom, **(paper_kw or {}))
+                    steps[n] = np.concatenate([[np.linalg.norm(qn - q[n])], xn - x[n], [0.0, 0.0]])
+                    q[n], x[n] = qn, xn
+                else:
+                    q[n], x[n], st, _, _, _ = mstep.gn_step(pairs[n], q[n], x[n], geom, distance)
+                    steps[n] = st
         rec = {"eps": eps, "n_iter": sol["n_iter"], "err": sol["err"],
                "step_max": float(np.max(np.linalg.norm(steps, axis=1))) if N else 0.0}
         if record:

@@ -62,13 +62,15 @@ class Pairs:
     """All (detected spot, model spot) pairs of one grain with their weights.
 
     p_lab [K,3] detected spot in the lab, t [K] rotation index, w [K,3] plane
-    normal (crystal frame), weight [K]."""
+    normal (crystal frame), weight [K], m [K] plane index (optional: without
+    it, pairs with the same normal count as one plane)."""
 
-    def __init__(self, p_lab, t, w, weight):
+    def __init__(self, p_lab, t, w, weight, m=None):
         self.p = np.asarray(p_lab, dtype=np.float64)
         self.t = np.asarray(t)
         self.w = np.asarray(w, dtype=np.float64)
         self.q = np.asarray(weight, dtype=np.float64)
+        self.m = None if m is None else np.asarray(m)
 
 
 def residuals_jacobians(pairs, R, x, geom, distance):
@@ -125,26 +127,35 @@ def wahba(a, b, w):
     return U @ M @ Vt
 
 
-def pos_newton(pairs, R, x, geom, n_iter=50, tol=1e-12):
-    """LauePosNewton: Newton on F(x) = sum Q rhat^T r (Eqs. xgrad, xhess, with the
-    chain rule through y = Gamma_t x)."""
-    x = np.asarray(x, dtype=np.float64).copy()
+def pos_grad_hess(pairs, R, x, geom):
+    """Gradient and Hessian in x of F(x) = sum Q rhat^T r (Eqs. xgrad, xhess,
+    without the 1/sigma^2 factor, with the chain rule through y = Gamma_t x):
+    per pair dF/dy = -(r - a rhat) / tau and
+    d2F/dy2 = -(r rhat^T + rhat r^T - 3 a rhat rhat^T + a I) / tau^2, a = rhat.r."""
     G = geom.G[pairs.t]
     v = pairs.w @ R.T
     u = np.einsum("kab,kb->ka", G, v)
     r = E - 2.0 * u[:, :1] * u
+    y = np.einsum("kab,b->ka", G, x)
+    dvec = pairs.p - y
+    tau = np.linalg.norm(dvec, axis=1)
+    rh = dvec / tau[:, None]
+    a = np.einsum("ka,ka->k", rh, r)
+    gy = -(r - a[:, None] * rh) / tau[:, None]
+    Hy = -(r[:, :, None] * rh[:, None, :] + rh[:, :, None] * r[:, None, :]
+           - 3.0 * a[:, None, None] * rh[:, :, None] * rh[:, None, :]
+           + a[:, None, None] * np.eye(3)[None]) / (tau ** 2)[:, None, None]
+    gx = np.einsum("k,kba,kb->a", pairs.q, G, gy)
+    Hx = np.einsum("k,kba,kbc,kcd->ad", pairs.q, G, Hy, G)
+    return gx, Hx
+
+
+def pos_newton(pairs, R, x, geom, n_iter=50, tol=1e-12):
+    """LauePosNewton: x <- x - H^-1 g with g, H of pos_grad_hess, until
+    ||dx|| < tol or n_iter steps (the step that meets tol is applied)."""
+    x = np.asarray(x, dtype=np.float64).copy()
     for _ in range(n_iter):
-        y = np.einsum("kab,b->ka", G, x)
-        dvec = pairs.p - y
-        tau = np.linalg.norm(dvec, axis=1)
-        rh = dvec / tau[:, None]
-        a = np.einsum("ka,ka->k", rh, r)
-        gy = -(r - a[:, None] * rh) / tau[:, None]                        # dF/dy per pair
-        Hy = -(r[:, :, None] * rh[:, None, :] + rh[:, :, None] * r[:, None, :]
-               - 3.0 * a[:, None, None] * rh[:, :, None] * rh[:, None, :]
-               + a[:, None, None] * np.eye(3)[None]) / (tau ** 2)[:, None, None]
-        gx = np.einsum("k,kba,kb->a", pairs.q, G, gy)
-        Hx = np.einsum("k,kba,kbc,kcd->ad", pairs.q, G, Hy, G)
+        gx, Hx = pos_grad_hess(pairs, R, x, geom)
         dx = np.linalg.solve(Hx, gx)
         x = x - dx
         if np.linalg.norm(dx) < tol:
@@ -152,28 +163,42 @@ def pos_newton(pairs, R, x, geom, n_iter=50, tol=1e-12):
     return x
 
 
-def rot_mm(pairs, R, x, geom, n_iter=2000, tol=1e-13):
-    """LaueRotMM: MM on R through Wahba's problem (Eqs. M0, Mm, majmin_step)."""
+def m0_matrices(pairs, x, geom):
+    """Eq. M0 per plane m of the grain:
+    M0_m = -sum_{pairs of plane m} Gamma_t^T Q (rhat e^T + e rhat^T) Gamma_t.
+    Planes are the pairs' plane indices (pairs without them: their normals).
+    Returns (plane keys, normals W [P,3], M0 [P,3,3])."""
     G = geom.G[pairs.t]
     y = np.einsum("kab,b->ka", G, x)
     dvec = pairs.p - y
     rh = dvec / np.linalg.norm(dvec, axis=1, keepdims=True)
-    # M^0_m summed per plane normal (pairs with the same w share M_m)
-    keys = [tuple(np.round(w, 12)) for w in pairs.w]
-    uniq = {}
+    keys = (list(pairs.m.tolist()) if pairs.m is not None
+            else [tuple(np.round(w, 12)) for w in pairs.w])
+    groups = {}
     for k, key in enumerate(keys):
-        uniq.setdefault(key, []).append(k)
-    W, Ms = [], []
-    for key, idx in uniq.items():
+        groups.setdefault(key, []).append(k)
+    W, M0s = [], []
+    for key, idx in groups.items():
         M0 = np.zeros((3, 3))
         for k in idx:
             qr = pairs.q[k] * rh[k]
             M0 -= G[k].T @ (np.outer(qr, E) + np.outer(E, qr)) @ G[k]
-        lam_min = np.linalg.eigvalsh(M0)[0]
-        W.append(np.array(key))
-        Ms.append(M0 + (abs(lam_min) if lam_min < 0 else 0.0) * np.eye(3))
-    W = np.array(W)
-    Ms = np.array(Ms)
+        W.append(pairs.w[idx[0]])
+        M0s.append(M0)
+    return list(groups), np.array(W), np.array(M0s)
+
+
+def mm_shift(M0):
+    """Eq. Mm: M0 + |iota| I with iota its smallest eigenvalue when negative."""
+    lam_min = np.linalg.eigvalsh(M0)[0]
+    return M0 + (abs(lam_min) if lam_min < 0 else 0.0) * np.eye(3)
+
+
+def rot_mm(pairs, R, x, geom, n_iter=2000, tol=1e-13):
+    """LaueRotMM: R <- Wahba(M_m R w_m, w_m, 1) (Eq. majmin_step) until
+    ||R' - R||_F < tol or n_iter steps."""
+    _, W, M0s = m0_matrices(pairs, x, geom)
+    Ms = np.array([mm_shift(M0) for M0 in M0s])
     for _ in range(n_iter):
         a = np.einsum("kab,kb->ka", Ms, W @ R.T)
         Rn = wahba(a, W, np.ones(len(W)))
@@ -182,6 +207,18 @@ def rot_mm(pairs, R, x, geom, n_iter=2000, tol=1e-13):
         if done:
             break
     return R
+
+
+def paper_step(pairs, q, x, geom, n_newton=50, tol_x=1e-12, n_mm=2000, tol_r=1e-13):
+    """One coordinate-descent sweep of the paper's M-step (Alg. LaueOT):
+    LauePosNewton on x with R fixed, then LaueRotMM on R at the new x."""
+    R = crystal.quat_to_R(q)
+    xn = pos_newton(pairs, R, x, geom, n_iter=n_newton, tol=tol_x)
+    Rn = rot_mm(pairs, R, xn, geom, n_iter=n_mm, tol=tol_r)
+    qn = crystal.R_to_quat(Rn)
+    if qn[0] < 0:
+        qn = -qn
+    return qn, xn
 
 
 def mm_objective(pairs, R, x, geom):

@@ -123,3 +123,86 @@ def test_em_noise_free_exact_recovery():
                  cost.c_out(p.sigma_mm, p.distance), t_b=sinkhorn.default_tb(len(model["m"]), 0.1))
     assert np.max(np.degrees(metrics.misorientation(res["q"], q))) < 1e-6
     assert np.max(np.linalg.norm(res["x"] - x, axis=1)) < 1e-6
+
+
+def test_pos_grad_hess_finite_differences():
+    """Eqs. xgrad and xhess (with the chain rule through y = Gamma_t x) against
+    central differences of F(x) = sum Q rhat^T r."""
+    pairs, q, x, g = _pairs(seed=5, noise=0.4)
+    R = crystal.quat_to_R(q)
+    gx, Hx = mstep.pos_grad_hess(pairs, R, x, g)
+    h = 1e-4
+    for k in range(3):
+        dx = np.zeros(3)
+        dx[k] = h
+        fa = mstep.mm_objective(pairs, R, x + dx, g)
+        fb = mstep.mm_objective(pairs, R, x - dx, g)
+        assert (fa - fb) / (2 * h) == pytest.approx(gx[k], rel=1e-6, abs=1e-9)
+        ga, _ = mstep.pos_grad_hess(pairs, R, x + dx, g)
+        gb, _ = mstep.pos_grad_hess(pairs, R, x - dx, g)
+        assert np.allclose((ga - gb) / (2 * h), Hx[:, k], rtol=1e-5, atol=1e-9 * np.abs(Hx).max())
+    assert np.allclose(Hx, Hx.T)
+
+
+def test_m0_matrices_give_the_objective():
+    """Eq. qcoc: sum_m w_m^T R^T M0_m R w_m differs from F(R) = sum Q rhat^T r
+    by a constant, for any two rotations."""
+    pairs, q, x, g = _pairs(seed=6, noise=0.4)
+    _, W, M0 = mstep.m0_matrices(pairs, x, g)
+    rng = np.random.default_rng(1)
+    Rs = crystal.quat_to_R(ig.random_quaternions(rng, 3))
+    G = [float(np.einsum("ma,mab,mb->", W @ R.T, M0, W @ R.T)) for R in Rs]
+    F = [mstep.mm_objective(pairs, R, x, g) for R in Rs]
+    for k in (1, 2):
+        assert G[k] - G[0] == pytest.approx(F[k] - F[0], rel=1e-10, abs=1e-9)
+
+
+def test_m0_per_plane_index_keeps_harmonics_apart():
+    """Eq. M0 sums over the model spots of one plane m: two planes with the
+    same normal (a harmonic pair) keep their own matrices (and shifts)."""
+    pairs, q, x, g = _pairs(seed=7)
+    K = len(pairs.q)
+    m = np.arange(K) % 2                     # two plane ids over pairs that share no normal structure
+    pairs.w[:] = pairs.w[0]                  # one normal for every pair
+    keyed = mstep.Pairs(pairs.p, pairs.t, pairs.w, pairs.q, m)
+    keys, W, M0 = mstep.m0_matrices(keyed, x, g)
+    assert sorted(keys) == [0, 1] and len(M0) == 2
+    _, _, M0w = mstep.m0_matrices(pairs, x, g)
+    assert len(M0w) == 1 and np.allclose(M0[0] + M0[1], M0w[0])
+
+
+def test_mm_shift_is_psd_and_minimal():
+    rng = np.random.default_rng(2)
+    A = rng.standard_normal((3, 3))
+    M0 = -(A @ A.T) + 0.1 * np.eye(3)
+    M = mstep.mm_shift(M0)
+    ev = np.linalg.eigvalsh(M)
+    assert ev[0] == pytest.approx(0.0, abs=1e-12) and np.all(ev >= -1e-12)
+    P = A @ A.T
+    assert np.array_equal(mstep.mm_shift(P), P)
+
+
+def test_paper_step_stationary_point_and_em_recovery():
+    """A sweep from the GN optimum stays there; the EM with the paper's
+    M-step recovers noise-free grains exactly (four sweeps per EM iteration:
+    coordinate descent between x and R converges linearly)."""
+    pairs, q, x, g = _pairs(seed=3, noise=0.4)
+    qg, xg = q.copy(), x.copy()
+    for _ in range(30):
+        qg, xg, _, _, _, _ = mstep.gn_step(pairs, qg, xg, g, D)
+    qp, xp = mstep.paper_step(pairs, qg, xg, g)
+    assert np.degrees(metrics.misorientation(qp, qg)) < 1e-7 and np.allclose(xp, xg, atol=1e-8)
+    p = ig.TINY
+    pl = crystal.cubic_planes(p.a, p.centering, p.n_max)
+    geo = forward.Geometry.from_preset(p)
+    qt, xt = ig.random_grains(p)
+    sim = simulate.simulate(pl, qt, xt, geo, 0.0, 0.0, p.seed, p.distance)
+    q0, x0 = ig.perturb_grains(qt, xt, 0.5, 0.5, 1)
+    model = forward.enumerate_visible(pl, q0, x0, geo)
+    model["offsets"] = forward.block_offsets(model["block"], geo.n_blocks)
+    eps = em.eps_schedule(p.eps_start, p.eps_end, p.n_stages, p.iters_per_stage)
+    res = em.run(pl, geo, p.distance, sim["p12"], sim["offsets"], model, q0, x0, eps,
+                 cost.c_out(p.sigma_mm, p.distance), k_gn=4, mstep_method="paper",
+                 paper_kw={"n_newton": 4, "tol_x": 1e-12, "n_mm": 500, "tol_r": 1e-13})
+    assert np.max(np.degrees(metrics.misorientation(res["q"], qt))) < 1e-6
+    assert np.max(np.linalg.norm(res["x"] - xt, axis=1)) < 1e-6
