@@ -299,17 +299,35 @@ int laue_cost_block(const laue_geometry *geom, const laue_obs_spots *obs,
 /* ---- M-step: per-grain weighted Gauss-Newton ----------------------------- */
 
 typedef struct laue_gn_params {
-    int32_t k_gn;               /* Gauss-Newton steps with the plan held fixed */
-    double mu_rel;              /* Levenberg term mu = mu_rel * tr(H) / 6 */
+    int32_t k_gn;               /* Gauss-Newton steps (method 0) or coordinate-descent
+                                 * sweeps (method 1) with the plan held fixed */
+    double mu_rel;              /* Levenberg term mu = mu_rel * tr(H) / 6 (method 0) */
+    /* 0: joint Gauss-Newton on (R, x); 1: the paper's coordinate descent
+     * (App. B, Alg. LaueOT's M-step): per sweep, LauePosNewton on x with R
+     * fixed (Eqs. xgrad, xhess; x <- x - H^-1 g, at most k_newton steps,
+     * a grain stops after the step with |dx| < tol_x mm), then LaueRotMM on R
+     * at the new x (Eqs. M0, Mm, majmin_step: M0 summed per plane, shifted by
+     * |smallest eigenvalue| when negative, R <- Wahba(M_m R w_m, w_m, 1) until
+     * ||R' - R||_F < tol_r or k_mm steps).  Wahba's problem is solved by
+     * Davenport's q-method (the same minimiser as the SVD of Alg. Wahba). */
+    int32_t method;
+    int32_t k_newton;           /* method 1: Newton steps per sweep (>= 1) */
+    int32_t k_mm;               /* method 1: MM steps per sweep (>= 1) */
+    double tol_x;               /* method 1: Newton stop, mm (>= 0) */
+    double tol_r;               /* method 1: MM stop, Frobenius norm (>= 0) */
 } laue_gn_params;
 
 /* M-step (Eq. mstep_obj): the plan Q is given by (pot, par->eps) and the
- * model spots' current geometry (the E-step state); each of k_gn steps
- * re-evaluates the model spots at the current grains, forms per grain the
- * FP64 normal equations H = sum Q J^T J + mu I, g = sum Q J^T rho with
+ * model spots' current geometry (the E-step state).  Method 0: each of k_gn
+ * steps re-evaluates the model spots at the current grains, forms per grain
+ * the FP64 normal equations H = sum Q J^T J + mu I, g = sum Q J^T rho with
  * rho = D (rhat - r), and applies R <- exp([omega]_x) R, x <- x + dx with
- * (omega, dx) = -H^-1 g.  Grains without weight stay unchanged.  step_norm:
- * optional device FP64 [n_grains], |(omega, dx)| of the last step. */
+ * (omega, dx) = -H^-1 g.  Method 1: k_gn sweeps of LauePosNewton then
+ * LaueRotMM (see laue_gn_params); a Newton step whose 3x3 Hessian is
+ * singular is skipped.  Grains without weight stay unchanged.  step_norm:
+ * optional device FP64 [n_grains], |(omega, dx)| of the last step (method
+ * 0) or |dx| of the last Newton step (method 1).  Method 1 needs
+ * planes->n <= 1024. */
 int laue_mstep(const laue_geometry *geom, const laue_planes *planes,
                const laue_obs_spots *obs, laue_model_spots *model,
                const laue_ot_params *par, const laue_potentials *pot,

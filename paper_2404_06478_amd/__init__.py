@@ -358,11 +358,21 @@ def laue_cost_block(geom, obs, model, distance, block):
     return Cm[:nI * nJ].reshape(nI, nJ)
 
 
-def laue_mstep(geom, planes, obs, model, ot, f, g, grains, k_gn=2, mu_rel=1e-9):
+def gn_params(k_gn=2, mu_rel=1e-9, mstep="gn", k_newton=3, k_mm=500, tol_x=1e-6, tol_r=1e-12):
+    """M-step parameters: mstep "gn" (k_gn joint Gauss-Newton steps) or
+    "paper" (k_gn sweeps of LauePosNewton, at most k_newton steps, then
+    LaueRotMM, at most k_mm steps)."""
+    if mstep not in ("gn", "paper"):
+        raise ValueError("mstep must be 'gn' or 'paper'")
+    return laue_gn_params(int(k_gn), float(mu_rel), 1 if mstep == "paper" else 0, int(k_newton), int(k_mm),
+                          float(tol_x), float(tol_r))
+
+
+def laue_mstep(geom, planes, obs, model, ot, f, g, grains, k_gn=2, mu_rel=1e-9, **mstep_kw):
     import torch
     lib = require_native()
     ws = _workspace(_ws_size(geom, obs.n, model.n, grains.n, ot.rho))
-    gn = laue_gn_params(int(k_gn), float(mu_rel))
+    gn = gn_params(k_gn, mu_rel, **mstep_kw)
     pot = laue_potentials(f.data_ptr(), g.data_ptr(), 0.0, 0.0)
     steps = torch.zeros(max(grains.n, 1), dtype=torch.float64, device=_dev())
     o, m = obs.struct(), model.struct()
@@ -372,10 +382,12 @@ def laue_mstep(geom, planes, obs, model, ot, f, g, grains, k_gn=2, mu_rel=1e-9):
     return steps[:grains.n]
 
 
-def em_params(ot, eps_start, eps_end, n_stages, iters_per_stage, k_gn=2, mu_rel=1e-9, launch=0, tile=0):
+def em_params(ot, eps_start, eps_end, n_stages, iters_per_stage, k_gn=2, mu_rel=1e-9, launch=0, tile=0,
+              **mstep_kw):
+    """mstep_kw: the M-step options of gn_params (mstep="paper", k_newton, ...)."""
     p = laue_em_params()
     p.ot = ot
-    p.gn = laue_gn_params(int(k_gn), float(mu_rel))
+    p.gn = gn_params(k_gn, mu_rel, **mstep_kw)
     p.eps_start, p.eps_end = float(eps_start), float(eps_end)
     p.n_stages, p.iters_per_stage = int(n_stages), int(iters_per_stage)
     p.launch = int(launch)

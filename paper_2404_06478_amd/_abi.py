@@ -65,7 +65,8 @@ class laue_ot_stats(C.Structure):
 
 
 class laue_gn_params(C.Structure):
-    _fields_ = [("k_gn", C.c_int32), ("mu_rel", C.c_double)]
+    _fields_ = [("k_gn", C.c_int32), ("mu_rel", C.c_double), ("method", C.c_int32), ("k_newton", C.c_int32),
+                ("k_mm", C.c_int32), ("tol_x", C.c_double), ("tol_r", C.c_double)]
 
 
 class laue_em_params(C.Structure):

@@ -453,6 +453,213 @@ __device__ inline void gn_solve_apply(const double *acc, double mu_rel, double *
     }
 }
 
+// ---------------------------------------------------------------- coordinate-descent M-step
+
+// The paper's own M-step (App. B): LauePosNewton on x with R fixed, then
+// LaueRotMM on R at the new x, both maximising F = sum Q rhat^T r.
+constexpr int kPosStat = 9;        // per-column statistics of LauePosNewton
+constexpr int kDirStat = 3;        // per-column statistics of LaueRotMM
+constexpr int kMaxPlanesMM = 1024; // planes a grain's MM can hold (LDS)
+
+// LauePosNewton statistics of one pair (detector frame).  With h = rhat,
+// eps = rhat - r (formed without cancellation as in accumulate_stats) and
+// eta = |eps|^2 / 2 = 1 - rhat.r, Eqs. xgrad and xhess per pair become
+//   dF/dy   = (eps - eta h) / tau
+//   d2F/dy2 = -[(1 - eta) I + (3 eta - 1) h h^T - (eps h^T + h eps^T)] / tau^2
+// (no term cancels: the small rhat.r - 1 and P r enter through eps and eta).
+//   a[0..2] += Q (eps - eta h) / tau,
+//   a[3..8] += Q [(1 - eta) I + (3 eta - 1) h h^T - (eps h^T + h eps^T)] / tau^2
+// (upper triangle 00, 01, 02, 11, 12, 22).
+__device__ __forceinline__ void accumulate_pos(float *a, float Q, float p1, float p2, const Col8 &cC, float vlen,
+                                               float rn, float r1, float r2) {
+    const float dy = p1 - cC.s1, dz = p2 - cC.s2;
+    const float h0u = cC.vn, h1u = cC.v1 + dy, h2u = cC.v2 + dz;
+    const float dd = fmaf(h2u, h2u, fmaf(h1u, h1u, h0u * h0u));
+    const float itau = __builtin_amdgcn_rsqf(dd);
+    const float tau = dd * itau;
+    const float dl = fmaf(2.0f, fmaf(cC.v2, dz, cC.v1 * dy), fmaf(dz, dz, dy * dy)) *
+                     __builtin_amdgcn_rcpf(tau + vlen);
+    const float e0 = (-rn * dl) * itau;
+    const float e1 = fmaf(-r1, dl, dy) * itau;
+    const float e2 = fmaf(-r2, dl, dz) * itau;
+    const float h0 = h0u * itau, h1 = h1u * itau, h2 = h2u * itau;
+    const float eta = 0.5f * fmaf(e2, e2, fmaf(e1, e1, e0 * e0));
+    const float wb = Q * itau, wa = wb * itau;
+    a[0] = fmaf(wb, fmaf(-eta, h0, e0), a[0]);
+    a[1] = fmaf(wb, fmaf(-eta, h1, e1), a[1]);
+    a[2] = fmaf(wb, fmaf(-eta, h2, e2), a[2]);
+    const float c1 = 1.0f - eta, c3 = fmaf(3.0f, eta, -1.0f);
+    a[3] = fmaf(wa, fmaf(c3 * h0, h0, fmaf(-2.0f * e0, h0, c1)), a[3]);
+    a[4] = fmaf(wa, fmaf(c3 * h0, h1, -fmaf(e0, h1, h0 * e1)), a[4]);
+    a[5] = fmaf(wa, fmaf(c3 * h0, h2, -fmaf(e0, h2, h0 * e2)), a[5]);
+    a[6] = fmaf(wa, fmaf(c3 * h1, h1, fmaf(-2.0f * e1, h1, c1)), a[6]);
+    a[7] = fmaf(wa, fmaf(c3 * h1, h2, -fmaf(e1, h2, h1 * e2)), a[7]);
+    a[8] = fmaf(wa, fmaf(c3 * h2, h2, fmaf(-2.0f * e2, h2, c1)), a[8]);
+}
+
+// LaueRotMM statistics of one pair (detector frame): a[0..2] += Q rhat.
+__device__ __forceinline__ void accumulate_dir(float *a, float Q, float p1, float p2, const Col8 &cC) {
+    const float dy = p1 - cC.s1, dz = p2 - cC.s2;
+    const float h0u = cC.vn, h1u = cC.v1 + dy, h2u = cC.v2 + dz;
+    const float dd = fmaf(h2u, h2u, fmaf(h1u, h1u, h0u * h0u));
+    const float wq = Q * __builtin_amdgcn_rsqf(dd);
+    a[0] = fmaf(wq, h0u, a[0]);
+    a[1] = fmaf(wq, h1u, a[1]);
+    a[2] = fmaf(wq, h2u, a[2]);
+}
+
+// Detector frame (lab = Mf local, columns normal, axis1, axis2) and the
+// rotation-stage matrix Gt (y = Gt x) of block b; false for an invalid block.
+__device__ inline bool column_frames(const GeomF &Gm, int b, double Mf[3][3], double Gt[3][3]) {
+    if (b < 0 || b >= Gm.n_rot * Gm.n_det) return false;
+    const int t = b / Gm.n_det, d = b - t * Gm.n_det;
+    const DetF &Dt = Gm.det[d];
+    for (int a_ = 0; a_ < 3; ++a_) {
+        Mf[a_][0] = Dt.n[a_];
+        Mf[a_][1] = Dt.a1[a_];
+        Mf[a_][2] = Dt.a2[a_];
+    }
+    const double cs = Gm.cs[t][0], sn = Gm.cs[t][1];
+    Gt[0][0] = cs;  Gt[0][1] = -sn; Gt[0][2] = 0.0;
+    Gt[1][0] = sn;  Gt[1][1] = cs;  Gt[1][2] = 0.0;
+    Gt[2][0] = 0.0; Gt[2][1] = 0.0; Gt[2][2] = 1.0;
+    return true;
+}
+
+// One column's FP64 contribution to its grain's LauePosNewton system, in the
+// sample frame: H_x = Gt^T (Mf Hy Mf^T) Gt and g_x = Gt^T Mf gy from the
+// statistics of accumulate_pos.  o[0..5]: H_x (00, 01, 02, 11, 12, 22),
+// o[6..8]: g_x.  Invalid ids contribute zeros.
+__device__ inline void column_pos_newton(const GeomF &Gm, int n_grains, int n, int b, const double *s64, double *o) {
+    double Mf[3][3], Gt[3][3];
+    if (n < 0 || n >= n_grains || !column_frames(Gm, b, Mf, Gt)) {
+        for (int k = 0; k < kPosStat; ++k) o[k] = 0.0;
+        return;
+    }
+    const double S[3][3] = {{s64[3], s64[4], s64[5]}, {s64[4], s64[6], s64[7]}, {s64[5], s64[7], s64[8]}};
+    double T[3][3], L[3][3], gl[3];
+    for (int a_ = 0; a_ < 3; ++a_) {
+        gl[a_] = Mf[a_][0] * s64[0] + Mf[a_][1] * s64[1] + Mf[a_][2] * s64[2];
+        for (int b_ = 0; b_ < 3; ++b_) T[a_][b_] = Mf[a_][0] * S[0][b_] + Mf[a_][1] * S[1][b_] + Mf[a_][2] * S[2][b_];
+    }
+    for (int a_ = 0; a_ < 3; ++a_)
+        for (int b_ = 0; b_ < 3; ++b_) L[a_][b_] = T[a_][0] * Mf[b_][0] + T[a_][1] * Mf[b_][1] + T[a_][2] * Mf[b_][2];
+    double GL[3][3], H[3][3];
+    for (int a_ = 0; a_ < 3; ++a_)
+        for (int b_ = 0; b_ < 3; ++b_) GL[a_][b_] = Gt[0][a_] * L[0][b_] + Gt[1][a_] * L[1][b_] + Gt[2][a_] * L[2][b_];
+    for (int a_ = 0; a_ < 3; ++a_)
+        for (int b_ = 0; b_ < 3; ++b_) H[a_][b_] = -(GL[a_][0] * Gt[0][b_] + GL[a_][1] * Gt[1][b_] + GL[a_][2] * Gt[2][b_]);
+    o[0] = H[0][0]; o[1] = H[0][1]; o[2] = H[0][2]; o[3] = H[1][1]; o[4] = H[1][2]; o[5] = H[2][2];
+    for (int a_ = 0; a_ < 3; ++a_) o[6 + a_] = Gt[0][a_] * gl[0] + Gt[1][a_] * gl[1] + Gt[2][a_] * gl[2];
+}
+
+// One column's FP64 contribution to M0 of its (grain, plane) (Eq. M0):
+// -Gt^T (q e^T + e q^T) Gt with q = sum_i Q rhat in the lab and e the beam
+// direction (1, 0, 0).  o[0..5]: 00, 01, 02, 11, 12, 22.
+__device__ inline void column_rot_m0(const GeomF &Gm, int b, const double *s64, double *o) {
+    double Mf[3][3], Gt[3][3];
+    if (!column_frames(Gm, b, Mf, Gt)) {
+        for (int k = 0; k < 6; ++k) o[k] = 0.0;
+        return;
+    }
+    double ql[3], c[3], f[3];
+    for (int a_ = 0; a_ < 3; ++a_) ql[a_] = Mf[a_][0] * s64[0] + Mf[a_][1] * s64[1] + Mf[a_][2] * s64[2];
+    for (int a_ = 0; a_ < 3; ++a_) {
+        c[a_] = Gt[0][a_] * ql[0] + Gt[1][a_] * ql[1] + Gt[2][a_] * ql[2];
+        f[a_] = Gt[0][a_];
+    }
+    o[0] = -2.0 * c[0] * f[0];
+    o[1] = -(c[0] * f[1] + f[0] * c[1]);
+    o[2] = -(c[0] * f[2] + f[0] * c[2]);
+    o[3] = -2.0 * c[1] * f[1];
+    o[4] = -(c[1] * f[2] + f[1] * c[2]);
+    o[5] = -2.0 * c[2] * f[2];
+}
+
+// Smallest eigenvalue of a symmetric 3x3 matrix (00, 01, 02, 11, 12, 22),
+// by the trigonometric solution of its characteristic cubic.  FP64.
+__device__ inline double sym3_min_eig(const double *m) {
+    const double p1 = m[1] * m[1] + m[2] * m[2] + m[4] * m[4];
+    const double tr3 = (m[0] + m[3] + m[5]) / 3.0;
+    if (p1 == 0.0) return fmin(m[0], fmin(m[3], m[5]));
+    const double d0 = m[0] - tr3, d1 = m[3] - tr3, d2 = m[5] - tr3;
+    const double p = sqrt((d0 * d0 + d1 * d1 + d2 * d2 + 2.0 * p1) / 6.0);
+    const double ip = 1.0 / p;
+    const double b00 = d0 * ip, b11 = d1 * ip, b22 = d2 * ip, b01 = m[1] * ip, b02 = m[2] * ip, b12 = m[4] * ip;
+    const double det = b00 * (b11 * b22 - b12 * b12) - b01 * (b01 * b22 - b12 * b02) + b02 * (b01 * b12 - b11 * b02);
+    const double r = fmin(1.0, fmax(-1.0, 0.5 * det));
+    const double phi = acos(r) / 3.0;
+    return tr3 + 2.0 * p * cos(phi + 2.0943951023931957);
+}
+
+// Largest-eigenvalue eigenvector of a symmetric 4x4 matrix (cyclic Jacobi, FP64).
+__device__ inline void sym4_top_eigvec(double A[4][4], double v[4]) {
+    double V[4][4] = {{1, 0, 0, 0}, {0, 1, 0, 0}, {0, 0, 1, 0}, {0, 0, 0, 1}};
+    for (int sweep = 0; sweep < 12; ++sweep) {
+        double off = 0.0, dia = 0.0;
+        for (int p = 0; p < 4; ++p) {
+            dia += A[p][p] * A[p][p];
+            for (int q = p + 1; q < 4; ++q) off += A[p][q] * A[p][q];
+        }
+        if (off <= 1e-30 * dia) break;
+        for (int p = 0; p < 3; ++p)
+            for (int q = p + 1; q < 4; ++q) {
+                if (fabs(A[p][q]) < 1e-300) continue;
+                const double th = (A[q][q] - A[p][p]) / (2.0 * A[p][q]);
+                const double t = (th >= 0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
+                const double c = 1.0 / sqrt(t * t + 1.0), s = t * c;
+                for (int k = 0; k < 4; ++k) {
+                    const double kp = A[k][p], kq = A[k][q];
+                    A[k][p] = c * kp - s * kq;
+                    A[k][q] = s * kp + c * kq;
+                }
+                for (int k = 0; k < 4; ++k) {
+                    const double pk = A[p][k], qk = A[q][k];
+                    A[p][k] = c * pk - s * qk;
+                    A[q][k] = s * pk + c * qk;
+                }
+                for (int k = 0; k < 4; ++k) {
+                    const double kp = V[k][p], kq = V[k][q];
+                    V[k][p] = c * kp - s * kq;
+                    V[k][q] = s * kp + c * kq;
+                }
+            }
+    }
+    int best = 0;
+    for (int i = 1; i < 4; ++i)
+        if (A[i][i] > A[best][best]) best = i;
+    for (int k = 0; k < 4; ++k) v[k] = V[k][best];
+}
+
+// Wahba's problem (App. A) from B = sum_k w_k a_k b_k^T: the rotation R
+// minimising sum_k w_k ||a_k - R b_k||^2, through Davenport's q-method (the
+// same minimiser as the SVD form of Alg. Wahba): the optimal unit quaternion
+// (w >= 0) is the top eigenvector of K = [[tr B, z^T], [z, B + B^T - tr(B) I]],
+// z = (B21 - B12, B02 - B20, B10 - B01).
+__device__ inline void wahba_quat_B(const double B[3][3], double *q) {
+    const double tr = B[0][0] + B[1][1] + B[2][2];
+    const double z[3] = {B[2][1] - B[1][2], B[0][2] - B[2][0], B[1][0] - B[0][1]};
+    double K[4][4];
+    K[0][0] = tr;
+    for (int i = 0; i < 3; ++i) {
+        K[0][1 + i] = z[i];
+        K[1 + i][0] = z[i];
+        for (int j = 0; j < 3; ++j) K[1 + i][1 + j] = B[i][j] + B[j][i] - (i == j ? tr : 0.0);
+    }
+    sym4_top_eigvec(K, q);
+    const double nrm = sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+    const double sg = q[0] < 0 ? -1.0 : 1.0;
+    for (int k = 0; k < 4; ++k) q[k] = sg * q[k] / nrm;
+}
+
+// Row-major rotation matrix of a unit quaternion (w, x, y, z).
+__device__ inline void quat_R(const double *q, double *R) {
+    const double w = q[0], a = q[1], b = q[2], c = q[3];
+    R[0] = 1 - 2 * (b * b + c * c); R[1] = 2 * (a * b - w * c);     R[2] = 2 * (a * c + w * b);
+    R[3] = 2 * (a * b + w * c);     R[4] = 1 - 2 * (a * a + c * c); R[5] = 2 * (b * c - w * a);
+    R[6] = 2 * (a * c - w * b);     R[7] = 2 * (b * c + w * a);     R[8] = 1 - 2 * (a * a + b * b);
+}
+
 // Workspace of the enumerate count/scan (forward.hip).
 struct EnumWs {
     GeomF *geom;

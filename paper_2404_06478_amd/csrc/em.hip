@@ -125,6 +125,10 @@ struct SampleDesc {
     int *knn_hist;                 // [nb x kGrid^2] model spots per detector cell
     int *sort_key, *sort_val;      // [n_obs x rho] radix-sort input (column, entry)
     const int *sorted_val;         // [n_obs x rho] entries ordered by column
+    // the paper's coordinate-descent M-step
+    int *gflag;                    // [n_grains] Newton converged in this sweep
+    int k_mm, pad1;                // MM steps per sweep
+    double tol_x, tol_r;           // Newton and MM stops
 };
 
 // ---------------------------------------------------------------- helpers
@@ -614,6 +618,49 @@ __global__ __launch_bounds__(64) void k_assign(const Item *__restrict__ items,
 //   H_ww = D^2 S0 K^T K, H_xx = D^2 Gt^T A Gt, H_xw = D^2 Gt^T B K,
 //   g_w = -D^2 K^T e,    g_x = D^2 Gt^T B r,
 // with K = 2 (u e^T + (u.e) I) Gt [R w]_x the rotation Jacobian of the ray.
+// Statistics per pair of the three M-step passes: 0 Gauss-Newton
+// (accumulate_stats), 1 LauePosNewton (accumulate_pos), 2 LaueRotMM
+// (accumulate_dir); and each column's FP64 epilogue into colHg.
+template <int MODE>
+struct MstepMode;
+template <>
+struct MstepMode<0> {
+    static constexpr int N = kStat;
+};
+template <>
+struct MstepMode<1> {
+    static constexpr int N = kPosStat;
+};
+template <>
+struct MstepMode<2> {
+    static constexpr int N = kDirStat;
+};
+
+template <int MODE>
+__device__ __forceinline__ void mode_acc(float *a, float Q, float p1, float p2, const Col8 &cC, float vlen, float rn,
+                                         float r1, float r2) {
+    if constexpr (MODE == 0)
+        accumulate_stats(a, Q, p1, p2, cC, vlen, rn, r1, r2);
+    else if constexpr (MODE == 1)
+        accumulate_pos(a, Q, p1, p2, cC, vlen, rn, r1, r2);
+    else
+        accumulate_dir(a, Q, p1, p2, cC);
+}
+
+template <int MODE>
+__device__ __forceinline__ void mode_epilogue(const SampleDesc &D, int j, const double *s64, float rn, float r1,
+                                              float r2) {
+    double *o = D.colHg + static_cast<int64_t>(j) * kHg;
+    if constexpr (MODE == 0)
+        column_normal_equations(*D.geom, D.W, D.n_planes, D.grains, D.n_grains, D.mplane[j], D.mgrain[j],
+                                D.mblock[j], s64, rn, r1, r2, D.D2, o);
+    else if constexpr (MODE == 1)
+        column_pos_newton(*D.geom, D.n_grains, D.mgrain[j], D.mblock[j], s64, o);
+    else
+        column_rot_m0(*D.geom, D.mblock[j], s64, o);
+}
+
+template <int MODE>
 __device__ __forceinline__ void mstep_pass(const Item &it, const SampleDesc &D,
                                            const LAUE_GLOBAL float *__restrict__ P1,
                                            const LAUE_GLOBAL float *__restrict__ P2,
@@ -636,30 +683,31 @@ __device__ __forceinline__ void mstep_pass(const Item &it, const SampleDesc &D,
     const float ivl = __builtin_amdgcn_rsqf(cC.vv);
     const float vlen = cC.vv * ivl;
     const float rn = cC.vn * ivl, r1 = cC.v1 * ivl, r2 = cC.v2 * ivl;
-    double s64[kStat];
-    for (int k = 0; k < kStat; ++k) s64[k] = 0.0;
+    constexpr int NS = MstepMode<MODE>::N;
+    double s64[NS];
+    for (int k = 0; k < NS; ++k) s64[k] = 0.0;
     for (int i0 = it.r0; i0 < it.r1; i0 += 64) {
         const int i1 = min(i0 + 64, it.r1);
-        float a[kStat];
-        for (int k = 0; k < kStat; ++k) a[k] = 0.0f;
+        float a[NS];
+        for (int k = 0; k < NS; ++k) a[k] = 0.0f;
         for (int i = i0; i < i1; ++i) {
             const float p1 = P1[i], p2 = P2[i];
             const float Q = fast_exp2(entry_exponent(p1, p2, cE.s1, cE.s2, cE.v1, cE.v2, cE.vv,
                                                      cE.vv2, K, fmaf(F[i], kx, gk)));
-            if (Q > 0.0f) accumulate_stats(a, Q, p1, p2, cC, vlen, rn, r1, r2);
+            if (Q > 0.0f) mode_acc<MODE>(a, Q, p1, p2, cC, vlen, rn, r1, r2);
         }
-        for (int k = 0; k < kStat; ++k) s64[k] += static_cast<double>(a[k]);
+        for (int k = 0; k < NS; ++k) s64[k] += static_cast<double>(a[k]);
     }
     if (!act) return;
-    column_normal_equations(*D.geom, D.W, D.n_planes, D.grains, D.n_grains, D.mplane[j], D.mgrain[j],
-                            D.mblock[j], s64, rn, r1, r2, D.D2, D.colHg + static_cast<int64_t>(j) * kHg);
+    mode_epilogue<MODE>(D, j, s64, rn, r1, r2);
 }
 
+template <int MODE>
 __global__ __launch_bounds__(64) void k_mstep_acc(const Item *__restrict__ items,
                                                   const SampleDesc *__restrict__ descs, int cur_c) {
     const Item it = items[blockIdx.x];
     const SampleDesc &D = descs[it.s];
-    mstep_pass(it, D, gptr(D.p1), gptr(D.p2), gptr(D.f), gptr(D.g), gptr(D.colsE), gptr(D.colsC), cur_c);
+    mstep_pass<MODE>(it, D, gptr(D.p1), gptr(D.p2), gptr(D.f), gptr(D.g), gptr(D.colsE), gptr(D.colsC), cur_c);
 }
 
 // One wave per grain of any sample (gbase: grain offsets of the samples):
@@ -694,6 +742,144 @@ __global__ __launch_bounds__(64) void k_mstep_solve(const SampleDesc *__restrict
     if (threadIdx.x != 0) return;
     gn_solve_apply(acc, D.mu_rel, D.q + 4 * n, D.x + 3 * n, D.grains + n,
                    D.step_norm ? D.step_norm + n : nullptr);
+}
+
+// the contiguous run [a, z) of grain n's columns in block b (columns of a
+// block ascend by grain)
+__device__ __forceinline__ void grain_run(const SampleDesc &D, int b, int n, int64_t &a, int64_t &z) {
+    const int *__restrict__ mgrain = D.mgrain;
+    const int64_t lo = D.mboff[b], hi = D.mboff[b + 1];
+    int64_t e = hi;
+    a = lo;
+    while (a < e) {
+        const int64_t mid = (a + e) >> 1;
+        if (mgrain[mid] < n) a = mid + 1; else e = mid;
+    }
+    z = a;
+    e = hi;
+    while (z < e) {
+        const int64_t mid = (z + e) >> 1;
+        if (mgrain[mid] <= n) z = mid + 1; else e = mid;
+    }
+}
+
+// LauePosNewton step it of one grain (one wave per grain of any sample): sum
+// its columns' (H_x, g_x) as k_mstep_solve does, then lane 0 applies
+// x <- x - H_x^-1 g_x (FP64, by the adjugate; a singular H_x is skipped).  A
+// grain whose step fell below tol_x takes no further step in this sweep
+// (it == 0 starts the sweep).
+__global__ __launch_bounds__(64) void k_pos_solve(const SampleDesc *__restrict__ descs, int n_samples,
+                                                  const int64_t *__restrict__ gbase, int it) {
+    const int s = sample_of(gbase, n_samples, blockIdx.x);
+    const SampleDesc &D = descs[s];
+    const int n = static_cast<int>(blockIdx.x - gbase[s]);
+    double acc[kPosStat];
+    for (int k = 0; k < kPosStat; ++k) acc[k] = 0.0;
+    for (int b = threadIdx.x; b < D.nb; b += 64) {
+        int64_t a, z;
+        grain_run(D, b, n, a, z);
+        for (int64_t j = a; j < z; ++j)
+            for (int k = 0; k < kPosStat; ++k) acc[k] += D.colHg[j * kHg + k];
+    }
+    for (int k = 0; k < kPosStat; ++k) acc[k] = wave_sum(acc[k]);
+    if (threadIdx.x != 0) return;
+    int *flag = D.gflag + n;
+    if (it == 0) *flag = 0;
+    else if (*flag) return;
+    const double h00 = acc[0], h01 = acc[1], h02 = acc[2], h11 = acc[3], h12 = acc[4], h22 = acc[5];
+    const double c00 = h11 * h22 - h12 * h12, c01 = h02 * h12 - h01 * h22, c02 = h01 * h12 - h02 * h11;
+    const double c11 = h00 * h22 - h02 * h02, c12 = h01 * h02 - h00 * h12, c22 = h00 * h11 - h01 * h01;
+    const double det = h00 * c00 + h01 * c01 + h02 * c02;
+    const double scale = fabs(h00) + fabs(h11) + fabs(h22);
+    if (!(fabs(det) > 1e-14 * scale * scale * scale) || !isfinite(det)) return;
+    const double g0 = acc[6], g1 = acc[7], g2 = acc[8];
+    const double dx[3] = {(c00 * g0 + c01 * g1 + c02 * g2) / det, (c01 * g0 + c11 * g1 + c12 * g2) / det,
+                          (c02 * g0 + c12 * g1 + c22 * g2) / det};
+    double *x = D.x + 3 * n;
+    for (int k = 0; k < 3; ++k) x[k] -= dx[k];
+    D.grains[n] = grain_f32(D.q + 4 * n, x);
+    const double nd = sqrt(dx[0] * dx[0] + dx[1] * dx[1] + dx[2] * dx[2]);
+    if (D.step_norm) D.step_norm[n] = nd;
+    if (nd < D.tol_x) *flag = 1;
+}
+
+// LaueRotMM of one grain (one wave per grain of any sample).  M0 per plane
+// (Eq. M0) is summed in LDS from the grain's columns, block by block in
+// order (lanes 0..5 each own one of the six entries, so the sum has a fixed
+// order); each M0 is shifted by the magnitude of its smallest eigenvalue when
+// that is negative (Eq. Mm); then R <- Wahba(M_m R w_m, w_m, 1) (Eq.
+// majmin_step) until ||R' - R||_F < tol_r or k_mm steps, with B = sum_m
+// (M_m R w_m) w_m^T summed over the lanes' planes and one fixed wave
+// reduction, so that every lane solves the same Wahba problem.
+__global__ __launch_bounds__(64) void k_rot_mm(const SampleDesc *__restrict__ descs, int n_samples,
+                                               const int64_t *__restrict__ gbase) {
+    __shared__ double Msh[kMaxPlanesMM * 6];
+    const int s = sample_of(gbase, n_samples, blockIdx.x);
+    const SampleDesc &D = descs[s];
+    const int n = static_cast<int>(blockIdx.x - gbase[s]);
+    const int np = min(D.n_planes, kMaxPlanesMM);
+    const int lane = threadIdx.x;
+    for (int k = lane; k < np * 6; k += 64) Msh[k] = 0.0;
+    __syncthreads();
+    if (lane < 6) {
+        for (int b = 0; b < D.nb; ++b) {
+            int64_t a, z;
+            grain_run(D, b, n, a, z);
+            for (int64_t j = a; j < z; ++j) {
+                const int m = D.mplane[j];
+                if (m >= 0 && m < np) Msh[6 * m + lane] += D.colHg[j * kHg + lane];
+            }
+        }
+    }
+    __syncthreads();
+    for (int m = lane; m < np; m += 64) {
+        double *M = Msh + 6 * m;
+        const double lmin = sym3_min_eig(M);
+        if (lmin < 0.0) {
+            M[0] -= lmin;
+            M[3] -= lmin;
+            M[5] -= lmin;
+        }
+    }
+    __syncthreads();
+    double q[4] = {D.q[4 * n], D.q[4 * n + 1], D.q[4 * n + 2], D.q[4 * n + 3]};
+    const double qn0 = sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+    for (int k = 0; k < 4; ++k) q[k] /= qn0;
+    double R[9];
+    quat_R(q, R);
+    bool moved = false;
+    for (int it = 0; it < D.k_mm; ++it) {
+        double Bl[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+        for (int m = lane; m < np; m += 64) {
+            const double *M = Msh + 6 * m;
+            if (M[0] == 0.0 && M[1] == 0.0 && M[2] == 0.0 && M[3] == 0.0 && M[4] == 0.0 && M[5] == 0.0) continue;
+            const double w[3] = {D.W[3 * m], D.W[3 * m + 1], D.W[3 * m + 2]};
+            const double v[3] = {R[0] * w[0] + R[1] * w[1] + R[2] * w[2], R[3] * w[0] + R[4] * w[1] + R[5] * w[2],
+                                 R[6] * w[0] + R[7] * w[1] + R[8] * w[2]};
+            const double av[3] = {M[0] * v[0] + M[1] * v[1] + M[2] * v[2], M[1] * v[0] + M[3] * v[1] + M[4] * v[2],
+                                  M[2] * v[0] + M[4] * v[1] + M[5] * v[2]};
+            for (int a_ = 0; a_ < 3; ++a_)
+                for (int b_ = 0; b_ < 3; ++b_) Bl[3 * a_ + b_] += av[a_] * w[b_];
+        }
+        double B[3][3], bn = 0.0;
+        for (int k = 0; k < 9; ++k) {
+            B[k / 3][k % 3] = wave_sum(Bl[k]);
+            bn += B[k / 3][k % 3] * B[k / 3][k % 3];
+        }
+        if (!(bn > 0.0) || !isfinite(bn)) break;
+        double qn[4], Rn[9];
+        wahba_quat_B(B, qn);
+        quat_R(qn, Rn);
+        double z = 0.0;
+        for (int k = 0; k < 9; ++k) z += (Rn[k] - R[k]) * (Rn[k] - R[k]);
+        for (int k = 0; k < 9; ++k) R[k] = Rn[k];
+        for (int k = 0; k < 4; ++k) q[k] = qn[k];
+        moved = true;
+        if (sqrt(z) < D.tol_r) break;
+    }
+    if (lane != 0 || !moved) return;
+    for (int k = 0; k < 4; ++k) D.q[4 * n + k] = q[k];
+    D.grains[n] = grain_f32(q, D.x + 3 * n);
 }
 
 // ---------------------------------------------------------------- sparse assignment
@@ -1045,6 +1231,7 @@ __global__ __launch_bounds__(64) void k_col_sparse(const Item *__restrict__ item
 // Sparse M-step statistics (lane = model spot): over the rows that keep it,
 // Q from the stored E-step cost and the potentials, the residual geometry at
 // the current grains; same epilogue as the dense pass.
+template <int MODE>
 __global__ __launch_bounds__(64) void k_mstep_acc_sparse(const Item *__restrict__ items,
                                                          const SampleDesc *__restrict__ descs, int cur_c) {
     const Item it = items[blockIdx.x];
@@ -1064,18 +1251,18 @@ __global__ __launch_bounds__(64) void k_mstep_acc_sparse(const Item *__restrict_
     const float vlen = cC.vv * ivl;
     const float rn = cC.vn * ivl, r1 = cC.v1 * ivl, r2 = cC.v2 * ivl;
     const int64_t a0 = act ? D.col_off[j] : 0, a1 = act ? D.col_off[j + 1] : 0;
-    float a[kStat];
-    for (int q = 0; q < kStat; ++q) a[q] = 0.0f;
+    constexpr int NS = MstepMode<MODE>::N;
+    float a[NS];
+    for (int q = 0; q < NS; ++q) a[q] = 0.0f;
     for (int64_t e = a0; e < a1; ++e) {
         const int i = D.col_row[e];
         const float Q = fast_exp2(fmaf(-K, D.col_cp[e], fmaf(D.f[i], kx, gk)));
-        if (Q > 0.0f) accumulate_stats(a, Q, D.p1[i], D.p2[i], cC, vlen, rn, r1, r2);
+        if (Q > 0.0f) mode_acc<MODE>(a, Q, D.p1[i], D.p2[i], cC, vlen, rn, r1, r2);
     }
     if (!act) return;
-    double s64[kStat];
-    for (int q = 0; q < kStat; ++q) s64[q] = static_cast<double>(a[q]);
-    column_normal_equations(*D.geom, D.W, D.n_planes, D.grains, D.n_grains, D.mplane[j], D.mgrain[j], D.mblock[j],
-                            s64, rn, r1, r2, D.D2, D.colHg + static_cast<int64_t>(j) * kHg);
+    double s64[NS];
+    for (int q = 0; q < NS; ++q) s64[q] = static_cast<double>(a[q]);
+    mode_epilogue<MODE>(D, j, s64, rn, r1, r2);
 }
 
 // Sparse hard assignment: argmax over the row's neighbours (lowest index on
@@ -1226,6 +1413,7 @@ struct SampleWs {
     double *colHg;
     GeomF *geom;
     GrainF *grains;
+    int *gflag;
     int64_t *mboff;
     // sparse assignment (rho > 0)
     int *nbr = nullptr, *cand_j = nullptr, *cand_n = nullptr, *knn_list = nullptr, *knn_nlist = nullptr;
@@ -1271,6 +1459,7 @@ static size_t carve_all(Carver &cv, BatchWs &bw, std::vector<SampleWs> &sw, cons
         w.colHg = cv.take<double>(std::max<int64_t>(d.n_model, 1) * kHg);
         w.geom = cv.take<GeomF>(1);
         w.grains = cv.take<GrainF>(std::max(d.n_grains, 1));
+        w.gflag = cv.take<int>(std::max(d.n_grains, 1));
         w.mboff = cv.take<int64_t>(nb + 1);
         if (d.rho > 0) {
             const int64_t no = std::max<int64_t>(d.n_obs, 1), nm = std::max<int64_t>(d.n_model, 1);
@@ -1352,6 +1541,17 @@ static bool bins_ok(const laue_ot_params *p, const laue_potentials *pot) {
     return p->outlier_model != 0 || (std::isfinite(pot->f0) && std::isfinite(pot->g0));
 }
 
+static int validate_gn(const laue_gn_params *gn) {
+    LAUE_REQUIRE(gn && gn->k_gn >= 0 && std::isfinite(gn->mu_rel) && gn->mu_rel >= 0, LAUE_EINVAL,
+                 "bad Gauss-Newton parameters");
+    LAUE_REQUIRE(gn->method == 0 || gn->method == 1, LAUE_EINVAL,
+                 "gn.method must be 0 (Gauss-Newton) or 1 (coordinate descent)");
+    LAUE_REQUIRE(gn->method == 0 || (gn->k_newton >= 1 && gn->k_mm >= 1 && std::isfinite(gn->tol_x) &&
+                                     gn->tol_x >= 0 && std::isfinite(gn->tol_r) && gn->tol_r >= 0),
+                 LAUE_EINVAL, "coordinate descent needs k_newton >= 1, k_mm >= 1 and tolerances >= 0");
+    return LAUE_OK;
+}
+
 static int validate_em_params(const laue_em_params *par) {
     int rc;
     LAUE_REQUIRE(par != nullptr, LAUE_EINVAL, "EM parameters are NULL");
@@ -1359,8 +1559,7 @@ static int validate_em_params(const laue_em_params *par) {
     LAUE_REQUIRE(par->n_stages >= 1 && par->iters_per_stage >= 1 && std::isfinite(par->eps_start) &&
                      std::isfinite(par->eps_end) && par->eps_start > 0 && par->eps_end > 0,
                  LAUE_EINVAL, "bad temperature schedule");
-    LAUE_REQUIRE(par->gn.k_gn >= 0 && std::isfinite(par->gn.mu_rel) && par->gn.mu_rel >= 0,
-                 LAUE_EINVAL, "bad Gauss-Newton parameters");
+    if ((rc = validate_gn(&par->gn))) return rc;
     LAUE_REQUIRE(par->launch >= 0 && par->launch <= 2, LAUE_EINVAL, "launch must be 0, 1 or 2");
     LAUE_REQUIRE(par->tile >= 0 && par->tile <= 2, LAUE_EINVAL, "tile must be 0, 1 or 2");
     return LAUE_OK;
@@ -1378,6 +1577,7 @@ struct SampleIn {
     double mu_rel;
     laue_assignments *assign;      // may be NULL
     double *step_norm;             // may be NULL
+    const laue_gn_params *gn;      // may be NULL (Gauss-Newton)
 };
 
 // E- and M-steps of one or more samples on one stream: one launch per pass.
@@ -1392,6 +1592,7 @@ struct BatchEngine {
     std::vector<int64_t> mbase, gbase;
     int n_rows = 0, n_cols = 0, n_rows2 = 0, n_cols2 = 0;
     int rho = 0;                                 // sparse assignment (0: dense)
+    int mmethod = 0, k_newton = 1;               // M-step: 0 Gauss-Newton, 1 the paper's coordinate descent
     std::vector<int64_t> sparse_entries;         // per sample: kept pairs of the current sets
     // per sample: streamed entries, Sinkhorn passes and their entries, M-step entries
     std::vector<int64_t> entries, passes, pass_entries, m_entries;
@@ -1612,6 +1813,15 @@ struct BatchEngine {
             dims[k] = SampleDims{a.geom, a.obs->n, a.model->n, a.grains ? a.grains->n : 0, a.ot->rho};
         }
         rho = n > 0 ? in[0].ot->rho : 0;
+        mmethod = n > 0 && in[0].gn ? in[0].gn->method : 0;
+        k_newton = n > 0 && in[0].gn ? std::max(in[0].gn->k_newton, 1) : 1;
+        for (int k = 0; k < n; ++k) {
+            const laue_gn_params *gk = in[k].gn;
+            LAUE_REQUIRE((gk ? gk->method : 0) == mmethod && (mmethod == 0 || gk->k_newton == k_newton), LAUE_EINVAL,
+                         "samples of a batch share gn.method and gn.k_newton");
+            LAUE_REQUIRE(mmethod == 0 || !in[k].planes || in[k].planes->n <= kMaxPlanesMM, LAUE_EINVAL,
+                         "the coordinate-descent M-step holds at most 1024 planes");
+        }
         Carver cv(ws);
         const size_t need = carve_all(cv, bw, sw, dims);
         if ((rc = check_ws(ws, ws_bytes, need))) return rc;
@@ -1682,6 +1892,10 @@ struct BatchEngine {
             D.Dsp = a.planes ? a.planes->d : nullptr;
             D.D2 = a.ot->distance * a.ot->distance;
             D.mu_rel = a.mu_rel;
+            D.gflag = sw[k].gflag;
+            D.k_mm = a.gn ? a.gn->k_mm : 1;
+            D.tol_x = a.gn ? a.gn->tol_x : 0.0;
+            D.tol_r = a.gn ? a.gn->tol_r : 0.0;
             if (a.assign && a.assign->j_star && a.assign->grain && a.assign->q_star && a.assign->q_out) {
                 D.jstar = a.assign->j_star;
                 D.gstar = a.assign->grain;
@@ -1786,19 +2000,41 @@ struct BatchEngine {
     // k_gn Gauss-Newton steps with the plan of (potentials, eps, colsE) fixed,
     // then the forward model at the new grains for the next E-step.
     // k_gn Gauss-Newton steps: statistics (dense or sparse) and the per-grain solve
+    template <int MODE>
+    void acc_pass(hipStream_t st, int cur_c) {
+        if (mbase[n] == 0) return;
+        if (rho > 0)
+            k_mstep_acc_sparse<MODE><<<n_cols, 64, 0, st>>>(bw.cols, bw.desc, cur_c);
+        else
+            k_mstep_acc<MODE><<<n_cols, 64, 0, st>>>(bw.cols, bw.desc, cur_c);
+    }
+
     void gn_steps(hipStream_t st, int k_gn) {
+        const unsigned ng = static_cast<unsigned>(gbase[n]);
+        if (mmethod == 1) {
+            // k_gn sweeps: LauePosNewton (k_newton steps) on x, then LaueRotMM on R at the new x
+            for (int sw_ = 0; sw_ < k_gn; ++sw_) {
+                for (int it = 0; it < k_newton; ++it) {
+                    const bool first = sw_ == 0 && it == 0;
+                    if (!first) eval_on(st, 1, 0);
+                    acc_pass<1>(st, first ? 0 : 1);
+                    if (ng > 0) k_pos_solve<<<ng, 64, 0, st>>>(bw.desc, n, bw.gbase, it);
+                }
+                eval_on(st, 1, 0);
+                acc_pass<2>(st, 1);
+                if (ng > 0) k_rot_mm<<<ng, 64, 0, st>>>(bw.desc, n, bw.gbase);
+            }
+            return;
+        }
         for (int k = 0; k < k_gn; ++k) {
             if (k > 0) eval_on(st, 1, 0);
-            if (mbase[n] > 0) {
-                if (rho > 0)
-                    k_mstep_acc_sparse<<<n_cols, 64, 0, st>>>(bw.cols, bw.desc, k > 0 ? 1 : 0);
-                else
-                    k_mstep_acc<<<n_cols, 64, 0, st>>>(bw.cols, bw.desc, k > 0 ? 1 : 0);
-            }
-            if (gbase[n] > 0)
-                k_mstep_solve<<<static_cast<unsigned>(gbase[n]), 64, 0, st>>>(bw.desc, n, bw.gbase);
+            acc_pass<0>(st, k > 0 ? 1 : 0);
+            if (ng > 0) k_mstep_solve<<<ng, 64, 0, st>>>(bw.desc, n, bw.gbase);
         }
     }
+
+    // streamed M-step passes of k_gn steps (sweeps)
+    int mstep_passes(int k_gn) const { return mmethod == 1 ? k_gn * (k_newton + 1) : k_gn; }
 
     void mstep_launches(hipStream_t st, int k_gn) {
         gn_steps(st, k_gn);
@@ -1952,8 +2188,8 @@ struct BatchEngine {
             LAUE_CHECK_HIP(hipGetLastError());
         }
         for (int j = 0; j < n; ++j) {
-            entries[j] += pass_work(j) * k_gn;
-            m_entries[j] += pass_work(j) * k_gn;
+            entries[j] += pass_work(j) * mstep_passes(k_gn);
+            m_entries[j] += pass_work(j) * mstep_passes(k_gn);
         }
         return timer_stop(&mstep_ms);
     }
@@ -2214,14 +2450,13 @@ extern "C" int laue_mstep(const laue_geometry *geom, const laue_planes *planes,
     int rc;
     if ((rc = validate_ot(par, true)) || (rc = validate_planes(planes)) || (rc = validate_grains(grains)))
         return rc;
-    LAUE_REQUIRE(gn && gn->k_gn >= 0 && std::isfinite(gn->mu_rel) && gn->mu_rel >= 0, LAUE_EINVAL,
-                 "bad Gauss-Newton parameters");
+    if ((rc = validate_gn(gn))) return rc;
     LAUE_REQUIRE(pot && obs && (obs->n == 0 || pot->f) && (model == nullptr || model->n == 0 || pot->g),
                  LAUE_EINVAL, "potentials are NULL");
     LAUE_REQUIRE(bins_ok(par, pot), LAUE_EINVAL, "bin potentials must be finite");
     BatchEngine e;
     laue_potentials p = *pot;           // read only
-    if ((rc = e.setup({SampleIn{geom, planes, obs, model, par, grains, &p, gn->mu_rel, nullptr, step_norm}}, ws,
+    if ((rc = e.setup({SampleIn{geom, planes, obs, model, par, grains, &p, gn->mu_rel, nullptr, step_norm, gn}}, ws,
                       ws_bytes, stream, true)))
         return rc;
     if ((rc = launch_pack(model, e.sw[0].colsE, e.s))) return rc;
@@ -2244,7 +2479,8 @@ extern "C" int laue_em(const laue_geometry *geom, const laue_planes *planes,
         return rc;
     LAUE_REQUIRE(bins_ok(&par->ot, pot), LAUE_EINVAL, "bin potentials must be finite");
     BatchEngine e;
-    if ((rc = e.setup({SampleIn{geom, planes, obs, model, &par->ot, grains, pot, par->gn.mu_rel, assign, nullptr}},
+    if ((rc = e.setup({SampleIn{geom, planes, obs, model, &par->ot, grains, pot, par->gn.mu_rel, assign, nullptr,
+                                &par->gn}},
                       ws, ws_bytes, stream, false)))
         return rc;
     std::vector<laue_em_stats> st;
@@ -2275,7 +2511,7 @@ extern "C" int laue_em_batched(int32_t n, const laue_geometry *geoms, const laue
                      LAUE_EINVAL, "samples of a batch share launch, tile and ot.chunk");
         LAUE_REQUIRE(bins_ok(&pars[k].ot, pots + k), LAUE_EINVAL, "bin potentials must be finite");
         in[k] = SampleIn{geoms + k, planes + k, obs + k, models + k, &pars[k].ot, grains + k, pots + k,
-                         pars[k].gn.mu_rel, assigns ? assigns + k : nullptr, nullptr};
+                         pars[k].gn.mu_rel, assigns ? assigns + k : nullptr, nullptr, &pars[k].gn};
         par[k] = pars + k;
     }
     BatchEngine e;

@@ -43,68 +43,14 @@ __device__ inline void spot_normal(const laue_geometry &G, int b, float p1, floa
     sth = 0.5 * nd;
 }
 
-// Largest-eigenvalue eigenvector of a symmetric 4x4 matrix (cyclic Jacobi, FP64).
-__device__ inline void sym4_top_eigvec(double A[4][4], double v[4]) {
-    double V[4][4] = {{1, 0, 0, 0}, {0, 1, 0, 0}, {0, 0, 1, 0}, {0, 0, 0, 1}};
-    for (int sweep = 0; sweep < 12; ++sweep) {
-        double off = 0.0, dia = 0.0;
-        for (int p = 0; p < 4; ++p) {
-            dia += A[p][p] * A[p][p];
-            for (int q = p + 1; q < 4; ++q) off += A[p][q] * A[p][q];
-        }
-        if (off <= 1e-30 * dia) break;
-        for (int p = 0; p < 3; ++p)
-            for (int q = p + 1; q < 4; ++q) {
-                if (fabs(A[p][q]) < 1e-300) continue;
-                const double th = (A[q][q] - A[p][p]) / (2.0 * A[p][q]);
-                const double t = (th >= 0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
-                const double c = 1.0 / sqrt(t * t + 1.0), s = t * c;
-                for (int k = 0; k < 4; ++k) {
-                    const double kp = A[k][p], kq = A[k][q];
-                    A[k][p] = c * kp - s * kq;
-                    A[k][q] = s * kp + c * kq;
-                }
-                for (int k = 0; k < 4; ++k) {
-                    const double pk = A[p][k], qk = A[q][k];
-                    A[p][k] = c * pk - s * qk;
-                    A[q][k] = s * pk + c * qk;
-                }
-                for (int k = 0; k < 4; ++k) {
-                    const double kp = V[k][p], kq = V[k][q];
-                    V[k][p] = c * kp - s * kq;
-                    V[k][q] = s * kp + c * kq;
-                }
-            }
-    }
-    int best = 0;
-    for (int i = 1; i < 4; ++i)
-        if (A[i][i] > A[best][best]) best = i;
-    for (int k = 0; k < 4; ++k) v[k] = V[k][best];
-}
-
-// Wahba's problem (App. A): the rotation R minimising sum_k ||a_k - R b_k||^2,
-// solved through Davenport's q-method (the same minimiser as the SVD form of
-// Alg. Wahba): the optimal unit quaternion is the top eigenvector of
-// K = [[tr B, z^T], [z, B + B^T - tr(B) I]], B = sum a_k b_k^T,
-// z = (B32 - B23, B13 - B31, B21 - B12).
+// Wahba's problem (App. A) for three vector pairs: R minimising
+// sum_k ||a_k - R b_k||^2 (rows of a and b), by wahba_quat_B.
 __device__ inline void wahba_quat(const double a[3][3], const double b[3][3], double *q) {
     double B[3][3] = {};
     for (int k = 0; k < 3; ++k)
         for (int i = 0; i < 3; ++i)
             for (int j = 0; j < 3; ++j) B[i][j] += a[k][i] * b[k][j];
-    const double tr = B[0][0] + B[1][1] + B[2][2];
-    const double z[3] = {B[2][1] - B[1][2], B[0][2] - B[2][0], B[1][0] - B[0][1]};
-    double K[4][4];
-    K[0][0] = tr;
-    for (int i = 0; i < 3; ++i) {
-        K[0][1 + i] = z[i];
-        K[1 + i][0] = z[i];
-        for (int j = 0; j < 3; ++j) K[1 + i][1 + j] = B[i][j] + B[j][i] - (i == j ? tr : 0.0);
-    }
-    sym4_top_eigvec(K, q);
-    double nrm = sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
-    const double sg = q[0] < 0 ? -1.0 : 1.0;
-    for (int k = 0; k < 4; ++k) q[k] = sg * q[k] / nrm;
+    wahba_quat_B(B, q);
 }
 
 __device__ __forceinline__ void cross3(const double *a, const double *b, double *c) {
