@@ -280,7 +280,7 @@ def _c_out(preset):
     return 2.0 * preset.distance ** 2 * (1.0 - math.cos(3.0 * preset.sigma_mm / preset.distance))
 
 
-def _em_iterations(laue, preset, ks, log, label, **ot_kw):
+def _em_iterations(laue, preset, ks, log, label, em_kw=None, **ot_kw):
     """EM iterations ks of the schedule from the same start (fresh problem,
     zero potentials), each one laue_em call of one iteration; returns the
     per-iteration stats summary and the final grains."""
@@ -305,7 +305,7 @@ def _em_iterations(laue, preset, ks, log, label, **ot_kw):
     for k in ks:
         eps = eps_list[k % len(eps_list)]
         ot = laue.ot_params(eps, preset.distance, _c_out(preset), t_b, tol=1e-5, n_max=2000, **ot_kw)
-        par = laue.em_params(ot, eps, eps, 1, 1, k_gn=2)
+        par = laue.em_params(ot, eps, eps, 1, 1, **(em_kw or {"k_gn": 2}))
         o = laue.laue_em(geom, planes, obs, model, par, grains, f, g, f0, g0, assign=False)
         if not ot_kw.get("unbalanced_kl"):
             f0, g0 = o["f0"], o["g0"]
@@ -389,6 +389,35 @@ def bench_unbalanced(laue, preset, kls, n_iter, log, first_iter=0):
     return out
 
 
+def bench_mstep_methods(laue, preset, quality_preset, n_iter, log, first_iter=2):
+    """The paper's coordinate-descent M-step (one or two sweeps of
+    LauePosNewton, 3 steps, then LaueRotMM) against the joint Gauss-Newton
+    M-step (2 steps):
+    time per EM iteration and in the M-step on preset (EM iterations
+    first_iter.. of the schedule, the throughput metric's iterations), and
+    recall over the whole schedule on quality_preset."""
+    import inputgen as ig
+    cd = {"mstep": "paper", "k_newton": 3, "k_mm": 500, "tol_x": 1e-6, "tol_r": 1e-12}
+    kws = {"gauss_newton": {"k_gn": 2}, "paper": dict(cd, k_gn=1), "paper_2_sweeps": dict(cd, k_gn=2)}
+    out = {"em_iterations": [first_iter, first_iter + n_iter], "settings": kws}
+    res = {}
+    for key, kw in kws.items():
+        summ, qg, xg, _ = _em_iterations(laue, preset, list(range(first_iter, first_iter + n_iter)), log,
+                                         f"mstep: {key}", em_kw=kw)
+        out[key] = summ
+        res[key] = (qg, xg)
+    out["paper_vs_gauss_newton"] = _deviation(res["paper"], res["gauss_newton"])
+    out["paper_2_sweeps_vs_gauss_newton"] = _deviation(res["paper_2_sweeps"], res["gauss_newton"])
+    q, x = ig.random_grains(quality_preset)
+    ks = list(range(len(_em_schedule(quality_preset))))
+    out["quality"] = {"workload": quality_preset.name, "em_iterations": [0, len(ks)]}
+    for key, kw in kws.items():
+        summ, qg, xg, _ = _em_iterations(laue, quality_preset, ks, log, f"mstep quality: {key}", em_kw=kw)
+        out["quality"][key] = {"ms_per_em_iteration": summ["ms_per_em_iteration"], "mstep_ms": summ["mstep_ms"],
+                               "recall_0.25deg_0.5mm": recall(qg, xg, q, x) / len(q)}
+    return out
+
+
 def bench_forward(laue, n_grains, log):
     """Forward model at candidate scale: enumerate the visible reflections of
     n_grains random grains (learned-scale scan and lattice), then time the
@@ -445,6 +474,7 @@ def main():
                          "(the paper's log-likelihood units)")
     ap.add_argument("--unbalanced-iters", type=int, default=20)
     ap.add_argument("--unbalanced-workload", default="medium", choices=["medium", "learned", "stress"])
+    ap.add_argument("--no-mstep-methods", action="store_true")
     ap.add_argument("--batch-samples", type=int, default=64)
     ap.add_argument("--index-workloads", default="medium:4096,learned:1024",
                     help="comma-separated workload:pairs; plain scoring takes the candidates of that many "
@@ -558,6 +588,9 @@ def main():
         line["unbalanced_ot"] = bench_unbalanced(laue, ig.PRESETS[args.unbalanced_workload], kl,
                                                  args.unbalanced_iters, log)
         line["unbalanced_ot"]["workload"] = args.unbalanced_workload
+    if not args.no_mstep_methods:
+        import inputgen as ig
+        line["mstep_methods"] = bench_mstep_methods(laue, preset, ig.PRESETS["medium"], args.steps, log)
     if not args.no_index:
         line["time_to_index"] = {}
         for item in args.index_workloads.split(","):
