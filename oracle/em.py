@@ -14,7 +14,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from . import cost, forward, mstep, sinkhorn, sparse, unbalanced
+from . import cost, forward, mstep, partial, sinkhorn, sparse, unbalanced
 
 
 def eps_schedule(eps0, eps_end, n_stages, iters_per_stage):
@@ -74,13 +74,15 @@ def grain_pairs(planes, geom, p_lab, obs_off, model, Qb, n_grains):
 
 def run(planes, geom, distance, p12, obs_off, model, q0, x0, eps_list, c_out, c_unm=0.0,
         c_sink=None, t_b=None, k_gn=2, tol=1e-5, n_max=2000, record=False, rho=None,
-        unbalanced_kl=None, mstep_method="gn", paper_kw=None):
+        unbalanced_kl=None, mstep_method="gn", paper_kw=None, partial_frac=None):
     """Run the EM.  model: dict with m, n, t, det (block-sorted) and offsets.
     rho: keep only each detected spot's rho nearest model spots, re-chosen at
     every EM iteration from that iteration's costs (oracle/sparse.py).
     unbalanced_kl: (kappa, lambda) replaces the E-step by unbalanced OT
     (oracle/unbalanced.py; no bins, so c_out, c_unm, c_sink and t_b are
     unused and f0, g0 come back as -inf).
+    partial_frac: m_OT replaces the E-step by partial OT (oracle/partial.py,
+    started from the Gibbs kernel at every iteration; no bins).
     mstep_method: "gn" (k_gn joint Gauss-Newton steps) or "paper" (k_gn
     coordinate-descent sweeps of LauePosNewton then LaueRotMM,
     mstep.paper_step with the keyword arguments paper_kw).
@@ -98,7 +100,12 @@ def run(planes, geom, distance, p12, obs_off, model, q0, x0, eps_list, c_out, c_
     stats = []
     for it, eps in enumerate(eps_list):
         C, _, _ = build_costs(planes, geom, distance, p12, obs_off, model, q, x)
-        if unbalanced_kl is not None:
+        if partial_frac is not None:
+            Cm = sparse.masked_blocks(C, rho) if rho else C
+            sol = partial.solve(Cm, eps, partial_frac, tol=tol, n_max=n_max)
+            f, g, f0, g0 = sol["f"], sol["g"], -np.inf, -np.inf
+            Qb = partial.plan_blocks(Cm, f, g, eps)
+        elif unbalanced_kl is not None:
             Cm = sparse.masked_blocks(C, rho) if rho else C
             sol = unbalanced.solve(Cm, eps, unbalanced_kl[0], unbalanced_kl[1], tol=tol, n_max=n_max, f=f, g=g)
             f, g, f0, g0 = sol["f"], sol["g"], -np.inf, -np.inf
