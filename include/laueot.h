@@ -243,9 +243,22 @@ typedef struct laue_ot_params {
      * change an update of the iteration makes to a row or column marginal of
      * the plan, S |exp(du / eps) - 1| (S its mass before the update, du its
      * potential change), is <= tol (or, as above, within 4 tol and stalled
-     * for 64 iterations). */
+     * for 64 iterations).
+     * 2 = partial OT (App. B, Problem A): no bins either; plans with row and
+     * column sums <= 1 and total mass m = m_frac * sum_b min(|I_b|, |J_b|)
+     * (the most the block plans can carry), the KL projection of the Gibbs
+     * kernel exp(-c/eps) by Dykstra's projections (Alg. PartialOT), in
+     * potential form: f = min(0, -eps LSE_j (g_j + H - c_ij)/eps), g likewise
+     * over the column, then H += eps ln(m / M) with M the mass after the
+     * column step.  Every solve starts from the Gibbs kernel (the given f and
+     * g are not read); on return H is folded into f, so that
+     * Q = exp((f + g - c)/eps).  Stop when the largest change between
+     * consecutive iterations of a row mass (of the plan entering the row
+     * step) or a column mass (of the plan entering the column step) is <= tol
+     * (or within 4 tol and stalled for 64 iterations). */
     int32_t outlier_model;
     double kappa, lam;
+    double m_frac;              /* partial OT: fraction of the mass transported, (0, 1] */
 } laue_ot_params;
 
 /* Dual potentials: Q_ij = exp((f_i + g_j - c_ij) / eps).  f [n_obs], g
@@ -261,7 +274,8 @@ typedef struct laue_ot_stats {
     int32_t converged;
     double err;                 /* the stopping test's value at the end: max relative
                                  * row-marginal error (outlier_model 0), largest
-                                 * marginal change of an update (outlier_model 1) */
+                                 * marginal change of an update (outlier_model 1),
+                                 * largest plan-mass change between iterations (2) */
 } laue_ot_stats;
 
 size_t laue_sinkhorn_workspace_size(const laue_geometry *geom, int64_t n_obs, int64_t n_model,
@@ -271,9 +285,9 @@ size_t laue_sinkhorn_workspace_size(const laue_geometry *geom, int64_t n_obs, in
  * potentials: row half (all f_i and f_0 from g, g0), then column half (all
  * g_j and g_0 from the new f, f0), until the max relative row-marginal error
  * after a column half is <= tol or n_max iterations.  With
- * par->outlier_model = 1 the iterations are those of Alg. UnbalancedOT
- * instead (see laue_ot_params; f0, g0 are then not read and come back as
- * -inf).  Uses the model spots' s1, s2, vn, v1, v2.  Synchronous.  Returns
+ * par->outlier_model = 1 or 2 the iterations are those of Alg. UnbalancedOT
+ * or Alg. PartialOT instead (see laue_ot_params; f0, g0 are then not read and
+ * come back as -inf).  Uses the model spots' s1, s2, vn, v1, v2.  Synchronous.  Returns
  * LAUE_ENOCONV at the cap. */
 int laue_sinkhorn(const laue_geometry *geom, const laue_obs_spots *obs,
                   const laue_model_spots *model, const laue_ot_params *par,
@@ -376,9 +390,9 @@ typedef struct laue_em_stats {
 /* Per detected spot (device, may be NULL): j_star = argmax over its block's
  * model spots and the outlier column of Q (lowest index on ties; -1 for the
  * outlier column), its grain (-1 for outlier), q_star = Q_ij*, q_out = Q_i0.
- * Under unbalanced OT (no outlier column) q_out is the mass the plan leaves
- * untransported, max(0, 1 - sum_j Q_ij), and takes the outlier column's
- * place in the comparison. */
+ * Under unbalanced or partial OT (no outlier column) q_out is the mass the
+ * plan leaves untransported, max(0, 1 - sum_j Q_ij), and takes the outlier
+ * column's place in the comparison. */
 typedef struct laue_assignments {
     int32_t *j_star;
     int32_t *grain;

@@ -276,9 +276,10 @@ def laue_simulate(geom, planes, truth, sigma_mm, distance, outlier_frac, seed):
 # ---------------------------------------------------------------- E / M steps
 
 def ot_params(eps, distance, c_out, t_b, c_unm=0.0, c_sink=None, tol=1e-5, n_max=2000, chunk=0, rho=0,
-              unbalanced_kl=None):
+              unbalanced_kl=None, partial_frac=None):
     """rho: 0 dense; 8, 16 or 32 keeps each detected spot's rho nearest model spots.
-    unbalanced_kl: (kappa, lam) in mm^2 selects unbalanced OT (no bins)."""
+    unbalanced_kl: (kappa, lam) in mm^2 selects unbalanced OT (no bins);
+    partial_frac: m_OT in (0, 1] selects partial OT (no bins)."""
     p = laue_ot_params()
     p.eps, p.distance, p.c_out, p.c_unm = float(eps), float(distance), float(c_out), float(c_unm)
     p.c_sink = float(c_out if c_sink is None else c_sink)
@@ -287,6 +288,9 @@ def ot_params(eps, distance, c_out, t_b, c_unm=0.0, c_sink=None, tol=1e-5, n_max
     if unbalanced_kl is not None:
         p.outlier_model = 1
         p.kappa, p.lam = float(unbalanced_kl[0]), float(unbalanced_kl[1])
+    if partial_frac is not None:
+        p.outlier_model = 2
+        p.m_frac = float(partial_frac)
     return p
 
 

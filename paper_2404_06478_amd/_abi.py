@@ -53,7 +53,8 @@ class laue_ot_params(C.Structure):
     _fields_ = [("eps", C.c_double), ("distance", C.c_double), ("c_out", C.c_double),
                 ("c_unm", C.c_double), ("c_sink", C.c_double), ("t_b", C.c_double),
                 ("tol", C.c_double), ("n_max", C.c_int32), ("chunk", C.c_int32), ("rho", C.c_int32),
-                ("outlier_model", C.c_int32), ("kappa", C.c_double), ("lam", C.c_double)]
+                ("outlier_model", C.c_int32), ("kappa", C.c_double), ("lam", C.c_double),
+                ("m_frac", C.c_double)]
 
 
 class laue_potentials(C.Structure):

@@ -54,16 +54,18 @@ struct SinkCtl {
     int best_iter;         // iteration of the last 1% improvement of the error
     int pad[2];
     double best_err;
-    double errf, errg;     // unbalanced OT: largest marginal change of the latest row / column half
+    double errf, errg;     // unbalanced / partial OT: largest marginal change of the latest row / column half
+    double H;              // partial OT: mass potential (Q = exp((f + g + H - c) / eps))
 };
 
 struct SinkParams {
     double c_out, c_unm, c_sink, t_a, t_b, tol;
     double kappa, lam;     // unbalanced OT: marginal penalties (unb = 1)
+    double mass;           // partial OT: transported mass m (part = 1)
     float twoD2;
     int n_max;
-    int unb;               // 0: outlier row and column; 1: unbalanced OT (no bins)
-    int pad;
+    int unb;               // 1: unbalanced OT (no bins)
+    int part;              // 1: partial OT (no bins)
 };
 
 // New potential of a row (column) from ln S, S the sum of the previous
@@ -75,6 +77,22 @@ __device__ __forceinline__ float potential_update(float u, double logS, double e
                                                   bool empty) {
     if (!unb) return static_cast<float>(static_cast<double>(u) - eps * logS);
     return empty ? 0.0f : static_cast<float>(tau * (static_cast<double>(u) - eps * logS));
+}
+
+// Partial OT (Alg. PartialOT, Dykstra's projections from the Gibbs kernel in
+// potential form): here S sums exp((v + H - c)/eps) over the row (column),
+// v the other side's potentials, and the new potential is min(0, -eps ln S)
+// (0 without entries).  The stopping value is the change of the row's
+// (column's) plan mass exp(ln S + u/eps) from the previous iteration's (prev;
+// none in the first); the new mass is stored in prev.
+__device__ __forceinline__ float partial_update(double logS, double eps, bool empty) {
+    return empty ? 0.0f : static_cast<float>(fmin(0.0, -eps * logS));
+}
+__device__ __forceinline__ double partial_change(double logS, float u, double eps, bool empty, int k, float *prev) {
+    const double m = empty ? 0.0 : exp(logS + static_cast<double>(u) / eps);
+    const double d = k > 1 ? fabs(m - static_cast<double>(*prev)) : INFINITY;
+    *prev = static_cast<float>(m);
+    return d;
 }
 
 // Unbalanced OT's stopping value for one row (column): the change its update
@@ -125,6 +143,8 @@ struct SampleDesc {
     int *knn_hist;                 // [nb x kGrid^2] model spots per detector cell
     int *sort_key, *sort_val;      // [n_obs x rho] radix-sort input (column, entry)
     const int *sorted_val;         // [n_obs x rho] entries ordered by column
+    // partial OT: plan masses of the previous iteration (stopping test)
+    float *rmass, *cmass;          // [n_obs], [n_model]
     // the paper's coordinate-descent M-step
     int *gflag;                    // [n_grains] Newton converged in this sweep
     int k_mm, pad1;                // MM steps per sweep
@@ -192,6 +212,7 @@ __global__ void k_ctl_init(const SampleDesc *__restrict__ descs, int n, const Ct
     ctl->best_err = INFINITY;
     ctl->errf = INFINITY;
     ctl->errg = INFINITY;
+    ctl->H = 0.0;
     ctl->final_state = 0;
     ctl->converged = 0;
     ctl->ticket = 0u;
@@ -235,8 +256,8 @@ __device__ __forceinline__ void row_finalize(SinkCtl *__restrict__ ctl, const do
         const double row0 = ctl->cs_sum + exp((f0p + g0p - p.c_sink) / eps);
         const double err0 = p.t_b > 0 ? fabs(row0 - p.t_b) / p.t_b : 0.0;
         double e = fmax(emax, err0);
-        if (p.unb) {
-            // unbalanced OT: the marginal changes of iteration k-1 decide
+        if (p.unb || p.part) {
+            // unbalanced / partial OT: the marginal changes of iteration k-1 decide
             // whether state k-1 is final; this half's changes wait for the next
             e = fmax(ctl->errf, ctl->errg);
             ctl->errf = emax;
@@ -270,9 +291,10 @@ __device__ __forceinline__ void row_finalize(SinkCtl *__restrict__ ctl, const do
 
 // The sample's last workgroup of a column half: stores
 // sum_j exp((f0 + g_j - c_unm)/eps) for the next row half and the largest
-// marginal change of the half (unbalanced OT's stopping test).
+// marginal change of the half (unbalanced and partial OT's stopping test);
+// under partial OT it applies the mass step.
 __device__ __forceinline__ void col_finalize(SinkCtl *__restrict__ ctl, const double2 *__restrict__ part,
-                                             int n_items) {
+                                             int n_items, const SinkParams &p) {
     double t = 0.0, m = 0.0;
     for (int w = threadIdx.x; w < n_items; w += 64) {
         t += part[w].x;
@@ -283,6 +305,9 @@ __device__ __forceinline__ void col_finalize(SinkCtl *__restrict__ ctl, const do
     if (threadIdx.x == 0) {
         ctl->cs_sum = t;
         ctl->errg = m;
+        // partial OT: the partials hold min(1, column sum) (the mass after the
+        // column step); scale the plan to the mass m
+        if (p.part && t > 0.0) ctl->H += ctl->eps * log(p.mass / t);
         ctl->ticket = 0u;
     }
 }
@@ -311,7 +336,8 @@ __device__ __forceinline__ void row_pass(const Item *its, const LAUE_GLOBAL floa
                                          const LAUE_GLOBAL Col8 *__restrict__ cols,
                                          const LAUE_GLOBAL float *__restrict__ G, LAUE_GLOBAL float *__restrict__ F0,
                                          LAUE_GLOBAL float *__restrict__ F1, SinkCtl *__restrict__ ctl,
-                                         double2 *__restrict__ part, const SinkParams &p, int n_wg, int n_items) {
+                                         double2 *__restrict__ part, const SinkParams &p, int n_wg, int n_items,
+                                         float *__restrict__ RM) {
     if (ctl->done) return;
     const int k = ctl->iter + 1;
     const LAUE_GLOBAL float *Fin = ((k - 1) & 1) ? F1 : F0;
@@ -333,7 +359,8 @@ __device__ __forceinline__ void row_pass(const Item *its, const LAUE_GLOBAL floa
         p1[r] = act[r] ? P1[i[r]] : 0.0f;
         p2[r] = act[r] ? P2[i[r]] : 0.0f;
         f[r] = act[r] ? Fin[i[r]] : 0.0f;
-        fk[r] = f[r] * kx;
+        // partial OT: the row sums of the Dykstra-corrected plan take the mass potential as shift
+        fk[r] = p.part ? static_cast<float>(ctl->H * kexp) : f[r] * kx;
         acc[r] = 0.0;
     }
     for (int j0 = c0; j0 < c1; j0 += 64) {
@@ -359,12 +386,13 @@ __device__ __forceinline__ void row_pass(const Item *its, const LAUE_GLOBAL floa
     for (int r = 0; r < R; ++r) {
         eb[r] = (g0 - p.c_out) * kexp + static_cast<double>(fk[r]);
         acc[r] += exp2(eb[r]);
-        slow[r] = act[r] && !(acc[r] > 1e-30);
+        slow[r] = act[r] && !(acc[r] > 1e-30 && acc[r] < 1e30);
         any_slow = any_slow || slow[r];
         logS[r] = log(acc[r]);
     }
     if (__any(any_slow)) {
-        // every term underflowed: recompute with the row maximum as shift
+        // every term underflowed (or, under partial OT, the sum overflowed):
+        // recompute with the row maximum as shift
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             float mx = static_cast<float>(eb[r]);
@@ -386,10 +414,12 @@ __device__ __forceinline__ void row_pass(const Item *its, const LAUE_GLOBAL floa
     const double tau = unb ? p.kappa / (p.kappa + eps) : 1.0;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-        const float fnf = potential_update(f[r], logS[r], eps, unb, tau, c1 <= c0);
+        const float fnf = p.part ? partial_update(logS[r], eps, c1 <= c0)
+                                 : potential_update(f[r], logS[r], eps, unb, tau, c1 <= c0);
         double err = !act[r] ? 0.0
-                     : unb   ? mass_change(logS[r], fnf, f[r], eps, c1 <= c0)
-                             : fabs(acc[r] - 1.0);
+                     : p.part ? partial_change(logS[r], f[r], eps, c1 <= c0, k, RM + i[r])
+                     : unb    ? mass_change(logS[r], fnf, f[r], eps, c1 <= c0)
+                              : fabs(acc[r] - 1.0);
         double rs = 0.0;
         if (act[r]) {
             Fout[i[r]] = fnf;
@@ -423,7 +453,7 @@ __global__ __launch_bounds__(64) void k_row(const Item *__restrict__ items, cons
     group_items<R>(items, groups, its);
     const SampleDesc &D = descs[its[0].s];
     row_pass<R>(its, gptr(D.p1), gptr(D.p2), gptr(D.colsE), gptr(D.g), gptr(D.f), gptr(D.f1), D.ctl, D.part,
-                D.sp, R == 1 ? D.n_row_items : D.n_row_wg2, D.n_row_items);
+                D.sp, R == 1 ? D.n_row_items : D.n_row_wg2, D.n_row_items, D.rmass);
 }
 
 // ---------------------------------------------------------------- column pass
@@ -466,7 +496,8 @@ __device__ __forceinline__ void col_pass(const Item *its, const LAUE_GLOBAL floa
                                          const LAUE_GLOBAL Col8 *__restrict__ cols, LAUE_GLOBAL float *__restrict__ G,
                                          const LAUE_GLOBAL float *__restrict__ F0,
                                          const LAUE_GLOBAL float *__restrict__ F1, SinkCtl *__restrict__ ctl,
-                                         double2 *__restrict__ part, const SinkParams &p, int n_wg, int n_items) {
+                                         double2 *__restrict__ part, const SinkParams &p, int n_wg, int n_items,
+                                         float *__restrict__ CM) {
     if (ctl->done) return;
     const int k = ctl->iter;
     const LAUE_GLOBAL float *__restrict__ F = (k & 1) ? F1 : F0;
@@ -491,7 +522,7 @@ __device__ __forceinline__ void col_pass(const Item *its, const LAUE_GLOBAL floa
             c[r] = ld_col(cols + j[r]);
             g[r] = G[j[r]];
         }
-        gk[r] = g[r] * kx;
+        gk[r] = p.part ? static_cast<float>(ctl->H * kexp) : g[r] * kx;
         acc[r] = 0.0;
     }
     // the potentials of state k by parity, each a restrict stream of its own
@@ -505,7 +536,7 @@ __device__ __forceinline__ void col_pass(const Item *its, const LAUE_GLOBAL floa
     for (int r = 0; r < R; ++r) {
         eb[r] = (f0 - p.c_unm) * kexp + static_cast<double>(gk[r]);
         acc[r] += exp2(eb[r]);
-        slow[r] = act[r] && !(acc[r] > 1e-30);
+        slow[r] = act[r] && !(acc[r] > 1e-30 && acc[r] < 1e30);
         any_slow = any_slow || slow[r];
         logS[r] = log(acc[r]);
     }
@@ -530,17 +561,24 @@ __device__ __forceinline__ void col_pass(const Item *its, const LAUE_GLOBAL floa
     for (int r = 0; r < R; ++r) {
         double cs = 0.0, err = 0.0;
         if (act[r]) {
-            const float gn = potential_update(g[r], logS[r], eps, unb, tau, r1 <= r0);
+            const bool empty = r1 <= r0;
+            const float gn = p.part ? partial_update(logS[r], eps, empty)
+                                    : potential_update(g[r], logS[r], eps, unb, tau, empty);
             G[j[r]] = gn;
-            cs = exp((f0 + static_cast<double>(gn) - p.c_unm) / eps);
-            if (unb) err = mass_change(logS[r], gn, g[r], eps, r1 <= r0);
+            if (p.part) {
+                cs = empty ? 0.0 : exp(fmin(logS[r], 0.0));
+                err = partial_change(logS[r], g[r], eps, empty, k, CM + j[r]);
+            } else {
+                cs = exp((f0 + static_cast<double>(gn) - p.c_unm) / eps);
+                if (unb) err = mass_change(logS[r], gn, g[r], eps, empty);
+            }
         }
         cs = wave_sum(cs);
         err = wave_max(err);
         if (threadIdx.x == 0 && its[r].local >= 0) part[its[r].local] = make_double2(cs, err);
     }
     if (!last_block(ctl, n_wg)) return;
-    col_finalize(ctl, part, n_items);
+    col_finalize(ctl, part, n_items, p);
 }
 
 template <int R>
@@ -550,7 +588,7 @@ __global__ __launch_bounds__(64) void k_col(const Item *__restrict__ items, cons
     group_items<R>(items, groups, its);
     const SampleDesc &D = descs[its[0].s];
     col_pass<R>(its, gptr(D.p1), gptr(D.p2), gptr(D.colsE), gptr(D.g), gptr(D.f), gptr(D.f1), D.ctl, D.part,
-                D.sp, R == 1 ? D.n_col_items : D.n_col_wg2, D.n_col_items);
+                D.sp, R == 1 ? D.n_col_items : D.n_col_wg2, D.n_col_items, D.cmass);
 }
 
 // ---------------------------------------------------------------- assign
@@ -572,7 +610,7 @@ __device__ __forceinline__ void assign_pass(const Item &it, const SampleDesc &D,
     const float K = p.twoD2 * kx;
     const float p1 = act ? D.p1[i] : 0.0f, p2 = act ? D.p2[i] : 0.0f, f = act ? D.f[i] : 0.0f;
     const float fk = f * kx;
-    const bool unb = p.unb != 0;
+    const bool unb = p.unb != 0 || p.part != 0;
     float best = -INFINITY, sum = 0.0f;
     int arg = -1;
     for (int j = it.c0; j < it.c1; ++j) {
@@ -1110,6 +1148,13 @@ __global__ void k_knn_out(const int *__restrict__ nbr, const float *__restrict__
     ocost[e] = ncp[q * n_obs + i] * twoD2;
 }
 
+// x[k] = v (partial OT: the Gibbs-kernel start) or x[k] += v (folding the
+// mass potential into the row potentials), k < n
+__global__ void k_fill_f(float *__restrict__ x, int64_t n, double v, int add) {
+    const int64_t k = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (k < n) x[k] = add ? static_cast<float>(static_cast<double>(x[k]) + v) : static_cast<float>(v);
+}
+
 __global__ void k_zero_i(int *__restrict__ p, int64_t n) {
     const int64_t k = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (k < n) p[k] = 0;
@@ -1136,7 +1181,7 @@ __global__ __launch_bounds__(64) void k_row_sparse(const Item *__restrict__ item
     const int i = it.r0 + static_cast<int>(threadIdx.x);
     const bool act = i < it.r1;
     const float f = act ? Fin[i] : 0.0f;
-    const float fk = f * kx;
+    const float fk = p.part ? static_cast<float>(ctl->H * kexp) : f * kx;
     const int64_t base = act ? i : 0, st = D.n_obs;   // neighbour-major: entry q of row i at q n_obs + i
     float a = 0.0f;
     for (int q = 0; q < R; ++q) {
@@ -1146,7 +1191,7 @@ __global__ __launch_bounds__(64) void k_row_sparse(const Item *__restrict__ item
     double acc = static_cast<double>(a);
     const double eb = (g0 - p.c_out) * kexp + static_cast<double>(fk);
     acc += exp2(eb);
-    const bool slow = act && !(acc > 1e-30);
+    const bool slow = act && !(acc > 1e-30 && acc < 1e30);
     double logS = log(acc);
     if (__any(slow) && slow) {
         float mx = static_cast<float>(eb);
@@ -1164,8 +1209,12 @@ __global__ __launch_bounds__(64) void k_row_sparse(const Item *__restrict__ item
     }
     const bool unb = p.unb != 0;
     const bool empty = !act || D.nbr[base] < 0;
-    const float fnf = potential_update(f, logS, eps, unb, unb ? p.kappa / (p.kappa + eps) : 1.0, empty);
-    double err = !act ? 0.0 : unb ? mass_change(logS, fnf, f, eps, empty) : fabs(acc - 1.0);
+    const float fnf = p.part ? partial_update(logS, eps, empty)
+                             : potential_update(f, logS, eps, unb, unb ? p.kappa / (p.kappa + eps) : 1.0, empty);
+    double err = !act     ? 0.0
+                 : p.part ? partial_change(logS, f, eps, empty, k, D.rmass + i)
+                 : unb    ? mass_change(logS, fnf, f, eps, empty)
+                          : fabs(acc - 1.0);
     double rs = 0.0;
     if (act) {
         Fout[i] = fnf;
@@ -1196,14 +1245,14 @@ __global__ __launch_bounds__(64) void k_col_sparse(const Item *__restrict__ item
     const int j = it.c0 + static_cast<int>(threadIdx.x);
     const bool act = j < it.c1;
     const float g = act ? D.g[j] : 0.0f;
-    const float gk = g * kx;
+    const float gk = p.part ? static_cast<float>(ctl->H * kexp) : g * kx;
     const int64_t a0 = act ? D.col_off[j] : 0, a1 = act ? D.col_off[j + 1] : 0;
     float a = 0.0f;
     for (int64_t e = a0; e < a1; ++e) a += fast_exp2(fmaf(-K, D.col_cp[e], fmaf(F[D.col_row[e]], kx, gk)));
     double acc = static_cast<double>(a);
     const double eb = (f0 - p.c_unm) * kexp + static_cast<double>(gk);
     acc += exp2(eb);
-    const bool slow = act && !(acc > 1e-30);
+    const bool slow = act && !(acc > 1e-30 && acc < 1e30);
     double logS = log(acc);
     if (__any(slow) && slow) {
         float mx = static_cast<float>(eb);
@@ -1216,16 +1265,23 @@ __global__ __launch_bounds__(64) void k_col_sparse(const Item *__restrict__ item
     const bool unb = p.unb != 0;
     double cs = 0.0, err = 0.0;
     if (act) {
-        const float gn = potential_update(g, logS, eps, unb, unb ? p.lam / (p.lam + eps) : 1.0, a1 <= a0);
+        const bool empty = a1 <= a0;
+        const float gn = p.part ? partial_update(logS, eps, empty)
+                                : potential_update(g, logS, eps, unb, unb ? p.lam / (p.lam + eps) : 1.0, empty);
         D.g[j] = gn;
-        cs = exp((f0 + static_cast<double>(gn) - p.c_unm) / eps);
-        if (unb) err = mass_change(logS, gn, g, eps, a1 <= a0);
+        if (p.part) {
+            cs = empty ? 0.0 : exp(fmin(logS, 0.0));
+            err = partial_change(logS, g, eps, empty, k, D.cmass + j);
+        } else {
+            cs = exp((f0 + static_cast<double>(gn) - p.c_unm) / eps);
+            if (unb) err = mass_change(logS, gn, g, eps, empty);
+        }
     }
     cs = wave_sum(cs);
     err = wave_max(err);
     if (threadIdx.x == 0) D.part[it.local] = make_double2(cs, err);
     if (!last_block(ctl, D.n_col_items)) return;
-    col_finalize(ctl, D.part, D.n_col_items);
+    col_finalize(ctl, D.part, D.n_col_items, p);
 }
 
 // Sparse M-step statistics (lane = model spot): over the rows that keep it,
@@ -1281,7 +1337,7 @@ __global__ __launch_bounds__(64) void k_assign_sparse(const Item *__restrict__ i
     const float kx = static_cast<float>(kexp);
     const float K = p.twoD2 * kx;
     const float fk = D.f[i] * kx;
-    const bool unb = p.unb != 0;
+    const bool unb = p.unb != 0 || p.part != 0;
     float best = -INFINITY, sum = 0.0f;
     int arg = -1;
     for (int q = 0; q < D.rho; ++q) {
@@ -1414,6 +1470,7 @@ struct SampleWs {
     GeomF *geom;
     GrainF *grains;
     int *gflag;
+    float *rmass, *cmass;
     int64_t *mboff;
     // sparse assignment (rho > 0)
     int *nbr = nullptr, *cand_j = nullptr, *cand_n = nullptr, *knn_list = nullptr, *knn_nlist = nullptr;
@@ -1460,6 +1517,8 @@ static size_t carve_all(Carver &cv, BatchWs &bw, std::vector<SampleWs> &sw, cons
         w.geom = cv.take<GeomF>(1);
         w.grains = cv.take<GrainF>(std::max(d.n_grains, 1));
         w.gflag = cv.take<int>(std::max(d.n_grains, 1));
+        w.rmass = cv.take<float>(std::max<int64_t>(d.n_obs, 1));
+        w.cmass = cv.take<float>(std::max<int64_t>(d.n_model, 1));
         w.mboff = cv.take<int64_t>(nb + 1);
         if (d.rho > 0) {
             const int64_t no = std::max<int64_t>(d.n_obs, 1), nm = std::max<int64_t>(d.n_model, 1);
@@ -1527,9 +1586,11 @@ static int validate_ot(const laue_ot_params *p, bool need_eps) {
     LAUE_REQUIRE(p->n_max >= 1, LAUE_EINVAL, "n_max must be >= 1");
     LAUE_REQUIRE(p->rho == 0 || p->rho == 8 || p->rho == 16 || p->rho == 32, LAUE_EINVAL,
                  "rho must be 0 (dense), 8, 16 or 32");
-    LAUE_REQUIRE(p->outlier_model == 0 || p->outlier_model == 1, LAUE_EINVAL,
-                 "outlier_model must be 0 (outlier row and column) or 1 (unbalanced OT)");
-    LAUE_REQUIRE(p->outlier_model == 0 || (std::isfinite(p->kappa) && p->kappa > 0 && std::isfinite(p->lam) &&
+    LAUE_REQUIRE(p->outlier_model >= 0 && p->outlier_model <= 2, LAUE_EINVAL,
+                 "outlier_model must be 0 (outlier row and column), 1 (unbalanced OT) or 2 (partial OT)");
+    LAUE_REQUIRE(p->outlier_model != 2 || (std::isfinite(p->m_frac) && p->m_frac > 0 && p->m_frac <= 1),
+                 LAUE_EINVAL, "partial OT needs 0 < m_frac <= 1");
+    LAUE_REQUIRE(p->outlier_model != 1 || (std::isfinite(p->kappa) && p->kappa > 0 && std::isfinite(p->lam) &&
                                            p->lam > 0),
                  LAUE_EINVAL, "unbalanced OT needs finite kappa > 0 and lam > 0");
     return LAUE_OK;
@@ -1858,12 +1919,19 @@ struct BatchEngine {
             sp.c_unm = a.ot->c_unm;
             sp.c_sink = a.ot->c_sink;
             sp.unb = a.ot->outlier_model == 1 ? 1 : 0;
-            // no bins under unbalanced OT: zero masses make their potentials -inf
-            sp.t_b = sp.unb ? 0.0 : a.ot->t_b;
-            sp.t_a = sp.unb ? 0.0 : a.ot->t_b + static_cast<double>(a.obs->n) - static_cast<double>(a.model->n);
+            sp.part = a.ot->outlier_model == 2 ? 1 : 0;
+            // no bins under unbalanced or partial OT: zero masses make their potentials -inf
+            const bool nobins = sp.unb || sp.part;
+            sp.t_b = nobins ? 0.0 : a.ot->t_b;
+            sp.t_a = nobins ? 0.0 : a.ot->t_b + static_cast<double>(a.obs->n) - static_cast<double>(a.model->n);
             sp.kappa = sp.unb ? a.ot->kappa : 0.0;
             sp.lam = sp.unb ? a.ot->lam : 0.0;
-            sp.pad = 0;
+            // partial OT: m = m_frac * sum_b min(|I_b|, |J_b|), the most the block plans can carry
+            double mmax = 0.0;
+            for (int b = 0; b < nb; ++b)
+                mmax += static_cast<double>(std::min(a.obs->block_off[b + 1] - a.obs->block_off[b],
+                                                     a.model->block_off[b + 1] - a.model->block_off[b]));
+            sp.mass = sp.part ? a.ot->m_frac * mmax : 0.0;
             sp.tol = a.ot->tol;
             sp.twoD2 = static_cast<float>(2.0 * a.ot->distance * a.ot->distance);
             sp.n_max = a.ot->n_max;
@@ -1893,6 +1961,8 @@ struct BatchEngine {
             D.D2 = a.ot->distance * a.ot->distance;
             D.mu_rel = a.mu_rel;
             D.gflag = sw[k].gflag;
+            D.rmass = sw[k].rmass;
+            D.cmass = sw[k].cmass;
             D.k_mm = a.gn ? a.gn->k_mm : 1;
             D.tol_x = a.gn ? a.gn->tol_x : 0.0;
             D.tol_r = a.gn ? a.gn->tol_r : 0.0;
@@ -2069,6 +2139,13 @@ struct BatchEngine {
         // sparse: the neighbour sets of this E-step's columns
         if ((rc = build_neighbors())) return rc;
         if ((rc = init_ctl(eps))) return rc;
+        // partial OT starts every solve from the Gibbs kernel (f = g = 0, H = 0)
+        for (int k = 0; k < n; ++k) {
+            if (!hd[k].sp.part) continue;
+            const int64_t no = in[k].obs->n, nm = in[k].model->n;
+            if (no > 0) k_fill_f<<<static_cast<unsigned>((no + 255) / 256), 256, 0, s>>>(in[k].pot->f, no, 0.0, 0);
+            if (nm > 0) k_fill_f<<<static_cast<unsigned>((nm + 255) / 256), 256, 0, s>>>(in[k].pot->g, nm, 0.0, 0);
+        }
         k_cs_init<<<n, 256, 0, s>>>(bw.desc);
         LAUE_CHECK_HIP(hipGetLastError());
         if (chunk <= 0) {
@@ -2159,6 +2236,10 @@ struct BatchEngine {
             if ((fin & 1) && in[k].obs->n > 0)
                 LAUE_CHECK_HIP(hipMemcpyAsync(pot->f, sw[k].F1, in[k].obs->n * sizeof(float),
                                               hipMemcpyDeviceToDevice, s));
+            // partial OT: fold the mass potential into f, so that Q = exp((f + g - c)/eps)
+            if (hd[k].sp.part && in[k].obs->n > 0 && h.H != 0.0)
+                k_fill_f<<<static_cast<unsigned>((in[k].obs->n + 255) / 256), 256, 0, s>>>(pot->f, in[k].obs->n, h.H,
+                                                                                           1);
             pot->f0 = h.f0[fin & 1];
             pot->g0 = h.g0[fin & 1];
             st[k].n_iter = fin;
