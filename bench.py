@@ -307,7 +307,7 @@ def _em_iterations(laue, preset, ks, log, label, em_kw=None, **ot_kw):
         ot = laue.ot_params(eps, preset.distance, _c_out(preset), t_b, tol=1e-5, n_max=2000, **ot_kw)
         par = laue.em_params(ot, eps, eps, 1, 1, **(em_kw or {"k_gn": 2}))
         o = laue.laue_em(geom, planes, obs, model, par, grains, f, g, f0, g0, assign=False)
-        if not ot_kw.get("unbalanced_kl"):
+        if not ot_kw.get("unbalanced_kl") and not ot_kw.get("partial_frac"):
             f0, g0 = o["f0"], o["g0"]
         stats.append(o)
     torch.cuda.synchronize()
@@ -358,15 +358,15 @@ def bench_sparse(laue, preset, rho, n_iter, log, first_iter=8):
     return out
 
 
-def bench_unbalanced(laue, preset, kls, n_iter, log, first_iter=0):
+def bench_outlier_models(laue, preset, kls, fracs, n_iter, log, first_iter=0):
     """The same EM iterations from the same start with the paper's outlier
-    row and column and with unbalanced OT at each (kappa, lambda) of kls
-    (units of 2 sigma^2, the paper's log-likelihood units): time per
-    iteration, the passes' entries/s (same streamed kernels, other epilogue),
-    Sinkhorn iterations, recall, and how far the grains end from those of the
-    paper's model.  Run on a workload where the paper's model recovers the
-    grains (100 grains, 30% outliers), so that recall compares the two
-    outlier treatments."""
+    row and column, with unbalanced OT at each (kappa, lambda) of kls (units
+    of 2 sigma^2, the paper's log-likelihood units) and with partial OT at
+    each transported fraction of fracs: time per iteration, the passes'
+    entries/s (same streamed kernels, other epilogue), Sinkhorn iterations,
+    recall, and how far the grains end from those of the paper's model.  Run
+    on a workload where the paper's model recovers the grains (100 grains,
+    30% outliers), so that recall compares the outlier treatments."""
     import inputgen as ig
     q, x = ig.random_grains(preset)
     eps_list = _em_schedule(preset)
@@ -386,6 +386,13 @@ def bench_unbalanced(laue, preset, kls, n_iter, log, first_iter=0):
         summ["recall_0.25deg_0.5mm"] = recall(qg, xg, q, x) / len(q)
         summ["vs_outlier_bins"] = _deviation((qg, xg), (qb, xb))
         out["unbalanced"].append(summ)
+    out["partial"] = []
+    for frac in fracs:
+        summ, qg, xg, _ = _em_iterations(laue, preset, ks, log, f"partial: m_OT = {frac}", partial_frac=frac)
+        summ["m_frac"] = frac
+        summ["recall_0.25deg_0.5mm"] = recall(qg, xg, q, x) / len(q)
+        summ["vs_outlier_bins"] = _deviation((qg, xg), (qb, xb))
+        out["partial"].append(summ)
     return out
 
 
@@ -473,6 +480,7 @@ def main():
                     help="kappa,lambda pairs (';'-separated) of unbalanced OT in units of 2 sigma^2 "
                          "(the paper's log-likelihood units)")
     ap.add_argument("--unbalanced-iters", type=int, default=20)
+    ap.add_argument("--partial-fracs", default="0.5,0.7,0.9", help="m_OT values of partial OT")
     ap.add_argument("--unbalanced-workload", default="medium", choices=["medium", "learned", "stress"])
     ap.add_argument("--no-mstep-methods", action="store_true")
     ap.add_argument("--batch-samples", type=int, default=64)
@@ -585,9 +593,10 @@ def main():
     if not args.no_unbalanced:
         kl = [tuple(float(v) for v in item.split(",")) for item in args.unbalanced_kl.split(";")]
         import inputgen as ig
-        line["unbalanced_ot"] = bench_unbalanced(laue, ig.PRESETS[args.unbalanced_workload], kl,
-                                                 args.unbalanced_iters, log)
-        line["unbalanced_ot"]["workload"] = args.unbalanced_workload
+        fracs = [float(v) for v in args.partial_fracs.split(",") if v]
+        line["outlier_models"] = bench_outlier_models(laue, ig.PRESETS[args.unbalanced_workload], kl, fracs,
+                                                      args.unbalanced_iters, log)
+        line["outlier_models"]["workload"] = args.unbalanced_workload
     if not args.no_mstep_methods:
         import inputgen as ig
         line["mstep_methods"] = bench_mstep_methods(laue, preset, ig.PRESETS["medium"], args.steps, log)
