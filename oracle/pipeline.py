@@ -14,6 +14,8 @@ its stage, taken in the paper's order:
   4. greedy SPOT with the outlier floor and k* = argmax (Delta_k - Delta_{k+1});
   5. the harmonic-merged model spots of the first k* picks, frozen, and the EM
      of oracle/em.py with T_b = max(ceil(t_b_frac |J|), |J| - |I|).
+With starts = (q, x) (the Sobol grid of Sec. 6.1, oracle/sobol.py) those
+replace steps 1-2: every start is refined from its own (q, x).
 """
 from __future__ import annotations
 
@@ -26,8 +28,11 @@ from . import candidates, em, forward, proposal, single
 
 def index(planes, geom, distance, p12, offsets, sigma, c_out, eps_list, n_pairs, seed, delta_deg=1.5,
           max_candidates=None, k_refine=8, k_gn_refine=2, f_out=0.1, k_max=None, t_b_frac=0.4, k_gn=2,
-          ranking=None, top_frac=0.05):
-    cand = candidates.generate(planes, geom, p12, offsets, n_pairs, seed, delta_deg)
+          ranking=None, top_frac=0.05, starts=None):
+    if starts is not None:
+        cand = {"q": np.asarray(starts[0], dtype=np.float64), "x": np.asarray(starts[1], dtype=np.float64)}
+    else:
+        cand = candidates.generate(planes, geom, p12, offsets, n_pairs, seed, delta_deg)
     n = len(cand["q"])
     if max_candidates is not None:
         n = min(n, int(max_candidates))
@@ -37,7 +42,8 @@ def index(planes, geom, distance, p12, offsets, sigma, c_out, eps_list, n_pairs,
     n_obs = int(offsets[-1])
     cols, refined = [], []
     for c in chosen:
-        q, x, mod = single.refine(planes, geom, distance, p12, offsets, cand["q"][c], np.zeros(3), sigma, c_out,
+        x_start = cand["x"][c] if "x" in cand else np.zeros(3)
+        q, x, mod = single.refine(planes, geom, distance, p12, offsets, cand["q"][c], x_start, sigma, c_out,
                                   k_refine=k_refine, k_gn=k_gn_refine)
         un, nm, rows, vals = single.score(planes, geom, distance, p12, offsets, mod, q, x, sigma, c_out)
         keep = nm > 0 and un < f_out * nm
