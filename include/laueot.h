@@ -643,10 +643,40 @@ int laue_mlp_train_step(laue_mlp *m, const float *feat, const float *label, int6
                         const laue_adam_params *ap, double *loss, void *ws, size_t ws_bytes,
                         void *stream);
 
+/* ---- Sobol-grid starts (Sec. 6.1) ------------------------------------------ */
+
+/* Starts of single-grain fitting from a Sobol sequence over the six
+ * dimensions (R, x) (Sec. 6.1): point n (Antonov-Saleev order: XOR of the
+ * direction numbers over the bits of the Gray code of n; Joe and Kuo's
+ * direction numbers for dimensions 2..6), u in [0, 1)^6; orientation from the
+ * modified Rodrigues parameters p = (2 u_1..3 - 1) mrp_half, q = ((1 - |p|^2),
+ * 2 p) / (1 + |p|^2); position x = (2 u_4..6 - 1) x_half.  With restrict_fz
+ * only orientations in the cubic (432) fundamental zone are kept: Rodrigues
+ * vector r = q_1..3 / q_0 with |r_i| <= tan(pi/8) and |r_1|+|r_2|+|r_3| <= 1
+ * (the crystal symmetry restriction of Sec. 6.1). */
+typedef struct laue_sobol_params {
+    int64_t first;              /* index of the first point (0 is the origin) */
+    double mrp_half;            /* half side of the MRP cube; 0: tan(pi/16), the
+                                 * largest MRP component in the cubic zone */
+    double x_half[3];           /* half extents of the position box (mm) */
+    int32_t restrict_fz;        /* 1: keep orientations in the cubic zone only */
+} laue_sobol_params;
+
+size_t laue_sobol_workspace_size(int64_t n_points);
+
+/* Points first .. first + n_points - 1 (n_points < 2^31, indices < 2^32): the
+ * kept ones, in index order, to q [n_kept][4] (q_0 > 0) and x [n_kept][3]
+ * (device FP64, capacity n_points); *n_kept (HOST).  Synchronous. */
+int laue_sobol_starts(const laue_sobol_params *par, int64_t n_points, double *q, double *x,
+                      int64_t *n_kept, void *ws, size_t ws_bytes, void *stream);
+
 /* ---- end-to-end indexing ------------------------------------------------- */
 
 #define LAUE_INDEX_PLAIN 0      /* every candidate is refined and scored */
 #define LAUE_INDEX_LEARNED 1    /* the network keeps the best-scored fraction */
+#define LAUE_INDEX_SOBOL 2      /* Sobol-grid starts (Sec. 6.1) in place of spot pairs:
+                                 * max_candidates points from sobol, the kept ones
+                                 * refined from their own (q, x) and scored */
 
 /* The multigrain solve (Sec. 6, Alg. MultiGrainLaueOT) from detected spots:
  *   1. spot-pair candidates (laue_candidates_generate; at most max_candidates
@@ -675,6 +705,7 @@ typedef struct laue_index_params {
     int64_t max_model_spots;
     double t_b_frac;
     laue_em_params em;              /* em.ot.t_b is set from t_b_frac */
+    laue_sobol_params sobol;        /* Sobol mode */
 } laue_index_params;
 
 /* Per-stage wall-clock times (ms, host clock around each synchronous stage)

@@ -685,14 +685,43 @@ def laue_pairs_same_grain(geom, obs, spot_grain, n_pairs, seed):
 
 # ---------------------------------------------------------------- end-to-end indexing
 
+def sobol_params(x_half, first=0, mrp_half=0.0, restrict_fz=True):
+    """laue_sobol_params: x_half (3 half extents of the sample box, mm)."""
+    p = _abi.laue_sobol_params()
+    p.first, p.mrp_half, p.restrict_fz = int(first), float(mrp_half), 1 if restrict_fz else 0
+    for k in range(3):
+        p.x_half[k] = float(x_half[k])
+    return p
+
+
+def laue_sobol_starts(par, n_points):
+    """Sobol-grid starts: (q [n_kept,4], x [n_kept,3]) device FP64 tensors."""
+    import torch
+    lib = require_native()
+    dev = _dev()
+    n = int(n_points)
+    q = torch.zeros((max(n, 1), 4), dtype=torch.float64, device=dev)
+    x = torch.zeros((max(n, 1), 3), dtype=torch.float64, device=dev)
+    ws = _workspace(lib.laue_sobol_workspace_size(n))
+    kept = C.c_int64(0)
+    _check(lib.laue_sobol_starts(C.byref(par), n, _ptr(q), _ptr(x), C.byref(kept), _ptr(ws), ws.numel(), _stream()))
+    return q[:kept.value], x[:kept.value]
+
+
 def index_params(preset_like, mode="plain", n_pairs=None, seed=0, delta_deg=1.5, max_candidates=None, mlp=None,
                  support_radius=None, n_support_planes=None, top_frac=0.05, score=None, lbar_cap=None, k_max=None,
-                 max_model_spots=None, t_b_frac=0.4, em=None, n_obs=0, n_planes=0):
+                 max_model_spots=None, t_b_frac=0.4, em=None, n_obs=0, n_planes=0, sobol=None):
     """laue_index_params from a workload description (sigma_mm, distance, grains,
-    rotations, schedule) with capacities sized for it."""
+    rotations, schedule) with capacities sized for it.  mode "plain",
+    "learned" or "sobol" (max_candidates Sobol points from sobol, default:
+    the whole sample box of the workload)."""
     p = _abi.laue_index_params()
     pl = preset_like
-    p.mode = _abi.LAUE_INDEX_LEARNED if mode == "learned" else _abi.LAUE_INDEX_PLAIN
+    p.mode = {"plain": _abi.LAUE_INDEX_PLAIN, "learned": _abi.LAUE_INDEX_LEARNED,
+              "sobol": _abi.LAUE_INDEX_SOBOL}[mode]
+    if mode == "sobol":
+        p.sobol = sobol if sobol is not None else sobol_params(
+            (pl.radius_mm, pl.radius_mm, 0.5 * pl.height_mm))
     n_pairs = int(n_pairs if n_pairs is not None else 8192)
     p.cand = _abi.laue_cand_params(n_pairs, int(seed), float(delta_deg), None, None)
     p.max_candidates = int(max_candidates if max_candidates is not None else 64 * n_pairs)

@@ -126,13 +126,20 @@ class laue_adam_params(C.Structure):
 
 LAUE_INDEX_PLAIN = 0
 LAUE_INDEX_LEARNED = 1
+LAUE_INDEX_SOBOL = 2
+
+
+class laue_sobol_params(C.Structure):
+    _fields_ = [("first", C.c_int64), ("mrp_half", C.c_double), ("x_half", C.c_double * 3),
+                ("restrict_fz", C.c_int32)]
 
 
 class laue_index_params(C.Structure):
     _fields_ = [("mode", C.c_int32), ("cand", laue_cand_params), ("max_candidates", C.c_int64),
                 ("mlp", C.POINTER(laue_mlp)), ("support", laue_support_params), ("top_frac", C.c_double),
                 ("score", laue_score_params), ("lbar_cap", C.c_int64), ("k_max", C.c_int32),
-                ("max_model_spots", C.c_int64), ("t_b_frac", C.c_double), ("em", laue_em_params)]
+                ("max_model_spots", C.c_int64), ("t_b_frac", C.c_double), ("em", laue_em_params),
+                ("sobol", laue_sobol_params)]
 
 
 class laue_index_stats(C.Structure):
@@ -213,6 +220,8 @@ SIGNATURES = {
                              P(laue_index_out), P(laue_index_stats), vp, C.c_size_t, vp]),
     "laue_em_batched_workspace_size": (C.c_size_t, [C.c_int32, P(laue_geometry), vp, vp, vp]),
     "laue_sparse_workspace_size": (C.c_size_t, [C.c_int32, P(laue_geometry), vp, vp, vp, C.c_int32]),
+    "laue_sobol_workspace_size": (C.c_size_t, [C.c_int64]),
+    "laue_sobol_starts": (C.c_int, [P(laue_sobol_params), C.c_int64, vp, vp, P(C.c_int64), vp, C.c_size_t, vp]),
     "laue_sparse_neighbors": (C.c_int, [P(laue_geometry), P(laue_obs_spots), P(laue_model_spots), P(laue_ot_params),
                                         vp, vp, P(C.c_int64), vp, C.c_size_t, vp]),
     "laue_em_batched": (C.c_int, [C.c_int32, P(laue_geometry), P(laue_planes), P(laue_obs_spots),

@@ -15,7 +15,7 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SOURCES = ["api.hip", "forward.hip", "em.hip", "index.hip", "mlp.hip", "proposal.hip", "pipeline.hip"]
+SOURCES = ["api.hip", "forward.hip", "em.hip", "index.hip", "mlp.hip", "proposal.hip", "pipeline.hip", "sobol.hip"]
 LIB = os.path.join(HERE, "liblaueot.so")
 ARCH = os.environ.get("LAUE_OFFLOAD_ARCH", "gfx950")
 

@@ -1,5 +1,6 @@
 // End-to-end indexing (the multigrain solve of Sec. 6 and Alg. MultiGrainLaueOT
-// with spot-pair candidates in place of the orientation grid):
+// with spot-pair candidates in place of the orientation grid, or with the
+// Sobol-grid starts of Sec. 6.1):
 //   candidates -> [learned: support features, network, top fraction] ->
 //   single-grain refinement and scoring -> greedy SPOT -> k* prototypes ->
 //   model spots of the prototypes (frozen) -> EM with annealed entropic OT.
@@ -55,6 +56,7 @@ size_t scratch_size(const laue_geometry *g, int n_planes, int64_t n_obs, const l
         s = std::max(s, laue_mlp_forward_workspace_size(p->max_candidates));
         s = std::max(s, laue_select_top_workspace_size(p->max_candidates));
     }
+    if (p->mode == LAUE_INDEX_SOBOL) s = std::max(s, laue_sobol_workspace_size(p->max_candidates));
     s = std::max(s, laue_score_workspace_size(g, &p->score));
     s = std::max(s, laue_spot_greedy_workspace_size(static_cast<int32_t>(n_scored_max(p)), n_obs));
     s = std::max(s, laue_forward_workspace_size(g, n_planes, p->k_max));
@@ -130,7 +132,8 @@ __global__ void k_zero_f(float *p, int64_t n) {
 
 int validate_index_params(const laue_index_params *p) {
     LAUE_REQUIRE(p, LAUE_EINVAL, "NULL index parameters");
-    LAUE_REQUIRE(p->mode == LAUE_INDEX_PLAIN || p->mode == LAUE_INDEX_LEARNED, LAUE_EINVAL, "bad index mode");
+    LAUE_REQUIRE(p->mode == LAUE_INDEX_PLAIN || p->mode == LAUE_INDEX_LEARNED || p->mode == LAUE_INDEX_SOBOL,
+                 LAUE_EINVAL, "bad index mode");
     LAUE_REQUIRE(p->cand.pair_a == nullptr && p->cand.pair_b == nullptr, LAUE_EINVAL,
                  "indexing draws its own pairs");
     LAUE_REQUIRE(p->max_candidates >= 1 && p->max_candidates < (int64_t(1) << 31), LAUE_EINVAL,
@@ -199,9 +202,17 @@ extern "C" int laue_index(const laue_geometry *geom, const laue_planes *planes, 
     cand.spot_b = w.sb;
     cand.feat = w.feat;
     int64_t n_found = 0;
-    if ((rc = laue_candidates_generate(geom, planes, obs, &par->cand, &cand, &n_found, w.scratch, w.scratch_bytes,
-                                       stream)))
+    const bool sobol = par->mode == LAUE_INDEX_SOBOL;
+    if (sobol) {
+        // Sobol-grid starts (Sec. 6.1) straight into the scored grains
+        if ((rc = laue_sobol_starts(&par->sobol, par->max_candidates, w.gq, w.gx, &n_found, w.scratch,
+                                    w.scratch_bytes, stream)))
+            return rc;
+        cand.n = n_found;
+    } else if ((rc = laue_candidates_generate(geom, planes, obs, &par->cand, &cand, &n_found, w.scratch,
+                                              w.scratch_bytes, stream))) {
         return rc;
+    }
     st.n_candidates = cand.n;
     st.n_candidates_found = n_found;
     st.ms_candidates = ms_since(t0);
@@ -229,7 +240,7 @@ extern "C" int laue_index(const laue_geometry *geom, const laue_planes *planes, 
 
     // 3. single-grain refinement and scoring of the chosen candidates
     t0 = std::chrono::steady_clock::now();
-    if (n_sc > 0) {
+    if (n_sc > 0 && !sobol) {
         k_seed_grains<<<static_cast<unsigned>((n_sc + 255) / 256), 256, 0, s>>>(w.cq, sel, n_sc, w.gq, w.gx);
         LAUE_CHECK_HIP(hipGetLastError());
     }
