@@ -222,11 +222,13 @@ def bench_batching(laue, n_samples, n_stages, log):
             "launch_used": outs[0]["launch_used"], "identical_to_sequential": bool(same)}
 
 
-def bench_index(laue, workload, n_pairs, learned_pairs, log):
+def bench_index(laue, workload, n_pairs, learned_pairs, log, sobol_points=0):
     """Time to index from device-resident spots (laue_index): plain exhaustive
     scoring of the candidates of n_pairs spot pairs, against the learned
     proposal scoring the top 5% of the candidates of learned_pairs pairs, with
-    a network trained here on 10^6 simulated examples."""
+    a network trained here on 10^6 simulated examples, and (sobol_points > 0)
+    the paper's Sobol-grid starts over the cubic fundamental zone and the
+    sample box."""
     import torch
     import inputgen as ig
     from paper_2404_06478_amd import learned
@@ -253,9 +255,13 @@ def bench_index(laue, workload, n_pairs, learned_pairs, log):
     out = {"workload": workload, "grains": p.n_grains, "detected_spots": obs.n,
            "training": {"examples": int(feat.shape[0]), "positives": int(lab.sum().item()),
                         "data_s": t_data, "train_s": t_train, "epochs": 10, "final_loss": losses[-1]}}
-    for mode, pairs in (("plain", n_pairs), ("learned", learned_pairs)):
-        par = laue.index_params(p, mode, n_pairs=pairs, seed=1, mlp=net if mode == "learned" else None,
-                                support_radius=radius, n_obs=obs.n, n_planes=planes.n)
+    modes = [("plain", n_pairs), ("learned", learned_pairs)] + ([("sobol", sobol_points)] if sobol_points else [])
+    for mode, pairs in modes:
+        if mode == "sobol":
+            par = laue.index_params(p, "sobol", max_candidates=pairs, n_obs=obs.n, n_planes=planes.n)
+        else:
+            par = laue.index_params(p, mode, n_pairs=pairs, seed=1, mlp=net if mode == "learned" else None,
+                                    support_radius=radius, n_obs=obs.n, n_planes=planes.n)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         g, st, _ = laue.laue_index(geom, planes, obs, par, assign=False)
@@ -263,11 +269,13 @@ def bench_index(laue, workload, n_pairs, learned_pairs, log):
         wall = time.perf_counter() - t0
         qg, xg = g.numpy()
         r = recall(qg[:g.n], xg[:g.n], q, x)
-        out[mode] = {"pairs": pairs, "candidates": st["n_candidates"], "scored": st["n_scored"],
+        out[mode] = {("sobol_points" if mode == "sobol" else "pairs"): pairs, "candidates": st["n_candidates"],
+                     "scored": st["n_scored"],
                      "prototypes": st["n_prototypes"], "recall": r / len(q), "time_s": wall,
                      "stage_ms": {k: st[k] for k in ("ms_candidates", "ms_proposal", "ms_score", "ms_greedy",
                                                      "ms_em")}}
-        log(f"index: {mode}: {pairs} pairs, {st['n_scored']} scored, recall {r}/{len(q)}, {wall:.2f} s")
+        log(f"index: {mode}: {pairs} {'points' if mode == 'sobol' else 'pairs'}, {st['n_scored']} scored, "
+            f"recall {r}/{len(q)}, {wall:.2f} s")
     return out
 
 
@@ -484,9 +492,9 @@ def main():
     ap.add_argument("--unbalanced-workload", default="medium", choices=["medium", "learned", "stress"])
     ap.add_argument("--no-mstep-methods", action="store_true")
     ap.add_argument("--batch-samples", type=int, default=64)
-    ap.add_argument("--index-workloads", default="medium:4096,learned:1024",
-                    help="comma-separated workload:pairs; plain scoring takes the candidates of that many "
-                         "spot pairs, the learned proposal of 8x as many (top 5%% scored)")
+    ap.add_argument("--index-workloads", default="medium:4096:200000,learned:1024",
+                    help="workload:pairs[:sobol_points] items; plain scoring of the pairs' candidates, the learned "
+                         "proposal on 8x the pairs, and the Sobol-grid starts when sobol_points > 0")
     ap.add_argument("--tile", type=int, default=0, choices=[0, 1, 2],
                     help="Sinkhorn tile shape: 1 or 2 spots per lane, 0 tuned per call")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -603,8 +611,10 @@ def main():
     if not args.no_index:
         line["time_to_index"] = {}
         for item in args.index_workloads.split(","):
-            wl, pairs = item.split(":")
-            line["time_to_index"][wl] = bench_index(laue, wl, int(pairs), 8 * int(pairs), log)
+            parts = item.split(":")
+            wl, pairs = parts[0], int(parts[1])
+            sob = int(parts[2]) if len(parts) > 2 else 0
+            line["time_to_index"][wl] = bench_index(laue, wl, pairs, 8 * pairs, log, sobol_points=sob)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(preset)
     print(json.dumps(line), flush=True)
