@@ -364,8 +364,9 @@ typedef struct laue_em_params {
     int32_t launch;
     /* tile shape of the Sinkhorn passes: 1 one detected (model) spot per lane,
      * 2 two per lane sharing each streamed load, 0 tune per temperature stage
-     * (the first row + column pass of a stage's Sinkhorns is timed in each
-     * shape and the faster kept); every shape gives the same result */
+     * (in the first Sinkhorn of a stage, row pass 2 is timed in shape 1 and
+     * row pass 3 in shape 2, and the faster kept; shape 1 when a sample
+     * converges within those iterations); every shape gives the same result */
     int32_t tile;
 } laue_em_params;
 

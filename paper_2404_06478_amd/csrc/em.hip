@@ -12,7 +12,9 @@
 //   control         SinkCtl (ws)     bin potentials, iteration, flags
 // A pass is a grid of one-wave workgroups; each owns 64 rows (row pass) or
 // 64 columns (column pass) of one (rotation, detector) block and streams the
-// other side of that block through scalar loads, so the |I_b| x |J_b| cost
+// other side of that block through LDS, 64 spots at a time (each lane loads
+// one, every lane then reads each one by a broadcast LDS load, so the entry
+// arithmetic has vector-register operands only), so the |I_b| x |J_b| cost
 // block is recomputed on the fly and never stored.
 //
 // Batching: every sample has a descriptor (its arrays, bins, temperature and
@@ -167,8 +169,7 @@ __device__ __forceinline__ bool last_block(SinkCtl *ctl, int n_items) {
 }
 
 // Pointers read from a descriptor are generic; the pass bodies take the hot
-// arrays as global-address-space, restrict-qualified parameters so that the
-// wave-uniform streams (columns, potentials) compile to scalar loads.
+// arrays as global-address-space, restrict-qualified parameters.
 #define LAUE_GLOBAL __attribute__((address_space(1)))
 template <class T>
 __device__ __forceinline__ LAUE_GLOBAL T *gptr(T *p) {
@@ -321,12 +322,11 @@ __device__ __forceinline__ void col_finalize(SinkCtl *__restrict__ ctl, const do
 // state k-1 (its error is the convergence test) and f_i^k = f_i^{k-1} -
 // eps ln S_i.  The sample's last workgroup updates its bin potentials and
 // decides its convergence.
-// The pass bodies take the sample's arrays as restrict-qualified parameters:
-// inlined into the kernels they keep their no-alias scopes, so the
-// wave-uniform streams (columns, potentials) stay scalar loads.
+// The block's columns come through LDS in chunks of 64 (double-buffered, the
+// next chunk's global loads in flight while a chunk is summed).
 // Tile shapes: R = 1 (one detected spot per lane, 64-row workgroups) or
 // R = 2 (two adjacent 64-row items of one block per workgroup, two rows per
-// lane sharing every column load).  Each 64-row item keeps its own partial and
+// lane sharing every column read).  Each 64-row item keeps its own partial and
 // per-row arithmetic, so both shapes give identical results; the sample's
 // ticket counts the workgroups of the launched shape (n_wg), its finalisation
 // sums the partials of all 64-row items (n_items).
@@ -363,22 +363,46 @@ __device__ __forceinline__ void row_pass(const Item *its, const LAUE_GLOBAL floa
         fk[r] = p.part ? static_cast<float>(ctl->H * kexp) : f[r] * kx;
         acc[r] = 0.0;
     }
-    for (int j0 = c0; j0 < c1; j0 += 64) {
-        const int j1 = min(j0 + 64, c1);
-        float a[R];
-#pragma unroll
-        for (int r = 0; r < R; ++r) a[r] = 0.0f;
-#pragma unroll 4
-        for (int j = j0; j < j1; ++j) {
-            const Col8 c = ld_col(cols + j);
-            const float gj = G[j];
-#pragma unroll
-            for (int r = 0; r < R; ++r)
-                a[r] += fast_exp2(entry_exponent(p1[r], p2[r], c.s1, c.s2, c.v1, c.v2, c.vv, c.vv2, K,
-                                                 fmaf(gj, kx, fk[r])));
+    {
+        // 64 columns at a time through LDS (lane t loads column j0 + t, the
+        // next chunk's load in flight while this one is summed); every lane
+        // then reads each column by a broadcast LDS load, so the entry
+        // arithmetic takes vector-register operands only
+        __shared__ float4 lc[2][64][2];
+        const int lane = static_cast<int>(threadIdx.x);
+        float4 na = make_float4(0.0f, 0.0f, 0.0f, 0.0f), nb = na;
+        if (c0 + lane < c1) {
+            const Col8 c = ld_col(cols + c0 + lane);
+            na = make_float4(c.s1, c.s2, c.v1, c.v2);
+            nb = make_float4(c.vv, c.vv2, G[c0 + lane], 0.0f);
         }
+        int buf = 0;
+        for (int j0 = c0; j0 < c1; j0 += 64) {
+            const int nj = min(64, c1 - j0);
+            lc[buf][lane][0] = na;
+            lc[buf][lane][1] = nb;
+            __syncthreads();
+            const int jn = j0 + 64 + lane;
+            if (jn < c1) {
+                const Col8 c = ld_col(cols + jn);
+                na = make_float4(c.s1, c.s2, c.v1, c.v2);
+                nb = make_float4(c.vv, c.vv2, G[jn], 0.0f);
+            }
+            float a[R];
 #pragma unroll
-        for (int r = 0; r < R; ++r) acc[r] += static_cast<double>(a[r]);
+            for (int r = 0; r < R; ++r) a[r] = 0.0f;
+#pragma unroll 4
+            for (int t = 0; t < nj; ++t) {
+                const float4 A = lc[buf][t][0], B = lc[buf][t][1];
+#pragma unroll
+                for (int r = 0; r < R; ++r)
+                    a[r] += fast_exp2(entry_exponent(p1[r], p2[r], A.x, A.y, A.z, A.w, B.x, B.y, K,
+                                                     fmaf(B.z, kx, fk[r])));
+            }
+#pragma unroll
+            for (int r = 0; r < R; ++r) acc[r] += static_cast<double>(a[r]);
+            buf ^= 1;
+        }
     }
     double eb[R], logS[R];
     bool slow[R], any_slow = false;
@@ -460,33 +484,45 @@ __global__ __launch_bounds__(64) void k_row(const Item *__restrict__ items, cons
 
 // Column half of iteration k = iter for 64 model spots of one block (R = 2:
 // two adjacent 64-column items per workgroup, two columns per lane sharing
-// every row load): each lane streams the block's detected spots (wave-uniform
-// scalar loads) with
+// every row read): each lane streams the block's detected spots (through
+// LDS, 64 at a time) with
 // g_j^{k-1} as shift (terms are entries of the plan after the row half, <= 1)
 // and sets g_j^k = g_j^{k-1} - eps ln(column marginal).  The sample's last
 // workgroup stores sum_j exp((f0 + g_j - c_unm)/eps) for the next row half.
-// Column sums of R adjacent 64-column items over the block's rows, with the
-// row potentials F as a restrict-qualified stream (scalar loads).
+// Column sums of R adjacent 64-column items over the block's rows (p1, p2 and
+// the row potentials F staged through LDS).
 template <int R>
 __device__ __forceinline__ void col_sums(const LAUE_GLOBAL float *__restrict__ P1,
                                          const LAUE_GLOBAL float *__restrict__ P2,
                                          const LAUE_GLOBAL float *__restrict__ F, int r0, int r1, const Col8 *c,
                                          const float *gk, float K, float kx, double *acc) {
+    // 64 rows at a time through LDS (p1, p2, f of row i0 + lane), read back
+    // by broadcast LDS loads: vector-register operands only
+    __shared__ float4 lr[2][64];
+    const int lane = static_cast<int>(threadIdx.x);
+    float4 nx = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    if (r0 + lane < r1) nx = make_float4(P1[r0 + lane], P2[r0 + lane], F[r0 + lane], 0.0f);
+    int buf = 0;
     for (int i0 = r0; i0 < r1; i0 += 64) {
-        const int i1 = min(i0 + 64, r1);
+        const int ni = min(64, r1 - i0);
+        lr[buf][lane] = nx;
+        __syncthreads();
+        const int in = i0 + 64 + lane;
+        if (in < r1) nx = make_float4(P1[in], P2[in], F[in], 0.0f);
         float a[R];
 #pragma unroll
         for (int r = 0; r < R; ++r) a[r] = 0.0f;
 #pragma unroll 4
-        for (int i = i0; i < i1; ++i) {
-            const float pi1 = P1[i], pi2 = P2[i], fi = F[i];
+        for (int t = 0; t < ni; ++t) {
+            const float4 X = lr[buf][t];
 #pragma unroll
             for (int r = 0; r < R; ++r)
-                a[r] += fast_exp2(entry_exponent(pi1, pi2, c[r].s1, c[r].s2, c[r].v1, c[r].v2, c[r].vv, c[r].vv2, K,
-                                                 fmaf(fi, kx, gk[r])));
+                a[r] += fast_exp2(entry_exponent(X.x, X.y, c[r].s1, c[r].s2, c[r].v1, c[r].v2, c[r].vv, c[r].vv2,
+                                                 K, fmaf(X.z, kx, gk[r])));
         }
 #pragma unroll
         for (int r = 0; r < R; ++r) acc[r] += static_cast<double>(a[r]);
+        buf ^= 1;
     }
 }
 
@@ -1673,7 +1709,7 @@ struct BatchEngine {
     int tile_mode = 1;
     std::vector<int> stage_tile;
     std::vector<int> tiles_used;
-    hipEvent_t tev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+    hipEvent_t tev[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
 
     ~BatchEngine() {
         if (!graphs.empty()) (void)hipStreamSynchronize(s);
@@ -2158,34 +2194,43 @@ struct BatchEngine {
         int cap = 0;
         for (int k = 0; k < n; ++k) cap = std::max(cap, hd[k].sp.n_max);
         // tile shape of this Sinkhorn.  Tuning (the first Sinkhorn of a stage)
-        // times row pass 1 in the one-per-lane shape and row pass 2 in the
-        // two-per-lane shape: both always run in full (convergence is decided
-        // at the end of a row pass from iteration 2 on), and the stage keeps
-        // the faster shape.
+        // times row pass 2 in the one-per-lane shape and row pass 3 in the
+        // two-per-lane shape, and the stage keeps the faster one.
         const int si = std::max(stage, 0);
         if (si >= static_cast<int>(stage_tile.size())) stage_tile.resize(si + 1, 0);
         int launched = 0;
         if (tile_mode == 0 && stage_tile[si] == 0 && rho == 0) {
             if (!tev[0])
                 for (auto &e : tev) LAUE_CHECK_HIP(hipEventCreate(&e));
+            // iteration 1 untimed (after a warm start it can take the slow
+            // underflow path), then row pass 2 in shape 1 and row pass 3 in
+            // shape 2 timed; if a sample converges within the three
+            // iterations the later timing is not a full pass: keep shape 1
             LAUE_CHECK_HIP(hipEventRecord(tev[0], s));
             row_launch(s, 1);
-            LAUE_CHECK_HIP(hipEventRecord(tev[1], s));
             col_launch(s, 1);
+            LAUE_CHECK_HIP(hipEventRecord(tev[1], s));
+            row_launch(s, 1);
             LAUE_CHECK_HIP(hipEventRecord(tev[2], s));
-            row_launch(s, 2);
+            col_launch(s, 1);
             LAUE_CHECK_HIP(hipEventRecord(tev[3], s));
-            col_launch(s, 2);
+            row_launch(s, 2);
             LAUE_CHECK_HIP(hipEventRecord(tev[4], s));
+            col_launch(s, 2);
+            LAUE_CHECK_HIP(hipEventRecord(tev[5], s));
             LAUE_CHECK_HIP(hipGetLastError());
-            LAUE_CHECK_HIP(hipEventSynchronize(tev[4]));
+            LAUE_CHECK_HIP(hipMemcpyAsync(hctl.data(), bw.ctl, n * sizeof(SinkCtl), hipMemcpyDeviceToHost, s));
+            LAUE_CHECK_HIP(hipEventSynchronize(tev[5]));
+            LAUE_CHECK_HIP(hipStreamSynchronize(s));
             float t1 = 0.0f, t2 = 0.0f, tall = 0.0f;
-            LAUE_CHECK_HIP(hipEventElapsedTime(&t1, tev[0], tev[1]));
-            LAUE_CHECK_HIP(hipEventElapsedTime(&t2, tev[2], tev[3]));
-            LAUE_CHECK_HIP(hipEventElapsedTime(&tall, tev[0], tev[4]));
+            LAUE_CHECK_HIP(hipEventElapsedTime(&t1, tev[1], tev[2]));
+            LAUE_CHECK_HIP(hipEventElapsedTime(&t2, tev[3], tev[4]));
+            LAUE_CHECK_HIP(hipEventElapsedTime(&tall, tev[0], tev[5]));
             sink_ms += tall;
-            stage_tile[si] = t2 < t1 ? 2 : 1;
-            launched = 2;
+            bool any_done = false;
+            for (int k = 0; k < n; ++k) any_done = any_done || hctl[k].done;
+            stage_tile[si] = (!any_done && t2 < t1) ? 2 : 1;
+            launched = 3;
         }
         const int R = rho > 0 ? 1 : (tile_mode ? tile_mode : std::max(stage_tile[si], 1));
         tiles_used.push_back(R);
