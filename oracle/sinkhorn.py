@@ -148,14 +148,15 @@ def objectives(P, f, g, f0, g0, eps, sigma_mm=None, distance=None):
     entropy H(Q) = -sum Q log Q, and (if sigma and D given) the paper-unit sEM
     objective <L,Q> + eps_p H(Q) with L = kappa - c / (2 sigma^2)."""
     Qb = plan_blocks(P, f, g, eps)
-    inl = sum(float(np.sum(q * c)) for q, c in zip(Qb, P.C))
+    # masked entries (c = +inf, sparse assignment) carry no mass: their terms are 0
+    inl = sum(float(np.sum(np.where(q > 0, q * np.where(np.isfinite(c), c, 0.0), 0.0))) for q, c in zip(Qb, P.C))
     q_i0 = np.exp((f + g0 - P.c_out) / eps)
     q_0j = np.exp((f0 + g - P.c_unm) / eps)
     q_00 = math.exp((f0 + g0 - P.c_sink) / eps)
     tot = inl + P.c_out * q_i0.sum() + P.c_unm * q_0j.sum() + P.c_sink * q_00
 
     def ent(qv, logq):
-        return -float(np.sum(qv * logq))
+        return -float(np.sum(np.where(qv > 0, qv * np.where(np.isfinite(logq), logq, 0.0), 0.0)))
     H = sum(ent(q, (f[P.row_off[b]:P.row_off[b + 1], None] + g[None, P.col_off[b]:P.col_off[b + 1]] - P.C[b]) / eps)
             for b, q in enumerate(Qb))
     H += ent(q_i0, (f + g0 - P.c_out) / eps) + ent(q_0j, (f0 + g - P.c_unm) / eps)

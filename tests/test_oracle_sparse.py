@@ -115,3 +115,21 @@ def test_sparse_em_noise_free_exact_recovery():
                  cost.c_out(p.sigma_mm, p.distance), t_b=sinkhorn.default_tb(len(model["m"]), 0.1), rho=4)
     assert np.max(np.degrees(metrics.misorientation(res["q"], q))) < 1e-6
     assert np.max(np.linalg.norm(res["x"] - x, axis=1)) < 1e-6
+
+
+def test_objectives_count_kept_entries_only():
+    """The plan summaries of a masked problem sum over the kept entries (and
+    the bins) only: the masked entries' 0 * inf terms are 0."""
+    rng = np.random.default_rng(7)
+    C = _blocks(rng, [(6, 7), (4, 3)])
+    P = sparse.masked_problem(sinkhorn.Problem(C, 9.0, 0.0, 9.0, 2.0), 2)
+    s = sinkhorn.solve(P, 1.5, tol=1e-10, n_max=10000)
+    o = sinkhorn.objectives(P, s["f"], s["g"], s["f0"], s["g0"], 1.5)
+    Q = sinkhorn.plan_blocks(P, s["f"], s["g"], 1.5)
+    inl = 0.0
+    for q, Cd, Cm in zip(Q, C, P.C):
+        kept = np.isfinite(Cm)
+        inl += float(np.sum(q[kept] * Cd[kept]))
+        assert np.all(q[~kept] == 0.0)
+    assert np.isfinite(o["cost_inlier"]) and o["cost_inlier"] == pytest.approx(inl, rel=1e-12)
+    assert np.isfinite(o["entropy"]) and o["mass"] == pytest.approx(P.I + P.t_b, rel=1e-9)
