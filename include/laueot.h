@@ -294,6 +294,24 @@ int laue_sinkhorn(const laue_geometry *geom, const laue_obs_spots *obs,
                   laue_potentials *pot, laue_ot_stats *stats,
                   void *ws, size_t ws_bytes, void *stream);
 
+/* FP64 summaries of the plan of (pot, par->eps) and its bins (Eqs. elbo,
+ * estep_obj): mass (every entry, bins included), cost_inlier = <c, Q> over
+ * the detected x model entries, cost_total with the bin entries at c_out,
+ * c_unm, c_sink, entropy = -sum Q ln Q, and sem_objective = kappa * mass -
+ * cost_total / (2 sigma^2) + eps / (2 sigma^2) * entropy with
+ * kappa = (D / sigma)^2, the paper's log-likelihood objective in its units
+ * (outlier row and column only; NaN for unbalanced and partial OT, whose
+ * plans have no bins).  Under the sparse assignment only kept entries count.
+ * Host output; synchronous.  Workspace as laue_sinkhorn. */
+typedef struct laue_objective {
+    double mass, cost_inlier, cost_total, entropy, sem_objective;
+} laue_objective;
+
+int laue_objectives(const laue_geometry *geom, const laue_obs_spots *obs,
+                    const laue_model_spots *model, const laue_ot_params *par,
+                    const laue_potentials *pot, double sigma_mm, laue_objective *out,
+                    void *ws, size_t ws_bytes, void *stream);
+
 /* Dense plan block b: Q[i][j] = exp((f_i + g_j - c_ij)/eps) for the
  * detected x model spots of block b, row-major FP32 [I_b][J_b] (device).
  * For tests and small problems. */

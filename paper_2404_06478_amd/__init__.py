@@ -335,6 +335,18 @@ def laue_sinkhorn(geom, obs, model, ot, f, g, f0=0.0, g0=0.0):
     return pot.f0, pot.g0, {"n_iter": st.n_iter, "converged": bool(st.converged), "err": st.err}, rc
 
 
+def laue_objectives(geom, obs, model, ot, f, g, f0, g0, sigma_mm):
+    """FP64 plan summaries (dict: mass, cost_inlier, cost_total, entropy, sem_objective)."""
+    lib = require_native()
+    ws = _workspace(_ws_size(geom, obs.n, model.n, 0, ot.rho))
+    pot = laue_potentials(f.data_ptr(), g.data_ptr(), float(f0), float(g0))
+    out = _abi.laue_objective()
+    o, m = obs.struct(), model.struct()
+    _check(lib.laue_objectives(C.byref(geom), C.byref(o), C.byref(m), C.byref(ot), C.byref(pot), float(sigma_mm),
+                               C.byref(out), _ptr(ws), ws.numel(), _stream()))
+    return {name: getattr(out, name) for name, _ in _abi.laue_objective._fields_}
+
+
 def laue_plan_block(geom, obs, model, ot, f, g, block):
     import torch
     lib = require_native()

@@ -61,6 +61,11 @@ class laue_potentials(C.Structure):
     _fields_ = [("f", vp), ("g", vp), ("f0", C.c_double), ("g0", C.c_double)]
 
 
+class laue_objective(C.Structure):
+    _fields_ = [("mass", C.c_double), ("cost_inlier", C.c_double), ("cost_total", C.c_double),
+                ("entropy", C.c_double), ("sem_objective", C.c_double)]
+
+
 class laue_ot_stats(C.Structure):
     _fields_ = [("n_iter", C.c_int32), ("converged", C.c_int32), ("err", C.c_double)]
 
@@ -221,6 +226,8 @@ SIGNATURES = {
     "laue_em_batched_workspace_size": (C.c_size_t, [C.c_int32, P(laue_geometry), vp, vp, vp]),
     "laue_sparse_workspace_size": (C.c_size_t, [C.c_int32, P(laue_geometry), vp, vp, vp, C.c_int32]),
     "laue_sobol_workspace_size": (C.c_size_t, [C.c_int64]),
+    "laue_objectives": (C.c_int, [P(laue_geometry), P(laue_obs_spots), P(laue_model_spots), P(laue_ot_params),
+                                  P(laue_potentials), C.c_double, P(laue_objective), vp, C.c_size_t, vp]),
     "laue_sobol_starts": (C.c_int, [P(laue_sobol_params), C.c_int64, vp, vp, P(C.c_int64), vp, C.c_size_t, vp]),
     "laue_sparse_neighbors": (C.c_int, [P(laue_geometry), P(laue_obs_spots), P(laue_model_spots), P(laue_ot_params),
                                         vp, vp, P(C.c_int64), vp, C.c_size_t, vp]),

@@ -1507,6 +1507,7 @@ struct SampleWs {
     GrainF *grains;
     int *gflag;
     float *rmass, *cmass;
+    double *obj;                   // objective partials (4 per work item) and totals
     int64_t *mboff;
     // sparse assignment (rho > 0)
     int *nbr = nullptr, *cand_j = nullptr, *cand_n = nullptr, *knn_list = nullptr, *knn_nlist = nullptr;
@@ -1546,6 +1547,7 @@ static size_t carve_all(Carver &cv, BatchWs &bw, std::vector<SampleWs> &sw, cons
         const int nb = d.geom->n_rot * d.geom->n_det;
         SampleWs &w = sw[s];
         w.part = cv.take<double2>(n_items_max(d.n_obs, d.n_model, nb));
+        w.obj = cv.take<double>(4 * n_items_max(d.n_obs, d.n_model, nb) + 8);
         w.F1 = cv.take<float>(std::max<int64_t>(d.n_obs, 1));
         w.colsE = cv.take<Col8>(std::max<int64_t>(d.n_model, 1));
         w.colsC = cv.take<Col8>(std::max<int64_t>(d.n_model, 1));
@@ -2430,6 +2432,137 @@ extern "C" size_t laue_em_batched_workspace_size(int32_t n, const laue_geometry 
     return carve_all(cv, bw, sw, dims_of(n, geoms, n_obs, n_model, n_grains));
 }
 
+// ---------------------------------------------------------------- objectives
+
+// Sums of the plan Q = exp((f + g - c)/eps) with its bins (Eqs. elbo,
+// estep_obj): per 64-row item, lane = detected spot, over its block's model
+// spots (or its neighbours under the sparse assignment) and its outlier entry
+// q_i0: mass, <c, Q> over the matches, the outlier entries' cost and
+// sum Q ln Q; per 64-column item the unmatched entries q_0j.  Each item's
+// four sums go to obj[4 local + k]; k_obj_final adds them in item order.
+struct ObjArgs {
+    double eps, f0, g0;
+    double *obj;                   // [4 * (row items + column items) + 8]
+};
+
+__global__ __launch_bounds__(64) void k_obj_rows(const Item *__restrict__ items, const SampleDesc *__restrict__ descs,
+                                                 ObjArgs A) {
+    const Item it = items[blockIdx.x];
+    const SampleDesc &D = descs[it.s];
+    const SinkParams p = D.sp;
+    const double kexp = 1.4426950408889634 / A.eps;
+    const float kx = static_cast<float>(kexp);
+    const float K = p.twoD2 * kx;
+    const int i = it.r0 + static_cast<int>(threadIdx.x);
+    const bool act = i < it.r1;
+    const float p1 = act ? D.p1[i] : 0.0f, p2 = act ? D.p2[i] : 0.0f, f = act ? D.f[i] : 0.0f;
+    const float fk = f * kx;
+    double m = 0.0, cin = 0.0, cb = 0.0, ql = 0.0;
+    float am = 0.0f, ac = 0.0f, al = 0.0f;
+    if (act) {
+        if (D.rho > 0) {
+            for (int q = 0; q < D.rho; ++q) {
+                const int j = D.nbr[q * D.n_obs + i];
+                if (j < 0) continue;
+                const float cp = D.ncp[q * D.n_obs + i];
+                const float e = fmaf(-K, cp, fmaf(D.g[j], kx, fk));
+                const float Q = fast_exp2(e);
+                if (Q > 0.0f) {
+                    am += Q;
+                    ac = fmaf(Q, p.twoD2 * cp, ac);
+                    al = fmaf(Q, e, al);
+                }
+            }
+        } else {
+            for (int j = it.c0; j < it.c1; ++j) {
+                const Col8 c = D.colsE[j];
+                const float cp = chord_cp(p1, p2, c.s1, c.s2, c.v1, c.v2, c.vv, c.vv2);
+                const float e = fmaf(-K, cp, fmaf(D.g[j], kx, fk));
+                const float Q = fast_exp2(e);
+                if (Q > 0.0f) {
+                    am += Q;
+                    ac = fmaf(Q, p.twoD2 * cp, ac);
+                    al = fmaf(Q, e, al);
+                }
+            }
+        }
+        m = static_cast<double>(am);
+        cin = static_cast<double>(ac);
+        ql = static_cast<double>(al) * 0.6931471805599453;   // e is in log2 units
+        const double lb = (static_cast<double>(f) + A.g0 - p.c_out) / A.eps;
+        const double qb = exp(lb);
+        if (qb > 0.0) {
+            m += qb;
+            cb = p.c_out * qb;
+            ql += qb * lb;
+        }
+    }
+    m = wave_sum(m);
+    cin = wave_sum(cin);
+    cb = wave_sum(cb);
+    ql = wave_sum(ql);
+    if (threadIdx.x == 0) {
+        double *o = A.obj + 4 * static_cast<int64_t>(it.local);
+        o[0] = m;
+        o[1] = cin;
+        o[2] = cb;
+        o[3] = ql;
+    }
+}
+
+__global__ __launch_bounds__(64) void k_obj_cols(const Item *__restrict__ items, const SampleDesc *__restrict__ descs,
+                                                 ObjArgs A) {
+    const Item it = items[blockIdx.x];
+    const SampleDesc &D = descs[it.s];
+    const SinkParams p = D.sp;
+    const int j = it.c0 + static_cast<int>(threadIdx.x);
+    double m = 0.0, cb = 0.0, ql = 0.0;
+    if (j < it.c1) {
+        const double lb = (A.f0 + static_cast<double>(D.g[j]) - p.c_unm) / A.eps;
+        const double qb = exp(lb);
+        if (qb > 0.0) {
+            m = qb;
+            cb = p.c_unm * qb;
+            ql = qb * lb;
+        }
+    }
+    m = wave_sum(m);
+    cb = wave_sum(cb);
+    ql = wave_sum(ql);
+    if (threadIdx.x == 0) {
+        double *o = A.obj + 4 * (static_cast<int64_t>(D.n_row_items) + it.local);
+        o[0] = m;
+        o[1] = 0.0;
+        o[2] = cb;
+        o[3] = ql;
+    }
+}
+
+// totals in item order: out = (mass, <c,Q> matches, total cost, sum Q ln Q)
+__global__ __launch_bounds__(64) void k_obj_final(const SampleDesc *__restrict__ descs, ObjArgs A) {
+    const SampleDesc &D = descs[0];
+    const int n = D.n_row_items + D.n_col_items;
+    double t[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int w = threadIdx.x; w < n; w += 64)
+        for (int k = 0; k < 4; ++k) t[k] += A.obj[4 * static_cast<int64_t>(w) + k];
+    for (int k = 0; k < 4; ++k) t[k] = wave_sum(t[k]);
+    if (threadIdx.x != 0) return;
+    const SinkParams p = D.sp;
+    double mass = t[0], cin = t[1], ctot = t[1] + t[2], ql = t[3];
+    const double l00 = (A.f0 + A.g0 - p.c_sink) / A.eps;
+    const double q00 = exp(l00);
+    if (q00 > 0.0) {
+        mass += q00;
+        ctot += p.c_sink * q00;
+        ql += q00 * l00;
+    }
+    double *o = A.obj + 4 * static_cast<int64_t>(n);
+    o[0] = mass;
+    o[1] = cin;
+    o[2] = ctot;
+    o[3] = ql;
+}
+
 extern "C" int laue_sinkhorn(const laue_geometry *geom, const laue_obs_spots *obs,
                              const laue_model_spots *model, const laue_ot_params *par,
                              laue_potentials *pot, laue_ot_stats *stats, void *ws, size_t ws_bytes,
@@ -2450,6 +2583,45 @@ extern "C" int laue_sinkhorn(const laue_geometry *geom, const laue_obs_spots *ob
     *stats = os[0];
     LAUE_CHECK_HIP(hipStreamSynchronize(e.s));
     return stats->converged ? LAUE_OK : LAUE_ENOCONV;
+}
+
+extern "C" int laue_objectives(const laue_geometry *geom, const laue_obs_spots *obs,
+                               const laue_model_spots *model, const laue_ot_params *par,
+                               const laue_potentials *pot, double sigma_mm, laue_objective *out, void *ws,
+                               size_t ws_bytes, void *stream) {
+    clear_error();
+    int rc;
+    if ((rc = validate_ot(par, true))) return rc;
+    LAUE_REQUIRE(pot && out, LAUE_EINVAL, "potentials or output is NULL");
+    LAUE_REQUIRE(std::isfinite(sigma_mm) && sigma_mm > 0, LAUE_EINVAL, "sigma_mm must be > 0");
+    LAUE_REQUIRE(bins_ok(par, pot), LAUE_EINVAL, "bin potentials must be finite");
+    BatchEngine e;
+    laue_potentials p = *pot;           // read only
+    laue_model_spots *m = const_cast<laue_model_spots *>(model);
+    if ((rc = e.setup({SampleIn{geom, nullptr, obs, m, par, nullptr, &p, 0.0, nullptr, nullptr}}, ws, ws_bytes,
+                      stream, true)))
+        return rc;
+    if ((rc = launch_pack(model, e.sw[0].colsE, e.s))) return rc;
+    if ((rc = e.build_neighbors())) return rc;
+    const bool bins = par->outlier_model == 0;
+    ObjArgs A{par->eps, bins && par->t_b > 0 ? pot->f0 : -INFINITY,
+              bins && e.hd[0].sp.t_a > 0 ? pot->g0 : -INFINITY, e.sw[0].obj};
+    if (e.n_rows) k_obj_rows<<<e.n_rows, 64, 0, e.s>>>(e.bw.rows, e.bw.desc, A);
+    if (e.n_cols) k_obj_cols<<<e.n_cols, 64, 0, e.s>>>(e.bw.cols, e.bw.desc, A);
+    k_obj_final<<<1, 64, 0, e.s>>>(e.bw.desc, A);
+    LAUE_CHECK_HIP(hipGetLastError());
+    const int64_t n_items = static_cast<int64_t>(e.hd[0].n_row_items) + e.hd[0].n_col_items;
+    double t[4];
+    LAUE_CHECK_HIP(hipMemcpyAsync(t, e.sw[0].obj + 4 * n_items, sizeof(t), hipMemcpyDeviceToHost, e.s));
+    LAUE_CHECK_HIP(hipStreamSynchronize(e.s));
+    out->mass = t[0];
+    out->cost_inlier = t[1];
+    out->cost_total = t[2];
+    out->entropy = -t[3];
+    const double s2 = 2.0 * sigma_mm * sigma_mm;
+    const double kappa = (par->distance / sigma_mm) * (par->distance / sigma_mm);
+    out->sem_objective = bins ? kappa * t[0] - t[2] / s2 + par->eps / s2 * (-t[3]) : NAN;
+    return LAUE_OK;
 }
 
 __global__ void k_plan_soa(const float *__restrict__ P1, const float *__restrict__ P2,
