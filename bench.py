@@ -279,6 +279,95 @@ def bench_index(laue, workload, n_pairs, learned_pairs, log, sobol_points=0):
     return out
 
 
+def _per_grain(q, x, qg, xg):
+    mis = np.diag(misorientation_deg(q, qg))
+    dx = np.linalg.norm(np.asarray(x) - np.asarray(xg), axis=1)
+    return {"within_0.25deg_0.5mm": int(np.sum((mis <= 0.25) & (dx <= 0.5))),
+            "median_deg": float(np.median(mis)), "median_mm": float(np.median(dx))}
+
+
+def _geometric(e0, e1, n):
+    return [e0 * (e1 / e0) ** (k / max(n - 1, 1)) for k in range(n)]
+
+
+def bench_index_limits(laue, preset, log, n_random=9000):
+    """Where indexing at a spot density holds and where it breaks, on one
+    simulated sample: (i) the multi-grain EM started from the true grains, at
+    the schedule's first temperature (111 sigma^2, four iterations) and on a
+    cold schedule (3.51 -> 1.11 sigma^2, eight iterations); (ii) the EM from
+    the true grains turned by 0.5 deg and moved by 0.5 mm (7.9 -> 1.11 sigma^2,
+    twenty iterations); (iii) single-grain refinement and SPOT selection of
+    candidates made of those turned grains mixed with n_random random grains.
+    A grain counts when it ends within 0.25 deg and 0.5 mm of its own true
+    grain."""
+    import torch
+    import inputgen as ig
+    geom = laue.geometry_from_preset(preset)
+    planes = laue.laue_planes_cubic(preset.a, preset.centering, preset.n_max)
+    q, x = ig.random_grains(preset)
+    obs = laue.laue_simulate(geom, planes, laue.Grains(q, x), preset.sigma_mm, preset.distance,
+                             preset.outlier_frac, preset.seed)
+    s2 = preset.sigma_mm ** 2
+    c_out = _c_out(preset)
+    qt, xt = ig.perturb_grains(q, x, 0.5, 0.5, preset.seed + 17)
+    dev = torch.device("cuda", 0)
+    out = {"workload": preset.name, "grains": len(q), "detected_spots": obs.n}
+
+    def em(q0, x0, sched):
+        grains = laue.Grains(q0, x0)
+        model = laue.laue_forward_enumerate(geom, planes, grains, True)
+        t_b = float(math.ceil(0.4 * model.n))
+        f = torch.zeros(obs.n, dtype=torch.float32, device=dev)
+        g = torch.zeros(model.n, dtype=torch.float32, device=dev)
+        f0 = g0 = 0.0
+        for eps in sched:
+            ot = laue.ot_params(eps, preset.distance, c_out, t_b, tol=1e-5, n_max=2000)
+            o = laue.laue_em(geom, planes, obs, model, laue.em_params(ot, eps, eps, 1, 1, k_gn=2), grains, f, g,
+                             f0, g0, assign=False)
+            f0, g0 = o["f0"], o["g0"]
+        qg, xg = grains.numpy()
+        return dict(_per_grain(q, x, qg, xg), eps_mm2=[round(sched[0], 4), round(sched[-1], 4)],
+                    iterations=len(sched))
+
+    out["em_hot_from_truth"] = em(q, x, [111.0 * s2] * 4)
+    out["em_cold_from_truth"] = em(q, x, _geometric(3.51 * s2, 1.11 * s2, 8))
+    out["em_from_turned"] = em(qt, xt, _geometric(7.9 * s2, 1.11 * s2, 20))
+    log(f"index limits {preset.name}: EM from truth hot {out['em_hot_from_truth']['within_0.25deg_0.5mm']}, "
+        f"cold {out['em_cold_from_truth']['within_0.25deg_0.5mm']}, from 0.5 deg "
+        f"{out['em_from_turned']['within_0.25deg_0.5mm']} of {len(q)}")
+    qr, xr = ig.random_grains(preset, n=n_random, seed=preset.seed + 4242)
+    ng = len(q)
+    cand = laue.Grains(np.concatenate([qt, qr]), np.concatenate([xt, xr]))
+    phi = -c_out / (2.0 * s2)
+    r = laue.laue_score_candidates(geom, planes, obs, cand, laue.score_params(preset.sigma_mm, preset.distance,
+                                                                              c_out),
+                                   lbar_cap=min((1 << 31) - 1, 12_000 * (ng + n_random)))
+    rq, rx = cand.numpy()
+    refined = _per_grain(q, x, rq[:ng], rx[:ng])
+    ok = (np.diag(misorientation_deg(q, rq[:ng])) <= 0.25) & (np.linalg.norm(x - rx[:ng], axis=1) <= 0.5)
+    keep = r["keep"].cpu().numpy().astype(bool)
+    off = r["lbar_off"].cpu().numpy()
+    cs = np.concatenate([[0.0], np.cumsum(r["lbar_val"].cpu().numpy().astype(np.float64) - phi)])
+    col = cs[off[1:]] - cs[off[:-1]]
+    picks, gains = laue.laue_spot_greedy(r["lbar_off"], r["lbar_row"], r["lbar_val"], ng + n_random, obs.n, phi, ng)
+    pk = picks.cpu().numpy()
+    gn = gains.cpu().numpy()
+    drop = gn - np.append(gn[1:], 0.0)
+    out["selection"] = {
+        "candidates": {"turned_true": ng, "random": n_random}, "spot_entries": int(r["lbar_n"]),
+        "refined_turned": refined, "kept_turned": float(keep[:ng].mean()), "kept_random": float(keep[ng:].mean()),
+        "column_sum_turned_median": float(np.median(col[:ng])),
+        "column_sum_random_median": float(np.median(col[ng:])),
+        "column_sum_random_p99": float(np.percentile(col[ng:], 99)),
+        "first_picks": int(len(pk)), "picks_turned": int(np.sum(pk < ng)),
+        "picks_turned_within": int(np.sum(ok[pk[pk < ng]])), "k_star": int(np.argmax(drop)) + 1 if len(gn) else 0}
+    sel = out["selection"]
+    log(f"index limits {preset.name}: refined {refined['within_0.25deg_0.5mm']}/{ng}, kept turned "
+        f"{sel['kept_turned']:.2f} random {sel['kept_random']:.2f}, first {len(pk)} picks: {sel['picks_turned']} "
+        f"turned ({sel['picks_turned_within']} within), k* {sel['k_star']}")
+    return out
+
+
 def _em_schedule(preset):
     return [preset.eps_start * (preset.eps_end / preset.eps_start) ** (s / (preset.n_stages - 1))
             for s in range(preset.n_stages) for _ in range(preset.iters_per_stage)]
@@ -492,9 +581,11 @@ def main():
     ap.add_argument("--unbalanced-workload", default="medium", choices=["medium", "learned", "stress"])
     ap.add_argument("--no-mstep-methods", action="store_true")
     ap.add_argument("--batch-samples", type=int, default=64)
-    ap.add_argument("--index-workloads", default="medium:4096:200000,learned:1024",
+    ap.add_argument("--index-workloads", default="medium:4096:200000,learned:1024,learned_fiducial:2048",
                     help="workload:pairs[:sobol_points] items; plain scoring of the pairs' candidates, the learned "
                          "proposal on 8x the pairs, and the Sobol-grid starts when sobol_points > 0")
+    ap.add_argument("--index-limits", default="learned,learned_fiducial",
+                    help="workloads of the EM-from-truth and selection diagnostics ('' to skip)")
     ap.add_argument("--tile", type=int, default=0, choices=[0, 1, 2],
                     help="Sinkhorn tile shape: 1 or 2 spots per lane, 0 tuned per call")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -615,6 +706,10 @@ def main():
             wl, pairs = parts[0], int(parts[1])
             sob = int(parts[2]) if len(parts) > 2 else 0
             line["time_to_index"][wl] = bench_index(laue, wl, pairs, 8 * pairs, log, sobol_points=sob)
+    if args.index_limits:
+        import inputgen as ig
+        line["index_limits"] = {wl: bench_index_limits(laue, ig.PRESETS[wl], log)
+                                for wl in args.index_limits.split(",") if wl}
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(preset)
     print(json.dumps(line), flush=True)

@@ -82,9 +82,13 @@ MEDIUM = Preset("medium", 2.87, "I", 30, 1.0, 4.0, 100, 60, 3.0, 1.0, 0.30,
                 *_schedule(1.0), 5, 4, n_candidates=100_000, index=1)
 LEARNED = Preset("learned", 2.87, "I", 30, 1.0, 4.0, 1000, 60, 3.0, 1.0, 0.70,
                  *_schedule(1.0), 5, 4, n_candidates=1 << 20, index=3)
+# The learned-scale sample at the paper's fiducial noise and outlier level
+# (Sec. 7: sigma = 0.4 mm on the detector, outliers 10% of the spot count).
+LEARNED_FIDUCIAL = Preset("learned_fiducial", 2.87, "I", 30, 1.0, 4.0, 1000, 60, 3.0, 0.4, 0.10,
+                          *_schedule(0.4), 5, 4, index=5)
 STRESS = Preset("stress", 3.52, "F", 40, 0.8, 5.0, 2000, 90, 2.0, 1.5, 0.50,
                 *_schedule(1.5), 5, 4, index=4)
-PRESETS = {p.name: p for p in (TINY, MEDIUM, LEARNED, STRESS)}
+PRESETS = {p.name: p for p in (TINY, MEDIUM, LEARNED, LEARNED_FIDUCIAL, STRESS)}
 
 
 def batching_samples(n_samples=64, seed=BASE_SEED + 2):
