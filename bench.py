@@ -272,6 +272,8 @@ def bench_index(laue, workload, n_pairs, learned_pairs, log, sobol_points=0):
         out[mode] = {("sobol_points" if mode == "sobol" else "pairs"): pairs, "candidates": st["n_candidates"],
                      "scored": st["n_scored"],
                      "prototypes": st["n_prototypes"], "recall": r / len(q), "time_s": wall,
+                     "score_pairs": st["score_pairs"],
+                     "score_pairs_per_s": st["score_pairs"] / max(st["ms_score"] * 1e-3, 1e-12),
                      "stage_ms": {k: st[k] for k in ("ms_candidates", "ms_proposal", "ms_score", "ms_greedy",
                                                      "ms_em")}}
         log(f"index: {mode}: {pairs} {'points' if mode == 'sobol' else 'pairs'}, {st['n_scored']} scored, "

@@ -542,6 +542,8 @@ typedef struct laue_score_out {
     float *lbar_val;
     int64_t lbar_cap;
     int64_t lbar_n;
+    int64_t pairs_streamed;   /* (out) same-block (detected, model) pairs taken
+                               * through cost -> exp -> accumulate, all passes */
 } laue_score_out;
 
 size_t laue_score_workspace_size(const laue_geometry *geom, const laue_score_params *par);
@@ -735,6 +737,7 @@ typedef struct laue_index_stats {
     int64_t n_model_spots;
     double ms_candidates, ms_proposal, ms_score, ms_greedy, ms_em, ms_total;
     laue_em_stats em;
+    int64_t score_pairs;            /* pairs streamed by the scoring stage */
 } laue_index_stats;
 
 /* Output grains (device, capacity >= k_max; n_grains = k* on return) and the

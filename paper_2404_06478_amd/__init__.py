@@ -526,6 +526,7 @@ def laue_score_candidates(geom, planes, obs, cand, par, lbar_cap=None):
     res["lbar_row"] = out_t["lbar_row"][:so.lbar_n]
     res["lbar_val"] = out_t["lbar_val"][:so.lbar_n]
     res["lbar_n"] = so.lbar_n
+    res["pairs_streamed"] = so.pairs_streamed
     return res
 
 

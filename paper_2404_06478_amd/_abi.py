@@ -113,7 +113,8 @@ class laue_score_params(C.Structure):
 
 class laue_score_out(C.Structure):
     _fields_ = [("n_model", vp), ("n_unmatched", vp), ("keep", vp), ("lbar_off", vp),
-                ("lbar_row", vp), ("lbar_val", vp), ("lbar_cap", C.c_int64), ("lbar_n", C.c_int64)]
+                ("lbar_row", vp), ("lbar_val", vp), ("lbar_cap", C.c_int64), ("lbar_n", C.c_int64),
+                ("pairs_streamed", C.c_int64)]
 
 
 class laue_mlp(C.Structure):
@@ -152,7 +153,7 @@ class laue_index_stats(C.Structure):
                 ("lbar_entries", C.c_int64), ("n_picked", C.c_int32), ("n_prototypes", C.c_int32),
                 ("n_model_spots", C.c_int64), ("ms_candidates", C.c_double), ("ms_proposal", C.c_double),
                 ("ms_score", C.c_double), ("ms_greedy", C.c_double), ("ms_em", C.c_double),
-                ("ms_total", C.c_double), ("em", laue_em_stats)]
+                ("ms_total", C.c_double), ("em", laue_em_stats), ("score_pairs", C.c_int64)]
 
 
 class laue_index_out(C.Structure):

@@ -219,23 +219,31 @@ __global__ void k_ctl_init(const SampleDesc *__restrict__ descs, int n, const Ct
     ctl->ticket = 0u;
 }
 
-// cs_sum of the initial state: sum_j exp((f0 + g_j - c_unm)/eps); one
-// workgroup per sample, fixed summation order.
-__global__ __launch_bounds__(256) void k_cs_init(const SampleDesc *__restrict__ descs) {
-    const SampleDesc &D = descs[blockIdx.x];
-    SinkCtl *ctl = D.ctl;
+// cs_sum of the initial state: sum_j exp((f0 + g_j - c_unm)/eps).  One wave
+// per column item (up to 64 model spots) writes the item's partial; then one
+// wave per sample sums them in item order (fixed summation order, no
+// cross-wave atomics).
+__global__ __launch_bounds__(64) void k_cs_init(const Item *__restrict__ items,
+                                                const SampleDesc *__restrict__ descs) {
+    const Item it = items[blockIdx.x];
+    const SampleDesc &D = descs[it.s];
+    const SinkCtl *ctl = D.ctl;
     const double eps = ctl->eps, f0 = ctl->f0[0];
-    double s = 0.0;
-    for (int64_t j = threadIdx.x; j < D.n_model; j += 256)
-        s += exp((f0 + static_cast<double>(D.g[j]) - D.sp.c_unm) / eps);
-    __shared__ double part[256];
-    part[threadIdx.x] = s;
+    const int j = it.c0 + static_cast<int>(threadIdx.x);
+    double s = j < it.c1 ? exp((f0 + static_cast<double>(D.g[j]) - D.sp.c_unm) / eps) : 0.0;
+    s = wave_sum(s);
+    if (threadIdx.x == 0) D.part[it.local] = make_double2(s, 0.0);
+}
+
+__global__ __launch_bounds__(256) void k_cs_final(const SampleDesc *__restrict__ descs) {
+    const SampleDesc &D = descs[blockIdx.x];
+    __shared__ double ws[4];
+    double t = 0.0;
+    for (int w = threadIdx.x; w < D.n_col_items; w += 256) t += D.part[w].x;
+    t = wave_sum(t);
+    if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = t;
     __syncthreads();
-    if (threadIdx.x == 0) {
-        double t = 0.0;
-        for (int k = 0; k < 256; ++k) t += part[k];
-        ctl->cs_sum = t;
-    }
+    if (threadIdx.x == 0) D.ctl->cs_sum = ((ws[0] + ws[1]) + ws[2]) + ws[3];
 }
 
 // ---------------------------------------------------------------- row pass
@@ -760,17 +768,29 @@ __device__ __forceinline__ void mstep_pass(const Item &it, const SampleDesc &D,
     constexpr int NS = MstepMode<MODE>::N;
     double s64[NS];
     for (int k = 0; k < NS; ++k) s64[k] = 0.0;
+    // 64 rows at a time through LDS (p1, p2, f of row i0 + lane), read back
+    // by broadcast LDS loads, the next chunk's loads in flight meanwhile
+    __shared__ float4 lr[2][64];
+    const int lane = static_cast<int>(threadIdx.x);
+    float4 nx = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    if (it.r0 + lane < it.r1) nx = make_float4(P1[it.r0 + lane], P2[it.r0 + lane], F[it.r0 + lane], 0.0f);
+    int buf = 0;
     for (int i0 = it.r0; i0 < it.r1; i0 += 64) {
-        const int i1 = min(i0 + 64, it.r1);
+        const int ni = min(64, it.r1 - i0);
+        lr[buf][lane] = nx;
+        __syncthreads();
+        const int in = i0 + 64 + lane;
+        if (in < it.r1) nx = make_float4(P1[in], P2[in], F[in], 0.0f);
         float a[NS];
         for (int k = 0; k < NS; ++k) a[k] = 0.0f;
-        for (int i = i0; i < i1; ++i) {
-            const float p1 = P1[i], p2 = P2[i];
-            const float Q = fast_exp2(entry_exponent(p1, p2, cE.s1, cE.s2, cE.v1, cE.v2, cE.vv,
-                                                     cE.vv2, K, fmaf(F[i], kx, gk)));
-            if (Q > 0.0f) mode_acc<MODE>(a, Q, p1, p2, cC, vlen, rn, r1, r2);
+        for (int t = 0; t < ni; ++t) {
+            const float4 X = lr[buf][t];
+            const float Q = fast_exp2(entry_exponent(X.x, X.y, cE.s1, cE.s2, cE.v1, cE.v2, cE.vv,
+                                                     cE.vv2, K, fmaf(X.z, kx, gk)));
+            if (Q > 0.0f) mode_acc<MODE>(a, Q, X.x, X.y, cC, vlen, rn, r1, r2);
         }
         for (int k = 0; k < NS; ++k) s64[k] += static_cast<double>(a[k]);
+        buf ^= 1;
     }
     if (!act) return;
     mode_epilogue<MODE>(D, j, s64, rn, r1, r2);
@@ -2184,7 +2204,10 @@ struct BatchEngine {
             if (no > 0) k_fill_f<<<static_cast<unsigned>((no + 255) / 256), 256, 0, s>>>(in[k].pot->f, no, 0.0, 0);
             if (nm > 0) k_fill_f<<<static_cast<unsigned>((nm + 255) / 256), 256, 0, s>>>(in[k].pot->g, nm, 0.0, 0);
         }
-        k_cs_init<<<n, 256, 0, s>>>(bw.desc);
+        if (n_cols) {
+            k_cs_init<<<n_cols, 64, 0, s>>>(bw.cols, bw.desc);
+            k_cs_final<<<n, 256, 0, s>>>(bw.desc);
+        }
         LAUE_CHECK_HIP(hipGetLastError());
         if (chunk <= 0) {
             chunk = 16;

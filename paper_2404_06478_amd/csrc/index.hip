@@ -604,6 +604,25 @@ __global__ __launch_bounds__(64 * kGreedyWaves) void k_lazy_greedy(const int64_t
 }
 
 __global__ void k_set_i64(int64_t *p, int64_t v) { *p = v; }
+
+// Same-block (detected, model) pairs of one batch, added to *acc: over the
+// (block, candidate) slots, model spots of the slot times detected spots of
+// its block; keep (may be NULL) limits the sum to kept candidates.
+__global__ __launch_bounds__(256) void k_slot_pairs(const int64_t *__restrict__ offs,
+                                                    const int64_t *__restrict__ ooff, int nb, int C,
+                                                    const uint8_t *__restrict__ keep,
+                                                    unsigned long long *__restrict__ acc) {
+    unsigned long long t = 0;
+    const int64_t L = static_cast<int64_t>(nb) * C;
+    for (int64_t k = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; k < L;
+         k += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+        const int b = static_cast<int>(k / C), c = static_cast<int>(k - static_cast<int64_t>(b) * C);
+        if (keep && !keep[c]) continue;
+        t += static_cast<unsigned long long>((offs[k + 1] - offs[k]) * (ooff[b + 1] - ooff[b]));
+    }
+    for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o);
+    if ((threadIdx.x & 63) == 0 && t) atomicAdd(acc, t);
+}
 __global__ void k_fill_f(float *p, int64_t n, float v) {
     int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i < n) p[i] = v;
@@ -783,6 +802,7 @@ struct ScoreWs {
     int64_t *loff;
     int64_t *ooff;
     int *maxc;
+    int64_t *pairs;   // pairs of all slots, of the kept candidates' slots
 };
 
 size_t carve_score(Carver &cv, ScoreWs &w, const laue_geometry *g, int chunk, int64_t spot_cap) {
@@ -801,6 +821,7 @@ size_t carve_score(Carver &cv, ScoreWs &w, const laue_geometry *g, int chunk, in
     w.keep = cv.take<uint8_t>(chunk);
     w.ooff = cv.take<int64_t>(nb + 1);
     w.maxc = cv.take<int>(1);
+    w.pairs = cv.take<int64_t>(2);
     return cv.size();
 }
 
@@ -864,6 +885,11 @@ extern "C" int laue_score_candidates(const laue_geometry *geom, const laue_plane
     const float floor_e = static_cast<float>(std::exp(-par->c_out / (2.0 * par->sigma_mm * par->sigma_mm)));
     int64_t lbar_total = 0;
     const int N = cand->n;
+    out->pairs_streamed = 0;
+    k_set_i64<<<1, 1, 0, s>>>(w.pairs, 0);
+    k_set_i64<<<1, 1, 0, s>>>(w.pairs + 1, 0);
+    LAUE_CHECK_HIP(hipGetLastError());
+    unsigned long long *pairs = reinterpret_cast<unsigned long long *>(w.pairs);
     if (N == 0) {
         k_set_i64<<<1, 1, 0, s>>>(out->lbar_off, 0);
         LAUE_CHECK_HIP(hipGetLastError());
@@ -908,6 +934,12 @@ extern "C" int laue_score_candidates(const laue_geometry *geom, const laue_plane
         A.mplane = w.plane;
         A.mgrain = w.grain;
         A.mblock = w.block;
+        // pairs of one pass over every slot (the refinement's k_refine * k_gn
+        // statistics passes and the first scoring pass stream them all; the
+        // second scoring pass streams the kept candidates' slots only)
+        const unsigned pg = static_cast<unsigned>(std::min<int64_t>((L + 255) / 256, 1024));
+        k_slot_pairs<<<pg, 256, 0, s>>>(w.e.offs, w.ooff, nb, C, nullptr, pairs);
+        LAUE_CHECK_HIP(hipGetLastError());
         for (int it = 0; it < par->k_refine; ++it) {
             const double eps = par->k_refine == 1 ? par->eps_start
                                : par->eps_start * std::pow(par->eps_end / par->eps_start,
@@ -956,6 +988,10 @@ extern "C" int laue_score_candidates(const laue_geometry *geom, const laue_plane
         }
         k_cand_off<<<(C + 1 + 127) / 128, 128, 0, s>>>(w.loff, C, nb, lbar_total, out->lbar_off, c0, 1);
         LAUE_CHECK_HIP(hipGetLastError());
+        if (ctot > 0) {
+            k_slot_pairs<<<pg, 256, 0, s>>>(w.e.offs, w.ooff, nb, C, w.keep, pairs + 1);
+            LAUE_CHECK_HIP(hipGetLastError());
+        }
         if (ctot > 0 &&
             (rc = launch_score(A, 1, twoD2, K2, floor_e, static_cast<float>(par->c_out), nullptr,
                                  nullptr, w.loff, w.keep, out->lbar_row + lbar_total,
@@ -964,7 +1000,10 @@ extern "C" int laue_score_candidates(const laue_geometry *geom, const laue_plane
         lbar_total += ctot;
     }
     out->lbar_n = lbar_total;
+    int64_t hp[2] = {0, 0};
+    LAUE_CHECK_HIP(hipMemcpyAsync(hp, w.pairs, 2 * sizeof(int64_t), hipMemcpyDeviceToHost, s));
     LAUE_CHECK_HIP(hipStreamSynchronize(s));
+    out->pairs_streamed = (static_cast<int64_t>(par->k_refine) * par->k_gn + 1) * hp[0] + hp[1];
     return LAUE_OK;
 }
 

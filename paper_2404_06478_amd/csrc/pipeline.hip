@@ -259,6 +259,7 @@ extern "C" int laue_index(const laue_geometry *geom, const laue_planes *planes, 
             return rc;
     }
     st.lbar_entries = so.lbar_n;
+    st.score_pairs = so.pairs_streamed;
     if (log_enabled()) LAUE_CHECK_HIP(hipStreamSynchronize(s));
     st.ms_score = ms_since(t0);
     log_line("index: scored %lld candidates, %lld SPOT entries, in %.1f ms", static_cast<long long>(n_sc),

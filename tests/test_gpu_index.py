@@ -58,10 +58,12 @@ def test_refine_score_match_oracle(gpu_lib):
     cq = ref["q"][sel]
     cx = np.zeros((len(sel), 3))
     c_out = cost.c_out(p.sigma_mm, p.distance)
-    outs = []
+    outs, slot_pairs = [], []
+    n_obs_blk = np.diff(sim["offsets"])
     for k in range(len(sel)):
         qq, xx, mod = single.refine(pl, g, p.distance, p12, sim["offsets"], cq[k], cx[k], p.sigma_mm, c_out,
                                     k_refine=6, k_gn=2)
+        slot_pairs.append(int(np.sum(np.diff(mod["offsets"]) * n_obs_blk)))
         outs.append((qq, xx) + single.score(pl, g, p.distance, p12, sim["offsets"], mod, qq, xx, p.sigma_mm, c_out))
     grains = laue.Grains(cq, cx)
     par = laue.score_params(p.sigma_mm, p.distance, c_out, k_refine=6, k_gn=2, chunk=5)
@@ -88,6 +90,10 @@ def test_refine_score_match_oracle(gpu_lib):
         assert np.max(np.abs(np.array([m[r] for r in rows[safe]]) - vals[safe])) < 1e-4
     # at least some true-grain candidates survive the filter
     assert res["keep"].sum().item() >= 3
+    # pairs streamed: 6 x 2 statistics passes and the first scoring pass over
+    # every candidate's frozen model spots, the second over the kept ones
+    kept = res["keep"].cpu().numpy().astype(bool)
+    assert res["pairs_streamed"] == 13 * sum(slot_pairs) + sum(np.array(slot_pairs)[kept])
 
 
 def test_greedy_matches_oracle(gpu_lib):
