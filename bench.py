@@ -48,8 +48,8 @@ PEAK_ENTRIES_PER_S = VALU_LANE_OPS_PER_S / (VALU_PER_ENTRY + 4 * TRANS_PER_ENTRY
 # HBM bytes of one working row pass (k_row) on this workload, from rocprofv3
 # FETCH_SIZE and WRITE_SIZE (KiB per dispatch) scaled by what the same
 # counters read for a plain 1 GiB device copy (x2.000 and x1.000):
-# 78,577 KiB x 2 + 4,456 KiB.  The column pass moves 1.04e8 B.
-ROW_PASS_HBM_BYTES = (78_577 * 2.0 + 4_456 * 1.0) * 1024
+# 78,340 KiB x 2 + 4,456 KiB.  The column pass moves 1.04e8 B.
+ROW_PASS_HBM_BYTES = (78_340 * 2.0 + 4_456 * 1.0) * 1024
 
 
 def build_problem(laue, preset):
