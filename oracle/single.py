@@ -10,9 +10,12 @@ candidate's model spots of its block and the outlier column:
     Q_ij = exp(-c_ij/eps) / (sum_{j' in J_n, blk(i)} exp(-c_ij'/eps) + exp(-c_out/eps))
 (Alg. SingleLaueOT's K diag(a / K1) read as diag(a / K1) K, i.e. rows sum to
 a_i).  Reading: k_refine iterations on a geometric temperature schedule
-111 sigma^2 -> 1.11 sigma^2, each an E-step followed by k_gn Gauss-Newton
-steps with Q fixed (the M-step of oracle/mstep.py); the model-spot set of a
-candidate is frozen at its start.
+30 sigma^2 -> 1.11 sigma^2 (the paper fixes no single-grain schedule; a
+start at 30 sigma^2 rather than the multi-grain EM's 111 sigma^2 keeps the
+wide first kernels from pulling a candidate onto the clutter around it),
+each an E-step followed by k_gn Gauss-Newton steps with Q fixed (the M-step
+of oracle/mstep.py); the model-spot set of a candidate is frozen at its
+start.
 
 Unmatched filter (Sec. 6.2, Sec. 7): a model spot is unmatched when no
 detected spot of its block lies within the 3-sigma outlier cost (min_i c_ij >
@@ -39,10 +42,14 @@ import numpy as np
 from . import cost, em, forward, mstep, sinkhorn
 
 
+REFINE_HOT = 30.0     # first temperature of the refinement, in sigma^2
+REFINE_COLD = 1.11    # last temperature, in sigma^2
+
+
 def refine_schedule(sigma, k_refine):
     if k_refine == 1:
-        return [111.0 * sigma ** 2]
-    return list(np.geomspace(111.0 * sigma ** 2, 1.11 * sigma ** 2, k_refine))
+        return [REFINE_HOT * sigma ** 2]
+    return list(np.geomspace(REFINE_HOT * sigma ** 2, REFINE_COLD * sigma ** 2, k_refine))
 
 
 def _blocks_costs(planes, geom, distance, p12, obs_off, model, q, x):

@@ -494,7 +494,7 @@ def score_params(sigma_mm, distance, c_out, f_out=0.1, k_refine=8, k_gn=2, mu_re
                  max_spots_per_cand=4096, eps_start=None, eps_end=None):
     p = _abi.laue_score_params()
     p.sigma_mm, p.distance, p.c_out, p.f_out = float(sigma_mm), float(distance), float(c_out), float(f_out)
-    p.eps_start = float(111.0 * sigma_mm ** 2 if eps_start is None else eps_start)
+    p.eps_start = float(30.0 * sigma_mm ** 2 if eps_start is None else eps_start)
     p.eps_end = float(1.11 * sigma_mm ** 2 if eps_end is None else eps_end)
     p.k_refine, p.k_gn, p.mu_rel = int(k_refine), int(k_gn), float(mu_rel)
     p.chunk, p.max_spots_per_cand = int(chunk), int(max_spots_per_cand)
