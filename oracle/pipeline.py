@@ -27,7 +27,7 @@ from . import candidates, em, forward, proposal, single
 
 
 def index(planes, geom, distance, p12, offsets, sigma, c_out, eps_list, n_pairs, seed, delta_deg=1.5,
-          max_candidates=None, k_refine=8, k_gn_refine=2, f_out=0.1, k_max=None, t_b_frac=0.4, k_gn=2,
+          max_candidates=None, k_refine=8, k_gn_refine=1, f_out=0.1, k_max=None, t_b_frac=0.4, k_gn=2,
           ranking=None, top_frac=0.05, starts=None):
     if starts is not None:
         cand = {"q": np.asarray(starts[0], dtype=np.float64), "x": np.asarray(starts[1], dtype=np.float64)}

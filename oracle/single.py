@@ -14,8 +14,9 @@ a_i).  Reading: k_refine iterations on a geometric temperature schedule
 start at 30 sigma^2 rather than the multi-grain EM's 111 sigma^2 keeps the
 wide first kernels from pulling a candidate onto the clutter around it),
 each an E-step followed by k_gn Gauss-Newton steps with Q fixed (the M-step
-of oracle/mstep.py); the model-spot set of a candidate is frozen at its
-start.
+of oracle/mstep.py; default one step, since with Q fixed a second step moves
+the candidate by a negligible amount); the model-spot set of a candidate is
+frozen at its start.
 
 Unmatched filter (Sec. 6.2, Sec. 7): a model spot is unmatched when no
 detected spot of its block lies within the 3-sigma outlier cost (min_i c_ij >
@@ -61,7 +62,7 @@ def _pairs_single(planes, geom, p_lab, obs_off, model, Qb):
     return em.grain_pairs(planes, geom, p_lab, obs_off, model, Qb, 1)[0]
 
 
-def refine(planes, geom, distance, p12, obs_off, q, x, sigma, c_out, k_refine=8, k_gn=2):
+def refine(planes, geom, distance, p12, obs_off, q, x, sigma, c_out, k_refine=8, k_gn=1):
     """Single-grain fit of one candidate from (q, x).  Returns (q, x, model)."""
     q = np.array(q, dtype=np.float64)
     x = np.array(x, dtype=np.float64)

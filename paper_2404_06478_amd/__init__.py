@@ -490,7 +490,7 @@ def laue_candidates_generate(geom, planes, obs, n_pairs, seed, delta_deg=1.5, ca
     return res
 
 
-def score_params(sigma_mm, distance, c_out, f_out=0.1, k_refine=8, k_gn=2, mu_rel=1e-9, chunk=4096,
+def score_params(sigma_mm, distance, c_out, f_out=0.1, k_refine=8, k_gn=1, mu_rel=1e-9, chunk=4096,
                  max_spots_per_cand=4096, eps_start=None, eps_end=None):
     p = _abi.laue_score_params()
     p.sigma_mm, p.distance, p.c_out, p.f_out = float(sigma_mm), float(distance), float(c_out), float(f_out)
