@@ -525,12 +525,13 @@ __global__ __launch_bounds__(64 * kGreedyWaves) void k_lazy_greedy(const int64_t
                                                                    const float *__restrict__ val, float *cur,
                                                                    uint8_t *picked, double *ub, int *stamp,
                                                                    int n, int k, int *picks, double *pgain,
-                                                                   int *done) {
+                                                                   int *done, int max_rounds, int *stop) {
     __shared__ double lv[kGreedyWaves];
     __shared__ int li[kGreedyWaves];
     __shared__ int top;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     for (int step = 0; step < k; ++step) {
+        int rounds = 0;
         for (;;) {
             // class leader of this wave
             double best = 0.0;
@@ -585,6 +586,12 @@ __global__ __launch_bounds__(64 * kGreedyWaves) void k_lazy_greedy(const int64_t
                 __syncthreads();
                 break;
             }
+            // a step that needs many refresh rounds hands the rest of the
+            // selection to the grid-wide exact steps (same picks)
+            if (++rounds > max_rounds) {
+                if (threadIdx.x == 0) *stop = step;
+                return;
+            }
             // refresh every stale class leader with a positive bound
             const int mine = li[wave];
             if (mine >= 0 && lv[wave] > 0.0 && stamp[mine] != step) {
@@ -601,6 +608,66 @@ __global__ __launch_bounds__(64 * kGreedyWaves) void k_lazy_greedy(const int64_t
             __syncthreads();
         }
     }
+}
+
+// One exact greedy step from exact gains (k_gain at this step): the largest
+// positive gain, lowest index on ties, is picked and its rows covered; no
+// positive gain ends the selection.  One workgroup of 1024 threads.
+__global__ __launch_bounds__(1024) void k_greedy_pick(const int64_t *__restrict__ off,
+                                                      const int *__restrict__ row,
+                                                      const float *__restrict__ val, float *cur,
+                                                      uint8_t *picked, const double *__restrict__ gain, int n,
+                                                      int step, int *picks, double *pgain, int *done) {
+    __shared__ double lv[16];
+    __shared__ int li[16];
+    __shared__ int top;
+    if (*done) return;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    double best = 0.0;
+    int arg = -1;
+    for (int c = threadIdx.x; c < n; c += 1024) {
+        const double g = gain[c];
+        if (g > best) {            // c ascends: the first of equal gains stays
+            best = g;
+            arg = c;
+        }
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const double ob = __shfl_xor(best, o, 64);
+        const int oa = __shfl_xor(arg, o, 64);
+        if (oa >= 0 && (arg < 0 || ob > best || (ob == best && oa < arg))) {
+            best = ob;
+            arg = oa;
+        }
+    }
+    if (lane == 0) {
+        lv[wave] = best;
+        li[wave] = arg;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double b = 0.0;
+        int a = -1;
+        for (int w = 0; w < 16; ++w)
+            if (li[w] >= 0 && (a < 0 || lv[w] > b || (lv[w] == b && li[w] < a))) {
+                b = lv[w];
+                a = li[w];
+            }
+        top = a;
+        if (a < 0) {
+            *done = 1;
+        } else {
+            picked[a] = 1;
+            picks[step] = a;
+            pgain[step] = b;
+        }
+    }
+    __syncthreads();
+    const int c = top;
+    if (c < 0) return;
+    // a candidate has at most one entry per row: no two threads share a row
+    for (int64_t e = off[c] + threadIdx.x; e < off[c + 1]; e += 1024) cur[row[e]] = fmaxf(cur[row[e]], val[e]);
 }
 
 __global__ void k_set_i64(int64_t *p, int64_t v) { *p = v; }
@@ -1016,6 +1083,7 @@ struct GreedyWs {
     double *gain;   // upper bounds of the gains (exact at their stamp)
     int *stamp;
     int *done;
+    int *stop;      // step at which the lazy selection handed over (-1: none)
 };
 size_t carve_greedy(Carver &cv, GreedyWs &w, int n_cand, int64_t n_rows) {
     w.cur = cv.take<float>(std::max<int64_t>(n_rows, 1));
@@ -1023,6 +1091,7 @@ size_t carve_greedy(Carver &cv, GreedyWs &w, int n_cand, int64_t n_rows) {
     w.gain = cv.take<double>(std::max(n_cand, 1));
     w.stamp = cv.take<int>(std::max(n_cand, 1));
     w.done = cv.take<int>(1);
+    w.stop = cv.take<int>(1);
     return cv.size();
 }
 }  // namespace
@@ -1060,9 +1129,25 @@ extern "C" int laue_spot_greedy(const int64_t *lbar_off, const int32_t *lbar_row
     // every gain once (exact for step 0), then the lazy steps
     k_gain<<<n_cand, 64, 0, s>>>(lbar_off, lbar_row, lbar_val, w.cur, w.picked, w.gain, w.done, n_cand);
     k_fill_i<<<(n_cand + 255) / 256, 256, 0, s>>>(w.stamp, n_cand, 0);
+    k_fill_i<<<1, 64, 0, s>>>(w.stop, 1, -1);
+    // the lazy selection runs on one workgroup; a step that needs more
+    // refresh rounds than about one grid-wide recomputation of every gain
+    // costs hands the remaining steps to exact grid-wide steps
+    const int max_rounds = std::max(4, n_cand / 4096);
     k_lazy_greedy<<<1, 64 * kGreedyWaves, 0, s>>>(lbar_off, lbar_row, lbar_val, w.cur, w.picked, w.gain, w.stamp,
-                                                  n_cand, K, picks, gains, w.done);
+                                                  n_cand, K, picks, gains, w.done, max_rounds, w.stop);
     LAUE_CHECK_HIP(hipGetLastError());
+    int stop = -1;
+    LAUE_CHECK_HIP(hipMemcpyAsync(&stop, w.stop, sizeof(int), hipMemcpyDeviceToHost, s));
+    LAUE_CHECK_HIP(hipStreamSynchronize(s));
+    if (stop >= 0) {
+        for (int step = stop; step < K; ++step) {
+            k_gain<<<n_cand, 64, 0, s>>>(lbar_off, lbar_row, lbar_val, w.cur, w.picked, w.gain, w.done, n_cand);
+            k_greedy_pick<<<1, 1024, 0, s>>>(lbar_off, lbar_row, lbar_val, w.cur, w.picked, w.gain, n_cand, step,
+                                             picks, gains, w.done);
+        }
+        LAUE_CHECK_HIP(hipGetLastError());
+    }
     std::vector<int> hp(K);
     LAUE_CHECK_HIP(hipMemcpyAsync(hp.data(), picks, K * sizeof(int), hipMemcpyDeviceToHost, s));
     LAUE_CHECK_HIP(hipStreamSynchronize(s));

@@ -142,3 +142,28 @@ def test_lazy_greedy_matches_oracle_many_candidates(gpu_lib):
                                    torch.tensor(vals, device=dev), len(cols), n_rows, phi, k_max)
     assert gp.cpu().tolist() == picks
     assert np.allclose(gg.cpu().numpy(), gains, rtol=1e-9, atol=1e-9)
+
+
+def test_greedy_heavy_overlap_matches_oracle(gpu_lib):
+    """Every candidate covers a third of the rows, as under dense clutter: each
+    pick lowers almost every other gain, so the lazy selection hands over to
+    the grid-wide exact steps after the first picks; the picks and gains stay
+    those of the plain greedy."""
+    laue = gpu_lib
+    rng = np.random.default_rng(5)
+    n_rows, n_cand, phi, k_max = 2000, 400, -4.5, 120
+    cols = []
+    for n in range(n_cand):
+        r = np.sort(rng.choice(n_rows, size=rng.integers(500, 700), replace=False))
+        v = phi + rng.uniform(0.01, 4.0, len(r))
+        cols.append((r, v.astype(np.float32).astype(np.float64)))
+    cols.append((cols[7][0].copy(), cols[7][1].copy()))          # an exact duplicate: the lower index wins
+    picks, gains = single.greedy(cols, n_rows, phi, k_max)
+    off = np.concatenate([[0], np.cumsum([len(c[0]) for c in cols])])
+    rows = np.concatenate([c[0] for c in cols]).astype(np.int32)
+    vals = np.concatenate([c[1] for c in cols]).astype(np.float32)
+    dev = torch.device("cuda")
+    gp, gg = laue.laue_spot_greedy(torch.tensor(off, device=dev), torch.tensor(rows, device=dev),
+                                   torch.tensor(vals, device=dev), len(cols), n_rows, phi, k_max)
+    assert gp.cpu().tolist() == picks
+    assert np.allclose(gg.cpu().numpy(), gains, rtol=1e-9, atol=1e-9)
