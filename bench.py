@@ -258,7 +258,10 @@ def bench_index(laue, workload, n_pairs, learned_pairs, log, sobol_points=0):
     modes = [("plain", n_pairs), ("learned", learned_pairs)] + ([("sobol", sobol_points)] if sobol_points else [])
     for mode, pairs in modes:
         if mode == "sobol":
-            par = laue.index_params(p, "sobol", max_candidates=pairs, n_obs=obs.n, n_planes=planes.n)
+            # dense samples keep nearly every start, each with thousands of
+            # SPOT entries: size the SPOT matrix for the starts (64-bit offsets)
+            cap = 8000 * pairs if obs.n * pairs > 1e11 else None
+            par = laue.index_params(p, "sobol", max_candidates=pairs, n_obs=obs.n, n_planes=planes.n, lbar_cap=cap)
         else:
             par = laue.index_params(p, mode, n_pairs=pairs, seed=1, mlp=net if mode == "learned" else None,
                                     support_radius=radius, n_obs=obs.n, n_planes=planes.n)

@@ -746,7 +746,7 @@ def index_params(preset_like, mode="plain", n_pairs=None, seed=0, delta_deg=1.5,
     p.top_frac = float(top_frac)
     c_out = 2.0 * pl.distance ** 2 * (1.0 - math.cos(3.0 * pl.sigma_mm / pl.distance))
     p.score = score if score is not None else score_params(pl.sigma_mm, pl.distance, c_out)
-    p.lbar_cap = int(lbar_cap if lbar_cap is not None else min((1 << 31) - 1, max(1 << 16, 2048 * n_obs)))
+    p.lbar_cap = int(lbar_cap if lbar_cap is not None else max(1 << 16, 2048 * n_obs))
     p.k_max = int(k_max if k_max is not None else max(8, 2 * pl.n_grains))
     p.max_model_spots = int(max_model_spots if max_model_spots is not None
                             else 64 * pl.n_rot * p.k_max)
