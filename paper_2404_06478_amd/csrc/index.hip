@@ -488,6 +488,26 @@ __global__ void k_cand_off(const int64_t *__restrict__ loff, int C, int nb, int6
 
 // ---------------------------------------------------------------- SPOT greedy
 
+// One lane's part of a candidate's increment: entries lane, lane + 64, ...
+// of its CSR range [e0, e1), added in that order (four loads in flight per
+// step, the order unchanged), so every caller gets the same value bit for bit.
+__device__ __forceinline__ double lane_gain(int64_t e0, int64_t e1, int lane, const int *__restrict__ row,
+                                            const float *__restrict__ val, const float *__restrict__ cur) {
+    double s = 0.0;
+    int64_t e = e0 + lane;
+    for (; e + 192 < e1; e += 256) {
+        const int r0 = row[e], r1 = row[e + 64], r2 = row[e + 128], r3 = row[e + 192];
+        const float v0 = val[e], v1 = val[e + 64], v2 = val[e + 128], v3 = val[e + 192];
+        const float c0 = cur[r0], c1 = cur[r1], c2 = cur[r2], c3 = cur[r3];
+        s += fmax(0.0, static_cast<double>(v0) - static_cast<double>(c0));
+        s += fmax(0.0, static_cast<double>(v1) - static_cast<double>(c1));
+        s += fmax(0.0, static_cast<double>(v2) - static_cast<double>(c2));
+        s += fmax(0.0, static_cast<double>(v3) - static_cast<double>(c3));
+    }
+    for (; e < e1; e += 64) s += fmax(0.0, static_cast<double>(val[e]) - static_cast<double>(cur[row[e]]));
+    return s;
+}
+
 __global__ __launch_bounds__(64) void k_gain(const int64_t *__restrict__ off,
                                              const int *__restrict__ row,
                                              const float *__restrict__ val,
@@ -501,10 +521,7 @@ __global__ __launch_bounds__(64) void k_gain(const int64_t *__restrict__ off,
         if (threadIdx.x == 0) gain[c] = -1.0;
         return;
     }
-    double s = 0.0;
-    for (int64_t e = off[c] + threadIdx.x; e < off[c + 1]; e += 64)
-        s += fmax(0.0, static_cast<double>(val[e]) - static_cast<double>(cur[row[e]]));
-    s = wave_sum(s);
+    const double s = wave_sum(lane_gain(off[c], off[c + 1], static_cast<int>(threadIdx.x), row, val, cur));
     if (threadIdx.x == 0) gain[c] = s;
 }
 
@@ -595,10 +612,7 @@ __global__ __launch_bounds__(64 * kGreedyWaves) void k_lazy_greedy(const int64_t
             // refresh every stale class leader with a positive bound
             const int mine = li[wave];
             if (mine >= 0 && lv[wave] > 0.0 && stamp[mine] != step) {
-                double sum = 0.0;
-                for (int64_t e = off[mine] + lane; e < off[mine + 1]; e += 64)
-                    sum += fmax(0.0, static_cast<double>(val[e]) - static_cast<double>(cur[row[e]]));
-                sum = wave_sum(sum);
+                const double sum = wave_sum(lane_gain(off[mine], off[mine + 1], lane, row, val, cur));
                 if (lane == 0) {
                     ub[mine] = sum;
                     stamp[mine] = step;
