@@ -586,7 +586,7 @@ def main():
     ap.add_argument("--unbalanced-workload", default="medium", choices=["medium", "learned", "stress"])
     ap.add_argument("--no-mstep-methods", action="store_true")
     ap.add_argument("--batch-samples", type=int, default=64)
-    ap.add_argument("--index-workloads", default="medium:4096:200000,learned:1024,learned_fiducial:2048",
+    ap.add_argument("--index-workloads", default="medium:8192:200000,learned:1024,learned_fiducial:2048",
                     help="workload:pairs[:sobol_points] items; plain scoring of the pairs' candidates, the learned "
                          "proposal on 8x the pairs, and the Sobol-grid starts when sobol_points > 0")
     ap.add_argument("--index-limits", default="learned,learned_fiducial",
