@@ -167,3 +167,29 @@ def test_greedy_heavy_overlap_matches_oracle(gpu_lib):
                                    torch.tensor(vals, device=dev), len(cols), n_rows, phi, k_max)
     assert gp.cpu().tolist() == picks
     assert np.allclose(gg.cpu().numpy(), gains, rtol=1e-9, atol=1e-9)
+
+
+def test_greedy_ends_early_after_hand_over(gpu_lib):
+    """Two hundred copies of one column and three small disjoint columns: after
+    the first pick every copy's increment is zero, the lazy selection hands
+    over while refreshing the copies, and the grid-wide steps pick the three
+    others and stop with no positive increment left (fewer picks than k_max)."""
+    laue = gpu_lib
+    rng = np.random.default_rng(9)
+    n_rows, phi = 1200, -4.5
+    base_r = np.sort(rng.choice(1000, size=600, replace=False))
+    base_v = (phi + rng.uniform(0.5, 4.0, len(base_r))).astype(np.float32).astype(np.float64)
+    cols = [(base_r.copy(), base_v.copy()) for _ in range(200)]
+    for k in range(3):
+        r = np.arange(1000 + 60 * k, 1000 + 60 * k + 40)
+        cols.append((r, (phi + rng.uniform(0.01, 1.0, len(r))).astype(np.float32).astype(np.float64)))
+    picks, gains = single.greedy(cols, n_rows, phi, 50)
+    assert len(picks) == 4
+    off = np.concatenate([[0], np.cumsum([len(c[0]) for c in cols])])
+    rows = np.concatenate([c[0] for c in cols]).astype(np.int32)
+    vals = np.concatenate([c[1] for c in cols]).astype(np.float32)
+    dev = torch.device("cuda")
+    gp, gg = laue.laue_spot_greedy(torch.tensor(off, device=dev), torch.tensor(rows, device=dev),
+                                   torch.tensor(vals, device=dev), len(cols), n_rows, phi, 50)
+    assert gp.cpu().tolist() == picks
+    assert np.allclose(gg.cpu().numpy(), gains, rtol=1e-9, atol=1e-9)
