@@ -783,6 +783,7 @@ __device__ __forceinline__ void mstep_pass(const Item &it, const SampleDesc &D,
         if (in < it.r1) nx = make_float4(P1[in], P2[in], F[in], 0.0f);
         float a[NS];
         for (int k = 0; k < NS; ++k) a[k] = 0.0f;
+#pragma unroll 4
         for (int t = 0; t < ni; ++t) {
             const float4 X = lr[buf][t];
             const float Q = fast_exp2(entry_exponent(X.x, X.y, cE.s1, cE.s2, cE.v1, cE.v2, cE.vv,
