@@ -223,7 +223,7 @@ typedef struct laue_ot_params {
     int32_t n_max;              /* iteration cap (>= 1) */
     int32_t chunk;              /* iterations between host polls (0: 16; in an EM, sized
                                  * per temperature stage) */
-    /* sparse assignment (Sec. 4.5): 0 dense; 8, 16 or 32 = every detected
+    /* sparse assignment (Sec. 5.2): 0 dense; 8, 16 or 32 = every detected
      * spot keeps only its rho nearest model spots of its block by the chord
      * cost (ties to the lower index), the plan being null elsewhere (the bins
      * stay).  The sets are chosen afresh before every Sinkhorn (and before a
@@ -231,7 +231,7 @@ typedef struct laue_ot_params {
      * comes from laue_sparse_workspace_size. */
     int32_t rho;
     /* outlier treatment: 0 = the outlier row and column of Sec. 4.3 (bins
-     * c_out, c_unm, c_sink and mass T_b); 1 = unbalanced OT (App. B,
+     * c_out, c_unm, c_sink and mass T_b); 1 = unbalanced OT (App. C,
      * Problem B): no bins (c_out, c_unm, c_sink and t_b are ignored; the bin
      * potentials come back as -inf), the row and column marginals relaxed by
      * KL penalties of strengths kappa (detected spots) and lam (model spots),
@@ -244,7 +244,7 @@ typedef struct laue_ot_params {
      * the plan, S |exp(du / eps) - 1| (S its mass before the update, du its
      * potential change), is <= tol (or, as above, within 4 tol and stalled
      * for 64 iterations).
-     * 2 = partial OT (App. B, Problem A): no bins either; plans with row and
+     * 2 = partial OT (App. C, Problem A): no bins either; plans with row and
      * column sums <= 1 and total mass m = m_frac * sum_b min(|I_b|, |J_b|)
      * (the most the block plans can carry), the KL projection of the Gibbs
      * kernel exp(-c/eps) by Dykstra's projections (Alg. PartialOT), in
@@ -428,7 +428,7 @@ int laue_em(const laue_geometry *geom, const laue_planes *planes,
             laue_assignments *assign, laue_em_stats *stats,
             void *ws, size_t ws_bytes, void *stream);
 
-/* The neighbour sets of the sparse assignment (Sec. 4.5), as the sparse
+/* The neighbour sets of the sparse assignment (Sec. 5.2), as the sparse
  * Sinkhorn builds them: for every detected spot the par->rho nearest model
  * spots of its block by the chord cost, ordered by (cost, index), ties to the
  * lower index.  nbr [n_obs x rho] (device int32, model-spot index or -1 when

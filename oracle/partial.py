@@ -1,4 +1,4 @@
-"""Partial entropic OT E-step (paper App. B, Problem A; Alg. PartialOT), the
+"""Partial entropic OT E-step (paper App. C, Problem A; Alg. PartialOT), the
 other outlier treatment the paper compares its model with.
 
 Test infrastructure: FP64, plain NumPy.

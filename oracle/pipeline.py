@@ -28,7 +28,10 @@ from . import candidates, em, forward, proposal, single
 
 def index(planes, geom, distance, p12, offsets, sigma, c_out, eps_list, n_pairs, seed, delta_deg=1.5,
           max_candidates=None, k_refine=8, k_gn_refine=1, f_out=0.1, k_max=None, t_b_frac=0.4, k_gn=2,
-          ranking=None, top_frac=0.05, starts=None):
+          ranking=None, top_frac=0.05, starts=None, refine_eps=None, zeta_tol=None, n_final_max=0):
+    """refine_eps: the single-grain temperature list (None: single.refine's
+    default); zeta_tol, n_final_max: Alg. LaueOT's plan-change stop at the last
+    EM temperature (em.run)."""
     if starts is not None:
         cand = {"q": np.asarray(starts[0], dtype=np.float64), "x": np.asarray(starts[1], dtype=np.float64)}
     else:
@@ -44,7 +47,7 @@ def index(planes, geom, distance, p12, offsets, sigma, c_out, eps_list, n_pairs,
     for c in chosen:
         x_start = cand["x"][c] if "x" in cand else np.zeros(3)
         q, x, mod = single.refine(planes, geom, distance, p12, offsets, cand["q"][c], x_start, sigma, c_out,
-                                  k_refine=k_refine, k_gn=k_gn_refine)
+                                  k_refine=k_refine, k_gn=k_gn_refine, eps_list=refine_eps)
         un, nm, rows, vals = single.score(planes, geom, distance, p12, offsets, mod, q, x, sigma, c_out)
         keep = nm > 0 and un < f_out * nm
         cols.append((rows, vals) if keep else (np.zeros(0, np.int64), np.zeros(0)))
@@ -62,6 +65,7 @@ def index(planes, geom, distance, p12, offsets, sigma, c_out, eps_list, n_pairs,
     model["offsets"] = forward.block_offsets(model["block"], geom.n_blocks)
     J = len(model["m"])
     t_b = max(math.ceil(t_b_frac * J), J - n_obs)
-    res = em.run(planes, geom, distance, p12, offsets, model, q0, x0, eps_list, c_out, t_b=t_b, k_gn=k_gn)
-    out.update(q=res["q"], x=res["x"], q_proto=q0, x_proto=x0, n_model=J, t_b=t_b)
+    res = em.run(planes, geom, distance, p12, offsets, model, q0, x0, eps_list, c_out, t_b=t_b, k_gn=k_gn,
+                 zeta_tol=zeta_tol, n_final_max=n_final_max)
+    out.update(q=res["q"], x=res["x"], q_proto=q0, x_proto=x0, n_model=J, t_b=t_b, em_stats=res["stats"])
     return out

@@ -9,7 +9,10 @@ dropped, so the assignment of a detected spot is a softmax over the
 candidate's model spots of its block and the outlier column:
     Q_ij = exp(-c_ij/eps) / (sum_{j' in J_n, blk(i)} exp(-c_ij'/eps) + exp(-c_out/eps))
 (Alg. SingleLaueOT's K diag(a / K1) read as diag(a / K1) K, i.e. rows sum to
-a_i).  Reading: k_refine iterations on a geometric temperature schedule
+a_i).  The paper's schedule (App. D) is the multigrain annealing rule with a
+fixed count k_max: eps_init cool^k, k < k_max (cooling_schedule), with four
+M-step steps per iteration.  Default reading, measured faster for the same
+grains: k_refine iterations on a geometric temperature schedule
 30 sigma^2 -> 1.11 sigma^2 (the paper fixes no single-grain schedule; a
 start at 30 sigma^2 rather than the multi-grain EM's 111 sigma^2 keeps the
 wide first kernels from pulling a candidate onto the clutter around it),
@@ -53,6 +56,15 @@ def refine_schedule(sigma, k_refine):
     return list(np.geomspace(REFINE_HOT * sigma ** 2, REFINE_COLD * sigma ** 2, k_refine))
 
 
+def cooling_schedule(eps_init, k_max, cool=0.97):
+    """Alg. SingleLaueOT's temperatures: a fixed number k_max of iterations,
+    the temperature multiplied by cool after each (App. D: the same annealing
+    rule as the multigrain fit, Sec. 5.1 and Sec. 7)."""
+    if k_max < 1 or not (0.0 < cool <= 1.0) or eps_init <= 0.0:
+        raise ValueError("need k_max >= 1, 0 < cool <= 1 and a positive temperature")
+    return [float(eps_init) * cool ** k for k in range(int(k_max))]
+
+
 def _blocks_costs(planes, geom, distance, p12, obs_off, model, q, x):
     C, ev, vloc = em.build_costs(planes, geom, distance, p12, obs_off, model, q, x)
     return C
@@ -62,8 +74,10 @@ def _pairs_single(planes, geom, p_lab, obs_off, model, Qb):
     return em.grain_pairs(planes, geom, p_lab, obs_off, model, Qb, 1)[0]
 
 
-def refine(planes, geom, distance, p12, obs_off, q, x, sigma, c_out, k_refine=8, k_gn=1):
-    """Single-grain fit of one candidate from (q, x).  Returns (q, x, model)."""
+def refine(planes, geom, distance, p12, obs_off, q, x, sigma, c_out, k_refine=8, k_gn=1, eps_list=None):
+    """Single-grain fit of one candidate from (q, x).  eps_list replaces the
+    default schedule (e.g. cooling_schedule, with k_gn = 4 for the paper's
+    four steps per iteration).  Returns (q, x, model)."""
     q = np.array(q, dtype=np.float64)
     x = np.array(x, dtype=np.float64)
     model = forward.enumerate_visible(planes, q[None], x[None], geom)
@@ -71,7 +85,7 @@ def refine(planes, geom, distance, p12, obs_off, q, x, sigma, c_out, k_refine=8,
     if len(model["m"]) == 0:
         return q, x, model
     p_lab = em.obs_lab(geom, p12, np.repeat(np.arange(geom.n_blocks), np.diff(obs_off)))
-    for eps in refine_schedule(sigma, k_refine):
+    for eps in (refine_schedule(sigma, k_refine) if eps_list is None else eps_list):
         C = _blocks_costs(planes, geom, distance, p12, obs_off, model, q[None], x[None])
         Qb = []
         for Cb in C:

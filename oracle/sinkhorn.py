@@ -116,12 +116,19 @@ def row_error(P, f, g, f0, g0, eps):
 
 
 def solve(P, eps, tol=1e-5, n_max=2000, f=None, g=None, f0=0.0, g0=0.0, history=False):
-    """Sinkhorn iterations from potentials (f, g, f0, g0) (zeros = Alg. BalancedOT's x=y=1).
+    """Sinkhorn iterations from potentials (f, g, f0, g0) (zeros = Alg. BalancedOT's x=y=1),
+    re-centred on entry so that f0 = 0 (the same plan and dual value).
 
     Returns dict with f, g, f0, g0, n_iter, err (and per-iteration dual values
     if history)."""
     f = np.zeros(P.I) if f is None else np.array(f, dtype=np.float64)
     g = np.zeros(P.J) if g is None else np.array(g, dtype=np.float64)
+    f0, g0 = float(f0), float(g0)
+    # gauge: the plan depends on the potentials only through f_i + g_j, f_i +
+    # g_0, f_0 + g_j and f_0 + g_0, so (f - C, g + C, f_0 - C, g_0 + C) is the
+    # same state; a warm start is re-centred with C = f_0 (f_0 = 0 on entry)
+    if math.isfinite(f0) and f0 != 0.0:
+        f, g, g0, f0 = f - f0, g + f0, g0 + f0, 0.0
     hist = []
     err = math.inf
     k = 0

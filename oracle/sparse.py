@@ -1,5 +1,5 @@
 """Sparse assignment: each detected spot keeps only its rho nearest model spots
-(paper Sec. 4.5, working with sparse assignment matrices; Sec. 7 uses
+(paper Sec. 5.2, working with sparse assignment matrices; Sec. 7 uses
 rho = 32).
 
 Test infrastructure: FP64, plain NumPy.

@@ -1,4 +1,4 @@
-"""Unbalanced entropic OT E-step (paper App. B, Problem B; Alg. UnbalancedOT),
+"""Unbalanced entropic OT E-step (paper App. C, Problem B; Alg. UnbalancedOT),
 one of the two outlier treatments the paper compares its model with.
 
 Test infrastructure: FP64, plain NumPy.

@@ -981,7 +981,7 @@ __global__ __launch_bounds__(64) void k_rot_mm(const SampleDesc *__restrict__ de
 
 // Each detected spot keeps its rho nearest model spots of its block by the
 // chord cost (ties to the lower model-spot index); the plan is null outside
-// these sets (Sec. 4.5).  The sets are chosen afresh before every Sinkhorn
+// these sets (Sec. 5.2).  The sets are chosen afresh before every Sinkhorn
 // from the packed columns of that E-step (colsE).  Row side: nbr / ncp
 // [rho x n_obs], neighbour-major so that a wave's rows read adjacent words
 // (model-spot index or -1, c' = c / (2 D^2)), ordered by (c', index).  Column side: CSR by model spot (col_off, col_row, col_cp),
