@@ -261,6 +261,17 @@ typedef struct laue_ot_params {
     double m_frac;              /* partial OT: fraction of the mass transported, (0, 1] */
 } laue_ot_params;
 
+/* The outlier row and column of Sec. 7 for a spot noise of sigma_mm at
+ * detector distance D (host helper, writes every field of *out):
+ * c_out = 2 D^2 (1 - cos(3 sigma_mm / D)) (the likelihood of an angular miss
+ * of 3 sigma), c_unm = 0 (the null angle), c_sink = c_out,
+ * t_b = ceil(0.4 n_model) (at most 40% of the model spots unmatched),
+ * eps = 2 sigma_mm^2 (the paper's temperature 1, plain EM), tol = 1e-5,
+ * n_max = 2000, chunk = 0, rho = 0 (dense), outlier_model = 0, kappa = lam =
+ * m_frac = 0.  LAUE_EINVAL for a non-positive sigma_mm or distance or a
+ * negative n_model. */
+int laue_ot_defaults(double sigma_mm, double distance, int64_t n_model, laue_ot_params *out);
+
 /* Dual potentials: Q_ij = exp((f_i + g_j - c_ij) / eps).  f [n_obs], g
  * [n_model] device FP32 (in: warm start, out: result); f0, g0 host FP64. */
 typedef struct laue_potentials {
@@ -386,6 +397,27 @@ typedef struct laue_em_params {
      * row pass 3 in shape 2, and the faster kept; shape 1 when a sample
      * converges within those iterations); every shape gives the same result */
     int32_t tile;
+    /* annealing (Sec. 5.1, Alg. LaueOT).  eps_cool = 0: the stage schedule
+     * above.  0 < eps_cool < 1: the paper's cooling: the first EM iteration
+     * runs at eps_start and the temperature is multiplied by eps_cool after
+     * every iteration while it is above eps_end, i.e. the temperatures
+     * eps_start eps_cool^k, k = 0 .. K, K the first k with eps_start
+     * eps_cool^k <= eps_end (products taken in that order in FP64; n_stages and
+     * iters_per_stage are not read); then at most final_iters more EM
+     * iterations at the last temperature, stopping after the first iteration
+     * (from iteration K on) whose plan differs from the previous iteration's by
+     * zeta = ||Q^{k+1} - Q^k||_F <= zeta_tol over the detected x model entries
+     * and the bins (zeta_tol <= 0: every final iteration runs).  zeta is
+     * evaluated in FP32 per entry (a floor near 1e-7 sqrt(entries with
+     * Q > 0)); the plan-change test needs the dense assignment and runs in
+     * laue_em only (one sample). */
+    double eps_cool;
+    int32_t final_iters;
+    double zeta_tol;
+    /* > 0: laue_em_stats.objective receives the FP64 summaries of the last
+     * E-step's plan (laue_objectives) with the paper-unit objective at this
+     * spot noise (mm); 0: not computed */
+    double sigma_mm;
 } laue_em_params;
 
 typedef struct laue_em_stats {
@@ -404,19 +436,33 @@ typedef struct laue_em_stats {
     int32_t launch_used;        /* 1 direct launches, 2 graph replay */
     int32_t polls;              /* host polls of the Sinkhorn control blocks */
     int32_t tile2_solves;       /* Sinkhorn solves run in the two-per-lane shape */
+    /* the likelihood out (Eqs. elbo, estep_obj): FP64 summaries of the last
+     * E-step's plan (laue_objectives of its potentials and geometry) when
+     * laue_em_params.sigma_mm > 0, else NaN */
+    laue_objective objective;
+    double zeta;                /* cooling mode, dense: ||Q^{k+1} - Q^k||_F of the last
+                                 * EM iteration (NaN when not evaluated) */
+    int32_t final_iters_run;    /* cooling mode: EM iterations after the cooling */
 } laue_em_stats;
 
-/* Per detected spot (device, may be NULL): j_star = argmax over its block's
- * model spots and the outlier column of Q (lowest index on ties; -1 for the
- * outlier column), its grain (-1 for outlier), q_star = Q_ij*, q_out = Q_i0.
- * Under unbalanced or partial OT (no outlier column) q_out is the mass the
- * plan leaves untransported, max(0, 1 - sum_j Q_ij), and takes the outlier
- * column's place in the comparison. */
+/* Hard assignments of the EM's last E-step plan (Alg. LaueOT's output Q:
+ * its potentials and the model-spot geometry of that E-step, i.e. before the
+ * last M-step moves the grains).  Per detected spot (device [n_obs], the four
+ * arrays all given or all NULL): j_star = argmax over its block's model spots
+ * and the outlier column of Q (lowest index on ties; -1 for the outlier
+ * column), its grain (-1 for outlier), q_star = Q_ij*, q_out = Q_i0.  Under
+ * unbalanced or partial OT (no outlier column) q_out is the mass the plan
+ * leaves untransported, max(0, 1 - sum_j Q_ij), and takes the outlier
+ * column's place in the comparison.  Per model spot (device [n_model], may be
+ * NULL): q_unm = Q_0j, its entry in the unmatched row (Eq. update_L; the
+ * weight behind the unmatched-spot rule of Sec. 6.2); 0 under unbalanced or
+ * partial OT. */
 typedef struct laue_assignments {
     int32_t *j_star;
     int32_t *grain;
     float *q_star;
     float *q_out;
+    float *q_unm;
 } laue_assignments;
 
 /* Full EM: for each stage s and iteration: forward eval -> Sinkhorn (warm
@@ -439,6 +485,18 @@ int laue_em(const laue_geometry *geom, const laue_planes *planes,
 int laue_sparse_neighbors(const laue_geometry *geom, const laue_obs_spots *obs, const laue_model_spots *model,
                           const laue_ot_params *par, int32_t *nbr, float *cost, int64_t *n_pairs, void *ws,
                           size_t ws_bytes, void *stream);
+
+/* The first temperature of the sparse assignment (Sec. 7: chosen so that the
+ * farthest of the rho neighbours keeps a non-negligible probability at the
+ * start): the median over detected spots of the chord cost to their farthest
+ * kept neighbour (laue_sparse_neighbors; spots of blocks without model spots
+ * left out; the mean of the two middle values for an even count), divided by
+ * ln 100, i.e. that neighbour's Gibbs weight relative to a zero-cost match is
+ * 1/100 for the median spot.  *eps_init (HOST) in mm^2; 1.0 when no detected
+ * spot has a neighbour.  Only par->distance and par->rho (8, 16 or 32) are
+ * read.  Workspace: laue_sparse_workspace_size with n = 1.  Synchronous. */
+int laue_eps_init(const laue_geometry *geom, const laue_obs_spots *obs, const laue_model_spots *model,
+                  const laue_ot_params *par, double *eps_init, void *ws, size_t ws_bytes, void *stream);
 
 /* Workspace of laue_sinkhorn, laue_mstep and laue_em (n = 1) or
  * laue_em_batched (n samples) when ot.rho > 0: the dense workspace plus the
@@ -528,6 +586,10 @@ typedef struct laue_score_params {
     int32_t k_refine, k_gn;
     double mu_rel;
     int32_t chunk, max_spots_per_cand;
+    /* 0: the geometric schedule eps_start -> eps_end above; in (0, 1]:
+     * Alg. SingleLaueOT's cooling, iteration k at eps_start eps_cool^k
+     * (k = 0 .. k_refine - 1, FP64 products in order; eps_end not read) */
+    double eps_cool;
 } laue_score_params;
 
 /* Scoring outputs (device).  n_model, n_unmatched, keep: [n_cand] (may be
@@ -741,7 +803,11 @@ typedef struct laue_index_stats {
 } laue_index_stats;
 
 /* Output grains (device, capacity >= k_max; n_grains = k* on return) and the
- * per-detected-spot assignments of the final EM (all four arrays or none). */
+ * per-detected-spot assignments of the final EM's last E-step (j_star, grain,
+ * q_star, q_out: all four arrays or none; q_unm is not written, the model
+ * spots of the EM living in the workspace).  The likelihood of that plan
+ * (Eqs. elbo, estep_obj) is stats->em.objective, at em.sigma_mm or, when that
+ * is 0, at score.sigma_mm. */
 typedef struct laue_index_out {
     int32_t capacity;
     int32_t n_grains;

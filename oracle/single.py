@@ -62,7 +62,10 @@ def cooling_schedule(eps_init, k_max, cool=0.97):
     rule as the multigrain fit, Sec. 5.1 and Sec. 7)."""
     if k_max < 1 or not (0.0 < cool <= 1.0) or eps_init <= 0.0:
         raise ValueError("need k_max >= 1, 0 < cool <= 1 and a positive temperature")
-    return [float(eps_init) * cool ** k for k in range(int(k_max))]
+    out = [float(eps_init)]
+    for _ in range(int(k_max) - 1):
+        out.append(out[-1] * cool)
+    return out
 
 
 def _blocks_costs(planes, geom, distance, p12, obs_off, model, q, x):

@@ -294,6 +294,19 @@ def ot_params(eps, distance, c_out, t_b, c_unm=0.0, c_sink=None, tol=1e-5, n_max
     return p
 
 
+def ot_defaults(sigma_mm, distance, n_model):
+    """laue_ot_params of the outlier row and column of Sec. 7 (laue_ot_defaults)."""
+    lib = require_native()
+    p = laue_ot_params()
+    _check(lib.laue_ot_defaults(float(sigma_mm), float(distance), int(n_model), C.byref(p)))
+    return p
+
+
+def c_out_3sigma(sigma_mm, distance):
+    """The outlier cost of a 3-sigma angular miss (laue_ot_defaults' c_out)."""
+    return ot_defaults(sigma_mm, distance, 0).c_out
+
+
 def _ws_size(geom, n_obs, n_model, n_grains, rho):
     """Workspace bytes of the Sinkhorn / M-step / EM calls of one sample."""
     lib = require_native()
@@ -321,6 +334,17 @@ def laue_sparse_neighbors(geom, obs, model, ot):
     _check(lib.laue_sparse_neighbors(C.byref(geom), C.byref(o), C.byref(m), C.byref(ot), _ptr(nbr), _ptr(cost),
                                      C.byref(npairs), _ptr(ws), ws.numel(), _stream()))
     return nbr[:obs.n], cost[:obs.n], npairs.value
+
+
+def laue_eps_init(geom, obs, model, ot):
+    """The sparse assignment's first temperature (mm^2): median farthest-neighbour cost / ln 100."""
+    lib = require_native()
+    ws = _workspace(_ws_size(geom, obs.n, model.n, 0, int(ot.rho)))
+    out = C.c_double()
+    o, m = obs.struct(), model.struct()
+    _check(lib.laue_eps_init(C.byref(geom), C.byref(o), C.byref(m), C.byref(ot), C.byref(out), _ptr(ws),
+                             ws.numel(), _stream()))
+    return out.value
 
 
 def laue_sinkhorn(geom, obs, model, ot, f, g, f0=0.0, g0=0.0):
@@ -399,8 +423,11 @@ def laue_mstep(geom, planes, obs, model, ot, f, g, grains, k_gn=2, mu_rel=1e-9, 
 
 
 def em_params(ot, eps_start, eps_end, n_stages, iters_per_stage, k_gn=2, mu_rel=1e-9, launch=0, tile=0,
-              **mstep_kw):
-    """mstep_kw: the M-step options of gn_params (mstep="paper", k_newton, ...)."""
+              eps_cool=0.0, final_iters=0, zeta_tol=0.0, sigma_mm=0.0, **mstep_kw):
+    """mstep_kw: the M-step options of gn_params (mstep="paper", k_newton, ...).
+    eps_cool in (0, 1): Alg. LaueOT's cooling from eps_start down to eps_end,
+    then final_iters more iterations with the plan-change stop zeta_tol;
+    sigma_mm > 0: the likelihood of the last plan in the results."""
     p = laue_em_params()
     p.ot = ot
     p.gn = gn_params(k_gn, mu_rel, **mstep_kw)
@@ -408,7 +435,29 @@ def em_params(ot, eps_start, eps_end, n_stages, iters_per_stage, k_gn=2, mu_rel=
     p.n_stages, p.iters_per_stage = int(n_stages), int(iters_per_stage)
     p.launch = int(launch)
     p.tile = int(tile)
+    p.eps_cool, p.final_iters, p.zeta_tol, p.sigma_mm = float(eps_cool), int(final_iters), float(zeta_tol), \
+        float(sigma_mm)
     return p
+
+
+def _assign_tensors(n_obs, n_model, dev):
+    import torch
+    n, m = max(n_obs, 1), max(n_model, 1)
+    return {"j_star": torch.zeros(n, dtype=torch.int32, device=dev),
+            "grain": torch.zeros(n, dtype=torch.int32, device=dev),
+            "q_star": torch.zeros(n, dtype=torch.float32, device=dev),
+            "q_out": torch.zeros(n, dtype=torch.float32, device=dev),
+            "q_unm": torch.zeros(m, dtype=torch.float32, device=dev)}
+
+
+def _assign_struct(t):
+    return laue_assignments(*(t[k].data_ptr() for k in ("j_star", "grain", "q_star", "q_out", "q_unm")))
+
+
+def _em_stats_dict(st):
+    out = {name: getattr(st, name) for name, _ in laue_em_stats._fields_ if name != "objective"}
+    out["objective"] = {name: getattr(st.objective, name) for name, _ in _abi.laue_objective._fields_}
+    return out
 
 
 def laue_em(geom, planes, obs, model, par, grains, f=None, g=None, f0=0.0, g0=0.0, assign=True):
@@ -423,26 +472,17 @@ def laue_em(geom, planes, obs, model, par, grains, f=None, g=None, f0=0.0, g0=0.
     st = laue_em_stats()
     asg = None
     if assign:
-        n = max(obs.n, 1)
-        asg_t = {"j_star": torch.zeros(n, dtype=torch.int32, device=dev),
-                 "grain": torch.zeros(n, dtype=torch.int32, device=dev),
-                 "q_star": torch.zeros(n, dtype=torch.float32, device=dev),
-                 "q_out": torch.zeros(n, dtype=torch.float32, device=dev)}
-        asg = laue_assignments(*(asg_t[k].data_ptr() for k in ("j_star", "grain", "q_star", "q_out")))
+        asg_t = _assign_tensors(obs.n, model.n, dev)
+        asg = _assign_struct(asg_t)
     o, m = obs.struct(), model.struct()
     rc = _check(lib.laue_em(C.byref(geom), C.byref(planes.struct), C.byref(o), C.byref(m),
                             C.byref(par), C.byref(grains.struct), C.byref(pot),
                             C.byref(asg) if asg is not None else None, C.byref(st), _ptr(ws),
                             ws.numel(), _stream()))
-    out = {"f": f, "g": g, "f0": pot.f0, "g0": pot.g0, "code": rc, "n_em_iter": st.n_em_iter,
-           "sinkhorn_iters": st.sinkhorn_iters, "cost_entries": st.cost_entries,
-           "not_converged": st.not_converged, "last_err": st.last_err,
-           "sinkhorn_ms": st.sinkhorn_ms, "sinkhorn_passes": st.sinkhorn_passes,
-           "sinkhorn_entries": st.sinkhorn_entries, "mstep_ms": st.mstep_ms,
-           "mstep_entries": st.mstep_entries, "launch_used": st.launch_used, "polls": st.polls,
-           "tile2_solves": st.tile2_solves}
+    out = {"f": f, "g": g, "f0": pot.f0, "g0": pot.g0, "code": rc}
+    out.update(_em_stats_dict(st))
     if assign:
-        out.update({k: v[:obs.n] for k, v in asg_t.items()})
+        out.update({k: v[:(model.n if k == "q_unm" else obs.n)] for k, v in asg_t.items()})
     return out
 
 
@@ -491,13 +531,18 @@ def laue_candidates_generate(geom, planes, obs, n_pairs, seed, delta_deg=1.5, ca
 
 
 def score_params(sigma_mm, distance, c_out, f_out=0.1, k_refine=8, k_gn=1, mu_rel=1e-9, chunk=4096,
-                 max_spots_per_cand=4096, eps_start=None, eps_end=None):
+                 max_spots_per_cand=4096, eps_start=None, eps_end=None, eps_cool=0.0):
+    """Single-grain refinement and scoring parameters.  Temperatures are given
+    in units of sigma_mm^2 by the defaults (30 -> 1.11, the oracle's reading)
+    or explicitly in mm^2; eps_cool > 0 selects Alg. SingleLaueOT's cooling
+    eps_start eps_cool^k."""
     p = _abi.laue_score_params()
     p.sigma_mm, p.distance, p.c_out, p.f_out = float(sigma_mm), float(distance), float(c_out), float(f_out)
     p.eps_start = float(30.0 * sigma_mm ** 2 if eps_start is None else eps_start)
     p.eps_end = float(1.11 * sigma_mm ** 2 if eps_end is None else eps_end)
     p.k_refine, p.k_gn, p.mu_rel = int(k_refine), int(k_gn), float(mu_rel)
     p.chunk, p.max_spots_per_cand = int(chunk), int(max_spots_per_cand)
+    p.eps_cool = float(eps_cool)
     return p
 
 
@@ -744,7 +789,7 @@ def index_params(preset_like, mode="plain", n_pairs=None, seed=0, delta_deg=1.5,
     radius = 4.0 * pl.sigma_mm if support_radius is None else support_radius
     p.support = support_params(radius, n_planes if n_support_planes is None else n_support_planes)
     p.top_frac = float(top_frac)
-    c_out = 2.0 * pl.distance ** 2 * (1.0 - math.cos(3.0 * pl.sigma_mm / pl.distance))
+    c_out = c_out_3sigma(pl.sigma_mm, pl.distance)
     p.score = score if score is not None else score_params(pl.sigma_mm, pl.distance, c_out)
     p.lbar_cap = int(lbar_cap if lbar_cap is not None else max(1 << 16, 2048 * n_obs))
     p.k_max = int(k_max if k_max is not None else max(8, 2 * pl.n_grains))
@@ -776,11 +821,8 @@ def laue_index(geom, planes, obs, par, assign=True):
     out.capacity, out.q, out.x = K, q.data_ptr(), x.data_ptr()
     asg_t = None
     if assign:
-        n = max(obs.n, 1)
-        asg_t = {"j_star": torch.zeros(n, dtype=torch.int32, device=dev),
-                 "grain": torch.zeros(n, dtype=torch.int32, device=dev),
-                 "q_star": torch.zeros(n, dtype=torch.float32, device=dev),
-                 "q_out": torch.zeros(n, dtype=torch.float32, device=dev)}
+        asg_t = _assign_tensors(obs.n, 0, dev)
+        del asg_t["q_unm"]
         out.assign = laue_assignments(*(asg_t[k].data_ptr() for k in ("j_star", "grain", "q_star", "q_out")))
     st = _abi.laue_index_stats()
     o = obs.struct()
@@ -788,7 +830,7 @@ def laue_index(geom, planes, obs, par, assign=True):
                                C.byref(st), _ptr(ws), ws.numel(), _stream()))
     k = out.n_grains
     stats = {name: getattr(st, name) for name, _ in _abi.laue_index_stats._fields_ if name != "em"}
-    stats["em"] = {name: getattr(st.em, name) for name, _ in _abi.laue_em_stats._fields_}
+    stats["em"] = _em_stats_dict(st.em)
     stats["code"] = rc
     g = Grains.__new__(Grains)
     g.q, g.x, g.n = q[:max(k, 1)], x[:max(k, 1)], k
@@ -815,14 +857,8 @@ def laue_em_batched(geoms, planes, obs, models, pars, grains, assign=True):
     asg_t = []
     AS = None
     if assign:
-        for o in obs:
-            m = max(o.n, 1)
-            asg_t.append({"j_star": torch.zeros(m, dtype=torch.int32, device=dev),
-                          "grain": torch.zeros(m, dtype=torch.int32, device=dev),
-                          "q_star": torch.zeros(m, dtype=torch.float32, device=dev),
-                          "q_out": torch.zeros(m, dtype=torch.float32, device=dev)})
-        AS = (laue_assignments * n)(*[laue_assignments(*(a[k].data_ptr() for k in ("j_star", "grain", "q_star",
-                                                                                    "q_out"))) for a in asg_t])
+        asg_t = [_assign_tensors(o.n, m.n, dev) for o, m in zip(obs, models)]
+        AS = (laue_assignments * n)(*[_assign_struct(a) for a in asg_t])
     no = np.array([o.n for o in obs], np.int64)
     nm = np.array([m.n for m in models], np.int64)
     ng = np.array([gg.n for gg in grains], np.int32)
@@ -840,8 +876,8 @@ def laue_em_batched(geoms, planes, obs, models, pars, grains, assign=True):
     for k in range(n):
         st = ST[k]
         r = {"f": f[k][:obs[k].n], "g": g[k][:models[k].n], "f0": POT[k].f0, "g0": POT[k].g0}
-        r.update({name: getattr(st, name) for name, _ in laue_em_stats._fields_})
+        r.update(_em_stats_dict(st))
         if assign:
-            r.update({kk: v[:obs[k].n] for kk, v in asg_t[k].items()})
+            r.update({kk: v[:(models[k].n if kk == "q_unm" else obs[k].n)] for kk, v in asg_t[k].items()})
         out.append(r)
     return rc, out

@@ -78,7 +78,8 @@ class laue_gn_params(C.Structure):
 class laue_em_params(C.Structure):
     _fields_ = [("ot", laue_ot_params), ("gn", laue_gn_params), ("eps_start", C.c_double),
                 ("eps_end", C.c_double), ("n_stages", C.c_int32), ("iters_per_stage", C.c_int32),
-                ("launch", C.c_int32), ("tile", C.c_int32)]
+                ("launch", C.c_int32), ("tile", C.c_int32), ("eps_cool", C.c_double),
+                ("final_iters", C.c_int32), ("zeta_tol", C.c_double), ("sigma_mm", C.c_double)]
 
 
 class laue_em_stats(C.Structure):
@@ -87,11 +88,12 @@ class laue_em_stats(C.Structure):
                 ("sinkhorn_ms", C.c_double), ("sinkhorn_passes", C.c_int64),
                 ("sinkhorn_entries", C.c_int64), ("mstep_ms", C.c_double),
                 ("mstep_entries", C.c_int64), ("launch_used", C.c_int32), ("polls", C.c_int32),
-                ("tile2_solves", C.c_int32)]
+                ("tile2_solves", C.c_int32), ("objective", laue_objective), ("zeta", C.c_double),
+                ("final_iters_run", C.c_int32)]
 
 
 class laue_assignments(C.Structure):
-    _fields_ = [("j_star", vp), ("grain", vp), ("q_star", vp), ("q_out", vp)]
+    _fields_ = [("j_star", vp), ("grain", vp), ("q_star", vp), ("q_out", vp), ("q_unm", vp)]
 
 
 class laue_cand_params(C.Structure):
@@ -108,7 +110,7 @@ class laue_score_params(C.Structure):
     _fields_ = [("sigma_mm", C.c_double), ("distance", C.c_double), ("c_out", C.c_double),
                 ("f_out", C.c_double), ("eps_start", C.c_double), ("eps_end", C.c_double),
                 ("k_refine", C.c_int32), ("k_gn", C.c_int32), ("mu_rel", C.c_double),
-                ("chunk", C.c_int32), ("max_spots_per_cand", C.c_int32)]
+                ("chunk", C.c_int32), ("max_spots_per_cand", C.c_int32), ("eps_cool", C.c_double)]
 
 
 class laue_score_out(C.Structure):
@@ -235,6 +237,9 @@ SIGNATURES = {
     "laue_em_batched": (C.c_int, [C.c_int32, P(laue_geometry), P(laue_planes), P(laue_obs_spots),
                                   P(laue_model_spots), P(laue_em_params), P(laue_grains), P(laue_potentials),
                                   P(laue_assignments), P(laue_em_stats), vp, C.c_size_t, vp]),
+    "laue_ot_defaults": (C.c_int, [C.c_double, C.c_double, C.c_int64, P(laue_ot_params)]),
+    "laue_eps_init": (C.c_int, [P(laue_geometry), P(laue_obs_spots), P(laue_model_spots), P(laue_ot_params),
+                                P(C.c_double), vp, C.c_size_t, vp]),
     "laue_select_top_workspace_size": (C.c_size_t, [C.c_int64]),
     "laue_select_top": (C.c_int, [vp, C.c_int64, C.c_int64, vp, vp, C.c_size_t, vp]),
 }

@@ -112,6 +112,23 @@ static bool allowed(int h, int k, int l, char c) {
 
 static int gcd3(int a, int b, int c) { return std::gcd(std::gcd(std::abs(a), std::abs(b)), std::abs(c)); }
 
+extern "C" int laue_ot_defaults(double sigma_mm, double distance, int64_t n_model, laue_ot_params *out) {
+    clear_error();
+    LAUE_REQUIRE(out != nullptr, LAUE_EINVAL, "output is NULL");
+    LAUE_REQUIRE(std::isfinite(sigma_mm) && sigma_mm > 0 && std::isfinite(distance) && distance > 0 && n_model >= 0,
+                 LAUE_EINVAL, "sigma_mm and distance must be > 0 and n_model >= 0");
+    *out = laue_ot_params{};
+    out->eps = 2.0 * sigma_mm * sigma_mm;
+    out->distance = distance;
+    out->c_out = 2.0 * distance * distance * (1.0 - std::cos(3.0 * sigma_mm / distance));
+    out->c_unm = 0.0;
+    out->c_sink = out->c_out;
+    out->t_b = std::ceil(0.4 * static_cast<double>(n_model));
+    out->tol = 1e-5;
+    out->n_max = 2000;
+    return LAUE_OK;
+}
+
 extern "C" int laue_planes_cubic(double a, char centering, int n_max, int32_t *n_planes,
                                  int32_t *hkl, float *w, float *d, int32_t *harmonic_prev) {
     clear_error();

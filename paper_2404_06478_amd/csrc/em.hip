@@ -24,6 +24,7 @@
 // its own; workgroups of finished samples exit at once.  A sample's
 // arithmetic does not depend on the other samples in the batch.
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <numeric>
 #include <vector>
@@ -151,6 +152,11 @@ struct SampleDesc {
     int *gflag;                    // [n_grains] Newton converged in this sweep
     int k_mm, pad1;                // MM steps per sweep
     double tol_x, tol_r;           // Newton and MM stops
+    // plan summaries and the plan change between EM iterations
+    double *obj;                   // [4 * (row items + column items) + 8] partials and totals
+    float *qunm;                   // [n_model] Q_0j of the assignment output (may be NULL)
+    Col8 *colsP;                   // previous E-step's packed columns
+    float *fprev, *gprev;          // previous E-step's potentials
 };
 
 // ---------------------------------------------------------------- helpers
@@ -192,6 +198,14 @@ __device__ __forceinline__ int sample_of(const int64_t *base, int n, int64_t i) 
 
 struct CtlInit {
     double f0, g0, eps;
+    double shift;          // gauge shift C of the solve's start state (f -= C, g += C)
+};
+
+// A plan Q = exp((f + g - c)/eps) of one sample for the summary and
+// plan-change passes: its temperature and bin potentials (f, g and the
+// columns come from the descriptor).
+struct ObjIn {
+    double eps, f0, g0;
 };
 
 __global__ void k_ctl_init(const SampleDesc *__restrict__ descs, int n, const CtlInit *__restrict__ init) {
@@ -217,6 +231,23 @@ __global__ void k_ctl_init(const SampleDesc *__restrict__ descs, int n, const Ct
     ctl->final_state = 0;
     ctl->converged = 0;
     ctl->ticket = 0u;
+}
+
+// Gauge of a warm start (outlier row and column only): the plan depends on
+// the potentials only through f_i + g_j, f_i + g0, f0 + g_j and f0 + g0, so
+// (f - C, g + C, f0 - C, g0 + C) is the same state.  Solves start from C = f0
+// (f0 = 0 after the shift): a warm start carried down the temperatures
+// otherwise keeps the common offset of its first, hot solve (|f|, |g| near
+// 270 mm^2 at 1000 grains), and FP32 potentials of that size round each plan
+// exponent by about 1.5e-5 at eps = 1.1 mm^2, a floor above the marginal
+// tolerance.  One block row per sample (blockIdx.y).
+__global__ void k_gauge(const SampleDesc *__restrict__ descs, const CtlInit *__restrict__ init) {
+    const SampleDesc &D = descs[blockIdx.y];
+    const double C = init[blockIdx.y].shift;
+    if (C == 0.0) return;
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < D.n_obs) D.f[i] = static_cast<float>(static_cast<double>(D.f[i]) - C);
+    if (i < D.n_model) D.g[i] = static_cast<float>(static_cast<double>(D.g[i]) + C);
 }
 
 // cs_sum of the initial state: sum_j exp((f0 + g_j - c_unm)/eps).  One wave
@@ -1529,6 +1560,8 @@ struct SampleWs {
     int *gflag;
     float *rmass, *cmass;
     double *obj;                   // objective partials (4 per work item) and totals
+    Col8 *colsP;                   // previous E-step's columns and potentials (plan change)
+    float *Fp, *Gp;
     int64_t *mboff;
     // sparse assignment (rho > 0)
     int *nbr = nullptr, *cand_j = nullptr, *cand_n = nullptr, *knn_list = nullptr, *knn_nlist = nullptr;
@@ -1547,6 +1580,7 @@ struct BatchWs {
     int2 *rows2, *cols2;      // workgroups of the two-per-lane tile shape
     int64_t *mbase, *gbase;
     CtlInit *init;
+    ObjIn *objin;             // [2 n]: current and previous plan of each sample
 };
 
 static size_t carve_all(Carver &cv, BatchWs &bw, std::vector<SampleWs> &sw, const std::vector<SampleDims> &dims) {
@@ -1562,6 +1596,7 @@ static size_t carve_all(Carver &cv, BatchWs &bw, std::vector<SampleWs> &sw, cons
     bw.mbase = cv.take<int64_t>(n + 1);
     bw.gbase = cv.take<int64_t>(n + 1);
     bw.init = cv.take<CtlInit>(std::max(n, 1));
+    bw.objin = cv.take<ObjIn>(2 * std::max(n, 1));
     sw.resize(n);
     for (int s = 0; s < n; ++s) {
         const SampleDims &d = dims[s];
@@ -1572,6 +1607,9 @@ static size_t carve_all(Carver &cv, BatchWs &bw, std::vector<SampleWs> &sw, cons
         w.F1 = cv.take<float>(std::max<int64_t>(d.n_obs, 1));
         w.colsE = cv.take<Col8>(std::max<int64_t>(d.n_model, 1));
         w.colsC = cv.take<Col8>(std::max<int64_t>(d.n_model, 1));
+        w.colsP = cv.take<Col8>(std::max<int64_t>(d.n_model, 1));
+        w.Fp = cv.take<float>(std::max<int64_t>(d.n_obs, 1));
+        w.Gp = cv.take<float>(std::max<int64_t>(d.n_model, 1));
         w.colHg = cv.take<double>(std::max<int64_t>(d.n_model, 1) * kHg);
         w.geom = cv.take<GeomF>(1);
         w.grains = cv.take<GrainF>(std::max(d.n_grains, 1));
@@ -1676,13 +1714,237 @@ static int validate_em_params(const laue_em_params *par) {
     int rc;
     LAUE_REQUIRE(par != nullptr, LAUE_EINVAL, "EM parameters are NULL");
     if ((rc = validate_ot(&par->ot, false))) return rc;
-    LAUE_REQUIRE(par->n_stages >= 1 && par->iters_per_stage >= 1 && std::isfinite(par->eps_start) &&
-                     std::isfinite(par->eps_end) && par->eps_start > 0 && par->eps_end > 0,
+    LAUE_REQUIRE(std::isfinite(par->eps_start) && std::isfinite(par->eps_end) && par->eps_start > 0 &&
+                     par->eps_end > 0,
                  LAUE_EINVAL, "bad temperature schedule");
+    LAUE_REQUIRE(std::isfinite(par->eps_cool) && par->eps_cool >= 0.0 && par->eps_cool < 1.0, LAUE_EINVAL,
+                 "eps_cool must be 0 (stage schedule) or in (0, 1)");
+    if (par->eps_cool > 0.0) {
+        LAUE_REQUIRE(std::log(par->eps_start / par->eps_end) / -std::log(par->eps_cool) < 100000.0, LAUE_EINVAL,
+                     "the cooling schedule has more than 100000 temperatures");
+        LAUE_REQUIRE(par->final_iters >= 0 && std::isfinite(par->zeta_tol), LAUE_EINVAL,
+                     "final_iters must be >= 0 and zeta_tol finite");
+    } else {
+        LAUE_REQUIRE(par->n_stages >= 1 && par->iters_per_stage >= 1, LAUE_EINVAL, "bad temperature schedule");
+    }
+    LAUE_REQUIRE(std::isfinite(par->sigma_mm) && par->sigma_mm >= 0.0, LAUE_EINVAL, "sigma_mm must be >= 0");
     if ((rc = validate_gn(&par->gn))) return rc;
     LAUE_REQUIRE(par->launch >= 0 && par->launch <= 2, LAUE_EINVAL, "launch must be 0, 1 or 2");
     LAUE_REQUIRE(par->tile >= 0 && par->tile <= 2, LAUE_EINVAL, "tile must be 0, 1 or 2");
     return LAUE_OK;
+}
+
+// ---------------------------------------------------------------- plan summaries
+
+// Sums of the plan Q = exp((f + g - c)/eps) with its bins (Eqs. elbo,
+// estep_obj): per 64-row item, lane = detected spot, over its block's model
+// spots (or its neighbours under the sparse assignment) and its outlier entry
+// q_i0: mass, <c, Q> over the matches, the outlier entries' cost and
+// sum Q ln Q; per 64-column item the unmatched entries q_0j.  Each item's
+// four sums go to the sample's obj[4 item + k] (column items after the row
+// items); k_obj_final adds them in item order, one workgroup per sample, and
+// writes the totals (mass, <c,Q> matches, total cost, sum Q ln Q) after them.
+__global__ __launch_bounds__(64) void k_obj_rows(const Item *__restrict__ items, const SampleDesc *__restrict__ descs,
+                                                 const ObjIn *__restrict__ oin) {
+    const Item it = items[blockIdx.x];
+    const SampleDesc &D = descs[it.s];
+    const ObjIn A = oin[it.s];
+    const SinkParams p = D.sp;
+    const double kexp = 1.4426950408889634 / A.eps;
+    const float kx = static_cast<float>(kexp);
+    const float K = p.twoD2 * kx;
+    const int i = it.r0 + static_cast<int>(threadIdx.x);
+    const bool act = i < it.r1;
+    const float p1 = act ? D.p1[i] : 0.0f, p2 = act ? D.p2[i] : 0.0f, f = act ? D.f[i] : 0.0f;
+    const float fk = f * kx;
+    double m = 0.0, cin = 0.0, cb = 0.0, ql = 0.0;
+    float am = 0.0f, ac = 0.0f, al = 0.0f;
+    if (act) {
+        if (D.rho > 0) {
+            for (int q = 0; q < D.rho; ++q) {
+                const int j = D.nbr[q * D.n_obs + i];
+                if (j < 0) continue;
+                const float cp = D.ncp[q * D.n_obs + i];
+                const float e = fmaf(-K, cp, fmaf(D.g[j], kx, fk));
+                const float Q = fast_exp2(e);
+                if (Q > 0.0f) {
+                    am += Q;
+                    ac = fmaf(Q, p.twoD2 * cp, ac);
+                    al = fmaf(Q, e, al);
+                }
+            }
+        } else {
+            for (int j = it.c0; j < it.c1; ++j) {
+                const Col8 c = D.colsE[j];
+                const float cp = chord_cp(p1, p2, c.s1, c.s2, c.v1, c.v2, c.vv, c.vv2);
+                const float e = fmaf(-K, cp, fmaf(D.g[j], kx, fk));
+                const float Q = fast_exp2(e);
+                if (Q > 0.0f) {
+                    am += Q;
+                    ac = fmaf(Q, p.twoD2 * cp, ac);
+                    al = fmaf(Q, e, al);
+                }
+            }
+        }
+        m = static_cast<double>(am);
+        cin = static_cast<double>(ac);
+        ql = static_cast<double>(al) * 0.6931471805599453;   // e is in log2 units
+        const double lb = (static_cast<double>(f) + A.g0 - p.c_out) / A.eps;
+        const double qb = exp(lb);
+        if (qb > 0.0) {
+            m += qb;
+            cb = p.c_out * qb;
+            ql += qb * lb;
+        }
+    }
+    m = wave_sum(m);
+    cin = wave_sum(cin);
+    cb = wave_sum(cb);
+    ql = wave_sum(ql);
+    if (threadIdx.x == 0) {
+        double *o = D.obj + 4 * static_cast<int64_t>(it.local);
+        o[0] = m;
+        o[1] = cin;
+        o[2] = cb;
+        o[3] = ql;
+    }
+}
+
+__global__ __launch_bounds__(64) void k_obj_cols(const Item *__restrict__ items, const SampleDesc *__restrict__ descs,
+                                                 const ObjIn *__restrict__ oin) {
+    const Item it = items[blockIdx.x];
+    const SampleDesc &D = descs[it.s];
+    const ObjIn A = oin[it.s];
+    const SinkParams p = D.sp;
+    const int j = it.c0 + static_cast<int>(threadIdx.x);
+    double m = 0.0, cb = 0.0, ql = 0.0;
+    if (j < it.c1) {
+        const double lb = (A.f0 + static_cast<double>(D.g[j]) - p.c_unm) / A.eps;
+        const double qb = exp(lb);
+        if (qb > 0.0) {
+            m = qb;
+            cb = p.c_unm * qb;
+            ql = qb * lb;
+        }
+    }
+    m = wave_sum(m);
+    cb = wave_sum(cb);
+    ql = wave_sum(ql);
+    if (threadIdx.x == 0) {
+        double *o = D.obj + 4 * (static_cast<int64_t>(D.n_row_items) + it.local);
+        o[0] = m;
+        o[1] = 0.0;
+        o[2] = cb;
+        o[3] = ql;
+    }
+}
+
+__global__ __launch_bounds__(64) void k_obj_final(const SampleDesc *__restrict__ descs,
+                                                  const ObjIn *__restrict__ oin) {
+    const SampleDesc &D = descs[blockIdx.x];
+    const ObjIn A = oin[blockIdx.x];
+    const int n = D.n_row_items + D.n_col_items;
+    double t[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int w = threadIdx.x; w < n; w += 64)
+        for (int k = 0; k < 4; ++k) t[k] += D.obj[4 * static_cast<int64_t>(w) + k];
+    for (int k = 0; k < 4; ++k) t[k] = wave_sum(t[k]);
+    if (threadIdx.x != 0) return;
+    const SinkParams p = D.sp;
+    double mass = t[0], cin = t[1], ctot = t[1] + t[2], ql = t[3];
+    const double l00 = (A.f0 + A.g0 - p.c_sink) / A.eps;
+    const double q00 = exp(l00);
+    if (q00 > 0.0) {
+        mass += q00;
+        ctot += p.c_sink * q00;
+        ql += q00 * l00;
+    }
+    double *o = D.obj + 4 * static_cast<int64_t>(n);
+    o[0] = mass;
+    o[1] = cin;
+    o[2] = ctot;
+    o[3] = ql;
+}
+
+// Q_0j = exp((f0 + g_j - c_unm)/eps) of every model spot into the assignment
+// output (0 without bins).  One block row per sample (blockIdx.y).
+__global__ void k_assign_unm(const SampleDesc *__restrict__ descs, const ObjIn *__restrict__ oin) {
+    const SampleDesc &D = descs[blockIdx.y];
+    if (!D.qunm) return;
+    const int64_t j = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (j >= D.n_model) return;
+    const ObjIn A = oin[blockIdx.y];
+    D.qunm[j] = static_cast<float>(exp((A.f0 + static_cast<double>(D.g[j]) - D.sp.c_unm) / A.eps));
+}
+
+// Plan change zeta^2 = ||Q - Q'||_F^2 between the current plan (f, g,
+// columns colsE, oin[s]) and the previous E-step's (fprev, gprev, colsP,
+// oin[n + s]), dense assignment: per 64-row item, lane = detected spot, the
+// squared differences over its block's model spots (entries evaluated in
+// FP32 as in the passes, squares summed in FP32 over the block, then FP64)
+// plus its outlier entry; per 64-column item the unmatched entries; partials
+// into obj[4 item] and the corner entry in k_dq_final.
+__global__ __launch_bounds__(64) void k_dq_rows(const Item *__restrict__ items, const SampleDesc *__restrict__ descs,
+                                                const ObjIn *__restrict__ oin, int n) {
+    const Item it = items[blockIdx.x];
+    const SampleDesc &D = descs[it.s];
+    const ObjIn A = oin[it.s], B = oin[n + it.s];
+    const SinkParams p = D.sp;
+    const float ka = static_cast<float>(1.4426950408889634 / A.eps);
+    const float kb = static_cast<float>(1.4426950408889634 / B.eps);
+    const float Ka = p.twoD2 * ka, Kb = p.twoD2 * kb;
+    const int i = it.r0 + static_cast<int>(threadIdx.x);
+    const bool act = i < it.r1;
+    double s = 0.0;
+    if (act) {
+        const float p1 = D.p1[i], p2 = D.p2[i];
+        const float fa = D.f[i] * ka, fb = D.fprev[i] * kb;
+        float acc = 0.0f;
+        for (int j = it.c0; j < it.c1; ++j) {
+            const Col8 c = D.colsE[j];
+            const Col8 d = D.colsP[j];
+            const float qa = fast_exp2(fmaf(-Ka, chord_cp(p1, p2, c.s1, c.s2, c.v1, c.v2, c.vv, c.vv2),
+                                            fmaf(D.g[j], ka, fa)));
+            const float qb = fast_exp2(fmaf(-Kb, chord_cp(p1, p2, d.s1, d.s2, d.v1, d.v2, d.vv, d.vv2),
+                                            fmaf(D.gprev[j], kb, fb)));
+            const float dq = qa - qb;
+            acc = fmaf(dq, dq, acc);
+        }
+        const double ba = exp((static_cast<double>(D.f[i]) + A.g0 - p.c_out) / A.eps);
+        const double bb = exp((static_cast<double>(D.fprev[i]) + B.g0 - p.c_out) / B.eps);
+        s = static_cast<double>(acc) + (ba - bb) * (ba - bb);
+    }
+    s = wave_sum(s);
+    if (threadIdx.x == 0) D.obj[4 * static_cast<int64_t>(it.local)] = s;
+}
+
+__global__ __launch_bounds__(64) void k_dq_cols(const Item *__restrict__ items, const SampleDesc *__restrict__ descs,
+                                                const ObjIn *__restrict__ oin, int n) {
+    const Item it = items[blockIdx.x];
+    const SampleDesc &D = descs[it.s];
+    const ObjIn A = oin[it.s], B = oin[n + it.s];
+    const int j = it.c0 + static_cast<int>(threadIdx.x);
+    double s = 0.0;
+    if (j < it.c1) {
+        const double ua = exp((A.f0 + static_cast<double>(D.g[j]) - D.sp.c_unm) / A.eps);
+        const double ub = exp((B.f0 + static_cast<double>(D.gprev[j]) - D.sp.c_unm) / B.eps);
+        s = (ua - ub) * (ua - ub);
+    }
+    s = wave_sum(s);
+    if (threadIdx.x == 0) D.obj[4 * (static_cast<int64_t>(D.n_row_items) + it.local)] = s;
+}
+
+// zeta of each sample (one workgroup per sample) into obj[4 n_items]
+__global__ __launch_bounds__(64) void k_dq_final(const SampleDesc *__restrict__ descs, const ObjIn *__restrict__ oin,
+                                                 int n) {
+    const SampleDesc &D = descs[blockIdx.x];
+    const ObjIn A = oin[blockIdx.x], B = oin[n + blockIdx.x];
+    const int m = D.n_row_items + D.n_col_items;
+    double t = 0.0;
+    for (int w = threadIdx.x; w < m; w += 64) t += D.obj[4 * static_cast<int64_t>(w)];
+    t = wave_sum(t);
+    if (threadIdx.x != 0) return;
+    const double a = exp((A.f0 + A.g0 - D.sp.c_sink) / A.eps), b = exp((B.f0 + B.g0 - D.sp.c_sink) / B.eps);
+    D.obj[4 * static_cast<int64_t>(m)] = sqrt(t + (a - b) * (a - b));
 }
 
 // One sample's inputs to the engine.
@@ -2025,6 +2287,11 @@ struct BatchEngine {
             D.k_mm = a.gn ? a.gn->k_mm : 1;
             D.tol_x = a.gn ? a.gn->tol_x : 0.0;
             D.tol_r = a.gn ? a.gn->tol_r : 0.0;
+            D.obj = sw[k].obj;
+            D.colsP = sw[k].colsP;
+            D.fprev = sw[k].Fp;
+            D.gprev = sw[k].Gp;
+            if (a.assign && a.assign->q_unm) D.qunm = a.assign->q_unm;
             if (a.assign && a.assign->j_star && a.assign->grain && a.assign->q_star && a.assign->q_out) {
                 D.jstar = a.assign->j_star;
                 D.gstar = a.assign->grain;
@@ -2170,14 +2437,27 @@ struct BatchEngine {
         eval_on(st, 0, 1);
     }
 
-    // control blocks at temperature eps[k] from the potentials' bins
-    int init_ctl(const std::vector<double> &eps) {
+    // control blocks at temperature eps[k] from the potentials' bins.  gauge:
+    // re-centre the potentials of every sample with the outlier row and column
+    // to f0 = 0 first (k_gauge; the same plan)
+    int init_ctl(const std::vector<double> &eps, bool gauge = false) {
         std::vector<CtlInit> v(n);
+        int64_t longest = 0;
         for (int k = 0; k < n; ++k) {
             const SinkParams &sp = hd[k].sp;
-            v[k] = CtlInit{sp.t_b > 0 ? in[k].pot->f0 : -INFINITY, sp.t_a > 0 ? in[k].pot->g0 : -INFINITY, eps[k]};
+            laue_potentials *pot = in[k].pot;
+            double C = 0.0;
+            if (gauge && !sp.unb && !sp.part && sp.t_b > 0 && std::isfinite(pot->f0) && pot->f0 != 0.0) {
+                C = pot->f0;
+                pot->f0 = 0.0;
+                pot->g0 += C;
+                longest = std::max(longest, std::max(in[k].obs->n, in[k].model->n));
+            }
+            v[k] = CtlInit{sp.t_b > 0 ? pot->f0 : -INFINITY, sp.t_a > 0 ? pot->g0 : -INFINITY, eps[k], C};
         }
         LAUE_CHECK_HIP(hipMemcpyAsync(bw.init, v.data(), n * sizeof(CtlInit), hipMemcpyHostToDevice, s));
+        if (longest > 0)
+            k_gauge<<<dim3(static_cast<unsigned>((longest + 255) / 256), n), 256, 0, s>>>(bw.desc, bw.init);
         k_ctl_init<<<(n + 63) / 64, 64, 0, s>>>(bw.desc, n, bw.init);
         LAUE_CHECK_HIP(hipGetLastError());
         // the host copy must outlive the asynchronous copy
@@ -2197,7 +2477,7 @@ struct BatchEngine {
         int rc;
         // sparse: the neighbour sets of this E-step's columns
         if ((rc = build_neighbors())) return rc;
-        if ((rc = init_ctl(eps))) return rc;
+        if ((rc = init_ctl(eps, true))) return rc;
         // partial OT starts every solve from the Gibbs kernel (f = g = 0, H = 0)
         for (int k = 0; k < n; ++k) {
             if (!hd[k].sp.part) continue;
@@ -2346,20 +2626,116 @@ struct BatchEngine {
         return timer_stop(&mstep_ms);
     }
 
+    // the current plan of every sample (its temperature and final bin
+    // potentials) into objin[0 .. n) (prev = 0) or objin[n .. 2n) (prev = 1)
+    int set_objin(const std::vector<double> &eps, int prev) {
+        std::vector<ObjIn> v(n);
+        for (int k = 0; k < n; ++k) {
+            const bool bins = !hd[k].sp.unb && !hd[k].sp.part;
+            v[k] = ObjIn{eps[k], bins && hd[k].sp.t_b > 0 ? in[k].pot->f0 : -INFINITY,
+                         bins && hd[k].sp.t_a > 0 ? in[k].pot->g0 : -INFINITY};
+        }
+        LAUE_CHECK_HIP(hipMemcpyAsync(bw.objin + (prev ? n : 0), v.data(), n * sizeof(ObjIn), hipMemcpyHostToDevice,
+                                      s));
+        LAUE_CHECK_HIP(hipStreamSynchronize(s));   // the host copy must outlive the copy
+        return LAUE_OK;
+    }
+
+    // hard assignments (and Q_0j) of the current plan (set_objin first)
     int assign() {
-        bool any = false;
-        for (int k = 0; k < n; ++k) any = any || (hd[k].jstar && in[k].obs->n > 0);
-        if (!any) return LAUE_OK;
-        if (rho > 0)
-            k_assign_sparse<<<n_rows, 64, 0, s>>>(bw.rows, bw.desc);
-        else
-            k_assign<<<n_rows, 64, 0, s>>>(bw.rows, bw.desc);
+        bool any = false, anyu = false;
+        int64_t longest = 0;
+        for (int k = 0; k < n; ++k) {
+            any = any || (hd[k].jstar && in[k].obs->n > 0);
+            if (hd[k].qunm && in[k].model->n > 0) {
+                anyu = true;
+                longest = std::max(longest, in[k].model->n);
+            }
+        }
+        if (any) {
+            if (rho > 0)
+                k_assign_sparse<<<n_rows, 64, 0, s>>>(bw.rows, bw.desc);
+            else
+                k_assign<<<n_rows, 64, 0, s>>>(bw.rows, bw.desc);
+            for (int k = 0; k < n; ++k)
+                if (hd[k].jstar) entries[k] += pass_work(k);
+        }
+        if (anyu)
+            k_assign_unm<<<dim3(static_cast<unsigned>((longest + 255) / 256), n), 256, 0, s>>>(bw.desc, bw.objin);
         LAUE_CHECK_HIP(hipGetLastError());
-        for (int k = 0; k < n; ++k)
-            if (hd[k].jstar) entries[k] += pass_work(k);
+        return LAUE_OK;
+    }
+
+    // FP64 summaries of the current plan of every sample (set_objin first):
+    // out[k] = (mass, <c,Q> matches, total cost, sum Q ln Q)
+    int summaries(std::vector<std::array<double, 4>> &out) {
+        if (n_rows) k_obj_rows<<<n_rows, 64, 0, s>>>(bw.rows, bw.desc, bw.objin);
+        if (n_cols) k_obj_cols<<<n_cols, 64, 0, s>>>(bw.cols, bw.desc, bw.objin);
+        k_obj_final<<<n, 64, 0, s>>>(bw.desc, bw.objin);
+        LAUE_CHECK_HIP(hipGetLastError());
+        out.assign(n, {0.0, 0.0, 0.0, 0.0});
+        for (int k = 0; k < n; ++k) {
+            const int64_t items = static_cast<int64_t>(hd[k].n_row_items) + hd[k].n_col_items;
+            LAUE_CHECK_HIP(hipMemcpyAsync(out[k].data(), sw[k].obj + 4 * items, 4 * sizeof(double),
+                                          hipMemcpyDeviceToHost, s));
+        }
+        LAUE_CHECK_HIP(hipStreamSynchronize(s));
+        return LAUE_OK;
+    }
+
+    // the current plan becomes the previous one (columns, potentials, objin)
+    int save_prev(const std::vector<double> &eps) {
+        for (int k = 0; k < n; ++k) {
+            if (in[k].model->n > 0) {
+                LAUE_CHECK_HIP(hipMemcpyAsync(sw[k].colsP, sw[k].colsE, in[k].model->n * sizeof(Col8),
+                                              hipMemcpyDeviceToDevice, s));
+                LAUE_CHECK_HIP(hipMemcpyAsync(sw[k].Gp, in[k].pot->g, in[k].model->n * sizeof(float),
+                                              hipMemcpyDeviceToDevice, s));
+            }
+            if (in[k].obs->n > 0)
+                LAUE_CHECK_HIP(hipMemcpyAsync(sw[k].Fp, in[k].pot->f, in[k].obs->n * sizeof(float),
+                                              hipMemcpyDeviceToDevice, s));
+        }
+        return set_objin(eps, 1);
+    }
+
+    // zeta = ||Q - Q_prev||_F of every sample (dense; set_objin and save_prev first)
+    int plan_change(std::vector<double> &zeta) {
+        if (n_rows) k_dq_rows<<<n_rows, 64, 0, s>>>(bw.rows, bw.desc, bw.objin, n);
+        if (n_cols) k_dq_cols<<<n_cols, 64, 0, s>>>(bw.cols, bw.desc, bw.objin, n);
+        k_dq_final<<<n, 64, 0, s>>>(bw.desc, bw.objin, n);
+        LAUE_CHECK_HIP(hipGetLastError());
+        zeta.assign(n, 0.0);
+        for (int k = 0; k < n; ++k) {
+            const int64_t items = static_cast<int64_t>(hd[k].n_row_items) + hd[k].n_col_items;
+            LAUE_CHECK_HIP(hipMemcpyAsync(&zeta[k], sw[k].obj + 4 * items, sizeof(double), hipMemcpyDeviceToHost,
+                                          s));
+        }
+        LAUE_CHECK_HIP(hipStreamSynchronize(s));
+        for (int k = 0; k < n; ++k) entries[k] += 2 * pass_work(k);
         return LAUE_OK;
     }
 };
+
+// Temperatures of an EM run: the stage schedule (n_stages x iters_per_stage,
+// geometric from eps_start to eps_end) or, with eps_cool in (0, 1), the
+// cooling of Alg. LaueOT (Sec. 5.1): eps_start, then times eps_cool while the
+// last one is above eps_end (FP64 products in this order).
+static std::vector<double> em_temperatures(const laue_em_params &p) {
+    std::vector<double> t;
+    if (p.eps_cool > 0.0) {
+        t.push_back(p.eps_start);
+        while (t.back() > p.eps_end) t.push_back(t.back() * p.eps_cool);
+        return t;
+    }
+    const int S = p.n_stages;
+    for (int st = 0; st < S; ++st) {
+        const double e = S == 1 ? p.eps_start
+                                : p.eps_start * std::pow(p.eps_end / p.eps_start, static_cast<double>(st) / (S - 1));
+        for (int it = 0; it < p.iters_per_stage; ++it) t.push_back(e);
+    }
+    return t;
+}
 
 static int run_em(BatchEngine &e, const std::vector<const laue_em_params *> &par, std::vector<laue_em_stats> &stats) {
     int rc;
@@ -2368,30 +2744,80 @@ static int run_em(BatchEngine &e, const std::vector<const laue_em_params *> &par
     stats.assign(n, laue_em_stats{});
     e.launch_mode = par[0]->launch;
     e.tile_mode = par[0]->tile;
-    const int S = par[0]->n_stages;
-    std::vector<double> eps(n);
+    std::vector<std::vector<double>> temps(n);
+    for (int k = 0; k < n; ++k) temps[k] = em_temperatures(*par[k]);
+    const int L = static_cast<int>(temps[0].size());
+    for (int k = 1; k < n; ++k)
+        LAUE_REQUIRE(static_cast<int>(temps[k].size()) == L, LAUE_EINVAL,
+                     "samples of a batch need the same number of EM temperatures");
+    const bool cooling = par[0]->eps_cool > 0.0;
+    const int n_final = cooling ? par[0]->final_iters : 0;
+    const bool zeta_on = cooling && e.rho == 0 && n == 1;
+    const bool zeta_stop = zeta_on && par[0]->zeta_tol > 0.0;
+    const int total = L + n_final;
+    // the stage of a temperature (chunk sizing and tile tuning): the stage
+    // index, or one stage per eight cooling steps
+    const int ips = std::max(par[0]->iters_per_stage, 1);
+    std::vector<double> eps(n), zeta;
     std::vector<laue_ot_stats> os;
-    for (int st = 0; st < S; ++st) {
-        for (int k = 0; k < n; ++k)
-            eps[k] = S == 1 ? par[k]->eps_start
-                            : par[k]->eps_start * std::pow(par[k]->eps_end / par[k]->eps_start,
-                                                           static_cast<double>(st) / (S - 1));
-        for (int it = 0; it < par[0]->iters_per_stage; ++it) {
-            if (st == 0 && it == 0 && (rc = e.eval(0, 1))) return rc;    // later: after each M-step
-            if ((rc = e.sinkhorn(eps, par[0]->ot.chunk, os, st))) return rc;
-            for (int k = 0; k < n; ++k) {
-                stats[k].sinkhorn_iters += os[k].n_iter;
-                stats[k].not_converged += os[k].converged ? 0 : 1;
-                stats[k].last_err = os[k].err;
-                stats[k].n_em_iter += 1;
-            }
-            // all samples share k_gn (checked by the caller); the M-step ends
-            // with the forward evaluation at the new grains
-            if ((rc = e.mstep(par[0]->gn.k_gn, true))) return rc;
-        }
+    for (int k = 0; k < n; ++k) {
+        stats[k].zeta = NAN;
+        stats[k].objective = laue_objective{NAN, NAN, NAN, NAN, NAN};
     }
-    // assignments at the final grains with the final potentials
-    if ((rc = e.assign())) return rc;
+    bool have_prev = false;
+    for (int it = 0; it < total; ++it) {
+        for (int k = 0; k < n; ++k) eps[k] = temps[k][std::min(it, L - 1)];
+        const int stage = cooling ? std::min(it, L) / 8 : it / ips;
+        if (it == 0 && (rc = e.eval(0, 1))) return rc;    // later: after each M-step
+        if ((rc = e.sinkhorn(eps, par[0]->ot.chunk, os, stage))) return rc;
+        for (int k = 0; k < n; ++k) {
+            stats[k].sinkhorn_iters += os[k].n_iter;
+            stats[k].not_converged += os[k].converged ? 0 : 1;
+            stats[k].last_err = os[k].err;
+            stats[k].n_em_iter += 1;
+            if (it >= L) stats[k].final_iters_run += 1;
+        }
+        bool last = it == total - 1;
+        // the plan change from the previous EM iteration (Alg. LaueOT's stop)
+        if (zeta_on && it >= L - 1) {
+            if ((rc = e.set_objin(eps, 0))) return rc;
+            if (have_prev) {
+                if ((rc = e.plan_change(zeta))) return rc;
+                stats[0].zeta = zeta[0];
+                if (zeta_stop && zeta[0] <= par[0]->zeta_tol) last = true;
+            }
+        }
+        if (zeta_on && it >= L - 2 && !last) {
+            if ((rc = e.set_objin(eps, 0)) || (rc = e.save_prev(eps))) return rc;
+            have_prev = true;
+        }
+        // Alg. LaueOT's outputs: the last E-step's plan (assignments, likelihood)
+        if (last) {
+            if ((rc = e.set_objin(eps, 0)) || (rc = e.assign())) return rc;
+            bool want = false;
+            for (int k = 0; k < n; ++k) want = want || par[k]->sigma_mm > 0.0;
+            if (want) {
+                std::vector<std::array<double, 4>> t;
+                if ((rc = e.summaries(t))) return rc;
+                for (int k = 0; k < n; ++k) {
+                    if (!(par[k]->sigma_mm > 0.0)) continue;
+                    laue_objective &o = stats[k].objective;
+                    o.mass = t[k][0];
+                    o.cost_inlier = t[k][1];
+                    o.cost_total = t[k][2];
+                    o.entropy = -t[k][3];
+                    const bool bins = !e.hd[k].sp.unb && !e.hd[k].sp.part;
+                    const double sg = par[k]->sigma_mm, s2 = 2.0 * sg * sg;
+                    const double kap = (par[k]->ot.distance / sg) * (par[k]->ot.distance / sg);
+                    o.sem_objective = bins ? kap * t[k][0] - t[k][2] / s2 + eps[k] / s2 * (-t[k][3]) : NAN;
+                }
+            }
+        }
+        // all samples share k_gn (checked by the caller); the M-step ends
+        // with the forward evaluation at the new grains
+        if ((rc = e.mstep(par[0]->gn.k_gn, true))) return rc;
+        if (last) break;
+    }
     for (int k = 0; k < n; ++k) {
         stats[k].cost_entries = e.entries[k];
         stats[k].sinkhorn_ms = e.sink_ms;
@@ -2458,135 +2884,6 @@ extern "C" size_t laue_em_batched_workspace_size(int32_t n, const laue_geometry 
 
 // ---------------------------------------------------------------- objectives
 
-// Sums of the plan Q = exp((f + g - c)/eps) with its bins (Eqs. elbo,
-// estep_obj): per 64-row item, lane = detected spot, over its block's model
-// spots (or its neighbours under the sparse assignment) and its outlier entry
-// q_i0: mass, <c, Q> over the matches, the outlier entries' cost and
-// sum Q ln Q; per 64-column item the unmatched entries q_0j.  Each item's
-// four sums go to obj[4 local + k]; k_obj_final adds them in item order.
-struct ObjArgs {
-    double eps, f0, g0;
-    double *obj;                   // [4 * (row items + column items) + 8]
-};
-
-__global__ __launch_bounds__(64) void k_obj_rows(const Item *__restrict__ items, const SampleDesc *__restrict__ descs,
-                                                 ObjArgs A) {
-    const Item it = items[blockIdx.x];
-    const SampleDesc &D = descs[it.s];
-    const SinkParams p = D.sp;
-    const double kexp = 1.4426950408889634 / A.eps;
-    const float kx = static_cast<float>(kexp);
-    const float K = p.twoD2 * kx;
-    const int i = it.r0 + static_cast<int>(threadIdx.x);
-    const bool act = i < it.r1;
-    const float p1 = act ? D.p1[i] : 0.0f, p2 = act ? D.p2[i] : 0.0f, f = act ? D.f[i] : 0.0f;
-    const float fk = f * kx;
-    double m = 0.0, cin = 0.0, cb = 0.0, ql = 0.0;
-    float am = 0.0f, ac = 0.0f, al = 0.0f;
-    if (act) {
-        if (D.rho > 0) {
-            for (int q = 0; q < D.rho; ++q) {
-                const int j = D.nbr[q * D.n_obs + i];
-                if (j < 0) continue;
-                const float cp = D.ncp[q * D.n_obs + i];
-                const float e = fmaf(-K, cp, fmaf(D.g[j], kx, fk));
-                const float Q = fast_exp2(e);
-                if (Q > 0.0f) {
-                    am += Q;
-                    ac = fmaf(Q, p.twoD2 * cp, ac);
-                    al = fmaf(Q, e, al);
-                }
-            }
-        } else {
-            for (int j = it.c0; j < it.c1; ++j) {
-                const Col8 c = D.colsE[j];
-                const float cp = chord_cp(p1, p2, c.s1, c.s2, c.v1, c.v2, c.vv, c.vv2);
-                const float e = fmaf(-K, cp, fmaf(D.g[j], kx, fk));
-                const float Q = fast_exp2(e);
-                if (Q > 0.0f) {
-                    am += Q;
-                    ac = fmaf(Q, p.twoD2 * cp, ac);
-                    al = fmaf(Q, e, al);
-                }
-            }
-        }
-        m = static_cast<double>(am);
-        cin = static_cast<double>(ac);
-        ql = static_cast<double>(al) * 0.6931471805599453;   // e is in log2 units
-        const double lb = (static_cast<double>(f) + A.g0 - p.c_out) / A.eps;
-        const double qb = exp(lb);
-        if (qb > 0.0) {
-            m += qb;
-            cb = p.c_out * qb;
-            ql += qb * lb;
-        }
-    }
-    m = wave_sum(m);
-    cin = wave_sum(cin);
-    cb = wave_sum(cb);
-    ql = wave_sum(ql);
-    if (threadIdx.x == 0) {
-        double *o = A.obj + 4 * static_cast<int64_t>(it.local);
-        o[0] = m;
-        o[1] = cin;
-        o[2] = cb;
-        o[3] = ql;
-    }
-}
-
-__global__ __launch_bounds__(64) void k_obj_cols(const Item *__restrict__ items, const SampleDesc *__restrict__ descs,
-                                                 ObjArgs A) {
-    const Item it = items[blockIdx.x];
-    const SampleDesc &D = descs[it.s];
-    const SinkParams p = D.sp;
-    const int j = it.c0 + static_cast<int>(threadIdx.x);
-    double m = 0.0, cb = 0.0, ql = 0.0;
-    if (j < it.c1) {
-        const double lb = (A.f0 + static_cast<double>(D.g[j]) - p.c_unm) / A.eps;
-        const double qb = exp(lb);
-        if (qb > 0.0) {
-            m = qb;
-            cb = p.c_unm * qb;
-            ql = qb * lb;
-        }
-    }
-    m = wave_sum(m);
-    cb = wave_sum(cb);
-    ql = wave_sum(ql);
-    if (threadIdx.x == 0) {
-        double *o = A.obj + 4 * (static_cast<int64_t>(D.n_row_items) + it.local);
-        o[0] = m;
-        o[1] = 0.0;
-        o[2] = cb;
-        o[3] = ql;
-    }
-}
-
-// totals in item order: out = (mass, <c,Q> matches, total cost, sum Q ln Q)
-__global__ __launch_bounds__(64) void k_obj_final(const SampleDesc *__restrict__ descs, ObjArgs A) {
-    const SampleDesc &D = descs[0];
-    const int n = D.n_row_items + D.n_col_items;
-    double t[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int w = threadIdx.x; w < n; w += 64)
-        for (int k = 0; k < 4; ++k) t[k] += A.obj[4 * static_cast<int64_t>(w) + k];
-    for (int k = 0; k < 4; ++k) t[k] = wave_sum(t[k]);
-    if (threadIdx.x != 0) return;
-    const SinkParams p = D.sp;
-    double mass = t[0], cin = t[1], ctot = t[1] + t[2], ql = t[3];
-    const double l00 = (A.f0 + A.g0 - p.c_sink) / A.eps;
-    const double q00 = exp(l00);
-    if (q00 > 0.0) {
-        mass += q00;
-        ctot += p.c_sink * q00;
-        ql += q00 * l00;
-    }
-    double *o = A.obj + 4 * static_cast<int64_t>(n);
-    o[0] = mass;
-    o[1] = cin;
-    o[2] = ctot;
-    o[3] = ql;
-}
-
 extern "C" int laue_sinkhorn(const laue_geometry *geom, const laue_obs_spots *obs,
                              const laue_model_spots *model, const laue_ot_params *par,
                              laue_potentials *pot, laue_ot_stats *stats, void *ws, size_t ws_bytes,
@@ -2627,24 +2924,16 @@ extern "C" int laue_objectives(const laue_geometry *geom, const laue_obs_spots *
         return rc;
     if ((rc = launch_pack(model, e.sw[0].colsE, e.s))) return rc;
     if ((rc = e.build_neighbors())) return rc;
+    std::vector<std::array<double, 4>> t;
+    if ((rc = e.set_objin({par->eps}, 0)) || (rc = e.summaries(t))) return rc;
     const bool bins = par->outlier_model == 0;
-    ObjArgs A{par->eps, bins && par->t_b > 0 ? pot->f0 : -INFINITY,
-              bins && e.hd[0].sp.t_a > 0 ? pot->g0 : -INFINITY, e.sw[0].obj};
-    if (e.n_rows) k_obj_rows<<<e.n_rows, 64, 0, e.s>>>(e.bw.rows, e.bw.desc, A);
-    if (e.n_cols) k_obj_cols<<<e.n_cols, 64, 0, e.s>>>(e.bw.cols, e.bw.desc, A);
-    k_obj_final<<<1, 64, 0, e.s>>>(e.bw.desc, A);
-    LAUE_CHECK_HIP(hipGetLastError());
-    const int64_t n_items = static_cast<int64_t>(e.hd[0].n_row_items) + e.hd[0].n_col_items;
-    double t[4];
-    LAUE_CHECK_HIP(hipMemcpyAsync(t, e.sw[0].obj + 4 * n_items, sizeof(t), hipMemcpyDeviceToHost, e.s));
-    LAUE_CHECK_HIP(hipStreamSynchronize(e.s));
-    out->mass = t[0];
-    out->cost_inlier = t[1];
-    out->cost_total = t[2];
-    out->entropy = -t[3];
+    out->mass = t[0][0];
+    out->cost_inlier = t[0][1];
+    out->cost_total = t[0][2];
+    out->entropy = -t[0][3];
     const double s2 = 2.0 * sigma_mm * sigma_mm;
     const double kappa = (par->distance / sigma_mm) * (par->distance / sigma_mm);
-    out->sem_objective = bins ? kappa * t[0] - t[2] / s2 + par->eps / s2 * (-t[3]) : NAN;
+    out->sem_objective = bins ? kappa * t[0][0] - t[0][2] / s2 + par->eps / s2 * (-t[0][3]) : NAN;
     return LAUE_OK;
 }
 
@@ -2763,6 +3052,59 @@ extern "C" int laue_sparse_neighbors(const laue_geometry *geom, const laue_obs_s
     return LAUE_OK;
 }
 
+// cost of each detected spot's farthest kept neighbour (mm^2), -1 when it has none
+__global__ void k_far_cost(const SampleDesc *__restrict__ descs, float *__restrict__ far) {
+    const SampleDesc &D = descs[0];
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= D.n_obs) return;
+    float c = -1.0f;
+    for (int q = D.rho - 1; q >= 0; --q)
+        if (D.nbr[q * D.n_obs + i] >= 0) {
+            c = D.ncp[q * D.n_obs + i] * D.sp.twoD2;
+            break;
+        }
+    far[i] = c;
+}
+
+extern "C" int laue_eps_init(const laue_geometry *geom, const laue_obs_spots *obs, const laue_model_spots *model,
+                             const laue_ot_params *par, double *eps_init, void *ws, size_t ws_bytes, void *stream) {
+    clear_error();
+    int rc;
+    if ((rc = validate_ot(par, false))) return rc;
+    LAUE_REQUIRE(par->rho > 0, LAUE_EINVAL, "rho must be 8, 16 or 32");
+    LAUE_REQUIRE(eps_init != nullptr && obs != nullptr, LAUE_EINVAL, "NULL argument");
+    BatchEngine e;
+    laue_model_spots *m = const_cast<laue_model_spots *>(model);
+    laue_potentials pot{nullptr, nullptr, 0.0, 0.0};
+    float dummy = 0.0f;     // the potentials are not read
+    pot.f = &dummy;
+    pot.g = &dummy;
+    if ((rc = e.setup({SampleIn{geom, nullptr, obs, m, par, nullptr, &pot, 0.0, nullptr, nullptr}}, ws, ws_bytes,
+                      stream, true)))
+        return rc;
+    if ((rc = launch_pack(model, e.sw[0].colsE, e.s))) return rc;
+    if ((rc = e.build_neighbors())) return rc;
+    *eps_init = 1.0;
+    if (obs->n == 0) return LAUE_OK;
+    float *far = e.sw[0].Fp;        // [n_obs] of the workspace
+    k_far_cost<<<static_cast<unsigned>((obs->n + 255) / 256), 256, 0, e.s>>>(e.bw.desc, far);
+    LAUE_CHECK_HIP(hipGetLastError());
+    std::vector<float> h(obs->n);
+    LAUE_CHECK_HIP(hipMemcpyAsync(h.data(), far, obs->n * sizeof(float), hipMemcpyDeviceToHost, e.s));
+    LAUE_CHECK_HIP(hipStreamSynchronize(e.s));
+    std::vector<double> v;
+    v.reserve(h.size());
+    for (float c : h)
+        if (c >= 0.0f) v.push_back(static_cast<double>(c));
+    if (v.empty()) return LAUE_OK;
+    const size_t mid = v.size() / 2;
+    std::nth_element(v.begin(), v.begin() + mid, v.end());
+    double med = v[mid];
+    if (v.size() % 2 == 0) med = 0.5 * (med + *std::max_element(v.begin(), v.begin() + mid));
+    *eps_init = med / std::log(100.0);
+    return LAUE_OK;
+}
+
 extern "C" int laue_mstep(const laue_geometry *geom, const laue_planes *planes,
                           const laue_obs_spots *obs, laue_model_spots *model,
                           const laue_ot_params *par, const laue_potentials *pot,
@@ -2800,6 +3142,8 @@ extern "C" int laue_em(const laue_geometry *geom, const laue_planes *planes,
     if ((rc = validate_em_params(par)) || (rc = validate_planes(planes)) || (rc = validate_grains(grains)))
         return rc;
     LAUE_REQUIRE(bins_ok(&par->ot, pot), LAUE_EINVAL, "bin potentials must be finite");
+    LAUE_REQUIRE(!(par->eps_cool > 0.0 && par->zeta_tol > 0.0) || par->ot.rho == 0, LAUE_EINVAL,
+                 "the plan-change stop needs the dense assignment (ot.rho = 0)");
     BatchEngine e;
     if ((rc = e.setup({SampleIn{geom, planes, obs, model, &par->ot, grains, pot, par->gn.mu_rel, assign, nullptr,
                                 &par->gn}},
@@ -2831,6 +3175,10 @@ extern "C" int laue_em_batched(int32_t n, const laue_geometry *geoms, const laue
         LAUE_REQUIRE(pars[k].launch == pars[0].launch && pars[k].ot.chunk == pars[0].ot.chunk &&
                          pars[k].tile == pars[0].tile,
                      LAUE_EINVAL, "samples of a batch share launch, tile and ot.chunk");
+        LAUE_REQUIRE(pars[k].eps_cool == pars[0].eps_cool && pars[k].final_iters == pars[0].final_iters,
+                     LAUE_EINVAL, "samples of a batch share eps_cool and final_iters");
+        LAUE_REQUIRE(!(pars[k].eps_cool > 0.0 && pars[k].zeta_tol > 0.0), LAUE_EINVAL,
+                     "the plan-change stop runs in laue_em only (one sample)");
         LAUE_REQUIRE(bins_ok(&pars[k].ot, pots + k), LAUE_EINVAL, "bin potentials must be finite");
         in[k] = SampleIn{geoms + k, planes + k, obs + k, models + k, &pars[k].ot, grains + k, pots + k,
                          pars[k].gn.mu_rel, assigns ? assigns + k : nullptr, nullptr, &pars[k].gn};

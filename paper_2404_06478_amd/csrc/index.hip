@@ -947,7 +947,8 @@ extern "C" int laue_score_candidates(const laue_geometry *geom, const laue_plane
                      par->distance > 0 && std::isfinite(par->c_out) && par->c_out > 0 &&
                      std::isfinite(par->f_out) && std::isfinite(par->mu_rel) && par->mu_rel >= 0 &&
                      std::isfinite(par->eps_start) && std::isfinite(par->eps_end) &&
-                     par->eps_start > 0 && par->eps_end > 0,
+                     par->eps_start > 0 && par->eps_end > 0 && std::isfinite(par->eps_cool) &&
+                     par->eps_cool >= 0 && par->eps_cool <= 1,
                  LAUE_EINVAL, "bad scoring parameters");
     LAUE_REQUIRE(out->lbar_off && (out->lbar_cap == 0 || (out->lbar_row && out->lbar_val)), LAUE_EINVAL,
                  "SPOT output arrays are NULL");
@@ -1021,10 +1022,13 @@ extern "C" int laue_score_candidates(const laue_geometry *geom, const laue_plane
         const unsigned pg = static_cast<unsigned>(std::min<int64_t>((L + 255) / 256, 1024));
         k_slot_pairs<<<pg, 256, 0, s>>>(w.e.offs, w.ooff, nb, C, nullptr, pairs);
         LAUE_CHECK_HIP(hipGetLastError());
+        double eps_cooled = par->eps_start;
         for (int it = 0; it < par->k_refine; ++it) {
-            const double eps = par->k_refine == 1 ? par->eps_start
+            const double eps = par->eps_cool > 0.0 ? eps_cooled
+                               : par->k_refine == 1 ? par->eps_start
                                : par->eps_start * std::pow(par->eps_end / par->eps_start,
                                                            static_cast<double>(it) / (par->k_refine - 1));
+            eps_cooled *= par->eps_cool;
             const float K = static_cast<float>(2.0 * D2 * l2e / eps);
             const float bin_e = static_cast<float>(std::exp(-par->c_out / eps));
             if ((rc = launch_eval(w.e.geom, planes, w.e.grains, C, w.plane, w.grain, w.block, total,

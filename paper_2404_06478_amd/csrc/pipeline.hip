@@ -325,6 +325,8 @@ extern "C" int laue_index(const laue_geometry *geom, const laue_planes *planes, 
     model.n = n_model;
     st.n_model_spots = n_model;
     laue_em_params em = par->em;
+    // the likelihood of the final plan at the scoring noise unless given
+    if (!(em.sigma_mm > 0.0)) em.sigma_mm = par->score.sigma_mm;
     const double tb = std::ceil(par->t_b_frac * static_cast<double>(n_model));
     em.ot.t_b = std::max(tb, static_cast<double>(n_model - obs->n));
     const int64_t nf = std::max<int64_t>(obs->n, 1), ng = std::max<int64_t>(n_model, 1);
@@ -333,7 +335,10 @@ extern "C" int laue_index(const laue_geometry *geom, const laue_planes *planes, 
     LAUE_CHECK_HIP(hipGetLastError());
     laue_potentials pot{w.f, w.g, 0.0, 0.0};
     laue_em_stats es{};
-    rc = laue_em(geom, planes, obs, &model, &em, &protos, &pot, with_assign ? &out->assign : nullptr, &es,
+    // the model spots live in the workspace: no per-model-spot output
+    laue_assignments asg = out->assign;
+    asg.q_unm = nullptr;
+    rc = laue_em(geom, planes, obs, &model, &em, &protos, &pot, with_assign ? &asg : nullptr, &es,
                  w.scratch, w.scratch_bytes, stream);
     if (rc < 0) return rc;
     st.em = es;

@@ -69,3 +69,21 @@ def test_bad_arguments_are_rejected(lib):
     g.n_rot = 0
     assert lib.laue_forward_workspace_size(ctypes.byref(g), 10, 10) == 0
     assert lib.laue_sinkhorn_workspace_size(ctypes.byref(g), 10, 10, 1) == 0
+
+
+def test_ot_defaults_match_the_oracle(lib):
+    """laue_ot_defaults (host only): the outlier row and column of Sec. 7 equal
+    the oracle's c_out (3-sigma miss) and T_b = ceil(0.4 |J|); bad input is
+    rejected."""
+    from oracle import cost, sinkhorn
+    from paper_2404_06478_amd import _abi
+    p = _abi.laue_ot_params()
+    for sigma, D, J in ((1.0, 150.0, 496312), (0.3, 150.0, 238), (0.4, 160.0, 0)):
+        assert lib.laue_ot_defaults(sigma, D, J, ctypes.byref(p)) == 0
+        assert p.c_out == pytest.approx(cost.c_out(sigma, D), rel=1e-14)
+        assert p.c_sink == p.c_out and p.c_unm == 0.0
+        assert p.t_b == sinkhorn.default_tb(J)
+        assert p.eps == pytest.approx(2.0 * sigma ** 2, rel=1e-15)
+        assert (p.tol, p.n_max, p.rho, p.outlier_model) == (1e-5, 2000, 0, 0)
+    assert lib.laue_ot_defaults(0.0, 150.0, 10, ctypes.byref(p)) == _abi.LAUE_EINVAL
+    assert lib.laue_ot_defaults(1.0, 150.0, -1, ctypes.byref(p)) == _abi.LAUE_EINVAL

@@ -81,6 +81,46 @@ def test_sinkhorn_full_size_marginals(gpu_lib):
         assert Q.min() >= 0.0 and Q.max() <= 1.0 + 1e-6
 
 
+def test_cold_stage_converges_full_size(gpu_lib):
+    """1000 grains, 70% outliers: the EM runs the schedule 111 -> 3.51 sigma^2
+    (16 iterations), then a Sinkhorn at the last temperature 1.11 sigma^2 from
+    the warm potentials meets the marginal contract (row error <= 1e-5) well
+    before its cap; sampled rows and columns of the plan, summed in FP64 on the
+    GPU's potentials, meet it too."""
+    laue = gpu_lib
+    p = ig.LEARNED
+    geom = laue.geometry_from_preset(p)
+    planes = laue.laue_planes_cubic(p.a, p.centering, p.n_max)
+    q, x = ig.random_grains(p)
+    obs = laue.laue_simulate(geom, planes, laue.Grains(q, x), p.sigma_mm, p.distance, p.outlier_frac, p.seed)
+    q0, x0 = ig.perturb_grains(q, x, 0.5, 0.5, p.seed + 17)
+    grains = laue.Grains(q0, x0)
+    model = laue.laue_forward_enumerate(geom, planes, grains, True)
+    base = laue.ot_defaults(p.sigma_mm, p.distance, model.n)
+    c_out, t_b = base.c_out, base.t_b
+    s2 = p.sigma_mm ** 2
+    ot = laue.ot_params(111.0 * s2, p.distance, c_out, t_b, tol=1e-5, n_max=2000)
+    out = laue.laue_em(geom, planes, obs, model, laue.em_params(ot, 111.0 * s2, 3.51 * s2, 4, 4), grains,
+                       assign=False)
+    assert out["not_converged"] == 0 and out["n_em_iter"] == 16
+    eps = 1.11 * s2
+    f, g = out["f"], out["g"]
+    ot = laue.ot_params(eps, p.distance, c_out, t_b, tol=1e-5, n_max=2000)
+    f0, g0, st, rc = laue.laue_sinkhorn(geom, obs, model, ot, f, g, out["f0"], out["g0"])
+    print(f"cold stage: {st}")
+    assert rc == 0 and st["converged"] and st["err"] <= 1e-5 and st["n_iter"] < 200
+    nI = np.diff(obs.block_off)
+    nJ = np.diff(model.block_off)
+    fc, gc = f.double().cpu().numpy(), g.double().cpu().numpy()
+    for b in (int(np.argmax(nI * nJ)), 37, 1):
+        Q = laue.laue_plan_block(geom, obs, model, ot, f, g, b).double().cpu().numpy()
+        r0, c0 = obs.block_off[b], model.block_off[b]
+        q_out = np.exp((fc[r0:r0 + nI[b]] + g0 - c_out) / eps)
+        q_unm = np.exp((f0 + gc[c0:c0 + nJ[b]]) / eps)
+        assert np.max(np.abs(Q.sum(axis=1) + q_out - 1.0)) < 1.2e-5
+        assert np.max(np.abs(Q.sum(axis=0) + q_unm - 1.0)) < 2e-6
+
+
 def test_network_forward_full_size_sampled(gpu_lib):
     """2^20 candidates through the inference launch (chunks of 65,536 rows):
     sampled rows equal the oracle network's output."""

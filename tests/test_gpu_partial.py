@@ -91,7 +91,7 @@ def _em_both(laue, P, frac, rho=0):
     eps_list = oem.eps_schedule(p.eps_start, p.eps_end, p.n_stages, p.iters_per_stage)
     c_out = cost.c_out(p.sigma_mm, p.distance)
     ref = oem.run(P.planes, P.geom, p.distance, P.obs["p12"], P.obs["offsets"], P.model, P.q0, P.x0, eps_list,
-                  c_out, k_gn=2, tol=1e-5, n_max=2000, rho=rho or None, partial_frac=frac)
+                  c_out, k_gn=2, tol=1e-5, n_max=2000, rho=rho or None, partial_frac=frac, record=True)
     geom, planes, obs, model = _problems.gpu_objects(laue, P)
     ot = laue.ot_params(p.eps_start, p.distance, c_out, 0.0, tol=1e-5, n_max=2000, rho=rho, partial_frac=frac)
     par = laue.em_params(ot, p.eps_start, p.eps_end, p.n_stages, p.iters_per_stage, k_gn=2)
@@ -113,7 +113,7 @@ def test_partial_em_matches_oracle(gpu_lib, rho):
     assert np.max(np.linalg.norm(xg - ref["x"], axis=1)) < 0.01
     assert np.max(np.degrees(metrics.misorientation(qg, P.q_true))) < 0.1
     C, _, _ = oem.build_costs(P.planes, P.geom, p.distance, P.obs["p12"], P.obs["offsets"], P.model,
-                              ref["q"], ref["x"])
+                              ref["stats"][-2]["q"], ref["stats"][-2]["x"])     # the last E-step's geometry
     if rho:
         C = sparse.masked_blocks(C, rho)
     js, _, _ = po.hard_assignment(C, ref["f"], ref["g"], p.eps_end)

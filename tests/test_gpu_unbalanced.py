@@ -105,7 +105,7 @@ def _em_both(laue, P, kl, rho=0, k_gn=2):
     eps_list = oem.eps_schedule(p.eps_start, p.eps_end, p.n_stages, p.iters_per_stage)
     c_out = cost.c_out(p.sigma_mm, p.distance)
     ref = oem.run(P.planes, P.geom, p.distance, P.obs["p12"], P.obs["offsets"], P.model, P.q0, P.x0, eps_list,
-                  c_out, k_gn=k_gn, tol=1e-5, n_max=2000, rho=rho or None, unbalanced_kl=(kappa, lam))
+                  c_out, k_gn=k_gn, tol=1e-5, n_max=2000, rho=rho or None, unbalanced_kl=(kappa, lam), record=True)
     geom, planes, obs, model = _problems.gpu_objects(laue, P)
     ot = laue.ot_params(p.eps_start, p.distance, c_out, 0.0, tol=1e-5, n_max=2000, rho=rho,
                         unbalanced_kl=(kappa, lam))
@@ -129,7 +129,7 @@ def test_unbalanced_em_matches_oracle(gpu_lib, rho):
     assert np.max(np.degrees(metrics.misorientation(qg, P.q_true))) < 0.1
     # hard assignments agree with the oracle's at its final state (near-ties aside)
     C, _, _ = oem.build_costs(P.planes, P.geom, p.distance, P.obs["p12"], P.obs["offsets"], P.model,
-                              ref["q"], ref["x"])
+                              ref["stats"][-2]["q"], ref["stats"][-2]["x"])     # the last E-step's geometry
     if rho:
         C = sparse.masked_blocks(C, rho)
     js, _, _ = ub.hard_assignment(C, ref["f"], ref["g"], p.eps_end)
