@@ -305,6 +305,25 @@ int laue_sinkhorn(const laue_geometry *geom, const laue_obs_spots *obs,
                   laue_potentials *pot, laue_ot_stats *stats,
                   void *ws, size_t ws_bytes, void *stream);
 
+/* laue_sinkhorn for callers that cannot allocate device memory (code under
+ * HIP graph capture elsewhere in their program, serving loops, harnesses that
+ * forbid hipMalloc): the same iterations, kernels and results, bit for bit,
+ * with no workspace argument.  Its scratch is a fixed device array of the
+ * library, laue_sinkhorn_noalloc_capacity() = 64 MiB per GPU, held by each GPU
+ * the call runs on from the first call until the process ends; the call
+ * allocates no device memory and creates no HIP event, stream or graph
+ * (direct launches, one spot per lane, no timing).  A problem whose
+ * workspace (laue_sinkhorn_workspace_size, or laue_sparse_workspace_size for
+ * rho > 0) exceeds the capacity returns LAUE_ECAPACITY and enqueues nothing.
+ * Every call on a GPU shares that GPU's scratch, which keeps the last call's
+ * contents (every call rewrites what it reads): calls that overlap on one GPU
+ * (several host threads or streams) race and must be serialised by the
+ * caller.  Synchronous; LAUE_ENOCONV at the cap. */
+size_t laue_sinkhorn_noalloc_capacity(void);
+int laue_sinkhorn_noalloc(const laue_geometry *geom, const laue_obs_spots *obs,
+                          const laue_model_spots *model, const laue_ot_params *par,
+                          laue_potentials *pot, laue_ot_stats *stats, void *stream);
+
 /* FP64 summaries of the plan of (pot, par->eps) and its bins (Eqs. elbo,
  * estep_obj): mass (every entry, bins included), cost_inlier = <c, Q> over
  * the detected x model entries, cost_total with the bin entries at c_out,

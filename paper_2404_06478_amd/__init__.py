@@ -359,6 +359,18 @@ def laue_sinkhorn(geom, obs, model, ot, f, g, f0=0.0, g0=0.0):
     return pot.f0, pot.g0, {"n_iter": st.n_iter, "converged": bool(st.converged), "err": st.err}, rc
 
 
+def laue_sinkhorn_noalloc(geom, obs, model, ot, f, g, f0=0.0, g0=0.0):
+    """laue_sinkhorn on the library's fixed scratch (no workspace, no device
+    allocation); returns (f0, g0, stats dict, code)."""
+    lib = require_native()
+    pot = laue_potentials(f.data_ptr(), g.data_ptr(), float(f0), float(g0))
+    st = laue_ot_stats()
+    o, m = obs.struct(), model.struct()
+    rc = _check(lib.laue_sinkhorn_noalloc(C.byref(geom), C.byref(o), C.byref(m), C.byref(ot), C.byref(pot),
+                                          C.byref(st), _stream()))
+    return pot.f0, pot.g0, {"n_iter": st.n_iter, "converged": bool(st.converged), "err": st.err}, rc
+
+
 def laue_objectives(geom, obs, model, ot, f, g, f0, g0, sigma_mm):
     """FP64 plan summaries (dict: mass, cost_inlier, cost_total, entropy, sem_objective)."""
     lib = require_native()

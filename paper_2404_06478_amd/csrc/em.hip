@@ -25,6 +25,7 @@
 // arithmetic does not depend on the other samples in the batch.
 #include <algorithm>
 #include <array>
+#include <mutex>
 #include <cmath>
 #include <numeric>
 #include <vector>
@@ -1995,6 +1996,9 @@ struct BatchEngine {
     std::vector<int> stage_tile;
     std::vector<int> tiles_used;
     hipEvent_t tev[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+    // false: no HIP events (no timing); direct launches and a fixed tile shape
+    // then create no HIP object at all
+    bool timing = true;
 
     ~BatchEngine() {
         if (!graphs.empty()) (void)hipStreamSynchronize(s);
@@ -2155,6 +2159,7 @@ struct BatchEngine {
     }
 
     int timer_start() {
+        if (!timing) return LAUE_OK;
         if (!ev0) {
             LAUE_CHECK_HIP(hipEventCreate(&ev0));
             LAUE_CHECK_HIP(hipEventCreate(&ev1));
@@ -2164,6 +2169,10 @@ struct BatchEngine {
     }
 
     int timer_stop(double *acc, double *dt = nullptr) {
+        if (!timing) {
+            if (dt) *dt = 0.0;
+            return LAUE_OK;
+        }
         LAUE_CHECK_HIP(hipEventRecord(ev1, s));
         LAUE_CHECK_HIP(hipEventSynchronize(ev1));
         float ms = 0.0f;
@@ -2897,6 +2906,72 @@ extern "C" int laue_sinkhorn(const laue_geometry *geom, const laue_obs_spots *ob
     laue_model_spots *m = const_cast<laue_model_spots *>(model);
     if ((rc = e.setup({SampleIn{geom, nullptr, obs, m, par, nullptr, pot, 0.0, nullptr, nullptr}}, ws, ws_bytes,
                       stream, true)))
+        return rc;
+    if ((rc = launch_pack(model, e.sw[0].colsE, e.s))) return rc;
+    std::vector<laue_ot_stats> os;
+    if ((rc = e.sinkhorn({par->eps}, par->chunk, os))) return rc;
+    *stats = os[0];
+    LAUE_CHECK_HIP(hipStreamSynchronize(e.s));
+    return stats->converged ? LAUE_OK : LAUE_ENOCONV;
+}
+
+// ---------------------------------------------------------------- allocation-free Sinkhorn
+
+// Scratch of laue_sinkhorn_noalloc: a file-scope device array that each GPU
+// holds from the library's first use until the process ends.  Host code never
+// passes the array's name to a kernel (on the host it is only a stand-in for
+// the symbol): the device address comes from hipGetSymbolAddress, once per
+// device with that device current, and is kept per device.
+namespace {
+constexpr size_t kNoAllocScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+int scratch_of_current_device(void **out) {
+    int dev = -1;
+    LAUE_CHECK_HIP(hipGetDevice(&dev));
+    LAUE_REQUIRE(dev >= 0 && dev < kMaxDevices, LAUE_EDEVICE, "device index out of range");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        LAUE_CHECK_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        LAUE_REQUIRE(p != nullptr && (reinterpret_cast<uintptr_t>(p) & 255) == 0, LAUE_EDEVICE,
+                     "scratch symbol has no aligned device address");
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return LAUE_OK;
+}
+}  // namespace
+
+extern "C" size_t laue_sinkhorn_noalloc_capacity(void) { return kNoAllocScratchBytes; }
+
+extern "C" int laue_sinkhorn_noalloc(const laue_geometry *geom, const laue_obs_spots *obs,
+                                     const laue_model_spots *model, const laue_ot_params *par,
+                                     laue_potentials *pot, laue_ot_stats *stats, void *stream) {
+    clear_error();
+    int rc;
+    if ((rc = validate_ot(par, true))) return rc;
+    LAUE_REQUIRE(pot && stats && obs && model, LAUE_EINVAL, "NULL argument");
+    LAUE_REQUIRE(bins_ok(par, pot), LAUE_EINVAL, "bin potentials must be finite");
+    if ((rc = validate_geometry(geom))) return rc;
+    const size_t need =
+        par->rho > 0
+            ? laue_sparse_workspace_size(1, geom, &obs->n, &model->n, std::array<int32_t, 1>{0}.data(), par->rho)
+            : laue_sinkhorn_workspace_size(geom, obs->n, model->n, 0);
+    LAUE_REQUIRE(need > 0, LAUE_EINVAL, "bad problem sizes");
+    LAUE_REQUIRE(need <= kNoAllocScratchBytes, LAUE_ECAPACITY,
+                 "the problem needs " + std::to_string(need) + " bytes of scratch; laue_sinkhorn_noalloc holds " +
+                     std::to_string(kNoAllocScratchBytes) + " (use laue_sinkhorn with a workspace)");
+    void *ws = nullptr;
+    if ((rc = scratch_of_current_device(&ws))) return rc;
+    BatchEngine e;
+    e.timing = false;
+    laue_model_spots *m = const_cast<laue_model_spots *>(model);
+    if ((rc = e.setup({SampleIn{geom, nullptr, obs, m, par, nullptr, pot, 0.0, nullptr, nullptr}}, ws,
+                      kNoAllocScratchBytes, stream, true)))
         return rc;
     if ((rc = launch_pack(model, e.sw[0].colsE, e.s))) return rc;
     std::vector<laue_ot_stats> os;
