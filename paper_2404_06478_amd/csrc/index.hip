@@ -11,6 +11,8 @@
 #include <algorithm>
 #include <cmath>
 
+#include <hipcub/hipcub.hpp>
+
 #include "common.h"
 
 namespace laue {
@@ -269,12 +271,67 @@ __device__ __forceinline__ Col8 col_of(const LaneCol &c, int j) {
                 bcast(c.vv, j), bcast(c.vv2, j), bcast(c.vn, j), 0.0f};
 }
 
+// Plan term and M-step statistics of one pair when the statistics are taken
+// at the E-step geometry itself (the first Gauss-Newton step of a refinement
+// iteration): the chord cost's intermediates serve both.  With delta = p - s
+// (detector-local), b = v.delta, w = 2 b + |delta|^2, the ray d = v + delta
+// has |d|^2 = |v|^2 + w and 1/|d| = rsq(|d|^2); the cost
+// c' = |v x delta|^2 / (|v|^2 |d|^2 + (v.d) |v| |d|) (chord_cp's expression
+// with sqrt(|v|^2 |d|^2) = |v| |d|), the plan entry Q = exp2(-K c') iz, and
+// the statistics of accumulate_stats (whose |d| - |v| numerator is the same
+// w).  Returns Q; adds the statistics when the wave has any Q > 0.
+__device__ __forceinline__ void fused_entry_stats(float *a, bool &any, float p1, float p2, const Col8 &c,
+                                                  float vlen, float rn, float r1, float r2, float K, float iz) {
+    const float dy = p1 - c.s1, dz = p2 - c.s2;
+    const float e = fmaf(dz, dz, dy * dy);
+    const float bb = fmaf(c.v2, dz, c.v1 * dy);
+    const float w = fmaf(2.0f, bb, e);
+    const float dd = c.vv + w;
+    const float itau = __builtin_amdgcn_rsqf(dd);
+    const float tau = dd * itau;
+    const float x2 = fmaf(c.vv, e, -(bb * bb));
+    const float den = fmaf((c.vv + bb) * vlen, tau, c.vv * dd);
+    const float Q = fast_exp2(-K * (x2 * __builtin_amdgcn_rcpf(den))) * iz;
+    if (!__any(Q > 0.0f)) return;                 // no weight in this chunk (wave-uniform)
+    any = true;
+    const float dl = w * __builtin_amdgcn_rcpf(tau + vlen);
+    const float e0 = (-rn * dl) * itau;
+    const float e1 = fmaf(-r1, dl, dy) * itau;
+    const float e2 = fmaf(-r2, dl, dz) * itau;
+    const float h0 = c.vn * itau, h1 = (c.v1 + dy) * itau, h2 = (c.v2 + dz) * itau;
+    const float wb = Q * itau, wa = wb * itau;
+    const float P00 = fmaf(-h0, h0, 1.0f), P01 = -h0 * h1, P02 = -h0 * h2;
+    const float P11 = fmaf(-h1, h1, 1.0f), P12 = -h1 * h2, P22 = fmaf(-h2, h2, 1.0f);
+    a[0] += Q;
+    a[1] = fmaf(Q, e0, a[1]);
+    a[2] = fmaf(Q, e1, a[2]);
+    a[3] = fmaf(Q, e2, a[3]);
+    a[4] = fmaf(wa, P00, a[4]);
+    a[5] = fmaf(wa, P01, a[5]);
+    a[6] = fmaf(wa, P02, a[6]);
+    a[7] = fmaf(wa, P11, a[7]);
+    a[8] = fmaf(wa, P12, a[8]);
+    a[9] = fmaf(wa, P22, a[9]);
+    a[10] = fmaf(wb, P00, a[10]);
+    a[11] = fmaf(wb, P01, a[11]);
+    a[12] = fmaf(wb, P02, a[12]);
+    a[13] = fmaf(wb, P11, a[13]);
+    a[14] = fmaf(wb, P12, a[14]);
+    a[15] = fmaf(wb, P22, a[15]);
+}
+
 // Single-grain E-step (row softmax with the outlier column, App. D) fused
 // with the M-step statistics: Q from the columns colsE (held fixed over the
 // Gauss-Newton steps of one refinement iteration), statistics at the current
 // columns colsC.  Writes per (candidate, block) the summed 27-value
 // normal-equation contribution.  One wave per (block b, candidate c), item =
 // b * C + c so that neighbouring waves stream the same detected spots.
+// SAME: colsC is colsE (the first step), and each pair's statistics reuse its
+// plan term's cost (fused_entry_stats); otherwise the statistics pass
+// evaluates the plan term at colsE and the statistics at colsC.  The loops
+// over a lane's kSup rows are unrolled with wave-uniform guards, so the rows
+// stay in named registers.
+template <bool SAME>
 __global__ __launch_bounds__(64) void k_single_acc(SlotArgs A, float K, float bin_e, double D2,
                                                    double *__restrict__ hg_out) {
     const int item = blockIdx.x;
@@ -288,13 +345,27 @@ __global__ __launch_bounds__(64) void k_single_acc(SlotArgs A, float K, float bi
         if (lane < kHg) out[lane] = 0.0;
         return;
     }
-    const LaneCol lE = lane_col(A.colsE, o0, nc, lane), lC = lane_col(A.colsC, o0, nc, lane);
+    const LaneCol lE = lane_col(A.colsE, o0, nc, lane);
+    const LaneCol lC = SAME ? lE : lane_col(A.colsC, o0, nc, lane);
     // per-column constants at the current geometry: |v|, v / |v|
     const float ivl_l = __builtin_amdgcn_rsqf(lC.vv), vlen_l = lC.vv * ivl_l;
     const float rn_l = lC.vn * ivl_l, r1_l = lC.v1 * ivl_l, r2_l = lC.v2 * ivl_l;
     // FP64 running statistics of model spot j at acc[16 j + q] (this wave only)
     __shared__ double acc[64 * kStat];
     for (int k = lane; k < nc * kStat; k += 64) acc[k] = 0.0;
+    // the columns' constants in LDS, read back by every lane with one
+    // broadcast load per value: the pair arithmetic then takes vector-register
+    // operands only (a scalar-register operand halves the VALU issue rate)
+    __shared__ float4 cst[64 * (SAME ? 3 : 5)];
+    if (lane < nc) {
+        cst[lane] = make_float4(lE.s1, lE.s2, lE.v1, lE.v2);
+        cst[64 + lane] = make_float4(lE.vv, lE.vv2, lE.vn, vlen_l);
+        cst[128 + lane] = make_float4(rn_l, r1_l, r2_l, 0.0f);
+        if (!SAME) {
+            cst[192 + lane] = make_float4(lC.s1, lC.s2, lC.v1, lC.v2);
+            cst[256 + lane] = make_float4(lC.vv, lC.vv2, lC.vn, 0.0f);
+        }
+    }
     __syncthreads();
     // Detected spots in super-chunks of kSup x 64 rows: each lane keeps its
     // kSup rows (coordinates and softmax normalisers) in registers, so the
@@ -311,32 +382,41 @@ __global__ __launch_bounds__(64) void k_single_acc(SlotArgs A, float K, float bi
             iz[u] = bin_e;
         }
         for (int j = 0; j < nc; ++j) {
-            const Col8 cE = col_of(lE, j);
+            const float4 x0 = cst[j], x1 = cst[64 + j];
 #pragma unroll
-            for (int u = 0; u < kSup; ++u) {
-                if (64 * u >= nrow) break;
-                iz[u] += fast_exp2(entry_exponent(p1[u], p2[u], cE.s1, cE.s2, cE.v1, cE.v2, cE.vv, cE.vv2, K, 0.0f));
-            }
+            for (int u = 0; u < kSup; ++u)
+                if (64 * u < nrow)
+                    iz[u] += fast_exp2(entry_exponent(p1[u], p2[u], x0.x, x0.y, x0.z, x0.w, x1.x, x1.y, K, 0.0f));
         }
 #pragma unroll
         for (int u = 0; u < kSup; ++u) iz[u] = 64 * u + lane < nrow ? __builtin_amdgcn_rcpf(iz[u]) : 0.0f;
         for (int j = 0; j < nc; ++j) {
-            const Col8 cE = col_of(lE, j);
-            const Col8 cC = col_of(lC, j);
-            const float vl = bcast(vlen_l, j), rn = bcast(rn_l, j), r1 = bcast(r1_l, j), r2 = bcast(r2_l, j);
+            const float4 x0 = cst[j], x1 = cst[64 + j], x2 = cst[128 + j];
+            const Col8 cE{x0.x, x0.y, x0.z, x0.w, x1.x, x1.y, x1.z, 0.0f};
+            const float vl = x1.w, rn = x2.x, r1 = x2.y, r2 = x2.z;
             float a[kStat];
 #pragma unroll
             for (int q = 0; q < kStat; ++q) a[q] = 0.0f;
             bool any = false;
+            if (SAME) {
 #pragma unroll
-            for (int u = 0; u < kSup; ++u) {
-                if (64 * u >= nrow) break;
-                const float Q =
-                    fast_exp2(entry_exponent(p1[u], p2[u], cE.s1, cE.s2, cE.v1, cE.v2, cE.vv, cE.vv2, K, 0.0f)) *
-                    iz[u];
-                if (!__any(Q > 0.0f)) continue;             // no weight in this chunk
-                any = true;
-                accumulate_stats(a, Q, p1[u], p2[u], cC, vl, rn, r1, r2);   // Q = 0 adds zeros
+                for (int u = 0; u < kSup; ++u)
+                    if (64 * u < nrow) fused_entry_stats(a, any, p1[u], p2[u], cE, vl, rn, r1, r2, K, iz[u]);
+            } else {
+                const float4 y0 = cst[SAME ? 0 : 192 + j], y1 = cst[SAME ? 0 : 256 + j];
+                const Col8 cC{y0.x, y0.y, y0.z, y0.w, y1.x, y1.y, y1.z, 0.0f};
+#pragma unroll
+                for (int u = 0; u < kSup; ++u) {
+                    if (64 * u < nrow) {
+                        const float Q = fast_exp2(entry_exponent(p1[u], p2[u], cE.s1, cE.s2, cE.v1, cE.v2, cE.vv,
+                                                                 cE.vv2, K, 0.0f)) *
+                                        iz[u];
+                        if (__any(Q > 0.0f)) {                      // weight in this chunk
+                            any = true;
+                            accumulate_stats(a, Q, p1[u], p2[u], cC, vl, rn, r1, r2);   // Q = 0 adds zeros
+                        }
+                    }
+                }
             }
             if (!any) continue;
             const float t = wave_reduce_scatter16(a, lane);
@@ -686,6 +766,56 @@ __global__ __launch_bounds__(1024) void k_greedy_pick(const int64_t *__restrict_
 
 __global__ void k_set_i64(int64_t *p, int64_t v) { *p = v; }
 
+// Live SPOT entries: an entry of an unpicked candidate whose value exceeds
+// its row's current cover.  Every other entry adds exactly 0 to every later
+// increment (covers only rise, picked candidates are never scored again), so
+// dropping it changes no increment beyond the order of its FP64 additions.
+// One wave per candidate: cnt[c] = its live entries.
+__global__ __launch_bounds__(64) void k_live_count(const int64_t *__restrict__ off, const int *__restrict__ row,
+                                                   const float *__restrict__ val, const float *__restrict__ cur,
+                                                   const uint8_t *__restrict__ picked, int64_t *__restrict__ cnt,
+                                                   int n) {
+    const int c = blockIdx.x;
+    if (c >= n) return;
+    int64_t k = 0;
+    if (!picked[c])
+        for (int64_t e = off[c] + threadIdx.x; e < off[c + 1]; e += 64) k += val[e] > cur[row[e]] ? 1 : 0;
+    for (int o = 32; o > 0; o >>= 1) k += __shfl_xor(k, o, 64);
+    if (threadIdx.x == 0) cnt[c] = k;
+}
+
+// The live entries of candidate c, in their order, to [noff[c], noff[c+1]) of
+// the other buffer (one wave per candidate, ballot and rank per 64 entries).
+__global__ __launch_bounds__(64) void k_live_write(const int64_t *__restrict__ off, const int *__restrict__ row,
+                                                   const float *__restrict__ val, const float *__restrict__ cur,
+                                                   const uint8_t *__restrict__ picked,
+                                                   const int64_t *__restrict__ noff, int *__restrict__ nrow,
+                                                   float *__restrict__ nval, int n) {
+    const int c = blockIdx.x;
+    if (c >= n || picked[c]) return;
+    const int lane = threadIdx.x;
+    int64_t pos = noff[c];
+    for (int64_t e0 = off[c]; e0 < off[c + 1]; e0 += 64) {
+        const int64_t e = e0 + lane;
+        int r = 0;
+        float v = 0.0f;
+        bool live = false;
+        if (e < off[c + 1]) {
+            r = row[e];
+            v = val[e];
+            live = v > cur[r];
+        }
+        const unsigned long long m = __ballot(live);
+        const int rank = __builtin_amdgcn_mbcnt_hi(static_cast<unsigned>(m >> 32),
+                                                   __builtin_amdgcn_mbcnt_lo(static_cast<unsigned>(m), 0));
+        if (live) {
+            nrow[pos + rank] = r;
+            nval[pos + rank] = v;
+        }
+        pos += __popcll(m);
+    }
+}
+
 // Same-block (detected, model) pairs of one batch, added to *acc: over the
 // (block, candidate) slots, model spots of the slot times detected spots of
 // its block; keep (may be NULL) limits the sum to kept candidates.
@@ -907,7 +1037,10 @@ size_t carve_score(Carver &cv, ScoreWs &w, const laue_geometry *g, int chunk, in
 }
 
 int launch_acc(const SlotArgs &A, float K, float bin_e, double D2, double *hg, hipStream_t s) {
-    k_single_acc<<<static_cast<unsigned>(A.nb) * A.C, 64, 0, s>>>(A, K, bin_e, D2, hg);
+    if (A.colsC == A.colsE)
+        k_single_acc<true><<<static_cast<unsigned>(A.nb) * A.C, 64, 0, s>>>(A, K, bin_e, D2, hg);
+    else
+        k_single_acc<false><<<static_cast<unsigned>(A.nb) * A.C, 64, 0, s>>>(A, K, bin_e, D2, hg);
     LAUE_CHECK_HIP(hipGetLastError());
     return LAUE_OK;
 }
@@ -1103,6 +1236,43 @@ struct GreedyWs {
     int *done;
     int *stop;      // step at which the lazy selection handed over (-1: none)
 };
+// Live-entry buffers of the grid-wide steps, carved from the workspace
+// beyond the minimum (none when it is too small to be useful).
+constexpr int kCompactEvery = 16;
+struct GreedyLive {
+    int64_t *off[2];
+    int64_t *cnt;
+    void *tmp;
+    size_t tmp_bytes;
+    int *row[2];
+    float *val[2];
+    int64_t cap;      // entries each buffer holds
+};
+bool carve_live(char *base, size_t bytes, int n, GreedyLive *lv) {
+    if (n < 1) return false;
+    size_t tmp = 0;
+    if (hipcub::DeviceScan::InclusiveSum(nullptr, tmp, static_cast<int64_t *>(nullptr),
+                                         static_cast<int64_t *>(nullptr), n) != hipSuccess)
+        return false;
+    Carver cv(base);
+    lv->off[0] = cv.take<int64_t>(n + 1);
+    lv->off[1] = cv.take<int64_t>(n + 1);
+    lv->cnt = cv.take<int64_t>(n);
+    lv->tmp = cv.take<char>(static_cast<int64_t>(tmp));
+    lv->tmp_bytes = tmp;
+    const size_t fixed = cv.size() + 4 * 256;
+    if (bytes <= fixed) return false;
+    const int64_t cap = static_cast<int64_t>((bytes - fixed) / 16);
+    if (cap < 65536) return false;
+    lv->row[0] = cv.take<int>(cap);
+    lv->val[0] = cv.take<float>(cap);
+    lv->row[1] = cv.take<int>(cap);
+    lv->val[1] = cv.take<float>(cap);
+    if (cv.size() > bytes) return false;
+    lv->cap = cap;
+    return true;
+}
+
 size_t carve_greedy(Carver &cv, GreedyWs &w, int n_cand, int64_t n_rows) {
     w.cur = cv.take<float>(std::max<int64_t>(n_rows, 1));
     w.picked = cv.take<uint8_t>(std::max(n_cand, 1));
@@ -1159,10 +1329,43 @@ extern "C" int laue_spot_greedy(const int64_t *lbar_off, const int32_t *lbar_row
     LAUE_CHECK_HIP(hipMemcpyAsync(&stop, w.stop, sizeof(int), hipMemcpyDeviceToHost, s));
     LAUE_CHECK_HIP(hipStreamSynchronize(s));
     if (stop >= 0) {
+        // grid-wide exact steps.  Workspace beyond the minimum holds two
+        // buffers of live entries: every kCompactEvery steps the live entries
+        // are counted and, when they fit, compacted into the other buffer, so
+        // later steps stream only entries that can still add to an increment.
+        const size_t spare = ws_bytes > need ? ws_bytes - need : 0;
+        GreedyLive lv{};
+        const bool compact = carve_live(static_cast<char *>(ws) + need, spare, n_cand, &lv);
+        const int64_t *off = lbar_off;
+        const int *row = lbar_row;
+        const float *val = lbar_val;
+        int nb = 0;
         for (int step = stop; step < K; ++step) {
-            k_gain<<<n_cand, 64, 0, s>>>(lbar_off, lbar_row, lbar_val, w.cur, w.picked, w.gain, w.done, n_cand);
-            k_greedy_pick<<<1, 1024, 0, s>>>(lbar_off, lbar_row, lbar_val, w.cur, w.picked, w.gain, n_cand, step,
-                                             picks, gains, w.done);
+            if (compact && (step - stop) % kCompactEvery == 0) {
+                int64_t *noff = lv.off[nb];
+                k_live_count<<<n_cand, 64, 0, s>>>(off, row, val, w.cur, w.picked, lv.cnt, n_cand);
+                k_set_i64<<<1, 1, 0, s>>>(noff, 0);
+                size_t tb = lv.tmp_bytes;
+                LAUE_CHECK_HIP(hipcub::DeviceScan::InclusiveSum(lv.tmp, tb, lv.cnt, noff + 1, n_cand, s));
+                int64_t total = 0;
+                int dn = 0;
+                LAUE_CHECK_HIP(hipMemcpyAsync(&total, noff + n_cand, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+                LAUE_CHECK_HIP(hipMemcpyAsync(&dn, w.done, sizeof(int), hipMemcpyDeviceToHost, s));
+                LAUE_CHECK_HIP(hipStreamSynchronize(s));
+                if (dn) break;
+                if (total <= lv.cap) {
+                    k_live_write<<<n_cand, 64, 0, s>>>(off, row, val, w.cur, w.picked, noff, lv.row[nb], lv.val[nb],
+                                                       n_cand);
+                    off = noff;
+                    row = lv.row[nb];
+                    val = lv.val[nb];
+                    nb ^= 1;
+                    log_line("greedy: step %d, %lld live SPOT entries compacted", step, static_cast<long long>(total));
+                }
+            }
+            k_gain<<<n_cand, 64, 0, s>>>(off, row, val, w.cur, w.picked, w.gain, w.done, n_cand);
+            k_greedy_pick<<<1, 1024, 0, s>>>(off, row, val, w.cur, w.picked, w.gain, n_cand, step, picks, gains,
+                                             w.done);
         }
         LAUE_CHECK_HIP(hipGetLastError());
     }
