@@ -9,10 +9,12 @@ iterations; Sinkhorn to a relative row-marginal error of 1e-5 (cap 2000).
 
 A step is one EM iteration through the whole path: forward evaluation of the
 frozen model spots, the streamed Sinkhorn E-step to tolerance, and two
-Gauss-Newton M-step passes.  W warm-up steps run the first W iterations of
-the schedule; the K timed steps continue it (wrapping after 20).  The value is
-the number of same-block (detected, model) pairs streamed through
-cost -> exp -> accumulate in the timed region divided by its wall time.
+Gauss-Newton M-step passes.  W warm-up steps run the first W iterations of a
+separate run from the same start; the K timed steps are one EM run from the
+start (K = 20 is the whole schedule; later steps stay at its last
+temperature).  The value is the number of same-block (detected, model) pairs
+streamed through cost -> exp -> accumulate in the timed region divided by its
+wall time.
 
 One JSON line is printed.  It carries the roofline of the dominant kernel
 (the Sinkhorn row/column passes, measured with HIP events inside the library)
@@ -43,7 +45,14 @@ sys.path.insert(0, ROOT)
 VALU_PER_ENTRY = 16.5
 TRANS_PER_ENTRY = 3
 VALU_LANE_OPS_PER_S = 256 * 4 * 32 * 2.4e9
-PEAK_ENTRIES_PER_S = VALU_LANE_OPS_PER_S / (VALU_PER_ENTRY + 4 * TRANS_PER_ENTRY)
+PEAK_COMPILED_ENTRIES_PER_S = VALU_LANE_OPS_PER_S / (VALU_PER_ENTRY + 4 * TRANS_PER_ENTRY)
+# The line's roofline counts the method's algorithmic work per entry instead
+# of the compiled count: about 20 FP32 VALU operations (two differences, the
+# cross and dot products, the FMAs of the cost, the potential FMA and the
+# accumulation) and 3 transcendentals (square root, reciprocal, exp2).
+ALGO_VALU_PER_ENTRY = 20
+ALGO_TRANS_PER_ENTRY = 3
+PEAK_ENTRIES_PER_S = VALU_LANE_OPS_PER_S / (ALGO_VALU_PER_ENTRY + 4 * ALGO_TRANS_PER_ENTRY)
 
 # HBM bytes of one working row pass (k_row) on this workload, from rocprofv3
 # FETCH_SIZE and WRITE_SIZE (KiB per dispatch) scaled by what the same
@@ -132,8 +141,113 @@ def cpu_baseline(preset, n_rows=10000, chunk=1000, workers=None):
                       f"({sum(ents):.3g} entries, {dtp:.1f} s); one process: {n1} rows ({n_ent:.3g} entries, "
                       f"{dt:.1f} s)",
             "single_process": {"value": single, "cores": 1},
-            "host": platform.processor() or platform.machine(), "os_cpu_count": os.cpu_count(),
-            "numpy": np.__version__}
+            "host": cpu_host()}
+
+
+def cpu_host():
+    """The host the oracle runs on: CPU model (/proc/cpuinfo), the cores this
+    process may use (nproc), os.cpu_count() and the NumPy version."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for ln in fh:
+                if ln.startswith("model name"):
+                    model = ln.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        nproc = len(os.sched_getaffinity(0))
+    except AttributeError:
+        nproc = os.cpu_count()
+    return {"cpu_model": model or platform.processor() or platform.machine(), "nproc": nproc,
+            "os_cpu_count": os.cpu_count(), "numpy": np.__version__}
+
+
+def cpu_oracle_runs(n_pairs_tiny=64, n_sample=1):
+    """The oracle as written (one process, FP64 NumPy): on the 5-grain
+    workload the whole 20-iteration EM and the whole time to index (candidates
+    of n_pairs_tiny spot pairs, refinement, scoring, greedy, EM); on the
+    100-grain workload the refinement and scoring of n_sample candidates, as
+    pairs per second in the library's count (refinement iterations x
+    Gauss-Newton steps + 1 passes over the candidate's same-block pairs, plus
+    one for a kept candidate), the rate the extrapolations use."""
+    import inputgen as ig
+    from oracle import candidates, cost, crystal, em, forward, pipeline, simulate, single
+    out = {}
+    p = ig.TINY
+    pl = crystal.cubic_planes(p.a, p.centering, p.n_max)
+    g = forward.Geometry.from_preset(p)
+    q, x = ig.random_grains(p)
+    sim = simulate.simulate(pl, q, x, g, p.sigma_mm, p.outlier_frac, p.seed, p.distance)
+    p12 = ig.to_f32_exact(sim["p12"])
+    q0, x0 = ig.perturb_grains(q, x, 0.5, 0.5, p.seed + 17)
+    model = forward.enumerate_visible(pl, q0, x0, g)
+    model["offsets"] = forward.block_offsets(model["block"], g.n_blocks)
+    sched = em.eps_schedule(p.eps_start, p.eps_end, p.n_stages, p.iters_per_stage)
+    c_out = cost.c_out(p.sigma_mm, p.distance)
+    t0 = time.perf_counter()
+    r = em.run(pl, g, p.distance, p12, sim["offsets"], model, q0, x0, sched, c_out)
+    t_em = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    ix = pipeline.index(pl, g, p.distance, p12, sim["offsets"], p.sigma_mm, c_out, sched, n_pairs_tiny, 1,
+                        k_max=2 * p.n_grains)
+    t_ix = time.perf_counter() - t0
+    out["tiny"] = {"em_iterations": len(sched), "em_s": t_em, "em_iters_per_s": len(sched) / t_em,
+                   "sinkhorn_iters": int(sum(s["n_iter"] for s in r["stats"])),
+                   "time_to_index_s": t_ix, "pairs": n_pairs_tiny, "candidates": int(len(ix["candidates"]["q"])),
+                   "prototypes": int(ix["k"]), "recall": recall(ix["q"], ix["x"], q, x) / len(q),
+                   "measured": True}
+    pm = ig.MEDIUM
+    plm = crystal.cubic_planes(pm.a, pm.centering, pm.n_max)
+    gm = forward.Geometry.from_preset(pm)
+    qm, xm = ig.random_grains(pm)
+    simm = simulate.simulate(plm, qm, xm, gm, pm.sigma_mm, pm.outlier_frac, pm.seed, pm.distance)
+    p12m = ig.to_f32_exact(simm["p12"])
+    cand = candidates.generate(plm, gm, p12m, simm["offsets"], 2, 1)
+    c_outm = cost.c_out(pm.sigma_mm, pm.distance)
+    n_blk = np.diff(simm["offsets"])
+    pairs, t_sc = 0, 0.0
+    for k in range(min(n_sample, len(cand["q"]))):
+        t0 = time.perf_counter()
+        qq, xx, mod = single.refine(plm, gm, pm.distance, p12m, simm["offsets"], cand["q"][k], np.zeros(3),
+                                    pm.sigma_mm, c_outm, k_refine=8, k_gn=1)
+        un, nm, rows, vals = single.score(plm, gm, pm.distance, p12m, simm["offsets"], mod, qq, xx, pm.sigma_mm,
+                                          c_outm)
+        t_sc += time.perf_counter() - t0
+        slot = int(np.sum(np.diff(mod["offsets"]) * n_blk))
+        pairs += (8 * 1 + 1) * slot + (slot if nm > 0 and un < 0.1 * nm else 0)
+    out["medium_scoring_sample"] = {"candidates": min(n_sample, len(cand["q"])), "pairs": pairs, "s": t_sc,
+                                    "pairs_per_s": pairs / t_sc if t_sc > 0 else None, "measured": True}
+    return out
+
+
+def cpu_extrapolate(line, base, runs):
+    """Oracle time for the GPU lines of this run, extrapolated from the
+    oracle's measured rates (labelled so): an EM iteration streams the passes
+    the library counted (cost_entries) at the oracle's single-process
+    row-pass rate; indexing adds the scoring pairs the library counted at the
+    oracle's sampled scoring rate."""
+    ent_rate = base["single_process"]["value"]
+    pair_rate = runs["medium_scoring_sample"]["pairs_per_s"]
+    out = {"note": "extrapolated, one process, from the measured oracle rates (not run)"}
+    if line.get("config", {}).get("em_iterations"):
+        per_it = line["value"] * line["ms_per_step"] * 1e-3
+        out["em_iters_per_s_main_workload"] = ent_rate / per_it
+    tti = {}
+    for key, v in line.get("time_to_index", {}).items():
+        tti[key] = {}
+        for mode in ("plain", "learned", "sobol"):
+            if mode not in v:
+                continue
+            x = v[mode]
+            em_ent = x.get("em_cost_entries", 0)
+            tti[key][mode] = (x["score_pairs"] / pair_rate if pair_rate else None,
+                              em_ent / ent_rate)
+            tti[key][mode] = {"time_to_index_s": sum(t for t in tti[key][mode] if t is not None),
+                              "scoring_s": tti[key][mode][0], "em_s": tti[key][mode][1]}
+    out["time_to_index"] = tti
+    return out
 
 
 def misorientation_deg(qa, qb):
@@ -222,13 +336,41 @@ def bench_batching(laue, n_samples, n_stages, log):
             "launch_used": outs[0]["launch_used"], "identical_to_sequential": bool(same)}
 
 
-def bench_index(laue, workload, n_pairs, learned_pairs, log, sobol_points=0):
+def recipe_params(laue, p, recipe, n_obs):
+    """Refinement and EM parameters of an index line.  "stages": the
+    refinement 30 -> 1.11 sigma^2 in 8 iterations and the EM's 5 x 4 stage
+    schedule 111 -> 1.11 sigma^2.  "paper": the paper's annealing (Sec. 5.1,
+    Sec. 7, App. D): the refinement cools by 0.97 per iteration from 30 sigma^2
+    to 2 sigma^2 (90 iterations, one Gauss-Newton step each), the EM cools by
+    0.97 per iteration from the data-tied first temperature (the farthest of 32
+    neighbours, computed by the library) to 2 sigma^2 (the paper's temperature
+    1), then at most 20 more iterations with the plan-change stop."""
+    s2 = p.sigma_mm ** 2
+    c_out = laue.c_out_3sigma(p.sigma_mm, p.distance)
+    if recipe == "stages":
+        return None, None
+    score = laue.score_params(p.sigma_mm, p.distance, c_out, k_refine=90, k_gn=1, eps_start=30.0 * s2,
+                              eps_cool=0.97)
+    ot = laue.ot_params(1.0, p.distance, c_out, 0.0)
+    em = laue.em_params(ot, 0.0, 2.0 * s2, 1, 1, eps_cool=0.97, final_iters=20,
+                        zeta_tol=ZETA_TOL_PER_ROOT_SPOT * math.sqrt(max(n_obs, 1)), sigma_mm=p.sigma_mm)
+    return score, em
+
+
+# Plan-change stop of the paper's EM recipe: ||Q^{k+1} - Q^k||_F <= this times
+# sqrt(detected spots), i.e. an RMS change per detected spot's row of 1e-3.
+ZETA_TOL_PER_ROOT_SPOT = 1e-3
+
+
+def bench_index(laue, workload, n_pairs, learned_pairs, log, sobol_points=0, recipe="stages", max_candidates=None,
+                plain_max=None, train_examples=1_000_000):
     """Time to index from device-resident spots (laue_index): plain exhaustive
     scoring of the candidates of n_pairs spot pairs, against the learned
     proposal scoring the top 5% of the candidates of learned_pairs pairs, with
     a network trained here on 10^6 simulated examples, and (sobol_points > 0)
     the paper's Sobol-grid starts over the cubic fundamental zone and the
-    sample box."""
+    sample box.  max_candidates caps the candidates of both forms (the first
+    ones); plain_max caps the plain form's alone."""
     import torch
     import inputgen as ig
     from paper_2404_06478_amd import learned
@@ -241,7 +383,7 @@ def bench_index(laue, workload, n_pairs, learned_pairs, log, sobol_points=0):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     feat, lab = learned.training_set(geom, planes, truths, p.sigma_mm, p.distance, p.outlier_frac, seeds,
-                                     1_000_000, support_radius=radius)
+                                     train_examples, support_radius=radius)
     torch.cuda.synchronize()
     t_data = time.perf_counter() - t0
     net = laue.Mlp(seed=3)
@@ -252,19 +394,28 @@ def bench_index(laue, workload, n_pairs, learned_pairs, log, sobol_points=0):
     log(f"index: training set {feat.shape[0]} examples in {t_data:.1f} s, 10 epochs in {t_train:.1f} s")
     q, x = ig.random_grains(p)
     obs = laue.laue_simulate(geom, planes, laue.Grains(q, x), p.sigma_mm, p.distance, p.outlier_frac, p.seed)
-    out = {"workload": workload, "grains": p.n_grains, "detected_spots": obs.n,
+    out = {"workload": workload, "grains": p.n_grains, "detected_spots": obs.n, "recipe": recipe,
            "training": {"examples": int(feat.shape[0]), "positives": int(lab.sum().item()),
                         "data_s": t_data, "train_s": t_train, "epochs": 10, "final_loss": losses[-1]}}
+    score, em = recipe_params(laue, p, recipe, obs.n)
     modes = [("plain", n_pairs), ("learned", learned_pairs)] + ([("sobol", sobol_points)] if sobol_points else [])
     for mode, pairs in modes:
+        mc = max_candidates if mode != "plain" or plain_max is None else plain_max
         if mode == "sobol":
             # dense samples keep nearly every start, each with thousands of
             # SPOT entries: size the SPOT matrix for the starts (64-bit offsets)
             cap = 8000 * pairs if obs.n * pairs > 1e11 else None
-            par = laue.index_params(p, "sobol", max_candidates=pairs, n_obs=obs.n, n_planes=planes.n, lbar_cap=cap)
+            par = laue.index_params(p, "sobol", max_candidates=pairs, n_obs=obs.n, n_planes=planes.n, lbar_cap=cap,
+                                    score=score, em=em)
         else:
+            n_sc = mc if mc is not None else 64 * pairs
+            n_sc = int(math.ceil(0.05 * n_sc)) if mode == "learned" else n_sc
+            # dense clutter keeps nearly every candidate, each with an entry for
+            # most detected spots within reach: size the SPOT matrix for it
+            cap = (8000 if p.n_grains <= 1000 else 32000) * n_sc if obs.n * n_sc > 1e11 else None
             par = laue.index_params(p, mode, n_pairs=pairs, seed=1, mlp=net if mode == "learned" else None,
-                                    support_radius=radius, n_obs=obs.n, n_planes=planes.n)
+                                    support_radius=radius, n_obs=obs.n, n_planes=planes.n, max_candidates=mc,
+                                    lbar_cap=cap, score=score, em=em)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         g, st, _ = laue.laue_index(geom, planes, obs, par, assign=False)
@@ -273,7 +424,10 @@ def bench_index(laue, workload, n_pairs, learned_pairs, log, sobol_points=0):
         qg, xg = g.numpy()
         r = recall(qg[:g.n], xg[:g.n], q, x)
         out[mode] = {("sobol_points" if mode == "sobol" else "pairs"): pairs, "candidates": st["n_candidates"],
-                     "scored": st["n_scored"],
+                     "candidates_found": st["n_candidates_found"], "scored": st["n_scored"],
+                     "em_iterations": st["em"]["n_em_iter"], "em_sinkhorn_capped": st["em"]["not_converged"],
+                     "em_cost_entries": st["em"]["cost_entries"],
+                     "em_zeta": st["em"]["zeta"], "likelihood": st["em"]["objective"]["sem_objective"],
                      "prototypes": st["n_prototypes"], "recall": r / len(q), "time_s": wall,
                      "score_pairs": st["score_pairs"],
                      "score_pairs_per_s": st["score_pairs"] / max(st["ms_score"] * 1e-3, 1e-12),
@@ -563,11 +717,41 @@ def bench_forward(laue, n_grains, log):
             "eval_hbm_frac": nbytes / t_eval / 8e12}
 
 
+# Index lines of the default run: the 100-grain workload (stage schedule);
+# the 1000-grain target workload as its configuration states it (2^20
+# spot-pair candidates: the network ranks them and the top 5% are scored,
+# against plain scoring of all 2^20), on the stage schedule; the same sample
+# at the paper's fiducial noise with the paper's annealing recipe; the
+# 2000-grain stress workload (the network ranks 2^20 candidates and scores the
+# top 5%; plain scoring of the first 2^16).
+DEFAULT_INDEX_LINES = ("medium,pairs=8192,sobol=200000;"
+                       "learned,pairs=32768,lpairs=32768,cand=1048576;"
+                       "learned_fiducial,pairs=2048,lpairs=16384,recipe=paper;"
+                       "stress,pairs=32768,lpairs=32768,cand=1048576,pcand=65536")
+
+
+def parse_index_line(item):
+    parts = [x.strip() for x in item.split(",") if x.strip()]
+    o = {"pairs": 4096, "lpairs": None, "sobol": 0, "recipe": "stages", "cand": None, "pcand": None,
+         "examples": 1_000_000}
+    for kv in parts[1:]:
+        k, v = kv.split("=")
+        if k not in o and k != "name":
+            raise ValueError(f"unknown index-line option {k}")
+        o[k] = v if k in ("recipe", "name") else int(v)
+    if o["lpairs"] is None:
+        o["lpairs"] = 8 * o["pairs"]
+    if o["recipe"] not in ("stages", "paper"):
+        raise ValueError("recipe must be stages or paper")
+    return parts[0], o
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=8)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=20, help="EM iterations timed: one run from the start "
+                    "(20 = the whole schedule; more continue at its last temperature)")
+    ap.add_argument("--warmup", type=int, default=2, help="iterations of a separate untimed run first")
     ap.add_argument("--workload", default="learned", choices=["learned", "medium", "stress"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batching", action="store_true")
@@ -586,9 +770,11 @@ def main():
     ap.add_argument("--unbalanced-workload", default="medium", choices=["medium", "learned", "stress"])
     ap.add_argument("--no-mstep-methods", action="store_true")
     ap.add_argument("--batch-samples", type=int, default=64)
-    ap.add_argument("--index-workloads", default="medium:8192:200000,learned:1024,learned_fiducial:2048",
-                    help="workload:pairs[:sobol_points] items; plain scoring of the pairs' candidates, the learned "
-                         "proposal on 8x the pairs, and the Sobol-grid starts when sobol_points > 0")
+    ap.add_argument("--index-workloads", default=DEFAULT_INDEX_LINES,
+                    help="';'-separated index lines, each 'workload' followed by ',key=value' options: pairs "
+                         "(plain form's spot pairs), lpairs (learned form's, default 8 x pairs), sobol (Sobol points, "
+                         "0: none), recipe (stages or paper), cand (candidate cap of both forms), pcand (plain "
+                         "form's cap), examples (training examples)")
     ap.add_argument("--index-limits", default="learned,learned_fiducial",
                     help="workloads of the EM-from-truth and selection diagnostics ('' to skip)")
     ap.add_argument("--tile", type=int, default=0, choices=[0, 1, 2],
@@ -615,38 +801,49 @@ def main():
     torch.cuda.set_device(0)
     preset = ig.PRESETS[args.workload]
     geom, planes, obs, model, grains = build_problem(laue, preset)
-    # outlier cost: the likelihood of a 3-sigma angular miss, in mm^2
-    c_out = 2.0 * preset.distance ** 2 * (1.0 - math.cos(3.0 * preset.sigma_mm / preset.distance))
-    t_b = float(math.ceil(0.4 * model.n))
-    n_sched = preset.n_stages * preset.iters_per_stage
-    eps_list = [preset.eps_start * (preset.eps_end / preset.eps_start) ** (s / (preset.n_stages - 1))
-                for s in range(preset.n_stages) for _ in range(preset.iters_per_stage)]
+    q_start, x_start = grains.numpy()
+    # the outlier row and column of Sec. 7 (3-sigma outlier cost, T_b = ceil(0.4 |J|))
+    base = laue.ot_defaults(preset.sigma_mm, preset.distance, model.n)
+    c_out, t_b = base.c_out, base.t_b
+    eps_list = _em_schedule(preset)
+    n_sched = len(eps_list)
     dev = torch.device("cuda", 0)
-    f = torch.zeros(obs.n, dtype=torch.float32, device=dev)
-    g = torch.zeros(model.n, dtype=torch.float32, device=dev)
-    pot = {"f0": 0.0, "g0": 0.0}
 
-    def step(k):
-        eps = eps_list[k % n_sched]
+    def fresh():
+        return (laue.Grains(q_start, x_start), torch.zeros(obs.n, dtype=torch.float32, device=dev),
+                torch.zeros(model.n, dtype=torch.float32, device=dev), {"f0": 0.0, "g0": 0.0})
+
+    def step(k, state):
+        # iteration k of one EM run from the start: the schedule's temperature,
+        # then (steps beyond it) its last temperature
+        gr, f, g, pot = state
+        eps = eps_list[min(k, n_sched - 1)]
         ot = laue.ot_params(eps, preset.distance, c_out, t_b, tol=1e-5, n_max=2000)
         par = laue.em_params(ot, eps, eps, 1, 1, k_gn=2, tile=args.tile)
-        out = laue.laue_em(geom, planes, obs, model, par, grains, f, g, pot["f0"], pot["g0"], assign=False)
+        out = laue.laue_em(geom, planes, obs, model, par, gr, f, g, pot["f0"], pot["g0"], assign=False)
         pot["f0"], pot["g0"] = out["f0"], out["g0"]
         return out
 
     print(f"bench: {args.workload}: {obs.n} detected, {model.n} model spots, "
           f"{int(np.sum(np.diff(obs.block_off) * np.diff(model.block_off)))} entries per pass",
           file=sys.stderr, flush=True)
+    # warm-up: the first W iterations of a separate run from the same start
+    warm = fresh()
     for k in range(args.warmup):
-        o = step(k)
+        o = step(k, warm)
         print(f"bench: warm-up step {k}: {o['sinkhorn_iters']} Sinkhorn iterations", file=sys.stderr, flush=True)
+    del warm
+    # timed: K iterations of one EM run from the start (no wrap of the schedule)
+    state = fresh()
     torch.cuda.synchronize()
-    stats = []
+    stats, step_s = [], []
     t0 = time.perf_counter()
-    for k in range(args.warmup, args.warmup + args.steps):
-        stats.append(step(k))
-        print(f"bench: step {k}: eps {eps_list[k % n_sched]:.3g}, {stats[-1]['sinkhorn_iters']} Sinkhorn "
-              f"iterations, {stats[-1]['sinkhorn_ms']:.1f} ms in Sinkhorn passes", file=sys.stderr, flush=True)
+    for k in range(args.steps):
+        ts = time.perf_counter()
+        stats.append(step(k, state))
+        step_s.append(time.perf_counter() - ts)
+        print(f"bench: step {k}: eps {eps_list[min(k, n_sched - 1)]:.3g}, {stats[-1]['sinkhorn_iters']} Sinkhorn "
+              f"iterations (err {stats[-1]['last_err']:.2e}), {step_s[-1] * 1e3:.1f} ms", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     entries = sum(s["cost_entries"] for s in stats)
@@ -656,6 +853,18 @@ def main():
     achieved = sk_ent / (sk_ms * 1e-3)
     blk_i = np.diff(obs.block_off)
     blk_j = np.diff(model.block_off)
+    qf, xf = state[0].numpy()
+    q_true, x_true = ig.random_grains(preset)
+    stages = []
+    for k, s in enumerate(stats):
+        e = round(eps_list[min(k, n_sched - 1)], 6)
+        if not stages or stages[-1]["eps_mm2"] != e:
+            stages.append({"eps_mm2": e, "em_iterations": 0, "sinkhorn_iters": 0, "ms": 0.0, "capped": 0})
+        st = stages[-1]
+        st["em_iterations"] += 1
+        st["sinkhorn_iters"] += int(s["sinkhorn_iters"])
+        st["ms"] += step_s[k] * 1e3
+        st["capped"] += int(s["not_converged"])
     line = {
         "metric": "Sinkhorn-EM cost-entries/s",
         "value": entries / dt,
@@ -670,11 +879,16 @@ def main():
                                f"{int(100 * preset.outlier_frac)}% outliers",
                    "detected_spots": obs.n, "model_spots": model.n,
                    "entries_per_pass": int(np.sum(blk_i * blk_j)),
-                   "em_iterations": [args.warmup, args.warmup + args.steps],
+                   "em_iterations": [0, args.steps], "schedule_length": n_sched,
+                   "schedule": f"{preset.n_stages} stages x {preset.iters_per_stage} EM iterations, "
+                               f"{preset.eps_start:.4g} -> {preset.eps_end:.4g} mm^2; one run from the start, "
+                               f"iterations beyond it at the last temperature",
                    "sinkhorn_tol": 1e-5, "k_gn": 2},
         "em_iters_per_s": args.steps / dt,
         "sinkhorn_iters": int(sum(s["sinkhorn_iters"] for s in stats)),
         "sinkhorn_capped": int(sum(s["not_converged"] for s in stats)),
+        "stages": stages,
+        "recall_after_run": recall(qf, xf, q_true, x_true) / len(q_true),
         "tile": {"requested": args.tile, "two_per_lane_solves": int(sum(s["tile2_solves"] for s in stats)),
                  "solves": len(stats)},
         "roofline": {"kernel": "Sinkhorn row/column pass (k_row, k_col)", "bound": "alu",
@@ -682,7 +896,11 @@ def main():
                      "unit": "Gentries/s", "frac": achieved / PEAK_ENTRIES_PER_S,
                      "traffic": ROW_PASS_HBM_BYTES if args.workload == "learned" else None,
                      "traffic_unit": "HBM bytes per row-pass launch",
-                     "per_entry": {"valu": VALU_PER_ENTRY, "trans": TRANS_PER_ENTRY},
+                     "per_entry": {"valu": ALGO_VALU_PER_ENTRY, "trans": ALGO_TRANS_PER_ENTRY,
+                                   "counted_as": "the method's algorithmic work per entry"},
+                     "compiled": {"valu": VALU_PER_ENTRY, "trans": TRANS_PER_ENTRY,
+                                  "peak": PEAK_COMPILED_ENTRIES_PER_S / 1e9,
+                                  "frac": achieved / PEAK_COMPILED_ENTRIES_PER_S},
                      "passes": sk_pass, "avg_pass_ms": sk_ms / max(sk_pass, 1)},
         "mstep": {"ms": sum(s["mstep_ms"] for s in stats),
                   "entries": int(sum(s["mstep_entries"] for s in stats))},
@@ -706,17 +924,22 @@ def main():
         line["mstep_methods"] = bench_mstep_methods(laue, preset, ig.PRESETS["medium"], args.steps, log)
     if not args.no_index:
         line["time_to_index"] = {}
-        for item in args.index_workloads.split(","):
-            parts = item.split(":")
-            wl, pairs = parts[0], int(parts[1])
-            sob = int(parts[2]) if len(parts) > 2 else 0
-            line["time_to_index"][wl] = bench_index(laue, wl, pairs, 8 * pairs, log, sobol_points=sob)
+        for item in [x for x in args.index_workloads.split(";") if x.strip()]:
+            wl, o = parse_index_line(item)
+            key = o.get("name", f"{wl}.{o['recipe']}")
+            line["time_to_index"][key] = bench_index(
+                laue, wl, o["pairs"], o["lpairs"], log, sobol_points=o["sobol"], recipe=o["recipe"],
+                max_candidates=o["cand"], plain_max=o["pcand"], train_examples=o["examples"])
     if args.index_limits:
         import inputgen as ig
         line["index_limits"] = {wl: bench_index_limits(laue, ig.PRESETS[wl], log)
                                 for wl in args.index_limits.split(",") if wl}
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(preset)
+        cb = cpu_baseline(preset)
+        runs = cpu_oracle_runs()
+        cb["oracle_runs"] = runs
+        cb["oracle_extrapolated"] = cpu_extrapolate(line, cb, runs)
+        line["cpu_baseline"] = cb
     print(json.dumps(line), flush=True)
 
 

@@ -812,7 +812,9 @@ typedef struct laue_index_params {
     int32_t k_max;
     int64_t max_model_spots;
     double t_b_frac;
-    laue_em_params em;              /* em.ot.t_b is set from t_b_frac */
+    laue_em_params em;              /* em.ot.t_b is set from t_b_frac; with em.eps_cool > 0 and
+                                     * em.eps_start <= 0 the first temperature is laue_eps_init
+                                     * of the prototypes' model spots (rho = em.ot.rho, or 32) */
     laue_sobol_params sobol;        /* Sobol mode */
 } laue_index_params;
 

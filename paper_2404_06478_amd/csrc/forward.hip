@@ -11,6 +11,8 @@ constexpr int kMaxPlanes = 1024;
 
 // ---------------------------------------------------------------- grains
 
+__global__ void k_set_i64_fwd(int64_t *p, int64_t v) { *p = v; }
+
 __global__ void k_grain_prep(const double *__restrict__ q, const double *__restrict__ x, int n,
                              GrainF *__restrict__ out) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -27,109 +29,219 @@ int prep_grains(const laue_grains *g, GrainF *dst, hipStream_t s) {
 
 // ---------------------------------------------------------------- enumerate
 
-// One wave per (grain n, rotation t).  Phase 1 marks, per detector, every
-// plane whose spot is in band and on the detector (the literal set).  Phase 2
-// applies the harmonic merge (drop a plane if a lower-order parallel plane is
-// visible on the same detector) and either counts (pass 0) or writes (pass 1)
-// the kept spots in (t, d, n, m) order.
+// One wave per workgroup, looping over (grain n, rotation t) items.  Phase 1
+// marks, per detector, every plane whose spot is in band and on the detector
+// (the literal set): first the wavelength of every plane (u_x of Gamma_t R w,
+// lambda = 2 d u_x, the arithmetic of spot_geometry), the planes in band
+// gathered into an LDS list by ballot; then the full geometry of the listed
+// planes only (most planes are out of band), so a wave computes detector
+// intersections for in-band planes without idle lanes.  Phase 2 walks the same
+// list, applies the harmonic merge (drop a plane if a lower-order parallel
+// plane is visible on the same detector) and either counts (pass 0) or writes
+// (pass 1) the kept spots in (t, d, n, m) order.
 __global__ __launch_bounds__(64) void k_enumerate(
     const GeomF *__restrict__ Gp, const float *__restrict__ W, const float *__restrict__ Dsp,
-    const int *__restrict__ prev, int M, const GrainF *__restrict__ grains, int N, int merge,
+    const int *__restrict__ prev, int M, const GrainF *__restrict__ grains, int N, int T, int merge,
     int pass, int *__restrict__ counts, const int64_t *__restrict__ offs, int *__restrict__ o_plane,
     int *__restrict__ o_grain, int *__restrict__ o_block, float *__restrict__ o_s1,
     float *__restrict__ o_s2, float *__restrict__ o_vn, float *__restrict__ o_v1,
     float *__restrict__ o_v2, float *__restrict__ o_lam, uint8_t *__restrict__ o_flags) {
     const GeomF &G = *Gp;
-    const int item = blockIdx.x;
-    const int n = item % N;
-    const int t = item / N;
     const int lane = threadIdx.x;
-    __shared__ uint8_t vis[LAUE_MAX_DET][kMaxPlanes];
-    const GrainF gr = grains[n];
-    const float c = G.cs[t][0], s = G.cs[t][1];
-    const int D = G.n_det;
-    for (int m = lane; m < M; m += 64) {
-        float wx = W[3 * m], wy = W[3 * m + 1], wz = W[3 * m + 2];
-        for (int d = 0; d < D; ++d) {
-            SpotGeo o = spot_geometry(G, G.det[d], gr.R, gr.x, c, s, wx, wy, wz, Dsp[m]);
-            vis[d][m] = (o.inband && o.on) ? 1 : 0;
-        }
-    }
+    // visibility per (detector, plane): dynamic LDS of n_det x M bytes
+    extern __shared__ uint8_t vis_lds[];
+    __shared__ short inb[kMaxPlanes];
+    // the harmonic parents, read by chains of dependent lookups: from LDS
+    __shared__ short pv[kMaxPlanes];
+    for (int m = lane; m < M; m += 64) pv[m] = static_cast<short>(prev[m] >= 0 && prev[m] < M ? prev[m] : -1);
     __syncthreads();
-    for (int d = 0; d < D; ++d) {
-        const int slot = (t * D + d) * N + n;
-        int64_t base = pass ? offs[slot] : 0;
-        int running = 0;
+    const int D = G.n_det;
+    const int64_t n_items = static_cast<int64_t>(N) * T;
+    for (int64_t item = blockIdx.x; item < n_items; item += gridDim.x) {
+        const int n = static_cast<int>(item % N);
+        const int t = static_cast<int>(item / N);
+        const GrainF gr = grains[n];
+        const float c = G.cs[t][0], s = G.cs[t][1];
+        int K = 0;
         for (int m0 = 0; m0 < M; m0 += 64) {
-            int m = m0 + lane;
-            bool keep = (m < M) && vis[d][m];
-            if (merge && keep) {
-                int a = prev[m];
-                for (int hop = 0; hop < 16 && a >= 0 && a < M; ++hop) {
-                    if (vis[d][a]) { keep = false; break; }
-                    a = prev[a];
-                }
+            const int m = m0 + lane;
+            bool ib = false;
+            if (m < M) {
+                float ux, uy, uz;
+                lab_normal(gr.R, c, s, W[3 * m], W[3 * m + 1], W[3 * m + 2], ux, uy, uz);
+                const float lam = 2.0f * Dsp[m] * ux;
+                ib = (lam >= G.lam_min) && (lam <= G.lam_max);
+                for (int d = 0; d < D; ++d) vis_lds[d * M + m] = 0;
             }
-            unsigned long long bal = __ballot(keep);
-            if (pass && keep) {
-                unsigned long long lower = bal & ((1ull << lane) - 1ull);
-                int64_t pos = base + running + __popcll(lower);
-                SpotGeo o = spot_geometry(G, G.det[d], gr.R, gr.x, c, s, W[3 * m], W[3 * m + 1],
-                                          W[3 * m + 2], Dsp[m]);
-                o_plane[pos] = m;
-                o_grain[pos] = n;
-                o_block[pos] = t * D + d;
-                if (o_s1) {
-                    o_s1[pos] = o.s1;
-                    o_s2[pos] = o.s2;
-                    o_vn[pos] = o.vn;
-                    o_v1[pos] = o.v1;
-                    o_v2[pos] = o.v2;
-                }
-                if (o_lam) o_lam[pos] = o.lam;
-                if (o_flags) o_flags[pos] = o.flags;
-            }
-            running += __popcll(bal);
+            const unsigned long long bal = __ballot(ib);
+            if (ib) inb[K + __popcll(bal & ((1ull << lane) - 1ull))] = static_cast<short>(m);
+            K += __popcll(bal);
         }
-        if (!pass && lane == 0) counts[slot] = running;
+        __syncthreads();
+        for (int k = lane; k < K; k += 64) {
+            const int m = inb[k];
+            const float wx = W[3 * m], wy = W[3 * m + 1], wz = W[3 * m + 2];
+            for (int d = 0; d < D; ++d) {
+                const SpotGeo o = spot_geometry(G, G.det[d], gr.R, gr.x, c, s, wx, wy, wz, Dsp[m]);
+                vis_lds[d * M + m] = (o.inband && o.on) ? 1 : 0;
+            }
+        }
+        __syncthreads();
+        for (int d = 0; d < D; ++d) {
+            const int slot = (t * D + d) * N + n;
+            int64_t base = pass ? offs[slot] : 0;
+            int running = 0;
+            // visible planes are in band: walk the in-band list (ascending m)
+            for (int k0 = 0; k0 < K; k0 += 64) {
+                const int m = k0 + lane < K ? inb[k0 + lane] : 0;
+                bool keep = (k0 + lane < K) && vis_lds[d * M + m];
+                if (merge && keep) {
+                    int a = pv[m];
+                    for (int hop = 0; hop < 16 && a >= 0; ++hop) {
+                        if (vis_lds[d * M + a]) { keep = false; break; }
+                        a = pv[a];
+                    }
+                }
+                unsigned long long bal = __ballot(keep);
+                if (pass && keep) {
+                    unsigned long long lower = bal & ((1ull << lane) - 1ull);
+                    int64_t pos = base + running + __popcll(lower);
+                    SpotGeo o = spot_geometry(G, G.det[d], gr.R, gr.x, c, s, W[3 * m], W[3 * m + 1],
+                                              W[3 * m + 2], Dsp[m]);
+                    o_plane[pos] = m;
+                    o_grain[pos] = n;
+                    o_block[pos] = t * D + d;
+                    if (o_s1) {
+                        o_s1[pos] = o.s1;
+                        o_s2[pos] = o.s2;
+                        o_vn[pos] = o.vn;
+                        o_v1[pos] = o.v1;
+                        o_v2[pos] = o.v2;
+                    }
+                    if (o_lam) o_lam[pos] = o.lam;
+                    if (o_flags) o_flags[pos] = o.flags;
+                }
+                running += __popcll(bal);
+            }
+            if (!pass && lane == 0) counts[slot] = running;
+        }
+        __syncthreads();        // vis and inb are reused by the next item
     }
 }
 
-// Exclusive scan of L counts by one workgroup; out has L + 1 entries.  Also
-// extracts per-block offsets: blk[b] = out[b * stride] for b <= n_blocks.
-__global__ __launch_bounds__(1024) void k_scan(const int *__restrict__ in, int64_t *__restrict__ out,
-                                               int64_t L, int64_t *__restrict__ blk, int n_blocks,
-                                               int64_t stride) {
+// Workgroups of k_enumerate: all resident at once (32 one-wave workgroups per
+// CU, 4 KB of static and n_det x M bytes of dynamic LDS each), at most one per
+// item; enum_lds is the dynamic part.
+unsigned enum_grid(int N, int T) {
+    return static_cast<unsigned>(std::min<int64_t>(static_cast<int64_t>(N) * T, 256 * 32));
+}
+size_t enum_lds(int n_det, int M) { return static_cast<size_t>(n_det) * M; }
+
+// Exclusive scan of L int counts into out[0 .. L] (out[L] = total), over
+// the whole GPU in three launches and no memory beyond out: chunks of
+// kScanChunk counts (kScanPerThread per thread of a 256-thread workgroup).
+// (1) each chunk's sum goes to out[chunk start]; (2) one workgroup scans those
+// sums in place, which leaves at each chunk start its exclusive prefix, i.e.
+// the chunk's offset, and writes the total to out[L]; (3) each chunk scans its
+// counts from that offset.  Fixed order everywhere: the result is the exact
+// integer scan.
+constexpr int kScanPerThread = 16;
+constexpr int kScanChunk = 256 * kScanPerThread;
+
+__device__ __forceinline__ int64_t block_exclusive_scan_256(int64_t v, int64_t *sh, int64_t *total) {
+    const int tid = threadIdx.x;
+    sh[tid] = v;
+    __syncthreads();
+    for (int o = 1; o < 256; o <<= 1) {
+        const int64_t t = tid >= o ? sh[tid - o] : 0;
+        __syncthreads();
+        sh[tid] += t;
+        __syncthreads();
+    }
+    const int64_t incl = sh[tid];
+    if (total) *total = sh[255];
+    __syncthreads();
+    return incl - v;
+}
+
+__global__ __launch_bounds__(256) void k_scan_part(const int *__restrict__ in, int64_t *__restrict__ out,
+                                                   int64_t L) {
+    __shared__ int64_t sh[256];
+    const int64_t c0 = static_cast<int64_t>(blockIdx.x) * kScanChunk;
+    const int64_t i0 = c0 + static_cast<int64_t>(threadIdx.x) * kScanPerThread;
+    int64_t sum = 0;
+#pragma unroll
+    for (int k = 0; k < kScanPerThread; ++k)
+        if (i0 + k < L) sum += in[i0 + k];
+    int64_t tot = 0;
+    block_exclusive_scan_256(sum, sh, &tot);
+    if (threadIdx.x == 0) out[c0] = tot;
+}
+
+__global__ __launch_bounds__(1024) void k_scan_top(int64_t *__restrict__ out, int64_t L, int64_t n_chunks) {
     __shared__ int64_t part[1024];
     const int tid = threadIdx.x;
-    const int64_t chunk = (L + 1023) / 1024;
-    const int64_t b0 = std::min<int64_t>(L, tid * chunk), b1 = std::min<int64_t>(L, b0 + chunk);
+    const int64_t per = (n_chunks + 1023) / 1024;
+    const int64_t b0 = std::min<int64_t>(n_chunks, tid * per), b1 = std::min<int64_t>(n_chunks, b0 + per);
     int64_t sum = 0;
-    for (int64_t i = b0; i < b1; ++i) sum += in[i];
+    for (int64_t b = b0; b < b1; ++b) sum += out[b * kScanChunk];
     part[tid] = sum;
     __syncthreads();
-    if (tid == 0) {
-        int64_t run = 0;
-        for (int k = 0; k < 1024; ++k) {
-            int64_t v = part[k];
-            part[k] = run;
-            run += v;
+    for (int o = 1; o < 1024; o <<= 1) {
+        const int64_t t = tid >= o ? part[tid - o] : 0;
+        __syncthreads();
+        part[tid] += t;
+        __syncthreads();
+    }
+    int64_t run = part[tid] - sum;
+    for (int64_t b = b0; b < b1; ++b) {
+        const int64_t v = out[b * kScanChunk];
+        out[b * kScanChunk] = run;
+        run += v;
+    }
+    if (tid == 1023) out[L] = part[1023];
+}
+
+__global__ __launch_bounds__(256) void k_scan_fill(const int *__restrict__ in, int64_t *__restrict__ out,
+                                                   int64_t L) {
+    __shared__ int64_t sh[256];
+    const int64_t c0 = static_cast<int64_t>(blockIdx.x) * kScanChunk;
+    const int64_t base = out[c0];
+    __syncthreads();            // every thread has read the offset before thread 0 rewrites out[c0]
+    const int64_t i0 = c0 + static_cast<int64_t>(threadIdx.x) * kScanPerThread;
+    int v[kScanPerThread];
+    int64_t sum = 0;
+#pragma unroll
+    for (int k = 0; k < kScanPerThread; ++k) {
+        v[k] = i0 + k < L ? in[i0 + k] : 0;
+        sum += v[k];
+    }
+    int64_t run = base + block_exclusive_scan_256(sum, sh, nullptr);
+#pragma unroll
+    for (int k = 0; k < kScanPerThread; ++k)
+        if (i0 + k < L) {
+            out[i0 + k] = run;
+            run += v[k];
         }
-    }
-    __syncthreads();
-    int64_t run = part[tid];
-    for (int64_t i = b0; i < b1; ++i) {
-        out[i] = run;
-        run += in[i];
-    }
-    if (tid == 1023) out[L] = run;
-    __syncthreads();
-    if (blk)
-        for (int b = tid; b <= n_blocks; b += 1024) blk[b] = out[std::min<int64_t>(L, b * stride)];
+}
+
+// blk[b] = out[min(L, b * stride)] for b <= n_blocks
+__global__ void k_scan_blocks(const int64_t *__restrict__ out, int64_t L, int64_t *__restrict__ blk, int n_blocks,
+                              int64_t stride) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b <= n_blocks) blk[b] = out[std::min<int64_t>(L, b * stride)];
 }
 
 int launch_scan(const int *in, int64_t *out, int64_t L, hipStream_t s) {
-    k_scan<<<1, 1024, 0, s>>>(in, out, L, nullptr, 0, 1);
+    if (L <= 0) {
+        k_set_i64_fwd<<<1, 1, 0, s>>>(out, 0);
+        LAUE_CHECK_HIP(hipGetLastError());
+        return LAUE_OK;
+    }
+    const int64_t nc = (L + kScanChunk - 1) / kScanChunk;
+    k_scan_part<<<static_cast<unsigned>(nc), 256, 0, s>>>(in, out, L);
+    k_scan_top<<<1, 1024, 0, s>>>(out, L, nc);
+    k_scan_fill<<<static_cast<unsigned>(nc), 256, 0, s>>>(in, out, L);
     LAUE_CHECK_HIP(hipGetLastError());
     return LAUE_OK;
 }
@@ -262,12 +374,13 @@ int enumerate_count(const laue_geometry *geom, const laue_planes *planes,
         return LAUE_OK;
     }
     const int64_t L = static_cast<int64_t>(geom->n_rot) * geom->n_det * N;
-    k_enumerate<<<geom->n_rot * N, 64, 0, s>>>(w.geom, planes->w, planes->d, planes->harmonic_prev,
-                                               planes->n, w.grains, N, merge, 0, w.counts, nullptr,
+    k_enumerate<<<enum_grid(N, geom->n_rot), 64, enum_lds(geom->n_det, planes->n), s>>>(w.geom, planes->w, planes->d, planes->harmonic_prev,
+                                               planes->n, w.grains, N, geom->n_rot, merge, 0, w.counts, nullptr,
                                                nullptr, nullptr, nullptr, nullptr, nullptr,
                                                nullptr, nullptr, nullptr, nullptr, nullptr);
     LAUE_CHECK_HIP(hipGetLastError());
-    k_scan<<<1, 1024, 0, s>>>(w.counts, w.offs, L, w.blk, nb, N);
+    if ((rc = launch_scan(w.counts, w.offs, L, s))) return rc;
+    k_scan_blocks<<<(nb + 1 + 255) / 256, 256, 0, s>>>(w.offs, L, w.blk, nb, N);
     LAUE_CHECK_HIP(hipGetLastError());
     LAUE_CHECK_HIP(hipMemcpyAsync(host_blk.data(), w.blk, (nb + 1) * sizeof(int64_t),
                                   hipMemcpyDeviceToHost, s));
@@ -280,8 +393,8 @@ int enumerate_count(const laue_geometry *geom, const laue_planes *planes,
 int launch_enumerate_ids(const laue_geometry *geom, const laue_planes *planes, EnumWs &w, int N,
                          int merge, int *plane, int *grain, int *block, hipStream_t s) {
     if (N == 0) return LAUE_OK;
-    k_enumerate<<<geom->n_rot * N, 64, 0, s>>>(w.geom, planes->w, planes->d, planes->harmonic_prev,
-                                               planes->n, w.grains, N, merge, 1, nullptr, w.offs,
+    k_enumerate<<<enum_grid(N, geom->n_rot), 64, enum_lds(geom->n_det, planes->n), s>>>(w.geom, planes->w, planes->d, planes->harmonic_prev,
+                                               planes->n, w.grains, N, geom->n_rot, merge, 1, nullptr, w.offs,
                                                plane, grain, block, nullptr, nullptr, nullptr,
                                                nullptr, nullptr, nullptr, nullptr);
     LAUE_CHECK_HIP(hipGetLastError());
@@ -503,8 +616,8 @@ extern "C" int laue_forward_enumerate(const laue_geometry *geom, const laue_plan
         LAUE_REQUIRE(out->plane && out->grain && out->block && out->s1 && out->s2 && out->vn &&
                          out->v1 && out->v2,
                      LAUE_EINVAL, "model-spot arrays are NULL");
-        k_enumerate<<<geom->n_rot * grains->n, 64, 0, s>>>(
-            w.geom, planes->w, planes->d, planes->harmonic_prev, planes->n, w.grains, grains->n,
+        k_enumerate<<<enum_grid(grains->n, geom->n_rot), 64, enum_lds(geom->n_det, planes->n), s>>>(
+            w.geom, planes->w, planes->d, planes->harmonic_prev, planes->n, w.grains, grains->n, geom->n_rot,
             merge_harmonics ? 1 : 0, 1, nullptr, w.offs, out->plane, out->grain, out->block,
             out->s1, out->s2, out->vn, out->v1, out->v2, out->lam, out->flags);
         LAUE_CHECK_HIP(hipGetLastError());
@@ -624,8 +737,8 @@ extern "C" int laue_simulate(const laue_geometry *geom, const laue_planes *plane
     const uint32_t k0 = static_cast<uint32_t>(seed & 0xffffffffu), k1 = static_cast<uint32_t>(seed >> 32);
     std::vector<int> nt(nb, 0), no(nb, 0);
     if (S > 0) {
-        k_enumerate<<<geom->n_rot * truth->n, 64, 0, s>>>(
-            w.e.geom, planes->w, planes->d, planes->harmonic_prev, planes->n, w.e.grains, truth->n, 1,
+        k_enumerate<<<enum_grid(truth->n, geom->n_rot), 64, enum_lds(geom->n_det, planes->n), s>>>(
+            w.e.geom, planes->w, planes->d, planes->harmonic_prev, planes->n, w.e.grains, truth->n, geom->n_rot, 1,
             1, nullptr, w.e.offs, w.plane, w.grain, w.block, nullptr, nullptr, nullptr, nullptr,
             nullptr, nullptr, nullptr);
         LAUE_CHECK_HIP(hipGetLastError());

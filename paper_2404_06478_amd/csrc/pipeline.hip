@@ -59,11 +59,16 @@ size_t scratch_size(const laue_geometry *g, int n_planes, int64_t n_obs, const l
     if (p->mode == LAUE_INDEX_SOBOL) s = std::max(s, laue_sobol_workspace_size(p->max_candidates));
     s = std::max(s, laue_score_workspace_size(g, &p->score));
     // the greedy's minimum plus room for its live-entry buffers (16 bytes per
-    // entry, up to 2^27 entries: a smaller room only delays the compaction)
+    // entry, up to 2^30 entries: a smaller room only delays the compaction)
     s = std::max(s, laue_spot_greedy_workspace_size(static_cast<int32_t>(n_scored_max(p)), n_obs) +
-                        16 * static_cast<size_t>(std::min<int64_t>(p->lbar_cap, int64_t(1) << 27)));
+                        16 * static_cast<size_t>(std::min<int64_t>(p->lbar_cap, int64_t(1) << 30)));
     s = std::max(s, laue_forward_workspace_size(g, n_planes, p->k_max));
     s = std::max(s, laue_sinkhorn_workspace_size(g, n_obs, p->max_model_spots, p->k_max));
+    if (p->em.eps_cool > 0.0 && !(p->em.eps_start > 0.0)) {
+        const int64_t no = n_obs, nm = p->max_model_spots;
+        const int32_t ng = p->k_max;
+        s = std::max(s, laue_sparse_workspace_size(1, g, &no, &nm, &ng, p->em.ot.rho > 0 ? p->em.ot.rho : 32));
+    }
     return s;
 }
 
@@ -330,6 +335,18 @@ extern "C" int laue_index(const laue_geometry *geom, const laue_planes *planes, 
     laue_em_params em = par->em;
     // the likelihood of the final plan at the scoring noise unless given
     if (!(em.sigma_mm > 0.0)) em.sigma_mm = par->score.sigma_mm;
+    if (em.eps_cool > 0.0 && !(em.eps_start > 0.0)) {
+        // the paper's first temperature (Sec. 7): the farthest of rho = 32 (or
+        // em.ot.rho) neighbours keeps a non-negligible weight (laue_eps_init)
+        laue_model_spots mk = model;
+        mk.n = n_model;
+        laue_ot_params on = em.ot;
+        on.rho = em.ot.rho > 0 ? em.ot.rho : 32;
+        double e0 = 0.0;
+        if ((rc = laue_eps_init(geom, obs, &mk, &on, &e0, w.scratch, w.scratch_bytes, stream))) return rc;
+        em.eps_start = std::max(e0, em.eps_end);
+        log_line("index: eps_init %.4g mm^2", e0);
+    }
     const double tb = std::ceil(par->t_b_frac * static_cast<double>(n_model));
     em.ot.t_b = std::max(tb, static_cast<double>(n_model - obs->n));
     const int64_t nf = std::max<int64_t>(obs->n, 1), ng = std::max<int64_t>(n_model, 1);
