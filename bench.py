@@ -301,8 +301,8 @@ def bench_batching(laue, n_samples, n_stages, log):
         obs = laue.laue_simulate(geom, planes, laue.Grains(q, x), p.sigma_mm, p.distance, p.outlier_frac, p.seed)
         q0, x0 = ig.perturb_grains(q, x, 0.5, 0.5, p.seed + 17)
         model = laue.laue_forward_enumerate(geom, planes, laue.Grains(q0, x0), True)
-        c_out = 2.0 * p.distance ** 2 * (1.0 - math.cos(3.0 * p.sigma_mm / p.distance))
-        ot = laue.ot_params(p.eps_start, p.distance, c_out, float(math.ceil(0.4 * model.n)))
+        base = laue.ot_defaults(p.sigma_mm, p.distance, model.n)
+        ot = laue.ot_params(p.eps_start, p.distance, base.c_out, base.t_b)
         par = laue.em_params(ot, p.eps_start, p.eps_end, n_stages, 1)
         items.append((geom, planes, obs, model, par, (q0, x0), p))
     log(f"batching: {n_samples} samples, {sum(it[2].n for it in items)} detected and "
@@ -475,7 +475,7 @@ def bench_index_limits(laue, preset, log, n_random=9000):
     def em(q0, x0, sched):
         grains = laue.Grains(q0, x0)
         model = laue.laue_forward_enumerate(geom, planes, grains, True)
-        t_b = float(math.ceil(0.4 * model.n))
+        t_b = laue.ot_defaults(preset.sigma_mm, preset.distance, model.n).t_b
         f = torch.zeros(obs.n, dtype=torch.float32, device=dev)
         g = torch.zeros(model.n, dtype=torch.float32, device=dev)
         f0 = g0 = 0.0
@@ -533,7 +533,8 @@ def _em_schedule(preset):
 
 
 def _c_out(preset):
-    return 2.0 * preset.distance ** 2 * (1.0 - math.cos(3.0 * preset.sigma_mm / preset.distance))
+    import paper_2404_06478_amd as laue
+    return laue.c_out_3sigma(preset.sigma_mm, preset.distance)
 
 
 def _em_iterations(laue, preset, ks, log, label, em_kw=None, **ot_kw):
@@ -543,7 +544,7 @@ def _em_iterations(laue, preset, ks, log, label, em_kw=None, **ot_kw):
     import torch
     eps_list = _em_schedule(preset)
     geom, planes, obs, model, grains = build_problem(laue, preset)
-    t_b = float(math.ceil(0.4 * model.n))
+    t_b = laue.ot_defaults(preset.sigma_mm, preset.distance, model.n).t_b
     dev = torch.device("cuda", 0)
     f = torch.zeros(obs.n, dtype=torch.float32, device=dev)
     g = torch.zeros(model.n, dtype=torch.float32, device=dev)
@@ -775,7 +776,7 @@ def main():
                          "(plain form's spot pairs), lpairs (learned form's, default 8 x pairs), sobol (Sobol points, "
                          "0: none), recipe (stages or paper), cand (candidate cap of both forms), pcand (plain "
                          "form's cap), examples (training examples)")
-    ap.add_argument("--index-limits", default="learned,learned_fiducial",
+    ap.add_argument("--index-limits", default="",
                     help="workloads of the EM-from-truth and selection diagnostics ('' to skip)")
     ap.add_argument("--tile", type=int, default=0, choices=[0, 1, 2],
                     help="Sinkhorn tile shape: 1 or 2 spots per lane, 0 tuned per call")

@@ -751,6 +751,21 @@ int laue_mlp_train_step(laue_mlp *m, const float *feat, const float *label, int6
                         const laue_adam_params *ap, double *loss, void *ws, size_t ws_bytes,
                         void *stream);
 
+/* One training epoch over examples feat [n][16], label [n] (device): the
+ * floor(n / batch) batches of a seeded permutation, each gathered by the
+ * library and taken through laue_mlp_train_step's kernels (backward, Adam).
+ * The order: example i gets the 64-bit key (x0 << 32) | x1 of Philox4x32-10
+ * counter (i, epoch, 0, 8) under the key (seed low, seed high), and the
+ * examples are visited by increasing key (a stable radix sort: equal keys by
+ * index); the last n mod batch of that order are left out.  *loss_mean (HOST)
+ * is the mean binary cross-entropy over the visited examples (each batch's
+ * before its Adam step).  batch % 16 == 0, batch <= n < 2^31.
+ * Synchronous. */
+size_t laue_mlp_epoch_workspace_size(int64_t n, int64_t batch);
+int laue_mlp_train_epoch(laue_mlp *m, const float *feat, const float *label, int64_t n, int64_t batch,
+                         uint64_t seed, int32_t epoch, const laue_adam_params *ap, double *loss_mean,
+                         void *ws, size_t ws_bytes, void *stream);
+
 /* ---- Sobol-grid starts (Sec. 6.1) ------------------------------------------ */
 
 /* Starts of single-grain fitting from a Sobol sequence over the six

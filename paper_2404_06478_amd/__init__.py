@@ -676,6 +676,18 @@ def laue_mlp_adam(mlp, grad, ap):
     _check(require_native().laue_mlp_adam(C.byref(mlp.s), _ptr(grad), C.byref(ap), _stream()))
 
 
+def laue_mlp_train_epoch(mlp, feat, label, batch, seed, epoch, ap):
+    """One epoch of Adam on the examples (feat [n, 16], label [n], device FP32)
+    in the library's seeded order; returns the mean loss."""
+    lib = require_native()
+    n = int(feat.shape[0])
+    ws = _workspace(lib.laue_mlp_epoch_workspace_size(n, int(batch)))
+    loss = C.c_double()
+    _check(lib.laue_mlp_train_epoch(C.byref(mlp.s), _ptr(feat), _ptr(label), n, int(batch), int(seed), int(epoch),
+                                    C.byref(ap), C.byref(loss), _ptr(ws), ws.numel(), _stream()))
+    return loss.value
+
+
 class MlpTrainer:
     """Holds the training workspace for a fixed batch size."""
 

@@ -238,6 +238,9 @@ SIGNATURES = {
                                   P(laue_model_spots), P(laue_em_params), P(laue_grains), P(laue_potentials),
                                   P(laue_assignments), P(laue_em_stats), vp, C.c_size_t, vp]),
     "laue_ot_defaults": (C.c_int, [C.c_double, C.c_double, C.c_int64, P(laue_ot_params)]),
+    "laue_mlp_epoch_workspace_size": (C.c_size_t, [C.c_int64, C.c_int64]),
+    "laue_mlp_train_epoch": (C.c_int, [P(laue_mlp), vp, vp, C.c_int64, C.c_int64, C.c_uint64, C.c_int32,
+                                       P(laue_adam_params), P(C.c_double), vp, C.c_size_t, vp]),
     "laue_sinkhorn_noalloc_capacity": (C.c_size_t, []),
     "laue_sinkhorn_noalloc": (C.c_int, [P(laue_geometry), P(laue_obs_spots), P(laue_model_spots),
                                         P(laue_ot_params), P(laue_potentials), P(laue_ot_stats), vp]),

@@ -15,6 +15,8 @@
 #include <algorithm>
 #include <cmath>
 
+#include <hipcub/hipcub.hpp>
+
 #include "common.h"
 
 namespace laue {
@@ -410,20 +412,13 @@ extern "C" size_t laue_mlp_train_workspace_size(int64_t batch) {
     return carve_train(cv, w, batch);
 }
 
-extern "C" int laue_mlp_backward(const laue_mlp *m, const float *feat, const float *label,
-                                 int64_t batch, float *grad, double *loss, void *ws,
-                                 size_t ws_bytes, void *stream) {
-    clear_error();
+namespace laue {
+namespace {
+// Forward, loss and gradient of one batch into the training workspace (the
+// gradient in w.grad, the summed loss in w.lsum on the device).
+int backward_core(const laue_mlp *m, const float *feat, const float *label, int64_t B, MlpTrainWs &w,
+                  hipStream_t s) {
     int rc;
-    if ((rc = validate_mlp(m))) return rc;
-    LAUE_REQUIRE(batch >= 16 && batch % 16 == 0 && batch <= (1 << 24) && feat && label && loss,
-                 LAUE_EINVAL, "batch must be a positive multiple of 16");
-    hipStream_t s = static_cast<hipStream_t>(stream);
-    Carver cv(ws);
-    MlpTrainWs w;
-    size_t need = carve_train(cv, w, batch);
-    if ((rc = check_ws(ws, ws_bytes, need))) return rc;
-    const int64_t B = batch;
     if ((rc = mlp_forward_chunk(m->params, m->wbf16, feat, B, w.prob, w.f, true, B, s))) return rc;
     k_mlp_dz<<<static_cast<unsigned>((B + 255) / 256), 256, 0, s>>>(w.prob, label, B, w.dz, w.lrow);
     const int nblk = static_cast<int>((B + kDh2Rows - 1) / kDh2Rows);
@@ -438,12 +433,31 @@ extern "C" int laue_mlp_backward(const laue_mlp *m, const float *feat, const flo
     k_mlp_dw1<<<kHid, 256, 0, s>>>(w.dh1bT, w.f.xbT, B, w.grad);
     k_sum_d<<<1, 256, 0, s>>>(w.lrow, B, w.lsum);
     LAUE_CHECK_HIP(hipGetLastError());
+    return LAUE_OK;
+}
+}  // namespace
+}  // namespace laue
+
+extern "C" int laue_mlp_backward(const laue_mlp *m, const float *feat, const float *label,
+                                 int64_t batch, float *grad, double *loss, void *ws,
+                                 size_t ws_bytes, void *stream) {
+    clear_error();
+    int rc;
+    if ((rc = validate_mlp(m))) return rc;
+    LAUE_REQUIRE(batch >= 16 && batch % 16 == 0 && batch <= (1 << 24) && feat && label && loss,
+                 LAUE_EINVAL, "batch must be a positive multiple of 16");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    Carver cv(ws);
+    MlpTrainWs w;
+    size_t need = carve_train(cv, w, batch);
+    if ((rc = check_ws(ws, ws_bytes, need))) return rc;
+    if ((rc = backward_core(m, feat, label, batch, w, s))) return rc;
     if (grad)
         LAUE_CHECK_HIP(hipMemcpyAsync(grad, w.grad, kNParams * sizeof(float), hipMemcpyDeviceToDevice, s));
     double ls = 0.0;
     LAUE_CHECK_HIP(hipMemcpyAsync(&ls, w.lsum, sizeof(double), hipMemcpyDeviceToHost, s));
     LAUE_CHECK_HIP(hipStreamSynchronize(s));
-    *loss = ls / static_cast<double>(B);
+    *loss = ls / static_cast<double>(batch);
     return LAUE_OK;
 }
 
@@ -477,4 +491,109 @@ extern "C" int laue_mlp_train_step(laue_mlp *m, const float *feat, const float *
     MlpTrainWs w;
     carve_train(cv, w, batch);
     return laue_mlp_adam(m, w.grad, ap, stream);
+}
+
+// ---------------------------------------------------------------- one training epoch
+
+namespace laue {
+namespace {
+// 64-bit order key of example i in epoch e: Philox4x32-10 counter (i, e, 0, 8)
+__global__ void k_epoch_keys(int64_t n, int epoch, uint32_t k0, uint32_t k1, unsigned long long *__restrict__ key,
+                             int *__restrict__ idx) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    uint32_t c[4] = {static_cast<uint32_t>(i), static_cast<uint32_t>(epoch), 0u, 8u};
+    philox(c, k0, k1);
+    key[i] = (static_cast<unsigned long long>(c[0]) << 32) | c[1];
+    idx[i] = static_cast<int>(i);
+}
+
+// rows perm[b0 .. b0 + B) of the examples into the batch buffers
+__global__ void k_epoch_gather(const float *__restrict__ feat, const float *__restrict__ label,
+                               const int *__restrict__ perm, int64_t b0, int64_t B, float *__restrict__ bf,
+                               float *__restrict__ bl) {
+    const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (t >= B * 16) return;
+    const int64_t r = t >> 4, k = t & 15;
+    const int64_t src = perm[b0 + r];
+    bf[t] = feat[src * 16 + k];
+    if (k == 0) bl[r] = label[src];
+}
+
+__global__ void k_epoch_add(const double *__restrict__ v, double *__restrict__ acc, int first) {
+    *acc = first ? *v : *acc + *v;
+}
+
+struct EpochWs {
+    unsigned long long *key_in, *key_out;
+    int *idx_in, *idx_out;
+    void *tmp;
+    size_t tmp_bytes;
+    float *bf, *bl;
+    double *acc;
+    MlpTrainWs t;
+};
+
+size_t carve_epoch(Carver &cv, EpochWs &w, int64_t n, int64_t batch) {
+    w.key_in = cv.take<unsigned long long>(std::max<int64_t>(n, 1));
+    w.key_out = cv.take<unsigned long long>(std::max<int64_t>(n, 1));
+    w.idx_in = cv.take<int>(std::max<int64_t>(n, 1));
+    w.idx_out = cv.take<int>(std::max<int64_t>(n, 1));
+    size_t tmp = 0;
+    (void)hipcub::DeviceRadixSort::SortPairs(nullptr, tmp, static_cast<unsigned long long *>(nullptr),
+                                             static_cast<unsigned long long *>(nullptr), static_cast<int *>(nullptr),
+                                             static_cast<int *>(nullptr), static_cast<int>(std::max<int64_t>(n, 1)));
+    w.tmp_bytes = tmp;
+    w.tmp = cv.take<char>(static_cast<int64_t>(tmp));
+    w.bf = cv.take<float>(batch * 16);
+    w.bl = cv.take<float>(batch);
+    w.acc = cv.take<double>(1);
+    carve_train(cv, w.t, batch);
+    return cv.size();
+}
+}  // namespace
+}  // namespace laue
+
+extern "C" size_t laue_mlp_epoch_workspace_size(int64_t n, int64_t batch) {
+    if (n < 1 || batch < 16) return 0;
+    Carver cv(nullptr);
+    EpochWs w;
+    return carve_epoch(cv, w, n, batch);
+}
+
+extern "C" int laue_mlp_train_epoch(laue_mlp *m, const float *feat, const float *label, int64_t n, int64_t batch,
+                                    uint64_t seed, int32_t epoch, const laue_adam_params *ap, double *loss_mean,
+                                    void *ws, size_t ws_bytes, void *stream) {
+    clear_error();
+    int rc;
+    if ((rc = validate_mlp(m))) return rc;
+    LAUE_REQUIRE(batch >= 16 && batch % 16 == 0 && batch <= (1 << 24), LAUE_EINVAL,
+                 "batch must be a positive multiple of 16");
+    LAUE_REQUIRE(n >= batch && n < (int64_t(1) << 31) && feat && label && ap && loss_mean && epoch >= 0,
+                 LAUE_EINVAL, "need at least one batch of examples (n < 2^31), features, labels and outputs");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    Carver cv(ws);
+    EpochWs w;
+    const size_t need = carve_epoch(cv, w, n, batch);
+    if ((rc = check_ws(ws, ws_bytes, need))) return rc;
+    const uint32_t k0 = static_cast<uint32_t>(seed & 0xffffffffu), k1 = static_cast<uint32_t>(seed >> 32);
+    k_epoch_keys<<<static_cast<unsigned>((n + 255) / 256), 256, 0, s>>>(n, epoch, k0, k1, w.key_in, w.idx_in);
+    LAUE_CHECK_HIP(hipGetLastError());
+    size_t tb = w.tmp_bytes;
+    LAUE_CHECK_HIP(hipcub::DeviceRadixSort::SortPairs(w.tmp, tb, w.key_in, w.key_out, w.idx_in, w.idx_out,
+                                                     static_cast<int>(n), 0, 64, s));
+    const int64_t nb = n / batch;
+    for (int64_t b = 0; b < nb; ++b) {
+        k_epoch_gather<<<static_cast<unsigned>((batch * 16 + 255) / 256), 256, 0, s>>>(feat, label, w.idx_out,
+                                                                                      b * batch, batch, w.bf, w.bl);
+        if ((rc = backward_core(m, w.bf, w.bl, batch, w.t, s))) return rc;
+        k_epoch_add<<<1, 1, 0, s>>>(w.t.lsum, w.acc, b == 0);
+        if ((rc = laue_mlp_adam(m, w.t.grad, ap, stream))) return rc;
+    }
+    LAUE_CHECK_HIP(hipGetLastError());
+    double tot = 0.0;
+    LAUE_CHECK_HIP(hipMemcpyAsync(&tot, w.acc, sizeof(double), hipMemcpyDeviceToHost, s));
+    LAUE_CHECK_HIP(hipStreamSynchronize(s));
+    *loss_mean = tot / static_cast<double>(nb * batch);
+    return LAUE_OK;
 }

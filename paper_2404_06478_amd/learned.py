@@ -7,8 +7,8 @@ the densities of interest almost no random pair comes from one grain, so half
 of the pairs are drawn among same-grain spots (laue_pairs_same_grain); their
 wrong plane hypotheses are negatives as well.  Every step runs in the
 library: simulation, candidates, features, labels, and the network's
-forward, backward and Adam kernels.  Batches are drawn by a seeded
-permutation of the example indices.
+forward, backward and Adam kernels, and the batches of each epoch
+(laue_mlp_train_epoch draws the seeded example order and gathers them).
 """
 from __future__ import annotations
 
@@ -16,8 +16,8 @@ import time
 
 import numpy as np
 
-from . import (Grains, MlpTrainer, adam_params, laue_candidate_labels, laue_candidate_support,
-               laue_candidates_generate, laue_mlp_forward, laue_pairs_same_grain, laue_simulate)
+from . import (Grains, adam_params, laue_candidate_labels, laue_candidate_support, laue_candidates_generate,
+               laue_mlp_forward, laue_mlp_train_epoch, laue_pairs_same_grain, laue_simulate)
 
 
 def sample_examples(geom, planes, truth, sigma_mm, distance, outlier_frac, seed, n_pairs_random,
@@ -61,23 +61,16 @@ def training_set(geom, planes, truths, sigma_mm, distance, outlier_frac, seeds, 
 
 
 def train(net, feat, label, epochs=8, batch=4096, lr=1e-3, seed=0, log=None):
-    """Adam on the mean binary cross-entropy; returns the mean loss per epoch."""
-    import torch
-    n = (feat.shape[0] // batch) * batch
-    if n == 0:
+    """Adam on the mean binary cross-entropy, one library epoch call per epoch
+    (the library draws each epoch's example order); returns the mean loss per
+    epoch."""
+    if feat.shape[0] < batch:
         raise ValueError("fewer examples than one batch")
-    tr = MlpTrainer(net, batch, adam_params(lr=lr))
-    gen = torch.Generator(device="cpu").manual_seed(int(seed))
+    ap = adam_params(lr=lr)
     out = []
     for ep in range(epochs):
-        perm = torch.randperm(feat.shape[0], generator=gen)[:n].to(feat.device)
-        fe = feat[perm].contiguous()
-        la = label[perm].contiguous()
         t0 = time.time()
-        tot = 0.0
-        for b0 in range(0, n, batch):
-            tot += tr.laue_mlp_train_step(fe[b0:b0 + batch], la[b0:b0 + batch])
-        out.append(tot / (n // batch))
+        out.append(laue_mlp_train_epoch(net, feat, label, batch, seed, ep, ap))
         if log:
             log(f"epoch {ep}: loss {out[-1]:.4f} ({time.time() - t0:.2f} s)")
     return out

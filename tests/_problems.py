@@ -65,3 +65,35 @@ def gpu_objects(laue, P):
                                         P.s12[:, 0], P.s12[:, 1], P.vloc[:, 0], P.vloc[:, 1],
                                         P.vloc[:, 2])
     return geom, planes, obs, model
+
+
+def tied_rows(P, rho, rel=1e-5, abs_=1e-5):
+    """Detected spots whose rho-nearest model-spot set is decided by a near-tie:
+    the rho-th and (rho+1)-th smallest FP64 costs of the row lie within the
+    FP32 cost accuracy of each other, so an FP32 evaluation may pick either."""
+    out = []
+    off = P.obs["offsets"]
+    for b, Cb in enumerate(oracle_costs(P)):
+        k = min(int(rho), Cb.shape[1])
+        if k == 0 or k == Cb.shape[1]:
+            continue
+        s = np.sort(Cb, axis=1)
+        gap = s[:, k] - s[:, k - 1]
+        out.extend(off[b] + np.flatnonzero(gap <= rel * s[:, k - 1] + abs_))
+    return np.array(out, dtype=np.int64)
+
+
+def without_tied_rows(P, rho):
+    """The problem with the near-tied detected spots of tied_rows removed (the
+    other rows keep their sets: a row's set depends on its own costs only)."""
+    drop = tied_rows(P, rho)
+    if drop.size == 0:
+        return P
+    n = P.obs["p12"].shape[0]
+    keep = np.ones(n, bool)
+    keep[drop] = False
+    obs = {k: (v[keep] if isinstance(v, np.ndarray) and v.shape[:1] == (n,) else v) for k, v in P.obs.items()}
+    nb = P.geom.n_blocks
+    obs["offsets"] = forward.block_offsets(obs["block"], nb)
+    obs["n_true"] = np.bincount(obs["block"][obs["grain"] >= 0], minlength=nb).astype(np.int64)
+    return dataclasses.replace(P, obs=obs)
