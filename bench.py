@@ -309,12 +309,14 @@ def bench_batching(laue, n_samples, n_stages, log):
         f"{sum(it[3].n for it in items)} model spots in all")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    seq, seq_entries = [], 0
+    seq, seq_entries, seq_pass_ms, seq_pass_entries = [], 0, 0.0, 0
     for geom, planes, obs, model, par, (q0, x0), _ in items:
         gr = laue.Grains(q0, x0)
         o = laue.laue_em(geom, planes, obs, model, par, gr, assign=False)
         seq.append(gr)
         seq_entries += o["cost_entries"]
+        seq_pass_ms += o["sinkhorn_ms"] + o["mstep_ms"]
+        seq_pass_entries += o["sinkhorn_entries"] + o["mstep_entries"]
     torch.cuda.synchronize()
     t_seq = time.perf_counter() - t0
     log(f"batching: sequential {t_seq:.2f} s")
@@ -327,12 +329,21 @@ def bench_batching(laue, n_samples, n_stages, log):
     t_b = time.perf_counter() - t0
     log(f"batching: batched {t_b:.2f} s")
     b_entries = sum(o["cost_entries"] for o in outs)
+    # pass time (HIP events around the Sinkhorn and M-step passes, the batch's
+    # totals in every entry of a batched call) and the entries it covers
+    b_pass_ms = outs[0]["sinkhorn_ms"] + outs[0]["mstep_ms"]
+    b_pass_entries = sum(o["sinkhorn_entries"] + o["mstep_entries"] for o in outs)
     same = all(torch.equal(a.q, b.q) and torch.equal(a.x, b.x) for a, b in zip(seq, grains))
     return {"samples": n_samples, "em_iterations": n_stages,
             "grains": [int(it[6].n_grains) for it in items][:8] + ["..."],
             "sequential_s": t_seq, "batched_s": t_b, "speedup": t_seq / t_b,
             "sequential_entries_per_s": seq_entries / t_seq, "batched_entries_per_s": b_entries / t_b,
             "batched_em_iters_per_s": n_samples * n_stages / t_b,
+            "passes": {"sequential_ms": seq_pass_ms, "batched_ms": b_pass_ms,
+                       "sequential_share_of_wall": seq_pass_ms * 1e-3 / t_seq,
+                       "batched_share_of_wall": b_pass_ms * 1e-3 / t_b,
+                       "sequential_entries_per_s": seq_pass_entries / max(seq_pass_ms * 1e-3, 1e-12),
+                       "batched_entries_per_s": b_pass_entries / max(b_pass_ms * 1e-3, 1e-12)},
             "launch_used": outs[0]["launch_used"], "identical_to_sequential": bool(same)}
 
 
@@ -429,12 +440,13 @@ def bench_index(laue, workload, n_pairs, learned_pairs, log, sobol_points=0, rec
                      "em_cost_entries": st["em"]["cost_entries"],
                      "em_zeta": st["em"]["zeta"], "likelihood": st["em"]["objective"]["sem_objective"],
                      "prototypes": st["n_prototypes"], "recall": r / len(q), "time_s": wall,
-                     "score_pairs": st["score_pairs"],
+                     "score_pairs": st["score_pairs"], "score_pairs_evaluated": st["score_pairs_evaluated"],
                      "score_pairs_per_s": st["score_pairs"] / max(st["ms_score"] * 1e-3, 1e-12),
                      "stage_ms": {k: st[k] for k in ("ms_candidates", "ms_proposal", "ms_score", "ms_greedy",
                                                      "ms_em")}}
         log(f"index: {mode}: {pairs} {'points' if mode == 'sobol' else 'pairs'}, {st['n_scored']} scored, "
-            f"recall {r}/{len(q)}, {wall:.2f} s")
+            f"recall {r}/{len(q)}, {wall:.2f} s (scoring evaluated "
+            f"{st['score_pairs_evaluated'] / max(st['score_pairs'], 1):.3f} of its pairs)")
     return out
 
 

@@ -623,11 +623,22 @@ typedef struct laue_score_out {
     float *lbar_val;
     int64_t lbar_cap;
     int64_t lbar_n;
-    int64_t pairs_streamed;   /* (out) same-block (detected, model) pairs taken
-                               * through cost -> exp -> accumulate, all passes */
+    int64_t pairs_streamed;   /* (out) same-block (detected, model) pairs of all
+                               * passes: the work the method defines */
+    int64_t pairs_evaluated;  /* (out) of those, the pairs the refinement passes
+                               * evaluate (see below) plus the scoring passes' */
 } laue_score_out;
 
-size_t laue_score_workspace_size(const laue_geometry *geom, const laue_score_params *par);
+/* The refinement passes read each block's detected spots through a cell
+ * index (a 32 x 32 grid over the block's bounding box, spots sorted stably by
+ * cell): a (block, candidate) pass evaluates only the spots of the cells
+ * within R_j of one of the candidate's model spots s_j, where R_j is the
+ * detector distance beyond which the plan term exp(-c / eps) of model spot j
+ * is 0 in FP32 (from c' >= t^2 v_n^2 / (2 |v|^2), t = |delta| / (|v| + |delta|),
+ * a bound that holds for every detected spot delta away in the detector
+ * plane).  The skipped pairs add exactly 0 to every sum.  n_obs (the
+ * detected spots of the calls) sizes the index; n_obs < 2^31. */
+size_t laue_score_workspace_size(const laue_geometry *geom, int64_t n_obs, const laue_score_params *par);
 
 /* Refines the candidates in place (q, x) and scores them.  Returns
  * LAUE_ECAPACITY if a batch or the SPOT output overflows.  Synchronous. */
@@ -841,7 +852,8 @@ typedef struct laue_index_stats {
     int64_t n_model_spots;
     double ms_candidates, ms_proposal, ms_score, ms_greedy, ms_em, ms_total;
     laue_em_stats em;
-    int64_t score_pairs;            /* pairs streamed by the scoring stage */
+    int64_t score_pairs;            /* same-block pairs of the scoring stage (laue_score_out.pairs_streamed) */
+    int64_t score_pairs_evaluated;  /* of those, the pairs evaluated (laue_score_out.pairs_evaluated) */
 } laue_index_stats;
 
 /* Output grains (device, capacity >= k_max; n_grains = k* on return) and the
@@ -864,6 +876,27 @@ size_t laue_index_workspace_size(const laue_geometry *geom, int32_t n_planes, in
 int laue_index(const laue_geometry *geom, const laue_planes *planes, const laue_obs_spots *obs,
                const laue_index_params *par, laue_index_out *out, laue_index_stats *stats,
                void *ws, size_t ws_bytes, void *stream);
+
+/* laue_index of n independent samples in one call (arrays of n, one entry per
+ * sample; each sample's device arrays, outputs and parameters are its own;
+ * the samples share em.ot.rho).  Stages 1-4 and the prototypes' model spots
+ * run sample by sample (each of those stages fills the GPU on its own); the
+ * final EM of every sample with prototypes then runs as one batch
+ * (laue_em_batched: one launch per pass over all samples) when the samples'
+ * EM parameters allow it (same n_stages, iters_per_stage, gn.k_gn, launch,
+ * tile, ot.chunk, eps_cool, final_iters and number of temperatures, and no
+ * plan-change stop), else sample after sample.  Every sample gets the grains,
+ * assignments and statistics that laue_index gives it alone; the EM and
+ * total milliseconds are the batch's.  Workspace: one region the size of the
+ * largest laue_index workspace or of the batched EM's at the capacities
+ * (max_model_spots, k_max), whichever is larger, plus each sample's model
+ * spots and potentials.  Synchronous; LAUE_ENOCONV when an EM Sinkhorn of
+ * some sample stopped at its cap. */
+size_t laue_index_batched_workspace_size(int32_t n, const laue_geometry *geoms, const int32_t *n_planes,
+                                         const int64_t *n_obs, const laue_index_params *pars);
+int laue_index_batched(int32_t n, const laue_geometry *geoms, const laue_planes *planes,
+                       const laue_obs_spots *obs, const laue_index_params *pars, laue_index_out *outs,
+                       laue_index_stats *stats, void *ws, size_t ws_bytes, void *stream);
 
 #ifdef __cplusplus
 }

@@ -565,7 +565,7 @@ def laue_score_candidates(geom, planes, obs, cand, par, lbar_cap=None):
     dev = _dev()
     n = cand.n
     cap = int(lbar_cap if lbar_cap is not None else max(1024, 64 * obs.n))
-    ws = _workspace(lib.laue_score_workspace_size(C.byref(geom), C.byref(par)))
+    ws = _workspace(lib.laue_score_workspace_size(C.byref(geom), obs.n, C.byref(par)))
     out_t = {"n_model": torch.zeros(max(n, 1), dtype=torch.int32, device=dev),
              "n_unmatched": torch.zeros(max(n, 1), dtype=torch.int32, device=dev),
              "keep": torch.zeros(max(n, 1), dtype=torch.uint8, device=dev),
@@ -584,6 +584,7 @@ def laue_score_candidates(geom, planes, obs, cand, par, lbar_cap=None):
     res["lbar_val"] = out_t["lbar_val"][:so.lbar_n]
     res["lbar_n"] = so.lbar_n
     res["pairs_streamed"] = so.pairs_streamed
+    res["pairs_evaluated"] = so.pairs_evaluated
     return res
 
 
@@ -839,6 +840,27 @@ def laue_index(geom, planes, obs, par, assign=True):
     if need == 0:
         raise LaueError(_abi.LAUE_EINVAL, "invalid index parameters")
     ws = _workspace(need)
+    out, q, x, asg_t = _index_outputs(par, obs.n, assign, dev)
+    st = _abi.laue_index_stats()
+    o = obs.struct()
+    rc = _check(lib.laue_index(C.byref(geom), C.byref(planes.struct), C.byref(o), C.byref(par), C.byref(out),
+                               C.byref(st), _ptr(ws), ws.numel(), _stream()))
+    return _index_result(out, st, q, x, asg_t, obs.n, rc)
+
+
+def _index_result(out, st, q, x, asg_t, n_obs, rc):
+    k = out.n_grains
+    stats = {name: getattr(st, name) for name, _ in _abi.laue_index_stats._fields_ if name != "em"}
+    stats["em"] = _em_stats_dict(st.em)
+    stats["code"] = rc
+    g = Grains.__new__(Grains)
+    g.q, g.x, g.n = q[:max(k, 1)], x[:max(k, 1)], k
+    asg = None if asg_t is None else {kk: v[:n_obs] for kk, v in asg_t.items()}
+    return g, stats, asg
+
+
+def _index_outputs(par, n_obs, assign, dev):
+    import torch
     K = int(par.k_max)
     q = torch.zeros((K, 4), dtype=torch.float64, device=dev)
     x = torch.zeros((K, 3), dtype=torch.float64, device=dev)
@@ -846,21 +868,36 @@ def laue_index(geom, planes, obs, par, assign=True):
     out.capacity, out.q, out.x = K, q.data_ptr(), x.data_ptr()
     asg_t = None
     if assign:
-        asg_t = _assign_tensors(obs.n, 0, dev)
+        asg_t = _assign_tensors(n_obs, 0, dev)
         del asg_t["q_unm"]
         out.assign = laue_assignments(*(asg_t[k].data_ptr() for k in ("j_star", "grain", "q_star", "q_out")))
-    st = _abi.laue_index_stats()
-    o = obs.struct()
-    rc = _check(lib.laue_index(C.byref(geom), C.byref(planes.struct), C.byref(o), C.byref(par), C.byref(out),
-                               C.byref(st), _ptr(ws), ws.numel(), _stream()))
-    k = out.n_grains
-    stats = {name: getattr(st, name) for name, _ in _abi.laue_index_stats._fields_ if name != "em"}
-    stats["em"] = _em_stats_dict(st.em)
-    stats["code"] = rc
-    g = Grains.__new__(Grains)
-    g.q, g.x, g.n = q[:max(k, 1)], x[:max(k, 1)], k
-    asg = None if asg_t is None else {kk: v[:obs.n] for kk, v in asg_t.items()}
-    return g, stats, asg
+    return out, q, x, asg_t
+
+
+def laue_index_batched(geoms, planes, obs, pars, assign=True):
+    """laue_index of independent samples in one call (lists of equal length).
+    Returns (code, list of (Grains, stats dict, assignments) per sample)."""
+    lib = require_native()
+    dev = _dev()
+    n = len(geoms)
+    for par, pl in zip(pars, planes):
+        if par.support.n_support_planes <= 0:
+            par.support.n_support_planes = pl.n
+    G = (laue_geometry * n)(*geoms)
+    PL = (_abi.laue_planes * n)(*[p.struct for p in planes])
+    O = (laue_obs_spots * n)(*[o.struct() for o in obs])
+    PA = (_abi.laue_index_params * n)(*pars)
+    npl = (C.c_int32 * n)(*[p.n for p in planes])
+    nob = (C.c_int64 * n)(*[o.n for o in obs])
+    need = lib.laue_index_batched_workspace_size(n, G, npl, nob, PA)
+    if need == 0:
+        raise LaueError(_abi.LAUE_EINVAL, "invalid index parameters")
+    ws = _workspace(need)
+    outs = [_index_outputs(par, o.n, assign, dev) for par, o in zip(pars, obs)]
+    OUT = (_abi.laue_index_out * n)(*[o[0] for o in outs])
+    ST = (_abi.laue_index_stats * n)()
+    rc = _check(lib.laue_index_batched(n, G, PL, O, PA, OUT, ST, _ptr(ws), ws.numel(), _stream()))
+    return rc, [_index_result(OUT[k], ST[k], outs[k][1], outs[k][2], outs[k][3], obs[k].n, rc) for k in range(n)]
 
 
 def laue_em_batched(geoms, planes, obs, models, pars, grains, assign=True):

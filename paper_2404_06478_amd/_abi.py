@@ -116,7 +116,7 @@ class laue_score_params(C.Structure):
 class laue_score_out(C.Structure):
     _fields_ = [("n_model", vp), ("n_unmatched", vp), ("keep", vp), ("lbar_off", vp),
                 ("lbar_row", vp), ("lbar_val", vp), ("lbar_cap", C.c_int64), ("lbar_n", C.c_int64),
-                ("pairs_streamed", C.c_int64)]
+                ("pairs_streamed", C.c_int64), ("pairs_evaluated", C.c_int64)]
 
 
 class laue_mlp(C.Structure):
@@ -155,7 +155,8 @@ class laue_index_stats(C.Structure):
                 ("lbar_entries", C.c_int64), ("n_picked", C.c_int32), ("n_prototypes", C.c_int32),
                 ("n_model_spots", C.c_int64), ("ms_candidates", C.c_double), ("ms_proposal", C.c_double),
                 ("ms_score", C.c_double), ("ms_greedy", C.c_double), ("ms_em", C.c_double),
-                ("ms_total", C.c_double), ("em", laue_em_stats), ("score_pairs", C.c_int64)]
+                ("ms_total", C.c_double), ("em", laue_em_stats), ("score_pairs", C.c_int64),
+                ("score_pairs_evaluated", C.c_int64)]
 
 
 class laue_index_out(C.Structure):
@@ -196,7 +197,7 @@ SIGNATURES = {
     "laue_candidates_generate": (C.c_int, [P(laue_geometry), P(laue_planes), P(laue_obs_spots),
                                            P(laue_cand_params), P(laue_candidates), P(C.c_int64), vp,
                                            C.c_size_t, vp]),
-    "laue_score_workspace_size": (C.c_size_t, [P(laue_geometry), P(laue_score_params)]),
+    "laue_score_workspace_size": (C.c_size_t, [P(laue_geometry), C.c_int64, P(laue_score_params)]),
     "laue_score_candidates": (C.c_int, [P(laue_geometry), P(laue_planes), P(laue_obs_spots),
                                         P(laue_grains), P(laue_score_params), P(laue_score_out), vp,
                                         C.c_size_t, vp]),
@@ -226,6 +227,11 @@ SIGNATURES = {
     "laue_index_workspace_size": (C.c_size_t, [P(laue_geometry), C.c_int32, C.c_int64, P(laue_index_params)]),
     "laue_index": (C.c_int, [P(laue_geometry), P(laue_planes), P(laue_obs_spots), P(laue_index_params),
                              P(laue_index_out), P(laue_index_stats), vp, C.c_size_t, vp]),
+    "laue_index_batched_workspace_size": (C.c_size_t, [C.c_int32, P(laue_geometry), vp, vp,
+                                                        P(laue_index_params)]),
+    "laue_index_batched": (C.c_int, [C.c_int32, P(laue_geometry), P(laue_planes), P(laue_obs_spots),
+                                     P(laue_index_params), P(laue_index_out), P(laue_index_stats), vp, C.c_size_t,
+                                     vp]),
     "laue_em_batched_workspace_size": (C.c_size_t, [C.c_int32, P(laue_geometry), vp, vp, vp]),
     "laue_sparse_workspace_size": (C.c_size_t, [C.c_int32, P(laue_geometry), vp, vp, vp, C.c_int32]),
     "laue_sobol_workspace_size": (C.c_size_t, [C.c_int64]),

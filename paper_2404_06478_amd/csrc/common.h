@@ -96,6 +96,10 @@ struct Carver {
 
 int check_ws(void *ws, size_t ws_bytes, size_t need);
 
+// number of temperatures of an EM run (the stage schedule, or the cooling
+// from eps_start down to eps_end), without the final iterations
+int em_n_temperatures(const laue_em_params &p);
+
 // ---------------------------------------------------------------- device math
 
 // Plane normal in the lab: u = Gamma_t R w (Sec. 3.3), explicit FMA chains.

@@ -2746,6 +2746,8 @@ static std::vector<double> em_temperatures(const laue_em_params &p) {
     return t;
 }
 
+int em_n_temperatures(const laue_em_params &p) { return static_cast<int>(em_temperatures(p).size()); }
+
 static int run_em(BatchEngine &e, const std::vector<const laue_em_params *> &par, std::vector<laue_em_stats> &stats) {
     int rc;
     const int n = e.n;

@@ -233,6 +233,18 @@ __device__ __forceinline__ float wave_min_f(float v) {
 
 constexpr int kSup = 16;    // 64-row chunks of detected spots held per lane
 
+// Cell index of the detected spots for the refinement passes: each block's
+// spots sorted (stably) into a kCellG x kCellG grid over their bounding box,
+// so that a pass reads only the cells within reach of a candidate's model
+// spots.  Runs of consecutive active cells are contiguous in that order.
+constexpr int kCellG = 32;
+constexpr int kCells = kCellG * kCellG;
+constexpr int kMaxRuns = 256;
+// Exponent (log2 units) beyond which an FP32 plan term exp2(-K c') is 0 for
+// any rounding of c' (2^-150 already rounds to 0; the margin covers the cost's
+// own rounding, a few ulps relative).
+constexpr float kZeroExp2 = 160.0f;
+
 struct SlotArgs {
     int C;                  // candidates in the batch
     int nb;                 // blocks
@@ -245,6 +257,12 @@ struct SlotArgs {
     int n_planes;
     const GrainF *grains;
     const int *mplane, *mgrain, *mblock;
+    // cell index (refinement passes): the spots in cell order, per-(block,
+    // cell) start positions [nb * kCells + 1], per-block grid (x0, y0, cx, cy)
+    const float *P1s, *P2s;
+    const int *cell_off;
+    const float4 *cbox;
+    unsigned long long *evaluated;   // pairs the refinement passes evaluate
 };
 
 // Column data of model spot j held by lane j, read by the whole wave with
@@ -366,19 +384,131 @@ __global__ __launch_bounds__(64) void k_single_acc(SlotArgs A, float K, float bi
             cst[256 + lane] = make_float4(lC.vv, lC.vv2, lC.vn, 0.0f);
         }
     }
+    // Rows that can carry weight.  Every plan term of model spot j is 0 in
+    // FP32 (so adds nothing to a normaliser or a statistic) for detected spots
+    // farther than R_j from s_j on the detector: with delta = p - s in the
+    // detector plane and v_n the normal part of v, |v x delta| >= |delta| v_n
+    // and |v|^2 |d|^2 + (v.d)|v||d| <= 2 |v|^2 (|v| + |delta|)^2, so
+    // c' >= t^2 v_n^2 / (2 |v|^2) with t = |delta| / (|v| + |delta|), and
+    // K c' >= kZeroExp2 once t >= t0 = sqrt(2 kZeroExp2 |v|^2 / (K v_n^2)),
+    // i.e. |delta| >= R_j = t0 |v| / (1 - t0).  The cells of the block's grid
+    // within R_j of some s_j are marked; their spots, in cell order, are the
+    // rows of the passes below (all of the block's when the marked cells
+    // hold most of them or form too many runs).
+    __shared__ float rad2[64];
+    __shared__ unsigned cmask[kCells / 32];
+    __shared__ int run_at[kMaxRuns], run_pre[kMaxRuns + 1];
+    {
+        float R2 = INFINITY;
+        if (lane < nc) {
+            const float vn2 = lE.vn * lE.vn;
+            const float t2 = 2.0f * (kZeroExp2 / K) * lE.vv / vn2;
+            if (vn2 >= 1e-4f * lE.vv && t2 < 0.81f) {
+                const float t0 = sqrtf(t2);
+                const float R = fmaf(t0 * sqrtf(lE.vv) / (1.0f - t0), 1.001f, 1e-3f);
+                R2 = R * R;
+            }
+        }
+        rad2[lane] = R2;
+    }
+    if (lane < kCells / 32) cmask[lane] = 0u;
     __syncthreads();
-    // Detected spots in super-chunks of kSup x 64 rows: each lane keeps its
-    // kSup rows (coordinates and softmax normalisers) in registers, so the
-    // statistics of a model spot accumulate per lane over the whole
-    // super-chunk and are wave-reduced once per super-chunk.
-    for (int64_t s0 = r0; s0 < rend; s0 += 64 * kSup) {
-        const int nrow = static_cast<int>(min<int64_t>(64 * kSup, rend - s0));
+    const float4 bx = A.cbox[b];   // x0, y0, cx, cy
+    const float pad_x = 1e-3f * bx.z + 1e-4f, pad_y = 1e-3f * bx.w + 1e-4f;
+    for (int j = 0; j < nc; ++j) {
+        const float R2 = rad2[j], s1 = cst[j].x, s2 = cst[j].y;
+        int ix0 = 0, ix1 = kCellG - 1, iy0 = 0, iy1 = kCellG - 1;
+        if (R2 < INFINITY) {
+            const float R = sqrtf(R2);
+            // cell coordinates clamped to [-2, 2 G] before the conversion
+            const float lo = -2.0f, hi = 2.0f * kCellG;
+            ix0 = max(0, static_cast<int>(floorf(fminf(fmaxf((s1 - R - bx.x) / bx.z, lo), hi))) - 1);
+            ix1 = min(kCellG - 1, static_cast<int>(floorf(fminf(fmaxf((s1 + R - bx.x) / bx.z, lo), hi))) + 1);
+            iy0 = max(0, static_cast<int>(floorf(fminf(fmaxf((s2 - R - bx.y) / bx.w, lo), hi))) - 1);
+            iy1 = min(kCellG - 1, static_cast<int>(floorf(fminf(fmaxf((s2 + R - bx.y) / bx.w, lo), hi))) + 1);
+        }
+        const int wdt = ix1 - ix0 + 1, hgt = iy1 - iy0 + 1;
+        if (wdt <= 0 || hgt <= 0) continue;
+        for (int k = lane; k < wdt * hgt; k += 64) {
+            const int ix = ix0 + k % wdt, iy = iy0 + k / wdt;
+            const float xa = fmaf(static_cast<float>(ix), bx.z, bx.x) - pad_x, xb = xa + bx.z + 2.0f * pad_x;
+            const float ya = fmaf(static_cast<float>(iy), bx.w, bx.y) - pad_y, yb = ya + bx.w + 2.0f * pad_y;
+            const float dx = fmaxf(0.0f, fmaxf(xa - s1, s1 - xb)), dy = fmaxf(0.0f, fmaxf(ya - s2, s2 - yb));
+            if (fmaf(dx, dx, dy * dy) < R2) {
+                const int cell = iy * kCellG + ix;
+                atomicOr(&cmask[cell >> 5], 1u << (cell & 31));
+            }
+        }
+    }
+    __syncthreads();
+    // runs of marked cells: lane l takes cells 16 l .. 16 l + 15
+    const int *co = A.cell_off + static_cast<int64_t>(b) * kCells;
+    int n_runs, n_act;
+    {
+        const unsigned bits = (cmask[lane >> 1] >> ((lane & 1) * 16)) & 0xFFFFu;
+        const unsigned starts = bits & ~(bits << 1);
+        const int my_runs = __popc(starts);
+        int my_rows = 0;
+        for (unsigned st = starts; st; st &= st - 1) {
+            const int c0 = __ffs(st) - 1;
+            int c1 = c0;
+            while (c1 + 1 < 16 && ((bits >> (c1 + 1)) & 1u)) ++c1;
+            my_rows += co[16 * lane + c1 + 1] - co[16 * lane + c0];
+        }
+        int run_base = my_runs, row_base = my_rows;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int a1 = __shfl_up(run_base, o, 64), a2 = __shfl_up(row_base, o, 64);
+            if (lane >= o) {
+                run_base += a1;
+                row_base += a2;
+            }
+        }
+        n_runs = __shfl(run_base, 63, 64);
+        n_act = __shfl(row_base, 63, 64);
+        run_base -= my_runs;
+        row_base -= my_rows;
+        const int n_block = static_cast<int>(rend - r0);
+        if (n_runs > kMaxRuns || 4 * n_act > 3 * n_block) {
+            n_runs = 1;
+            n_act = n_block;
+            if (lane == 0) {
+                run_at[0] = static_cast<int>(r0);
+                run_pre[0] = 0;
+            }
+        } else {
+            int k = run_base, pre = row_base;
+            for (unsigned st = starts; st; st &= st - 1) {
+                const int c0 = __ffs(st) - 1;
+                int c1 = c0;
+                while (c1 + 1 < 16 && ((bits >> (c1 + 1)) & 1u)) ++c1;
+                run_at[k] = co[16 * lane + c0];
+                run_pre[k] = pre;
+                pre += co[16 * lane + c1 + 1] - co[16 * lane + c0];
+                ++k;
+            }
+        }
+        if (lane == 0) run_pre[n_runs] = n_act;
+    }
+    if (lane == 0 && n_act > 0 && A.evaluated)
+        atomicAdd(A.evaluated, static_cast<unsigned long long>(n_act) * static_cast<unsigned long long>(nc));
+    __syncthreads();
+    // Those rows in super-chunks of kSup x 64: each lane keeps its kSup rows
+    // (coordinates and softmax normalisers) in registers, so the statistics
+    // of a model spot accumulate per lane over the whole super-chunk and are
+    // wave-reduced once per super-chunk.
+    int kr = 0;   // this lane's current run
+    for (int s0 = 0; s0 < n_act; s0 += 64 * kSup) {
+        const int nrow = min(64 * kSup, n_act - s0);
         float p1[kSup], p2[kSup], iz[kSup];
 #pragma unroll
         for (int u = 0; u < kSup; ++u) {
-            const bool rv = 64 * u + lane < nrow;
-            p1[u] = rv ? A.P1[s0 + 64 * u + lane] : 0.0f;
-            p2[u] = rv ? A.P2[s0 + 64 * u + lane] : 0.0f;
+            const int pos = s0 + 64 * u + lane;
+            const bool rv = pos < n_act;
+            while (rv && kr + 1 < n_runs && run_pre[kr + 1] <= pos) ++kr;
+            const int row = rv ? run_at[kr] + (pos - run_pre[kr]) : static_cast<int>(r0);
+            p1[u] = rv ? A.P1s[row] : 0.0f;
+            p2[u] = rv ? A.P2s[row] : 0.0f;
             iz[u] = bin_e;
         }
         for (int j = 0; j < nc; ++j) {
@@ -999,9 +1129,150 @@ extern "C" int laue_candidates_generate(const laue_geometry *geom, const laue_pl
     return LAUE_OK;
 }
 
+// ---------------------------------------------------------------- cell index
+
+namespace laue {
+
+// Per block: the bounding box of its detected spots and the grid's cell size.
+__global__ __launch_bounds__(256) void k_cell_box(const float *__restrict__ P1, const float *__restrict__ P2,
+                                                  const int64_t *__restrict__ ooff, float4 *__restrict__ box) {
+    const int b = blockIdx.x;
+    const int64_t r0 = ooff[b], r1 = ooff[b + 1];
+    float x0 = INFINITY, x1 = -INFINITY, y0 = INFINITY, y1 = -INFINITY;
+    for (int64_t i = r0 + threadIdx.x; i < r1; i += blockDim.x) {
+        const float u = P1[i], v = P2[i];
+        x0 = fminf(x0, u);
+        x1 = fmaxf(x1, u);
+        y0 = fminf(y0, v);
+        y1 = fmaxf(y1, v);
+    }
+    __shared__ float red[4][256];
+    red[0][threadIdx.x] = x0;
+    red[1][threadIdx.x] = -x1;
+    red[2][threadIdx.x] = y0;
+    red[3][threadIdx.x] = -y1;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (static_cast<int>(threadIdx.x) < o)
+            for (int q = 0; q < 4; ++q) red[q][threadIdx.x] = fminf(red[q][threadIdx.x], red[q][threadIdx.x + o]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        x0 = red[0][0];
+        x1 = -red[1][0];
+        y0 = red[2][0];
+        y1 = -red[3][0];
+        if (!(x0 <= x1)) x0 = x1 = 0.0f;
+        if (!(y0 <= y1)) y0 = y1 = 0.0f;
+        box[b] = make_float4(x0, y0, fmaxf((x1 - x0) / kCellG, 1e-6f), fmaxf((y1 - y0) / kCellG, 1e-6f));
+    }
+}
+
+__device__ __forceinline__ int cell_coord(float u) {
+    return u >= 0.0f ? min(kCellG - 1, static_cast<int>(fminf(u, static_cast<float>(kCellG)))) : 0;
+}
+
+// Sort key of every detected spot: block * kCells + cell (row-major cells).
+__global__ void k_cell_keys(const float *__restrict__ P1, const float *__restrict__ P2,
+                            const int64_t *__restrict__ ooff, int nb, const float4 *__restrict__ box, int64_t n,
+                            unsigned *__restrict__ key, int *__restrict__ idx) {
+    for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+         i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+        int lo = 0, hi = nb - 1;            // the block b with ooff[b] <= i < ooff[b + 1]
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (ooff[mid] <= i) lo = mid;
+            else hi = mid - 1;
+        }
+        const float4 bx = box[lo];
+        const int ix = cell_coord((P1[i] - bx.x) / bx.z), iy = cell_coord((P2[i] - bx.y) / bx.w);
+        key[i] = static_cast<unsigned>(lo) * kCells + static_cast<unsigned>(iy * kCellG + ix);
+        idx[i] = static_cast<int>(i);
+    }
+}
+
+__global__ void k_cell_gather(const float *__restrict__ P1, const float *__restrict__ P2,
+                              const int *__restrict__ idx, int64_t n, float *__restrict__ P1s,
+                              float *__restrict__ P2s) {
+    for (int64_t k = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; k < n;
+         k += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+        const int i = idx[k];
+        P1s[k] = P1[i];
+        P2s[k] = P2[i];
+    }
+}
+
+// cell_off[t] = first position whose key is >= t, t = 0 .. nb * kCells.
+__global__ void k_cell_off(const unsigned *__restrict__ key, int64_t n, int64_t n_keys, int *__restrict__ off) {
+    for (int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; t <= n_keys;
+         t += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+        int64_t lo = 0, hi = n;
+        while (lo < hi) {
+            const int64_t mid = (lo + hi) >> 1;
+            if (static_cast<int64_t>(key[mid]) < t) lo = mid + 1;
+            else hi = mid;
+        }
+        off[t] = static_cast<int>(lo);
+    }
+}
+
+}  // namespace laue
+
 // ---------------------------------------------------------------- host: scoring
 
 namespace {
+
+struct CellWs {
+    unsigned *key_in, *key_out;
+    int *idx_in, *idx_out;
+    float *P1s, *P2s;
+    int *off;
+    float4 *box;
+    void *tmp;
+    size_t tmp_bytes;
+};
+
+void carve_cells(Carver &cv, CellWs &w, int nb, int64_t n_obs) {
+    const int64_t n = std::max<int64_t>(n_obs, 1);
+    w.key_in = cv.take<unsigned>(n);
+    w.key_out = cv.take<unsigned>(n);
+    w.idx_in = cv.take<int>(n);
+    w.idx_out = cv.take<int>(n);
+    w.P1s = cv.take<float>(n);
+    w.P2s = cv.take<float>(n);
+    w.off = cv.take<int>(static_cast<int64_t>(nb) * kCells + 1);
+    w.box = cv.take<float4>(nb);
+    size_t tmp = 0;
+    (void)hipcub::DeviceRadixSort::SortPairs(nullptr, tmp, static_cast<unsigned *>(nullptr),
+                                             static_cast<unsigned *>(nullptr), static_cast<int *>(nullptr),
+                                             static_cast<int *>(nullptr), static_cast<int>(n));
+    w.tmp_bytes = tmp;
+    w.tmp = cv.take<char>(tmp);
+}
+
+// The cell index of the detected spots (stable: spots of one cell keep their order).
+int build_cells(CellWs &w, const laue_obs_spots *obs, const int64_t *ooff_dev, int nb, hipStream_t s) {
+    const int64_t n = obs->n;
+    k_cell_box<<<nb, 256, 0, s>>>(obs->p1, obs->p2, ooff_dev, w.box);
+    LAUE_CHECK_HIP(hipGetLastError());
+    const int64_t n_keys = static_cast<int64_t>(nb) * kCells;
+    if (n > 0) {
+        const unsigned g = static_cast<unsigned>(std::min<int64_t>((n + 255) / 256, 4096));
+        k_cell_keys<<<g, 256, 0, s>>>(obs->p1, obs->p2, ooff_dev, nb, w.box, n, w.key_in, w.idx_in);
+        LAUE_CHECK_HIP(hipGetLastError());
+        int end_bit = 1;
+        while (end_bit < 32 && (int64_t(1) << end_bit) <= n_keys) ++end_bit;
+        size_t tb = w.tmp_bytes;
+        LAUE_CHECK_HIP(hipcub::DeviceRadixSort::SortPairs(w.tmp, tb, w.key_in, w.key_out, w.idx_in, w.idx_out,
+                                                         static_cast<int>(n), 0, end_bit, s));
+        k_cell_gather<<<g, 256, 0, s>>>(obs->p1, obs->p2, w.idx_out, n, w.P1s, w.P2s);
+        LAUE_CHECK_HIP(hipGetLastError());
+    }
+    const unsigned go = static_cast<unsigned>(std::min<int64_t>((n_keys + 1 + 255) / 256, 4096));
+    k_cell_off<<<go, 256, 0, s>>>(w.key_out, n, n_keys, w.off);
+    LAUE_CHECK_HIP(hipGetLastError());
+    return LAUE_OK;
+}
 
 struct ScoreWs {
     EnumWs e;
@@ -1013,12 +1284,14 @@ struct ScoreWs {
     int64_t *loff;
     int64_t *ooff;
     int *maxc;
-    int64_t *pairs;   // pairs of all slots, of the kept candidates' slots
+    int64_t *pairs;   // pairs of all slots, of the kept candidates' slots, evaluated by the refinement
+    CellWs cells;
 };
 
-size_t carve_score(Carver &cv, ScoreWs &w, const laue_geometry *g, int chunk, int64_t spot_cap) {
+size_t carve_score(Carver &cv, ScoreWs &w, const laue_geometry *g, int chunk, int64_t spot_cap, int64_t n_obs) {
     const int nb = g->n_rot * g->n_det;
     carve_enum(cv, w.e, g, chunk);
+    carve_cells(cv, w.cells, nb, n_obs);
     const int64_t S = std::max<int64_t>(spot_cap, 1);
     w.plane = cv.take<int>(S);
     w.grain = cv.take<int>(S);
@@ -1032,7 +1305,7 @@ size_t carve_score(Carver &cv, ScoreWs &w, const laue_geometry *g, int chunk, in
     w.keep = cv.take<uint8_t>(chunk);
     w.ooff = cv.take<int64_t>(nb + 1);
     w.maxc = cv.take<int>(1);
-    w.pairs = cv.take<int64_t>(2);
+    w.pairs = cv.take<int64_t>(3);
     return cv.size();
 }
 
@@ -1055,12 +1328,14 @@ int launch_score(const SlotArgs &A, int pass, float twoD2, float K2, float floor
 
 }  // namespace
 
-extern "C" size_t laue_score_workspace_size(const laue_geometry *geom, const laue_score_params *par) {
-    if (!geom || !par || validate_geometry(geom) != LAUE_OK || par->chunk < 1 || par->max_spots_per_cand < 1)
+extern "C" size_t laue_score_workspace_size(const laue_geometry *geom, int64_t n_obs,
+                                            const laue_score_params *par) {
+    if (!geom || !par || validate_geometry(geom) != LAUE_OK || par->chunk < 1 || par->max_spots_per_cand < 1 ||
+        n_obs < 0 || n_obs >= (int64_t(1) << 31))
         return 0;
     Carver cv(nullptr);
     ScoreWs w;
-    return carve_score(cv, w, geom, par->chunk, static_cast<int64_t>(par->chunk) * par->max_spots_per_cand);
+    return carve_score(cv, w, geom, par->chunk, static_cast<int64_t>(par->chunk) * par->max_spots_per_cand, n_obs);
 }
 
 extern "C" int laue_score_candidates(const laue_geometry *geom, const laue_planes *planes,
@@ -1088,11 +1363,13 @@ extern "C" int laue_score_candidates(const laue_geometry *geom, const laue_plane
     hipStream_t s = static_cast<hipStream_t>(stream);
     const int chunk = par->chunk;
     const int64_t spot_cap = static_cast<int64_t>(chunk) * par->max_spots_per_cand;
+    LAUE_REQUIRE(obs->n < (int64_t(1) << 31), LAUE_EINVAL, "scoring takes fewer than 2^31 detected spots");
     Carver cv(ws);
     ScoreWs w;
-    size_t need = carve_score(cv, w, geom, chunk, spot_cap);
+    size_t need = carve_score(cv, w, geom, chunk, spot_cap, obs->n);
     if ((rc = check_ws(ws, ws_bytes, need))) return rc;
     LAUE_CHECK_HIP(hipMemcpyAsync(w.ooff, obs->block_off, (nb + 1) * sizeof(int64_t), hipMemcpyHostToDevice, s));
+    if ((rc = build_cells(w.cells, obs, w.ooff, nb, s))) return rc;
     const double l2e = 1.4426950408889634;
     const double D2 = par->distance * par->distance;
     const float twoD2 = static_cast<float>(2.0 * D2);
@@ -1103,6 +1380,7 @@ extern "C" int laue_score_candidates(const laue_geometry *geom, const laue_plane
     out->pairs_streamed = 0;
     k_set_i64<<<1, 1, 0, s>>>(w.pairs, 0);
     k_set_i64<<<1, 1, 0, s>>>(w.pairs + 1, 0);
+    k_set_i64<<<1, 1, 0, s>>>(w.pairs + 2, 0);
     LAUE_CHECK_HIP(hipGetLastError());
     unsigned long long *pairs = reinterpret_cast<unsigned long long *>(w.pairs);
     if (N == 0) {
@@ -1149,6 +1427,11 @@ extern "C" int laue_score_candidates(const laue_geometry *geom, const laue_plane
         A.mplane = w.plane;
         A.mgrain = w.grain;
         A.mblock = w.block;
+        A.P1s = w.cells.P1s;
+        A.P2s = w.cells.P2s;
+        A.cell_off = w.cells.off;
+        A.cbox = w.cells.box;
+        A.evaluated = pairs + 2;
         // pairs of one pass over every slot (the refinement's k_refine * k_gn
         // statistics passes and the first scoring pass stream them all; the
         // second scoring pass streams the kept candidates' slots only)
@@ -1218,10 +1501,11 @@ extern "C" int laue_score_candidates(const laue_geometry *geom, const laue_plane
         lbar_total += ctot;
     }
     out->lbar_n = lbar_total;
-    int64_t hp[2] = {0, 0};
-    LAUE_CHECK_HIP(hipMemcpyAsync(hp, w.pairs, 2 * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    int64_t hp[3] = {0, 0, 0};
+    LAUE_CHECK_HIP(hipMemcpyAsync(hp, w.pairs, 3 * sizeof(int64_t), hipMemcpyDeviceToHost, s));
     LAUE_CHECK_HIP(hipStreamSynchronize(s));
     out->pairs_streamed = (static_cast<int64_t>(par->k_refine) * par->k_gn + 1) * hp[0] + hp[1];
+    out->pairs_evaluated = hp[2] + hp[0] + hp[1];
     return LAUE_OK;
 }
 

@@ -57,14 +57,14 @@ size_t scratch_size(const laue_geometry *g, int n_planes, int64_t n_obs, const l
         s = std::max(s, laue_select_top_workspace_size(p->max_candidates));
     }
     if (p->mode == LAUE_INDEX_SOBOL) s = std::max(s, laue_sobol_workspace_size(p->max_candidates));
-    s = std::max(s, laue_score_workspace_size(g, &p->score));
+    s = std::max(s, laue_score_workspace_size(g, n_obs, &p->score));
     // the greedy's minimum plus room for its live-entry buffers (16 bytes per
     // entry, up to 2^30 entries: a smaller room only delays the compaction)
     s = std::max(s, laue_spot_greedy_workspace_size(static_cast<int32_t>(n_scored_max(p)), n_obs) +
                         16 * static_cast<size_t>(std::min<int64_t>(p->lbar_cap, int64_t(1) << 30)));
     s = std::max(s, laue_forward_workspace_size(g, n_planes, p->k_max));
     s = std::max(s, laue_sinkhorn_workspace_size(g, n_obs, p->max_model_spots, p->k_max));
-    if (p->em.eps_cool > 0.0 && !(p->em.eps_start > 0.0)) {
+    if (p->em.ot.rho > 0 || (p->em.eps_cool > 0.0 && !(p->em.eps_start > 0.0))) {
         const int64_t no = n_obs, nm = p->max_model_spots;
         const int32_t ng = p->k_max;
         s = std::max(s, laue_sparse_workspace_size(1, g, &no, &nm, &ng, p->em.ot.rho > 0 ? p->em.ot.rho : 32));
@@ -174,28 +174,33 @@ extern "C" size_t laue_index_workspace_size(const laue_geometry *geom, int32_t n
     return carve_index(cv, w, geom, n_planes, n_obs, par);
 }
 
-extern "C" int laue_index(const laue_geometry *geom, const laue_planes *planes, const laue_obs_spots *obs,
-                          const laue_index_params *par, laue_index_out *out, laue_index_stats *stats, void *ws,
-                          size_t ws_bytes, void *stream) {
-    clear_error();
+namespace laue {
+namespace {
+
+// What the EM stage of one sample needs once stages 1-5a have run.
+struct EmJob {
+    laue_grains protos;
+    laue_model_spots model;
+    laue_em_params em;
+    laue_potentials pot;
+    laue_assignments asg;
+    bool with_assign;
+    std::vector<int64_t> moff;   // host block offsets of model (model.block_off points here)
+};
+
+// Stages 1-4 and the first half of 5 for one sample: candidates, proposal,
+// refinement and scoring, greedy SPOT, the k* prototypes into out, their
+// frozen model spots (w.mplane ... w.flags), the EM's temperatures and bins,
+// zeroed potentials (w.f, w.g).  job.protos.n = 0 when k* = 0.
+int index_front(const laue_geometry *geom, const laue_planes *planes, const laue_obs_spots *obs,
+                const laue_index_params *par, laue_index_out *out, IndexWs &w, laue_index_stats &st, EmJob &job,
+                hipStream_t s) {
     int rc;
-    if ((rc = validate_geometry(geom)) || (rc = validate_planes(planes)) || (rc = validate_index_params(par)))
-        return rc;
-    LAUE_REQUIRE(obs && obs->block_off && obs->n >= 0, LAUE_EINVAL, "detected spots are NULL");
-    LAUE_REQUIRE(out && out->q && out->x && out->capacity >= par->k_max, LAUE_EINVAL,
-                 "output grains need capacity >= k_max");
-    const laue_assignments &as = out->assign;
-    const bool with_assign = as.j_star && as.grain && as.q_star && as.q_out;
-    LAUE_REQUIRE(with_assign || (!as.j_star && !as.grain && !as.q_star && !as.q_out), LAUE_EINVAL,
-                 "assignment arrays must be all given or all NULL");
-    hipStream_t s = static_cast<hipStream_t>(stream);
-    Carver cv(ws);
-    IndexWs w;
-    const size_t need = carve_index(cv, w, geom, planes->n, obs->n, par);
-    if ((rc = check_ws(ws, ws_bytes, need))) return rc;
-    laue_index_stats st{};
-    const auto t_all = std::chrono::steady_clock::now();
+    void *stream = s;
     const int nb = geom->n_rot * geom->n_det;
+    const laue_assignments &as = out->assign;
+    job.with_assign = as.j_star && as.grain && as.q_star && as.q_out;
+    job.protos = laue_grains{0, out->q, out->x};
     out->n_grains = 0;
 
     // 1. spot-pair candidates
@@ -268,6 +273,7 @@ extern "C" int laue_index(const laue_geometry *geom, const laue_planes *planes, 
     }
     st.lbar_entries = so.lbar_n;
     st.score_pairs = so.pairs_streamed;
+    st.score_pairs_evaluated = so.pairs_evaluated;
     if (log_enabled()) LAUE_CHECK_HIP(hipStreamSynchronize(s));
     st.ms_score = ms_since(t0);
     log_line("index: scored %lld candidates, %lld SPOT entries, in %.1f ms", static_cast<long long>(n_sc),
@@ -304,16 +310,14 @@ extern "C" int laue_index(const laue_geometry *geom, const laue_planes *planes, 
     log_line("index: greedy picked %d, k* = %d, in %.1f ms", n_picked, k_star, st.ms_greedy);
     out->n_grains = k_star;
     if (k_star == 0) {
-        st.ms_total = ms_since(t_all);
-        if (stats) *stats = st;
         LAUE_CHECK_HIP(hipStreamSynchronize(s));
         return LAUE_OK;
     }
 
-    // 5. frozen model spots of the prototypes, then EM
+    // 5. frozen model spots of the prototypes, then (the caller) EM
     t0 = std::chrono::steady_clock::now();
     laue_grains protos{k_star, out->q, out->x};
-    std::vector<int64_t> moff(nb + 1, 0);
+    job.moff.assign(nb + 1, 0);
     laue_model_spots model{};
     model.n = par->max_model_spots;
     model.plane = w.mplane;
@@ -326,7 +330,7 @@ extern "C" int laue_index(const laue_geometry *geom, const laue_planes *planes, 
     model.v2 = w.v2;
     model.lam = w.lam;
     model.flags = w.flags;
-    model.block_off = moff.data();
+    model.block_off = job.moff.data();
     int64_t n_model = 0;
     if ((rc = laue_forward_enumerate(geom, planes, &protos, 1, &model, &n_model, w.scratch, w.scratch_bytes, stream)))
         return rc;
@@ -353,19 +357,265 @@ extern "C" int laue_index(const laue_geometry *geom, const laue_planes *planes, 
     k_zero_f<<<static_cast<unsigned>((nf + 255) / 256), 256, 0, s>>>(w.f, nf);
     k_zero_f<<<static_cast<unsigned>((ng + 255) / 256), 256, 0, s>>>(w.g, ng);
     LAUE_CHECK_HIP(hipGetLastError());
-    laue_potentials pot{w.f, w.g, 0.0, 0.0};
-    laue_em_stats es{};
+    job.protos = protos;
+    job.model = model;
+    job.em = em;
+    job.pot = laue_potentials{w.f, w.g, 0.0, 0.0};
     // the model spots live in the workspace: no per-model-spot output
-    laue_assignments asg = out->assign;
-    asg.q_unm = nullptr;
-    rc = laue_em(geom, planes, obs, &model, &em, &protos, &pot, with_assign ? &asg : nullptr, &es,
-                 w.scratch, w.scratch_bytes, stream);
-    if (rc < 0) return rc;
-    st.em = es;
+    job.asg = out->assign;
+    job.asg.q_unm = nullptr;
     st.ms_em = ms_since(t0);
-    log_line("index: EM on %lld model spots, %d iterations, in %.1f ms", static_cast<long long>(n_model),
-             es.n_em_iter, st.ms_em);
+    return LAUE_OK;
+}
+
+// Whether laue_em_batched takes these EM jobs in one batch: the samples share
+// what a batch shares (schedule shape, Gauss-Newton steps, launch, tile,
+// chunk, rho and assignment kind) and none asks for the plan-change stop.
+bool batchable(const std::vector<EmJob *> &jobs) {
+    const laue_em_params &a = jobs[0]->em;
+    for (const EmJob *j : jobs) {
+        const laue_em_params &b = j->em;
+        if (b.eps_cool > 0.0 && b.zeta_tol > 0.0) return false;
+        if (b.n_stages != a.n_stages || b.iters_per_stage != a.iters_per_stage || b.gn.k_gn != a.gn.k_gn ||
+            b.launch != a.launch || b.tile != a.tile || b.ot.chunk != a.ot.chunk || b.eps_cool != a.eps_cool ||
+            b.final_iters != a.final_iters || b.ot.rho != a.ot.rho)
+            return false;
+        if (em_n_temperatures(b) != em_n_temperatures(a)) return false;
+    }
+    return true;
+}
+
+size_t em_batch_workspace(const std::vector<laue_geometry> &g, const std::vector<int64_t> &no,
+                          const std::vector<int64_t> &nm, const std::vector<int32_t> &ng, int32_t rho) {
+    const int32_t n = static_cast<int32_t>(g.size());
+    return rho > 0 ? laue_sparse_workspace_size(n, g.data(), no.data(), nm.data(), ng.data(), rho)
+                   : laue_em_batched_workspace_size(n, g.data(), no.data(), nm.data(), ng.data());
+}
+
+// The per-sample storage of laue_index_batched that outlives the front:
+// model spots and potentials.
+size_t carve_persist(Carver &cv, IndexWs &w, int64_t n_obs, const laue_index_params *p) {
+    const int64_t J = std::max<int64_t>(p->max_model_spots, 1);
+    w.mplane = cv.take<int>(J);
+    w.mgrain = cv.take<int>(J);
+    w.mblock = cv.take<int>(J);
+    w.s1 = cv.take<float>(J);
+    w.s2 = cv.take<float>(J);
+    w.vn = cv.take<float>(J);
+    w.v1 = cv.take<float>(J);
+    w.v2 = cv.take<float>(J);
+    w.lam = cv.take<float>(J);
+    w.flags = cv.take<uint8_t>(J);
+    w.f = cv.take<float>(std::max<int64_t>(n_obs, 1));
+    w.g = cv.take<float>(J);
+    return cv.size();
+}
+
+int validate_index_call(const laue_geometry *geom, const laue_planes *planes, const laue_obs_spots *obs,
+                        const laue_index_params *par, const laue_index_out *out) {
+    int rc;
+    if ((rc = validate_geometry(geom)) || (rc = validate_planes(planes)) || (rc = validate_index_params(par)))
+        return rc;
+    LAUE_REQUIRE(obs && obs->block_off && obs->n >= 0, LAUE_EINVAL, "detected spots are NULL");
+    LAUE_REQUIRE(out && out->q && out->x && out->capacity >= par->k_max, LAUE_EINVAL,
+                 "output grains need capacity >= k_max");
+    const laue_assignments &as = out->assign;
+    const bool with_assign = as.j_star && as.grain && as.q_star && as.q_out;
+    LAUE_REQUIRE(with_assign || (!as.j_star && !as.grain && !as.q_star && !as.q_out), LAUE_EINVAL,
+                 "assignment arrays must be all given or all NULL");
+    return LAUE_OK;
+}
+
+}  // namespace
+}  // namespace laue
+
+extern "C" int laue_index(const laue_geometry *geom, const laue_planes *planes, const laue_obs_spots *obs,
+                          const laue_index_params *par, laue_index_out *out, laue_index_stats *stats, void *ws,
+                          size_t ws_bytes, void *stream) {
+    clear_error();
+    int rc;
+    if ((rc = validate_index_call(geom, planes, obs, par, out))) return rc;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    Carver cv(ws);
+    IndexWs w;
+    const size_t need = carve_index(cv, w, geom, planes->n, obs->n, par);
+    if ((rc = check_ws(ws, ws_bytes, need))) return rc;
+    laue_index_stats st{};
+    const auto t_all = std::chrono::steady_clock::now();
+    EmJob job{};
+    if ((rc = index_front(geom, planes, obs, par, out, w, st, job, s))) return rc;
+    if (job.protos.n > 0) {
+        const auto t0 = std::chrono::steady_clock::now();
+        laue_em_stats es{};
+        rc = laue_em(geom, planes, obs, &job.model, &job.em, &job.protos, &job.pot,
+                     job.with_assign ? &job.asg : nullptr, &es, w.scratch, w.scratch_bytes, stream);
+        if (rc < 0) return rc;
+        st.em = es;
+        st.ms_em += ms_since(t0);
+        log_line("index: EM on %lld model spots, %d iterations, in %.1f ms", static_cast<long long>(job.model.n),
+                 es.n_em_iter, st.ms_em);
+    }
     st.ms_total = ms_since(t_all);
     if (stats) *stats = st;
     return rc;
+}
+
+namespace laue {
+namespace {
+
+// Workspace of laue_index_batched: one shared region (each sample's stages
+// 1-5a in turn, then the EM of all samples), then every sample's model spots
+// and potentials.  Returns the size; with a base, fills shared and persist.
+size_t carve_batched(Carver &cv, int32_t n, const laue_geometry *geoms, const int32_t *n_planes,
+                     const int64_t *n_obs, const laue_index_params *pars, char **shared, size_t *shared_bytes,
+                     std::vector<IndexWs> *persist) {
+    size_t front = 0;
+    std::vector<laue_geometry> g(geoms, geoms + n);
+    std::vector<int64_t> no(n_obs, n_obs + n), nm(n);
+    std::vector<int32_t> ng(n);
+    for (int k = 0; k < n; ++k) {
+        const size_t one = laue_index_workspace_size(geoms + k, n_planes[k], n_obs[k], pars + k);
+        if (one == 0) return 0;
+        front = std::max(front, one);
+        nm[k] = pars[k].max_model_spots;
+        ng[k] = pars[k].k_max;
+    }
+    const size_t em = em_batch_workspace(g, no, nm, ng, pars[0].em.ot.rho);
+    if (em == 0) return 0;
+    const size_t sh = std::max(front, em);
+    char *p = cv.take<char>(sh);
+    if (shared) *shared = p;
+    if (shared_bytes) *shared_bytes = sh;
+    if (persist) persist->assign(n, IndexWs{});
+    for (int k = 0; k < n; ++k) {
+        IndexWs w{};
+        carve_persist(cv, w, n_obs[k], pars + k);
+        if (persist) (*persist)[k] = w;
+    }
+    return cv.size();
+}
+
+}  // namespace
+}  // namespace laue
+
+extern "C" size_t laue_index_batched_workspace_size(int32_t n, const laue_geometry *geoms, const int32_t *n_planes,
+                                                    const int64_t *n_obs, const laue_index_params *pars) {
+    if (n < 1 || !geoms || !n_planes || !n_obs || !pars) return 0;
+    Carver cv(nullptr);
+    return carve_batched(cv, n, geoms, n_planes, n_obs, pars, nullptr, nullptr, nullptr);
+}
+
+extern "C" int laue_index_batched(int32_t n, const laue_geometry *geoms, const laue_planes *planes,
+                                  const laue_obs_spots *obs, const laue_index_params *pars, laue_index_out *outs,
+                                  laue_index_stats *stats, void *ws, size_t ws_bytes, void *stream) {
+    clear_error();
+    int rc;
+    LAUE_REQUIRE(n >= 1 && geoms && planes && obs && pars && outs, LAUE_EINVAL, "NULL argument");
+    std::vector<int32_t> npl(n);
+    std::vector<int64_t> nob(n);
+    for (int k = 0; k < n; ++k) {
+        if ((rc = validate_index_call(geoms + k, planes + k, obs + k, pars + k, outs + k))) return rc;
+        LAUE_REQUIRE(pars[k].em.ot.rho == pars[0].em.ot.rho, LAUE_EINVAL, "samples of a batch share em.ot.rho");
+        npl[k] = planes[k].n;
+        nob[k] = obs[k].n;
+    }
+    const size_t need = laue_index_batched_workspace_size(n, geoms, npl.data(), nob.data(), pars);
+    LAUE_REQUIRE(need > 0, LAUE_EINVAL, "invalid index parameters");
+    if ((rc = check_ws(ws, ws_bytes, need))) return rc;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    Carver cv(ws);
+    char *shared = nullptr;
+    size_t shared_bytes = 0;
+    std::vector<IndexWs> keep;
+    carve_batched(cv, n, geoms, npl.data(), nob.data(), pars, &shared, &shared_bytes, &keep);
+
+    // stages 1-5a sample by sample (each fills the GPU on its own), the
+    // sample's model spots and potentials in its own storage
+    std::vector<laue_index_stats> st(n, laue_index_stats{});
+    std::vector<EmJob> jobs(n);
+    std::vector<std::chrono::steady_clock::time_point> t_start(n);
+    double ms_fronts = 0.0;
+    for (int k = 0; k < n; ++k) {
+        t_start[k] = std::chrono::steady_clock::now();
+        Carver sc(shared);
+        IndexWs w;
+        carve_index(sc, w, geoms + k, npl[k], nob[k], pars + k);
+        const IndexWs &pk = keep[k];
+        w.mplane = pk.mplane;
+        w.mgrain = pk.mgrain;
+        w.mblock = pk.mblock;
+        w.s1 = pk.s1;
+        w.s2 = pk.s2;
+        w.vn = pk.vn;
+        w.v1 = pk.v1;
+        w.v2 = pk.v2;
+        w.lam = pk.lam;
+        w.flags = pk.flags;
+        w.f = pk.f;
+        w.g = pk.g;
+        if ((rc = index_front(geoms + k, planes + k, obs + k, pars + k, outs + k, w, st[k], jobs[k], s))) return rc;
+        ms_fronts += ms_since(t_start[k]);
+    }
+
+    // the EM of every sample with prototypes: one batch when the samples'
+    // schedules allow it (laue_em_batched gives each the result of laue_em),
+    // else one after another
+    std::vector<int> live;
+    std::vector<EmJob *> lj;
+    for (int k = 0; k < n; ++k)
+        if (jobs[k].protos.n > 0) {
+            live.push_back(k);
+            lj.push_back(&jobs[k]);
+        }
+    int worst = LAUE_OK;
+    const auto t0 = std::chrono::steady_clock::now();
+    if (!live.empty() && live.size() > 1 && batchable(lj)) {
+        const int m = static_cast<int>(live.size());
+        std::vector<laue_geometry> g(m);
+        std::vector<laue_planes> pl(m);
+        std::vector<laue_obs_spots> ob(m);
+        std::vector<laue_model_spots> md(m);
+        std::vector<laue_em_params> ep(m);
+        std::vector<laue_grains> gr(m);
+        std::vector<laue_potentials> pt(m);
+        std::vector<laue_assignments> as(m);
+        std::vector<laue_em_stats> es(m);
+        bool any_assign = false;
+        for (int i = 0; i < m; ++i) {
+            const int k = live[i];
+            g[i] = geoms[k];
+            pl[i] = planes[k];
+            ob[i] = obs[k];
+            md[i] = jobs[k].model;
+            ep[i] = jobs[k].em;
+            gr[i] = jobs[k].protos;
+            pt[i] = jobs[k].pot;
+            as[i] = jobs[k].with_assign ? jobs[k].asg : laue_assignments{};
+            any_assign = any_assign || jobs[k].with_assign;
+        }
+        rc = laue_em_batched(m, g.data(), pl.data(), ob.data(), md.data(), ep.data(), gr.data(), pt.data(),
+                             any_assign ? as.data() : nullptr, es.data(), shared, shared_bytes, stream);
+        if (rc < 0) return rc;
+        worst = rc;
+        for (int i = 0; i < m; ++i) st[live[i]].em = es[i];
+        log_line("index batch: EM of %d samples in one batch, %.1f ms", m, ms_since(t0));
+    } else {
+        for (int k : live) {
+            laue_em_stats es{};
+            rc = laue_em(geoms + k, planes + k, obs + k, &jobs[k].model, &jobs[k].em, &jobs[k].protos, &jobs[k].pot,
+                         jobs[k].with_assign ? &jobs[k].asg : nullptr, &es, shared, shared_bytes, stream);
+            if (rc < 0) return rc;
+            worst = std::max(worst, rc);
+            st[k].em = es;
+        }
+        log_line("index batch: EM of %d samples one after another, %.1f ms", static_cast<int>(live.size()),
+                 ms_since(t0));
+    }
+    const double ms_em = ms_since(t0);
+    for (int k = 0; k < n; ++k) {
+        if (jobs[k].protos.n > 0) st[k].ms_em += ms_em;
+        st[k].ms_total = ms_fronts + ms_em;
+        if (stats) stats[k] = st[k];
+    }
+    return worst;
 }
