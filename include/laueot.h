@@ -609,6 +609,13 @@ typedef struct laue_score_params {
      * Alg. SingleLaueOT's cooling, iteration k at eps_start eps_cool^k
      * (k = 0 .. k_refine - 1, FP64 products in order; eps_end not read) */
     double eps_cool;
+    /* refinement passes: 0 skips only the pairs whose plan term is 0 in FP32
+     * (the result is that of evaluating every pair); d > 0 also skips pairs
+     * whose term exp(-c / eps) is below 2^-d times the outlier bin's
+     * exp(-c_out / eps), i.e. below 2^-d of the row's softmax normaliser: each
+     * such row weight is < 2^-d, and the row normalisers change by less than
+     * 64 x 2^-d relative (the binding's default: d = 40) */
+    double drop_log2;
 } laue_score_params;
 
 /* Scoring outputs (device).  n_model, n_unmatched, keep: [n_cand] (may be

@@ -110,7 +110,8 @@ class laue_score_params(C.Structure):
     _fields_ = [("sigma_mm", C.c_double), ("distance", C.c_double), ("c_out", C.c_double),
                 ("f_out", C.c_double), ("eps_start", C.c_double), ("eps_end", C.c_double),
                 ("k_refine", C.c_int32), ("k_gn", C.c_int32), ("mu_rel", C.c_double),
-                ("chunk", C.c_int32), ("max_spots_per_cand", C.c_int32), ("eps_cool", C.c_double)]
+                ("chunk", C.c_int32), ("max_spots_per_cand", C.c_int32), ("eps_cool", C.c_double),
+                ("drop_log2", C.c_double)]
 
 
 class laue_score_out(C.Structure):

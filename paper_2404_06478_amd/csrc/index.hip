@@ -242,7 +242,8 @@ constexpr int kCells = kCellG * kCellG;
 constexpr int kMaxRuns = 256;
 // Exponent (log2 units) beyond which an FP32 plan term exp2(-K c') is 0 for
 // any rounding of c' (2^-150 already rounds to 0; the margin covers the cost's
-// own rounding, a few ulps relative).
+// own rounding, a few ulps relative).  The passes skip pairs beyond a
+// threshold T <= kZeroExp2 (laue_score_params.drop_log2).
 constexpr float kZeroExp2 = 160.0f;
 
 struct SlotArgs {
@@ -350,19 +351,15 @@ __device__ __forceinline__ void fused_entry_stats(float *a, bool &any, float p1,
 // over a lane's kSup rows are unrolled with wave-uniform guards, so the rows
 // stay in named registers.
 template <bool SAME>
-__global__ __launch_bounds__(64) void k_single_acc(SlotArgs A, float K, float bin_e, double D2,
-                                                   double *__restrict__ hg_out) {
+__global__ __launch_bounds__(64) void k_single_acc(SlotArgs A, float K, float bin_e, float T_skip,
+                                                   double *__restrict__ st_out) {
     const int item = blockIdx.x;
     const int b = item / A.C, c = item - b * A.C;
     const int lane = threadIdx.x;
     const int64_t o0 = A.offs[static_cast<int64_t>(b) * A.C + c];
     const int nc = static_cast<int>(A.offs[static_cast<int64_t>(b) * A.C + c + 1] - o0);
-    double *out = hg_out + (static_cast<int64_t>(c) * A.nb + b) * kHg;
     const int64_t r0 = A.ooff[b], rend = A.ooff[b + 1];
-    if (nc == 0) {
-        if (lane < kHg) out[lane] = 0.0;
-        return;
-    }
+    if (nc == 0) return;
     const LaneCol lE = lane_col(A.colsE, o0, nc, lane);
     const LaneCol lC = SAME ? lE : lane_col(A.colsC, o0, nc, lane);
     // per-column constants at the current geometry: |v|, v / |v|
@@ -384,13 +381,14 @@ __global__ __launch_bounds__(64) void k_single_acc(SlotArgs A, float K, float bi
             cst[256 + lane] = make_float4(lC.vv, lC.vv2, lC.vn, 0.0f);
         }
     }
-    // Rows that can carry weight.  Every plan term of model spot j is 0 in
-    // FP32 (so adds nothing to a normaliser or a statistic) for detected spots
+    // Rows that can carry weight.  Every plan term of model spot j has
+    // exponent K c' >= T_skip (so is 0 in FP32 for T_skip = kZeroExp2, or
+    // below 2^-drop_log2 of the outlier bin's term) for detected spots
     // farther than R_j from s_j on the detector: with delta = p - s in the
     // detector plane and v_n the normal part of v, |v x delta| >= |delta| v_n
     // and |v|^2 |d|^2 + (v.d)|v||d| <= 2 |v|^2 (|v| + |delta|)^2, so
     // c' >= t^2 v_n^2 / (2 |v|^2) with t = |delta| / (|v| + |delta|), and
-    // K c' >= kZeroExp2 once t >= t0 = sqrt(2 kZeroExp2 |v|^2 / (K v_n^2)),
+    // K c' >= T_skip once t >= t0 = sqrt(2 T_skip |v|^2 / (K v_n^2)),
     // i.e. |delta| >= R_j = t0 |v| / (1 - t0).  The cells of the block's grid
     // within R_j of some s_j are marked; their spots, in cell order, are the
     // rows of the passes below (all of the block's when the marked cells
@@ -402,7 +400,7 @@ __global__ __launch_bounds__(64) void k_single_acc(SlotArgs A, float K, float bi
         float R2 = INFINITY;
         if (lane < nc) {
             const float vn2 = lE.vn * lE.vn;
-            const float t2 = 2.0f * (kZeroExp2 / K) * lE.vv / vn2;
+            const float t2 = 2.0f * (T_skip / K) * lE.vv / vn2;
             if (vn2 >= 1e-4f * lE.vv && t2 < 0.81f) {
                 const float t0 = sqrtf(t2);
                 const float R = fmaf(t0 * sqrtf(lE.vv) / (1.0f - t0), 1.001f, 1e-3f);
@@ -554,35 +552,38 @@ __global__ __launch_bounds__(64) void k_single_acc(SlotArgs A, float K, float bi
         }
     }
     __syncthreads();
-    double hg[kHg];
+    // the model spots' statistics; k_single_solve forms their normal equations
     if (lane < nc) {
-        double s64[kStat];
+        double *dst = st_out + (o0 + lane) * kStat;
 #pragma unroll
-        for (int q = 0; q < kStat; ++q) s64[q] = acc[kStat * lane + q];
-        const int64_t col = o0 + lane;
-        column_normal_equations(*A.geom, A.W, A.n_planes, A.grains, A.C, A.mplane[col], A.mgrain[col],
-                                A.mblock[col], s64, rn_l, r1_l, r2_l, D2, hg);
-    } else {
-#pragma unroll
-        for (int q = 0; q < kHg; ++q) hg[q] = 0.0;
-    }
-    for (int q = 0; q < kHg; ++q) {
-        const double v = wave_sum(hg[q]);
-        if (lane == 0) out[q] = v;
+        for (int q = 0; q < kStat; ++q) dst[q] = acc[kStat * lane + q];
     }
 }
 
-// One wave per candidate: sum its per-block contributions (fixed order),
-// then the FP64 Gauss-Newton step.
-__global__ __launch_bounds__(64) void k_single_solve(const double *__restrict__ hg, int nb, int C,
+// One wave per candidate: the FP64 normal equations of each of its model
+// spots from the statistics of k_single_acc (lane l takes the spots of blocks
+// l, l + 64, ...; the current columns colsC give the spot's unit ray), summed,
+// then the Gauss-Newton step.  A candidate's spots carry its own grain index,
+// so the grain read here is written by this wave only.
+__global__ __launch_bounds__(64) void k_single_solve(SlotArgs A, const double *__restrict__ st, double D2,
                                                      double mu_rel, double *q, double *x,
                                                      GrainF *__restrict__ gf) {
     const int c = blockIdx.x;
-    if (c >= C) return;
+    if (c >= A.C) return;
     double acc[kHg];
     for (int k = 0; k < kHg; ++k) acc[k] = 0.0;
-    for (int b = threadIdx.x; b < nb; b += 64)
-        for (int k = 0; k < kHg; ++k) acc[k] += hg[(static_cast<int64_t>(c) * nb + b) * kHg + k];
+    for (int b = threadIdx.x; b < A.nb; b += 64) {
+        const int64_t o1 = A.offs[static_cast<int64_t>(b) * A.C + c + 1];
+        for (int64_t o = A.offs[static_cast<int64_t>(b) * A.C + c]; o < o1; ++o) {
+            const Col8 cc = A.colsC[o];
+            const float ivl = __builtin_amdgcn_rsqf(cc.vv);
+            double s64[kStat], hg[kHg];
+            for (int k = 0; k < kStat; ++k) s64[k] = st[o * kStat + k];
+            column_normal_equations(*A.geom, A.W, A.n_planes, A.grains, A.C, A.mplane[o], A.mgrain[o],
+                                    A.mblock[o], s64, cc.vn * ivl, cc.v1 * ivl, cc.v2 * ivl, D2, hg);
+            for (int k = 0; k < kHg; ++k) acc[k] += hg[k];
+        }
+    }
     for (int k = 0; k < kHg; ++k) acc[k] = wave_sum(acc[k]);
     if (threadIdx.x != 0) return;
     gn_solve_apply(acc, mu_rel, q + 4 * c, x + 3 * c, gf + c, nullptr);
@@ -1278,7 +1279,7 @@ struct ScoreWs {
     EnumWs e;
     int *plane, *grain, *block;
     Col8 *colsE, *colsC;
-    double *hg;
+    double *st;       // per model spot: the kStat statistics of the last pass
     int *unm, *lcnt;
     uint8_t *keep;
     int64_t *loff;
@@ -1298,7 +1299,7 @@ size_t carve_score(Carver &cv, ScoreWs &w, const laue_geometry *g, int chunk, in
     w.block = cv.take<int>(S);
     w.colsE = cv.take<Col8>(S);
     w.colsC = cv.take<Col8>(S);
-    w.hg = cv.take<double>(static_cast<size_t>(chunk) * nb * kHg);
+    w.st = cv.take<double>(static_cast<size_t>(S) * kStat);
     w.unm = cv.take<int>(static_cast<size_t>(chunk) * nb);
     w.lcnt = cv.take<int>(static_cast<size_t>(chunk) * nb + 1);
     w.loff = cv.take<int64_t>(static_cast<size_t>(chunk) * nb + 1);
@@ -1309,11 +1310,11 @@ size_t carve_score(Carver &cv, ScoreWs &w, const laue_geometry *g, int chunk, in
     return cv.size();
 }
 
-int launch_acc(const SlotArgs &A, float K, float bin_e, double D2, double *hg, hipStream_t s) {
+int launch_acc(const SlotArgs &A, float K, float bin_e, float T_skip, double *st, hipStream_t s) {
     if (A.colsC == A.colsE)
-        k_single_acc<true><<<static_cast<unsigned>(A.nb) * A.C, 64, 0, s>>>(A, K, bin_e, D2, hg);
+        k_single_acc<true><<<static_cast<unsigned>(A.nb) * A.C, 64, 0, s>>>(A, K, bin_e, T_skip, st);
     else
-        k_single_acc<false><<<static_cast<unsigned>(A.nb) * A.C, 64, 0, s>>>(A, K, bin_e, D2, hg);
+        k_single_acc<false><<<static_cast<unsigned>(A.nb) * A.C, 64, 0, s>>>(A, K, bin_e, T_skip, st);
     LAUE_CHECK_HIP(hipGetLastError());
     return LAUE_OK;
 }
@@ -1356,7 +1357,8 @@ extern "C" int laue_score_candidates(const laue_geometry *geom, const laue_plane
                      std::isfinite(par->f_out) && std::isfinite(par->mu_rel) && par->mu_rel >= 0 &&
                      std::isfinite(par->eps_start) && std::isfinite(par->eps_end) &&
                      par->eps_start > 0 && par->eps_end > 0 && std::isfinite(par->eps_cool) &&
-                     par->eps_cool >= 0 && par->eps_cool <= 1,
+                     par->eps_cool >= 0 && par->eps_cool <= 1 && std::isfinite(par->drop_log2) &&
+                     par->drop_log2 >= 0,
                  LAUE_EINVAL, "bad scoring parameters");
     LAUE_REQUIRE(out->lbar_off && (out->lbar_cap == 0 || (out->lbar_row && out->lbar_val)), LAUE_EINVAL,
                  "SPOT output arrays are NULL");
@@ -1447,6 +1449,12 @@ extern "C" int laue_score_candidates(const laue_geometry *geom, const laue_plane
             eps_cooled *= par->eps_cool;
             const float K = static_cast<float>(2.0 * D2 * l2e / eps);
             const float bin_e = static_cast<float>(std::exp(-par->c_out / eps));
+            // skip threshold: terms below 2^-drop_log2 of the bin's (whose
+            // exponent is c_out / (eps ln 2)), at most the FP32-zero exponent
+            const float T_skip = par->drop_log2 > 0.0
+                                     ? static_cast<float>(std::min<double>(kZeroExp2, par->drop_log2 +
+                                                                                       par->c_out * l2e / eps))
+                                     : kZeroExp2;
             if ((rc = launch_eval(w.e.geom, planes, w.e.grains, C, w.plane, w.grain, w.block, total,
                                   nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, w.colsE, s)))
                 return rc;
@@ -1459,8 +1467,8 @@ extern "C" int laue_score_candidates(const laue_geometry *geom, const laue_plane
                         return rc;
                     A.colsC = w.colsC;
                 }
-                if ((rc = launch_acc(A, K, bin_e, D2, w.hg, s))) return rc;
-                k_single_solve<<<C, 64, 0, s>>>(w.hg, nb, C, par->mu_rel, sub.q, sub.x, w.e.grains);
+                if ((rc = launch_acc(A, K, bin_e, T_skip, w.st, s))) return rc;
+                k_single_solve<<<C, 64, 0, s>>>(A, w.st, D2, par->mu_rel, sub.q, sub.x, w.e.grains);
                 LAUE_CHECK_HIP(hipGetLastError());
             }
         }

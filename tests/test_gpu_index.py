@@ -48,7 +48,11 @@ def test_candidates_match_oracle(gpu_lib):
     assert np.array_equal(gc["spot_a"].cpu().numpy()[gi], ref["a"][oi])
 
 
-def test_refine_score_match_oracle(gpu_lib):
+@pytest.mark.parametrize("drop_log2", [0.0, 40.0])
+def test_refine_score_match_oracle(gpu_lib, drop_log2):
+    """Refinement and scoring against the oracle (which keeps every pair), with
+    the passes skipping only FP32-zero terms (0) and terms below 2^-40 of the
+    outlier bin's (the default)."""
     laue = gpu_lib
     p, pl, g, q, x, sim, p12, geom, planes, obs = _setup(laue)
     ref = candidates.generate(pl, g, p12, sim["offsets"], 200, 5)
@@ -66,7 +70,7 @@ def test_refine_score_match_oracle(gpu_lib):
         slot_pairs.append(int(np.sum(np.diff(mod["offsets"]) * n_obs_blk)))
         outs.append((qq, xx) + single.score(pl, g, p.distance, p12, sim["offsets"], mod, qq, xx, p.sigma_mm, c_out))
     grains = laue.Grains(cq, cx)
-    par = laue.score_params(p.sigma_mm, p.distance, c_out, k_refine=6, k_gn=2, chunk=5)
+    par = laue.score_params(p.sigma_mm, p.distance, c_out, k_refine=6, k_gn=2, chunk=5, drop_log2=drop_log2)
     res = laue.laue_score_candidates(geom, planes, obs, grains, par)
     qg, xg = grains.numpy()
     for k, (qq, xx, un, nm, rows, vals) in enumerate(outs):
