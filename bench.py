@@ -441,12 +441,14 @@ def bench_index(laue, workload, n_pairs, learned_pairs, log, sobol_points=0, rec
                      "em_zeta": st["em"]["zeta"], "likelihood": st["em"]["objective"]["sem_objective"],
                      "prototypes": st["n_prototypes"], "recall": r / len(q), "time_s": wall,
                      "score_pairs": st["score_pairs"], "score_pairs_evaluated": st["score_pairs_evaluated"],
+                     "score_pairs_refine": st["score_pairs_refine"],
                      "score_pairs_per_s": st["score_pairs"] / max(st["ms_score"] * 1e-3, 1e-12),
                      "stage_ms": {k: st[k] for k in ("ms_candidates", "ms_proposal", "ms_score", "ms_greedy",
                                                      "ms_em")}}
         log(f"index: {mode}: {pairs} {'points' if mode == 'sobol' else 'pairs'}, {st['n_scored']} scored, "
-            f"recall {r}/{len(q)}, {wall:.2f} s (scoring evaluated "
-            f"{st['score_pairs_evaluated'] / max(st['score_pairs'], 1):.3f} of its pairs)")
+            f"recall {r}/{len(q)}, {wall:.2f} s (the refinement evaluated "
+            f"{(st['score_pairs_evaluated'] - st['score_pairs'] + st['score_pairs_refine']) / max(st['score_pairs_refine'], 1):.3f}"
+            f" of its pairs)")
     return out
 
 

@@ -634,6 +634,7 @@ typedef struct laue_score_out {
                                * passes: the work the method defines */
     int64_t pairs_evaluated;  /* (out) of those, the pairs the refinement passes
                                * evaluate (see below) plus the scoring passes' */
+    int64_t pairs_refine;     /* (out) the refinement passes' share of pairs_streamed */
 } laue_score_out;
 
 /* The refinement passes read each block's detected spots through a cell
@@ -861,6 +862,7 @@ typedef struct laue_index_stats {
     laue_em_stats em;
     int64_t score_pairs;            /* same-block pairs of the scoring stage (laue_score_out.pairs_streamed) */
     int64_t score_pairs_evaluated;  /* of those, the pairs evaluated (laue_score_out.pairs_evaluated) */
+    int64_t score_pairs_refine;     /* the refinement passes' share (laue_score_out.pairs_refine) */
 } laue_index_stats;
 
 /* Output grains (device, capacity >= k_max; n_grains = k* on return) and the

@@ -587,6 +587,7 @@ def laue_score_candidates(geom, planes, obs, cand, par, lbar_cap=None):
     res["lbar_n"] = so.lbar_n
     res["pairs_streamed"] = so.pairs_streamed
     res["pairs_evaluated"] = so.pairs_evaluated
+    res["pairs_refine"] = so.pairs_refine
     return res
 
 

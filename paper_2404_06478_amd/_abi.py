@@ -117,7 +117,8 @@ class laue_score_params(C.Structure):
 class laue_score_out(C.Structure):
     _fields_ = [("n_model", vp), ("n_unmatched", vp), ("keep", vp), ("lbar_off", vp),
                 ("lbar_row", vp), ("lbar_val", vp), ("lbar_cap", C.c_int64), ("lbar_n", C.c_int64),
-                ("pairs_streamed", C.c_int64), ("pairs_evaluated", C.c_int64)]
+                ("pairs_streamed", C.c_int64), ("pairs_evaluated", C.c_int64),
+                ("pairs_refine", C.c_int64)]
 
 
 class laue_mlp(C.Structure):
@@ -157,7 +158,7 @@ class laue_index_stats(C.Structure):
                 ("n_model_spots", C.c_int64), ("ms_candidates", C.c_double), ("ms_proposal", C.c_double),
                 ("ms_score", C.c_double), ("ms_greedy", C.c_double), ("ms_em", C.c_double),
                 ("ms_total", C.c_double), ("em", laue_em_stats), ("score_pairs", C.c_int64),
-                ("score_pairs_evaluated", C.c_int64)]
+                ("score_pairs_evaluated", C.c_int64), ("score_pairs_refine", C.c_int64)]
 
 
 class laue_index_out(C.Structure):

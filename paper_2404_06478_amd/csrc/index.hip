@@ -1514,6 +1514,7 @@ extern "C" int laue_score_candidates(const laue_geometry *geom, const laue_plane
     LAUE_CHECK_HIP(hipStreamSynchronize(s));
     out->pairs_streamed = (static_cast<int64_t>(par->k_refine) * par->k_gn + 1) * hp[0] + hp[1];
     out->pairs_evaluated = hp[2] + hp[0] + hp[1];
+    out->pairs_refine = static_cast<int64_t>(par->k_refine) * par->k_gn * hp[0];
     return LAUE_OK;
 }
 

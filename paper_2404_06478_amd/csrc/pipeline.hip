@@ -274,6 +274,7 @@ int index_front(const laue_geometry *geom, const laue_planes *planes, const laue
     st.lbar_entries = so.lbar_n;
     st.score_pairs = so.pairs_streamed;
     st.score_pairs_evaluated = so.pairs_evaluated;
+    st.score_pairs_refine = so.pairs_refine;
     if (log_enabled()) LAUE_CHECK_HIP(hipStreamSynchronize(s));
     st.ms_score = ms_since(t0);
     log_line("index: scored %lld candidates, %lld SPOT entries, in %.1f ms", static_cast<long long>(n_sc),
