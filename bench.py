@@ -376,9 +376,10 @@ ZETA_TOL_PER_ROOT_SPOT = 1e-3
 def bench_index(laue, workload, n_pairs, learned_pairs, log, sobol_points=0, recipe="stages", max_candidates=None,
                 plain_max=None, train_examples=1_000_000):
     """Time to index from device-resident spots (laue_index): plain exhaustive
-    scoring of the candidates of n_pairs spot pairs, against the learned
-    proposal scoring the top 5% of the candidates of learned_pairs pairs, with
-    a network trained here on 10^6 simulated examples, and (sobol_points > 0)
+    scoring of the candidates of n_pairs spot pairs, against (learned_pairs >
+    0) the learned proposal scoring the top 5% of the candidates of
+    learned_pairs pairs, with a network trained here on 10^6 simulated
+    examples, and (sobol_points > 0)
     the paper's Sobol-grid starts over the cubic fundamental zone and the
     sample box.  max_candidates caps the candidates of both forms (the first
     ones); plain_max caps the plain form's alone."""
@@ -389,27 +390,31 @@ def bench_index(laue, workload, n_pairs, learned_pairs, log, sobol_points=0, rec
     geom = laue.geometry_from_preset(p)
     planes = laue.laue_planes_cubic(p.a, p.centering, p.n_max)
     radius = 4.0 * p.sigma_mm
-    truths = [ig.random_grains(p, seed=p.seed + 1000 + k) for k in range(10)]
-    seeds = [p.seed + 1000 + k for k in range(10)]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    feat, lab = learned.training_set(geom, planes, truths, p.sigma_mm, p.distance, p.outlier_frac, seeds,
-                                     train_examples, support_radius=radius)
-    torch.cuda.synchronize()
-    t_data = time.perf_counter() - t0
-    net = laue.Mlp(seed=3)
-    t0 = time.perf_counter()
-    losses = learned.train(net, feat, lab, epochs=10, lr=2e-3)
-    torch.cuda.synchronize()
-    t_train = time.perf_counter() - t0
-    log(f"index: training set {feat.shape[0]} examples in {t_data:.1f} s, 10 epochs in {t_train:.1f} s")
+    net, training = None, None
+    if learned_pairs:
+        truths = [ig.random_grains(p, seed=p.seed + 1000 + k) for k in range(10)]
+        seeds = [p.seed + 1000 + k for k in range(10)]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        feat, lab = learned.training_set(geom, planes, truths, p.sigma_mm, p.distance, p.outlier_frac, seeds,
+                                         train_examples, support_radius=radius)
+        torch.cuda.synchronize()
+        t_data = time.perf_counter() - t0
+        net = laue.Mlp(seed=3)
+        t0 = time.perf_counter()
+        losses = learned.train(net, feat, lab, epochs=10, lr=2e-3)
+        torch.cuda.synchronize()
+        t_train = time.perf_counter() - t0
+        log(f"index: training set {feat.shape[0]} examples in {t_data:.1f} s, 10 epochs in {t_train:.1f} s")
+        training = {"examples": int(feat.shape[0]), "positives": int(lab.sum().item()), "data_s": t_data,
+                    "train_s": t_train, "epochs": 10, "final_loss": losses[-1]}
     q, x = ig.random_grains(p)
     obs = laue.laue_simulate(geom, planes, laue.Grains(q, x), p.sigma_mm, p.distance, p.outlier_frac, p.seed)
     out = {"workload": workload, "grains": p.n_grains, "detected_spots": obs.n, "recipe": recipe,
-           "training": {"examples": int(feat.shape[0]), "positives": int(lab.sum().item()),
-                        "data_s": t_data, "train_s": t_train, "epochs": 10, "final_loss": losses[-1]}}
+           "training": training}
     score, em = recipe_params(laue, p, recipe, obs.n)
-    modes = [("plain", n_pairs), ("learned", learned_pairs)] + ([("sobol", sobol_points)] if sobol_points else [])
+    modes = [("plain", n_pairs)] + ([("learned", learned_pairs)] if learned_pairs else []) + \
+        ([("sobol", sobol_points)] if sobol_points else [])
     for mode, pairs in modes:
         mc = max_candidates if mode != "plain" or plain_max is None else plain_max
         if mode == "sobol":
@@ -736,12 +741,15 @@ def bench_forward(laue, n_grains, log):
 # the 1000-grain target workload as its configuration states it (2^20
 # spot-pair candidates: the network ranks them and the top 5% are scored,
 # against plain scoring of all 2^20), on the stage schedule; the same sample
-# at the paper's fiducial noise with the paper's annealing recipe; the
-# 2000-grain stress workload (the network ranks 2^20 candidates and scores the
-# top 5%; plain scoring of the first 2^16).
+# at the paper's fiducial noise with the paper's annealing recipe, the same
+# 2^20 candidates both ways, and plain scoring of 2048 pairs' candidates (the
+# recall the learned form reaches); the 2000-grain stress workload (the
+# network ranks 2^20 candidates and scores the top 5%; plain scoring of the
+# first 2^16).
 DEFAULT_INDEX_LINES = ("medium,pairs=8192,sobol=200000;"
                        "learned,pairs=32768,lpairs=32768,cand=1048576;"
-                       "learned_fiducial,pairs=2048,lpairs=16384,recipe=paper;"
+                       "learned_fiducial,pairs=24576,lpairs=24576,cand=1048576,recipe=paper;"
+                       "learned_fiducial,pairs=2048,lpairs=0,recipe=paper,name=learned_fiducial.paper_2048;"
                        "stress,pairs=32768,lpairs=32768,cand=1048576,pcand=65536")
 
 
@@ -787,7 +795,8 @@ def main():
     ap.add_argument("--batch-samples", type=int, default=64)
     ap.add_argument("--index-workloads", default=DEFAULT_INDEX_LINES,
                     help="';'-separated index lines, each 'workload' followed by ',key=value' options: pairs "
-                         "(plain form's spot pairs), lpairs (learned form's, default 8 x pairs), sobol (Sobol points, "
+                         "(plain form's spot pairs), lpairs (learned form's, default 8 x pairs; 0: no learned form), "
+                         "sobol (Sobol points, "
                          "0: none), recipe (stages or paper), cand (candidate cap of both forms), pcand (plain "
                          "form's cap), examples (training examples)")
     ap.add_argument("--index-limits", default="",

@@ -706,6 +706,16 @@ int laue_candidate_labels(const laue_candidates *cand, const int32_t *spot_grain
                           const laue_grains *truth, double max_deg, float *label, float *mis_deg,
                           void *stream);
 
+/* Training labels by the nearest true grain: label[c] = 1 when the candidate
+ * orientation is within max_deg of some truth->q[g] up to the 24 proper cubic
+ * rotations, whichever spots its pair came from (single-grain refinement from
+ * such a start reaches the grain; farther starts seldom do).  mis_deg and
+ * nearest (may be NULL) receive the smallest misorientation (degrees) and its
+ * grain (lowest index on ties; -1 without true grains).  FP64.  Device
+ * outputs [cand->n]; only cand->q is read; asynchronous. */
+int laue_candidate_labels_nearest(const laue_candidates *cand, const laue_grains *truth, double max_deg,
+                                  float *label, float *mis_deg, int32_t *nearest, void *stream);
+
 /* Same-grain spot pairs for training the proposal on simulated spots.  Pair k
  * draws Philox4x32-10 counter (k, 0, 0, 7) under the key (seed low, seed
  * high): a = x0 mod n_obs; if spot a is an outlier (spot_grain -1) or no
@@ -827,8 +837,11 @@ int laue_sobol_starts(const laue_sobol_params *par, int64_t n_points, double *q,
  *      (laue_mlp_forward), the ceil(top_frac * n) best (laue_select_top);
  *   3. single-grain refinement and scoring (laue_score_candidates, x = 0 start);
  *   4. greedy SPOT (laue_spot_greedy, floor -c_out / (2 sigma^2), at most k_max
- *      picks) and k* = argmax_k (Delta_k - Delta_{k+1}) (Delta beyond the picks
- *      is 0): the first k* picks are the prototypes;
+ *      picks) and k* where f, the running sum of the increments Delta, bends
+ *      most (Eq. spot_ngrains' second difference over h = 8 picks): the
+ *      argmax over k >= 1 of the mean Delta of the m = min(k, 8) picks up to k
+ *      minus the mean of the 8 picks after k (Delta beyond the picks is 0);
+ *      the first k* picks are the prototypes;
  *   5. the harmonic-merged model spots of the prototypes, frozen (Sec. 4.2),
  *      and the EM of laue_em from zero potentials with
  *      T_b = max(ceil(t_b_frac |J|), |J| - |I|).

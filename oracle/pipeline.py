@@ -11,7 +11,8 @@ its stage, taken in the paper's order:
      (oracle/single.py); a candidate with model spots is kept when its
      unmatched count is below f_out times its model spots; dropped
      candidates get an empty SPOT column;
-  4. greedy SPOT with the outlier floor and k* = argmax (Delta_k - Delta_{k+1});
+  4. greedy SPOT with the outlier floor and k* at the largest drop of the
+     increment over 8 picks (single.n_prototypes);
   5. the harmonic-merged model spots of the first k* picks, frozen, and the EM
      of oracle/em.py with T_b = max(ceil(t_b_frac |J|), |J| - |I|).
 With starts = (q, x) (the Sobol grid of Sec. 6.1, oracle/sobol.py) those

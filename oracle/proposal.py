@@ -121,6 +121,21 @@ def labels(q, spot_a, spot_b, spot_grain, q_true, max_deg=2.0):
     return (mis <= max_deg).astype(np.float64), mis
 
 
+def labels_nearest(q, q_true, max_deg=1.0):
+    """Training labels by the nearest true grain: 1 when the candidate
+    orientation is within max_deg of some true grain (cubic symmetry), with the
+    smallest misorientation (deg) and that grain (lowest index on ties; -1 and
+    inf without true grains)."""
+    q = np.atleast_2d(np.asarray(q, dtype=np.float64))
+    qt = np.atleast_2d(np.asarray(q_true, dtype=np.float64))
+    if qt.shape[0] == 0 or qt.shape[1] == 0:
+        return np.zeros(len(q)), np.full(len(q), np.inf), -np.ones(len(q), dtype=np.int64)
+    mis = np.degrees(metrics.misorientation(q[:, None, :], qt[None, :, :]))
+    near = np.argmin(mis, axis=1)
+    m = mis[np.arange(len(q)), near]
+    return (m <= max_deg).astype(np.float64), m, near
+
+
 def select_top(score, frac):
     """Indices (ascending) of the ceil(frac * n) highest scores; ties by index."""
     score = np.asarray(score)

@@ -746,6 +746,20 @@ def laue_candidate_labels(cand, spot_grain, truth, max_deg=2.0):
     return lab[:n], mis[:n]
 
 
+def laue_candidate_labels_nearest(cand, truth, max_deg=1.0):
+    """(label, misorientation in degrees, nearest true grain) per candidate."""
+    import torch
+    n = int(cand["q"].shape[0])
+    dev = _dev()
+    lab = torch.zeros(max(n, 1), dtype=torch.float32, device=dev)
+    mis = torch.zeros(max(n, 1), dtype=torch.float32, device=dev)
+    near = torch.zeros(max(n, 1), dtype=torch.int32, device=dev)
+    _check(require_native().laue_candidate_labels_nearest(C.byref(_cand_struct(cand)), C.byref(truth.struct),
+                                                          float(max_deg), _ptr(lab), _ptr(mis), _ptr(near),
+                                                          _stream()))
+    return lab[:n], mis[:n], near[:n]
+
+
 def laue_select_top(score, k):
     """Ascending indices (int32 device) of the k largest scores, ties by index."""
     import torch

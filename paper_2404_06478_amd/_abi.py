@@ -223,6 +223,8 @@ SIGNATURES = {
                                          P(laue_support_params), vp, C.c_size_t, vp]),
     "laue_candidate_labels": (C.c_int, [P(laue_candidates), vp, C.c_int64, P(laue_grains), C.c_double, vp, vp,
                                         vp]),
+    "laue_candidate_labels_nearest": (C.c_int, [P(laue_candidates), P(laue_grains), C.c_double, vp, vp, vp,
+                                                vp]),
     "laue_pairs_same_grain": (C.c_int, [P(laue_geometry), P(laue_obs_spots), vp, C.c_int64, C.c_uint64, vp, vp,
                                         vp, C.c_size_t, vp]),
     "laue_pairs_same_grain_workspace_size": (C.c_size_t, [P(laue_geometry)]),

@@ -671,8 +671,12 @@ struct EnumWs {
     int *counts;
     int64_t *offs;      // exclusive scan of counts in (t, d, n) order, L + 1 entries
     int64_t *blk;       // per-block offsets (n_blocks + 1)
+    unsigned *kmask;    // kept-plane bits per (t, n) item and detector (w32 words each), or NULL
+    int w32;
+    bool mask_ready;    // set by enumerate_count when it wrote kmask for these grains
 };
-size_t carve_enum(Carver &cv, EnumWs &w, const laue_geometry *g, int n_grains);
+// n_planes sizes the kept-plane bits (the kernel's limit of 1024 when unknown)
+size_t carve_enum(Carver &cv, EnumWs &w, const laue_geometry *g, int n_grains, int n_planes = 1024);
 int enumerate_count(const laue_geometry *geom, const laue_planes *planes, const laue_grains *grains,
                     int merge, EnumWs &w, std::vector<int64_t> &host_blk, int64_t *total,
                     hipStream_t s);

@@ -45,9 +45,14 @@ __global__ __launch_bounds__(64) void k_enumerate(
     int pass, int *__restrict__ counts, const int64_t *__restrict__ offs, int *__restrict__ o_plane,
     int *__restrict__ o_grain, int *__restrict__ o_block, float *__restrict__ o_s1,
     float *__restrict__ o_s2, float *__restrict__ o_vn, float *__restrict__ o_v1,
-    float *__restrict__ o_v2, float *__restrict__ o_lam, uint8_t *__restrict__ o_flags) {
+    float *__restrict__ o_v2, float *__restrict__ o_lam, uint8_t *__restrict__ o_flags,
+    unsigned *__restrict__ kmask, int W32) {
     const GeomF &G = *Gp;
     const int lane = threadIdx.x;
+    // kmask (may be NULL): per item (t, n) and detector, W32 words of kept-plane
+    // bits (bit m of word m / 32).  The count pass writes them; a write pass
+    // given them evaluates only the kept planes.
+    __shared__ unsigned kbits[2 * (kMaxPlanes / 32)];
     // visibility per (detector, plane): dynamic LDS of n_det x M bytes
     extern __shared__ uint8_t vis_lds[];
     __shared__ short inb[kMaxPlanes];
@@ -62,6 +67,41 @@ __global__ __launch_bounds__(64) void k_enumerate(
         const int t = static_cast<int>(item / N);
         const GrainF gr = grains[n];
         const float c = G.cs[t][0], s = G.cs[t][1];
+        if (pass && kmask) {
+            // write pass from the count pass's bits: only the kept planes
+            for (int d = 0; d < D; ++d) {
+                const int slot = (t * D + d) * N + n;
+                const int64_t base = offs[slot];
+                const unsigned *mk = kmask + (item * D + d) * W32;
+                int running = 0;
+                for (int m0 = 0; m0 < M; m0 += 64) {
+                    const int m = m0 + lane;
+                    const bool keep = m < M && ((mk[m >> 5] >> (m & 31)) & 1u);
+                    const unsigned long long bal = __ballot(keep);
+                    if (keep) {
+                        const int64_t pos = base + running + __popcll(bal & ((1ull << lane) - 1ull));
+                        const SpotGeo o = spot_geometry(G, G.det[d], gr.R, gr.x, c, s, W[3 * m], W[3 * m + 1],
+                                                        W[3 * m + 2], Dsp[m]);
+                        o_plane[pos] = m;
+                        o_grain[pos] = n;
+                        o_block[pos] = t * D + d;
+                        if (o_s1) {
+                            o_s1[pos] = o.s1;
+                            o_s2[pos] = o.s2;
+                            o_vn[pos] = o.vn;
+                            o_v1[pos] = o.v1;
+                            o_v2[pos] = o.v2;
+                        }
+                        if (o_lam) o_lam[pos] = o.lam;
+                        if (o_flags) o_flags[pos] = o.flags;
+                    }
+                    running += __popcll(bal);
+                }
+            }
+            continue;
+        }
+        if (!pass && kmask)
+            for (int w = lane; w < D * W32; w += 64) kbits[w] = 0u;
         int K = 0;
         for (int m0 = 0; m0 < M; m0 += 64) {
             const int m = m0 + lane;
@@ -103,6 +143,7 @@ __global__ __launch_bounds__(64) void k_enumerate(
                     }
                 }
                 unsigned long long bal = __ballot(keep);
+                if (!pass && kmask && keep) atomicOr(&kbits[d * W32 + (m >> 5)], 1u << (m & 31));
                 if (pass && keep) {
                     unsigned long long lower = bal & ((1ull << lane) - 1ull);
                     int64_t pos = base + running + __popcll(lower);
@@ -125,7 +166,11 @@ __global__ __launch_bounds__(64) void k_enumerate(
             }
             if (!pass && lane == 0) counts[slot] = running;
         }
-        __syncthreads();        // vis and inb are reused by the next item
+        if (!pass && kmask) {
+            __syncthreads();
+            for (int w = lane; w < D * W32; w += 64) kmask[item * D * W32 + w] = kbits[w];
+        }
+        __syncthreads();        // vis, inb and kbits are reused by the next item
     }
 }
 
@@ -345,13 +390,18 @@ int validate_grains(const laue_grains *g) {
     return LAUE_OK;
 }
 
-size_t carve_enum(Carver &cv, EnumWs &w, const laue_geometry *g, int n_grains) {
+size_t carve_enum(Carver &cv, EnumWs &w, const laue_geometry *g, int n_grains, int n_planes) {
     int64_t L = static_cast<int64_t>(g->n_rot) * g->n_det * std::max(n_grains, 1);
     w.geom = cv.take<GeomF>(1);
     w.grains = cv.take<GrainF>(std::max(n_grains, 1));
     w.counts = cv.take<int>(L);
     w.offs = cv.take<int64_t>(L + 1);
     w.blk = cv.take<int64_t>(g->n_rot * g->n_det + 1);
+    // kept-plane bits of the count pass (not when a plane list is larger
+    // than the kernel's limit or the geometry has more than two detectors)
+    w.w32 = (std::min(std::max(n_planes, 1), kMaxPlanes) + 31) / 32;
+    w.kmask = g->n_det <= 2 ? cv.take<unsigned>(L * w.w32) : nullptr;
+    w.mask_ready = false;
     return cv.size();
 }
 
@@ -374,11 +424,13 @@ int enumerate_count(const laue_geometry *geom, const laue_planes *planes,
         return LAUE_OK;
     }
     const int64_t L = static_cast<int64_t>(geom->n_rot) * geom->n_det * N;
+    unsigned *mask = w.kmask && planes->n <= 32 * w.w32 ? w.kmask : nullptr;
     k_enumerate<<<enum_grid(N, geom->n_rot), 64, enum_lds(geom->n_det, planes->n), s>>>(w.geom, planes->w, planes->d, planes->harmonic_prev,
                                                planes->n, w.grains, N, geom->n_rot, merge, 0, w.counts, nullptr,
                                                nullptr, nullptr, nullptr, nullptr, nullptr,
-                                               nullptr, nullptr, nullptr, nullptr, nullptr);
+                                               nullptr, nullptr, nullptr, nullptr, nullptr, mask, w.w32);
     LAUE_CHECK_HIP(hipGetLastError());
+    w.mask_ready = mask != nullptr;
     if ((rc = launch_scan(w.counts, w.offs, L, s))) return rc;
     k_scan_blocks<<<(nb + 1 + 255) / 256, 256, 0, s>>>(w.offs, L, w.blk, nb, N);
     LAUE_CHECK_HIP(hipGetLastError());
@@ -396,7 +448,8 @@ int launch_enumerate_ids(const laue_geometry *geom, const laue_planes *planes, E
     k_enumerate<<<enum_grid(N, geom->n_rot), 64, enum_lds(geom->n_det, planes->n), s>>>(w.geom, planes->w, planes->d, planes->harmonic_prev,
                                                planes->n, w.grains, N, geom->n_rot, merge, 1, nullptr, w.offs,
                                                plane, grain, block, nullptr, nullptr, nullptr,
-                                               nullptr, nullptr, nullptr, nullptr);
+                                               nullptr, nullptr, nullptr, nullptr,
+                                               w.mask_ready ? w.kmask : nullptr, w.w32);
     LAUE_CHECK_HIP(hipGetLastError());
     return LAUE_OK;
 }
@@ -579,11 +632,10 @@ using namespace laue;
 
 extern "C" size_t laue_forward_workspace_size(const laue_geometry *geom, int32_t n_planes,
                                               int32_t n_grains) {
-    (void)n_planes;
-    if (!geom || validate_geometry(geom) != LAUE_OK || n_grains < 0) return 0;
+    if (!geom || validate_geometry(geom) != LAUE_OK || n_grains < 0 || n_planes < 0) return 0;
     Carver cv(nullptr);
     EnumWs w;
-    return carve_enum(cv, w, geom, n_grains);
+    return carve_enum(cv, w, geom, n_grains, n_planes);
 }
 
 extern "C" int laue_forward_enumerate(const laue_geometry *geom, const laue_planes *planes,
@@ -599,7 +651,7 @@ extern "C" int laue_forward_enumerate(const laue_geometry *geom, const laue_plan
     hipStream_t s = static_cast<hipStream_t>(stream);
     Carver cv(ws);
     EnumWs w;
-    size_t need = carve_enum(cv, w, geom, grains->n);
+    size_t need = carve_enum(cv, w, geom, grains->n, planes->n);
     if ((rc = check_ws(ws, ws_bytes, need))) return rc;
     std::vector<int64_t> hb;
     int64_t total = 0;
@@ -619,7 +671,8 @@ extern "C" int laue_forward_enumerate(const laue_geometry *geom, const laue_plan
         k_enumerate<<<enum_grid(grains->n, geom->n_rot), 64, enum_lds(geom->n_det, planes->n), s>>>(
             w.geom, planes->w, planes->d, planes->harmonic_prev, planes->n, w.grains, grains->n, geom->n_rot,
             merge_harmonics ? 1 : 0, 1, nullptr, w.offs, out->plane, out->grain, out->block,
-            out->s1, out->s2, out->vn, out->v1, out->v2, out->lam, out->flags);
+            out->s1, out->s2, out->vn, out->v1, out->v2, out->lam, out->flags, w.mask_ready ? w.kmask : nullptr,
+            w.w32);
         LAUE_CHECK_HIP(hipGetLastError());
     }
     out->n = total;
@@ -642,7 +695,7 @@ extern "C" int laue_forward_eval(const laue_geometry *geom, const laue_planes *p
     hipStream_t s = static_cast<hipStream_t>(stream);
     Carver cv(ws);
     EnumWs w;
-    size_t need = carve_enum(cv, w, geom, grains->n);
+    size_t need = carve_enum(cv, w, geom, grains->n, planes->n);
     if ((rc = check_ws(ws, ws_bytes, need))) return rc;
     GeomF hg;
     make_geomf(geom, &hg);
@@ -670,8 +723,8 @@ struct SimWs {
 };
 
 static size_t carve_sim(Carver &cv, SimWs &w, const laue_geometry *g, int n_grains, int64_t n_true_max,
-                        int64_t n_obs_max) {
-    carve_enum(cv, w.e, g, n_grains);
+                        int64_t n_obs_max, int n_planes) {
+    carve_enum(cv, w.e, g, n_grains, n_planes);
     int64_t S = std::max<int64_t>(n_true_max, 1), O = std::max<int64_t>(n_obs_max, 1);
     int nb = g->n_rot * g->n_det;
     w.plane = cv.take<int>(S);
@@ -696,11 +749,10 @@ static size_t carve_sim(Carver &cv, SimWs &w, const laue_geometry *g, int n_grai
 extern "C" size_t laue_simulate_workspace_size(const laue_geometry *geom, int32_t n_planes,
                                                int32_t n_grains, int64_t n_true_max,
                                                int64_t n_obs_max) {
-    (void)n_planes;
-    if (!geom || validate_geometry(geom) != LAUE_OK || n_grains < 0) return 0;
+    if (!geom || validate_geometry(geom) != LAUE_OK || n_grains < 0 || n_planes < 0) return 0;
     Carver cv(nullptr);
     SimWs w;
-    return carve_sim(cv, w, geom, n_grains, n_true_max, n_obs_max);
+    return carve_sim(cv, w, geom, n_grains, n_true_max, n_obs_max, n_planes);
 }
 
 extern "C" int laue_simulate(const laue_geometry *geom, const laue_planes *planes,
@@ -723,7 +775,7 @@ extern "C" int laue_simulate(const laue_geometry *geom, const laue_planes *plane
     const int64_t cap = *n_out;
     Carver cv(ws);
     SimWs w;
-    size_t need = carve_sim(cv, w, geom, truth->n, n_true_max, cap);
+    size_t need = carve_sim(cv, w, geom, truth->n, n_true_max, cap, planes->n);
     if ((rc = check_ws(ws, ws_bytes, need))) return rc;
     std::vector<int64_t> sb;
     int64_t S = 0;
@@ -740,7 +792,7 @@ extern "C" int laue_simulate(const laue_geometry *geom, const laue_planes *plane
         k_enumerate<<<enum_grid(truth->n, geom->n_rot), 64, enum_lds(geom->n_det, planes->n), s>>>(
             w.e.geom, planes->w, planes->d, planes->harmonic_prev, planes->n, w.e.grains, truth->n, geom->n_rot, 1,
             1, nullptr, w.e.offs, w.plane, w.grain, w.block, nullptr, nullptr, nullptr, nullptr,
-            nullptr, nullptr, nullptr);
+            nullptr, nullptr, nullptr, w.e.mask_ready ? w.e.kmask : nullptr, w.e.w32);
         LAUE_CHECK_HIP(hipGetLastError());
         k_sim_noise<<<static_cast<unsigned>((S + 255) / 256), 256, 0, s>>>(
             *geom, planes->w, truth->q, truth->x, w.plane, w.grain, w.block, S, sigma_mm / distance,

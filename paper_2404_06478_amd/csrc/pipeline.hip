@@ -156,6 +156,32 @@ int validate_index_params(const laue_index_params *p) {
     return LAUE_OK;
 }
 
+// Eq. spot_ngrains: k* where f (the running sum of the greedy's increments)
+// bends most, its second difference taken over h picks: argmax over k >= 1 of
+// the mean increment of the h picks up to k (m = min(k, h) of them) minus that
+// of the h picks after k (increments beyond the picks are 0); lowest k on
+// ties.  A step of one pick is the printed difference; the increments of a
+// long run of true grains vary by about 1% from pick to pick, so that step can
+// peak among the first picks.
+constexpr int kPrototypeStep = 8;
+
+int prototype_count(const std::vector<double> &gains, int h) {
+    const int K = static_cast<int>(gains.size());
+    std::vector<double> f(K + 1, 0.0);
+    for (int k = 0; k < K; ++k) f[k + 1] = f[k] + gains[k];
+    double best = -INFINITY;
+    int arg = K > 0 ? 1 : 0;
+    for (int k = 1; k <= K; ++k) {
+        const int m = std::min(k, h);
+        const double v = (f[k] - f[k - m]) / m - (f[std::min(K, k + h)] - f[k]) / h;
+        if (v > best) {
+            best = v;
+            arg = k;
+        }
+    }
+    return arg;
+}
+
 double ms_since(std::chrono::steady_clock::time_point t0) {
     return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
 }
@@ -294,14 +320,7 @@ int index_front(const laue_geometry *geom, const laue_planes *planes, const laue
         std::vector<double> gains(n_picked);
         LAUE_CHECK_HIP(hipMemcpyAsync(gains.data(), w.gains, n_picked * sizeof(double), hipMemcpyDeviceToHost, s));
         LAUE_CHECK_HIP(hipStreamSynchronize(s));
-        double best = -INFINITY;
-        for (int k = 0; k < n_picked; ++k) {
-            const double drop = gains[k] - (k + 1 < n_picked ? gains[k + 1] : 0.0);
-            if (drop > best) {
-                best = drop;
-                k_star = k + 1;
-            }
-        }
+        k_star = prototype_count(gains, kPrototypeStep);
         k_gather_protos<<<(k_star + 63) / 64, 64, 0, s>>>(w.gq, w.gx, w.picks, k_star, out->q, out->x);
         LAUE_CHECK_HIP(hipGetLastError());
     }

@@ -184,6 +184,38 @@ __global__ void k_labels(const double *__restrict__ q, const int *__restrict__ s
     if (mis_deg) mis_deg[c] = mis;
 }
 
+// Nearest true grain of each candidate orientation: the largest cos(angle / 2)
+// over the true grains and the 24 proper cubic rotations (FP64), lowest grain
+// index on ties; label 1 when the angle is within max_deg.
+__global__ void k_labels_nearest(const double *__restrict__ q, int64_t n_cand, const double *__restrict__ qt,
+                                 int n_true, double cos_half_max, float *__restrict__ label,
+                                 float *__restrict__ mis_deg, int *__restrict__ nearest) {
+    const int64_t c = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (c >= n_cand) return;
+    const double *r = q + 4 * c;
+    const double nr = sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2] + r[3] * r[3]);
+    double best = -2.0;
+    int arg = -1;
+    for (int g = 0; g < n_true; ++g) {
+        const double *p = qt + 4 * g;
+        const double np_ = sqrt(p[0] * p[0] + p[1] * p[1] + p[2] * p[2] + p[3] * p[3]);
+        double dq[4];
+        dq[0] = p[0] * r[0] + p[1] * r[1] + p[2] * r[2] + p[3] * r[3];
+        dq[1] = p[0] * r[1] - p[1] * r[0] - p[2] * r[3] + p[3] * r[2];
+        dq[2] = p[0] * r[2] + p[1] * r[3] - p[2] * r[0] - p[3] * r[1];
+        dq[3] = p[0] * r[3] - p[1] * r[2] + p[2] * r[1] - p[3] * r[0];
+        for (int i = 0; i < 4; ++i) dq[i] /= np_ * nr;
+        const double ch = fmin(1.0, cubic_cos_half(dq));
+        if (ch > best) {
+            best = ch;
+            arg = g;
+        }
+    }
+    label[c] = arg >= 0 && best >= cos_half_max ? 1.0f : 0.0f;
+    if (mis_deg) mis_deg[c] = arg >= 0 ? static_cast<float>(2.0 * acos(best) * (180.0 / M_PI)) : __builtin_inff();
+    if (nearest) nearest[c] = arg;
+}
+
 // Same-grain pair k: Philox counter (k, 0, 0, 7); a = x0 mod n; b = the
 // (x1 mod count)-th other spot of a's grain and rotation, in index order.
 __global__ void k_same_pairs(const int64_t *__restrict__ ooff, int n_rot, int n_det,
@@ -435,6 +467,24 @@ extern "C" int laue_candidate_labels(const laue_candidates *cand, const int32_t 
     const double ch = std::cos(0.5 * max_deg * M_PI / 180.0);
     k_labels<<<static_cast<unsigned>((cand->n + 255) / 256), 256, 0, s>>>(
         cand->q, cand->spot_a, cand->spot_b, cand->n, spot_grain, n_obs, truth->q, truth->n, ch, label, mis_deg);
+    LAUE_CHECK_HIP(hipGetLastError());
+    return LAUE_OK;
+}
+
+extern "C" int laue_candidate_labels_nearest(const laue_candidates *cand, const laue_grains *truth,
+                                             double max_deg, float *label, float *mis_deg, int32_t *nearest,
+                                             void *stream) {
+    clear_error();
+    int rc;
+    LAUE_REQUIRE(cand && cand->n >= 0 && label, LAUE_EINVAL, "NULL argument");
+    if ((rc = validate_grains(truth))) return rc;
+    LAUE_REQUIRE(cand->n == 0 || cand->q, LAUE_EINVAL, "candidates need q");
+    LAUE_REQUIRE(std::isfinite(max_deg) && max_deg >= 0 && max_deg <= 180, LAUE_EINVAL, "bad angle");
+    if (cand->n == 0) return LAUE_OK;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const double ch = std::cos(0.5 * max_deg * M_PI / 180.0);
+    k_labels_nearest<<<static_cast<unsigned>((cand->n + 255) / 256), 256, 0, s>>>(
+        cand->q, cand->n, truth->q, truth->n, ch, label, mis_deg, nearest);
     LAUE_CHECK_HIP(hipGetLastError());
     return LAUE_OK;
 }

@@ -7,7 +7,7 @@ import pytest
 import torch
 
 import inputgen as ig
-from oracle import candidates, crystal, forward, proposal, simulate
+from oracle import candidates, crystal, forward, metrics, proposal, simulate
 
 pytestmark = pytest.mark.gpu
 
@@ -105,6 +105,38 @@ def test_labels_match_oracle(gpu_lib):
     assert np.allclose(mis_g[fin], mis_o[fin], atol=1e-4)
     edge = np.abs(mis_o - 2.0) < 1e-6
     assert np.array_equal(lab_g[~edge], lab_o[~edge])
+
+
+def test_nearest_labels_match_oracle(gpu_lib):
+    """Labels by the nearest true grain on candidates of random pairs and on
+    orientations placed near the true grains (so that both labels occur)."""
+    laue = gpu_lib
+    p, pl, g, q, x, sim, p12, geom, planes, obs = _setup(laue, n_grains=6, seed=5)
+    ref = candidates.generate(pl, g, p12, sim["offsets"], 400, 3)
+    rng = np.random.default_rng(4)
+    ang = np.radians(rng.uniform(0.0, 2.0, 60))
+    ax = rng.standard_normal((60, 3))
+    ax /= np.linalg.norm(ax, axis=1, keepdims=True)
+    dq = np.concatenate([np.cos(ang / 2)[:, None], np.sin(ang / 2)[:, None] * ax], axis=1)
+    base = q[rng.integers(0, len(q), 60)]
+    w0, x0, y0, z0 = base.T
+    w1, x1, y1, z1 = dq.T
+    near_q = np.stack([w0 * w1 - x0 * x1 - y0 * y1 - z0 * z1, w0 * x1 + x0 * w1 + y0 * z1 - z0 * y1,
+                       w0 * y1 - x0 * z1 + y0 * w1 + z0 * x1, w0 * z1 + x0 * y1 - y0 * x1 + z0 * w1], axis=1)
+    cq = np.concatenate([ref["q"], near_q])
+    lab_o, mis_o, near_o = proposal.labels_nearest(cq, q, 1.0)
+    assert 10 <= lab_o.sum() < len(cq)
+    c = {"q": torch.tensor(cq, device="cuda")}
+    lab_g, mis_g, near_g = laue.laue_candidate_labels_nearest(c, laue.Grains(q, x), 1.0)
+    lab_g, mis_g, near_g = lab_g.cpu().numpy(), mis_g.cpu().numpy(), near_g.cpu().numpy()
+    assert np.allclose(mis_g, mis_o, atol=1e-4)
+    edge = np.abs(mis_o - 1.0) < 1e-6
+    assert np.array_equal(lab_g[~edge], lab_o[~edge])
+    # the nearest grain where it is unique (no other grain within 1e-6 deg)
+    all_mis = np.degrees(metrics.misorientation(cq[:, None, :], q[None, :, :]))
+    second = np.sort(all_mis, axis=1)[:, 1] if len(q) > 1 else np.full(len(cq), np.inf)
+    uniq = second - mis_o > 1e-6
+    assert np.array_equal(near_g[uniq], near_o[uniq])
 
 
 @pytest.mark.parametrize("n,frac", [(1, 1.0), (7, 0.5), (1000, 0.05), (100003, 0.05), (262144, 0.3)])

@@ -99,6 +99,28 @@ def test_labels():
     assert np.isinf(mis[3]) and np.isinf(mis[4])
 
 
+def test_labels_nearest():
+    """By construction: a candidate 0.9 deg from grain 1 (through a cube
+    symmetry of it) and 3 deg from grain 0 labels 1 with grain 1; one 1.1 deg
+    from grain 0 labels 0 at 1 deg; equal distances go to the lower index."""
+    q_true = np.array([[1.0, 0, 0, 0], [np.cos(np.radians(30) / 2), 0, 0, np.sin(np.radians(30) / 2)]])
+    S = crystal.cubic_group()[7]
+    R1 = crystal.quat_to_R(q_true[1])
+    h = np.radians(0.9) / 2
+    dR = crystal.quat_to_R(np.array([np.cos(h), np.sin(h), 0, 0]))
+    q_a = crystal.R_to_quat(R1 @ dR @ S)
+    h = np.radians(1.1) / 2
+    q_b = np.array([np.cos(h), 0, np.sin(h), 0])
+    h = np.radians(15) / 2
+    q_mid = np.array([np.cos(h), 0, 0, np.sin(h)])       # 15 deg from both grains
+    lab, mis, near = proposal.labels_nearest(np.array([q_a, q_b, q_mid]), q_true, 1.0)
+    assert lab.tolist() == [1.0, 0.0, 0.0]
+    assert near.tolist() == [1, 0, 0]
+    assert abs(mis[0] - 0.9) < 1e-9 and abs(mis[1] - 1.1) < 1e-9 and abs(mis[2] - 15.0) < 1e-9
+    lab, mis, near = proposal.labels_nearest(np.array([q_a]), np.zeros((0, 4)), 1.0)
+    assert lab.tolist() == [0.0] and near.tolist() == [-1] and np.isinf(mis[0])
+
+
 def test_select_top():
     s = np.array([0.5, 0.9, 0.5, 0.9, 0.1])
     assert proposal.select_top(s, 0.6).tolist() == [0, 1, 3]

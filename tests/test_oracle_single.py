@@ -111,6 +111,34 @@ def test_greedy_guarantee_against_brute_force(seed):
     assert np.all(np.diff(gains) <= 1e-12)          # increments never grow (submodularity)
 
 
+def test_prototype_count_step_one_is_the_largest_drop():
+    """With a step of one pick the rule is the printed second difference:
+    argmax_k (Delta_k - Delta_{k+1}), Delta beyond the picks 0 (brute force)."""
+    rng = np.random.default_rng(5)
+    for _ in range(50):
+        g = np.sort(rng.uniform(0, 10, rng.integers(1, 40)))[::-1]
+        d = np.append(g, 0.0)
+        assert single.n_prototypes(g, h=1) == int(np.argmax(d[:-1] - d[1:])) + 1
+
+
+def test_prototype_count_is_not_decided_by_one_gap():
+    """300 true grains whose increments fall by 9 per pick from 3800 (to about
+    1060), except one gap of 50 between picks 2 and 3 (the largest single gap,
+    as the top order statistics of the grains' gains give), then a sustained
+    fall of 20 per pick over 40 picks and a tail falling by 0.4 per pick to
+    about 0: the printed step peaks at the one gap (k = 2), the 8-pick
+    difference at the fall (k ~ 300)."""
+    top = 3800.0 - 9.0 * np.arange(300)
+    top[2:] -= 50.0
+    fall = top[-1] - 20.0 * np.arange(1, 41)
+    tail = fall[-1] - 0.395 * np.arange(1, 651)
+    g = np.concatenate([top, fall, tail])
+    assert np.all(np.diff(g) < 0)
+    assert single.n_prototypes(g, h=1) == 2
+    k = single.n_prototypes(g)
+    assert 296 <= k <= 312, k
+
+
 def test_number_of_prototypes_on_separated_grains():
     # 4 disjoint groups of rows, each covered by 3 near-identical candidates
     phi = -4.5
