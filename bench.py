@@ -742,14 +742,15 @@ def bench_forward(laue, n_grains, log):
 # spot-pair candidates: the network ranks them and the top 5% are scored,
 # against plain scoring of all 2^20), on the stage schedule; the same sample
 # at the paper's fiducial noise with the paper's annealing recipe, the same
-# 2^20 candidates both ways, and plain scoring of 2048 pairs' candidates (the
-# recall the learned form reaches); the 2000-grain stress workload (the
+# 2^20 candidates both ways, plain scoring of 2048 pairs' candidates (the
+# recall the learned form reaches) and the paper's 500,000 Sobol-grid starts;
+# the 2000-grain stress workload (the
 # network ranks 2^20 candidates and scores the top 5%; plain scoring of the
 # first 2^16).
 DEFAULT_INDEX_LINES = ("medium,pairs=8192,sobol=200000;"
                        "learned,pairs=32768,lpairs=32768,cand=1048576;"
                        "learned_fiducial,pairs=24576,lpairs=24576,cand=1048576,recipe=paper;"
-                       "learned_fiducial,pairs=2048,lpairs=0,recipe=paper,name=learned_fiducial.paper_2048;"
+                       "learned_fiducial,pairs=2048,lpairs=0,sobol=500000,recipe=paper,name=learned_fiducial.paper_2048;"
                        "stress,pairs=32768,lpairs=32768,cand=1048576,pcand=65536")
 
 

@@ -8,6 +8,8 @@
 namespace laue {
 
 constexpr int kMaxPlanes = 1024;
+constexpr int kEnumChunk = 16;   // grains per enumerate work item
+constexpr int kEmitList = 2048;  // LDS list of the write pass (>= the bits of 64 mask words)
 
 // ---------------------------------------------------------------- grains
 
@@ -50,8 +52,8 @@ __global__ __launch_bounds__(64) void k_enumerate(
     const GeomF &G = *Gp;
     const int lane = threadIdx.x;
     // kmask (may be NULL): per item (t, n) and detector, W32 words of kept-plane
-    // bits (bit m of word m / 32).  The count pass writes them; a write pass
-    // given them evaluates only the kept planes.
+    // bits (bit m of word m / 32), written by the count pass for
+    // k_enumerate_emit.
     __shared__ unsigned kbits[2 * (kMaxPlanes / 32)];
     // visibility per (detector, plane): dynamic LDS of n_det x M bytes
     extern __shared__ uint8_t vis_lds[];
@@ -61,27 +63,69 @@ __global__ __launch_bounds__(64) void k_enumerate(
     for (int m = lane; m < M; m += 64) pv[m] = static_cast<short>(prev[m] >= 0 && prev[m] < M ? prev[m] : -1);
     __syncthreads();
     const int D = G.n_det;
-    const int64_t n_items = static_cast<int64_t>(N) * T;
-    for (int64_t item = blockIdx.x; item < n_items; item += gridDim.x) {
-        const int n = static_cast<int>(item % N);
-        const int t = static_cast<int>(item / N);
-        const GrainF gr = grains[n];
+    // work items: (rotation t, kEnumChunk consecutive grains), so that the
+    // outputs of neighbouring grains (adjacent in every (block, grain, plane)
+    // ordered array, runs of a few entries each) are written by one wave and
+    // reach memory as whole cache lines
+    const int64_t n_chunks = (static_cast<int64_t>(N) + kEnumChunk - 1) / kEnumChunk;
+    const int64_t n_work = n_chunks * T;
+    for (int64_t wi = blockIdx.x; wi < n_work; wi += gridDim.x) {
+        const int t = static_cast<int>(wi / n_chunks);
+        const int n_lo = static_cast<int>((wi % n_chunks) * kEnumChunk);
+        const int n_hi = std::min(N, n_lo + kEnumChunk);
         const float c = G.cs[t][0], s = G.cs[t][1];
-        if (pass && kmask) {
-            // write pass from the count pass's bits: only the kept planes
+        for (int n = n_lo; n < n_hi; ++n) {
+            const int64_t item = static_cast<int64_t>(t) * N + n;
+            const GrainF gr = grains[n];
+            if (!pass && kmask)
+                for (int w = lane; w < D * W32; w += 64) kbits[w] = 0u;
+            int K = 0;
+            for (int m0 = 0; m0 < M; m0 += 64) {
+                const int m = m0 + lane;
+                bool ib = false;
+                if (m < M) {
+                    float ux, uy, uz;
+                    lab_normal(gr.R, c, s, W[3 * m], W[3 * m + 1], W[3 * m + 2], ux, uy, uz);
+                    const float lam = 2.0f * Dsp[m] * ux;
+                    ib = (lam >= G.lam_min) && (lam <= G.lam_max);
+                    for (int d = 0; d < D; ++d) vis_lds[d * M + m] = 0;
+                }
+                const unsigned long long bal = __ballot(ib);
+                if (ib) inb[K + __popcll(bal & ((1ull << lane) - 1ull))] = static_cast<short>(m);
+                K += __popcll(bal);
+            }
+            __syncthreads();
+            for (int k = lane; k < K; k += 64) {
+                const int m = inb[k];
+                const float wx = W[3 * m], wy = W[3 * m + 1], wz = W[3 * m + 2];
+                for (int d = 0; d < D; ++d) {
+                    const SpotGeo o = spot_geometry(G, G.det[d], gr.R, gr.x, c, s, wx, wy, wz, Dsp[m]);
+                    vis_lds[d * M + m] = (o.inband && o.on) ? 1 : 0;
+                }
+            }
+            __syncthreads();
             for (int d = 0; d < D; ++d) {
                 const int slot = (t * D + d) * N + n;
-                const int64_t base = offs[slot];
-                const unsigned *mk = kmask + (item * D + d) * W32;
+                int64_t base = pass ? offs[slot] : 0;
                 int running = 0;
-                for (int m0 = 0; m0 < M; m0 += 64) {
-                    const int m = m0 + lane;
-                    const bool keep = m < M && ((mk[m >> 5] >> (m & 31)) & 1u);
-                    const unsigned long long bal = __ballot(keep);
-                    if (keep) {
-                        const int64_t pos = base + running + __popcll(bal & ((1ull << lane) - 1ull));
-                        const SpotGeo o = spot_geometry(G, G.det[d], gr.R, gr.x, c, s, W[3 * m], W[3 * m + 1],
-                                                        W[3 * m + 2], Dsp[m]);
+                // visible planes are in band: walk the in-band list (ascending m)
+                for (int k0 = 0; k0 < K; k0 += 64) {
+                    const int m = k0 + lane < K ? inb[k0 + lane] : 0;
+                    bool keep = (k0 + lane < K) && vis_lds[d * M + m];
+                    if (merge && keep) {
+                        int a = pv[m];
+                        for (int hop = 0; hop < 16 && a >= 0; ++hop) {
+                            if (vis_lds[d * M + a]) { keep = false; break; }
+                            a = pv[a];
+                        }
+                    }
+                    unsigned long long bal = __ballot(keep);
+                    if (!pass && kmask && keep) atomicOr(&kbits[d * W32 + (m >> 5)], 1u << (m & 31));
+                    if (pass && keep) {
+                        unsigned long long lower = bal & ((1ull << lane) - 1ull);
+                        int64_t pos = base + running + __popcll(lower);
+                        SpotGeo o = spot_geometry(G, G.det[d], gr.R, gr.x, c, s, W[3 * m], W[3 * m + 1],
+                                                  W[3 * m + 2], Dsp[m]);
                         o_plane[pos] = m;
                         o_grain[pos] = n;
                         o_block[pos] = t * D + d;
@@ -97,80 +141,119 @@ __global__ __launch_bounds__(64) void k_enumerate(
                     }
                     running += __popcll(bal);
                 }
+                if (!pass && lane == 0) counts[slot] = running;
             }
-            continue;
-        }
-        if (!pass && kmask)
-            for (int w = lane; w < D * W32; w += 64) kbits[w] = 0u;
-        int K = 0;
-        for (int m0 = 0; m0 < M; m0 += 64) {
-            const int m = m0 + lane;
-            bool ib = false;
-            if (m < M) {
-                float ux, uy, uz;
-                lab_normal(gr.R, c, s, W[3 * m], W[3 * m + 1], W[3 * m + 2], ux, uy, uz);
-                const float lam = 2.0f * Dsp[m] * ux;
-                ib = (lam >= G.lam_min) && (lam <= G.lam_max);
-                for (int d = 0; d < D; ++d) vis_lds[d * M + m] = 0;
+            if (!pass && kmask) {
+                __syncthreads();
+                for (int w = lane; w < D * W32; w += 64) kmask[item * D * W32 + w] = kbits[w];
             }
-            const unsigned long long bal = __ballot(ib);
-            if (ib) inb[K + __popcll(bal & ((1ull << lane) - 1ull))] = static_cast<short>(m);
-            K += __popcll(bal);
+            __syncthreads();        // vis, inb and kbits are reused by the next item
         }
-        __syncthreads();
-        for (int k = lane; k < K; k += 64) {
-            const int m = inb[k];
-            const float wx = W[3 * m], wy = W[3 * m + 1], wz = W[3 * m + 2];
-            for (int d = 0; d < D; ++d) {
-                const SpotGeo o = spot_geometry(G, G.det[d], gr.R, gr.x, c, s, wx, wy, wz, Dsp[m]);
-                vis_lds[d * M + m] = (o.inband && o.on) ? 1 : 0;
-            }
+    }
+}
+
+// Evaluates and writes the cnt listed (grain in chunk << 16 | plane) entries
+// of detector d at base, base + 1, ... with every lane; the list is read after
+// a barrier and may be refilled after the closing one.
+__device__ __forceinline__ void emit_list(const GeomF &G, const float *__restrict__ W, const float *__restrict__ Dsp,
+                                          const GrainF *__restrict__ grains, int n_lo, int t, int d, float c, float s,
+                                          const int *elist, int cnt, int64_t base, int *__restrict__ o_plane,
+                                          int *__restrict__ o_grain, int *__restrict__ o_block,
+                                          float *__restrict__ o_s1, float *__restrict__ o_s2,
+                                          float *__restrict__ o_vn, float *__restrict__ o_v1,
+                                          float *__restrict__ o_v2, float *__restrict__ o_lam,
+                                          uint8_t *__restrict__ o_flags) {
+    __syncthreads();
+    for (int k = static_cast<int>(threadIdx.x); k < cnt; k += 64) {
+        const int e = elist[k];
+        const int nn = n_lo + (e >> 16), m = e & 0xffff;
+        const GrainF &g2 = grains[nn];
+        const SpotGeo o = spot_geometry(G, G.det[d], g2.R, g2.x, c, s, W[3 * m], W[3 * m + 1], W[3 * m + 2], Dsp[m]);
+        const int64_t pos = base + k;
+        o_plane[pos] = m;
+        o_grain[pos] = nn;
+        o_block[pos] = t * G.n_det + d;
+        if (o_s1) {
+            o_s1[pos] = o.s1;
+            o_s2[pos] = o.s2;
+            o_vn[pos] = o.vn;
+            o_v1[pos] = o.v1;
+            o_v2[pos] = o.v2;
         }
+        if (o_lam) o_lam[pos] = o.lam;
+        if (o_flags) o_flags[pos] = o.flags;
+    }
+    __syncthreads();
+}
+
+// Write pass from the count pass's kept-plane bits (kmask, W32 words per (t,
+// n) item and detector): per work item (rotation t, kEnumChunk grains), the
+// chunk's mask words in one coalesced load to LDS (they are contiguous), then
+// detector by detector the kept (grain, plane) pairs listed in LDS in output
+// order (ballot compaction) and evaluated and written by every lane: for one
+// detector the chunk's outputs are one contiguous range (offsets in (t, d, n)
+// order), written in coalesced runs.
+__global__ __launch_bounds__(64) void k_enumerate_emit(
+    const GeomF *__restrict__ Gp, const float *__restrict__ W, const float *__restrict__ Dsp, int M,
+    const GrainF *__restrict__ grains, int N, int T, const int64_t *__restrict__ offs, int *__restrict__ o_plane,
+    int *__restrict__ o_grain, int *__restrict__ o_block, float *__restrict__ o_s1, float *__restrict__ o_s2,
+    float *__restrict__ o_vn, float *__restrict__ o_v1, float *__restrict__ o_v2, float *__restrict__ o_lam,
+    uint8_t *__restrict__ o_flags, const unsigned *__restrict__ kmask, int W32) {
+    const GeomF &G = *Gp;
+    const int lane = threadIdx.x;
+    const int D = G.n_det;
+    __shared__ unsigned mw[kEnumChunk * 2 * (kMaxPlanes / 32)];
+    __shared__ int elist[kEmitList];
+    const int64_t n_chunks = (static_cast<int64_t>(N) + kEnumChunk - 1) / kEnumChunk;
+    const int64_t n_work = n_chunks * T;
+    for (int64_t wi = blockIdx.x; wi < n_work; wi += gridDim.x) {
+        const int t = static_cast<int>(wi / n_chunks);
+        const int n_lo = static_cast<int>((wi % n_chunks) * kEnumChunk);
+        const int n_hi = std::min(N, n_lo + kEnumChunk);
+        const float c = G.cs[t][0], s = G.cs[t][1];
+        const int n_words = (n_hi - n_lo) * D * W32;
+        const unsigned *src = kmask + (static_cast<int64_t>(t) * N + n_lo) * D * W32;
+        for (int k = lane; k < n_words; k += 64) mw[k] = src[k];
         __syncthreads();
         for (int d = 0; d < D; ++d) {
-            const int slot = (t * D + d) * N + n;
-            int64_t base = pass ? offs[slot] : 0;
-            int running = 0;
-            // visible planes are in band: walk the in-band list (ascending m)
-            for (int k0 = 0; k0 < K; k0 += 64) {
-                const int m = k0 + lane < K ? inb[k0 + lane] : 0;
-                bool keep = (k0 + lane < K) && vis_lds[d * M + m];
-                if (merge && keep) {
-                    int a = pv[m];
-                    for (int hop = 0; hop < 16 && a >= 0; ++hop) {
-                        if (vis_lds[d * M + a]) { keep = false; break; }
-                        a = pv[a];
-                    }
+            int64_t base = offs[(static_cast<int64_t>(t) * D + d) * N + n_lo];
+            int cnt = 0;
+            // the chunk's mask words of detector d in (grain, word) order, 64
+            // at a time: each lane lists the set bits of its word at its
+            // scanned position, so the list stays in (grain, plane) order
+            const int nw = (n_hi - n_lo) * W32;
+            for (int r0 = 0; r0 < nw; r0 += 64) {
+                const int idx = r0 + lane;
+                unsigned word = 0u;
+                int nrel = 0, w = 0;
+                if (idx < nw) {
+                    nrel = idx / W32;
+                    w = idx - nrel * W32;
+                    word = mw[(nrel * D + d) * W32 + w];
                 }
-                unsigned long long bal = __ballot(keep);
-                if (!pass && kmask && keep) atomicOr(&kbits[d * W32 + (m >> 5)], 1u << (m & 31));
-                if (pass && keep) {
-                    unsigned long long lower = bal & ((1ull << lane) - 1ull);
-                    int64_t pos = base + running + __popcll(lower);
-                    SpotGeo o = spot_geometry(G, G.det[d], gr.R, gr.x, c, s, W[3 * m], W[3 * m + 1],
-                                              W[3 * m + 2], Dsp[m]);
-                    o_plane[pos] = m;
-                    o_grain[pos] = n;
-                    o_block[pos] = t * D + d;
-                    if (o_s1) {
-                        o_s1[pos] = o.s1;
-                        o_s2[pos] = o.s2;
-                        o_vn[pos] = o.vn;
-                        o_v1[pos] = o.v1;
-                        o_v2[pos] = o.v2;
-                    }
-                    if (o_lam) o_lam[pos] = o.lam;
-                    if (o_flags) o_flags[pos] = o.flags;
+                const int pc = __popc(word);
+                int incl = pc;
+#pragma unroll
+                for (int o = 1; o < 64; o <<= 1) {
+                    const int y = __shfl_up(incl, o, 64);
+                    if (lane >= o) incl += y;
                 }
-                running += __popcll(bal);
+                const int total = __shfl(incl, 63, 64);
+                if (cnt + total > kEmitList) {        // no room for this round: write the list out
+                    emit_list(G, W, Dsp, grains, n_lo, t, d, c, s, elist, cnt, base, o_plane, o_grain, o_block,
+                              o_s1, o_s2, o_vn, o_v1, o_v2, o_lam, o_flags);
+                    base += cnt;
+                    cnt = 0;
+                }
+                int q = cnt + incl - pc;
+                for (unsigned wb = word; wb; wb &= wb - 1u) elist[q++] = (nrel << 16) | (w * 32 + __ffs(wb) - 1);
+                cnt += total;
             }
-            if (!pass && lane == 0) counts[slot] = running;
+            if (cnt > 0)
+                emit_list(G, W, Dsp, grains, n_lo, t, d, c, s, elist, cnt, base, o_plane, o_grain, o_block, o_s1,
+                          o_s2, o_vn, o_v1, o_v2, o_lam, o_flags);
         }
-        if (!pass && kmask) {
-            __syncthreads();
-            for (int w = lane; w < D * W32; w += 64) kmask[item * D * W32 + w] = kbits[w];
-        }
-        __syncthreads();        // vis, inb and kbits are reused by the next item
+        __syncthreads();        // mw is reused by the next work item
     }
 }
 
@@ -178,7 +261,8 @@ __global__ __launch_bounds__(64) void k_enumerate(
 // CU, 4 KB of static and n_det x M bytes of dynamic LDS each), at most one per
 // item; enum_lds is the dynamic part.
 unsigned enum_grid(int N, int T) {
-    return static_cast<unsigned>(std::min<int64_t>(static_cast<int64_t>(N) * T, 256 * 32));
+    const int64_t chunks = (static_cast<int64_t>(N) + kEnumChunk - 1) / kEnumChunk;
+    return static_cast<unsigned>(std::max<int64_t>(1, std::min<int64_t>(chunks * T, 256 * 32)));
 }
 size_t enum_lds(int n_det, int M) { return static_cast<size_t>(n_det) * M; }
 
@@ -441,17 +525,29 @@ int enumerate_count(const laue_geometry *geom, const laue_planes *planes,
     return LAUE_OK;
 }
 
+// Write pass after enumerate_count on the same workspace: from the count
+// pass's kept-plane bits when it wrote them, else recomputing every plane.
+int launch_emit(const laue_geometry *geom, const laue_planes *planes, EnumWs &w, int N, int merge, int *plane,
+                int *grain, int *block, float *s1, float *s2, float *vn, float *v1, float *v2, float *lam,
+                uint8_t *flags, hipStream_t s) {
+    if (N == 0) return LAUE_OK;
+    if (w.mask_ready)
+        k_enumerate_emit<<<enum_grid(N, geom->n_rot), 64, 0, s>>>(
+            w.geom, planes->w, planes->d, planes->n, w.grains, N, geom->n_rot, w.offs, plane, grain, block, s1, s2,
+            vn, v1, v2, lam, flags, w.kmask, w.w32);
+    else
+        k_enumerate<<<enum_grid(N, geom->n_rot), 64, enum_lds(geom->n_det, planes->n), s>>>(
+            w.geom, planes->w, planes->d, planes->harmonic_prev, planes->n, w.grains, N, geom->n_rot, merge, 1,
+            nullptr, w.offs, plane, grain, block, s1, s2, vn, v1, v2, lam, flags, nullptr, w.w32);
+    LAUE_CHECK_HIP(hipGetLastError());
+    return LAUE_OK;
+}
+
 // Write pass of the enumerate (ids only) after enumerate_count on the same workspace.
 int launch_enumerate_ids(const laue_geometry *geom, const laue_planes *planes, EnumWs &w, int N,
                          int merge, int *plane, int *grain, int *block, hipStream_t s) {
-    if (N == 0) return LAUE_OK;
-    k_enumerate<<<enum_grid(N, geom->n_rot), 64, enum_lds(geom->n_det, planes->n), s>>>(w.geom, planes->w, planes->d, planes->harmonic_prev,
-                                               planes->n, w.grains, N, geom->n_rot, merge, 1, nullptr, w.offs,
-                                               plane, grain, block, nullptr, nullptr, nullptr,
-                                               nullptr, nullptr, nullptr, nullptr,
-                                               w.mask_ready ? w.kmask : nullptr, w.w32);
-    LAUE_CHECK_HIP(hipGetLastError());
-    return LAUE_OK;
+    return launch_emit(geom, planes, w, N, merge, plane, grain, block, nullptr, nullptr, nullptr, nullptr, nullptr,
+                       nullptr, nullptr, s);
 }
 
 // ---------------------------------------------------------------- simulate
@@ -668,12 +764,9 @@ extern "C" int laue_forward_enumerate(const laue_geometry *geom, const laue_plan
         LAUE_REQUIRE(out->plane && out->grain && out->block && out->s1 && out->s2 && out->vn &&
                          out->v1 && out->v2,
                      LAUE_EINVAL, "model-spot arrays are NULL");
-        k_enumerate<<<enum_grid(grains->n, geom->n_rot), 64, enum_lds(geom->n_det, planes->n), s>>>(
-            w.geom, planes->w, planes->d, planes->harmonic_prev, planes->n, w.grains, grains->n, geom->n_rot,
-            merge_harmonics ? 1 : 0, 1, nullptr, w.offs, out->plane, out->grain, out->block,
-            out->s1, out->s2, out->vn, out->v1, out->v2, out->lam, out->flags, w.mask_ready ? w.kmask : nullptr,
-            w.w32);
-        LAUE_CHECK_HIP(hipGetLastError());
+        if ((rc = launch_emit(geom, planes, w, grains->n, merge_harmonics ? 1 : 0, out->plane, out->grain,
+                              out->block, out->s1, out->s2, out->vn, out->v1, out->v2, out->lam, out->flags, s)))
+            return rc;
     }
     out->n = total;
     LAUE_CHECK_HIP(hipStreamSynchronize(s));
@@ -789,11 +882,7 @@ extern "C" int laue_simulate(const laue_geometry *geom, const laue_planes *plane
     const uint32_t k0 = static_cast<uint32_t>(seed & 0xffffffffu), k1 = static_cast<uint32_t>(seed >> 32);
     std::vector<int> nt(nb, 0), no(nb, 0);
     if (S > 0) {
-        k_enumerate<<<enum_grid(truth->n, geom->n_rot), 64, enum_lds(geom->n_det, planes->n), s>>>(
-            w.e.geom, planes->w, planes->d, planes->harmonic_prev, planes->n, w.e.grains, truth->n, geom->n_rot, 1,
-            1, nullptr, w.e.offs, w.plane, w.grain, w.block, nullptr, nullptr, nullptr, nullptr,
-            nullptr, nullptr, nullptr, w.e.mask_ready ? w.e.kmask : nullptr, w.e.w32);
-        LAUE_CHECK_HIP(hipGetLastError());
+        if ((rc = launch_enumerate_ids(geom, planes, w.e, truth->n, 1, w.plane, w.grain, w.block, s))) return rc;
         k_sim_noise<<<static_cast<unsigned>((S + 255) / 256), 256, 0, s>>>(
             *geom, planes->w, truth->q, truth->x, w.plane, w.grain, w.block, S, sigma_mm / distance,
             k0, k1, w.np1, w.np2, w.keep, w.key);

@@ -1,17 +1,15 @@
 """Training the learned proposal on simulated spots, on the GPU.
 
 A training example is one spot-pair candidate of a simulated sample: its 16
-features (14 from the pair, 2 cheap-support fractions) and its label: the
-candidate orientation lies within 1 degree of some true grain
-(laue_candidate_labels_nearest), the start from which single-grain refinement
-reaches a grain (measured on the 1000-grain workload at the paper's fiducial
-noise with the paper's refinement cooling: about half of the candidates within
-1 degree of a grain end on it, 2% of those within 1-2 degrees, none beyond).
-At the densities of interest almost no random pair comes from one grain, and
-most candidates that refine to a grain come from pairs with one spot of it or
-none, so the label does not ask for a same-grain pair.  Half of the pairs are
-still drawn among same-grain spots (laue_pairs_same_grain), which supplies
-positives with the pair features of a consistent pair.  Every step runs in the
+features (14 from the pair, 2 cheap-support fractions) and its label (both
+spots from one true grain and the orientation within 2 degrees of it;
+laue_candidate_labels).  At the densities of interest almost no random pair
+comes from one grain, so half of the pairs are drawn among same-grain spots
+(laue_pairs_same_grain); their wrong plane hypotheses are negatives as well.
+(Labels by the nearest true grain, laue_candidate_labels_nearest, name the
+candidates that refinement brings to a grain, but at 1000 grains the features
+do not rank them: the network and the support features alone both score
+them at chance, the clutter hitting every support probe.)  Every step runs in the
 library: simulation, candidates, features, labels, and the network's
 forward, backward and Adam kernels, and the batches of each epoch
 (laue_mlp_train_epoch draws the seeded example order and gathers them).
@@ -22,13 +20,12 @@ import time
 
 import numpy as np
 
-from . import (Grains, adam_params, laue_candidate_labels_nearest, laue_candidate_support,
-               laue_candidates_generate, laue_mlp_forward, laue_mlp_train_epoch, laue_pairs_same_grain,
-               laue_simulate)
+from . import (Grains, adam_params, laue_candidate_labels, laue_candidate_support, laue_candidates_generate,
+               laue_mlp_forward, laue_mlp_train_epoch, laue_pairs_same_grain, laue_simulate)
 
 
 def sample_examples(geom, planes, truth, sigma_mm, distance, outlier_frac, seed, n_pairs_random,
-                    n_pairs_same, support_radius, max_deg=1.0):
+                    n_pairs_same, support_radius, max_deg=2.0):
     """Features [n, 16] and labels [n] (device FP32) of one simulated sample."""
     import torch
     obs = laue_simulate(geom, planes, truth, sigma_mm, distance, outlier_frac, seed)
@@ -39,7 +36,7 @@ def sample_examples(geom, planes, truth, sigma_mm, distance, outlier_frac, seed,
         if c["q"].shape[0] == 0:
             continue
         laue_candidate_support(geom, planes, obs, c, support_radius, planes.n)
-        lab, _, _ = laue_candidate_labels_nearest(c, truth, max_deg)
+        lab, _ = laue_candidate_labels(c, obs.grain, truth, max_deg)
         feats.append(c["feat"])
         labels.append(lab)
     if not feats:
