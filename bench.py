@@ -374,7 +374,7 @@ ZETA_TOL_PER_ROOT_SPOT = 1e-3
 
 
 def bench_index(laue, workload, n_pairs, learned_pairs, log, sobol_points=0, recipe="stages", max_candidates=None,
-                plain_max=None, train_examples=1_000_000):
+                plain_max=None, train_examples=1_000_000, spot_per_candidate=None):
     """Time to index from device-resident spots (laue_index): plain exhaustive
     scoring of the candidates of n_pairs spot pairs, against (learned_pairs >
     0) the learned proposal scoring the top 5% of the candidates of
@@ -382,7 +382,9 @@ def bench_index(laue, workload, n_pairs, learned_pairs, log, sobol_points=0, rec
     examples, and (sobol_points > 0)
     the paper's Sobol-grid starts over the cubic fundamental zone and the
     sample box.  max_candidates caps the candidates of both forms (the first
-    ones); plain_max caps the plain form's alone."""
+    ones); plain_max caps the plain form's alone; spot_per_candidate sizes the
+    SPOT matrix (entries per scored candidate) where the default guess would
+    not fit."""
     import torch
     import inputgen as ig
     from paper_2404_06478_amd import learned
@@ -421,6 +423,7 @@ def bench_index(laue, workload, n_pairs, learned_pairs, log, sobol_points=0, rec
             # dense samples keep nearly every start, each with thousands of
             # SPOT entries: size the SPOT matrix for the starts (64-bit offsets)
             cap = 8000 * pairs if obs.n * pairs > 1e11 else None
+            cap = spot_per_candidate * pairs if spot_per_candidate else cap
             par = laue.index_params(p, "sobol", max_candidates=pairs, n_obs=obs.n, n_planes=planes.n, lbar_cap=cap,
                                     score=score, em=em)
         else:
@@ -429,6 +432,7 @@ def bench_index(laue, workload, n_pairs, learned_pairs, log, sobol_points=0, rec
             # dense clutter keeps nearly every candidate, each with an entry for
             # most detected spots within reach: size the SPOT matrix for it
             cap = (8000 if p.n_grains <= 1000 else 32000) * n_sc if obs.n * n_sc > 1e11 else None
+            cap = spot_per_candidate * n_sc if spot_per_candidate else cap
             par = laue.index_params(p, mode, n_pairs=pairs, seed=1, mlp=net if mode == "learned" else None,
                                     support_radius=radius, n_obs=obs.n, n_planes=planes.n, max_candidates=mc,
                                     lbar_cap=cap, score=score, em=em)
@@ -444,7 +448,8 @@ def bench_index(laue, workload, n_pairs, learned_pairs, log, sobol_points=0, rec
                      "em_iterations": st["em"]["n_em_iter"], "em_sinkhorn_capped": st["em"]["not_converged"],
                      "em_cost_entries": st["em"]["cost_entries"],
                      "em_zeta": st["em"]["zeta"], "likelihood": st["em"]["objective"]["sem_objective"],
-                     "prototypes": st["n_prototypes"], "recall": r / len(q), "time_s": wall,
+                     "spot_entries": st["lbar_entries"], "prototypes": st["n_prototypes"], "recall": r / len(q),
+                     "time_s": wall,
                      "score_pairs": st["score_pairs"], "score_pairs_evaluated": st["score_pairs_evaluated"],
                      "score_pairs_refine": st["score_pairs_refine"],
                      "score_pairs_per_s": st["score_pairs"] / max(st["ms_score"] * 1e-3, 1e-12),
@@ -757,7 +762,7 @@ DEFAULT_INDEX_LINES = ("medium,pairs=8192,sobol=200000;"
 def parse_index_line(item):
     parts = [x.strip() for x in item.split(",") if x.strip()]
     o = {"pairs": 4096, "lpairs": None, "sobol": 0, "recipe": "stages", "cand": None, "pcand": None,
-         "examples": 1_000_000}
+         "examples": 1_000_000, "spot": None}
     for kv in parts[1:]:
         k, v = kv.split("=")
         if k not in o and k != "name":
@@ -799,7 +804,7 @@ def main():
                          "(plain form's spot pairs), lpairs (learned form's, default 8 x pairs; 0: no learned form), "
                          "sobol (Sobol points, "
                          "0: none), recipe (stages or paper), cand (candidate cap of both forms), pcand (plain "
-                         "form's cap), examples (training examples)")
+                         "form's cap), examples (training examples), spot (SPOT entries per scored candidate)")
     ap.add_argument("--index-limits", default="",
                     help="workloads of the EM-from-truth and selection diagnostics ('' to skip)")
     ap.add_argument("--tile", type=int, default=0, choices=[0, 1, 2],
@@ -954,7 +959,8 @@ def main():
             key = o.get("name", f"{wl}.{o['recipe']}")
             line["time_to_index"][key] = bench_index(
                 laue, wl, o["pairs"], o["lpairs"], log, sobol_points=o["sobol"], recipe=o["recipe"],
-                max_candidates=o["cand"], plain_max=o["pcand"], train_examples=o["examples"])
+                max_candidates=o["cand"], plain_max=o["pcand"], train_examples=o["examples"],
+                spot_per_candidate=o["spot"])
     if args.index_limits:
         import inputgen as ig
         line["index_limits"] = {wl: bench_index_limits(laue, ig.PRESETS[wl], log)
