@@ -662,12 +662,11 @@ size_t laue_spot_greedy_workspace_size(int32_t n_cand, int64_t n_rows);
  * adds the candidate of largest increment (lowest index on ties) until k_max
  * or no increment is left.  picks [k_max], gains [k_max] (device, FP64
  * increments Delta_k); *n_picked (HOST).  Synchronous.
- * laue_spot_greedy_workspace_size is the minimum; workspace beyond it (16
- * bytes per SPOT entry lets it start at once) holds copies of the entries that
- * can still add to an increment, compacted every 16 exact grid-wide steps when
- * they fit, so that later steps read fewer entries.  The picks do not depend
- * on it; increments differ from an uncompacted run by the rounding of their
- * FP64 sums only. */
+ * Increments computed at an earlier step bound the current ones from above
+ * (covers only rise): each step recomputes, grid-wide, only the candidates
+ * whose bound reaches the best exact increment, so the picks and increments
+ * are those of recomputing every increment at every step.  Workspace beyond
+ * laue_spot_greedy_workspace_size is not used. */
 int laue_spot_greedy(const int64_t *lbar_off, const int32_t *lbar_row, const float *lbar_val,
                      int32_t n_cand, int64_t n_rows, double phi, int32_t k_max, int32_t *picks,
                      double *gains, int32_t *n_picked, void *ws, size_t ws_bytes, void *stream);

@@ -595,8 +595,7 @@ def laue_spot_greedy(lbar_off, lbar_row, lbar_val, n_cand, n_rows, phi, k_max):
     import torch
     lib = require_native()
     dev = _dev()
-    # the minimum plus room for the live-entry buffers of the grid-wide steps
-    ws = _workspace(lib.laue_spot_greedy_workspace_size(int(n_cand), int(n_rows)) + 16 * int(lbar_row.numel()) + 4096)
+    ws = _workspace(lib.laue_spot_greedy_workspace_size(int(n_cand), int(n_rows)))
     picks = torch.zeros(max(int(k_max), 1), dtype=torch.int32, device=dev)
     gains = torch.zeros(max(int(k_max), 1), dtype=torch.float64, device=dev)
     npk = C.c_int32()

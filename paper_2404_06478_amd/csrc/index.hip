@@ -736,157 +736,137 @@ __global__ __launch_bounds__(64) void k_gain(const int64_t *__restrict__ off,
     if (threadIdx.x == 0) gain[c] = s;
 }
 
-// Lazy greedy: the same picks and gains as recomputing every gain at every
-// step.  A candidate's gain can only fall as rows are covered (cur only
-// rises), so a gain computed at an earlier step bounds it from above.  The 16
-// waves of the one workgroup each lead a residue class of candidates (c mod
-// 16) by (bound desc, index asc); the overall leader is the best class
-// leader.  If its bound was computed at this step it is the exact argmax and
-// is picked; otherwise every stale class leader is recomputed at once (each by
-// its wave, with k_gain's summation order, so the value is the same bit for
-// bit) and the leaders are sought again.  The loop ends after k picks or when
-// no bound is positive.
-constexpr int kGreedyWaves = 16;
+// Band steps of the greedy: the same picks and increments as recomputing every
+// increment at every step.  An increment can only fall as rows are covered
+// (cur only rises), so an increment computed at an earlier step bounds the
+// current one from above: ub[c] is such a bound, exact when stamp[c] is the
+// current step.  A step scans every unpicked candidate for the best exact
+// increment (lowest index on ties) and the largest stale bound S; when the
+// best exact increment is positive and above S it is the exact argmax and is
+// picked.  Otherwise the stale bounds at or above a threshold are recomputed
+// grid-wide and the scan repeats: first the threshold S (the candidates of the
+// largest bound), then the best exact increment so found, after which no stale
+// bound reaches the best exact increment and the third scan decides the step
+// (no positive exact increment: the selection ends).
+constexpr int kBandScanBlocks = 1024;
+constexpr int kBandRefreshWaves = 4096;
 
-__global__ __launch_bounds__(64 * kGreedyWaves) void k_lazy_greedy(const int64_t *__restrict__ off,
-                                                                   const int *__restrict__ row,
-                                                                   const float *__restrict__ val, float *cur,
-                                                                   uint8_t *picked, double *ub, int *stamp,
-                                                                   int n, int k, int *picks, double *pgain,
-                                                                   int *done, int max_rounds, int *stop) {
-    __shared__ double lv[kGreedyWaves];
-    __shared__ int li[kGreedyWaves];
-    __shared__ int top;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    for (int step = 0; step < k; ++step) {
-        int rounds = 0;
-        for (;;) {
-            // class leader of this wave
-            double best = 0.0;
-            int arg = -1;
-            for (int c = wave + kGreedyWaves * lane; c < n; c += 64 * kGreedyWaves) {
-                if (picked[c]) continue;
-                const double g = ub[c];
-                if (g > best || (g == best && arg >= 0 && g > 0.0 && c < arg)) {
-                    best = g;
-                    arg = c;
-                }
-            }
-#pragma unroll
-            for (int o = 32; o > 0; o >>= 1) {
-                const double ob = __shfl_xor(best, o, 64);
-                const int oa = __shfl_xor(arg, o, 64);
-                if (ob > best || (ob == best && oa >= 0 && (arg < 0 || oa < arg))) {
-                    best = ob;
-                    arg = oa;
-                }
-            }
-            if (lane == 0) {
-                lv[wave] = best;
-                li[wave] = arg;
-            }
-            __syncthreads();
-            if (threadIdx.x == 0) {
-                double b = 0.0;
-                int a = -1;
-                for (int w = 0; w < kGreedyWaves; ++w)
-                    if (li[w] >= 0 && (lv[w] > b || (lv[w] == b && (a < 0 || li[w] < a)))) {
-                        b = lv[w];
-                        a = li[w];
-                    }
-                top = (a >= 0 && b > 0.0) ? a : -1;
-            }
-            __syncthreads();
-            const int c = top;
-            if (c < 0) {
-                if (threadIdx.x == 0) *done = 1;
-                return;
-            }
-            if (stamp[c] == step) {
-                for (int64_t e = off[c] + threadIdx.x; e < off[c + 1]; e += 64 * kGreedyWaves)
-                    cur[row[e]] = fmaxf(cur[row[e]], val[e]);
-                if (threadIdx.x == 0) {
-                    picked[c] = 1;
-                    picks[step] = c;
-                    pgain[step] = ub[c];
-                }
-                __threadfence_block();
-                __syncthreads();
-                break;
-            }
-            // a step that needs many refresh rounds hands the rest of the
-            // selection to the grid-wide exact steps (same picks)
-            if (++rounds > max_rounds) {
-                if (threadIdx.x == 0) *stop = step;
-                return;
-            }
-            // refresh every stale class leader with a positive bound
-            const int mine = li[wave];
-            if (mine >= 0 && lv[wave] > 0.0 && stamp[mine] != step) {
-                const double sum = wave_sum(lane_gain(off[mine], off[mine + 1], lane, row, val, cur));
-                if (lane == 0) {
-                    ub[mine] = sum;
-                    stamp[mine] = step;
-                }
-            }
-            __threadfence_block();
-            __syncthreads();
-        }
+struct BandState {
+    double thr;    // recompute stale bounds >= thr (and > 0)
+    int decided;   // last step whose pick is made
+};
+
+__global__ void k_band_init(BandState *st) {
+    st->thr = 0.0;
+    st->decided = -1;
+}
+
+// (value, index) maximum, the lower index on equal values; index -1 is empty.
+__device__ __forceinline__ void band_best(double &b, int &bi, double ob, int oi) {
+    if (oi >= 0 && (bi < 0 || ob > b || (ob == b && oi < bi))) {
+        b = ob;
+        bi = oi;
     }
 }
 
-// One exact greedy step from exact gains (k_gain at this step): the largest
-// positive gain, lowest index on ties, is picked and its rows covered; no
-// positive gain ends the selection.  One workgroup of 1024 threads.
-__global__ __launch_bounds__(1024) void k_greedy_pick(const int64_t *__restrict__ off,
-                                                      const int *__restrict__ row,
-                                                      const float *__restrict__ val, float *cur,
-                                                      uint8_t *picked, const double *__restrict__ gain, int n,
-                                                      int step, int *picks, double *pgain, int *done) {
-    __shared__ double lv[16];
-    __shared__ int li[16];
-    __shared__ int top;
-    if (*done) return;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    double best = 0.0;
-    int arg = -1;
-    for (int c = threadIdx.x; c < n; c += 1024) {
-        const double g = gain[c];
-        if (g > best) {            // c ascends: the first of equal gains stays
-            best = g;
-            arg = c;
+// Per block: best exact (ub, index) at this step and the largest stale bound.
+__global__ __launch_bounds__(256) void k_band_scan(const uint8_t *__restrict__ picked, const double *__restrict__ ub,
+                                                   const int *__restrict__ stamp, int n, int step,
+                                                   const BandState *__restrict__ st, const int *__restrict__ done,
+                                                   double *__restrict__ pb, int *__restrict__ pi,
+                                                   double *__restrict__ ps) {
+    __shared__ double lb[4], ls[4];
+    __shared__ int li[4];
+    if (*done || st->decided == step) return;
+    double b = -1.0, sm = -1.0;
+    int bi = -1;
+    for (int c = blockIdx.x * 256 + threadIdx.x; c < n; c += gridDim.x * 256) {
+        if (picked[c]) continue;
+        const double g = ub[c];
+        if (stamp[c] == step) {
+            if (bi < 0 || g > b) {   // c ascends: the first of equal values stays
+                b = g;
+                bi = c;
+            }
+        } else {
+            sm = fmax(sm, g);
         }
     }
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
-        const double ob = __shfl_xor(best, o, 64);
-        const int oa = __shfl_xor(arg, o, 64);
-        if (oa >= 0 && (arg < 0 || ob > best || (ob == best && oa < arg))) {
-            best = ob;
-            arg = oa;
-        }
+        const double ob = __shfl_xor(b, o, 64);
+        const int oi = __shfl_xor(bi, o, 64);
+        band_best(b, bi, ob, oi);
+        sm = fmax(sm, __shfl_xor(sm, o, 64));
     }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     if (lane == 0) {
-        lv[wave] = best;
-        li[wave] = arg;
+        lb[wave] = b;
+        li[wave] = bi;
+        ls[wave] = sm;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        double b = 0.0;
-        int a = -1;
-        for (int w = 0; w < 16; ++w)
-            if (li[w] >= 0 && (a < 0 || lv[w] > b || (lv[w] == b && li[w] < a))) {
-                b = lv[w];
-                a = li[w];
-            }
-        top = a;
-        if (a < 0) {
-            *done = 1;
-        } else {
-            picked[a] = 1;
-            picks[step] = a;
-            pgain[step] = b;
+        for (int w = 1; w < 4; ++w) {
+            band_best(b, bi, lb[w], li[w]);
+            sm = fmax(sm, ls[w]);
         }
+        pb[blockIdx.x] = b;
+        pi[blockIdx.x] = bi;
+        ps[blockIdx.x] = sm;
+    }
+}
+
+// Reduce the scan's nb partials and decide the step (phase 0, 1, 2 as above);
+// a pick covers its rows.  One workgroup of 1024 threads.
+__global__ __launch_bounds__(1024) void k_band_decide(int phase, int step, int nb, const double *__restrict__ pb,
+                                                      const int *__restrict__ pi, const double *__restrict__ ps,
+                                                      BandState *st, int *done, const int64_t *__restrict__ off,
+                                                      const int *__restrict__ row, const float *__restrict__ val,
+                                                      float *cur, uint8_t *picked, int *picks, double *pgain) {
+    __shared__ double lb[16], ls[16];
+    __shared__ int li[16];
+    __shared__ int top;
+    if (*done || st->decided == step) return;
+    double b = -1.0, sm = -1.0;
+    int bi = -1;
+    if (static_cast<int>(threadIdx.x) < nb) {
+        b = pb[threadIdx.x];
+        bi = pi[threadIdx.x];
+        sm = ps[threadIdx.x];
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const double ob = __shfl_xor(b, o, 64);
+        const int oi = __shfl_xor(bi, o, 64);
+        band_best(b, bi, ob, oi);
+        sm = fmax(sm, __shfl_xor(sm, o, 64));
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0) {
+        lb[wave] = b;
+        li[wave] = bi;
+        ls[wave] = sm;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < 16; ++w) {
+            band_best(b, bi, lb[w], li[w]);
+            sm = fmax(sm, ls[w]);
+        }
+        int pick = -1;
+        if (bi >= 0 && b > 0.0 && b > sm) {
+            pick = bi;
+            picked[bi] = 1;
+            picks[step] = bi;
+            pgain[step] = b;
+            st->decided = step;
+        } else if (phase == 2 || (phase == 0 && !(sm > 0.0))) {
+            *done = 1;       // no positive increment is left
+        } else {
+            st->thr = phase == 0 ? sm : (bi >= 0 && b > 0.0 ? b : 0.0);
+        }
+        top = pick;
     }
     __syncthreads();
     const int c = top;
@@ -895,58 +875,37 @@ __global__ __launch_bounds__(1024) void k_greedy_pick(const int64_t *__restrict_
     for (int64_t e = off[c] + threadIdx.x; e < off[c + 1]; e += 1024) cur[row[e]] = fmaxf(cur[row[e]], val[e]);
 }
 
-__global__ void k_set_i64(int64_t *p, int64_t v) { *p = v; }
-
-// Live SPOT entries: an entry of an unpicked candidate whose value exceeds
-// its row's current cover.  Every other entry adds exactly 0 to every later
-// increment (covers only rise, picked candidates are never scored again), so
-// dropping it changes no increment beyond the order of its FP64 additions.
-// One wave per candidate: cnt[c] = its live entries.
-__global__ __launch_bounds__(64) void k_live_count(const int64_t *__restrict__ off, const int *__restrict__ row,
-                                                   const float *__restrict__ val, const float *__restrict__ cur,
-                                                   const uint8_t *__restrict__ picked, int64_t *__restrict__ cnt,
-                                                   int n) {
-    const int c = blockIdx.x;
-    if (c >= n) return;
-    int64_t k = 0;
-    if (!picked[c])
-        for (int64_t e = off[c] + threadIdx.x; e < off[c + 1]; e += 64) k += val[e] > cur[row[e]] ? 1 : 0;
-    for (int o = 32; o > 0; o >>= 1) k += __shfl_xor(k, o, 64);
-    if (threadIdx.x == 0) cnt[c] = k;
-}
-
-// The live entries of candidate c, in their order, to [noff[c], noff[c+1]) of
-// the other buffer (one wave per candidate, ballot and rank per 64 entries).
-__global__ __launch_bounds__(64) void k_live_write(const int64_t *__restrict__ off, const int *__restrict__ row,
-                                                   const float *__restrict__ val, const float *__restrict__ cur,
-                                                   const uint8_t *__restrict__ picked,
-                                                   const int64_t *__restrict__ noff, int *__restrict__ nrow,
-                                                   float *__restrict__ nval, int n) {
-    const int c = blockIdx.x;
-    if (c >= n || picked[c]) return;
+// Recompute every stale bound at or above the threshold (and positive), one
+// wave per such candidate with k_gain's summation order.
+__global__ __launch_bounds__(64) void k_band_refresh(const int64_t *__restrict__ off, const int *__restrict__ row,
+                                                     const float *__restrict__ val, const float *__restrict__ cur,
+                                                     const uint8_t *__restrict__ picked, double *ub, int *stamp,
+                                                     int n, int step, const BandState *__restrict__ st,
+                                                     const int *__restrict__ done) {
+    if (*done || st->decided == step) return;
+    const double thr = st->thr;
     const int lane = threadIdx.x;
-    int64_t pos = noff[c];
-    for (int64_t e0 = off[c]; e0 < off[c + 1]; e0 += 64) {
-        const int64_t e = e0 + lane;
-        int r = 0;
-        float v = 0.0f;
-        bool live = false;
-        if (e < off[c + 1]) {
-            r = row[e];
-            v = val[e];
-            live = v > cur[r];
+    for (int c0 = blockIdx.x * 64; c0 < n; c0 += gridDim.x * 64) {
+        const int c = c0 + lane;
+        bool q = false;
+        if (c < n && !picked[c] && stamp[c] != step) {
+            const double g = ub[c];
+            q = g > 0.0 && g >= thr;
         }
-        const unsigned long long m = __ballot(live);
-        const int rank = __builtin_amdgcn_mbcnt_hi(static_cast<unsigned>(m >> 32),
-                                                   __builtin_amdgcn_mbcnt_lo(static_cast<unsigned>(m), 0));
-        if (live) {
-            nrow[pos + rank] = r;
-            nval[pos + rank] = v;
+        unsigned long long m = __ballot(q);
+        while (m) {
+            const int cc = c0 + __builtin_ctzll(m);
+            m &= m - 1;
+            const double s = wave_sum(lane_gain(off[cc], off[cc + 1], lane, row, val, cur));
+            if (lane == 0) {
+                ub[cc] = s;
+                stamp[cc] = step;
+            }
         }
-        pos += __popcll(m);
     }
 }
 
+__global__ void k_set_i64(int64_t *p, int64_t v) { *p = v; }
 // Same-block (detected, model) pairs of one batch, added to *acc: over the
 // (block, candidate) slots, model spots of the slot times detected spots of
 // its block; keep (may be NULL) limits the sum to kept candidates.
@@ -1524,47 +1483,13 @@ namespace {
 struct GreedyWs {
     float *cur;
     uint8_t *picked;
-    double *gain;   // upper bounds of the gains (exact at their stamp)
+    double *gain;   // upper bounds of the increments (exact at their stamp)
     int *stamp;
     int *done;
-    int *stop;      // step at which the lazy selection handed over (-1: none)
+    double *pb, *ps;   // the band scan's per-block partials
+    int *pi;
+    BandState *st;
 };
-// Live-entry buffers of the grid-wide steps, carved from the workspace
-// beyond the minimum (none when it is too small to be useful).
-constexpr int kCompactEvery = 16;
-struct GreedyLive {
-    int64_t *off[2];
-    int64_t *cnt;
-    void *tmp;
-    size_t tmp_bytes;
-    int *row[2];
-    float *val[2];
-    int64_t cap;      // entries each buffer holds
-};
-bool carve_live(char *base, size_t bytes, int n, GreedyLive *lv) {
-    if (n < 1) return false;
-    size_t tmp = 0;
-    if (hipcub::DeviceScan::InclusiveSum(nullptr, tmp, static_cast<int64_t *>(nullptr),
-                                         static_cast<int64_t *>(nullptr), n) != hipSuccess)
-        return false;
-    Carver cv(base);
-    lv->off[0] = cv.take<int64_t>(n + 1);
-    lv->off[1] = cv.take<int64_t>(n + 1);
-    lv->cnt = cv.take<int64_t>(n);
-    lv->tmp = cv.take<char>(static_cast<int64_t>(tmp));
-    lv->tmp_bytes = tmp;
-    const size_t fixed = cv.size() + 4 * 256;
-    if (bytes <= fixed) return false;
-    const int64_t cap = static_cast<int64_t>((bytes - fixed) / 16);
-    if (cap < 65536) return false;
-    lv->row[0] = cv.take<int>(cap);
-    lv->val[0] = cv.take<float>(cap);
-    lv->row[1] = cv.take<int>(cap);
-    lv->val[1] = cv.take<float>(cap);
-    if (cv.size() > bytes) return false;
-    lv->cap = cap;
-    return true;
-}
 
 size_t carve_greedy(Carver &cv, GreedyWs &w, int n_cand, int64_t n_rows) {
     w.cur = cv.take<float>(std::max<int64_t>(n_rows, 1));
@@ -1572,7 +1497,10 @@ size_t carve_greedy(Carver &cv, GreedyWs &w, int n_cand, int64_t n_rows) {
     w.gain = cv.take<double>(std::max(n_cand, 1));
     w.stamp = cv.take<int>(std::max(n_cand, 1));
     w.done = cv.take<int>(1);
-    w.stop = cv.take<int>(1);
+    w.pb = cv.take<double>(kBandScanBlocks);
+    w.ps = cv.take<double>(kBandScanBlocks);
+    w.pi = cv.take<int>(kBandScanBlocks);
+    w.st = cv.take<BandState>(1);
     return cv.size();
 }
 }  // namespace
@@ -1605,62 +1533,30 @@ extern "C" int laue_spot_greedy(const int64_t *lbar_off, const int32_t *lbar_row
     k_fill_u8<<<(n_cand + 255) / 256, 256, 0, s>>>(w.picked, n_cand, 0);
     k_fill_i<<<1, 64, 0, s>>>(w.done, 1, 0);
     k_fill_i<<<(k_max + 255) / 256, 256, 0, s>>>(picks, k_max, -1);
+    k_band_init<<<1, 1, 0, s>>>(w.st);
     LAUE_CHECK_HIP(hipGetLastError());
     const int K = std::min(k_max, n_cand);
-    // every gain once (exact for step 0), then the lazy steps
+    // every increment once: exact at step 0
     k_gain<<<n_cand, 64, 0, s>>>(lbar_off, lbar_row, lbar_val, w.cur, w.picked, w.gain, w.done, n_cand);
     k_fill_i<<<(n_cand + 255) / 256, 256, 0, s>>>(w.stamp, n_cand, 0);
-    k_fill_i<<<1, 64, 0, s>>>(w.stop, 1, -1);
-    // the lazy selection runs on one workgroup; a step that needs more
-    // refresh rounds than about one grid-wide recomputation of every gain
-    // costs hands the remaining steps to exact grid-wide steps
-    const int max_rounds = std::max(4, n_cand / 4096);
-    k_lazy_greedy<<<1, 64 * kGreedyWaves, 0, s>>>(lbar_off, lbar_row, lbar_val, w.cur, w.picked, w.gain, w.stamp,
-                                                  n_cand, K, picks, gains, w.done, max_rounds, w.stop);
-    LAUE_CHECK_HIP(hipGetLastError());
-    int stop = -1;
-    LAUE_CHECK_HIP(hipMemcpyAsync(&stop, w.stop, sizeof(int), hipMemcpyDeviceToHost, s));
-    LAUE_CHECK_HIP(hipStreamSynchronize(s));
-    if (stop >= 0) {
-        // grid-wide exact steps.  Workspace beyond the minimum holds two
-        // buffers of live entries: every kCompactEvery steps the live entries
-        // are counted and, when they fit, compacted into the other buffer, so
-        // later steps stream only entries that can still add to an increment.
-        const size_t spare = ws_bytes > need ? ws_bytes - need : 0;
-        GreedyLive lv{};
-        const bool compact = carve_live(static_cast<char *>(ws) + need, spare, n_cand, &lv);
-        const int64_t *off = lbar_off;
-        const int *row = lbar_row;
-        const float *val = lbar_val;
-        int nb = 0;
-        for (int step = stop; step < K; ++step) {
-            if (compact && (step - stop) % kCompactEvery == 0) {
-                int64_t *noff = lv.off[nb];
-                k_live_count<<<n_cand, 64, 0, s>>>(off, row, val, w.cur, w.picked, lv.cnt, n_cand);
-                k_set_i64<<<1, 1, 0, s>>>(noff, 0);
-                size_t tb = lv.tmp_bytes;
-                LAUE_CHECK_HIP(hipcub::DeviceScan::InclusiveSum(lv.tmp, tb, lv.cnt, noff + 1, n_cand, s));
-                int64_t total = 0;
-                int dn = 0;
-                LAUE_CHECK_HIP(hipMemcpyAsync(&total, noff + n_cand, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-                LAUE_CHECK_HIP(hipMemcpyAsync(&dn, w.done, sizeof(int), hipMemcpyDeviceToHost, s));
-                LAUE_CHECK_HIP(hipStreamSynchronize(s));
-                if (dn) break;
-                if (total <= lv.cap) {
-                    k_live_write<<<n_cand, 64, 0, s>>>(off, row, val, w.cur, w.picked, noff, lv.row[nb], lv.val[nb],
-                                                       n_cand);
-                    off = noff;
-                    row = lv.row[nb];
-                    val = lv.val[nb];
-                    nb ^= 1;
-                    log_line("greedy: step %d, %lld live SPOT entries compacted", step, static_cast<long long>(total));
-                }
-            }
-            k_gain<<<n_cand, 64, 0, s>>>(off, row, val, w.cur, w.picked, w.gain, w.done, n_cand);
-            k_greedy_pick<<<1, 1024, 0, s>>>(off, row, val, w.cur, w.picked, w.gain, n_cand, step, picks, gains,
-                                             w.done);
+    const int nb = std::min(kBandScanBlocks, (n_cand + 255) / 256);
+    const int nr = std::min(kBandRefreshWaves, (n_cand + 63) / 64);
+    for (int step = 0; step < K; ++step) {
+        for (int phase = 0; phase < 3; ++phase) {
+            if (phase > 0)
+                k_band_refresh<<<nr, 64, 0, s>>>(lbar_off, lbar_row, lbar_val, w.cur, w.picked, w.gain, w.stamp,
+                                                 n_cand, step, w.st, w.done);
+            k_band_scan<<<nb, 256, 0, s>>>(w.picked, w.gain, w.stamp, n_cand, step, w.st, w.done, w.pb, w.pi, w.ps);
+            k_band_decide<<<1, 1024, 0, s>>>(phase, step, nb, w.pb, w.pi, w.ps, w.st, w.done, lbar_off, lbar_row,
+                                             lbar_val, w.cur, w.picked, picks, gains);
         }
         LAUE_CHECK_HIP(hipGetLastError());
+        if (step % 64 == 63 && step + 1 < K) {   // stop launching once the selection has ended
+            int dn = 0;
+            LAUE_CHECK_HIP(hipMemcpyAsync(&dn, w.done, sizeof(int), hipMemcpyDeviceToHost, s));
+            LAUE_CHECK_HIP(hipStreamSynchronize(s));
+            if (dn) break;
+        }
     }
     std::vector<int> hp(K);
     LAUE_CHECK_HIP(hipMemcpyAsync(hp.data(), picks, K * sizeof(int), hipMemcpyDeviceToHost, s));

@@ -58,10 +58,7 @@ size_t scratch_size(const laue_geometry *g, int n_planes, int64_t n_obs, const l
     }
     if (p->mode == LAUE_INDEX_SOBOL) s = std::max(s, laue_sobol_workspace_size(p->max_candidates));
     s = std::max(s, laue_score_workspace_size(g, n_obs, &p->score));
-    // the greedy's minimum plus room for its live-entry buffers (16 bytes per
-    // entry, up to 2^30 entries: a smaller room only delays the compaction)
-    s = std::max(s, laue_spot_greedy_workspace_size(static_cast<int32_t>(n_scored_max(p)), n_obs) +
-                        16 * static_cast<size_t>(std::min<int64_t>(p->lbar_cap, int64_t(1) << 30)));
+    s = std::max(s, laue_spot_greedy_workspace_size(static_cast<int32_t>(n_scored_max(p)), n_obs));
     s = std::max(s, laue_forward_workspace_size(g, n_planes, p->k_max));
     s = std::max(s, laue_sinkhorn_workspace_size(g, n_obs, p->max_model_spots, p->k_max));
     if (p->em.ot.rho > 0 || (p->em.eps_cool > 0.0 && !(p->em.eps_start > 0.0))) {

@@ -125,10 +125,10 @@ def test_greedy_matches_oracle(gpu_lib):
     assert single.n_prototypes(gg.cpu().numpy()) == single.n_prototypes(gains)
 
 
-def test_lazy_greedy_matches_oracle_many_candidates(gpu_lib):
+def test_band_greedy_matches_oracle_many_candidates(gpu_lib):
     """Hundreds of overlapping candidates, exact duplicates among them (ties
-    go to the lowest index): the lazy greedy (stale gains as upper bounds)
-    picks exactly what the plain greedy picks, with the same gains."""
+    go to the lowest index): the band steps (stale increments as upper
+    bounds) pick exactly what the plain greedy picks, with the same gains."""
     laue = gpu_lib
     rng = np.random.default_rng(11)
     n_rows, phi = 3000, -4.5
@@ -154,9 +154,9 @@ def test_lazy_greedy_matches_oracle_many_candidates(gpu_lib):
 
 def test_greedy_heavy_overlap_matches_oracle(gpu_lib):
     """Every candidate covers a third of the rows, as under dense clutter: each
-    pick lowers almost every other gain, so the lazy selection hands over to
-    the grid-wide exact steps after the first picks; the picks and gains stay
-    those of the plain greedy."""
+    pick lowers almost every other gain, so most bounds go stale at every step
+    and the band steps recompute many of them; the picks and gains stay those
+    of the plain greedy."""
     laue = gpu_lib
     rng = np.random.default_rng(5)
     n_rows, n_cand, phi, k_max = 2000, 400, -4.5, 120
@@ -177,11 +177,11 @@ def test_greedy_heavy_overlap_matches_oracle(gpu_lib):
     assert np.allclose(gg.cpu().numpy(), gains, rtol=1e-9, atol=1e-9)
 
 
-def test_greedy_ends_early_after_hand_over(gpu_lib):
+def test_greedy_ends_early(gpu_lib):
     """Two hundred copies of one column and three small disjoint columns: after
-    the first pick every copy's increment is zero, the lazy selection hands
-    over while refreshing the copies, and the grid-wide steps pick the three
-    others and stop with no positive increment left (fewer picks than k_max)."""
+    the first pick every copy's increment is zero (their stale bounds are
+    recomputed to 0), the three others are picked and the selection stops with
+    no positive increment left (fewer picks than k_max)."""
     laue = gpu_lib
     rng = np.random.default_rng(9)
     n_rows, phi = 1200, -4.5
@@ -201,3 +201,54 @@ def test_greedy_ends_early_after_hand_over(gpu_lib):
                                    torch.tensor(vals, device=dev), len(cols), n_rows, phi, 50)
     assert gp.cpu().tolist() == picks
     assert np.allclose(gg.cpu().numpy(), gains, rtol=1e-9, atol=1e-9)
+
+
+def test_greedy_many_candidates_exact_increments(gpu_lib):
+    """300,000 small candidates in clusters of shared rows (more than one pass
+    of the scan and recompute grids), exact duplicates among them, values on a
+    1/8 grid so that every increment is exact in any summation order: each
+    pick is the lowest-index candidate of largest increment, the increments
+    recomputed here from the definition of the set function at every step."""
+    laue = gpu_lib
+    rng = np.random.default_rng(21)
+    n_rows, n_cand, phi, k_max = 20000, 300_000, -4.5, 40
+    centre = rng.integers(0, n_rows, size=n_cand)
+    cnt = rng.integers(1, 9, size=n_cand)
+    off = np.concatenate([[0], np.cumsum(cnt)])
+    seg = np.repeat(np.arange(n_cand), cnt)
+    rows = np.clip(centre[seg] + rng.integers(-40, 40, size=off[-1]), 0, n_rows - 1)
+    vals = phi + rng.integers(1, 33, size=off[-1]) / 8.0
+    for c in rng.choice(n_cand - 1, size=2000, replace=False):    # duplicate c into c + 1
+        if cnt[c] == cnt[c + 1]:
+            rows[off[c + 1]:off[c + 2]] = rows[off[c]:off[c + 1]]
+            vals[off[c + 1]:off[c + 2]] = vals[off[c]:off[c + 1]]
+    # a candidate holds at most one entry per row: keep the first of repeats
+    keep = np.ones(off[-1], bool)
+    for c in range(n_cand):
+        r = rows[off[c]:off[c + 1]]
+        _, first = np.unique(r, return_index=True)
+        k = np.zeros(len(r), bool)
+        k[first] = True
+        keep[off[c]:off[c + 1]] = k
+    rows, vals, seg = rows[keep], vals[keep], seg[keep]
+    cnt = np.bincount(seg, minlength=n_cand)
+    off = np.concatenate([[0], np.cumsum(cnt)])
+    cur = np.full(n_rows, phi)
+    picked = np.zeros(n_cand, bool)
+    picks, gains = [], []
+    for _ in range(k_max):
+        inc = np.bincount(seg, weights=np.maximum(0.0, vals - cur[rows]), minlength=n_cand)
+        inc[picked] = -1.0
+        c = int(np.argmax(inc))                 # the first of equal maxima
+        if inc[c] <= 0.0:
+            break
+        picks.append(c)
+        gains.append(inc[c])
+        picked[c] = True
+        r = rows[off[c]:off[c + 1]]
+        cur[r] = np.maximum(cur[r], vals[off[c]:off[c + 1]])
+    dev = torch.device("cuda")
+    gp, gg = laue.laue_spot_greedy(torch.tensor(off, device=dev), torch.tensor(rows.astype(np.int32), device=dev),
+                                   torch.tensor(vals.astype(np.float32), device=dev), n_cand, n_rows, phi, k_max)
+    assert gp.cpu().tolist() == picks
+    assert np.array_equal(gg.cpu().numpy(), np.array(gains))
