@@ -32,6 +32,10 @@ import time
 
 import numpy as np
 
+# the library's progress lines (candidates scored, greedy, EM) on stderr, so
+# that the index lines' long calls report as they go
+os.environ.setdefault("LAUE_LOG", "1")
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -383,7 +387,7 @@ def bench_index(laue, workload, n_pairs, learned_pairs, log, sobol_points=0, rec
     the paper's Sobol-grid starts over the cubic fundamental zone and the
     sample box.  max_candidates caps the candidates of both forms (the first
     ones); plain_max caps the plain form's alone; spot_per_candidate sizes the
-    SPOT matrix (entries per scored candidate) where the default guess would
+    Sobol form's SPOT matrix (entries per start) where the default guess would
     not fit."""
     import torch
     import inputgen as ig
@@ -432,7 +436,6 @@ def bench_index(laue, workload, n_pairs, learned_pairs, log, sobol_points=0, rec
             # dense clutter keeps nearly every candidate, each with an entry for
             # most detected spots within reach: size the SPOT matrix for it
             cap = (8000 if p.n_grains <= 1000 else 32000) * n_sc if obs.n * n_sc > 1e11 else None
-            cap = spot_per_candidate * n_sc if spot_per_candidate else cap
             par = laue.index_params(p, mode, n_pairs=pairs, seed=1, mlp=net if mode == "learned" else None,
                                     support_radius=radius, n_obs=obs.n, n_planes=planes.n, max_candidates=mc,
                                     lbar_cap=cap, score=score, em=em)
@@ -747,15 +750,15 @@ def bench_forward(laue, n_grains, log):
 # spot-pair candidates: the network ranks them and the top 5% are scored,
 # against plain scoring of all 2^20), on the stage schedule; the same sample
 # at the paper's fiducial noise with the paper's annealing recipe, the same
-# 2^20 candidates both ways, plain scoring of 2048 pairs' candidates (the
-# recall the learned form reaches) and the paper's 500,000 Sobol-grid starts;
-# the 2000-grain stress workload (the
-# network ranks 2^20 candidates and scores the top 5%; plain scoring of the
-# first 2^16).
+# 100 grains; 1000 grains at 70% outliers (2^20 candidates both ways); 1000
+# grains at the paper's fiducial noise with the paper's recipe (plain scoring
+# of 2048 pairs' candidates, about the recall the learned form reaches from
+# the top 5% of 2^20, and 3,000,000 Sobol-grid starts); the 2000-grain stress
+# workload (the network ranks 2^20 candidates and scores the top 5%; plain
+# scoring of the first 2^16).
 DEFAULT_INDEX_LINES = ("medium,pairs=8192,sobol=200000;"
                        "learned,pairs=32768,lpairs=32768,cand=1048576;"
-                       "learned_fiducial,pairs=24576,lpairs=24576,cand=1048576,recipe=paper;"
-                       "learned_fiducial,pairs=2048,lpairs=0,sobol=500000,recipe=paper,name=learned_fiducial.paper_2048;"
+                       "learned_fiducial,pairs=2048,lpairs=24576,cand=1048576,sobol=3000000,spot=64,recipe=paper;"
                        "stress,pairs=32768,lpairs=32768,cand=1048576,pcand=65536")
 
 
@@ -804,7 +807,7 @@ def main():
                          "(plain form's spot pairs), lpairs (learned form's, default 8 x pairs; 0: no learned form), "
                          "sobol (Sobol points, "
                          "0: none), recipe (stages or paper), cand (candidate cap of both forms), pcand (plain "
-                         "form's cap), examples (training examples), spot (SPOT entries per scored candidate)")
+                         "form's cap), examples (training examples), spot (SPOT entries per Sobol start)")
     ap.add_argument("--index-limits", default="",
                     help="workloads of the EM-from-truth and selection diagnostics ('' to skip)")
     ap.add_argument("--tile", type=int, default=0, choices=[0, 1, 2],

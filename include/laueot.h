@@ -612,9 +612,11 @@ typedef struct laue_score_params {
     /* refinement passes: 0 skips only the pairs whose plan term is 0 in FP32
      * (the result is that of evaluating every pair); d > 0 also skips pairs
      * whose term exp(-c / eps) is below 2^-d times the outlier bin's
-     * exp(-c_out / eps), i.e. below 2^-d of the row's softmax normaliser: each
-     * such row weight is < 2^-d, and the row normalisers change by less than
-     * 64 x 2^-d relative (the binding's default: d = 40) */
+     * exp(-c_out / eps), i.e. below 2^-d of the row's softmax normaliser
+     * (which starts at the bin term and only grows): each such row weight is
+     * < 2^-d, and for d >= 26 the term is below a quarter of the normaliser's
+     * FP32 ulp, so the normalisers are those of evaluating every pair (the
+     * binding's default: d = 26) */
     double drop_log2;
 } laue_score_params;
 

@@ -543,12 +543,13 @@ def laue_candidates_generate(geom, planes, obs, n_pairs, seed, delta_deg=1.5, ca
 
 
 def score_params(sigma_mm, distance, c_out, f_out=0.1, k_refine=8, k_gn=1, mu_rel=1e-9, chunk=4096,
-                 max_spots_per_cand=4096, eps_start=None, eps_end=None, eps_cool=0.0, drop_log2=40.0):
+                 max_spots_per_cand=4096, eps_start=None, eps_end=None, eps_cool=0.0, drop_log2=26.0):
     """Single-grain refinement and scoring parameters.  Temperatures are given
     in units of sigma_mm^2 by the defaults (30 -> 1.11, the oracle's reading)
     or explicitly in mm^2; eps_cool > 0 selects Alg. SingleLaueOT's cooling
     eps_start eps_cool^k; drop_log2 (0: FP32-zero terms only) sets which far
-    pairs the refinement passes skip."""
+    pairs the refinement passes skip (26: terms too small to change an FP32
+    row normaliser)."""
     p = _abi.laue_score_params()
     p.sigma_mm, p.distance, p.c_out, p.f_out = float(sigma_mm), float(distance), float(c_out), float(f_out)
     p.eps_start = float(30.0 * sigma_mm ** 2 if eps_start is None else eps_start)

@@ -233,6 +233,13 @@ __device__ __forceinline__ float wave_min_f(float v) {
 
 constexpr int kSup = 16;    // 64-row chunks of detected spots held per lane
 
+// Whether some lane's detected spot p lies within R (R2 = R^2) of the model
+// spot s on the detector (wave-uniform).
+__device__ __forceinline__ bool reaches(float p1, float p2, float s1, float s2, float R2) {
+    const float dy = p1 - s1, dz = p2 - s2;
+    return __any(fmaf(dz, dz, dy * dy) < R2);
+}
+
 // Cell index of the detected spots for the refinement passes: each block's
 // spots sorted (stably) into a kCellG x kCellG grid over their bounding box,
 // so that a pass reads only the cells within reach of a candidate's model
@@ -509,11 +516,14 @@ __global__ __launch_bounds__(64) void k_single_acc(SlotArgs A, float K, float bi
             p2[u] = rv ? A.P2s[row] : 0.0f;
             iz[u] = bin_e;
         }
+        // a 64-row chunk none of whose rows lies within R_j of s_j adds
+        // terms below the threshold only: it skips model spot j
         for (int j = 0; j < nc; ++j) {
             const float4 x0 = cst[j], x1 = cst[64 + j];
+            const float R2 = rad2[j];
 #pragma unroll
             for (int u = 0; u < kSup; ++u)
-                if (64 * u < nrow)
+                if (64 * u < nrow && reaches(p1[u], p2[u], x0.x, x0.y, R2))
                     iz[u] += fast_exp2(entry_exponent(p1[u], p2[u], x0.x, x0.y, x0.z, x0.w, x1.x, x1.y, K, 0.0f));
         }
 #pragma unroll
@@ -522,6 +532,7 @@ __global__ __launch_bounds__(64) void k_single_acc(SlotArgs A, float K, float bi
             const float4 x0 = cst[j], x1 = cst[64 + j], x2 = cst[128 + j];
             const Col8 cE{x0.x, x0.y, x0.z, x0.w, x1.x, x1.y, x1.z, 0.0f};
             const float vl = x1.w, rn = x2.x, r1 = x2.y, r2 = x2.z;
+            const float R2 = rad2[j];
             float a[kStat];
 #pragma unroll
             for (int q = 0; q < kStat; ++q) a[q] = 0.0f;
@@ -529,13 +540,14 @@ __global__ __launch_bounds__(64) void k_single_acc(SlotArgs A, float K, float bi
             if (SAME) {
 #pragma unroll
                 for (int u = 0; u < kSup; ++u)
-                    if (64 * u < nrow) fused_entry_stats(a, any, p1[u], p2[u], cE, vl, rn, r1, r2, K, iz[u]);
+                    if (64 * u < nrow && reaches(p1[u], p2[u], cE.s1, cE.s2, R2))
+                        fused_entry_stats(a, any, p1[u], p2[u], cE, vl, rn, r1, r2, K, iz[u]);
             } else {
                 const float4 y0 = cst[SAME ? 0 : 192 + j], y1 = cst[SAME ? 0 : 256 + j];
                 const Col8 cC{y0.x, y0.y, y0.z, y0.w, y1.x, y1.y, y1.z, 0.0f};
 #pragma unroll
                 for (int u = 0; u < kSup; ++u) {
-                    if (64 * u < nrow) {
+                    if (64 * u < nrow && reaches(p1[u], p2[u], cE.s1, cE.s2, R2)) {
                         const float Q = fast_exp2(entry_exponent(p1[u], p2[u], cE.s1, cE.s2, cE.v1, cE.v2, cE.vv,
                                                                  cE.vv2, K, 0.0f)) *
                                         iz[u];

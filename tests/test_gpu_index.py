@@ -48,7 +48,7 @@ def test_candidates_match_oracle(gpu_lib):
     assert np.array_equal(gc["spot_a"].cpu().numpy()[gi], ref["a"][oi])
 
 
-@pytest.mark.parametrize("drop_log2", [0.0, 40.0])
+@pytest.mark.parametrize("drop_log2", [0.0, 26.0])
 def test_refine_score_match_oracle(gpu_lib, drop_log2):
     """Refinement and scoring against the oracle (which keeps every pair), with
     the passes skipping only FP32-zero terms (0) and terms below 2^-40 of the
