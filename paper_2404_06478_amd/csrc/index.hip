@@ -233,6 +233,19 @@ __device__ __forceinline__ float wave_min_f(float v) {
 
 constexpr int kSup = 16;    // 64-row chunks of detected spots held per lane
 
+// Squared zero radius of a model spot at threshold T (INFINITY where the
+// bound does not apply): R_j of the refinement passes' cell marking (see k_single_acc).
+__device__ __forceinline__ float zero_radius2(float vv, float vn, float K, float T) {
+    const float vn2 = vn * vn;
+    const float t2 = 2.0f * (T / K) * vv / vn2;
+    if (vn2 >= 1e-4f * vv && t2 < 0.81f) {
+        const float t0 = sqrtf(t2);
+        const float R = fmaf(t0 * sqrtf(vv) / (1.0f - t0), 1.001f, 1e-3f);
+        return R * R;
+    }
+    return INFINITY;
+}
+
 // Whether some lane's detected spot p lies within R (R2 = R^2) of the model
 // spot s on the detector (wave-uniform).
 __device__ __forceinline__ bool reaches(float p1, float p2, float s1, float s2, float R2) {
@@ -247,6 +260,11 @@ __device__ __forceinline__ bool reaches(float p1, float p2, float s1, float s2, 
 constexpr int kCellG = 32;
 constexpr int kCells = kCellG * kCellG;
 constexpr int kMaxRuns = 256;
+
+// Cell of a coordinate in cell units (row or column of the kCellG grid).
+__device__ __forceinline__ int cell_coord(float u) {
+    return u >= 0.0f ? min(kCellG - 1, static_cast<int>(fminf(u, static_cast<float>(kCellG)))) : 0;
+}
 // Exponent (log2 units) beyond which an FP32 plan term exp2(-K c') is 0 for
 // any rounding of c' (2^-150 already rounds to 0; the margin covers the cost's
 // own rounding, a few ulps relative).  The passes skip pairs beyond a
@@ -268,6 +286,7 @@ struct SlotArgs {
     // cell index (refinement passes): the spots in cell order, per-(block,
     // cell) start positions [nb * kCells + 1], per-block grid (x0, y0, cx, cy)
     const float *P1s, *P2s;
+    const float2 *P12s;     // the same, interleaved
     const int *cell_off;
     const float4 *cbox;
     unsigned long long *evaluated;   // pairs the refinement passes evaluate
@@ -305,9 +324,9 @@ __device__ __forceinline__ Col8 col_of(const LaneCol &c, int j) {
 // c' = |v x delta|^2 / (|v|^2 |d|^2 + (v.d) |v| |d|) (chord_cp's expression
 // with sqrt(|v|^2 |d|^2) = |v| |d|), the plan entry Q = exp2(-K c') iz, and
 // the statistics of accumulate_stats (whose |d| - |v| numerator is the same
-// w).  Returns Q; adds the statistics when the wave has any Q > 0.
-__device__ __forceinline__ void fused_entry_stats(float *a, bool &any, float p1, float p2, const Col8 &c,
-                                                  float vlen, float rn, float r1, float r2, float K, float iz) {
+// w).  Adds the statistics when Q > 0.
+__device__ __forceinline__ void spot_entry_stats(float *a, float p1, float p2, const Col8 &c, float vlen, float rn,
+                                                 float r1, float r2, float K, float iz) {
     const float dy = p1 - c.s1, dz = p2 - c.s2;
     const float e = fmaf(dz, dz, dy * dy);
     const float bb = fmaf(c.v2, dz, c.v1 * dy);
@@ -318,8 +337,7 @@ __device__ __forceinline__ void fused_entry_stats(float *a, bool &any, float p1,
     const float x2 = fmaf(c.vv, e, -(bb * bb));
     const float den = fmaf((c.vv + bb) * vlen, tau, c.vv * dd);
     const float Q = fast_exp2(-K * (x2 * __builtin_amdgcn_rcpf(den))) * iz;
-    if (!__any(Q > 0.0f)) return;                 // no weight in this chunk (wave-uniform)
-    any = true;
+    if (!(Q > 0.0f)) return;
     const float dl = w * __builtin_amdgcn_rcpf(tau + vlen);
     const float e0 = (-rn * dl) * itau;
     const float e1 = fmaf(-r1, dl, dy) * itau;
@@ -351,13 +369,11 @@ __device__ __forceinline__ void fused_entry_stats(float *a, bool &any, float p1,
 // Gauss-Newton steps of one refinement iteration), statistics at the current
 // columns colsC.  Writes per (candidate, block) the summed 27-value
 // normal-equation contribution.  One wave per (block b, candidate c), item =
-// b * C + c so that neighbouring waves stream the same detected spots.
-// SAME: colsC is colsE (the first step), and each pair's statistics reuse its
-// plan term's cost (fused_entry_stats); otherwise the statistics pass
-// evaluates the plan term at colsE and the statistics at colsC.  The loops
-// over a lane's kSup rows are unrolled with wave-uniform guards, so the rows
-// stay in named registers.
-template <bool SAME>
+// b * C + c so that neighbouring waves stream the same detected spots.  The
+// Gauss-Newton steps after the first of an iteration (colsC not colsE; the
+// first step runs per model spot, k_spot_acc).  The loops over a lane's kSup
+// rows are unrolled with wave-uniform guards, so the rows stay in named
+// registers.
 __global__ __launch_bounds__(64) void k_single_acc(SlotArgs A, float K, float bin_e, float T_skip,
                                                    double *__restrict__ st_out) {
     const int item = blockIdx.x;
@@ -368,7 +384,7 @@ __global__ __launch_bounds__(64) void k_single_acc(SlotArgs A, float K, float bi
     const int64_t r0 = A.ooff[b], rend = A.ooff[b + 1];
     if (nc == 0) return;
     const LaneCol lE = lane_col(A.colsE, o0, nc, lane);
-    const LaneCol lC = SAME ? lE : lane_col(A.colsC, o0, nc, lane);
+    const LaneCol lC = lane_col(A.colsC, o0, nc, lane);
     // per-column constants at the current geometry: |v|, v / |v|
     const float ivl_l = __builtin_amdgcn_rsqf(lC.vv), vlen_l = lC.vv * ivl_l;
     const float rn_l = lC.vn * ivl_l, r1_l = lC.v1 * ivl_l, r2_l = lC.v2 * ivl_l;
@@ -378,15 +394,13 @@ __global__ __launch_bounds__(64) void k_single_acc(SlotArgs A, float K, float bi
     // the columns' constants in LDS, read back by every lane with one
     // broadcast load per value: the pair arithmetic then takes vector-register
     // operands only (a scalar-register operand halves the VALU issue rate)
-    __shared__ float4 cst[64 * (SAME ? 3 : 5)];
+    __shared__ float4 cst[64 * 5];
     if (lane < nc) {
         cst[lane] = make_float4(lE.s1, lE.s2, lE.v1, lE.v2);
         cst[64 + lane] = make_float4(lE.vv, lE.vv2, lE.vn, vlen_l);
         cst[128 + lane] = make_float4(rn_l, r1_l, r2_l, 0.0f);
-        if (!SAME) {
-            cst[192 + lane] = make_float4(lC.s1, lC.s2, lC.v1, lC.v2);
-            cst[256 + lane] = make_float4(lC.vv, lC.vv2, lC.vn, 0.0f);
-        }
+        cst[192 + lane] = make_float4(lC.s1, lC.s2, lC.v1, lC.v2);
+        cst[256 + lane] = make_float4(lC.vv, lC.vv2, lC.vn, 0.0f);
     }
     // Rows that can carry weight.  Every plan term of model spot j has
     // exponent K c' >= T_skip (so is 0 in FP32 for T_skip = kZeroExp2, or
@@ -403,19 +417,7 @@ __global__ __launch_bounds__(64) void k_single_acc(SlotArgs A, float K, float bi
     __shared__ float rad2[64];
     __shared__ unsigned cmask[kCells / 32];
     __shared__ int run_at[kMaxRuns], run_pre[kMaxRuns + 1];
-    {
-        float R2 = INFINITY;
-        if (lane < nc) {
-            const float vn2 = lE.vn * lE.vn;
-            const float t2 = 2.0f * (T_skip / K) * lE.vv / vn2;
-            if (vn2 >= 1e-4f * lE.vv && t2 < 0.81f) {
-                const float t0 = sqrtf(t2);
-                const float R = fmaf(t0 * sqrtf(lE.vv) / (1.0f - t0), 1.001f, 1e-3f);
-                R2 = R * R;
-            }
-        }
-        rad2[lane] = R2;
-    }
+    rad2[lane] = lane < nc ? zero_radius2(lE.vv, lE.vn, K, T_skip) : INFINITY;
     if (lane < kCells / 32) cmask[lane] = 0u;
     __syncthreads();
     const float4 bx = A.cbox[b];   // x0, y0, cx, cy
@@ -537,24 +539,17 @@ __global__ __launch_bounds__(64) void k_single_acc(SlotArgs A, float K, float bi
 #pragma unroll
             for (int q = 0; q < kStat; ++q) a[q] = 0.0f;
             bool any = false;
-            if (SAME) {
+            const float4 y0 = cst[192 + j], y1 = cst[256 + j];
+            const Col8 cC{y0.x, y0.y, y0.z, y0.w, y1.x, y1.y, y1.z, 0.0f};
 #pragma unroll
-                for (int u = 0; u < kSup; ++u)
-                    if (64 * u < nrow && reaches(p1[u], p2[u], cE.s1, cE.s2, R2))
-                        fused_entry_stats(a, any, p1[u], p2[u], cE, vl, rn, r1, r2, K, iz[u]);
-            } else {
-                const float4 y0 = cst[SAME ? 0 : 192 + j], y1 = cst[SAME ? 0 : 256 + j];
-                const Col8 cC{y0.x, y0.y, y0.z, y0.w, y1.x, y1.y, y1.z, 0.0f};
-#pragma unroll
-                for (int u = 0; u < kSup; ++u) {
-                    if (64 * u < nrow && reaches(p1[u], p2[u], cE.s1, cE.s2, R2)) {
-                        const float Q = fast_exp2(entry_exponent(p1[u], p2[u], cE.s1, cE.s2, cE.v1, cE.v2, cE.vv,
-                                                                 cE.vv2, K, 0.0f)) *
-                                        iz[u];
-                        if (__any(Q > 0.0f)) {                      // weight in this chunk
-                            any = true;
-                            accumulate_stats(a, Q, p1[u], p2[u], cC, vl, rn, r1, r2);   // Q = 0 adds zeros
-                        }
+            for (int u = 0; u < kSup; ++u) {
+                if (64 * u < nrow && reaches(p1[u], p2[u], cE.s1, cE.s2, R2)) {
+                    const float Q = fast_exp2(entry_exponent(p1[u], p2[u], cE.s1, cE.s2, cE.v1, cE.v2, cE.vv,
+                                                             cE.vv2, K, 0.0f)) *
+                                    iz[u];
+                    if (__any(Q > 0.0f)) {                      // weight in this chunk
+                        any = true;
+                        accumulate_stats(a, Q, p1[u], p2[u], cC, vl, rn, r1, r2);   // Q = 0 adds zeros
                     }
                 }
             }
@@ -599,6 +594,144 @@ __global__ __launch_bounds__(64) void k_single_solve(SlotArgs A, const double *_
     for (int k = 0; k < kHg; ++k) acc[k] = wave_sum(acc[k]);
     if (threadIdx.x != 0) return;
     gn_solve_apply(acc, mu_rel, q + 4 * c, x + 3 * c, gf + c, nullptr);
+}
+
+// ---------------------------------------------------------------- per model spot refinement pass
+
+// The (block, candidate) slot of model spot o: [*o0, *o1) and its block.
+__device__ __forceinline__ int spot_slot(const SlotArgs &A, int64_t o, int64_t *o0, int64_t *o1) {
+    int b = A.mblock[o];
+    const int g = A.mgrain[o];
+    int64_t item = static_cast<int64_t>(b) * A.C + g;
+    if (b < 0 || b >= A.nb || g < 0 || g >= A.C || !(A.offs[item] <= o && o < A.offs[item + 1])) {
+        // by the offsets themselves
+        int64_t lo = 0, hi = static_cast<int64_t>(A.nb) * A.C - 1;
+        while (lo < hi) {
+            const int64_t mid = (lo + hi + 1) >> 1;
+            if (A.offs[mid] <= o) lo = mid;
+            else hi = mid - 1;
+        }
+        item = lo;
+        b = static_cast<int>(item / A.C);
+    }
+    *o0 = A.offs[item];
+    *o1 = A.offs[item + 1];
+    return b;
+}
+
+__global__ void k_spot_rad(const Col8 *__restrict__ cols, int64_t M, float K, float T, float *__restrict__ rad2) {
+    for (int64_t o = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; o < M;
+         o += static_cast<int64_t>(gridDim.x) * blockDim.x)
+        rad2[o] = zero_radius2(cols[o].vv, cols[o].vn, K, T);
+}
+
+// Bit k of nbr[o]: model spot o0 + k of o's slot has a zero disk that meets
+// o's (its own bit included): only those can weigh on a row within reach of o.
+__global__ void k_spot_nbr(SlotArgs A, const float *__restrict__ rad2, int64_t M,
+                           unsigned long long *__restrict__ nbr) {
+    for (int64_t o = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; o < M;
+         o += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+        int64_t o0, o1;
+        spot_slot(A, o, &o0, &o1);
+        const float Ro = sqrtf(rad2[o]);
+        const float s1 = A.colsE[o].s1, s2 = A.colsE[o].s2;
+        unsigned long long m = 0ull;
+        for (int64_t j = o0; j < o1; ++j) {
+            const float R = Ro + sqrtf(rad2[j]);
+            const float dy = A.colsE[j].s1 - s1, dz = A.colsE[j].s2 - s2;
+            if (j == o || !(fmaf(dz, dz, dy * dy) >= R * R)) m |= 1ull << (j - o0);
+        }
+        nbr[o] = m;
+    }
+}
+
+// The statistics pass of the first Gauss-Newton step of a refinement
+// iteration (statistics at the E-step geometry colsE), one thread per model
+// spot o: the detected spots of the cell rows of o's cell
+// box, those within R_o of s_o, each with its row normaliser (the bin term,
+// then the terms of the slot's spots that reach the row, in index order: a
+// spot out of reach adds less than a quarter ulp, so the normaliser is the
+// one over every spot of the slot), accumulated in FP32 over 16 rows at a
+// time and in FP64 across.  Writes o's kStat statistics.
+__global__ __launch_bounds__(256) void k_spot_acc(SlotArgs A, float K, float bin_e, const float *__restrict__ rad2,
+                                                  const unsigned long long *__restrict__ nbr, int64_t M,
+                                                  double *__restrict__ st_out) {
+    const int64_t o = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    unsigned long long evaluated = 0;
+    if (o < M) {
+        int64_t o0, o1;
+        const int b = spot_slot(A, o, &o0, &o1);
+        const Col8 me = A.colsE[o];
+        const float R2 = rad2[o];
+        const unsigned long long mask = nbr[o];
+        const float ivl = __builtin_amdgcn_rsqf(me.vv), vl = me.vv * ivl;
+        const float rn = me.vn * ivl, r1 = me.v1 * ivl, r2 = me.v2 * ivl;
+        double acc[kStat];
+        float a[kStat];
+#pragma unroll
+        for (int q = 0; q < kStat; ++q) {
+            acc[q] = 0.0;
+            a[q] = 0.0f;
+        }
+        // the cells a spot within R_o can fall in (cell_coord of the
+        // coordinate range, widened by a thousandth of a cell against the
+        // rounding of the cell assignment), per cell row the chord of the
+        // disk over that row's band
+        const float4 bx = A.cbox[b];
+        const float R = sqrtf(R2);
+        const float eps_c = 1e-3f;
+        const int iy0 = cell_coord((me.s2 - R - bx.y) / bx.w - eps_c);
+        const int iy1 = cell_coord((me.s2 + R - bx.y) / bx.w + eps_c);
+        const int *co = A.cell_off + static_cast<int64_t>(b) * kCells;
+        int n16 = 0;
+        for (int iy = iy0; iy <= iy1; ++iy) {
+            const float ya = bx.y + (static_cast<float>(iy) - eps_c) * bx.w;
+            const float yb = bx.y + (static_cast<float>(iy + 1) + eps_c) * bx.w;
+            const float dyb = fmaxf(0.0f, fmaxf(ya - me.s2, me.s2 - yb));
+            if (!(dyb * dyb < R2)) continue;
+            const float hw = sqrtf(R2 - dyb * dyb);
+            const int ix0 = cell_coord((me.s1 - hw - bx.x) / bx.z - eps_c);
+            const int ix1 = cell_coord((me.s1 + hw - bx.x) / bx.z + eps_c);
+            const int re = co[iy * kCellG + ix1 + 1];
+            for (int r = co[iy * kCellG + ix0]; r < re; ++r) {
+                const float2 pp = A.P12s[r];
+                const float p1 = pp.x, p2 = pp.y;
+                const float dy = p1 - me.s1, dz = p2 - me.s2;
+                if (!(fmaf(dz, dz, dy * dy) < R2)) continue;
+                ++evaluated;
+                float z = bin_e;
+                for (unsigned long long m = mask; m; m &= m - 1) {
+                    const int64_t j = o0 + __builtin_ctzll(m);
+                    if (j == o) {
+                        z += fast_exp2(entry_exponent(p1, p2, me.s1, me.s2, me.v1, me.v2, me.vv, me.vv2, K, 0.0f));
+                    } else {
+                        const Col8 cj = A.colsE[j];
+                        const float ey = p1 - cj.s1, ez = p2 - cj.s2;
+                        if (fmaf(ez, ez, ey * ey) < rad2[j])
+                            z += fast_exp2(entry_exponent(p1, p2, cj.s1, cj.s2, cj.v1, cj.v2, cj.vv, cj.vv2, K,
+                                                          0.0f));
+                    }
+                }
+                spot_entry_stats(a, p1, p2, me, vl, rn, r1, r2, K, __builtin_amdgcn_rcpf(z));
+                if (++n16 == 16) {
+#pragma unroll
+                    for (int q = 0; q < kStat; ++q) {
+                        acc[q] += static_cast<double>(a[q]);
+                        a[q] = 0.0f;
+                    }
+                    n16 = 0;
+                }
+            }
+        }
+        double *dst = st_out + o * kStat;
+#pragma unroll
+        for (int q = 0; q < kStat; ++q) dst[q] = acc[q] + static_cast<double>(a[q]);
+    }
+    if (A.evaluated) {
+        for (int off = 32; off > 0; off >>= 1)
+            evaluated += __shfl_xor(evaluated, off, 64);
+        if ((threadIdx.x & 63) == 0 && evaluated) atomicAdd(A.evaluated, evaluated);
+    }
 }
 
 // Scoring at the final grains.  Per model spot: unmatched when no detected
@@ -1140,10 +1273,6 @@ __global__ __launch_bounds__(256) void k_cell_box(const float *__restrict__ P1, 
     }
 }
 
-__device__ __forceinline__ int cell_coord(float u) {
-    return u >= 0.0f ? min(kCellG - 1, static_cast<int>(fminf(u, static_cast<float>(kCellG)))) : 0;
-}
-
 // Sort key of every detected spot: block * kCells + cell (row-major cells).
 __global__ void k_cell_keys(const float *__restrict__ P1, const float *__restrict__ P2,
                             const int64_t *__restrict__ ooff, int nb, const float4 *__restrict__ box, int64_t n,
@@ -1165,12 +1294,13 @@ __global__ void k_cell_keys(const float *__restrict__ P1, const float *__restric
 
 __global__ void k_cell_gather(const float *__restrict__ P1, const float *__restrict__ P2,
                               const int *__restrict__ idx, int64_t n, float *__restrict__ P1s,
-                              float *__restrict__ P2s) {
+                              float *__restrict__ P2s, float2 *__restrict__ P12s) {
     for (int64_t k = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; k < n;
          k += static_cast<int64_t>(gridDim.x) * blockDim.x) {
         const int i = idx[k];
         P1s[k] = P1[i];
         P2s[k] = P2[i];
+        P12s[k] = make_float2(P1[i], P2[i]);
     }
 }
 
@@ -1198,6 +1328,7 @@ struct CellWs {
     unsigned *key_in, *key_out;
     int *idx_in, *idx_out;
     float *P1s, *P2s;
+    float2 *P12s;
     int *off;
     float4 *box;
     void *tmp;
@@ -1212,6 +1343,7 @@ void carve_cells(Carver &cv, CellWs &w, int nb, int64_t n_obs) {
     w.idx_out = cv.take<int>(n);
     w.P1s = cv.take<float>(n);
     w.P2s = cv.take<float>(n);
+    w.P12s = cv.take<float2>(n);
     w.off = cv.take<int>(static_cast<int64_t>(nb) * kCells + 1);
     w.box = cv.take<float4>(nb);
     size_t tmp = 0;
@@ -1237,7 +1369,7 @@ int build_cells(CellWs &w, const laue_obs_spots *obs, const int64_t *ooff_dev, i
         size_t tb = w.tmp_bytes;
         LAUE_CHECK_HIP(hipcub::DeviceRadixSort::SortPairs(w.tmp, tb, w.key_in, w.key_out, w.idx_in, w.idx_out,
                                                          static_cast<int>(n), 0, end_bit, s));
-        k_cell_gather<<<g, 256, 0, s>>>(obs->p1, obs->p2, w.idx_out, n, w.P1s, w.P2s);
+        k_cell_gather<<<g, 256, 0, s>>>(obs->p1, obs->p2, w.idx_out, n, w.P1s, w.P2s, w.P12s);
         LAUE_CHECK_HIP(hipGetLastError());
     }
     const unsigned go = static_cast<unsigned>(std::min<int64_t>((n_keys + 1 + 255) / 256, 4096));
@@ -1251,6 +1383,8 @@ struct ScoreWs {
     int *plane, *grain, *block;
     Col8 *colsE, *colsC;
     double *st;       // per model spot: the kStat statistics of the last pass
+    float *rad2;      // per model spot: squared zero radius (per-spot pass)
+    unsigned long long *nbr;   // per model spot: slot spots whose zero disks meet its own
     int *unm, *lcnt;
     uint8_t *keep;
     int64_t *loff;
@@ -1271,6 +1405,8 @@ size_t carve_score(Carver &cv, ScoreWs &w, const laue_geometry *g, int chunk, in
     w.colsE = cv.take<Col8>(S);
     w.colsC = cv.take<Col8>(S);
     w.st = cv.take<double>(static_cast<size_t>(S) * kStat);
+    w.rad2 = cv.take<float>(S);
+    w.nbr = cv.take<unsigned long long>(S);
     w.unm = cv.take<int>(static_cast<size_t>(chunk) * nb);
     w.lcnt = cv.take<int>(static_cast<size_t>(chunk) * nb + 1);
     w.loff = cv.take<int64_t>(static_cast<size_t>(chunk) * nb + 1);
@@ -1281,11 +1417,20 @@ size_t carve_score(Carver &cv, ScoreWs &w, const laue_geometry *g, int chunk, in
     return cv.size();
 }
 
-int launch_acc(const SlotArgs &A, float K, float bin_e, float T_skip, double *st, hipStream_t s) {
-    if (A.colsC == A.colsE)
-        k_single_acc<true><<<static_cast<unsigned>(A.nb) * A.C, 64, 0, s>>>(A, K, bin_e, T_skip, st);
-    else
-        k_single_acc<false><<<static_cast<unsigned>(A.nb) * A.C, 64, 0, s>>>(A, K, bin_e, T_skip, st);
+// The statistics pass: per model spot at the E-step geometry (the first
+// Gauss-Newton step), per (block, candidate) wave otherwise.
+int launch_acc(const SlotArgs &A, float K, float bin_e, float T_skip, int64_t M, float *rad2,
+               unsigned long long *nbr, double *st, hipStream_t s) {
+    if (A.colsC == A.colsE) {
+        if (M > 0) {
+            const unsigned g = static_cast<unsigned>(std::min<int64_t>((M + 255) / 256, 16384));
+            k_spot_rad<<<g, 256, 0, s>>>(A.colsE, M, K, T_skip, rad2);
+            k_spot_nbr<<<g, 256, 0, s>>>(A, rad2, M, nbr);
+            k_spot_acc<<<static_cast<unsigned>((M + 255) / 256), 256, 0, s>>>(A, K, bin_e, rad2, nbr, M, st);
+        }
+    } else {
+        k_single_acc<<<static_cast<unsigned>(A.nb) * A.C, 64, 0, s>>>(A, K, bin_e, T_skip, st);
+    }
     LAUE_CHECK_HIP(hipGetLastError());
     return LAUE_OK;
 }
@@ -1402,6 +1547,7 @@ extern "C" int laue_score_candidates(const laue_geometry *geom, const laue_plane
         A.mblock = w.block;
         A.P1s = w.cells.P1s;
         A.P2s = w.cells.P2s;
+        A.P12s = w.cells.P12s;
         A.cell_off = w.cells.off;
         A.cbox = w.cells.box;
         A.evaluated = pairs + 2;
@@ -1438,7 +1584,7 @@ extern "C" int laue_score_candidates(const laue_geometry *geom, const laue_plane
                         return rc;
                     A.colsC = w.colsC;
                 }
-                if ((rc = launch_acc(A, K, bin_e, T_skip, w.st, s))) return rc;
+                if ((rc = launch_acc(A, K, bin_e, T_skip, total, w.rad2, w.nbr, w.st, s))) return rc;
                 k_single_solve<<<C, 64, 0, s>>>(A, w.st, D2, par->mu_rel, sub.q, sub.x, w.e.grains);
                 LAUE_CHECK_HIP(hipGetLastError());
             }
