@@ -667,8 +667,11 @@ size_t laue_spot_greedy_workspace_size(int32_t n_cand, int64_t n_rows);
  * Increments computed at an earlier step bound the current ones from above
  * (covers only rise): each step recomputes, grid-wide, only the candidates
  * whose bound reaches the best exact increment, so the picks and increments
- * are those of recomputing every increment at every step.  Workspace beyond
- * laue_spot_greedy_workspace_size is not used. */
+ * are those of recomputing every increment at every step.
+ * laue_spot_greedy_workspace_size is the minimum; with 8 bytes per SPOT entry
+ * beyond it (and lbar_off[0] = 0) the entries are copied there and each
+ * recomputation drops the entries that can no longer add to an increment
+ * (the picks and increments do not change, bit for bit). */
 int laue_spot_greedy(const int64_t *lbar_off, const int32_t *lbar_row, const float *lbar_val,
                      int32_t n_cand, int64_t n_rows, double phi, int32_t k_max, int32_t *picks,
                      double *gains, int32_t *n_picked, void *ws, size_t ws_bytes, void *stream);

@@ -596,7 +596,8 @@ def laue_spot_greedy(lbar_off, lbar_row, lbar_val, n_cand, n_rows, phi, k_max):
     import torch
     lib = require_native()
     dev = _dev()
-    ws = _workspace(lib.laue_spot_greedy_workspace_size(int(n_cand), int(n_rows)))
+    # the minimum plus room for a copy of the entries, which the selection compacts
+    ws = _workspace(lib.laue_spot_greedy_workspace_size(int(n_cand), int(n_rows)) + 8 * int(lbar_row.numel()) + 1024)
     picks = torch.zeros(max(int(k_max), 1), dtype=torch.int32, device=dev)
     gains = torch.zeros(max(int(k_max), 1), dtype=torch.float64, device=dev)
     npk = C.c_int32()

@@ -100,6 +100,13 @@ int check_ws(void *ws, size_t ws_bytes, size_t need);
 // from eps_start down to eps_end), without the final iterations
 int em_n_temperatures(const laue_em_params &p);
 
+// laue_spot_greedy on a SPOT matrix the selection may reorder: each
+// candidate's live entries are compacted to the front of its range as the
+// selection goes (the picks and increments are those of laue_spot_greedy).
+int spot_greedy_inplace(const int64_t *lbar_off, int32_t *lbar_row, float *lbar_val, int32_t n_cand,
+                        int64_t n_rows, double phi, int32_t k_max, int32_t *picks, double *gains,
+                        int32_t *n_picked, void *ws, size_t ws_bytes, void *stream);
+
 // ---------------------------------------------------------------- device math
 
 // Plane normal in the lab: u = Gamma_t R w (Sec. 3.3), explicit FMA chains.

@@ -774,6 +774,11 @@ __device__ __forceinline__ void mode_epilogue(const SampleDesc &D, int j, const 
         column_rot_m0(*D.geom, D.mblock[j], s64, o);
 }
 
+// Plan entries at or below this weight (2^-40 of a detected spot's row
+// mass) have their M-step statistics skipped; the wave still runs the
+// statistics of a row when any of its columns has a larger entry.
+constexpr float kMstepMinQ = 0x1p-40f;
+
 template <int MODE>
 __device__ __forceinline__ void mstep_pass(const Item &it, const SampleDesc &D,
                                            const LAUE_GLOBAL float *__restrict__ P1,
@@ -820,7 +825,7 @@ __device__ __forceinline__ void mstep_pass(const Item &it, const SampleDesc &D,
             const float4 X = lr[buf][t];
             const float Q = fast_exp2(entry_exponent(X.x, X.y, cE.s1, cE.s2, cE.v1, cE.v2, cE.vv,
                                                      cE.vv2, K, fmaf(X.z, kx, gk)));
-            if (Q > 0.0f) mode_acc<MODE>(a, Q, X.x, X.y, cC, vlen, rn, r1, r2);
+            if (Q > kMstepMinQ) mode_acc<MODE>(a, Q, X.x, X.y, cC, vlen, rn, r1, r2);
         }
         for (int k = 0; k < NS; ++k) s64[k] += static_cast<double>(a[k]);
         buf ^= 1;

@@ -864,6 +864,51 @@ __device__ __forceinline__ double lane_gain(int64_t e0, int64_t e1, int lane, co
     return s;
 }
 
+// lane_gain over the lane's positions of [e0, e0 + L) that also moves the
+// lane's live entries (Lbar above the row's cover) down to its first
+// positions e0 + lane + 64 k, in order: the entries it drops add exactly 0
+// to this and every later increment (covers only rise), so a lane's FP64 sum
+// over the kept entries is the sum over all of them bit for bit.  n_live
+// returns the lane's kept entries.
+__device__ __forceinline__ double lane_gain_compact(int64_t e0, int64_t L, int lane, int *row, float *val,
+                                                    const float *__restrict__ cur, int &n_live) {
+    double s = 0.0;
+    int n = 0;
+    int64_t e = e0 + lane;
+    const int64_t e1 = e0 + L;
+    auto keep = [&](int64_t at, int r, float v, float c) {
+        if (v > c) {
+            const int64_t d = e0 + lane + 64 * static_cast<int64_t>(n);
+            if (d != at) {
+                row[d] = r;
+                val[d] = v;
+            }
+            ++n;
+        }
+    };
+    for (; e + 192 < e1; e += 256) {
+        const int r0 = row[e], r1 = row[e + 64], r2 = row[e + 128], r3 = row[e + 192];
+        const float v0 = val[e], v1 = val[e + 64], v2 = val[e + 128], v3 = val[e + 192];
+        const float c0 = cur[r0], c1 = cur[r1], c2 = cur[r2], c3 = cur[r3];
+        s += fmax(0.0, static_cast<double>(v0) - static_cast<double>(c0));
+        s += fmax(0.0, static_cast<double>(v1) - static_cast<double>(c1));
+        s += fmax(0.0, static_cast<double>(v2) - static_cast<double>(c2));
+        s += fmax(0.0, static_cast<double>(v3) - static_cast<double>(c3));
+        keep(e, r0, v0, c0);
+        keep(e + 64, r1, v1, c1);
+        keep(e + 128, r2, v2, c2);
+        keep(e + 192, r3, v3, c3);
+    }
+    for (; e < e1; e += 64) {
+        const int r = row[e];
+        const float v = val[e], c = cur[r];
+        s += fmax(0.0, static_cast<double>(v) - static_cast<double>(c));
+        keep(e, r, v, c);
+    }
+    n_live = n;
+    return s;
+}
+
 __global__ __launch_bounds__(64) void k_gain(const int64_t *__restrict__ off,
                                              const int *__restrict__ row,
                                              const float *__restrict__ val,
@@ -967,8 +1012,9 @@ __global__ __launch_bounds__(256) void k_band_scan(const uint8_t *__restrict__ p
 __global__ __launch_bounds__(1024) void k_band_decide(int phase, int step, int nb, const double *__restrict__ pb,
                                                       const int *__restrict__ pi, const double *__restrict__ ps,
                                                       BandState *st, int *done, const int64_t *__restrict__ off,
-                                                      const int *__restrict__ row, const float *__restrict__ val,
-                                                      float *cur, uint8_t *picked, int *picks, double *pgain) {
+                                                      const int *__restrict__ len, const int *__restrict__ row,
+                                                      const float *__restrict__ val, float *cur, uint8_t *picked,
+                                                      int *picks, double *pgain) {
     __shared__ double lb[16], ls[16];
     __shared__ int li[16];
     __shared__ int top;
@@ -1016,16 +1062,32 @@ __global__ __launch_bounds__(1024) void k_band_decide(int phase, int step, int n
     __syncthreads();
     const int c = top;
     if (c < 0) return;
-    // a candidate has at most one entry per row: no two threads share a row
-    for (int64_t e = off[c] + threadIdx.x; e < off[c + 1]; e += 1024) cur[row[e]] = fmaxf(cur[row[e]], val[e]);
+    // the range's live entries hold distinct rows (at most one entry per row
+    // and candidate); a compacted range may repeat a row at a position filled
+    // with Lbar = -inf, which never raises a cover and so never writes
+    for (int64_t e = off[c] + threadIdx.x; e < off[c] + len[c]; e += 1024) {
+        const int r = row[e];
+        const float v = val[e];
+        if (v > cur[r]) cur[r] = v;
+    }
+}
+
+__global__ void k_len_init(const int64_t *__restrict__ off, int n, int *__restrict__ len) {
+    for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < n; c += gridDim.x * blockDim.x)
+        len[c] = static_cast<int>(off[c + 1] - off[c]);
 }
 
 // Recompute every stale bound at or above the threshold (and positive), one
-// wave per such candidate with k_gain's summation order.
-__global__ __launch_bounds__(64) void k_band_refresh(const int64_t *__restrict__ off, const int *__restrict__ row,
-                                                     const float *__restrict__ val, const float *__restrict__ cur,
+// wave per such candidate with k_gain's summation order.  len[c]: the
+// candidate's current range [off[c], off[c] + len[c]).  With compact the
+// range is compacted on the way (lane_gain_compact): the new length ends at
+// the last kept entry, and positions below it that no lane keeps are filled
+// with Lbar = -inf (never above a cover, adding exactly 0).
+__global__ __launch_bounds__(64) void k_band_refresh(const int64_t *__restrict__ off, int *row, float *val,
+                                                     const float *__restrict__ cur,
                                                      const uint8_t *__restrict__ picked, double *ub, int *stamp,
-                                                     int n, int step, const BandState *__restrict__ st,
+                                                     int *len, int compact, int n, int step,
+                                                     const BandState *__restrict__ st,
                                                      const int *__restrict__ done) {
     if (*done || st->decided == step) return;
     const double thr = st->thr;
@@ -1041,7 +1103,21 @@ __global__ __launch_bounds__(64) void k_band_refresh(const int64_t *__restrict__
         while (m) {
             const int cc = c0 + __builtin_ctzll(m);
             m &= m - 1;
-            const double s = wave_sum(lane_gain(off[cc], off[cc + 1], lane, row, val, cur));
+            const int64_t e0 = off[cc];
+            const int L = len[cc];
+            double s;
+            if (compact) {
+                int nl;
+                s = wave_sum(lane_gain_compact(e0, L, lane, row, val, cur, nl));
+                int last = nl > 0 ? 64 * (nl - 1) + lane + 1 : 0;
+#pragma unroll
+                for (int o = 32; o > 0; o >>= 1) last = max(last, __shfl_xor(last, o, 64));
+                for (int64_t p = e0 + lane + 64 * static_cast<int64_t>(nl); p < e0 + last; p += 64)
+                    val[p] = -INFINITY;
+                if (lane == 0) len[cc] = last;
+            } else {
+                s = wave_sum(lane_gain(e0, e0 + L, lane, row, val, cur));
+            }
             if (lane == 0) {
                 ub[cc] = s;
                 stamp[cc] = step;
@@ -1643,6 +1719,7 @@ struct GreedyWs {
     uint8_t *picked;
     double *gain;   // upper bounds of the increments (exact at their stamp)
     int *stamp;
+    int *len;       // current length of each candidate's range (compaction)
     int *done;
     double *pb, *ps;   // the band scan's per-block partials
     int *pi;
@@ -1654,6 +1731,7 @@ size_t carve_greedy(Carver &cv, GreedyWs &w, int n_cand, int64_t n_rows) {
     w.picked = cv.take<uint8_t>(std::max(n_cand, 1));
     w.gain = cv.take<double>(std::max(n_cand, 1));
     w.stamp = cv.take<int>(std::max(n_cand, 1));
+    w.len = cv.take<int>(std::max(n_cand, 1));
     w.done = cv.take<int>(1);
     w.pb = cv.take<double>(kBandScanBlocks);
     w.ps = cv.take<double>(kBandScanBlocks);
@@ -1661,30 +1739,13 @@ size_t carve_greedy(Carver &cv, GreedyWs &w, int n_cand, int64_t n_rows) {
     w.st = cv.take<BandState>(1);
     return cv.size();
 }
-}  // namespace
 
-extern "C" size_t laue_spot_greedy_workspace_size(int32_t n_cand, int64_t n_rows) {
-    if (n_cand < 0 || n_rows < 0) return 0;
-    Carver cv(nullptr);
-    GreedyWs w;
-    return carve_greedy(cv, w, n_cand, n_rows);
-}
-
-extern "C" int laue_spot_greedy(const int64_t *lbar_off, const int32_t *lbar_row,
-                                const float *lbar_val, int32_t n_cand, int64_t n_rows, double phi,
-                                int32_t k_max, int32_t *picks, double *gains, int32_t *n_picked,
-                                void *ws, size_t ws_bytes, void *stream) {
-    clear_error();
-    int rc;
-    LAUE_REQUIRE(n_cand >= 0 && n_rows >= 0 && k_max >= 0 && n_picked, LAUE_EINVAL, "bad sizes");
-    LAUE_REQUIRE(n_cand == 0 || (lbar_off && lbar_row && lbar_val), LAUE_EINVAL, "SPOT arrays are NULL");
-    LAUE_REQUIRE(k_max == 0 || (picks && gains), LAUE_EINVAL, "outputs are NULL");
-    LAUE_REQUIRE(std::isfinite(phi), LAUE_EINVAL, "phi must be finite");
-    hipStream_t s = static_cast<hipStream_t>(stream);
-    Carver cv(ws);
-    GreedyWs w;
-    size_t need = carve_greedy(cv, w, n_cand, n_rows);
-    if ((rc = check_ws(ws, ws_bytes, need))) return rc;
+// The selection on a SPOT matrix whose entries it may reorder within each
+// candidate's range when compact (row and val then hold each range's live
+// entries first; lbar_off is unchanged).
+int greedy_run(const int64_t *lbar_off, int32_t *lbar_row, float *lbar_val, bool compact, int32_t n_cand,
+               int64_t n_rows, double phi, int32_t k_max, int32_t *picks, double *gains, int32_t *n_picked,
+               GreedyWs &w, hipStream_t s) {
     *n_picked = 0;
     if (n_cand == 0 || k_max == 0) return LAUE_OK;
     k_fill_f<<<static_cast<unsigned>((std::max<int64_t>(n_rows, 1) + 255) / 256), 256, 0, s>>>(w.cur, n_rows, static_cast<float>(phi));
@@ -1692,6 +1753,7 @@ extern "C" int laue_spot_greedy(const int64_t *lbar_off, const int32_t *lbar_row
     k_fill_i<<<1, 64, 0, s>>>(w.done, 1, 0);
     k_fill_i<<<(k_max + 255) / 256, 256, 0, s>>>(picks, k_max, -1);
     k_band_init<<<1, 1, 0, s>>>(w.st);
+    k_len_init<<<static_cast<unsigned>(std::min((n_cand + 255) / 256, 4096)), 256, 0, s>>>(lbar_off, n_cand, w.len);
     LAUE_CHECK_HIP(hipGetLastError());
     const int K = std::min(k_max, n_cand);
     // every increment once: exact at step 0
@@ -1703,10 +1765,10 @@ extern "C" int laue_spot_greedy(const int64_t *lbar_off, const int32_t *lbar_row
         for (int phase = 0; phase < 3; ++phase) {
             if (phase > 0)
                 k_band_refresh<<<nr, 64, 0, s>>>(lbar_off, lbar_row, lbar_val, w.cur, w.picked, w.gain, w.stamp,
-                                                 n_cand, step, w.st, w.done);
+                                                 w.len, compact ? 1 : 0, n_cand, step, w.st, w.done);
             k_band_scan<<<nb, 256, 0, s>>>(w.picked, w.gain, w.stamp, n_cand, step, w.st, w.done, w.pb, w.pi, w.ps);
-            k_band_decide<<<1, 1024, 0, s>>>(phase, step, nb, w.pb, w.pi, w.ps, w.st, w.done, lbar_off, lbar_row,
-                                             lbar_val, w.cur, w.picked, picks, gains);
+            k_band_decide<<<1, 1024, 0, s>>>(phase, step, nb, w.pb, w.pi, w.ps, w.st, w.done, lbar_off, w.len,
+                                             lbar_row, lbar_val, w.cur, w.picked, picks, gains);
         }
         LAUE_CHECK_HIP(hipGetLastError());
         if (step % 64 == 63 && step + 1 < K) {   // stop launching once the selection has ended
@@ -1724,3 +1786,72 @@ extern "C" int laue_spot_greedy(const int64_t *lbar_off, const int32_t *lbar_row
     *n_picked = n;
     return LAUE_OK;
 }
+}  // namespace
+
+extern "C" size_t laue_spot_greedy_workspace_size(int32_t n_cand, int64_t n_rows) {
+    if (n_cand < 0 || n_rows < 0) return 0;
+    Carver cv(nullptr);
+    GreedyWs w;
+    return carve_greedy(cv, w, n_cand, n_rows);
+}
+
+#define GREEDY_ARGS_OK()                                                                                  \
+    LAUE_REQUIRE(n_cand >= 0 && n_rows >= 0 && k_max >= 0 && n_picked, LAUE_EINVAL, "bad sizes");       \
+    LAUE_REQUIRE(n_cand == 0 || (lbar_off && lbar_row && lbar_val), LAUE_EINVAL, "SPOT arrays are NULL"); \
+    LAUE_REQUIRE(k_max == 0 || (picks && gains), LAUE_EINVAL, "outputs are NULL");                       \
+    LAUE_REQUIRE(std::isfinite(phi), LAUE_EINVAL, "phi must be finite")
+
+extern "C" int laue_spot_greedy(const int64_t *lbar_off, const int32_t *lbar_row,
+                                const float *lbar_val, int32_t n_cand, int64_t n_rows, double phi,
+                                int32_t k_max, int32_t *picks, double *gains, int32_t *n_picked,
+                                void *ws, size_t ws_bytes, void *stream) {
+    clear_error();
+    int rc;
+    GREEDY_ARGS_OK();
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    Carver cv(ws);
+    GreedyWs w;
+    const size_t need = carve_greedy(cv, w, n_cand, n_rows);
+    if ((rc = check_ws(ws, ws_bytes, need))) return rc;
+    *n_picked = 0;
+    if (n_cand == 0 || k_max == 0) return LAUE_OK;
+    // room for a copy of the entries: the selection compacts the copy
+    int64_t n_ent = 0;
+    LAUE_CHECK_HIP(hipMemcpyAsync(&n_ent, lbar_off + n_cand, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    LAUE_CHECK_HIP(hipStreamSynchronize(s));
+    int64_t e_first = 0;
+    LAUE_CHECK_HIP(hipMemcpyAsync(&e_first, lbar_off, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    LAUE_CHECK_HIP(hipStreamSynchronize(s));
+    int32_t *row = const_cast<int32_t *>(lbar_row);
+    float *val = const_cast<float *>(lbar_val);
+    bool compact = false;
+    if (e_first == 0 && n_ent > 0) {
+        Carver cc(static_cast<char *>(ws) + need);
+        int32_t *row_c = cc.take<int32_t>(n_ent);
+        float *val_c = cc.take<float>(n_ent);
+        if (need + cc.size() <= ws_bytes) {
+            LAUE_CHECK_HIP(hipMemcpyAsync(row_c, lbar_row, n_ent * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+            LAUE_CHECK_HIP(hipMemcpyAsync(val_c, lbar_val, n_ent * sizeof(float), hipMemcpyDeviceToDevice, s));
+            row = row_c;
+            val = val_c;
+            compact = true;
+        }
+    }
+    return greedy_run(lbar_off, row, val, compact, n_cand, n_rows, phi, k_max, picks, gains, n_picked, w, s);
+}
+
+namespace laue {
+int spot_greedy_inplace(const int64_t *lbar_off, int32_t *lbar_row, float *lbar_val, int32_t n_cand,
+                        int64_t n_rows, double phi, int32_t k_max, int32_t *picks, double *gains,
+                        int32_t *n_picked, void *ws, size_t ws_bytes, void *stream) {
+    clear_error();
+    int rc;
+    GREEDY_ARGS_OK();
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    Carver cv(ws);
+    GreedyWs w;
+    const size_t need = carve_greedy(cv, w, n_cand, n_rows);
+    if ((rc = check_ws(ws, ws_bytes, need))) return rc;
+    return greedy_run(lbar_off, lbar_row, lbar_val, true, n_cand, n_rows, phi, k_max, picks, gains, n_picked, w, s);
+}
+}  // namespace laue

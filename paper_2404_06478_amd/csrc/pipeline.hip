@@ -308,7 +308,8 @@ int index_front(const laue_geometry *geom, const laue_planes *planes, const laue
     int32_t n_picked = 0;
     if (n_sc > 0) {
         const double phi = -par->score.c_out / (2.0 * par->score.sigma_mm * par->score.sigma_mm);
-        if ((rc = laue_spot_greedy(w.loff, w.lrow, w.lval, static_cast<int32_t>(n_sc), obs->n, phi, par->k_max,
+        // the SPOT matrix is not read after the selection: compacted in place
+        if ((rc = spot_greedy_inplace(w.loff, w.lrow, w.lval, static_cast<int32_t>(n_sc), obs->n, phi, par->k_max,
                                    w.picks, w.gains, &n_picked, w.scratch, w.scratch_bytes, stream)))
             return rc;
     }

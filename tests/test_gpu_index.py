@@ -51,7 +51,7 @@ def test_candidates_match_oracle(gpu_lib):
 @pytest.mark.parametrize("drop_log2", [0.0, 26.0])
 def test_refine_score_match_oracle(gpu_lib, drop_log2):
     """Refinement and scoring against the oracle (which keeps every pair), with
-    the passes skipping only FP32-zero terms (0) and terms below 2^-40 of the
+    the passes skipping only FP32-zero terms (0) and terms below 2^-26 of the
     outlier bin's (the default)."""
     laue = gpu_lib
     p, pl, g, q, x, sim, p12, geom, planes, obs = _setup(laue)
