@@ -592,12 +592,14 @@ def laue_score_candidates(geom, planes, obs, cand, par, lbar_cap=None):
     return res
 
 
-def laue_spot_greedy(lbar_off, lbar_row, lbar_val, n_cand, n_rows, phi, k_max):
+def laue_spot_greedy(lbar_off, lbar_row, lbar_val, n_cand, n_rows, phi, k_max, compact=True):
+    """compact: give the library room for a copy of the entries, which the
+    selection compacts (the picks and increments are the same either way)."""
     import torch
     lib = require_native()
     dev = _dev()
-    # the minimum plus room for a copy of the entries, which the selection compacts
-    ws = _workspace(lib.laue_spot_greedy_workspace_size(int(n_cand), int(n_rows)) + 8 * int(lbar_row.numel()) + 1024)
+    extra = 8 * int(lbar_row.numel()) + 1024 if compact else 0
+    ws = _workspace(lib.laue_spot_greedy_workspace_size(int(n_cand), int(n_rows)) + extra)
     picks = torch.zeros(max(int(k_max), 1), dtype=torch.int32, device=dev)
     gains = torch.zeros(max(int(k_max), 1), dtype=torch.float64, device=dev)
     npk = C.c_int32()

@@ -125,7 +125,8 @@ def test_greedy_matches_oracle(gpu_lib):
     assert single.n_prototypes(gg.cpu().numpy()) == single.n_prototypes(gains)
 
 
-def test_band_greedy_matches_oracle_many_candidates(gpu_lib):
+@pytest.mark.parametrize("compact", [True, False])
+def test_band_greedy_matches_oracle_many_candidates(gpu_lib, compact):
     """Hundreds of overlapping candidates, exact duplicates among them (ties
     go to the lowest index): the band steps (stale increments as upper
     bounds) pick exactly what the plain greedy picks, with the same gains."""
@@ -147,12 +148,13 @@ def test_band_greedy_matches_oracle_many_candidates(gpu_lib):
     vals = np.concatenate([c[1] for c in cols]).astype(np.float32)
     dev = torch.device("cuda")
     gp, gg = laue.laue_spot_greedy(torch.tensor(off, device=dev), torch.tensor(rows, device=dev),
-                                   torch.tensor(vals, device=dev), len(cols), n_rows, phi, k_max)
+                                   torch.tensor(vals, device=dev), len(cols), n_rows, phi, k_max, compact=compact)
     assert gp.cpu().tolist() == picks
     assert np.allclose(gg.cpu().numpy(), gains, rtol=1e-9, atol=1e-9)
 
 
-def test_greedy_heavy_overlap_matches_oracle(gpu_lib):
+@pytest.mark.parametrize("compact", [True, False])
+def test_greedy_heavy_overlap_matches_oracle(gpu_lib, compact):
     """Every candidate covers a third of the rows, as under dense clutter: each
     pick lowers almost every other gain, so most bounds go stale at every step
     and the band steps recompute many of them; the picks and gains stay those
@@ -172,7 +174,7 @@ def test_greedy_heavy_overlap_matches_oracle(gpu_lib):
     vals = np.concatenate([c[1] for c in cols]).astype(np.float32)
     dev = torch.device("cuda")
     gp, gg = laue.laue_spot_greedy(torch.tensor(off, device=dev), torch.tensor(rows, device=dev),
-                                   torch.tensor(vals, device=dev), len(cols), n_rows, phi, k_max)
+                                   torch.tensor(vals, device=dev), len(cols), n_rows, phi, k_max, compact=compact)
     assert gp.cpu().tolist() == picks
     assert np.allclose(gg.cpu().numpy(), gains, rtol=1e-9, atol=1e-9)
 
