@@ -261,9 +261,16 @@ constexpr int kCellG = 32;
 constexpr int kCells = kCellG * kCellG;
 constexpr int kMaxRuns = 256;
 
-// Cell of a coordinate in cell units (row or column of the kCellG grid).
+// The per-model-spot pass walks a finer grid over the same boxes (cells a
+// quarter of the side), so that the cells under a small zero disk hold few
+// spots beyond it.
+constexpr int kFineG = 128;
+constexpr int kFineCells = kFineG * kFineG;
+
+// Cell of a coordinate in cell units (row or column of a G x G grid).
+template <int G = kCellG>
 __device__ __forceinline__ int cell_coord(float u) {
-    return u >= 0.0f ? min(kCellG - 1, static_cast<int>(fminf(u, static_cast<float>(kCellG)))) : 0;
+    return u >= 0.0f ? min(G - 1, static_cast<int>(fminf(u, static_cast<float>(G)))) : 0;
 }
 // Exponent (log2 units) beyond which an FP32 plan term exp2(-K c') is 0 for
 // any rounding of c' (2^-150 already rounds to 0; the margin covers the cost's
@@ -287,6 +294,8 @@ struct SlotArgs {
     // cell) start positions [nb * kCells + 1], per-block grid (x0, y0, cx, cy)
     const float *P1s, *P2s;
     const float2 *P12s;     // the same, interleaved
+    const float2 *P12f;     // the spots in the order of the fine grid (kFineG)
+    const int *cell_off_f;  // [nb * kFineCells + 1]
     const int *cell_off;
     const float4 *cbox;
     unsigned long long *evaluated;   // pairs the refinement passes evaluate
@@ -677,12 +686,14 @@ __global__ __launch_bounds__(256) void k_spot_acc(SlotArgs A, float K, float bin
         // coordinate range, widened by a thousandth of a cell against the
         // rounding of the cell assignment), per cell row the chord of the
         // disk over that row's band
-        const float4 bx = A.cbox[b];
+        const float4 bc = A.cbox[b];
+        const float4 bx = make_float4(bc.x, bc.y, bc.z * (static_cast<float>(kCellG) / kFineG),
+                                      bc.w * (static_cast<float>(kCellG) / kFineG));
         const float R = sqrtf(R2);
         const float eps_c = 1e-3f;
-        const int iy0 = cell_coord((me.s2 - R - bx.y) / bx.w - eps_c);
-        const int iy1 = cell_coord((me.s2 + R - bx.y) / bx.w + eps_c);
-        const int *co = A.cell_off + static_cast<int64_t>(b) * kCells;
+        const int iy0 = cell_coord<kFineG>((me.s2 - R - bx.y) / bx.w - eps_c);
+        const int iy1 = cell_coord<kFineG>((me.s2 + R - bx.y) / bx.w + eps_c);
+        const int *co = A.cell_off_f + static_cast<int64_t>(b) * kFineCells;
         int n16 = 0;
         for (int iy = iy0; iy <= iy1; ++iy) {
             const float ya = bx.y + (static_cast<float>(iy) - eps_c) * bx.w;
@@ -690,11 +701,11 @@ __global__ __launch_bounds__(256) void k_spot_acc(SlotArgs A, float K, float bin
             const float dyb = fmaxf(0.0f, fmaxf(ya - me.s2, me.s2 - yb));
             if (!(dyb * dyb < R2)) continue;
             const float hw = sqrtf(R2 - dyb * dyb);
-            const int ix0 = cell_coord((me.s1 - hw - bx.x) / bx.z - eps_c);
-            const int ix1 = cell_coord((me.s1 + hw - bx.x) / bx.z + eps_c);
-            const int re = co[iy * kCellG + ix1 + 1];
-            for (int r = co[iy * kCellG + ix0]; r < re; ++r) {
-                const float2 pp = A.P12s[r];
+            const int ix0 = cell_coord<kFineG>((me.s1 - hw - bx.x) / bx.z - eps_c);
+            const int ix1 = cell_coord<kFineG>((me.s1 + hw - bx.x) / bx.z + eps_c);
+            const int re = co[iy * kFineG + ix1 + 1];
+            for (int r = co[iy * kFineG + ix0]; r < re; ++r) {
+                const float2 pp = A.P12f[r];
                 const float p1 = pp.x, p2 = pp.y;
                 const float dy = p1 - me.s1, dz = p2 - me.s2;
                 if (!(fmaf(dz, dz, dy * dy) < R2)) continue;
@@ -1349,7 +1360,9 @@ __global__ __launch_bounds__(256) void k_cell_box(const float *__restrict__ P1, 
     }
 }
 
-// Sort key of every detected spot: block * kCells + cell (row-major cells).
+// Sort key of every detected spot: block * G^2 + cell (row-major cells of
+// the G x G grid over the block's box; the box's cells are kCellG a side).
+template <int G>
 __global__ void k_cell_keys(const float *__restrict__ P1, const float *__restrict__ P2,
                             const int64_t *__restrict__ ooff, int nb, const float4 *__restrict__ box, int64_t n,
                             unsigned *__restrict__ key, int *__restrict__ idx) {
@@ -1361,9 +1374,10 @@ __global__ void k_cell_keys(const float *__restrict__ P1, const float *__restric
             if (ooff[mid] <= i) lo = mid;
             else hi = mid - 1;
         }
-        const float4 bx = box[lo];
-        const int ix = cell_coord((P1[i] - bx.x) / bx.z), iy = cell_coord((P2[i] - bx.y) / bx.w);
-        key[i] = static_cast<unsigned>(lo) * kCells + static_cast<unsigned>(iy * kCellG + ix);
+        const float4 bc = box[lo];
+        const float cx = bc.z * (static_cast<float>(kCellG) / G), cy = bc.w * (static_cast<float>(kCellG) / G);
+        const int ix = cell_coord<G>((P1[i] - bc.x) / cx), iy = cell_coord<G>((P2[i] - bc.y) / cy);
+        key[i] = static_cast<unsigned>(lo) * (G * G) + static_cast<unsigned>(iy * G + ix);
         idx[i] = static_cast<int>(i);
     }
 }
@@ -1380,7 +1394,16 @@ __global__ void k_cell_gather(const float *__restrict__ P1, const float *__restr
     }
 }
 
-// cell_off[t] = first position whose key is >= t, t = 0 .. nb * kCells.
+__global__ void k_cell_gather2(const float *__restrict__ P1, const float *__restrict__ P2,
+                               const int *__restrict__ idx, int64_t n, float2 *__restrict__ P12) {
+    for (int64_t k = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; k < n;
+         k += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+        const int i = idx[k];
+        P12[k] = make_float2(P1[i], P2[i]);
+    }
+}
+
+// cell_off[t] = first position whose key is >= t, t = 0 .. n_keys.
 __global__ void k_cell_off(const unsigned *__restrict__ key, int64_t n, int64_t n_keys, int *__restrict__ off) {
     for (int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; t <= n_keys;
          t += static_cast<int64_t>(gridDim.x) * blockDim.x) {
@@ -1405,7 +1428,9 @@ struct CellWs {
     int *idx_in, *idx_out;
     float *P1s, *P2s;
     float2 *P12s;
+    float2 *P12f;    // fine grid order
     int *off;
+    int *off_f;
     float4 *box;
     void *tmp;
     size_t tmp_bytes;
@@ -1420,7 +1445,9 @@ void carve_cells(Carver &cv, CellWs &w, int nb, int64_t n_obs) {
     w.P1s = cv.take<float>(n);
     w.P2s = cv.take<float>(n);
     w.P12s = cv.take<float2>(n);
+    w.P12f = cv.take<float2>(n);
     w.off = cv.take<int>(static_cast<int64_t>(nb) * kCells + 1);
+    w.off_f = cv.take<int>(static_cast<int64_t>(nb) * kFineCells + 1);
     w.box = cv.take<float4>(nb);
     size_t tmp = 0;
     (void)hipcub::DeviceRadixSort::SortPairs(nullptr, tmp, static_cast<unsigned *>(nullptr),
@@ -1435,22 +1462,32 @@ int build_cells(CellWs &w, const laue_obs_spots *obs, const int64_t *ooff_dev, i
     const int64_t n = obs->n;
     k_cell_box<<<nb, 256, 0, s>>>(obs->p1, obs->p2, ooff_dev, w.box);
     LAUE_CHECK_HIP(hipGetLastError());
-    const int64_t n_keys = static_cast<int64_t>(nb) * kCells;
-    if (n > 0) {
-        const unsigned g = static_cast<unsigned>(std::min<int64_t>((n + 255) / 256, 4096));
-        k_cell_keys<<<g, 256, 0, s>>>(obs->p1, obs->p2, ooff_dev, nb, w.box, n, w.key_in, w.idx_in);
-        LAUE_CHECK_HIP(hipGetLastError());
-        int end_bit = 1;
-        while (end_bit < 32 && (int64_t(1) << end_bit) <= n_keys) ++end_bit;
-        size_t tb = w.tmp_bytes;
-        LAUE_CHECK_HIP(hipcub::DeviceRadixSort::SortPairs(w.tmp, tb, w.key_in, w.key_out, w.idx_in, w.idx_out,
-                                                         static_cast<int>(n), 0, end_bit, s));
-        k_cell_gather<<<g, 256, 0, s>>>(obs->p1, obs->p2, w.idx_out, n, w.P1s, w.P2s, w.P12s);
+    // the kCellG grid (per-(block, candidate) passes), then the kFineG grid
+    // (per-model-spot pass); both sorts are stable
+    for (int fine = 0; fine < 2; ++fine) {
+        const int64_t n_keys = static_cast<int64_t>(nb) * (fine ? kFineCells : kCells);
+        if (n > 0) {
+            const unsigned g = static_cast<unsigned>(std::min<int64_t>((n + 255) / 256, 4096));
+            if (fine)
+                k_cell_keys<kFineG><<<g, 256, 0, s>>>(obs->p1, obs->p2, ooff_dev, nb, w.box, n, w.key_in, w.idx_in);
+            else
+                k_cell_keys<kCellG><<<g, 256, 0, s>>>(obs->p1, obs->p2, ooff_dev, nb, w.box, n, w.key_in, w.idx_in);
+            LAUE_CHECK_HIP(hipGetLastError());
+            int end_bit = 1;
+            while (end_bit < 32 && (int64_t(1) << end_bit) <= n_keys) ++end_bit;
+            size_t tb = w.tmp_bytes;
+            LAUE_CHECK_HIP(hipcub::DeviceRadixSort::SortPairs(w.tmp, tb, w.key_in, w.key_out, w.idx_in, w.idx_out,
+                                                             static_cast<int>(n), 0, end_bit, s));
+            if (fine)
+                k_cell_gather2<<<g, 256, 0, s>>>(obs->p1, obs->p2, w.idx_out, n, w.P12f);
+            else
+                k_cell_gather<<<g, 256, 0, s>>>(obs->p1, obs->p2, w.idx_out, n, w.P1s, w.P2s, w.P12s);
+            LAUE_CHECK_HIP(hipGetLastError());
+        }
+        const unsigned go = static_cast<unsigned>(std::min<int64_t>((n_keys + 1 + 255) / 256, 4096));
+        k_cell_off<<<go, 256, 0, s>>>(w.key_out, n, n_keys, fine ? w.off_f : w.off);
         LAUE_CHECK_HIP(hipGetLastError());
     }
-    const unsigned go = static_cast<unsigned>(std::min<int64_t>((n_keys + 1 + 255) / 256, 4096));
-    k_cell_off<<<go, 256, 0, s>>>(w.key_out, n, n_keys, w.off);
-    LAUE_CHECK_HIP(hipGetLastError());
     return LAUE_OK;
 }
 
@@ -1624,6 +1661,8 @@ extern "C" int laue_score_candidates(const laue_geometry *geom, const laue_plane
         A.P1s = w.cells.P1s;
         A.P2s = w.cells.P2s;
         A.P12s = w.cells.P12s;
+        A.P12f = w.cells.P12f;
+        A.cell_off_f = w.cells.off_f;
         A.cell_off = w.cells.off;
         A.cbox = w.cells.box;
         A.evaluated = pairs + 2;
