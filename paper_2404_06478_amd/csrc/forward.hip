@@ -10,6 +10,8 @@ namespace laue {
 constexpr int kMaxPlanes = 1024;
 constexpr int kEnumChunk = 16;   // grains per enumerate work item
 constexpr int kEmitList = 2048;  // LDS list of the write pass (>= the bits of 64 mask words)
+// a write-pass list entry: grain in chunk << 10 | plane, in 16 bits
+static_assert(kMaxPlanes <= 1024 && kEnumChunk <= 64, "write-pass list entries are 16 bits");
 
 // ---------------------------------------------------------------- grains
 
@@ -152,12 +154,12 @@ __global__ __launch_bounds__(64) void k_enumerate(
     }
 }
 
-// Evaluates and writes the cnt listed (grain in chunk << 16 | plane) entries
+// Evaluates and writes the cnt listed (grain in chunk << 10 | plane) entries
 // of detector d at base, base + 1, ... with every lane; the list is read after
 // a barrier and may be refilled after the closing one.
 __device__ __forceinline__ void emit_list(const GeomF &G, const float *__restrict__ W, const float *__restrict__ Dsp,
                                           const GrainF *__restrict__ grains, int n_lo, int t, int d, float c, float s,
-                                          const int *elist, int cnt, int64_t base, int *__restrict__ o_plane,
+                                          const uint16_t *elist, int cnt, int64_t base, int *__restrict__ o_plane,
                                           int *__restrict__ o_grain, int *__restrict__ o_block,
                                           float *__restrict__ o_s1, float *__restrict__ o_s2,
                                           float *__restrict__ o_vn, float *__restrict__ o_v1,
@@ -166,7 +168,7 @@ __device__ __forceinline__ void emit_list(const GeomF &G, const float *__restric
     __syncthreads();
     for (int k = static_cast<int>(threadIdx.x); k < cnt; k += 64) {
         const int e = elist[k];
-        const int nn = n_lo + (e >> 16), m = e & 0xffff;
+        const int nn = n_lo + (e >> 10), m = e & 1023;
         const GrainF &g2 = grains[nn];
         const SpotGeo o = spot_geometry(G, G.det[d], g2.R, g2.x, c, s, W[3 * m], W[3 * m + 1], W[3 * m + 2], Dsp[m]);
         const int64_t pos = base + k;
@@ -188,7 +190,8 @@ __device__ __forceinline__ void emit_list(const GeomF &G, const float *__restric
 
 // Write pass from the count pass's kept-plane bits (kmask, W32 words per (t,
 // n) item and detector): per work item (rotation t, kEnumChunk grains), the
-// chunk's mask words in one coalesced load to LDS (they are contiguous), then
+// chunk's mask words in one coalesced load to LDS (they are contiguous; dynamic
+// LDS of kEnumChunk x n_det x W32 words), then
 // detector by detector the kept (grain, plane) pairs listed in LDS in output
 // order (ballot compaction) and evaluated and written by every lane: for one
 // detector the chunk's outputs are one contiguous range (offsets in (t, d, n)
@@ -202,8 +205,8 @@ __global__ __launch_bounds__(64) void k_enumerate_emit(
     const GeomF &G = *Gp;
     const int lane = threadIdx.x;
     const int D = G.n_det;
-    __shared__ unsigned mw[kEnumChunk * 2 * (kMaxPlanes / 32)];
-    __shared__ int elist[kEmitList];
+    extern __shared__ unsigned mw[];
+    __shared__ uint16_t elist[kEmitList];
     const int64_t n_chunks = (static_cast<int64_t>(N) + kEnumChunk - 1) / kEnumChunk;
     const int64_t n_work = n_chunks * T;
     for (int64_t wi = blockIdx.x; wi < n_work; wi += gridDim.x) {
@@ -246,7 +249,8 @@ __global__ __launch_bounds__(64) void k_enumerate_emit(
                     cnt = 0;
                 }
                 int q = cnt + incl - pc;
-                for (unsigned wb = word; wb; wb &= wb - 1u) elist[q++] = (nrel << 16) | (w * 32 + __ffs(wb) - 1);
+                for (unsigned wb = word; wb; wb &= wb - 1u)
+                    elist[q++] = static_cast<uint16_t>((nrel << 10) | (w * 32 + __ffs(wb) - 1));
                 cnt += total;
             }
             if (cnt > 0)
@@ -532,7 +536,8 @@ int launch_emit(const laue_geometry *geom, const laue_planes *planes, EnumWs &w,
                 uint8_t *flags, hipStream_t s) {
     if (N == 0) return LAUE_OK;
     if (w.mask_ready)
-        k_enumerate_emit<<<enum_grid(N, geom->n_rot), 64, 0, s>>>(
+        k_enumerate_emit<<<enum_grid(N, geom->n_rot), 64,
+                           static_cast<size_t>(kEnumChunk) * geom->n_det * w.w32 * sizeof(unsigned), s>>>(
             w.geom, planes->w, planes->d, planes->n, w.grains, N, geom->n_rot, w.offs, plane, grain, block, s1, s2,
             vn, v1, v2, lam, flags, w.kmask, w.w32);
     else
