@@ -334,19 +334,33 @@ __device__ __forceinline__ Col8 col_of(const LaneCol &c, int j) {
 // with sqrt(|v|^2 |d|^2) = |v| |d|), the plan entry Q = exp2(-K c') iz, and
 // the statistics of accumulate_stats (whose |d| - |v| numerator is the same
 // w).  Adds the statistics when Q > 0.
-__device__ __forceinline__ void spot_entry_stats(float *a, float p1, float p2, const Col8 &c, float vlen, float rn,
-                                                 float r1, float r2, float K, float iz) {
-    const float dy = p1 - c.s1, dz = p2 - c.s2;
-    const float e = fmaf(dz, dz, dy * dy);
-    const float bb = fmaf(c.v2, dz, c.v1 * dy);
-    const float w = fmaf(2.0f, bb, e);
-    const float dd = c.vv + w;
-    const float itau = __builtin_amdgcn_rsqf(dd);
-    const float tau = dd * itau;
+// The pair's intermediates, formed once: its plan term t = exp2(-K c') (the
+// row normaliser's own term) and what the statistics need.
+struct PairTerm {
+    float dy, dz, w, itau, tau, t;
+};
+
+__device__ __forceinline__ PairTerm pair_term(float p1, float p2, const Col8 &c, float vlen, float K) {
+    PairTerm q;
+    q.dy = p1 - c.s1;
+    q.dz = p2 - c.s2;
+    const float e = fmaf(q.dz, q.dz, q.dy * q.dy);
+    const float bb = fmaf(c.v2, q.dz, c.v1 * q.dy);
+    q.w = fmaf(2.0f, bb, e);
+    const float dd = c.vv + q.w;
+    q.itau = __builtin_amdgcn_rsqf(dd);
+    q.tau = dd * q.itau;
     const float x2 = fmaf(c.vv, e, -(bb * bb));
-    const float den = fmaf((c.vv + bb) * vlen, tau, c.vv * dd);
-    const float Q = fast_exp2(-K * (x2 * __builtin_amdgcn_rcpf(den))) * iz;
+    const float den = fmaf((c.vv + bb) * vlen, q.tau, c.vv * dd);
+    q.t = fast_exp2(-K * (x2 * __builtin_amdgcn_rcpf(den)));
+    return q;
+}
+
+// Statistics of a pair with plan entry Q = t / (row normaliser).
+__device__ __forceinline__ void spot_entry_stats(float *a, const PairTerm &pt, const Col8 &c, float vlen, float rn,
+                                                 float r1, float r2, float Q) {
     if (!(Q > 0.0f)) return;
+    const float dy = pt.dy, dz = pt.dz, w = pt.w, itau = pt.itau, tau = pt.tau;
     const float dl = w * __builtin_amdgcn_rcpf(tau + vlen);
     const float e0 = (-rn * dl) * itau;
     const float e1 = fmaf(-r1, dl, dy) * itau;
@@ -660,8 +674,9 @@ __global__ void k_spot_nbr(SlotArgs A, const float *__restrict__ rad2, int64_t M
 // box, those within R_o of s_o, each with its row normaliser (the bin term,
 // then the terms of the slot's spots that reach the row, in index order: a
 // spot out of reach adds less than a quarter ulp, so the normaliser is the
-// one over every spot of the slot), accumulated in FP32 over 16 rows at a
-// time and in FP64 across.  Writes o's kStat statistics.
+// one over every spot of the slot; o's own term is the one its statistics
+// use), accumulated in FP32 over 16 rows at a time and in FP64 across.
+// Writes o's kStat statistics.
 __global__ __launch_bounds__(256) void k_spot_acc(SlotArgs A, float K, float bin_e, const float *__restrict__ rad2,
                                                   const unsigned long long *__restrict__ nbr, int64_t M,
                                                   double *__restrict__ st_out) {
@@ -710,11 +725,12 @@ __global__ __launch_bounds__(256) void k_spot_acc(SlotArgs A, float K, float bin
                 const float dy = p1 - me.s1, dz = p2 - me.s2;
                 if (!(fmaf(dz, dz, dy * dy) < R2)) continue;
                 ++evaluated;
+                const PairTerm pt = pair_term(p1, p2, me, vl, K);
                 float z = bin_e;
                 for (unsigned long long m = mask; m; m &= m - 1) {
                     const int64_t j = o0 + __builtin_ctzll(m);
                     if (j == o) {
-                        z += fast_exp2(entry_exponent(p1, p2, me.s1, me.s2, me.v1, me.v2, me.vv, me.vv2, K, 0.0f));
+                        z += pt.t;
                     } else {
                         const Col8 cj = A.colsE[j];
                         const float ey = p1 - cj.s1, ez = p2 - cj.s2;
@@ -723,7 +739,7 @@ __global__ __launch_bounds__(256) void k_spot_acc(SlotArgs A, float K, float bin
                                                           0.0f));
                     }
                 }
-                spot_entry_stats(a, p1, p2, me, vl, rn, r1, r2, K, __builtin_amdgcn_rcpf(z));
+                spot_entry_stats(a, pt, me, vl, rn, r1, r2, pt.t * __builtin_amdgcn_rcpf(z));
                 if (++n16 == 16) {
 #pragma unroll
                     for (int q = 0; q < kStat; ++q) {
