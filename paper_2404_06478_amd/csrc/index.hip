@@ -719,9 +719,15 @@ __global__ __launch_bounds__(256) void k_spot_acc(SlotArgs A, float K, float bin
             const int ix0 = cell_coord<kFineG>((me.s1 - hw - bx.x) / bx.z - eps_c);
             const int ix1 = cell_coord<kFineG>((me.s1 + hw - bx.x) / bx.z + eps_c);
             const int re = co[iy * kFineG + ix1 + 1];
-            for (int r = co[iy * kFineG + ix0]; r < re; ++r) {
-                const float2 pp = A.P12f[r];
-                const float p1 = pp.x, p2 = pp.y;
+            // four rows' loads in flight before the first is used
+            for (int r0 = co[iy * kFineG + ix0]; r0 < re; r0 += 4) {
+                float2 pq[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+                    pq[u] = r0 + u < re ? A.P12f[r0 + u] : make_float2(INFINITY, INFINITY);
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                const float p1 = pq[u].x, p2 = pq[u].y;
                 const float dy = p1 - me.s1, dz = p2 - me.s2;
                 if (!(fmaf(dz, dz, dy * dy) < R2)) continue;
                 ++evaluated;
@@ -747,6 +753,7 @@ __global__ __launch_bounds__(256) void k_spot_acc(SlotArgs A, float K, float bin
                         a[q] = 0.0f;
                     }
                     n16 = 0;
+                }
                 }
             }
         }
