@@ -704,10 +704,14 @@ __global__ __launch_bounds__(256) void k_spot_acc(SlotArgs A, float K, float bin
         const float4 bc = A.cbox[b];
         const float4 bx = make_float4(bc.x, bc.y, bc.z * (static_cast<float>(kCellG) / kFineG),
                                       bc.w * (static_cast<float>(kCellG) / kFineG));
-        const float R = sqrtf(R2);
+        // hardware sqrt and reciprocal (an ulp or two): the ranges are
+        // widened by eps_c cells, far beyond that; the reach test below is
+        // exact
+        const float R = __builtin_amdgcn_sqrtf(R2);
         const float eps_c = 1e-3f;
-        const int iy0 = cell_coord<kFineG>((me.s2 - R - bx.y) / bx.w - eps_c);
-        const int iy1 = cell_coord<kFineG>((me.s2 + R - bx.y) / bx.w + eps_c);
+        const float icx = __builtin_amdgcn_rcpf(bx.z), icy = __builtin_amdgcn_rcpf(bx.w);
+        const int iy0 = cell_coord<kFineG>((me.s2 - R - bx.y) * icy - eps_c);
+        const int iy1 = cell_coord<kFineG>((me.s2 + R - bx.y) * icy + eps_c);
         const int *co = A.cell_off_f + static_cast<int64_t>(b) * kFineCells;
         int n16 = 0;
         for (int iy = iy0; iy <= iy1; ++iy) {
@@ -715,9 +719,9 @@ __global__ __launch_bounds__(256) void k_spot_acc(SlotArgs A, float K, float bin
             const float yb = bx.y + (static_cast<float>(iy + 1) + eps_c) * bx.w;
             const float dyb = fmaxf(0.0f, fmaxf(ya - me.s2, me.s2 - yb));
             if (!(dyb * dyb < R2)) continue;
-            const float hw = sqrtf(R2 - dyb * dyb);
-            const int ix0 = cell_coord<kFineG>((me.s1 - hw - bx.x) / bx.z - eps_c);
-            const int ix1 = cell_coord<kFineG>((me.s1 + hw - bx.x) / bx.z + eps_c);
+            const float hw = __builtin_amdgcn_sqrtf(R2 - dyb * dyb);
+            const int ix0 = cell_coord<kFineG>((me.s1 - hw - bx.x) * icx - eps_c);
+            const int ix1 = cell_coord<kFineG>((me.s1 + hw - bx.x) * icx + eps_c);
             const int re = co[iy * kFineG + ix1 + 1];
             // four rows' loads in flight before the first is used
             for (int r0 = co[iy * kFineG + ix0]; r0 < re; r0 += 4) {
