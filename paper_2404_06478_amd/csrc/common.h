@@ -391,28 +391,38 @@ __device__ inline void gn_solve_apply(const double *acc, double mu_rel, double *
                                       GrainF *gf, double *step_norm) {
     double H[6][6], gv[6];
     int c = 0;
+#pragma unroll
     for (int a = 0; a < 6; ++a)
+#pragma unroll
         for (int b = a; b < 6; ++b) {
             H[a][b] = acc[c];
             H[b][a] = acc[c];
             ++c;
         }
+#pragma unroll
     for (int a = 0; a < 6; ++a) gv[a] = acc[21 + a];
     double tr = 0.0;
+#pragma unroll
     for (int a = 0; a < 6; ++a) tr += H[a][a];
     double step[6] = {0, 0, 0, 0, 0, 0};
     bool ok = tr > 1e-300 && isfinite(tr);
     if (ok) {
         const double mu = mu_rel * tr / 6.0;
         for (int a = 0; a < 6; ++a) H[a][a] += mu;
+        // fully unrolled (the factors stay in registers): a non-positive
+        // pivot clears ok and the factorisation runs on with a unit pivot,
+        // its result discarded
         double L[6][6] = {};
-        for (int a = 0; a < 6 && ok; ++a) {
+#pragma unroll
+        for (int a = 0; a < 6; ++a) {
+#pragma unroll
             for (int b = 0; b <= a; ++b) {
                 double s = H[a][b];
+#pragma unroll
                 for (int k = 0; k < b; ++k) s -= L[a][k] * L[b][k];
                 if (a == b) {
-                    if (!(s > 0.0)) { ok = false; break; }
-                    L[a][a] = sqrt(s);
+                    ok = ok && s > 0.0;
+                    L[a][a] = sqrt(s > 0.0 ? s : 1.0);
                 } else {
                     L[a][b] = s / L[b][b];
                 }
@@ -420,13 +430,17 @@ __device__ inline void gn_solve_apply(const double *acc, double mu_rel, double *
         }
         if (ok) {
             double y[6];
+#pragma unroll
             for (int a = 0; a < 6; ++a) {
                 double s = -gv[a];
+#pragma unroll
                 for (int k = 0; k < a; ++k) s -= L[a][k] * y[k];
                 y[a] = s / L[a][a];
             }
+#pragma unroll
             for (int a = 5; a >= 0; --a) {
                 double s = y[a];
+#pragma unroll
                 for (int k = a + 1; k < 6; ++k) s -= L[k][a] * step[k];
                 step[a] = s / L[a][a];
             }
