@@ -166,6 +166,22 @@ int laue_forward_enumerate(const laue_geometry *geom, const laue_planes *planes,
                            laue_model_spots *out, int64_t *n_out,
                            void *ws, size_t ws_bytes, void *stream);
 
+/* The write half of laue_forward_enumerate (Eq. model_spot_cut), for a call
+ * that follows one of laue_forward_enumerate on the same workspace (typically
+ * the capacity query, out->n = 0, that returned LAUE_ECAPACITY): the counts,
+ * offsets and kept-plane bits that call left in ws are written out without
+ * counting again.  geom, planes, grains (the same arrays) and merge_harmonics
+ * must be those of that call; the library checks the sizes, the geometry and
+ * the array pointers (LAUE_EINVAL on a mismatch, or when the workspace holds
+ * no count), but not their contents: neither the grain arrays nor the
+ * workspace may change in between (no other call on ws).  Capacity,
+ * *n_out, out->block_off and the result are as for laue_forward_enumerate.
+ * Synchronous. */
+int laue_forward_enumerate_counted(const laue_geometry *geom, const laue_planes *planes,
+                                   const laue_grains *grains, int merge_harmonics,
+                                   laue_model_spots *out, int64_t *n_out,
+                                   void *ws, size_t ws_bytes, void *stream);
+
 /* Forward model on a frozen list (Sec. 4.2: the model-spot set is fixed at
  * the prototypes): recomputes s1, s2, vn, v1, v2 (and lam) of every spot of
  * `spots` from its (plane, grain, block) at the given grains; no filtering. */

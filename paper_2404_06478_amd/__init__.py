@@ -230,14 +230,31 @@ def laue_forward_enumerate(geom, planes, grains, merge_harmonics=True):
     if rc == _abi.LAUE_ECAPACITY:
         out = ModelSpots(nout.value, nb)
         s = out.struct()
-        rc = lib.laue_forward_enumerate(C.byref(geom), C.byref(ps_planes), C.byref(ps_grains),
-                                        int(bool(merge_harmonics)), C.byref(s), C.byref(nout),
-                                        _ptr(ws), ws.numel(), _stream())
+        rc = lib.laue_forward_enumerate_counted(C.byref(geom), C.byref(ps_planes), C.byref(ps_grains),
+                                                int(bool(merge_harmonics)), C.byref(s), C.byref(nout),
+                                                _ptr(ws), ws.numel(), _stream())
         _check(rc)
         return out
     _check(rc)
     probe.block_off[:] = np.zeros(nb + 1, np.int64)
     return probe
+
+
+def laue_forward_count(geom, planes, grains, merge_harmonics=True):
+    """Number of visible reflections (the count of laue_forward_enumerate,
+    no spot written)."""
+    lib = require_native()
+    ws = _workspace(lib.laue_forward_workspace_size(C.byref(geom), planes.n, grains.n))
+    probe = ModelSpots(0, n_blocks(geom))
+    ps = probe.struct()
+    ps.n = 0
+    nout = C.c_int64()
+    rc = lib.laue_forward_enumerate(C.byref(geom), C.byref(planes.struct), C.byref(grains.struct),
+                                    int(bool(merge_harmonics)), C.byref(ps), C.byref(nout),
+                                    _ptr(ws), ws.numel(), _stream())
+    if rc != _abi.LAUE_ECAPACITY:
+        _check(rc)
+    return int(nout.value)
 
 
 def laue_forward_eval(geom, planes, grains, model):
@@ -252,8 +269,7 @@ def laue_forward_eval(geom, planes, grains, model):
 def laue_simulate(geom, planes, truth, sigma_mm, distance, outlier_frac, seed):
     import torch
     lib = require_native()
-    probe = laue_forward_enumerate(geom, planes, truth, True)
-    n_true = probe.n
+    n_true = laue_forward_count(geom, planes, truth, True)
     # capacity: true spots + outliers (frac * n_true rounded per block, + 1 per block)
     cap = int(n_true * (1.0 + outlier_frac)) + n_blocks(geom) + 1
     ws = _workspace(lib.laue_simulate_workspace_size(C.byref(geom), planes.n, truth.n, n_true, cap))

@@ -174,6 +174,8 @@ SIGNATURES = {
     "laue_forward_workspace_size": (C.c_size_t, [P(laue_geometry), C.c_int32, C.c_int32]),
     "laue_forward_enumerate": (C.c_int, [P(laue_geometry), P(laue_planes), P(laue_grains), C.c_int,
                                          P(laue_model_spots), P(C.c_int64), vp, C.c_size_t, vp]),
+    "laue_forward_enumerate_counted": (C.c_int, [P(laue_geometry), P(laue_planes), P(laue_grains), C.c_int,
+                                                 P(laue_model_spots), P(C.c_int64), vp, C.c_size_t, vp]),
     "laue_forward_eval": (C.c_int, [P(laue_geometry), P(laue_planes), P(laue_grains),
                                     P(laue_model_spots), vp, C.c_size_t, vp]),
     "laue_simulate_workspace_size": (C.c_size_t, [P(laue_geometry), C.c_int32, C.c_int32, C.c_int64,

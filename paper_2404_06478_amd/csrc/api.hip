@@ -99,7 +99,7 @@ void make_geomf(const laue_geometry *g, GeomF *o) {
 
 using namespace laue;
 
-extern "C" int laue_version(void) { return 100; }
+extern "C" int laue_version(void) { return 200; }
 
 extern "C" const char *laue_last_error(void) { return g_err.c_str(); }
 

@@ -705,8 +705,10 @@ int prep_grains(const laue_grains *g, GrainF *dst, hipStream_t s);
 int launch_eval(const GeomF *dG, const laue_planes *pl, const GrainF *dgr, int n_grains,
                 const int *plane, const int *grain, const int *block, int64_t n, float *s1,
                 float *s2, float *vn, float *v1, float *v2, float *lam, Col8 *cols, hipStream_t s);
+// Write pass of the enumerate (ids only) after enumerate_count on the same
+// workspace; n_total is the count's total (the length of the id arrays).
 int launch_enumerate_ids(const laue_geometry *geom, const laue_planes *planes, EnumWs &w, int N,
-                         int merge, int *plane, int *grain, int *block, hipStream_t s);
+                         int merge, int64_t n_total, int *plane, int *grain, int *block, hipStream_t s);
 int validate_planes(const laue_planes *p);
 int validate_grains(const laue_grains *g);
 // exclusive scan of L ints into L + 1 int64 (one workgroup)

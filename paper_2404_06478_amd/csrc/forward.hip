@@ -2,6 +2,9 @@
 // (Sec. 3.3.1).
 #include <algorithm>
 #include <cmath>
+#include <cstring>
+#include <mutex>
+#include <vector>
 
 #include "common.h"
 
@@ -50,7 +53,7 @@ __global__ __launch_bounds__(64) void k_enumerate(
     int *__restrict__ o_grain, int *__restrict__ o_block, float *__restrict__ o_s1,
     float *__restrict__ o_s2, float *__restrict__ o_vn, float *__restrict__ o_v1,
     float *__restrict__ o_v2, float *__restrict__ o_lam, uint8_t *__restrict__ o_flags,
-    unsigned *__restrict__ kmask, int W32) {
+    unsigned *__restrict__ kmask, int W32, int64_t n_total) {
     const GeomF &G = *Gp;
     const int lane = threadIdx.x;
     // kmask (may be NULL): per item (t, n) and detector, W32 words of kept-plane
@@ -123,9 +126,10 @@ __global__ __launch_bounds__(64) void k_enumerate(
                     }
                     unsigned long long bal = __ballot(keep);
                     if (!pass && kmask && keep) atomicOr(&kbits[d * W32 + (m >> 5)], 1u << (m & 31));
-                    if (pass && keep) {
-                        unsigned long long lower = bal & ((1ull << lane) - 1ull);
-                        int64_t pos = base + running + __popcll(lower);
+                    const int64_t pos = base + running + __popcll(bal & ((1ull << lane) - 1ull));
+                    // (positions outside the output, which only offsets not
+                    // made by this set's count could give, are not written)
+                    if (pass && keep && pos >= 0 && pos < n_total) {
                         SpotGeo o = spot_geometry(G, G.det[d], gr.R, gr.x, c, s, W[3 * m], W[3 * m + 1],
                                                   W[3 * m + 2], Dsp[m]);
                         o_plane[pos] = m;
@@ -154,73 +158,218 @@ __global__ __launch_bounds__(64) void k_enumerate(
     }
 }
 
-// Evaluates and writes the cnt listed (grain in chunk << 10 | plane) entries
-// of detector d at base, base + 1, ... with every lane; the list is read after
-// a barrier and may be refilled after the closing one.
-__device__ __forceinline__ void emit_list(const GeomF &G, const float *__restrict__ W, const float *__restrict__ Dsp,
-                                          const GrainF *__restrict__ grains, int n_lo, int t, int d, float c, float s,
-                                          const uint16_t *elist, int cnt, int64_t base, int *__restrict__ o_plane,
-                                          int *__restrict__ o_grain, int *__restrict__ o_block,
-                                          float *__restrict__ o_s1, float *__restrict__ o_s2,
-                                          float *__restrict__ o_vn, float *__restrict__ o_v1,
-                                          float *__restrict__ o_v2, float *__restrict__ o_lam,
-                                          uint8_t *__restrict__ o_flags) {
-    __syncthreads();
-    for (int k = static_cast<int>(threadIdx.x); k < cnt; k += 64) {
-        const int e = elist[k];
-        const int nn = n_lo + (e >> 10), m = e & 1023;
-        const GrainF &g2 = grains[nn];
-        const SpotGeo o = spot_geometry(G, G.det[d], g2.R, g2.x, c, s, W[3 * m], W[3 * m + 1], W[3 * m + 2], Dsp[m]);
-        const int64_t pos = base + k;
-        o_plane[pos] = m;
-        o_grain[pos] = nn;
-        o_block[pos] = t * G.n_det + d;
-        if (o_s1) {
-            o_s1[pos] = o.s1;
-            o_s2[pos] = o.s2;
-            o_vn[pos] = o.vn;
-            o_v1[pos] = o.v1;
-            o_v2[pos] = o.v2;
-        }
-        if (o_lam) o_lam[pos] = o.lam;
-        if (o_flags) o_flags[pos] = o.flags;
+constexpr int kEmitPer = 2;
+constexpr int kDetFr = 13;   // floats of a detector frame (DetF) in the write pass's LDS table
+static_assert(sizeof(DetF) == kDetFr * sizeof(float), "DetF is 13 floats");
+
+// A wave-uniform value kept in scalar registers.
+__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+// Inclusive prefix sum over the 64 lanes of a wave by DPP moves: shifts
+// by 1, 2, 4 and 8 lanes within each row of 16, then the row broadcasts of
+// lane 15 (to rows 1 and 3) and lane 31 (to rows 2 and 3).
+__device__ __forceinline__ int wave_incl_scan(int v) {
+    v += __builtin_amdgcn_update_dpp(0, v, 0x111, 0xf, 0xf, false);   // row_shr:1
+    v += __builtin_amdgcn_update_dpp(0, v, 0x112, 0xf, 0xf, false);   // row_shr:2
+    v += __builtin_amdgcn_update_dpp(0, v, 0x114, 0xf, 0xf, false);   // row_shr:4
+    v += __builtin_amdgcn_update_dpp(0, v, 0x118, 0xf, 0xf, false);   // row_shr:8
+    v += __builtin_amdgcn_update_dpp(0, v, 0x142, 0xa, 0xf, false);   // row_bcast:15
+    v += __builtin_amdgcn_update_dpp(0, v, 0x143, 0xc, 0xf, false);   // row_bcast:31
+    return v;
+}
+__device__ __forceinline__ int64_t uni(int64_t v) {
+    const uint32_t lo = static_cast<uint32_t>(__builtin_amdgcn_readfirstlane(static_cast<int>(v)));
+    const uint32_t hi = static_cast<uint32_t>(__builtin_amdgcn_readfirstlane(static_cast<int>(v >> 32)));
+    return static_cast<int64_t>((static_cast<uint64_t>(hi) << 32) | lo);
+}
+
+// Output element idx of array a: a + b0 + off, where off (entries from b0)
+// is a 32-bit byte offset from a uniform base when NARROW (fewer than 2^30
+// entries from b0), else 64-bit.
+template <bool NARROW, typename T>
+__device__ __forceinline__ void emit_store(T *__restrict__ a, int64_t b0, int64_t off, T v) {
+    if constexpr (NARROW) {
+        char *base = reinterpret_cast<char *>(a + b0);
+        *reinterpret_cast<T *>(base + (static_cast<uint32_t>(off) * static_cast<uint32_t>(sizeof(T)))) = v;
+    } else {
+        a[b0 + off] = v;
     }
+}
+
+template <bool NARROW>
+__device__ __forceinline__ void emit_rows(const GeomF &G, const float *__restrict__ W, const float *__restrict__ Dsp,
+                                          const float *gsh, int n_lo, int t, float c, float s,
+                                          const uint16_t *elist, int cnt, int s1, int d0, int d1, int64_t b0,
+                                          int64_t delta, const float *dfr, int M,
+                                          int *__restrict__ o_plane, int *__restrict__ o_grain,
+                                          int *__restrict__ o_block, float *__restrict__ o_s1,
+                                          float *__restrict__ o_s2, float *__restrict__ o_vn,
+                                          float *__restrict__ o_v1, float *__restrict__ o_v2,
+                                          float *__restrict__ o_lam, uint8_t *__restrict__ o_flags) {
+    for (int k0 = 0; k0 < cnt; k0 += 64 * kEmitPer) {
+        int e[kEmitPer];
+        float wx[kEmitPer], wy[kEmitPer], wz[kEmitPer], ds[kEmitPer];
+#pragma unroll
+        for (int j = 0; j < kEmitPer; ++j) {
+            const int k = k0 + 64 * j + static_cast<int>(threadIdx.x);
+            e[j] = k < cnt ? elist[k] : 0;
+            const int m = min(e[j] & 1023, M - 1);        // (bits beyond the plane list are never set)
+            wx[j] = W[3 * m];
+            wy[j] = W[3 * m + 1];
+            wz[j] = W[3 * m + 2];
+            ds[j] = Dsp[m];
+        }
+#pragma unroll
+        for (int j = 0; j < kEmitPer; ++j) {
+            const int k = k0 + 64 * j + static_cast<int>(threadIdx.x);
+            if (k >= cnt) break;
+            const int nrel = e[j] >> 10, m = e[j] & 1023;
+            const bool hi = k >= s1;
+            const float *F = dfr + kDetFr * (hi ? d1 : d0);
+            DetF Dd;
+#pragma unroll
+            for (int r = 0; r < 3; ++r) {
+                Dd.c[r] = F[r];
+                Dd.n[r] = F[3 + r];
+                Dd.a1[r] = F[6 + r];
+                Dd.a2[r] = F[9 + r];
+            }
+            Dd.half = F[12];
+            const SpotGeo o = spot_geometry(G, Dd, gsh + 12 * nrel, gsh + 12 * nrel + 9, c, s, wx[j], wy[j], wz[j],
+                                            ds[j]);
+            const int64_t off = hi ? delta + k : k;
+            emit_store<NARROW>(o_plane, b0, off, m);
+            emit_store<NARROW>(o_grain, b0, off, n_lo + nrel);
+            emit_store<NARROW>(o_block, b0, off, t * G.n_det + (hi ? d1 : d0));
+            if (o_s1) {
+                emit_store<NARROW>(o_s1, b0, off, o.s1);
+                emit_store<NARROW>(o_s2, b0, off, o.s2);
+                emit_store<NARROW>(o_vn, b0, off, o.vn);
+                emit_store<NARROW>(o_v1, b0, off, o.v1);
+                emit_store<NARROW>(o_v2, b0, off, o.v2);
+            }
+            if (o_lam) emit_store<NARROW>(o_lam, b0, off, o.lam);
+            if (o_flags) emit_store<NARROW>(o_flags, b0, off, o.flags);
+        }
+    }
+}
+
+// Evaluates and writes the cnt listed (grain in chunk << 10 | plane) entries
+// of a work item, read after a barrier (the list may be refilled after the
+// closing one).  The list holds at most two detector runs: entries [0, s1) of
+// detector d0 go to b0, b0 + 1, ..., entries [s1, cnt) of detector d1 to b1,
+// b1 + 1, ... (b1 - s1 >= b0: detector d1's outputs follow d0's).  Every lane
+// takes kEmitPer entries at a time and gathers their planes before it writes
+// anything: on this chip one counter tracks both the loads and the stores of
+// a wave, so a gather issued after a store would also wait for that store to
+// complete.  The chunk's grains are in LDS (gsh).
+__device__ __forceinline__ void emit_list(const GeomF &G, const float *__restrict__ W, const float *__restrict__ Dsp,
+                                          int M, int64_t n_total, const float *gsh, const float *dfr, int n_lo,
+                                          int t, float c, float s,
+                                          const uint16_t *elist, int cnt, int s1, int d0, int d1, int64_t b0,
+                                          int64_t b1, int *__restrict__ o_plane, int *__restrict__ o_grain,
+                                          int *__restrict__ o_block, float *__restrict__ o_s1,
+                                          float *__restrict__ o_s2, float *__restrict__ o_vn,
+                                          float *__restrict__ o_v1, float *__restrict__ o_v2,
+                                          float *__restrict__ o_lam, uint8_t *__restrict__ o_flags) {
+    __syncthreads();
+    b0 = uni(b0);
+    const bool two = s1 <= cnt;
+    const int64_t delta = uni(two ? b1 - s1 - b0 : int64_t{0});
+    // the list's output ranges lie in [0, n_total) for offsets made by this
+    // set's count; a list that would leave it is not written
+    const bool inside = b0 >= 0 && b0 + (two ? s1 : cnt) <= n_total &&
+                        (!two || (b1 >= 0 && b1 + (cnt - s1) <= n_total));
+    if (!inside) {
+    } else if (delta >= 0 && delta + cnt < (int64_t{1} << 30))
+        emit_rows<true>(G, W, Dsp, gsh, n_lo, t, c, s, elist, cnt, s1, d0, d1, b0, delta, dfr, M, o_plane, o_grain,
+                        o_block, o_s1, o_s2, o_vn, o_v1, o_v2, o_lam, o_flags);
+    else
+        emit_rows<false>(G, W, Dsp, gsh, n_lo, t, c, s, elist, cnt, s1, d0, d1, b0, delta, dfr, M, o_plane, o_grain,
+                         o_block, o_s1, o_s2, o_vn, o_v1, o_v2, o_lam, o_flags);
     __syncthreads();
 }
 
 // Write pass from the count pass's kept-plane bits (kmask, W32 words per (t,
-// n) item and detector): per work item (rotation t, kEnumChunk grains), the
-// chunk's mask words in one coalesced load to LDS (they are contiguous; dynamic
-// LDS of kEnumChunk x n_det x W32 words), then
-// detector by detector the kept (grain, plane) pairs listed in LDS in output
-// order (ballot compaction) and evaluated and written by every lane: for one
-// detector the chunk's outputs are one contiguous range (offsets in (t, d, n)
-// order), written in coalesced runs.
+// n) item and detector; at most two detectors): per work item (rotation t,
+// kEnumChunk grains), the chunk's mask words, grains and per-detector output
+// offsets (all prefetched into registers while the previous item was
+// processed) go to LDS; then detector by detector the kept (grain, plane)
+// pairs are listed in LDS in output order (ballot compaction), and the list
+// of both detectors is evaluated and written by every lane: for one detector
+// the chunk's outputs are one contiguous range (offsets in (t, d, n) order),
+// written in coalesced runs.
+constexpr int kEmitPre = 6;   // mask words per lane prefetched (the rest, if any, load in place)
 __global__ __launch_bounds__(64) void k_enumerate_emit(
     const GeomF *__restrict__ Gp, const float *__restrict__ W, const float *__restrict__ Dsp, int M,
     const GrainF *__restrict__ grains, int N, int T, const int64_t *__restrict__ offs, int *__restrict__ o_plane,
     int *__restrict__ o_grain, int *__restrict__ o_block, float *__restrict__ o_s1, float *__restrict__ o_s2,
     float *__restrict__ o_vn, float *__restrict__ o_v1, float *__restrict__ o_v2, float *__restrict__ o_lam,
-    uint8_t *__restrict__ o_flags, const unsigned *__restrict__ kmask, int W32) {
+    uint8_t *__restrict__ o_flags, const unsigned *__restrict__ kmask, int W32, int64_t n_total) {
     const GeomF &G = *Gp;
     const int lane = threadIdx.x;
     const int D = G.n_det;
     extern __shared__ unsigned mw[];
     __shared__ uint16_t elist[kEmitList];
+    __shared__ float gsh[kEnumChunk * 12];
+    __shared__ int64_t bsh[2];
+    __shared__ float dfr[2 * kDetFr];      // the (at most two) detector frames
+    if (lane < D * kDetFr) dfr[lane] = G.det[lane / kDetFr].c[lane % kDetFr];
+    const float *gflat = reinterpret_cast<const float *>(grains);
     const int64_t n_chunks = (static_cast<int64_t>(N) + kEnumChunk - 1) / kEnumChunk;
     const int64_t n_work = n_chunks * T;
+    unsigned pm[kEmitPre];
+    float pg[3];
+    int64_t pb = 0;
+    auto prefetch = [&](int64_t wi) {
+        const int t = static_cast<int>(wi / n_chunks);
+        const int n_lo = static_cast<int>((wi % n_chunks) * kEnumChunk);
+        const int ng = std::min(N, n_lo + kEnumChunk) - n_lo;
+        const int n_words = ng * D * W32;
+        const unsigned *src = kmask + (static_cast<int64_t>(t) * N + n_lo) * D * W32;
+#pragma unroll
+        for (int j = 0; j < kEmitPre; ++j) {
+            const int k = lane + 64 * j;
+            pm[j] = k < n_words ? src[k] : 0u;
+        }
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            const int k = lane + 64 * j;
+            pg[j] = k < 12 * ng ? gflat[static_cast<int64_t>(n_lo) * 12 + k] : 0.0f;
+        }
+        pb = lane < D ? offs[(static_cast<int64_t>(t) * D + lane) * N + n_lo] : 0;
+    };
+    if (static_cast<int64_t>(blockIdx.x) < n_work) prefetch(blockIdx.x);
     for (int64_t wi = blockIdx.x; wi < n_work; wi += gridDim.x) {
         const int t = static_cast<int>(wi / n_chunks);
         const int n_lo = static_cast<int>((wi % n_chunks) * kEnumChunk);
         const int n_hi = std::min(N, n_lo + kEnumChunk);
         const float c = G.cs[t][0], s = G.cs[t][1];
         const int n_words = (n_hi - n_lo) * D * W32;
+#pragma unroll
+        for (int j = 0; j < kEmitPre; ++j) {
+            const int k = lane + 64 * j;
+            if (k < n_words) mw[k] = pm[j];
+        }
         const unsigned *src = kmask + (static_cast<int64_t>(t) * N + n_lo) * D * W32;
-        for (int k = lane; k < n_words; k += 64) mw[k] = src[k];
+        for (int k = 64 * kEmitPre + lane; k < n_words; k += 64) mw[k] = src[k];
+#pragma unroll
+        for (int j = 0; j < 3; ++j) gsh[lane + 64 * j] = pg[j];
+        if (lane < D) bsh[lane] = pb;
         __syncthreads();
+        if (wi + gridDim.x < n_work) prefetch(wi + gridDim.x);
+        // the list: run of detector d0 from b0, then (from entry s1) detector d1 from b1
+        int cnt = 0, s1 = kEmitList + 1, d0 = 0, d1 = 0;
+        int64_t b0 = 0, b1 = 0;
         for (int d = 0; d < D; ++d) {
-            int64_t base = offs[(static_cast<int64_t>(t) * D + d) * N + n_lo];
-            int cnt = 0;
+            if (cnt == 0) {
+                d0 = d;
+                b0 = uni(bsh[d]);
+                s1 = kEmitList + 1;
+            } else {
+                d1 = d;
+                b1 = uni(bsh[d]);
+                s1 = cnt;
+            }
             // the chunk's mask words of detector d in (grain, word) order, 64
             // at a time: each lane lists the set bits of its word at its
             // scanned position, so the list stays in (grain, plane) order
@@ -235,29 +384,28 @@ __global__ __launch_bounds__(64) void k_enumerate_emit(
                     word = mw[(nrel * D + d) * W32 + w];
                 }
                 const int pc = __popc(word);
-                int incl = pc;
-#pragma unroll
-                for (int o = 1; o < 64; o <<= 1) {
-                    const int y = __shfl_up(incl, o, 64);
-                    if (lane >= o) incl += y;
-                }
-                const int total = __shfl(incl, 63, 64);
+                const int incl = wave_incl_scan(pc);
+                const int total = __builtin_amdgcn_readlane(incl, 63);
                 if (cnt + total > kEmitList) {        // no room for this round: write the list out
-                    emit_list(G, W, Dsp, grains, n_lo, t, d, c, s, elist, cnt, base, o_plane, o_grain, o_block,
-                              o_s1, o_s2, o_vn, o_v1, o_v2, o_lam, o_flags);
-                    base += cnt;
+                    emit_list(G, W, Dsp, M, n_total, gsh, dfr, n_lo, t, c, s, elist, cnt, s1, d0, d1, b0, b1, o_plane, o_grain,
+                              o_block, o_s1, o_s2, o_vn, o_v1, o_v2, o_lam, o_flags);
+                    // detector d goes on in a new list
+                    const int64_t next = s1 <= cnt ? b1 + (cnt - s1) : b0 + cnt;
                     cnt = 0;
+                    d0 = d;
+                    b0 = next;
+                    s1 = kEmitList + 1;
                 }
                 int q = cnt + incl - pc;
                 for (unsigned wb = word; wb; wb &= wb - 1u)
                     elist[q++] = static_cast<uint16_t>((nrel << 10) | (w * 32 + __ffs(wb) - 1));
                 cnt += total;
             }
-            if (cnt > 0)
-                emit_list(G, W, Dsp, grains, n_lo, t, d, c, s, elist, cnt, base, o_plane, o_grain, o_block, o_s1,
-                          o_s2, o_vn, o_v1, o_v2, o_lam, o_flags);
         }
-        __syncthreads();        // mw is reused by the next work item
+        if (cnt > 0)
+            emit_list(G, W, Dsp, M, n_total, gsh, dfr, n_lo, t, c, s, elist, cnt, s1, d0, d1, b0, b1, o_plane, o_grain, o_block,
+                      o_s1, o_s2, o_vn, o_v1, o_v2, o_lam, o_flags);
+        __syncthreads();        // mw, gsh and bsh are reused by the next work item
     }
 }
 
@@ -269,6 +417,12 @@ unsigned enum_grid(int N, int T) {
     return static_cast<unsigned>(std::max<int64_t>(1, std::min<int64_t>(chunks * T, 256 * 32)));
 }
 size_t enum_lds(int n_det, int M) { return static_cast<size_t>(n_det) * M; }
+// Workgroups of k_enumerate_emit: all resident at once (20 one-wave
+// workgroups per CU, bound by its vector registers), at most one per item.
+unsigned emit_grid(int N, int T) {
+    const int64_t chunks = (static_cast<int64_t>(N) + kEnumChunk - 1) / kEnumChunk;
+    return static_cast<unsigned>(std::max<int64_t>(1, std::min<int64_t>(chunks * T, 256 * 20)));
+}
 
 // Exclusive scan of L int counts into out[0 .. L] (out[L] = total), over
 // the whole GPU in three launches and no memory beyond out: chunks of
@@ -516,7 +670,7 @@ int enumerate_count(const laue_geometry *geom, const laue_planes *planes,
     k_enumerate<<<enum_grid(N, geom->n_rot), 64, enum_lds(geom->n_det, planes->n), s>>>(w.geom, planes->w, planes->d, planes->harmonic_prev,
                                                planes->n, w.grains, N, geom->n_rot, merge, 0, w.counts, nullptr,
                                                nullptr, nullptr, nullptr, nullptr, nullptr,
-                                               nullptr, nullptr, nullptr, nullptr, nullptr, mask, w.w32);
+                                               nullptr, nullptr, nullptr, nullptr, nullptr, mask, w.w32, 0);
     LAUE_CHECK_HIP(hipGetLastError());
     w.mask_ready = mask != nullptr;
     if ((rc = launch_scan(w.counts, w.offs, L, s))) return rc;
@@ -531,28 +685,28 @@ int enumerate_count(const laue_geometry *geom, const laue_planes *planes,
 
 // Write pass after enumerate_count on the same workspace: from the count
 // pass's kept-plane bits when it wrote them, else recomputing every plane.
-int launch_emit(const laue_geometry *geom, const laue_planes *planes, EnumWs &w, int N, int merge, int *plane,
-                int *grain, int *block, float *s1, float *s2, float *vn, float *v1, float *v2, float *lam,
+int launch_emit(const laue_geometry *geom, const laue_planes *planes, EnumWs &w, int N, int merge, int64_t n_total,
+                int *plane, int *grain, int *block, float *s1, float *s2, float *vn, float *v1, float *v2, float *lam,
                 uint8_t *flags, hipStream_t s) {
     if (N == 0) return LAUE_OK;
     if (w.mask_ready)
-        k_enumerate_emit<<<enum_grid(N, geom->n_rot), 64,
+        k_enumerate_emit<<<emit_grid(N, geom->n_rot), 64,
                            static_cast<size_t>(kEnumChunk) * geom->n_det * w.w32 * sizeof(unsigned), s>>>(
             w.geom, planes->w, planes->d, planes->n, w.grains, N, geom->n_rot, w.offs, plane, grain, block, s1, s2,
-            vn, v1, v2, lam, flags, w.kmask, w.w32);
+            vn, v1, v2, lam, flags, w.kmask, w.w32, n_total);
     else
         k_enumerate<<<enum_grid(N, geom->n_rot), 64, enum_lds(geom->n_det, planes->n), s>>>(
             w.geom, planes->w, planes->d, planes->harmonic_prev, planes->n, w.grains, N, geom->n_rot, merge, 1,
-            nullptr, w.offs, plane, grain, block, s1, s2, vn, v1, v2, lam, flags, nullptr, w.w32);
+            nullptr, w.offs, plane, grain, block, s1, s2, vn, v1, v2, lam, flags, nullptr, w.w32, n_total);
     LAUE_CHECK_HIP(hipGetLastError());
     return LAUE_OK;
 }
 
 // Write pass of the enumerate (ids only) after enumerate_count on the same workspace.
 int launch_enumerate_ids(const laue_geometry *geom, const laue_planes *planes, EnumWs &w, int N,
-                         int merge, int *plane, int *grain, int *block, hipStream_t s) {
-    return launch_emit(geom, planes, w, N, merge, plane, grain, block, nullptr, nullptr, nullptr, nullptr, nullptr,
-                       nullptr, nullptr, s);
+                         int merge, int64_t n_total, int *plane, int *grain, int *block, hipStream_t s) {
+    return launch_emit(geom, planes, w, N, merge, n_total, plane, grain, block, nullptr, nullptr, nullptr, nullptr,
+                       nullptr, nullptr, nullptr, s);
 }
 
 // ---------------------------------------------------------------- simulate
@@ -739,6 +893,52 @@ extern "C" size_t laue_forward_workspace_size(const laue_geometry *geom, int32_t
     return carve_enum(cv, w, geom, n_grains, n_planes);
 }
 
+namespace {
+// What a count of laue_forward_enumerate left in its workspace: the call's
+// sizes, geometry, argument pointers and results, so that
+// laue_forward_enumerate_counted can check that it writes the set counted for
+// the same arguments.  A few workspaces at a time (most recent first).
+struct CountRecord {
+    const void *ws = nullptr;
+    GeomF geom;
+    const float *pw = nullptr, *pd = nullptr;
+    const int32_t *pprev = nullptr;
+    int32_t n_planes = 0;
+    const double *q = nullptr, *x = nullptr;
+    int64_t n_grains = 0;
+    int merge = 0;
+    bool mask_ready = false;
+    int64_t total = 0;
+    std::vector<int64_t> blk;
+};
+constexpr size_t kCountRecords = 8;
+std::mutex g_count_mu;
+std::vector<CountRecord> g_counts;
+
+void remember_count(const void *ws, const laue_geometry *geom, const laue_planes *planes, const laue_grains *grains,
+                    int merge, const EnumWs &w, int64_t total, const std::vector<int64_t> &blk) {
+    CountRecord r;
+    r.ws = ws;
+    make_geomf(geom, &r.geom);
+    r.pw = planes->w;
+    r.pd = planes->d;
+    r.pprev = planes->harmonic_prev;
+    r.n_planes = planes->n;
+    r.q = grains->q;
+    r.x = grains->x;
+    r.n_grains = grains->n;
+    r.merge = merge;
+    r.mask_ready = w.mask_ready;
+    r.total = total;
+    r.blk = blk;
+    std::lock_guard<std::mutex> lk(g_count_mu);
+    g_counts.erase(std::remove_if(g_counts.begin(), g_counts.end(), [&](const CountRecord &c) { return c.ws == ws; }),
+                   g_counts.end());
+    g_counts.insert(g_counts.begin(), std::move(r));
+    if (g_counts.size() > kCountRecords) g_counts.pop_back();
+}
+}  // namespace
+
 extern "C" int laue_forward_enumerate(const laue_geometry *geom, const laue_planes *planes,
                                       const laue_grains *grains, int merge_harmonics,
                                       laue_model_spots *out, int64_t *n_out, void *ws,
@@ -758,6 +958,7 @@ extern "C" int laue_forward_enumerate(const laue_geometry *geom, const laue_plan
     int64_t total = 0;
     if ((rc = enumerate_count(geom, planes, grains, merge_harmonics ? 1 : 0, w, hb, &total, s)))
         return rc;
+    remember_count(ws, geom, planes, grains, merge_harmonics ? 1 : 0, w, total, hb);
     *n_out = total;
     std::memcpy(out->block_off, hb.data(), hb.size() * sizeof(int64_t));
     if (total > out->n) {
@@ -769,11 +970,71 @@ extern "C" int laue_forward_enumerate(const laue_geometry *geom, const laue_plan
         LAUE_REQUIRE(out->plane && out->grain && out->block && out->s1 && out->s2 && out->vn &&
                          out->v1 && out->v2,
                      LAUE_EINVAL, "model-spot arrays are NULL");
-        if ((rc = launch_emit(geom, planes, w, grains->n, merge_harmonics ? 1 : 0, out->plane, out->grain,
+        if ((rc = launch_emit(geom, planes, w, grains->n, merge_harmonics ? 1 : 0, total, out->plane, out->grain,
                               out->block, out->s1, out->s2, out->vn, out->v1, out->v2, out->lam, out->flags, s)))
             return rc;
     }
     out->n = total;
+    LAUE_CHECK_HIP(hipStreamSynchronize(s));
+    return LAUE_OK;
+}
+
+extern "C" int laue_forward_enumerate_counted(const laue_geometry *geom, const laue_planes *planes,
+                                              const laue_grains *grains, int merge_harmonics,
+                                              laue_model_spots *out, int64_t *n_out, void *ws,
+                                              size_t ws_bytes, void *stream) {
+    clear_error();
+    int rc;
+    if ((rc = validate_geometry(geom)) || (rc = validate_planes(planes)) ||
+        (rc = validate_grains(grains)))
+        return rc;
+    LAUE_REQUIRE(out && n_out && out->block_off, LAUE_EINVAL, "output or n_out is NULL");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    Carver cv(ws);
+    EnumWs w;
+    size_t need = carve_enum(cv, w, geom, grains->n, planes->n);
+    if ((rc = check_ws(ws, ws_bytes, need))) return rc;
+    const int merge = merge_harmonics ? 1 : 0;
+    GeomF hg;
+    make_geomf(geom, &hg);
+    CountRecord r;
+    bool found = false;
+    {
+        std::lock_guard<std::mutex> lk(g_count_mu);
+        for (const CountRecord &c : g_counts)
+            if (c.ws == ws) {
+                r = c;
+                found = true;
+                break;
+            }
+    }
+    LAUE_REQUIRE(found, LAUE_EINVAL, "no laue_forward_enumerate count on this workspace");
+    LAUE_REQUIRE(std::memcmp(&r.geom, &hg, sizeof(GeomF)) == 0 && r.pw == planes->w && r.pd == planes->d &&
+                     r.pprev == planes->harmonic_prev && r.n_planes == planes->n && r.q == grains->q &&
+                     r.x == grains->x && r.n_grains == grains->n && r.merge == merge,
+                 LAUE_EINVAL, "arguments differ from those of the count on this workspace");
+    if (grains->n > 0) {
+        // the count's block offsets must still be in the workspace
+        std::vector<int64_t> blk(r.blk.size());
+        LAUE_CHECK_HIP(hipMemcpyAsync(blk.data(), w.blk, blk.size() * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+        LAUE_CHECK_HIP(hipStreamSynchronize(s));
+        LAUE_REQUIRE(blk == r.blk, LAUE_EINVAL, "the workspace no longer holds the count of laue_forward_enumerate");
+    }
+    *n_out = r.total;
+    std::memcpy(out->block_off, r.blk.data(), r.blk.size() * sizeof(int64_t));
+    if (r.total > out->n) {
+        set_error("model-spot capacity " + std::to_string(out->n) + " < required " + std::to_string(r.total));
+        return LAUE_ECAPACITY;
+    }
+    if (r.total > 0) {
+        LAUE_REQUIRE(out->plane && out->grain && out->block && out->s1 && out->s2 && out->vn && out->v1 && out->v2,
+                     LAUE_EINVAL, "model-spot arrays are NULL");
+        w.mask_ready = r.mask_ready;
+        if ((rc = launch_emit(geom, planes, w, grains->n, merge, r.total, out->plane, out->grain, out->block, out->s1,
+                              out->s2, out->vn, out->v1, out->v2, out->lam, out->flags, s)))
+            return rc;
+    }
+    out->n = r.total;
     LAUE_CHECK_HIP(hipStreamSynchronize(s));
     return LAUE_OK;
 }
@@ -887,7 +1148,7 @@ extern "C" int laue_simulate(const laue_geometry *geom, const laue_planes *plane
     const uint32_t k0 = static_cast<uint32_t>(seed & 0xffffffffu), k1 = static_cast<uint32_t>(seed >> 32);
     std::vector<int> nt(nb, 0), no(nb, 0);
     if (S > 0) {
-        if ((rc = launch_enumerate_ids(geom, planes, w.e, truth->n, 1, w.plane, w.grain, w.block, s))) return rc;
+        if ((rc = launch_enumerate_ids(geom, planes, w.e, truth->n, 1, S, w.plane, w.grain, w.block, s))) return rc;
         k_sim_noise<<<static_cast<unsigned>((S + 255) / 256), 256, 0, s>>>(
             *geom, planes->w, truth->q, truth->x, w.plane, w.grain, w.block, S, sigma_mm / distance,
             k0, k1, w.np1, w.np2, w.keep, w.key);

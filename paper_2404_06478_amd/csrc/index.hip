@@ -1668,7 +1668,7 @@ extern "C" int laue_score_candidates(const laue_geometry *geom, const laue_plane
         LAUE_CHECK_HIP(hipMemcpyAsync(&maxc, w.maxc, sizeof(int), hipMemcpyDeviceToHost, s));
         LAUE_CHECK_HIP(hipStreamSynchronize(s));
         LAUE_REQUIRE(maxc <= 64, LAUE_ECAPACITY, "a candidate has more than 64 model spots in one block");
-        if ((rc = launch_enumerate_ids(geom, planes, w.e, C, 1, w.plane, w.grain, w.block, s))) return rc;
+        if ((rc = launch_enumerate_ids(geom, planes, w.e, C, 1, total, w.plane, w.grain, w.block, s))) return rc;
         SlotArgs A;
         A.C = C;
         A.nb = nb;

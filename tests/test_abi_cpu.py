@@ -38,7 +38,7 @@ def test_exports_every_declared_symbol(lib):
 
 
 def test_version(lib):
-    assert lib.laue_version() == 100
+    assert lib.laue_version() == 200
 
 
 @pytest.mark.parametrize("a,cen,nmax", [(2.87, "I", 14), (2.87, "I", 30), (3.52, "F", 40), (4.05, "F", 30)])

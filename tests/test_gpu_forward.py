@@ -1,4 +1,6 @@
 """GPU parity of the forward model and the simulator against the oracle."""
+import dataclasses
+
 import numpy as np
 import pytest
 
@@ -66,6 +68,101 @@ def test_enumerate_matches_oracle(gpu_lib, name, n_rot, n_grains, merge):
     vl = cost.v_local(g, V["det"][oi], ev["v"])
     for c, col in enumerate(("vn", "v1", "v2")):
         assert np.max(np.abs(M[col][gi] - vl[:, c])) < 2e-3
+
+
+# Many planes (868, 28 mask words per detector), a wide band and large
+# detectors close to the sample: about 4,300 kept spots per 16-grain work item
+# of the write pass, so its LDS list (2048 entries) is written out in the
+# middle of a detector's run, and the mask words exceed what it prefetches.
+WIDE = dataclasses.replace(
+    ig.STRESS, a=4.05, centering="F", n_max=84, lam_min=0.2, lam_max=8.0,
+    detectors=(ig.Detector((30.0, 0.0, 0.0), (1.0, 0.0, 0.0), (0.0, 1.0, 0.0), (0.0, 0.0, 1.0), 500.0),
+               ig.Detector((-30.0, 0.0, 0.0), (1.0, 0.0, 0.0), (0.0, 1.0, 0.0), (0.0, 0.0, 1.0), 500.0)))
+
+
+@pytest.mark.parametrize("merge", [True, False])
+def test_enumerate_long_lists_match_oracle(gpu_lib, merge):
+    laue = gpu_lib
+    pl, g, q, x, geom, planes = _setup(laue, WIDE, 3, 40)      # 40 grains: chunks of 16, 16 and 8
+    V = forward.enumerate_visible(pl, q, x, g, merge_harmonics=merge)
+    # more than 2048 kept spots per 16 grains and rotation (both detectors)
+    assert np.bincount(V["t"]).min() * 16 / 40 > 2048
+    M = laue.laue_forward_enumerate(geom, planes, laue.Grains(q, x), merge).numpy()
+    common = _compare_sets(V, M, g.n_det, merge)
+    assert len(common) > 0.99 * len(V["m"])
+    key = M["block"].astype(np.int64) * 10**9 + M["grain"].astype(np.int64) * 10**4 + M["plane"]
+    assert np.all(np.diff(key) > 0)
+    assert np.array_equal(M["block_off"], np.concatenate([[0], np.cumsum(np.bincount(M["block"], minlength=g.n_blocks))]))
+
+
+def test_enumerate_candidate_scale_equals_eval(gpu_lib):
+    """8192 grains of the 1000-grain workload's lattice, band and 60-rotation
+    scan: the write pass's geometry equals, bit for bit, the frozen-list
+    evaluation of the ids it wrote (one forward model, two kernels), and the
+    ids are in (block, grain, plane) order with matching block offsets."""
+    laue = gpu_lib
+    p = ig.LEARNED
+    geom = laue.geometry_from_preset(p)
+    planes = laue.laue_planes_cubic(p.a, p.centering, p.n_max)
+    q, x = ig.random_grains(p, n=8192, seed=p.seed + 11)
+    M = laue.laue_forward_enumerate(geom, planes, laue.Grains(q, x), True)
+    A = M.numpy()
+    assert M.n > 1_000_000
+    key = A["block"].astype(np.int64) * 10**9 + A["grain"].astype(np.int64) * 10**4 + A["plane"]
+    assert np.all(np.diff(key) > 0)
+    nb = len(A["block_off"]) - 1
+    assert np.array_equal(A["block_off"], np.concatenate([[0], np.cumsum(np.bincount(A["block"], minlength=nb))]))
+    E = laue.ModelSpots.from_arrays(nb, A["block_off"], A["plane"], A["grain"], A["block"])
+    laue.laue_forward_eval(geom, planes, laue.Grains(q, x), E)
+    B = E.numpy()
+    for f in ("s1", "s2", "vn", "v1", "v2", "lam"):
+        assert np.array_equal(A[f].view(np.uint32), B[f].view(np.uint32)), f
+
+
+def test_enumerate_counted_equals_one_call(gpu_lib):
+    """laue_forward_enumerate_counted after a capacity query writes, bit for
+    bit, what one laue_forward_enumerate call with room writes; it refuses a
+    workspace with no count, changed arguments and a short capacity."""
+    import ctypes as C
+    laue = gpu_lib
+    lib = laue.require_native()
+    pl, g, q, x, geom, planes = _setup(laue, ig.MEDIUM, 7, 40)
+    grains = laue.Grains(q, x)
+    nb = laue.n_blocks(geom)
+    wsz = lib.laue_forward_workspace_size(C.byref(geom), planes.n, grains.n)
+    ws = laue._workspace(wsz)
+    n = laue.laue_forward_count(geom, planes, grains, True)
+    assert n > 1000
+    stream = laue._stream()
+
+    def call(fn, out, merge=1, ws_=ws, cap=None):
+        st = out.struct()
+        if cap is not None:
+            st.n = cap
+        nout = C.c_int64()
+        rc = fn(C.byref(geom), C.byref(planes.struct), C.byref(grains.struct), merge, C.byref(st), C.byref(nout),
+                laue._ptr(ws_), ws_.numel(), stream)
+        return rc, nout.value
+
+    A = laue.ModelSpots(n, nb)
+    assert call(lib.laue_forward_enumerate, A) == (0, n)
+    # a capacity query, then the counted write
+    assert call(lib.laue_forward_enumerate, laue.ModelSpots(0, nb), cap=0) == (laue._abi.LAUE_ECAPACITY, n)
+    B = laue.ModelSpots(n, nb)
+    assert call(lib.laue_forward_enumerate_counted, B) == (0, n)
+    a, b = A.numpy(), B.numpy()
+    for f in a:
+        assert np.array_equal(a[f].view(np.uint8), b[f].view(np.uint8)), f
+    # the same count serves again; a short capacity is refused with the size
+    assert call(lib.laue_forward_enumerate_counted, laue.ModelSpots(n, nb))[0] == 0
+    assert call(lib.laue_forward_enumerate_counted, laue.ModelSpots(n - 1, nb)) == (laue._abi.LAUE_ECAPACITY, n)
+    # other arguments, or a workspace that holds no count
+    assert call(lib.laue_forward_enumerate_counted, laue.ModelSpots(n, nb), merge=0)[0] == laue._abi.LAUE_EINVAL
+    other = laue._workspace(wsz + 4096)
+    assert call(lib.laue_forward_enumerate_counted, laue.ModelSpots(n, nb), ws_=other)[0] == laue._abi.LAUE_EINVAL
+    # a workspace overwritten since the count
+    ws.fill_(0)
+    assert call(lib.laue_forward_enumerate_counted, laue.ModelSpots(n, nb))[0] == laue._abi.LAUE_EINVAL
 
 
 def test_enumerate_empty_and_capacity(gpu_lib):
