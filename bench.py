@@ -459,9 +459,8 @@ def bench_index(laue, workload, n_pairs, learned_pairs, log, sobol_points=0, rec
                      "stage_ms": {k: st[k] for k in ("ms_candidates", "ms_proposal", "ms_score", "ms_greedy",
                                                      "ms_em")}}
         log(f"index: {mode}: {pairs} {'points' if mode == 'sobol' else 'pairs'}, {st['n_scored']} scored, "
-            f"recall {r}/{len(q)}, {wall:.2f} s (the refinement evaluated "
-            f"{(st['score_pairs_evaluated'] - st['score_pairs'] + st['score_pairs_refine']) / max(st['score_pairs_refine'], 1):.3f}"
-            f" of its pairs)")
+            f"recall {r}/{len(q)}, {wall:.2f} s (the refinement and scoring passes evaluated "
+            f"{st['score_pairs_evaluated'] / max(st['score_pairs'], 1):.4f} of their pairs)")
     return out
 
 

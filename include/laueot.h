@@ -650,8 +650,11 @@ typedef struct laue_score_out {
     int64_t lbar_n;
     int64_t pairs_streamed;   /* (out) same-block (detected, model) pairs of all
                                * passes: the work the method defines */
-    int64_t pairs_evaluated;  /* (out) of those, the pairs the refinement passes
-                               * evaluate (see below) plus the scoring passes' */
+    int64_t pairs_evaluated;  /* (out) of those, the pairs the passes evaluate:
+                               * the refinement passes' (see below) and the
+                               * scoring passes' (the detected spots within
+                               * each model spot's scoring radius, times the
+                               * slot's model spots) */
     int64_t pairs_refine;     /* (out) the refinement passes' share of pairs_streamed */
 } laue_score_out;
 

@@ -295,6 +295,7 @@ struct SlotArgs {
     const float *P1s, *P2s;
     const float2 *P12s;     // the same, interleaved
     const float2 *P12f;     // the spots in the order of the fine grid (kFineG)
+    const int *rowid_f;     // the detected spot's index of each position of that order
     const int *cell_off_f;  // [nb * kFineCells + 1]
     const int *cell_off;
     const float4 *cbox;
@@ -582,7 +583,7 @@ __global__ __launch_bounds__(64) void k_single_acc(SlotArgs A, float K, float bi
         }
     }
     __syncthreads();
-    // the model spots' statistics; k_single_solve forms their normal equations
+    // the model spots' statistics; k_single_normal forms their normal equations
     if (lane < nc) {
         double *dst = st_out + (o0 + lane) * kStat;
 #pragma unroll
@@ -592,12 +593,10 @@ __global__ __launch_bounds__(64) void k_single_acc(SlotArgs A, float K, float bi
 
 // One wave per candidate: the FP64 normal equations of each of its model
 // spots from the statistics of k_single_acc (lane l takes the spots of blocks
-// l, l + 64, ...; the current columns colsC give the spot's unit ray), summed,
-// then the Gauss-Newton step.  A candidate's spots carry its own grain index,
-// so the grain read here is written by this wave only.
-__global__ __launch_bounds__(64) void k_single_solve(SlotArgs A, const double *__restrict__ st, double D2,
-                                                     double mu_rel, double *q, double *x,
-                                                     GrainF *__restrict__ gf) {
+// l, l + 64, ...; the current columns colsC give the spot's unit ray), summed
+// over the wave in a fixed order into hg[c] (kHg values).
+__global__ __launch_bounds__(64) void k_single_normal(SlotArgs A, const double *__restrict__ st, double D2,
+                                                      double *__restrict__ hg_out) {
     const int c = blockIdx.x;
     if (c >= A.C) return;
     double acc[kHg];
@@ -616,13 +615,25 @@ __global__ __launch_bounds__(64) void k_single_solve(SlotArgs A, const double *_
     }
     for (int k = 0; k < kHg; ++k) acc[k] = wave_sum(acc[k]);
     if (threadIdx.x != 0) return;
-    gn_solve_apply(acc, mu_rel, q + 4 * c, x + 3 * c, gf + c, nullptr);
+    double *dst = hg_out + static_cast<int64_t>(c) * kHg;
+    for (int k = 0; k < kHg; ++k) dst[k] = acc[k];
+}
+
+// One thread per candidate: the Gauss-Newton step from its summed normal
+// equations (64 candidates' factorisations side by side in a wave).
+__global__ __launch_bounds__(64) void k_single_step(int C, const double *__restrict__ hg, double mu_rel, double *q,
+                                                    double *x, GrainF *__restrict__ gf) {
+    const int c = blockIdx.x * 64 + threadIdx.x;
+    if (c >= C) return;
+    gn_solve_apply(hg + static_cast<int64_t>(c) * kHg, mu_rel, q + 4 * c, x + 3 * c, gf + c, nullptr);
 }
 
 // ---------------------------------------------------------------- per model spot refinement pass
 
-// The (block, candidate) slot of model spot o: [*o0, *o1) and its block.
-__device__ __forceinline__ int spot_slot(const SlotArgs &A, int64_t o, int64_t *o0, int64_t *o1) {
+// The (block, candidate) slot of model spot o: [*o0, *o1) and its block
+// (and, if item is given, block * C + candidate).
+__device__ __forceinline__ int spot_slot(const SlotArgs &A, int64_t o, int64_t *o0, int64_t *o1,
+                                         int64_t *item_out = nullptr) {
     int b = A.mblock[o];
     const int g = A.mgrain[o];
     int64_t item = static_cast<int64_t>(b) * A.C + g;
@@ -639,6 +650,7 @@ __device__ __forceinline__ int spot_slot(const SlotArgs &A, int64_t o, int64_t *
     }
     *o0 = A.offs[item];
     *o1 = A.offs[item + 1];
+    if (item_out) *item_out = item;
     return b;
 }
 
@@ -772,68 +784,135 @@ __global__ __launch_bounds__(256) void k_spot_acc(SlotArgs A, float K, float bin
     }
 }
 
-// Scoring at the final grains.  Per model spot: unmatched when no detected
-// spot of its block is within c_out.  Per detected spot and candidate: the
-// SPOT entry Lbar = ln sum_j exp(-c_ij / (2 sigma^2)) when above the floor
-// exp(-c_out / (2 sigma^2)).  pass 0 counts per (candidate, block); pass 1
-// writes the entries at loff (CSR by candidate, then block, then row).
-// One wave per (block, candidate) as in k_single_acc.
-__global__ __launch_bounds__(64) void k_single_score(SlotArgs A, int pass, float twoD2, float K2,
-                                                     float floor_e, float c_out,
-                                                     int *__restrict__ unm, int *__restrict__ lcnt,
-                                                     const int64_t *__restrict__ loff,
-                                                     const uint8_t *__restrict__ keep,
-                                                     int *__restrict__ lrow,
-                                                     float *__restrict__ lval) {
-    const int item = blockIdx.x;
-    const int b = item / A.C, c = item - b * A.C;
-    const int lane = threadIdx.x;
-    const int64_t o0 = A.offs[static_cast<int64_t>(b) * A.C + c];
-    const int nc = static_cast<int>(A.offs[static_cast<int64_t>(b) * A.C + c + 1] - o0);
-    const int64_t slot = static_cast<int64_t>(c) * A.nb + b;
-    if (nc == 0 || (pass && !keep[c])) {
-        if (!pass && lane == 0) {
-            unm[slot] = 0;
-            lcnt[slot] = 0;
-        }
-        return;
+// Scoring radius of each model spot o (at the scoring geometry colsC, nc
+// spots in its slot): beyond it every row's cost to o exceeds c_out (the
+// unmatched test), and o's term of a row's sum is below floor_e / (2 nc), so
+// a row beyond the radius of every spot of the slot sums to less than half the
+// floor (no SPOT entry).  Lhit = -log2(floor_e).
+__global__ void k_score_rad(SlotArgs A, int64_t M, float twoD2, float K2, float c_out, float Lhit,
+                            float *__restrict__ rad2) {
+    for (int64_t o = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; o < M;
+         o += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+        int64_t o0, o1;
+        spot_slot(A, o, &o0, &o1);
+        const Col8 c = A.colsC[o];
+        const float Thit = Lhit + 1.0f + log2f(static_cast<float>(o1 - o0));
+        rad2[o] = fmaxf(zero_radius2(c.vv, c.vn, twoD2, c_out * 1.001f), zero_radius2(c.vv, c.vn, K2, Thit));
     }
-    const int64_t r0 = A.ooff[b], rend = A.ooff[b + 1];
-    const LaneCol lC = lane_col(A.colsC, o0, nc, lane);
-    float cmin = INFINITY;                       // lane j: nearest detected spot of model spot j
-    int64_t pos = pass ? loff[slot] : 0;
-    int cnt = 0;
-    for (int64_t i0 = r0; i0 < rend; i0 += 64) {
-        const int64_t i = i0 + lane;
-        const bool rv = i < rend;
-        const float p1 = rv ? A.P1[i] : 0.0f, p2 = rv ? A.P2[i] : 0.0f;
-        float zz = 0.0f;
-        for (int j = 0; j < nc; ++j) {
-            const Col8 cC = col_of(lC, j);
-            const float cp = entry_exponent(p1, p2, cC.s1, cC.s2, cC.v1, cC.v2, cC.vv, cC.vv2, -1.0f, 0.0f);
-            zz += rv ? fast_exp2(-K2 * cp) : 0.0f;
-            if (!pass) {
-                const float m = wave_min_f(rv ? twoD2 * cp : INFINITY);
-                if (lane == j) cmin = fminf(cmin, m);
+}
+
+// The scoring passes at the final grains (colsC), one thread per model spot
+// o over the detected spots within its scoring radius (the fine cell grid, as
+// in k_spot_acc).  Unmatched: no detected spot with 2 D^2 c' <= c_out (the
+// spots beyond the radius are all farther).  SPOT entry of a detected spot
+// and candidate: Lbar = ln sum_j exp2(-K2 c'_j) over the candidate's model
+// spots j of the block, in index order, when the sum exceeds floor_e; a row
+// is taken by the lowest-index spot of the slot whose radius holds it (rows
+// beyond every radius have no entry).  pass 0 counts o's entries (hcnt) and
+// adds them and o's unmatched flag to its (candidate, block) slot (unm and
+// lcnt start at zero); pass 1 writes the kept candidates' entries at loff of
+// the slot plus the counts of the slot's earlier spots, in o's walk order
+// (CSR by candidate, then block).  Lrow is the detected spot's index.
+template <int PASS>
+__global__ __launch_bounds__(256) void k_spot_score(SlotArgs A, int64_t M, float twoD2, float K2, float floor_e,
+                                                    float c_out, const float *__restrict__ rad2,
+                                                    const unsigned long long *__restrict__ nbr, int *__restrict__ hcnt,
+                                                    int *__restrict__ unm, int *__restrict__ lcnt,
+                                                    const int64_t *__restrict__ loff,
+                                                    const uint8_t *__restrict__ keep, int *__restrict__ lrow,
+                                                    float *__restrict__ lval, unsigned long long *ev) {
+    const int64_t o = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    unsigned long long evaluated = 0;
+    int64_t o0 = 0, o1 = 0, item = 0;
+    if (o < M) spot_slot(A, o, &o0, &o1, &item);
+    const int b = static_cast<int>(item / A.C), c = static_cast<int>(item - static_cast<int64_t>(b) * A.C);
+    const int64_t slot = static_cast<int64_t>(c) * A.nb + b;
+    if (o < M && (PASS == 0 || keep[c])) {
+        const Col8 me = A.colsC[o];
+        const float R2 = rad2[o];
+        // the slot's spots before o whose radius may hold a row within o's
+        const unsigned long long before = nbr[o] & ((1ull << (o - o0)) - 1ull);
+        int64_t pos = 0;
+        if (PASS == 1) {
+            pos = loff[slot];
+            for (int64_t j = o0; j < o; ++j) pos += hcnt[j];
+        }
+        bool matched = false;
+        int h = 0;
+        const float4 bc = A.cbox[b];
+        const float4 bx = make_float4(bc.x, bc.y, bc.z * (static_cast<float>(kCellG) / kFineG),
+                                      bc.w * (static_cast<float>(kCellG) / kFineG));
+        const float R = __builtin_amdgcn_sqrtf(R2);
+        const float eps_c = 1e-3f;
+        const float icx = __builtin_amdgcn_rcpf(bx.z), icy = __builtin_amdgcn_rcpf(bx.w);
+        const int iy0 = cell_coord<kFineG>((me.s2 - R - bx.y) * icy - eps_c);
+        const int iy1 = cell_coord<kFineG>((me.s2 + R - bx.y) * icy + eps_c);
+        const int *co = A.cell_off_f + static_cast<int64_t>(b) * kFineCells;
+        for (int iy = iy0; iy <= iy1; ++iy) {
+            const float ya = bx.y + (static_cast<float>(iy) - eps_c) * bx.w;
+            const float yb = bx.y + (static_cast<float>(iy + 1) + eps_c) * bx.w;
+            const float dyb = fmaxf(0.0f, fmaxf(ya - me.s2, me.s2 - yb));
+            if (!(dyb * dyb < R2)) continue;
+            const float hw = __builtin_amdgcn_sqrtf(R2 - dyb * dyb);
+            const int ix0 = cell_coord<kFineG>((me.s1 - hw - bx.x) * icx - eps_c);
+            const int ix1 = cell_coord<kFineG>((me.s1 + hw - bx.x) * icx + eps_c);
+            const int re = co[iy * kFineG + ix1 + 1];
+            for (int r = co[iy * kFineG + ix0]; r < re; ++r) {
+                const float2 pq = A.P12f[r];
+                const float p1 = pq.x, p2 = pq.y;
+                const float dy = p1 - me.s1, dz = p2 - me.s2;
+                if (!(fmaf(dz, dz, dy * dy) < R2)) continue;
+                if (PASS == 0 && !matched) {
+                    const float cp = entry_exponent(p1, p2, me.s1, me.s2, me.v1, me.v2, me.vv, me.vv2, -1.0f, 0.0f);
+                    matched = twoD2 * cp <= c_out;
+                }
+                bool own = true;
+                for (unsigned long long m = before; m; m &= m - 1) {
+                    const int64_t j = o0 + __builtin_ctzll(m);
+                    const Col8 cj = A.colsC[j];
+                    const float ey = p1 - cj.s1, ez = p2 - cj.s2;
+                    if (fmaf(ez, ez, ey * ey) < rad2[j]) {
+                        own = false;
+                        break;
+                    }
+                }
+                if (!own) continue;
+                float zz = 0.0f;
+                for (int64_t j = o0; j < o1; ++j) {
+                    const Col8 cj = A.colsC[j];
+                    const float cp = entry_exponent(p1, p2, cj.s1, cj.s2, cj.v1, cj.v2, cj.vv, cj.vv2, -1.0f, 0.0f);
+                    zz += fast_exp2(-K2 * cp);
+                }
+                evaluated += static_cast<unsigned long long>(o1 - o0);
+                if (zz > floor_e) {
+                    if (PASS == 0) {
+                        ++h;
+                    } else {
+                        lrow[pos] = A.rowid_f[r];
+                        lval[pos] = __logf(zz);
+                        ++pos;
+                    }
+                }
             }
         }
-        const bool hit = rv && zz > floor_e;
-        const uint64_t mask = __ballot(hit);
-        if (pass && hit) {
-            const int my = __popcll(mask & ((uint64_t(1) << lane) - 1));
-            lrow[pos + my] = static_cast<int>(i);
-            lval[pos + my] = __logf(zz);
+        if (PASS == 0) {
+            hcnt[o] = h;
+            if (h) atomicAdd(&lcnt[slot], h);
+            if (!matched) atomicAdd(&unm[slot], 1);
         }
-        const int nh = __popcll(mask);
-        pos += nh;
-        cnt += nh;
     }
-    if (!pass) {
-        const int um = __popcll(__ballot(lane < nc && cmin > c_out));
-        if (lane == 0) {
-            unm[slot] = um;
-            lcnt[slot] = cnt;
-        }
+    if (ev) {
+        for (int off = 32; off > 0; off >>= 1)
+            evaluated += __shfl_xor(evaluated, off, 64);
+        if ((threadIdx.x & 63) == 0 && evaluated) atomicAdd(ev, evaluated);
+    }
+}
+
+__global__ void k_fill_int2(int *__restrict__ a, int *__restrict__ b, int64_t n) {
+    for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+         i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+        a[i] = 0;
+        b[i] = 0;
     }
 }
 
@@ -1523,6 +1602,8 @@ struct ScoreWs {
     int *plane, *grain, *block;
     Col8 *colsE, *colsC;
     double *st;       // per model spot: the kStat statistics of the last pass
+    double *hg;       // per candidate: its summed normal equations (kHg values)
+    int *hcnt;        // per model spot: its SPOT entries (scoring passes)
     float *rad2;      // per model spot: squared zero radius (per-spot pass)
     unsigned long long *nbr;   // per model spot: slot spots whose zero disks meet its own
     int *unm, *lcnt;
@@ -1530,7 +1611,8 @@ struct ScoreWs {
     int64_t *loff;
     int64_t *ooff;
     int *maxc;
-    int64_t *pairs;   // pairs of all slots, of the kept candidates' slots, evaluated by the refinement
+    int64_t *pairs;   // pairs of all slots, of the kept candidates' slots, evaluated by the refinement,
+                      // evaluated by the scoring
     CellWs cells;
 };
 
@@ -1545,6 +1627,8 @@ size_t carve_score(Carver &cv, ScoreWs &w, const laue_geometry *g, int chunk, in
     w.colsE = cv.take<Col8>(S);
     w.colsC = cv.take<Col8>(S);
     w.st = cv.take<double>(static_cast<size_t>(S) * kStat);
+    w.hg = cv.take<double>(static_cast<size_t>(std::max(chunk, 1)) * kHg);
+    w.hcnt = cv.take<int>(S);
     w.rad2 = cv.take<float>(S);
     w.nbr = cv.take<unsigned long long>(S);
     w.unm = cv.take<int>(static_cast<size_t>(chunk) * nb);
@@ -1553,7 +1637,7 @@ size_t carve_score(Carver &cv, ScoreWs &w, const laue_geometry *g, int chunk, in
     w.keep = cv.take<uint8_t>(chunk);
     w.ooff = cv.take<int64_t>(nb + 1);
     w.maxc = cv.take<int>(1);
-    w.pairs = cv.take<int64_t>(3);
+    w.pairs = cv.take<int64_t>(4);
     return cv.size();
 }
 
@@ -1575,10 +1659,31 @@ int launch_acc(const SlotArgs &A, float K, float bin_e, float T_skip, int64_t M,
     return LAUE_OK;
 }
 
-int launch_score(const SlotArgs &A, int pass, float twoD2, float K2, float floor_e, float c_out, int *unm,
-                 int *lcnt, const int64_t *loff, const uint8_t *keep, int *lrow, float *lval, hipStream_t s) {
-    k_single_score<<<static_cast<unsigned>(A.nb) * A.C, 64, 0, s>>>(A, pass, twoD2, K2, floor_e, c_out, unm,
-                                                                       lcnt, loff, keep, lrow, lval);
+// The scoring passes (k_spot_score); pass 0 also sets the scoring radii and
+// disk masks that pass 1 reuses.
+int launch_score(const SlotArgs &A, int pass, int64_t M, float twoD2, float K2, float floor_e, float c_out,
+                 float Lhit, float *rad2, unsigned long long *nbr, int *hcnt, int *unm, int *lcnt,
+                 const int64_t *loff, const uint8_t *keep, int *lrow, float *lval, unsigned long long *ev,
+                 hipStream_t s) {
+    const int64_t L = static_cast<int64_t>(A.nb) * A.C;
+    if (pass == 0) {
+        k_fill_int2<<<static_cast<unsigned>(std::min<int64_t>((L + 255) / 256, 4096)), 256, 0, s>>>(unm, lcnt, L);
+        LAUE_CHECK_HIP(hipGetLastError());
+    }
+    if (M == 0) return LAUE_OK;
+    const unsigned g = static_cast<unsigned>(std::min<int64_t>((M + 255) / 256, 16384));
+    const unsigned gs = static_cast<unsigned>((M + 255) / 256);
+    if (pass == 0) {
+        SlotArgs B = A;
+        B.colsE = A.colsC;      // the disks at the scoring geometry
+        k_score_rad<<<g, 256, 0, s>>>(A, M, twoD2, K2, c_out, Lhit, rad2);
+        k_spot_nbr<<<g, 256, 0, s>>>(B, rad2, M, nbr);
+        k_spot_score<0><<<gs, 256, 0, s>>>(A, M, twoD2, K2, floor_e, c_out, rad2, nbr, hcnt, unm, lcnt, nullptr,
+                                           nullptr, nullptr, nullptr, ev);
+    } else {
+        k_spot_score<1><<<gs, 256, 0, s>>>(A, M, twoD2, K2, floor_e, c_out, rad2, nbr, hcnt, nullptr, nullptr, loff,
+                                           keep, lrow, lval, ev);
+    }
     LAUE_CHECK_HIP(hipGetLastError());
     return LAUE_OK;
 }
@@ -1633,12 +1738,14 @@ extern "C" int laue_score_candidates(const laue_geometry *geom, const laue_plane
     const float twoD2 = static_cast<float>(2.0 * D2);
     const float K2 = static_cast<float>(2.0 * D2 * l2e / (2.0 * par->sigma_mm * par->sigma_mm));
     const float floor_e = static_cast<float>(std::exp(-par->c_out / (2.0 * par->sigma_mm * par->sigma_mm)));
+    const float Lhit = static_cast<float>(par->c_out * l2e / (2.0 * par->sigma_mm * par->sigma_mm));
     int64_t lbar_total = 0;
     const int N = cand->n;
     out->pairs_streamed = 0;
     k_set_i64<<<1, 1, 0, s>>>(w.pairs, 0);
     k_set_i64<<<1, 1, 0, s>>>(w.pairs + 1, 0);
     k_set_i64<<<1, 1, 0, s>>>(w.pairs + 2, 0);
+    k_set_i64<<<1, 1, 0, s>>>(w.pairs + 3, 0);
     LAUE_CHECK_HIP(hipGetLastError());
     unsigned long long *pairs = reinterpret_cast<unsigned long long *>(w.pairs);
     if (N == 0) {
@@ -1689,6 +1796,7 @@ extern "C" int laue_score_candidates(const laue_geometry *geom, const laue_plane
         A.P2s = w.cells.P2s;
         A.P12s = w.cells.P12s;
         A.P12f = w.cells.P12f;
+        A.rowid_f = w.cells.idx_out;
         A.cell_off_f = w.cells.off_f;
         A.cell_off = w.cells.off;
         A.cbox = w.cells.box;
@@ -1727,7 +1835,8 @@ extern "C" int laue_score_candidates(const laue_geometry *geom, const laue_plane
                     A.colsC = w.colsC;
                 }
                 if ((rc = launch_acc(A, K, bin_e, T_skip, total, w.rad2, w.nbr, w.st, s))) return rc;
-                k_single_solve<<<C, 64, 0, s>>>(A, w.st, D2, par->mu_rel, sub.q, sub.x, w.e.grains);
+                k_single_normal<<<C, 64, 0, s>>>(A, w.st, D2, w.hg);
+                k_single_step<<<(C + 63) / 64, 64, 0, s>>>(C, w.hg, par->mu_rel, sub.q, sub.x, w.e.grains);
                 LAUE_CHECK_HIP(hipGetLastError());
             }
         }
@@ -1736,8 +1845,8 @@ extern "C" int laue_score_candidates(const laue_geometry *geom, const laue_plane
                               nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, w.colsC, s)))
             return rc;
         A.colsC = w.colsC;
-        if ((rc = launch_score(A, 0, twoD2, K2, floor_e, static_cast<float>(par->c_out), w.unm,
-                                 w.lcnt, nullptr, nullptr, nullptr, nullptr, s)))
+        if ((rc = launch_score(A, 0, total, twoD2, K2, floor_e, static_cast<float>(par->c_out), Lhit, w.rad2,
+                               w.nbr, w.hcnt, w.unm, w.lcnt, nullptr, nullptr, nullptr, nullptr, pairs + 3, s)))
             return rc;
         k_single_keep<<<(C + 127) / 128, 128, 0, s>>>(C, nb, w.e.offs, w.unm, w.lcnt, par->f_out,
                                                       w.keep,
@@ -1761,18 +1870,18 @@ extern "C" int laue_score_candidates(const laue_geometry *geom, const laue_plane
             LAUE_CHECK_HIP(hipGetLastError());
         }
         if (ctot > 0 &&
-            (rc = launch_score(A, 1, twoD2, K2, floor_e, static_cast<float>(par->c_out), nullptr,
-                                 nullptr, w.loff, w.keep, out->lbar_row + lbar_total,
-                                 out->lbar_val + lbar_total, s)))
+            (rc = launch_score(A, 1, total, twoD2, K2, floor_e, static_cast<float>(par->c_out), Lhit, w.rad2,
+                               w.nbr, w.hcnt, nullptr, nullptr, w.loff, w.keep, out->lbar_row + lbar_total,
+                               out->lbar_val + lbar_total, pairs + 3, s)))
             return rc;
         lbar_total += ctot;
     }
     out->lbar_n = lbar_total;
-    int64_t hp[3] = {0, 0, 0};
-    LAUE_CHECK_HIP(hipMemcpyAsync(hp, w.pairs, 3 * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    int64_t hp[4] = {0, 0, 0, 0};
+    LAUE_CHECK_HIP(hipMemcpyAsync(hp, w.pairs, 4 * sizeof(int64_t), hipMemcpyDeviceToHost, s));
     LAUE_CHECK_HIP(hipStreamSynchronize(s));
     out->pairs_streamed = (static_cast<int64_t>(par->k_refine) * par->k_gn + 1) * hp[0] + hp[1];
-    out->pairs_evaluated = hp[2] + hp[0] + hp[1];
+    out->pairs_evaluated = hp[2] + hp[3];
     out->pairs_refine = static_cast<int64_t>(par->k_refine) * par->k_gn * hp[0];
     return LAUE_OK;
 }
