@@ -638,7 +638,14 @@ typedef struct laue_score_params {
 
 /* Scoring outputs (device).  n_model, n_unmatched, keep: [n_cand] (may be
  * NULL).  SPOT matrix as CSR by candidate: lbar_off [n_cand + 1], lbar_row,
- * lbar_val [lbar_cap]; lbar_n (out) entries. */
+ * lbar_val [lbar_cap]; lbar_n (out) entries.  Within a candidate the entries
+ * are grouped by block; within a block their order is the scoring pass's
+ * (deterministic, not by row).  The scoring passes (unmatched filter, SPOT
+ * entries, Sec. 6.2 and App. E) read the detected spots through the cell
+ * index below: per model spot, the detected spots within a radius beyond
+ * which its cost exceeds c_out and its term of a row's sum is below half the
+ * floor over the block's model spots of the candidate, so the rows and spots
+ * they skip have no entry and are unmatched as evaluated. */
 typedef struct laue_score_out {
     int32_t *n_model;
     int32_t *n_unmatched;
