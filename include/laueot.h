@@ -644,8 +644,8 @@ typedef struct laue_score_params {
  * entries, Sec. 6.2 and App. E) read the detected spots through the cell
  * index below: per model spot, the detected spots within a radius beyond
  * which its cost exceeds c_out and its term of a row's sum is below half the
- * floor over the block's model spots of the candidate, so the rows and spots
- * they skip have no entry and are unmatched as evaluated. */
+ * floor over the block's model spots of the candidate: skipping the others
+ * changes neither the entries nor the unmatched counts. */
 typedef struct laue_score_out {
     int32_t *n_model;
     int32_t *n_unmatched;
