@@ -105,6 +105,60 @@ def test_refine_score_match_oracle(gpu_lib, drop_log2):
     assert 0 < res["pairs_evaluated"] <= res["pairs_streamed"]
 
 
+@pytest.mark.parametrize("sigma", [1.0, 6.0])
+def test_scoring_passes_match_oracle_dense(gpu_lib, sigma):
+    """The scoring passes alone (k_refine = 0: the candidates, 8 true grains
+    and 8 pair candidates, are scored where they start) on a dense sample (30
+    grains, 70% outliers), against the oracle, which evaluates every pair.  At
+    sigma = 6 mm the scoring radii
+    (a few sigma) make the disks of a candidate's model spots of one block
+    overlap, so rows are shared and taken by the slot's lowest-index spot.
+    Unmatched counts, keep decisions and the SPOT entries (rows as a set,
+    values) agree; a GPU entry missing from the oracle's set is at the floor
+    within rounding."""
+    laue = gpu_lib
+    p, pl, g, q, x, sim, p12, geom, planes, obs = _setup(laue, n_grains=30, sigma=sigma, frac=0.7, seed=13)
+    ref = candidates.generate(pl, g, p12, sim["offsets"], 200, 5)
+    # 8 true grains (kept), 8 candidates spread over the list
+    sel = np.arange(0, len(ref["q"]), max(1, len(ref["q"]) // 8))[:8]
+    cq = np.concatenate([q[:8], ref["q"][sel]])
+    cx = np.concatenate([x[:8], np.zeros((len(sel), 3))])
+    c_out = cost.c_out(sigma, p.distance)
+    par = laue.score_params(sigma, p.distance, c_out, k_refine=0, k_gn=1, chunk=7)
+    res = laue.laue_score_candidates(geom, planes, obs, laue.Grains(cq, cx), par)
+    phi = -c_out / (2 * sigma ** 2)
+    close_pairs = 0
+    for k in range(len(cq)):
+        mod = forward.enumerate_visible(pl, cq[k][None], cx[k][None], g)
+        mod["offsets"] = forward.block_offsets(mod["block"], g.n_blocks)
+        un, nm, rows, vals = single.score(pl, g, p.distance, p12, sim["offsets"], mod, cq[k], cx[k], sigma, c_out)
+        for b in range(g.n_blocks):
+            s12 = mod["s12"][mod["offsets"][b]:mod["offsets"][b + 1]] if "s12" in mod else None
+            if s12 is not None and len(s12) > 1:
+                d = np.linalg.norm(s12[:, None, :] - s12[None, :, :], axis=-1)
+                close_pairs += int(np.sum(np.triu(d < 6 * sigma, 1)))
+        assert res["n_model"][k].item() == nm
+        assert abs(res["n_unmatched"][k].item() - un) <= 1
+        keep = nm > 0 and un < 0.1 * nm
+        assert bool(res["keep"][k].item()) == keep
+        lo, hi = res["lbar_off"][k].item(), res["lbar_off"][k + 1].item()
+        if not keep:
+            assert hi == lo
+            continue
+        gr = res["lbar_row"][lo:hi].cpu().numpy()
+        gv = res["lbar_val"][lo:hi].cpu().numpy()
+        assert len(set(gr.tolist())) == len(gr)             # each row once
+        safe = np.abs(vals - phi) > 1e-3
+        assert set(rows[safe].tolist()) <= set(gr.tolist())
+        m = {r: v for r, v in zip(gr.tolist(), gv.tolist())}
+        assert np.max(np.abs(np.array([m[r] for r in rows[safe]]) - vals[safe]), initial=0.0) < 1e-4
+        extra = [v for r, v in m.items() if r not in set(rows.tolist())]
+        assert all(abs(v - phi) < 1e-3 for v in extra)
+    assert res["keep"].sum().item() >= 3
+    if sigma > 2.0:
+        assert close_pairs > 0
+
+
 def test_greedy_matches_oracle(gpu_lib):
     laue = gpu_lib
     rng = np.random.default_rng(3)
