@@ -444,8 +444,10 @@ typedef struct laue_em_params {
      * zeta = ||Q^{k+1} - Q^k||_F <= zeta_tol over the detected x model entries
      * and the bins (zeta_tol <= 0: every final iteration runs).  zeta is
      * evaluated in FP32 per entry (a floor near 1e-7 sqrt(entries with
-     * Q > 0)); the plan-change test needs the dense assignment and runs in
-     * laue_em only (one sample). */
+     * Q > 0)).  With the sparse assignment (ot.rho > 0) the plans are 0 off
+     * each detected spot's rho neighbours, which each E-step chooses anew:
+     * zeta runs over the union of the two E-steps' neighbour sets.  The
+     * plan-change test runs in laue_em and laue_index (one sample). */
     double eps_cool;
     int32_t final_iters;
     double zeta_tol;

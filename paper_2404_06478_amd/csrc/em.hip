@@ -136,6 +136,7 @@ struct SampleDesc {
     int rho, cand_cap;             // neighbours per detected spot; filter capacity per row
     float knn_k;                   // filter threshold = knn_k / (model spots of the block)
     int *nbr;                      // [n_obs x rho]
+    int *nbr_prev;                 // [n_obs x rho] the previous E-step's (plan change)
     float *ncp;                    // [n_obs x rho] c / (2 D^2)
     int *cand_j, *cand_n;          // [n_obs x cand_cap], [n_obs]
     float *cand_c;                 // [n_obs x cand_cap]
@@ -1570,7 +1571,8 @@ struct SampleWs {
     float *Fp, *Gp;
     int64_t *mboff;
     // sparse assignment (rho > 0)
-    int *nbr = nullptr, *cand_j = nullptr, *cand_n = nullptr, *knn_list = nullptr, *knn_nlist = nullptr;
+    int *nbr = nullptr, *nbr_prev = nullptr, *cand_j = nullptr, *cand_n = nullptr, *knn_list = nullptr,
+        *knn_nlist = nullptr;
     float *ncp = nullptr, *cand_c = nullptr, *col_cp = nullptr;
     int *col_row = nullptr, *knn_hist = nullptr;
     int *sk_in = nullptr, *sk_out = nullptr, *sv_in = nullptr, *sv_out = nullptr;
@@ -1627,6 +1629,7 @@ static size_t carve_all(Carver &cv, BatchWs &bw, std::vector<SampleWs> &sw, cons
             const int64_t no = std::max<int64_t>(d.n_obs, 1), nm = std::max<int64_t>(d.n_model, 1);
             const int64_t cap = static_cast<int64_t>(kCandPerNbr) * d.rho;
             w.nbr = cv.take<int>(no * d.rho);
+            w.nbr_prev = cv.take<int>(no * d.rho);
             w.ncp = cv.take<float>(no * d.rho);
             w.cand_j = cv.take<int>(no * cap);
             w.cand_c = cv.take<float>(no * cap);
@@ -1914,6 +1917,76 @@ __global__ __launch_bounds__(64) void k_dq_rows(const Item *__restrict__ items, 
                                             fmaf(D.gprev[j], kb, fb)));
             const float dq = qa - qb;
             acc = fmaf(dq, dq, acc);
+        }
+        const double ba = exp((static_cast<double>(D.f[i]) + A.g0 - p.c_out) / A.eps);
+        const double bb = exp((static_cast<double>(D.fprev[i]) + B.g0 - p.c_out) / B.eps);
+        s = static_cast<double>(acc) + (ba - bb) * (ba - bb);
+    }
+    s = wave_sum(s);
+    if (threadIdx.x == 0) D.obj[4 * static_cast<int64_t>(it.local)] = s;
+}
+
+// The same for the sparse assignment (rho > 0): a detected spot's entries
+// are those of its rho neighbours in the current plan (nbr) and of its
+// neighbours of the previous E-step in the previous one (nbr_prev, -1 for an
+// empty slot); an entry in one set only counts with 0 from the other plan
+// (the plans are 0 off their neighbour sets).  Both lists in registers.
+constexpr int kMaxRho = 32;
+__global__ __launch_bounds__(64) void k_dq_rows_sparse(const Item *__restrict__ items,
+                                                       const SampleDesc *__restrict__ descs,
+                                                       const ObjIn *__restrict__ oin, int n) {
+    const Item it = items[blockIdx.x];
+    const SampleDesc &D = descs[it.s];
+    const ObjIn A = oin[it.s], B = oin[n + it.s];
+    const SinkParams p = D.sp;
+    const float ka = static_cast<float>(1.4426950408889634 / A.eps);
+    const float kb = static_cast<float>(1.4426950408889634 / B.eps);
+    const float Ka = p.twoD2 * ka, Kb = p.twoD2 * kb;
+    const int i = it.r0 + static_cast<int>(threadIdx.x);
+    const bool act = i < it.r1;
+    const int rho = min(D.rho, kMaxRho);
+    double s = 0.0;
+    if (act) {
+        const float p1 = D.p1[i], p2 = D.p2[i];
+        const float fa = D.f[i] * ka, fb = D.fprev[i] * kb;
+        int na[kMaxRho], nb[kMaxRho];
+#pragma unroll
+        for (int q = 0; q < kMaxRho; ++q) {
+            na[q] = q < rho ? D.nbr[static_cast<int64_t>(q) * D.n_obs + i] : -1;
+            nb[q] = q < rho ? D.nbr_prev[static_cast<int64_t>(q) * D.n_obs + i] : -1;
+        }
+        float acc = 0.0f;
+#pragma unroll
+        for (int q = 0; q < kMaxRho; ++q) {
+            const int j = na[q];
+            if (j < 0) continue;
+            const Col8 c = D.colsE[j];
+            const float qa = fast_exp2(fmaf(-Ka, chord_cp(p1, p2, c.s1, c.s2, c.v1, c.v2, c.vv, c.vv2),
+                                            fmaf(D.g[j], ka, fa)));
+            bool both = false;
+#pragma unroll
+            for (int r = 0; r < kMaxRho; ++r) both = both || nb[r] == j;
+            float qb = 0.0f;
+            if (both) {
+                const Col8 d = D.colsP[j];
+                qb = fast_exp2(fmaf(-Kb, chord_cp(p1, p2, d.s1, d.s2, d.v1, d.v2, d.vv, d.vv2),
+                                    fmaf(D.gprev[j], kb, fb)));
+            }
+            const float dq = qa - qb;
+            acc = fmaf(dq, dq, acc);
+        }
+#pragma unroll
+        for (int r = 0; r < kMaxRho; ++r) {
+            const int j = nb[r];
+            if (j < 0) continue;
+            bool both = false;
+#pragma unroll
+            for (int q = 0; q < kMaxRho; ++q) both = both || na[q] == j;
+            if (both) continue;
+            const Col8 d = D.colsP[j];
+            const float qb = fast_exp2(fmaf(-Kb, chord_cp(p1, p2, d.s1, d.s2, d.v1, d.v2, d.vv, d.vv2),
+                                            fmaf(D.gprev[j], kb, fb)));
+            acc = fmaf(qb, qb, acc);
         }
         const double ba = exp((static_cast<double>(D.f[i]) + A.g0 - p.c_out) / A.eps);
         const double bb = exp((static_cast<double>(D.fprev[i]) + B.g0 - p.c_out) / B.eps);
@@ -2323,6 +2396,7 @@ struct BatchEngine {
                     area = std::max(area, 4.0 * a.geom->det[d].half_size * a.geom->det[d].half_size);
                 D.knn_k = static_cast<float>(3.0 * rho * area / (M_PI * 2.0 * a.ot->distance * a.ot->distance));
                 D.nbr = sw[k].nbr;
+                D.nbr_prev = sw[k].nbr_prev;
                 D.ncp = sw[k].ncp;
                 D.cand_j = sw[k].cand_j;
                 D.cand_c = sw[k].cand_c;
@@ -2709,13 +2783,17 @@ struct BatchEngine {
             if (in[k].obs->n > 0)
                 LAUE_CHECK_HIP(hipMemcpyAsync(sw[k].Fp, in[k].pot->f, in[k].obs->n * sizeof(float),
                                               hipMemcpyDeviceToDevice, s));
+            if (rho > 0 && in[k].obs->n > 0)
+                LAUE_CHECK_HIP(hipMemcpyAsync(sw[k].nbr_prev, sw[k].nbr, in[k].obs->n * rho * sizeof(int),
+                                              hipMemcpyDeviceToDevice, s));
         }
         return set_objin(eps, 1);
     }
 
-    // zeta = ||Q - Q_prev||_F of every sample (dense; set_objin and save_prev first)
+    // zeta = ||Q - Q_prev||_F of every sample (set_objin and save_prev first)
     int plan_change(std::vector<double> &zeta) {
-        if (n_rows) k_dq_rows<<<n_rows, 64, 0, s>>>(bw.rows, bw.desc, bw.objin, n);
+        if (n_rows && rho > 0) k_dq_rows_sparse<<<n_rows, 64, 0, s>>>(bw.rows, bw.desc, bw.objin, n);
+        else if (n_rows) k_dq_rows<<<n_rows, 64, 0, s>>>(bw.rows, bw.desc, bw.objin, n);
         if (n_cols) k_dq_cols<<<n_cols, 64, 0, s>>>(bw.cols, bw.desc, bw.objin, n);
         k_dq_final<<<n, 64, 0, s>>>(bw.desc, bw.objin, n);
         LAUE_CHECK_HIP(hipGetLastError());
@@ -2768,7 +2846,7 @@ static int run_em(BatchEngine &e, const std::vector<const laue_em_params *> &par
                      "samples of a batch need the same number of EM temperatures");
     const bool cooling = par[0]->eps_cool > 0.0;
     const int n_final = cooling ? par[0]->final_iters : 0;
-    const bool zeta_on = cooling && e.rho == 0 && n == 1;
+    const bool zeta_on = cooling && n == 1;
     const bool zeta_stop = zeta_on && par[0]->zeta_tol > 0.0;
     const int total = L + n_final;
     // the stage of a temperature (chunk sizing and tile tuning): the stage
@@ -3224,8 +3302,6 @@ extern "C" int laue_em(const laue_geometry *geom, const laue_planes *planes,
     if ((rc = validate_em_params(par)) || (rc = validate_planes(planes)) || (rc = validate_grains(grains)))
         return rc;
     LAUE_REQUIRE(bins_ok(&par->ot, pot), LAUE_EINVAL, "bin potentials must be finite");
-    LAUE_REQUIRE(!(par->eps_cool > 0.0 && par->zeta_tol > 0.0) || par->ot.rho == 0, LAUE_EINVAL,
-                 "the plan-change stop needs the dense assignment (ot.rho = 0)");
     BatchEngine e;
     if ((rc = e.setup({SampleIn{geom, planes, obs, model, &par->ot, grains, pot, par->gn.mu_rel, assign, nullptr,
                                 &par->gn}},
