@@ -351,7 +351,7 @@ def bench_batching(laue, n_samples, n_stages, log):
             "launch_used": outs[0]["launch_used"], "identical_to_sequential": bool(same)}
 
 
-def recipe_params(laue, p, recipe, n_obs):
+def recipe_params(laue, p, recipe, n_obs, rho=0):
     """Refinement and EM parameters of an index line.  "stages": the
     refinement 30 -> 1.11 sigma^2 in 8 iterations and the EM's 5 x 4 stage
     schedule 111 -> 1.11 sigma^2.  "paper": the paper's annealing (Sec. 5.1,
@@ -359,14 +359,16 @@ def recipe_params(laue, p, recipe, n_obs):
     to 2 sigma^2 (90 iterations, one Gauss-Newton step each), the EM cools by
     0.97 per iteration from the data-tied first temperature (the farthest of 32
     neighbours, computed by the library) to 2 sigma^2 (the paper's temperature
-    1), then at most 20 more iterations with the plan-change stop."""
+    1), then at most 20 more iterations with the plan-change stop.  rho > 0:
+    the EM's E-step keeps each detected spot's rho nearest model spots (the
+    paper's sparse assignment, Sec. 5.2)."""
     s2 = p.sigma_mm ** 2
     c_out = laue.c_out_3sigma(p.sigma_mm, p.distance)
     if recipe == "stages":
         return None, None
     score = laue.score_params(p.sigma_mm, p.distance, c_out, k_refine=90, k_gn=1, eps_start=30.0 * s2,
                               eps_cool=0.97)
-    ot = laue.ot_params(1.0, p.distance, c_out, 0.0)
+    ot = laue.ot_params(1.0, p.distance, c_out, 0.0, rho=rho)
     em = laue.em_params(ot, 0.0, 2.0 * s2, 1, 1, eps_cool=0.97, final_iters=20,
                         zeta_tol=ZETA_TOL_PER_ROOT_SPOT * math.sqrt(max(n_obs, 1)), sigma_mm=p.sigma_mm)
     return score, em
@@ -378,7 +380,7 @@ ZETA_TOL_PER_ROOT_SPOT = 1e-3
 
 
 def bench_index(laue, workload, n_pairs, learned_pairs, log, sobol_points=0, recipe="stages", max_candidates=None,
-                plain_max=None, train_examples=1_000_000, spot_per_candidate=None):
+                plain_max=None, train_examples=1_000_000, spot_per_candidate=None, rho=0):
     """Time to index from device-resident spots (laue_index): plain exhaustive
     scoring of the candidates of n_pairs spot pairs, against (learned_pairs >
     0) the learned proposal scoring the top 5% of the candidates of
@@ -417,8 +419,13 @@ def bench_index(laue, workload, n_pairs, learned_pairs, log, sobol_points=0, rec
     q, x = ig.random_grains(p)
     obs = laue.laue_simulate(geom, planes, laue.Grains(q, x), p.sigma_mm, p.distance, p.outlier_frac, p.seed)
     out = {"workload": workload, "grains": p.n_grains, "detected_spots": obs.n, "recipe": recipe,
-           "training": training}
+           "training": training, "rho": rho}
+    # the sparse E-step (rho) for the Sobol form's EM only: its prototypes give
+    # hundreds of model spots per block; the pair forms' few dozen
+    # prototypes leave fewer model spots per block than rho, where choosing
+    # neighbours at every E-step costs more than the dense passes it saves
     score, em = recipe_params(laue, p, recipe, obs.n)
+    em_sobol = recipe_params(laue, p, recipe, obs.n, rho)[1]
     modes = [("plain", n_pairs)] + ([("learned", learned_pairs)] if learned_pairs else []) + \
         ([("sobol", sobol_points)] if sobol_points else [])
     for mode, pairs in modes:
@@ -429,7 +436,7 @@ def bench_index(laue, workload, n_pairs, learned_pairs, log, sobol_points=0, rec
             cap = 8000 * pairs if obs.n * pairs > 1e11 else None
             cap = spot_per_candidate * pairs if spot_per_candidate else cap
             par = laue.index_params(p, "sobol", max_candidates=pairs, n_obs=obs.n, n_planes=planes.n, lbar_cap=cap,
-                                    score=score, em=em)
+                                    score=score, em=em_sobol)
         else:
             n_sc = mc if mc is not None else 64 * pairs
             n_sc = int(math.ceil(0.05 * n_sc)) if mode == "learned" else n_sc
@@ -752,19 +759,20 @@ def bench_forward(laue, n_grains, log):
 # 100 grains; 1000 grains at 70% outliers (2^20 candidates both ways); 1000
 # grains at the paper's fiducial noise with the paper's recipe (plain scoring
 # of 2048 pairs' candidates, about the recall the learned form reaches from
-# the top 5% of 2^20, and 3,000,000 Sobol-grid starts); the 2000-grain stress
+# the top 5% of 2^20, and 3,000,000 Sobol-grid starts, whose EM keeps each
+# detected spot's 32 nearest model spots as the paper's does); the 2000-grain stress
 # workload (the network ranks 2^20 candidates and scores the top 5%; plain
 # scoring of the first 2^16).
 DEFAULT_INDEX_LINES = ("medium,pairs=8192,sobol=200000;"
                        "learned,pairs=32768,lpairs=32768,cand=1048576;"
-                       "learned_fiducial,pairs=2048,lpairs=24576,cand=1048576,sobol=3000000,spot=64,recipe=paper;"
+                       "learned_fiducial,pairs=2048,lpairs=24576,cand=1048576,sobol=3000000,spot=64,recipe=paper,rho=32;"
                        "stress,pairs=32768,lpairs=32768,cand=1048576,pcand=65536")
 
 
 def parse_index_line(item):
     parts = [x.strip() for x in item.split(",") if x.strip()]
     o = {"pairs": 4096, "lpairs": None, "sobol": 0, "recipe": "stages", "cand": None, "pcand": None,
-         "examples": 1_000_000, "spot": None}
+         "examples": 1_000_000, "spot": None, "rho": 0}
     for kv in parts[1:]:
         k, v = kv.split("=")
         if k not in o and k != "name":
@@ -774,6 +782,8 @@ def parse_index_line(item):
         o["lpairs"] = 8 * o["pairs"]
     if o["recipe"] not in ("stages", "paper"):
         raise ValueError("recipe must be stages or paper")
+    if o["rho"] and o["recipe"] != "paper":
+        raise ValueError("rho applies to the paper recipe's EM")
     return parts[0], o
 
 
@@ -806,7 +816,9 @@ def main():
                          "(plain form's spot pairs), lpairs (learned form's, default 8 x pairs; 0: no learned form), "
                          "sobol (Sobol points, "
                          "0: none), recipe (stages or paper), cand (candidate cap of both forms), pcand (plain "
-                         "form's cap), examples (training examples), spot (SPOT entries per Sobol start)")
+                         "form's cap), examples (training examples), spot (SPOT entries per Sobol start), rho "
+                         "(the paper recipe's sparse E-step in the Sobol form's EM: nearest model spots kept per detected "
+                         "spot; 0: dense)")
     ap.add_argument("--index-limits", default="",
                     help="workloads of the EM-from-truth and selection diagnostics ('' to skip)")
     ap.add_argument("--tile", type=int, default=0, choices=[0, 1, 2],
@@ -962,7 +974,7 @@ def main():
             line["time_to_index"][key] = bench_index(
                 laue, wl, o["pairs"], o["lpairs"], log, sobol_points=o["sobol"], recipe=o["recipe"],
                 max_candidates=o["cand"], plain_max=o["pcand"], train_examples=o["examples"],
-                spot_per_candidate=o["spot"])
+                spot_per_candidate=o["spot"], rho=o["rho"])
     if args.index_limits:
         import inputgen as ig
         line["index_limits"] = {wl: bench_index_limits(laue, ig.PRESETS[wl], log)
